@@ -1,0 +1,214 @@
+"""Seeded synthetic snapshot matrices.
+
+This module only manufactures inputs.  It contains none of the compressor's
+arithmetic (no sketching, no pivoted QR, no interpolation coefficients), so both
+the HIP product path and the CPU oracle can take their inputs from it.
+
+The paper's data (DNS channel-flow fields and particle trajectories, Sec. 3)
+are not available; the generators below stand in for them with the shapes and
+structure the paper describes:
+
+* ``spectral_snapshots`` -- channel-like velocity snapshots: a sum of random
+  Fourier modes with a k^-5/3 energy spectrum, wall-damped profiles in y on a
+  wall-clustered grid, and slowly drifting phases in time.  Rows are
+  (component, x, y, z) grid points, z fastest; columns are snapshots.  The grid
+  defaults follow the paper's DNS box (Sec. 3: 4*pi x 2 x 4*pi/3, stretched
+  toward the walls in y).
+* ``lowrank_exact_spectrum`` -- A = U diag(sigma) V^T (+ optional absolute
+  noise) with U, V orthonormal from QR of seeded Gaussians.
+* ``dct_lowrank`` -- A = U diag(sigma) V^T with U made of randomly signed,
+  row-permuted orthonormal DCT-II columns, cheap to build at millions of rows.
+
+Everything is generated with torch (CPU or GPU), in FP64, and returned as a
+column-major matrix: a tensor of shape (n, N) whose transpose view is the
+N x n matrix, so that ``t.T`` is A and every snapshot (column of A) is
+contiguous.  ``as_colmajor``/``colmajor_view`` convert.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+
+def colmajor_empty(N: int, n: int, dtype=torch.float32, device="cpu") -> torch.Tensor:
+    """Storage for an N x n column-major matrix; returns the N x n view."""
+    return torch.empty((n, N), dtype=dtype, device=device).T
+
+
+def as_colmajor(A: torch.Tensor) -> torch.Tensor:
+    """Copy A (N x n) into column-major storage and return the N x n view."""
+    out = colmajor_empty(A.shape[0], A.shape[1], A.dtype, A.device)
+    out.copy_(A)
+    return out
+
+
+@dataclass(frozen=True)
+class SpectralConfig:
+    nx: int = 128
+    ny: int = 64
+    nz: int = 64
+    n_snapshots: int = 500
+    n_modes: int = 400
+    seed: int = 1001
+    drift: float = 0.02          # U_c: phase drift rate (radians per snapshot per unit wavenumber)
+    decorrelation: float = 0.1   # relative random drift per mode
+    lx: float = 4.0 * math.pi
+    lz: float = 4.0 * math.pi / 3.0
+
+    @property
+    def rows(self) -> int:
+        return 3 * self.nx * self.ny * self.nz
+
+
+def _modes(cfg: SpectralConfig):
+    rng = np.random.default_rng(cfg.seed)
+    q = cfg.n_modes
+    mmax = max(cfg.nz / 4.0, 1.5)
+    m = rng.uniform(1.0, mmax, size=q)                       # |kappa| in domain units
+    d = rng.normal(size=(q, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)            # direction on the sphere
+    e = rng.normal(size=(q, 3))
+    e -= (e * d).sum(1, keepdims=True) * d                   # component direction, perpendicular
+    e /= np.linalg.norm(e, axis=1, keepdims=True)
+    amp = m ** (-5.0 / 6.0)                                  # E(k) ~ k^-5/3 with uniform |k|
+    phase0 = rng.uniform(0.0, 2.0 * math.pi, size=q)
+    xi = rng.normal(size=q)
+    # physical wavenumbers: m wavelengths across each (periodic-looking) extent
+    kx = 2.0 * math.pi * m * d[:, 0] / cfg.lx
+    ky = 2.0 * math.pi * m * d[:, 1] / 2.0
+    kz = 2.0 * math.pi * m * d[:, 2] / cfg.lz
+    omega = cfg.drift * m * (d[:, 0] + cfg.decorrelation * xi)  # radians per snapshot
+    return dict(kx=kx, ky=ky, kz=kz, e=e, amp=amp, phase0=phase0, omega=omega)
+
+
+def spectral_snapshots(cfg: SpectralConfig, dtype=torch.float32, device="cpu",
+                       col0: int = 0, ncols: int | None = None,
+                       rms: float | None = None) -> torch.Tensor:
+    """Channel-like snapshot matrix (rows = grid points x components, columns =
+    snapshots col0 .. col0+ncols-1), column-major N x ncols view.
+
+    Each entry is sum_q a_q e_{q,c} f_c(y) cos(kappa_q . x + phi_q(t)) with
+    phi_q(t) = phi_q0 + omega_q t, evaluated in FP64 as a product of a spatial
+    factor (N x 2Q) and a temporal factor (2Q x ncols), rounded to dtype, then
+    divided by ``rms`` (default: the RMS of the generated block itself, so a
+    full matrix has unit RMS; pass the full matrix's value to make column
+    blocks of one matrix share one scale -- see ``spectral_rms``).
+    """
+    if ncols is None:
+        ncols = cfg.n_snapshots - col0
+    md = _modes(cfg)
+    dev = torch.device(device)
+    f64 = torch.float64
+    kx = torch.tensor(md["kx"], dtype=f64, device=dev)
+    ky = torch.tensor(md["ky"], dtype=f64, device=dev)
+    kz = torch.tensor(md["kz"], dtype=f64, device=dev)
+    e = torch.tensor(md["e"], dtype=f64, device=dev)
+    amp = torch.tensor(md["amp"], dtype=f64, device=dev)
+    ph0 = torch.tensor(md["phase0"], dtype=f64, device=dev)
+    om = torch.tensor(md["omega"], dtype=f64, device=dev)
+
+    x = torch.arange(cfg.nx, dtype=f64, device=dev) * (cfg.lx / cfg.nx)
+    z = torch.arange(cfg.nz, dtype=f64, device=dev) * (cfg.lz / cfg.nz)
+    jj = torch.arange(cfg.ny, dtype=f64, device=dev)
+    y = -torch.cos(math.pi * jj / max(cfg.ny - 1, 1))
+    wall = 1.0 - y * y
+    prof = [wall, wall * wall, wall]                          # u, v, w damping
+
+    def cexp(coord, k):
+        ang = coord[:, None] * k[None, :]
+        return torch.complex(torch.cos(ang), torch.sin(ang))
+
+    ex, ey, ez = cexp(x, kx), cexp(y, ky), cexp(z, kz)
+
+    t = torch.arange(col0, col0 + ncols, dtype=f64, device=dev)
+    phase = ph0[None, :] + t[:, None] * om[None, :]           # ncols x Q
+    temporal = torch.cat([torch.cos(phase), -torch.sin(phase)], dim=1)
+
+    N = cfg.rows
+    out = torch.empty((ncols, N), dtype=dtype, device=dev)    # column-major storage
+    plane = cfg.ny * cfg.nz
+    sumsq = torch.zeros((), dtype=f64, device=dev)
+    for c in range(3):
+        wc = amp * e[:, c]                                     # Q
+        pc = prof[c].repeat_interleave(cfg.nz)[:, None] * wc[None, :]
+        eyz = (ey[:, None, :] * ez[None, :, :]).reshape(plane, -1)
+        for i in range(cfg.nx):
+            sp = (eyz * ex[i][None, :]) * pc                   # plane x Q complex
+            F = torch.cat([sp.real, sp.imag], dim=1)           # plane x 2Q
+            blk = temporal @ F.T                               # ncols x plane
+            sumsq += torch.sum(blk * blk)
+            r0 = (c * cfg.nx + i) * plane
+            out[:, r0:r0 + plane] = blk.to(dtype)
+    if rms is None:
+        rms = float(torch.sqrt(sumsq / (N * ncols)))
+    out /= rms
+    return out.T
+
+
+def spectral_rms(cfg: SpectralConfig) -> float:
+    """RMS of the full (all snapshots) FP64 field, for scaling column blocks."""
+    md = _modes(cfg)
+    # sum over rows and columns of (F T)^2 computed plane by plane on a
+    # coarse-in-time subsample would be approximate; generate exactly instead.
+    A = spectral_snapshots(cfg, dtype=torch.float64, rms=1.0)
+    return float(torch.sqrt(torch.mean(A.T.reshape(-1) ** 2)))
+
+
+def lowrank_exact_spectrum(N: int, n: int, sigma: np.ndarray, seed: int,
+                           noise: float = 0.0, dtype=torch.float64,
+                           device="cpu") -> torch.Tensor:
+    """A = U diag(sigma) V^T + noise * G (column-major N x n view).
+
+    U (N x r) and V (n x r), r = len(sigma), are the Q factors of seeded
+    Gaussian matrices (numpy PCG64 streams derived from ``seed``); G is an
+    independent standard Gaussian N x n matrix.
+    """
+    r = len(sigma)
+    rng_u = np.random.default_rng([seed, 1])
+    rng_v = np.random.default_rng([seed, 2])
+    U, _ = np.linalg.qr(rng_u.standard_normal((N, r)))
+    V, _ = np.linalg.qr(rng_v.standard_normal((n, r)))
+    A = (U * np.asarray(sigma, dtype=np.float64)[None, :]) @ V.T
+    if noise:
+        rng_n = np.random.default_rng([seed, 3])
+        A = A + noise * rng_n.standard_normal((N, n))
+    At = torch.from_numpy(np.asfortranarray(A))
+    return as_colmajor(At.to(dtype)).to(device)
+
+
+def dct_lowrank(N: int, n: int, sigma: np.ndarray, seed: int,
+                dtype=torch.float32, device="cpu") -> torch.Tensor:
+    """A = U diag(sigma) V^T with exactly orthonormal U built from n distinct
+    DCT-II columns (random frequencies, random signs, random row permutation)
+    and V from QR of a seeded n x n Gaussian.  O(N n) work to form U."""
+    rng = np.random.default_rng([seed, 7])
+    freqs = np.sort(rng.choice(N, size=n, replace=False))
+    signs = rng.choice([-1.0, 1.0], size=n)
+    perm = torch.from_numpy(rng.permutation(N))
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    dev = torch.device(device)
+    i = torch.arange(N, dtype=torch.float64, device=dev)
+    f = torch.tensor(freqs, dtype=torch.float64, device=dev)
+    scale = torch.where(f == 0, math.sqrt(1.0 / N), math.sqrt(2.0 / N))
+    U = torch.cos(math.pi * (i[:, None] + 0.5) * f[None, :] / N) * scale[None, :]
+    U = U * torch.tensor(signs, dtype=torch.float64, device=dev)[None, :]
+    U = U[perm.to(dev)]
+    SVt = torch.tensor(np.asarray(sigma, dtype=np.float64)[:, None] * V.T, device=dev)
+    A = U @ SVt
+    out = colmajor_empty(N, n, dtype, dev)
+    out.copy_(A)
+    return out
+
+
+def coarse_rows_every_other(nx: int, ny: int, nz: int, ncomp: int = 3) -> np.ndarray:
+    """Row indices of the grid points with even (i, j, k) in every component
+    (2x sub-sampling per dimension, "direct injection"), sorted ascending."""
+    c = np.arange(ncomp)[:, None, None, None]
+    i = np.arange(0, nx, 2)[None, :, None, None]
+    j = np.arange(0, ny, 2)[None, None, :, None]
+    k = np.arange(0, nz, 2)[None, None, None, :]
+    rows = ((c * nx + i) * ny + j) * nz + k
+    return np.sort(rows.reshape(-1)).astype(np.int64)
