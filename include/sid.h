@@ -1,0 +1,195 @@
+/*
+ * sid.h -- C ABI of the MI355X (gfx950) pass-efficient interpolative
+ * decomposition (ID) compressor.
+ *
+ * Method: Dunton, Jofre, Iaccarino & Doostan, "Pass-efficient methods for
+ * compression of high-dimensional turbulent flow data" (arXiv:1905.13257).
+ *
+ * Problem statement (Sec. 2.1, Sec. 2.4 eq. (ID), Remark 2.1).  A snapshot
+ * matrix A holds one time snapshot per column: A is N x n, N = grid points x
+ * field components, n = snapshots.  (The paper stores snapshots as rows and
+ * computes a row ID; this library stores A transposed and computes the
+ * column ID A ~ A(:, J) P, which is the same decomposition.)  J lists k
+ * snapshot indices (the skeleton) and P is k x n with P(:, J) = I.
+ *
+ * Pass structure.
+ *   - Randomized ID (Alg. 4): one pass forms the Gaussian sketch W = Psi A
+ *     ((l+q) x n, l = k + oversample, q held-out probe rows); a column-pivoted
+ *     modified Gram-Schmidt QR (mgsqr) of W's first l rows gives J and R, and
+ *     back substitution gives P (Alg. 4 steps after the sketch).
+ *   - Sub-sampled ID (Alg. 5, Sec. 2.5): the sketch reads only a coarse set of
+ *     rows S of A: W = Psi(:, S) A(S, :).
+ *   - Two-pass mode then reads the skeleton A(:, J) in a second pass.
+ *   - Single-pass mode also forms Y = A Omega (N x l) in the same pass and
+ *     estimates A(:, J) from W and Y without touching A again (the two-sided
+ *     single-pass sketch of Halko et al. Sec. 5.5, quoted in Sec. 2.3).
+ *
+ * Conventions.
+ *   - Matrices are column-major with a leading dimension (lda >= rows).
+ *   - Indices are 0-based int64.
+ *   - Array arguments are DEVICE pointers unless stated "host".
+ *   - Calls that launch work are asynchronous on the context's stream and
+ *     return before the work finishes; outputs are valid after the stream
+ *     synchronizes.  Calls never allocate inside the launched sequence other
+ *     than growing the context workspace, which happens on the host before
+ *     any launch (sid_reserve grows it ahead of time).
+ *   - Errors: every call returns sid_status; no exception or abort crosses
+ *     the ABI.  Argument validation happens on the host before any device
+ *     work; on error nothing is launched and sid_last_error() describes it.
+ *   - Thread safety: a context is used by one host thread at a time.
+ */
+#ifndef SID_H
+#define SID_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sid_ctx sid_ctx;
+typedef struct sid_rowset sid_rowset;
+
+typedef enum {
+    SID_OK = 0,
+    SID_EINVAL = -1,     /* bad argument (shape, pointer, parameter)            */
+    SID_ENOMEM = -2,     /* device or host allocation failed / workspace cap     */
+    SID_EDEVICE = -3,    /* HIP runtime error                                    */
+    SID_ESTATE = -4,     /* call not valid in the object's current state         */
+    SID_ENONFINITE = -5, /* reserved: non-finite values detected                 */
+    SID_ERANK = -6       /* reserved                                             */
+} sid_status;
+
+typedef enum { SID_F64 = 0, SID_F32 = 1 } sid_dtype;
+
+/* Arithmetic of the sketch pass.  Gaussian entries are single-precision
+ * draws (sid_fill_gaussian); each mode stores them, and reads the data, as:
+ *   F64     FP64 data (FP32 data promoted exactly), FP64 accumulation
+ *   F32     FP32 data, FP32 products/accumulation within a row panel, FP64
+ *           across panels
+ *   BF16    data and Gaussians rounded to bfloat16, FP32 accumulation
+ *   BF16X2  Gaussians rounded to bfloat16; data split a = hi + lo, hi =
+ *           bf16(a), lo = bf16(a - hi) (16 significant bits); FP32
+ *           accumulation
+ * The small factorizations after the pass are always FP64. */
+typedef enum {
+    SID_SK_F64 = 0,
+    SID_SK_F32 = 1,
+    SID_SK_BF16 = 2,
+    SID_SK_BF16X2 = 3
+} sid_sketch_prec;
+
+typedef enum { SID_TWO_PASS = 0, SID_SINGLE_PASS = 1 } sid_mode;
+
+typedef struct {
+    int64_t k;                 /* target rank, 1 <= k <= min(n, k + oversample)   */
+    int64_t oversample;        /* p >= 0; sketch rows l = k + p (Alg. 4)          */
+    uint64_t seed;             /* Omega = stream 0, Psi = stream 1 of the generator */
+    const sid_rowset *coarse;  /* NULL: all rows; else the coarse row set S       */
+    sid_mode mode;
+    sid_sketch_prec prec;
+    int32_t probe_rows;        /* q >= 0 held-out Psi rows for the error estimate */
+    int32_t corange_rows;      /* single pass: e extra Psi rows (beyond the l that
+                                  select J) used by the skeleton solve; < 0 means
+                                  e = oversample.  Ignored in two-pass mode.     */
+    double rank_tol;           /* 0: fixed rank k; > 0: stop the pivoted QR when
+                                  the pivot's residual norm <= rank_tol times the
+                                  first pivot's (Remark 2.2), k_eff < k then      */
+    double sp_rcond;           /* single pass: relative drop tolerance of the
+                                  small solve (0: default for the precision)     */
+} sid_params;
+
+/* Fill a parameter block with defaults: oversample 10, seed 0, all rows,
+ * two-pass, F32 sketch, probe_rows 10, corange_rows -1, rank_tol 0,
+ * sp_rcond 0.
+ * Psi row layout: rows [0, l) select J and P (Alg. 4); in single pass rows
+ * [l, l + e) are the extra co-range rows; the last q rows are the probe. */
+void sid_params_init(sid_params *p, int64_t k);
+
+/* Context: binds a device and a stream and owns the workspace.  `device` is a
+ * HIP device ordinal; `hip_stream` is a hipStream_t to launch on, or NULL for
+ * a stream the context creates (and destroys).  device = -1 makes a
+ * validation-only context: calls on it check their arguments exactly as on a
+ * device context, then return SID_ESTATE instead of launching (no GPU
+ * needed).  Errors: SID_EINVAL (out NULL or device out of range),
+ * SID_EDEVICE (no HIP device / runtime failure). */
+sid_status sid_create(sid_ctx **out, int device, void *hip_stream);
+sid_status sid_destroy(sid_ctx *ctx);
+/* Human-readable description of the last failing call on this context
+ * (valid until the next call on it).  Never NULL. */
+const char *sid_last_error(const sid_ctx *ctx);
+/* Bytes of device workspace currently held by the context. */
+size_t sid_workspace_bytes(const sid_ctx *ctx);
+/* Cap on workspace growth in bytes (0 = none); growth beyond it fails with
+ * SID_ENOMEM. */
+sid_status sid_set_workspace_limit(sid_ctx *ctx, size_t bytes);
+
+/* Coarse row set S (Sec. 2.5 eq. (A_c): the sub-sampled degrees of freedom).
+ * `host_rows` (host) must be strictly increasing, within [0, N), and count >
+ * 0; it is validated on the host and copied to the device once.  The sketch
+ * then reads only A(S, :) (Alg. 5 step "subsample").  Psi columns are keyed
+ * by the global row index, so a coarse sketch equals the full sketch of
+ * A(S, :). */
+sid_status sid_rowset_create(sid_ctx *ctx, const int64_t *host_rows, int64_t count,
+                             int64_t N, sid_rowset **out);
+sid_status sid_rowset_destroy(sid_rowset *rs);
+
+/* Grow the workspace for compress calls of this shape ahead of time. */
+sid_status sid_reserve(sid_ctx *ctx, int64_t N, int64_t n, const sid_params *p);
+
+/*
+ * Compress A (N x n, column-major, leading dimension lda, element type
+ * `dtype`) into a rank-k column ID.
+ *   J     [k] int64: skeleton columns in pivot order; entries beyond k_eff -1.
+ *   P     k x n (ldp), element type `dtype`; P(:, J_i) = e_i exactly; rows
+ *         beyond k_eff zero.
+ *   AJ    N x k (ldaj), element type `dtype`, or NULL.  Two-pass: the copy
+ *         A(:, J) (second pass, Sec. 2.6).  Single-pass: the estimate of
+ *         A(:, J) from the sketches (columns beyond k_eff zero).
+ *   err   [2] double: err[0] = relative Frobenius residual of the held-out
+ *         probe rows (an estimate of ||A - AJ P||_F / ||A||_F; NaN when
+ *         probe_rows = 0), err[1] = relative residual of the sketch fit.
+ *   k_eff [1] int64: number of skeleton columns actually chosen.
+ * Any of J, P, err, k_eff may be NULL when not wanted.
+ * Errors: SID_EINVAL for bad shapes/parameters/null A; SID_ENOMEM when the
+ * workspace cannot grow; SID_EDEVICE for a launch failure.
+ */
+sid_status sid_compress(sid_ctx *ctx, const void *A, sid_dtype dtype, int64_t N, int64_t n,
+                        int64_t lda, const sid_params *p, int64_t *J, void *P, int64_t ldp,
+                        void *AJ, int64_t ldaj, double *err, int64_t *k_eff);
+
+/* Reconstruct Ahat = AJ P (eq. (ID)); AJ N x k (ldaj), P k x n (ldp), Ahat
+ * N x n (ldo), all of element type `dtype`. */
+sid_status sid_reconstruct(sid_ctx *ctx, const void *AJ, int64_t ldaj, const void *P,
+                           int64_t ldp, sid_dtype dtype, int64_t N, int64_t k, int64_t n,
+                           void *Ahat, int64_t ldo);
+
+/* Error of an ID against the data without forming Ahat (Sec. 3: relative
+ * Frobenius error, Tables 4-7; relative entry-wise max error, Sec. 3.1).
+ * out4 (host, 4 doubles): ||A - AJ P||_F, ||A||_F, max |A - Ahat|/|A| over
+ * A != 0, max |A - Ahat|.  Synchronizes the stream. */
+sid_status sid_error_norms(sid_ctx *ctx, const void *A, int64_t lda, const void *AJ,
+                           int64_t ldaj, const void *P, int64_t ldp, sid_dtype dtype,
+                           int64_t N, int64_t k, int64_t n, double *out4);
+
+/* Test hook: the Gaussian test-matrix entries the sketches use.
+ * out[t + nminor * s] = G(seed, stream, major0 + s, minor0 + t) as float, for
+ * s < nmajor, t < nminor (device pointer).  Omega(j, c) = G(seed, 0, j, c);
+ * Psi(r, i) = G(seed, 1, i, r).  See the generator specification in the
+ * device sources (Philox4x32-10 + single-precision Box-Muller). */
+sid_status sid_fill_gaussian(sid_ctx *ctx, uint64_t seed, int stream, int64_t major0,
+                             int64_t nmajor, int64_t minor0, int64_t nminor, float *out);
+
+/* Test hook: the sketch W = Psi(:, S) A(S, :) (lw x n, FP64, column-major,
+ * ld = lw, lw = l + e + q with e as in single-pass mode when Y != NULL and 0
+ * otherwise) and, when Y != NULL, Y = A Omega (N x l, row-major, element type
+ * FP64 for SID_SK_F64 else FP32) exactly as sid_compress forms them. */
+sid_status sid_sketch(sid_ctx *ctx, const void *A, sid_dtype dtype, int64_t N, int64_t n,
+                      int64_t lda, const sid_params *p, double *W, void *Y);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SID_H */

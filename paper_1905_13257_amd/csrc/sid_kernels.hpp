@@ -1,0 +1,45 @@
+// sid_kernels.hpp -- launchers of the gfx950 kernels (internal to libsid).
+#pragma once
+#include <type_traits>
+#include "sid_device.hpp"
+
+namespace sid {
+
+hipError_t launch_fill_gaussian(hipStream_t st, uint64_t seed, uint32_t stream, int64_t major0,
+                                int64_t nmajor, int64_t minor0, int64_t nminor, float* out);
+hipError_t launch_sketch(hipStream_t st, int prec, bool a_is_f64, const void* A, int64_t lda,
+                         int64_t N, int64_t n, const int64_t* rows, int64_t Ns, int lq,
+                         uint64_t seed, int64_t nchunks, double* part, double* W,
+                         const float* omega, int l, void* Y);
+hipError_t launch_cpqr(hipStream_t st, const double* X, int64_t ldx, int m, int nc, int kmax,
+                       double rank_tol, double* Wr, double* nrm2, int64_t* piv, double* R,
+                       double* Q, int64_t* keff, double* stats);
+hipError_t launch_backsolve(hipStream_t st, const double* R, const int64_t* piv,
+                            const int64_t* keff, int kcap, int nc, double* Pd, void* P,
+                            int64_t ldp, bool p_is_f64);
+hipError_t launch_fit_residual(hipStream_t st, const double* W, int lq, int r0, int q, int nc,
+                               const int64_t* piv, const int64_t* keff, const double* Pd, int kcap,
+                               const double* mix, double* out);
+hipError_t launch_omega_values(hipStream_t st, int prec, const float* z, int64_t count,
+                               double* out);
+hipError_t launch_ratio_sqrt(hipStream_t st, const double* stats, double* out);
+hipError_t launch_gemm64(hipStream_t st, int M, int Nn, int K, const double* A, int64_t lda,
+                         int tA, const double* B, int64_t ldb, int tB, double* C, int64_t ldc);
+hipError_t launch_gather_cols(hipStream_t st, const void* src, bool src_f64, int64_t lds,
+                              int64_t rows, const int64_t* piv, const int64_t* keff, int kcap,
+                              void* dst, bool dst_f64, int64_t ldd);
+hipError_t launch_gather_block(hipStream_t st, const double* W, int lq, int r0, int q,
+                               const int64_t* piv, const int64_t* keff, int kcap, double* out);
+hipError_t launch_small_backsolve(hipStream_t st, const double* RM, const int64_t* pivM,
+                                  const int64_t* rM, int l, const double* Cm, int64_t ldc, int kc,
+                                  double* Tm);
+hipError_t launch_apply_t(hipStream_t st, const void* Y, bool y_f64, int64_t N, int l,
+                          const double* Tm, int k, void* AJ, bool aj_f64, int64_t ldaj);
+hipError_t launch_reconstruct(hipStream_t st, bool f64, const void* AJ, int64_t ldaj,
+                              const void* P, int64_t ldp, int64_t N, int k, int64_t n, void* out,
+                              int64_t ldo);
+hipError_t launch_error_norms(hipStream_t st, bool f64, const void* A, int64_t lda,
+                              const void* AJ, int64_t ldaj, const void* P, int64_t ldp, int64_t N,
+                              int k, int64_t n, double* part, int64_t part_cap, double* out4);
+
+}  // namespace sid

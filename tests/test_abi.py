@@ -1,0 +1,122 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+include/sid.h declares, and rejects bad arguments with the documented status
+codes (through a validation-only context, device -1)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1905_13257_amd as sid
+from paper_1905_13257_amd import _native
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+EINVAL, ENOMEM, EDEVICE, ESTATE = -1, -2, -3, -4
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "sid.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sid_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_match_header():
+    L = sid.load()
+    names = declared_functions()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(_native.EXPORTS)
+
+
+@pytest.fixture()
+def vctx():
+    L = sid.load()
+    h = ctypes.c_void_p()
+    assert L.sid_create(ctypes.byref(h), -1, None) == 0
+    yield L, h
+    assert L.sid_destroy(h) == 0
+
+
+def _params(L, k=5, **kw):
+    p = _native._Params()
+    L.sid_params_init(ctypes.byref(p), k)
+    for key, v in kw.items():
+        setattr(p, key, v)
+    return p
+
+
+def _compress(L, h, N=100, n=20, lda=100, p=None, A=1, dtype=1, J=None, P=None, ldp=5, AJ=None,
+              ldaj=100):
+    vp = ctypes.c_void_p
+    return L.sid_compress(h, vp(A), dtype, N, n, lda, ctypes.byref(p), vp(J), vp(P), ldp,
+                          vp(AJ), ldaj, vp(0), vp(0))
+
+
+def test_defaults(vctx):
+    L, h = vctx
+    p = _params(L, 7)
+    assert (p.k, p.oversample, p.seed, p.mode, p.prec, p.probe_rows, p.corange_rows) == \
+        (7, 10, 0, 0, 1, 10, -1)
+    assert p.rank_tol == 0.0 and p.sp_rcond == 0.0
+
+
+@pytest.mark.parametrize("kw,args,code", [
+    (dict(k=0), {}, EINVAL),                       # k >= 1
+    (dict(k=30), dict(n=20), EINVAL),              # k <= n
+    (dict(oversample=-1), {}, EINVAL),
+    (dict(probe_rows=-2), {}, EINVAL),
+    (dict(mode=7), {}, EINVAL),
+    (dict(prec=9), {}, EINVAL),
+    (dict(rank_tol=-1.0), {}, EINVAL),
+    (dict(k=5, oversample=300), {}, EINVAL),       # sketch rows <= 256
+    ({}, dict(N=0), EINVAL),
+    ({}, dict(n=0), EINVAL),
+    ({}, dict(lda=50), EINVAL),                    # lda >= N
+    ({}, dict(A=0), EINVAL),                       # A non-NULL
+    ({}, dict(dtype=5), EINVAL),
+    ({}, dict(P=1, ldp=3), EINVAL),                # ldp >= k
+    ({}, dict(AJ=1, ldaj=10), EINVAL),             # ldaj >= N
+    ({}, {}, ESTATE),                              # valid -> no device to launch on
+])
+def test_compress_validation(vctx, kw, args, code):
+    L, h = vctx
+    p = _params(L, **({"k": 5} | kw))
+    st = _compress(L, h, p=p, **args)
+    assert st == code, L.sid_last_error(h)
+    assert L.sid_last_error(h)
+
+
+def test_rowset_validation(vctx):
+    L, h = vctx
+    out = ctypes.c_void_p()
+    rows = np.array([0, 3, 3, 9], dtype=np.int64)
+    assert L.sid_rowset_create(h, ctypes.c_void_p(rows.ctypes.data), 4, 10, ctypes.byref(out)) == EINVAL
+    rows = np.array([0, 3, 12], dtype=np.int64)
+    assert L.sid_rowset_create(h, ctypes.c_void_p(rows.ctypes.data), 3, 10, ctypes.byref(out)) == EINVAL
+    rows = np.array([-1, 3], dtype=np.int64)
+    assert L.sid_rowset_create(h, ctypes.c_void_p(rows.ctypes.data), 2, 10, ctypes.byref(out)) == EINVAL
+    rows = np.array([1, 3, 5], dtype=np.int64)
+    assert L.sid_rowset_create(h, ctypes.c_void_p(rows.ctypes.data), 3, 10, ctypes.byref(out)) == ESTATE
+    assert L.sid_rowset_create(h, None, 3, 10, ctypes.byref(out)) == EINVAL
+
+
+def test_other_calls_validate(vctx):
+    L, h = vctx
+    vp = ctypes.c_void_p
+    assert L.sid_reconstruct(h, vp(0), 10, vp(1), 3, 1, 10, 3, 5, vp(1), 10) == EINVAL
+    assert L.sid_reconstruct(h, vp(1), 5, vp(1), 3, 1, 10, 3, 5, vp(1), 10) == EINVAL
+    assert L.sid_reconstruct(h, vp(1), 10, vp(1), 3, 1, 10, 3, 5, vp(1), 10) == ESTATE
+    out = (ctypes.c_double * 4)()
+    assert L.sid_error_norms(h, vp(1), 10, vp(1), 10, vp(1), 3, 1, 10, 3, 5, None) == EINVAL
+    assert L.sid_error_norms(h, vp(1), 10, vp(1), 10, vp(1), 3, 1, 10, 3, 5, out) == ESTATE
+    assert L.sid_fill_gaussian(h, 0, -1, 0, 4, 0, 4, vp(1)) == EINVAL
+    assert L.sid_fill_gaussian(h, 0, 0, 0, 4, 0, 4, vp(1)) == ESTATE
+    p = _params(L, 5)
+    assert L.sid_reserve(h, 100, 20, ctypes.byref(p)) == ESTATE
+    assert L.sid_reserve(h, 100, 2, ctypes.byref(p)) == EINVAL
+    assert L.sid_sketch(h, vp(1), 1, 100, 20, 100, ctypes.byref(p), vp(0), vp(0)) == EINVAL
+    assert L.sid_set_workspace_limit(h, 1 << 20) == 0
+    assert L.sid_workspace_bytes(h) == 0
+    assert L.sid_create(None, 0, None) == EINVAL

@@ -1,0 +1,210 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.  Marked gpu."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sid():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1905_13257_amd as m
+    m.load()
+    return m
+
+
+def to_gpu(A64: np.ndarray, dtype=torch.float32) -> torch.Tensor:
+    t = torch.from_numpy(np.asfortranarray(A64)).to(dtype)
+    return synth.as_colmajor(t).cuda()
+
+
+def host(t: torch.Tensor) -> np.ndarray:
+    return t.detach().cpu().numpy()
+
+
+# sketch tolerance: relative to sum |Psi||A| per entry (accumulation error bound)
+# |err| <= 10 sqrt(L) u * sum|Psi||A| with L <= 8192 terms per partial sum
+RTOL = {"f64": 1e-13, "f32": 5e-5, "bf16": 5e-5, "bf16x2": 5e-5}
+
+
+def _absbound(A64, rows, lq, seed, prec, oracle_mod):
+    Psi = oracle_mod.psi(seed, rows, lq, prec)
+    return np.abs(Psi) @ np.abs(oracle_mod.data_values(A64[rows], prec))
+
+
+def test_gaussian_bit_identical(sid, oracle_mod):
+    """Device generator == oracle generator, bit for bit, both streams."""
+    for seed in (0, 7, 2**40 + 3):
+        for stream, major0, nmajor, minor0, nminor in [(0, 0, 513, 0, 120), (1, 10**6, 257, 3, 131),
+                                                       (1, 2**32 - 5, 20, 0, 9)]:
+            say("gauss", seed, stream, major0, nmajor, minor0, nminor)
+            g = host(sid.fill_gaussian(seed, stream, major0, nmajor, minor0, nminor))
+            o = oracle_mod.gaussian(seed, stream, np.arange(major0, major0 + nmajor, dtype=np.int64),
+                                    minor0, nminor)
+            assert np.array_equal(g.view(np.uint32), o.view(np.uint32))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "bf16x2"])
+@pytest.mark.parametrize("shape", [(1000, 77, 6, 4, 3), (4096, 256, 20, 10, 10), (333, 5, 3, 2, 0)])
+def test_sketch_parity(sid, oracle_mod, prec, shape):
+    N, n, k, p, q = shape
+    say("sketch", prec, shape)
+    rng = np.random.default_rng(N + n)
+    A64 = rng.standard_normal((N, n)).astype(np.float32).astype(np.float64)
+    A = to_gpu(A64, torch.float64 if prec == "f64" else torch.float32)
+    seed = 5
+    W, Y = sid.sketch(A, k, p, seed=seed, prec=prec, probe_rows=q, want_y=True)
+    l = k + p
+    lq = l + p + q
+    Wo = oracle_mod.sketch_w(A64, None, lq, seed, prec)
+    bound = _absbound(A64, np.arange(N), lq, seed, prec, oracle_mod)
+    err = np.abs(host(W) - Wo)
+    assert np.all(err <= RTOL[prec] * bound + 1e-300), (err / bound).max()
+    Yo = oracle_mod.sketch_y(A64, oracle_mod.omega(seed, n, l, prec), prec)
+    ybound = np.abs(oracle_mod.data_values(A64, prec)) @ np.abs(oracle_mod.omega(seed, n, l, prec))
+    yerr = np.abs(host(Y).astype(np.float64) - Yo)
+    assert np.all(yerr <= RTOL[prec] * ybound + 1e-300), (yerr / ybound).max()
+
+
+def test_sketch_coarse_rows(sid, oracle_mod):
+    N, n, k, p, q = 2000, 40, 5, 5, 4
+    say("coarse sketch")
+    rng = np.random.default_rng(3)
+    A64 = rng.standard_normal((N, n)).astype(np.float32).astype(np.float64)
+    A = to_gpu(A64, torch.float64)
+    S = np.sort(rng.choice(N, size=300, replace=False)).astype(np.int64)
+    rs = sid.RowSet(S, N)
+    W, _ = sid.sketch(A, k, p, seed=9, coarse=rs, prec="f64", probe_rows=q, want_y=False)
+    Wo = oracle_mod.sketch_w(A64, S, k + p + q, 9, "f64")
+    np.testing.assert_allclose(host(W), Wo, rtol=1e-12, atol=1e-12 * np.abs(Wo).max())
+
+
+def c1_matrix(N=4096, n=256, seed=1000):
+    sig = np.exp(-np.arange(1, n + 1) / 10.0)
+    return np.asarray(synth.lowrank_exact_spectrum(N, n, sig, seed=seed, noise=1e-8)), sig
+
+
+@pytest.mark.parametrize("mode", ["two_pass", "single_pass"])
+def test_c1_fp64_bit_exact_pivots(sid, oracle_mod, mode):
+    """FP64 mode on the 4096 x 256 exact-spectrum matrix (k=20, p=10):
+    J identical to the oracle, P and errors to FP64 roundoff."""
+    say("c1 fp64", mode)
+    A64, sig = c1_matrix()
+    A = to_gpu(A64, torch.float64)
+    k, p, q = 20, 10, 10
+    out = sid.compress(A, k, p, seed=0, mode=mode, prec="f64", probe_rows=q)
+    torch.cuda.synchronize()
+    ref = oracle_mod.compress(A64, k, p, seed=0, mode=mode, prec="f64", probe_rows=q)
+    assert ref.cp.margins.min() > 1e-10
+    assert host(out.J).tolist() == ref.J.tolist()
+    assert int(host(out.k_eff)[0]) == k
+    P = host(out.P)
+    np.testing.assert_allclose(P, ref.P, rtol=0, atol=1e-10 * np.abs(ref.P).max())
+    assert np.array_equal(P[:, ref.J], np.eye(k))
+    e = host(out.err)
+    assert abs(e[1] - ref.err_sketch) <= 1e-9 * ref.err_sketch
+    assert abs(e[0] - ref.err_probe) <= 1e-8 * ref.err_probe
+    AJ = host(out.AJ)
+    if mode == "two_pass":
+        assert np.array_equal(AJ, A64[:, ref.J])
+    else:
+        np.testing.assert_allclose(AJ, ref.AJ, rtol=0, atol=1e-9 * np.abs(ref.AJ).max())
+    eg = sid.error_norms(A, out.AJ, out.P)
+    eo = oracle_mod.error_norms(A64, ref.AJ, ref.P)
+    assert abs(eg["rel_fro"] - eo["rel_fro"]) <= 1e-9 * eo["rel_fro"]
+    opt = math.sqrt(np.sum(sig[k:] ** 2) / np.sum(sig ** 2))
+    assert eg["rel_fro"] >= opt * (1 - 1e-6)
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x2", "bf16"])
+def test_low_precision_modes(sid, oracle_mod, prec):
+    """FP32 data, low-precision sketches: pivots agree with the oracle (run
+    in the same sketch precision) until its first near-tie, and the error is
+    within a stated factor of the oracle's."""
+    say("lowprec", prec)
+    A64, _ = c1_matrix(N=4096, n=256, seed=1001)
+    A64 = A64.astype(np.float32).astype(np.float64)
+    A = to_gpu(A64, torch.float32)
+    k, p, q = 20, 10, 10
+    for mode in ("two_pass", "single_pass"):
+        out = sid.compress(A, k, p, seed=1, mode=mode, prec=prec, probe_rows=q)
+        torch.cuda.synchronize()
+        ref = oracle_mod.compress(A64, k, p, seed=1, mode=mode, prec=prec, probe_rows=q)
+        J = host(out.J)
+        tie = {"f32": 1e-5, "bf16x2": 1e-4, "bf16": 1e-2}[prec]
+        ist = next((i for i, m in enumerate(ref.cp.margins) if m <= tie), k)
+        assert J[:ist].tolist() == ref.J[:ist].tolist(), (prec, mode, ist)
+        eg = sid.error_norms(A, out.AJ, out.P)["rel_fro"]
+        eo = oracle_mod.error_norms(A64, ref.AJ, ref.P)["rel_fro"]
+        fac = {"f32": 1.01, "bf16x2": 1.05, "bf16": 1.5}[prec]
+        assert eg <= fac * eo + 1e-6, (prec, mode, eg, eo)
+
+
+def test_exact_rank_recovery(sid):
+    """rank(A) = 7 <= k: both modes reproduce A (FP64 and FP32)."""
+    rng = np.random.default_rng(4)
+    A64 = rng.standard_normal((3000, 7)) @ rng.standard_normal((7, 90))
+    for dt, prec, tol in [(torch.float64, "f64", 1e-11), (torch.float32, "f32", 5e-6)]:
+        A = to_gpu(A64, dt)
+        for mode in ("two_pass", "single_pass"):
+            say("exact rank", prec, mode)
+            out = sid.compress(A, 10, 6, seed=2, mode=mode, prec=prec)
+            e = sid.error_norms(A, out.AJ, out.P)
+            assert e["rel_fro"] < tol, (prec, mode, e)
+
+
+def test_rank_tolerance_and_degenerate(sid):
+    say("rank tol")
+    rng = np.random.default_rng(5)
+    A64 = rng.standard_normal((500, 5)) @ rng.standard_normal((5, 40))
+    A = to_gpu(A64, torch.float64)
+    out = sid.compress(A, 12, 4, seed=0, prec="f64", rank_tol=1e-9)
+    keff = int(host(out.k_eff)[0])
+    assert keff == 5
+    J = host(out.J)
+    assert (J[keff:] == -1).all()
+    assert np.all(host(out.P)[keff:] == 0)
+    Z = torch.zeros((300, 20), dtype=torch.float64, device="cuda").T.contiguous().T
+    out = sid.compress(Z, 4, 2, prec="f64")
+    assert int(host(out.k_eff)[0]) == 0
+
+
+def test_edge_shapes(sid, oracle_mod):
+    """k = n, k = 1, no oversampling, no probe rows, n not a multiple of the
+    tile, tiny N."""
+    rng = np.random.default_rng(6)
+    for (N, n, k, p, q) in [(70, 12, 12, 0, 0), (129, 3, 1, 0, 2), (65, 65, 30, 5, 1), (1, 1, 1, 0, 0)]:
+        say("edge", N, n, k, p, q)
+        A64 = rng.standard_normal((N, n))
+        A = to_gpu(A64, torch.float64)
+        for mode in ("two_pass", "single_pass"):
+            out = sid.compress(A, k, p, seed=3, mode=mode, prec="f64", probe_rows=q)
+            torch.cuda.synchronize()
+            ref = oracle_mod.compress(A64, k, p, seed=3, mode=mode, prec="f64", probe_rows=q)
+            kk = ref.k_eff
+            assert host(out.J)[:kk].tolist() == ref.J[:kk].tolist()
+            np.testing.assert_allclose(host(out.P), ref.P, atol=1e-9 * max(1, np.abs(ref.P).max()))
+
+
+def test_reconstruct_matches_oracle(sid, oracle_mod):
+    say("reconstruct")
+    rng = np.random.default_rng(7)
+    AJ64 = rng.standard_normal((1000, 13))
+    P64 = rng.standard_normal((13, 70))
+    for dt, tol in [(torch.float64, 1e-13), (torch.float32, 1e-5)]:
+        out = sid.reconstruct(to_gpu(AJ64, dt), to_gpu(P64, dt))
+        ref = oracle_mod.reconstruct(AJ64, P64)
+        np.testing.assert_allclose(host(out), ref, rtol=0, atol=tol * np.abs(ref).max())
