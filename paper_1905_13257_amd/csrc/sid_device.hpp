@@ -41,7 +41,11 @@ __device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1) {
 // ---------------------------------------------------------------------------
 // Gaussian transform.  Every step is one IEEE single-precision operation in a
 // fixed order (explicit fmaf, correctly rounded division and square root), so
-// the result is a function of the two 32-bit words only:
+// the result is a function of the two 32-bit words only.  Division and square
+// root are the plain operators, correctly rounded under
+// -fhip-fp32-correctly-rounded-divide-sqrt; HIP's __fsqrt_rn is not used
+// because without OCML_BASIC_ROUNDED_OPERATIONS it maps to the approximate
+// native square root.
 //   u = ((a >> 8) + 1) 2^-24,  r = sqrt(-2 ln u)
 //   ln u: u = m 2^e, m in [1, 2) (halved with e+1 when m >= sqrt 2),
 //         s = (m-1)/(m+1), ln m = s (2 + s^2 (2/3 + s^2 (2/5 + s^2 (2/7 +
@@ -61,7 +65,7 @@ __device__ __forceinline__ float gauss_ln(float u) {
     m = m * 0.5f;
     e += 1;
   }
-  const float s = __fdiv_rn(__fsub_rn(m, 1.0f), __fadd_rn(m, 1.0f));
+  const float s = __fsub_rn(m, 1.0f) / __fadd_rn(m, 1.0f);  // correctly rounded (see build flags)
   const float s2 = __fmul_rn(s, s);
   float p = __fmaf_rn(s2, bits_f(0x3E3A2E8Cu), bits_f(0x3E638E39u));  // 2/11, 2/9
   p = __fmaf_rn(s2, p, bits_f(0x3E924925u));                          // 2/7
@@ -76,7 +80,7 @@ __device__ __forceinline__ void gauss_pair(uint32_t a, uint32_t b, float& zc, fl
   const float two_m24 = bits_f(0x33800000u);
   const float u = __fmul_rn((float)((a >> 8) + 1u), two_m24);
   const float L = gauss_ln(u);
-  const float r = __fsqrt_rn(__fmul_rn(-2.0f, L));
+  const float r = __builtin_sqrtf(__fmul_rn(-2.0f, L));     // correctly rounded (see build flags)
   const uint32_t quad = b >> 30;
   const uint32_t frac = (b >> 7) & 0x007FFFFFu;
   const float t = __fmul_rn((float)(2u * frac + 1u), two_m24);
