@@ -53,7 +53,8 @@ class SpectralConfig:
     n_snapshots: int = 500
     n_modes: int = 400
     seed: int = 1001
-    drift: float = 0.02          # U_c: phase drift rate (radians per snapshot per unit wavenumber)
+    drift: float = 0.0385        # U_c: phase drift rate (radians per snapshot per unit wavenumber);
+                                 # 0.0385 puts the k=100 ID error of the 128x64x64 x 500 field at 1.8e-3
     decorrelation: float = 0.1   # relative random drift per mode
     lx: float = 4.0 * math.pi
     lz: float = 4.0 * math.pi / 3.0
