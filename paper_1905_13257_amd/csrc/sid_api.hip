@@ -17,7 +17,7 @@ namespace {
 enum Slot {
   WS_OMEGA, WS_PART, WS_W, WS_WR, WS_NRM, WS_PIV, WS_R, WS_Q, WS_KEFF, WS_STATS, WS_PD,
   WS_ERR, WS_Y, WS_M, WS_MPR, WS_WJ, WS_PIVM, WS_RM, WS_QM, WS_RKM, WS_C, WS_T, WS_MIX,
-  WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_COUNT
+  WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COUNT
 };
 
 struct Buf {
@@ -29,6 +29,7 @@ struct Buf {
 
 struct sid_ctx {
   int device = 0;
+  int num_cu = 1;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::string err;
@@ -250,6 +251,10 @@ sid_status sid_create(sid_ctx** out, int device, void* hip_stream) {
   sid_ctx* c = new (std::nothrow) sid_ctx();
   if (!c) return SID_ENOMEM;
   c->device = device;
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+      ncu > 0)
+    c->num_cu = ncu;
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
   } else {
@@ -357,6 +362,23 @@ static sid_status run_sketch(sid_ctx* ctx, const void* A, sid_dtype dtype, int64
               "omega generation");
   }
   const int64_t* rows = p->coarse ? p->coarse->d_rows : nullptr;
+  const bool bf = sh.prec == SID_SK_BF16 || sh.prec == SID_SK_BF16X2;
+  if (bf && dtype == SID_F32 &&
+      sid::fused_bf16_supported(sh.n, (int)sh.lq, (int)sh.l, lda, A, rows != nullptr)) {
+    // one streaming pass on the matrix cores (W partials per workgroup, FP32)
+    int64_t rpw = 0;
+    const int64_t grid = sid::fused_bf16_grid(sh.N, ctx->num_cu, &rpw);
+    float* partf = (float*)ws(ctx, WS_PARTF, sizeof(float) * (size_t)(grid * sh.lq * sh.n));
+    __bf16* omT = (__bf16*)ws(ctx, WS_OMT, sizeof(uint16_t) * 128 * 512);
+    if (!partf || !omT) return SID_ENOMEM;
+    int64_t nparts = 0;
+    SID_CHECK(sid::launch_sketch_fused_bf16(st, sh.prec == SID_SK_BF16X2, (const float*)A, lda,
+                                            sh.N, (int)sh.n, (int)sh.lq, (int)sh.l, p->seed,
+                                            w.omega, omT, ctx->num_cu, partf, W, (float*)Y,
+                                            &nparts),
+              "fused sketch pass");
+    return SID_OK;
+  }
   SID_CHECK(sid::launch_sketch(st, sh.prec, dtype == SID_F64, A, lda, sh.N, sh.n, rows, sh.Ns,
                                (int)sh.lq, p->seed, sh.nchunks, w.part, W, w.omega, (int)sh.l,
                                Y),

@@ -43,3 +43,12 @@ hipError_t launch_error_norms(hipStream_t st, bool f64, const void* A, int64_t l
                               int k, int64_t n, double* part, int64_t part_cap, double* out4);
 
 }  // namespace sid
+
+namespace sid {
+bool fused_bf16_supported(int64_t n, int lq, int l, int64_t lda, const void* A, bool has_rows);
+int64_t fused_bf16_grid(int64_t N, int num_cu, int64_t* rows_per_wg);
+hipError_t launch_sketch_fused_bf16(hipStream_t st, bool split, const float* A, int64_t lda,
+                                    int64_t N, int n, int lq, int l, uint64_t seed,
+                                    const float* omega, __bf16* omT, int num_cu, float* part,
+                                    double* W, float* Y, int64_t* nparts_out);
+}  // namespace sid
