@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -17,7 +18,7 @@ namespace {
 enum Slot {
   WS_OMEGA, WS_PART, WS_W, WS_WR, WS_NRM, WS_PIV, WS_R, WS_Q, WS_KEFF, WS_STATS, WS_PD,
   WS_ERR, WS_Y, WS_M, WS_MPR, WS_WJ, WS_PIVM, WS_RM, WS_QM, WS_RKM, WS_C, WS_T, WS_MIX,
-  WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COUNT
+  WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COOP, WS_SYNC, WS_R11, WS_COUNT
 };
 
 struct Buf {
@@ -30,6 +31,7 @@ struct Buf {
 struct sid_ctx {
   int device = 0;
   int num_cu = 1;
+  bool cooperative = false;  // SID_COOPERATIVE=1: cooperative launch of the pivoted QR
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::string err;
@@ -157,6 +159,9 @@ struct Work {
   void* Y;
   double *M, *Mpr, *WJ, *RM, *QM, *C, *T, *mix, *statsM, *om64;
   int64_t *pivM, *rkM;
+  void* coop;
+  unsigned int* sync2;
+  double* R11;
 };
 
 sid_status reserve(sid_ctx* c, const Shape& s, Work* w) {
@@ -174,6 +179,15 @@ sid_status reserve(sid_ctx* c, const Shape& s, Work* w) {
   w->stats = (double*)ws(c, WS_STATS, d * 2);
   w->Pd = (double*)ws(c, WS_PD, d * (size_t)(s.k * s.n));
   w->err = (double*)ws(c, WS_ERR, d * 2);
+  {
+    const int mmax = (int)s.lz;
+    const int ncmax = (int)(s.n > s.l ? s.n : s.l);
+    w->coop = ws(c, WS_COOP, sid::cpqr_coop_scratch_bytes(mmax, ncmax));
+    w->sync2 = (unsigned int*)ws(c, WS_SYNC, 64);
+    const int64_t kk = s.k > s.l ? s.k : s.l;
+    w->R11 = (double*)ws(c, WS_R11, d * (size_t)(kk * kk));
+    if (!w->coop || !w->sync2 || !w->R11) return SID_ENOMEM;
+  }
   if (!w->omega || !w->part || !w->W || !w->Wr || !w->nrm || !w->piv || !w->R || !w->Q ||
       !w->keff || !w->stats || !w->Pd || !w->err)
     return SID_ENOMEM;
@@ -251,6 +265,10 @@ sid_status sid_create(sid_ctx** out, int device, void* hip_stream) {
   sid_ctx* c = new (std::nothrow) sid_ctx();
   if (!c) return SID_ENOMEM;
   c->device = device;
+  {
+    const char* env = std::getenv("SID_COOPERATIVE");
+    c->cooperative = env && env[0] == '1';
+  }
   int ncu = 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
       ncu > 0)
@@ -429,11 +447,16 @@ sid_status sid_compress(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N,
   s = run_sketch(ctx, A, dtype, lda, p, sh, w, w.W, sh.single ? w.Y : nullptr);
   if (s != SID_OK) return s;
   // (2) mgsqr on the selection rows of W
-  SID_CHECK(sid::launch_cpqr(st, w.W, lq, l, n_, k, p->rank_tol, w.Wr, w.nrm, w.piv, w.R, w.Q,
-                             w.keff, w.stats),
-            "pivoted QR");
-  // (3) coefficients P
-  SID_CHECK(sid::launch_backsolve(st, w.R, w.piv, w.keff, k, n_, w.Pd, P, ldp, f64),
+  if (sid::cpqr_coop_supported(l, n_))
+    SID_CHECK(sid::launch_cpqr_coop(st, w.W, lq, l, n_, k, p->rank_tol, w.coop, w.sync2, w.piv,
+                                    w.R, w.Q, w.keff, w.stats, ctx->cooperative),
+              "pivoted QR");
+  else
+    SID_CHECK(sid::launch_cpqr(st, w.W, lq, l, n_, k, p->rank_tol, w.Wr, w.nrm, w.piv, w.R, w.Q,
+                               w.keff, w.stats),
+              "pivoted QR");
+  // (3) coefficients P = R11^{-1} R(:, j) on the non-pivot columns
+  SID_CHECK(sid::launch_id_coefficients(st, w.R, n_, w.piv, w.keff, k, w.R11, w.Pd, P, ldp, f64),
             "coefficients");
   // (4) estimates: err[1] sketch fit (final residual of mgsqr), err[0] probe rows
   SID_CHECK(sid::launch_ratio_sqrt(st, w.stats, w.err + 1), "sketch residual");
@@ -459,15 +482,25 @@ sid_status sid_compress(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N,
     if (q > 0)
       SID_CHECK(sid::launch_gemm64(st, q, l, n_, w.W + lz, lq, 0, w.om64, l, 1, w.Mpr, q),
                 "Mpr = Wpr Omega");
-    SID_CHECK(sid::launch_cpqr(st, w.M, lz, lz, l, l, rcond, w.Wr, w.nrm, w.pivM, w.RM, w.QM,
-                               w.rkM, w.statsM),
-              "pivoted QR of M");
+    if (sid::cpqr_coop_supported(lz, l))
+      SID_CHECK(sid::launch_cpqr_coop(st, w.M, lz, lz, l, l, rcond, w.coop, w.sync2, w.pivM, w.RM,
+                                      w.QM, w.rkM, w.statsM, ctx->cooperative),
+                "pivoted QR of M");
+    else
+      SID_CHECK(sid::launch_cpqr(st, w.M, lz, lz, l, l, rcond, w.Wr, w.nrm, w.pivM, w.RM, w.QM,
+                                 w.rkM, w.statsM),
+                "pivoted QR of M");
     SID_CHECK(sid::launch_gather_block(st, w.W, lq, 0, lz, w.piv, w.keff, k, w.WJ), "W(:, J)");
     SID_CHECK(sid::launch_gemm64(st, l, k, lz, w.QM, lz, 1, w.WJ, lz, 0, w.C, l), "QM^T W(:, J)");
-    SID_CHECK(sid::launch_small_backsolve(st, w.RM, w.pivM, w.rkM, l, w.C, l, k, w.T), "T");
-    if (AJ)
-      SID_CHECK(sid::launch_apply_t(st, w.Y, sh.prec == SID_SK_F64, sh.N, l, w.T, k, AJ, f64, ldaj),
-                "AJ = Y T");
+    SID_CHECK(sid::launch_small_solve(st, w.RM, l, w.pivM, w.rkM, w.R11, w.C, l, k, w.T), "T");
+    if (AJ) {
+      const bool yf64 = sh.prec == SID_SK_F64;
+      if (sid::apply_t_mfma_supported(k, l, yf64))
+        SID_CHECK(sid::launch_apply_t_mfma(st, w.Y, yf64, sh.N, l, w.T, k, AJ, f64, ldaj),
+                  "AJ = Y T");
+      else
+        SID_CHECK(sid::launch_apply_t(st, w.Y, yf64, sh.N, l, w.T, k, AJ, f64, ldaj), "AJ = Y T");
+    }
     if (q > 0)
       SID_CHECK(sid::launch_gemm64(st, q, k, l, w.Mpr, q, 0, w.T, l, 0, w.mix, q), "Mpr T");
     SID_CHECK(sid::launch_fit_residual(st, w.W, lq, lz, q, n_, w.piv, w.keff, w.Pd, k,

@@ -1,0 +1,349 @@
+// sid_cpqr.hip -- the paper's mgsqr (column-pivoted modified Gram-Schmidt,
+// Sec. 2.4, Alg. 3-5 step 3) and the ID coefficient solve C = R11^+ R12
+// (Alg. 3-5, the step after mgsqr), FP64 on the GPU.
+//
+// mgsqr is a chain of k dependent steps (argmax of the residual column norms,
+// normalize the pivot, project it out of every other column), so its cost is
+// latency, not flops.  Here the residual matrix stays in registers, spread
+// over G cooperating workgroups (64 columns each, 4 threads per column), and
+// every step crosses exactly one device-wide barrier:
+//   1. each workgroup finds its best live column (ties: smallest index),
+//   2. publishes (norm^2, index, residual column) into a double-buffered slot,
+//   3. barrier (monotonic counter, bounded spin),
+//   4. every workgroup reads all G candidates and picks the same winner,
+//      normalizes its column into q (LDS) and updates its own columns
+//      (R(i, j) = q^T r_j, r_j -= R(i, j) q, new norm^2 of r_j).
+// The participating workgroups are spread 8 block indices apart so that, with
+// the round-robin workgroup-to-XCD dispatch, they share one XCD's L2.
+#include "sid_kernels.hpp"
+
+namespace sid {
+
+constexpr int CQ_THREADS = 256;
+constexpr int CQ_TPC = 4;                    // threads per column
+constexpr int CQ_CPW = CQ_THREADS / CQ_TPC;  // columns per workgroup
+constexpr unsigned CQ_SPIN_LIMIT = 1u << 22; // bounded wait (~0.1 s); never reached when co-resident
+
+__global__ void k_zero_u32(unsigned int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+template <typename T>
+__device__ __forceinline__ T ld_agent(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void better(double& bv, int& bj, double ov, int oj) {
+  if (ov > bv || (ov == bv && oj < bj)) {
+    bv = ov;
+    bj = oj;
+  }
+}
+
+// device-wide barrier over G workgroups: counter value after the b-th
+// barrier is G*b.  Only thread 0 waits; returns false on spin timeout.
+__device__ __forceinline__ bool grid_barrier(unsigned int* bar, unsigned target) {
+  __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  unsigned spins = 0;
+  while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    if (++spins > CQ_SPIN_LIMIT) return false;
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return true;
+}
+
+template <int RPT>
+__global__ __launch_bounds__(CQ_THREADS) void k_cpqr_coop(
+    const double* __restrict__ X, int64_t ldx, int m, int nc, int kmax, double rank_tol, int G,
+    int stride_blk, double* __restrict__ pub_v, int* __restrict__ pub_j,
+    double* __restrict__ pub_col, double* __restrict__ red, unsigned int* __restrict__ bar,
+    unsigned int* __restrict__ fail, int64_t* __restrict__ piv, double* __restrict__ R,
+    double* __restrict__ Q, int64_t* __restrict__ keff, double* __restrict__ stats) {
+  if (blockIdx.x % stride_blk) return;
+  const int g = blockIdx.x / stride_blk;
+  if (g >= G) return;
+  __shared__ double s_q[RPT * CQ_TPC];
+  __shared__ double s_wv[CQ_THREADS / 64];
+  __shared__ int s_wj[CQ_THREADS / 64];
+  __shared__ double s_win_v;
+  __shared__ int s_win_j, s_win_g;
+  __shared__ double s_sum[2][CQ_THREADS / 64];
+
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int cl = tid / CQ_TPC, seg = tid % CQ_TPC;
+  const int j = g * CQ_CPW + cl;
+  const bool mine = j < nc;
+
+  double w[RPT];
+  double ps = 0.0;
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int r = seg + CQ_TPC * i;
+    w[i] = (mine && r < m) ? X[r + ldx * j] : 0.0;
+    ps = fma(w[i], w[i], ps);
+  }
+  double nrm = ps;
+  nrm += __shfl_xor(nrm, 1, 64);
+  nrm += __shfl_xor(nrm, 2, 64);
+  const double tot_local = (seg == 0 && mine) ? nrm : 0.0;
+  bool alive = mine;
+  bool ok = true;
+
+  double first = -1.0;
+  int k = 0, nbar = 0;
+  for (; k < kmax; ++k) {
+    const int par = k & 1;
+    // 1. local argmax
+    double bv = alive ? nrm : -1.0;
+    int bj = alive ? j : 0x7fffffff;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) better(bv, bj, __shfl_xor(bv, o, 64), __shfl_xor(bj, o, 64));
+    if (lane == 0) { s_wv[wv] = bv; s_wj[wv] = bj; }
+    __syncthreads();
+    bv = s_wv[0];
+    bj = s_wj[0];
+    for (int u = 1; u < CQ_THREADS / 64; ++u) better(bv, bj, s_wv[u], s_wj[u]);
+    // 2. publish the candidate
+    if (tid == 0) {
+      pub_v[par * G + g] = bv;
+      pub_j[par * G + g] = bj;
+    }
+    if (alive && j == bj) {
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int r = seg + CQ_TPC * i;
+        if (r < m) pub_col[(int64_t)(par * G + g) * m + r] = w[i];
+      }
+    }
+    __threadfence();
+    __syncthreads();
+    // 3. barrier, 4. global winner
+    if (tid == 0) {
+      ok = grid_barrier(bar, (unsigned)G * (unsigned)(nbar + 1)) && ok;
+      double gv = -1.0;
+      int gj = 0x7fffffff, gg = 0;
+      for (int h = 0; h < G; ++h) {
+        const double v = ld_agent(&pub_v[par * G + h]);
+        const int jj = ld_agent(&pub_j[par * G + h]);
+        if (v > gv || (v == gv && jj < gj)) { gv = v; gj = jj; gg = h; }
+      }
+      s_win_v = gv;
+      s_win_j = gj;
+      s_win_g = gg;
+    }
+    ++nbar;
+    __syncthreads();
+    const double vmax = s_win_v;
+    const int p = s_win_j;
+    const int gp = s_win_g;
+    if (!(vmax > 0.0)) break;
+    const double nu = sqrt(vmax);
+    if (first < 0.0) first = nu;
+    else if (rank_tol > 0.0 && nu <= rank_tol * first) break;
+    for (int r = tid; r < m; r += CQ_THREADS)
+      s_q[r] = ld_agent(&pub_col[(int64_t)(par * G + gp) * m + r]) / nu;
+    __syncthreads();
+    if (g == 0) {
+      if (tid == 0) piv[k] = p;
+      for (int r = tid; r < m; r += CQ_THREADS) Q[r + (int64_t)m * k] = s_q[r];
+    }
+    // update: R(k, j) = q^T r_j, r_j -= R(k, j) q
+    double d = 0.0;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = seg + CQ_TPC * i;
+      if (r < m) d = fma(s_q[r], w[i], d);
+    }
+    d += __shfl_xor(d, 1, 64);
+    d += __shfl_xor(d, 2, 64);
+    if (mine && j == p) {
+      alive = false;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) w[i] = 0.0;
+      if (seg == 0) R[(int64_t)k * nc + j] = nu;
+    } else if (alive) {
+      ps = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int r = seg + CQ_TPC * i;
+        if (r < m) w[i] = fma(-d, s_q[r], w[i]);
+        ps = fma(w[i], w[i], ps);
+      }
+      if (seg == 0) R[(int64_t)k * nc + j] = d;
+    } else if (mine) {
+      ps = 0.0;
+      if (seg == 0) R[(int64_t)k * nc + j] = 0.0;
+    }
+    nrm = ps;
+    nrm += __shfl_xor(nrm, 1, 64);
+    nrm += __shfl_xor(nrm, 2, 64);
+  }
+
+  // statistics: final residual energy of live columns and ||X||_F^2
+  double res_local = (seg == 0 && alive) ? nrm : 0.0;
+  double a = res_local, b = tot_local;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o, 64);
+    b += __shfl_xor(b, o, 64);
+  }
+  if (lane == 0) { s_sum[0][wv] = a; s_sum[1][wv] = b; }
+  __syncthreads();
+  if (tid == 0) {
+    double sa = 0.0, sb = 0.0;
+    for (int u = 0; u < CQ_THREADS / 64; ++u) { sa += s_sum[0][u]; sb += s_sum[1][u]; }
+    red[2 * g] = sa;
+    red[2 * g + 1] = sb;
+    __threadfence();
+    ok = grid_barrier(bar, (unsigned)G * (unsigned)(nbar + 1)) && ok;
+    if (!ok) atomicOr(fail, 1u);
+    if (g == 0) {
+      double ta = 0.0, tb = 0.0;
+      for (int h = 0; h < G; ++h) { ta += ld_agent(&red[2 * h]); tb += ld_agent(&red[2 * h + 1]); }
+      stats[0] = ta;
+      stats[1] = tb;
+    }
+  }
+  if (g == 0) {
+    for (int i = k + tid; i < kmax; i += CQ_THREADS) piv[i] = -1;
+    if (tid == 0) *keff = k;
+  }
+}
+
+// keff := -1 when a cooperative wait timed out (results invalid)
+__global__ void k_mark_failure(const unsigned int* fail, int64_t* keff) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && *fail) *keff = -1;
+}
+
+bool cpqr_coop_supported(int m, int nc) { return m <= 256 && nc <= 64 * CQ_CPW && nc >= 1; }
+
+size_t cpqr_coop_scratch_bytes(int m, int nc) {
+  const int G = (nc + CQ_CPW - 1) / CQ_CPW;
+  return sizeof(double) * (size_t)(2 * G + 2 * G * m + 2 * G) + sizeof(int) * (size_t)(2 * G) +
+         64;
+}
+
+hipError_t launch_cpqr_coop(hipStream_t st, const double* X, int64_t ldx, int m, int nc, int kmax,
+                            double rank_tol, void* scratch, unsigned int* sync2, int64_t* piv,
+                            double* R, double* Q, int64_t* keff, double* stats,
+                            bool cooperative) {
+  const int G = (nc + CQ_CPW - 1) / CQ_CPW;
+  double* pub_v = (double*)scratch;
+  double* pub_col = pub_v + 2 * G;
+  double* red = pub_col + (size_t)2 * G * m;
+  int* pub_j = (int*)(red + 2 * G);
+  unsigned int* bar = sync2;
+  unsigned int* fail = sync2 + 1;
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, sync2, 2);
+  const int stride = (G <= 32) ? 8 : 1;
+  const dim3 grid((unsigned)(G * stride)), block(CQ_THREADS);
+  void* args[] = {(void*)&X, (void*)&ldx, (void*)&m, (void*)&nc, (void*)&kmax, (void*)&rank_tol,
+                  (void*)&G, (void*)&stride, (void*)&pub_v, (void*)&pub_j, (void*)&pub_col,
+                  (void*)&red, (void*)&bar, (void*)&fail, (void*)&piv, (void*)&R, (void*)&Q,
+                  (void*)&keff, (void*)&stats};
+  const int rpt = (m + CQ_TPC - 1) / CQ_TPC;
+  const void* kern = rpt <= 8    ? (const void*)k_cpqr_coop<8>
+                     : rpt <= 16 ? (const void*)k_cpqr_coop<16>
+                     : rpt <= 32 ? (const void*)k_cpqr_coop<32>
+                     : rpt <= 48 ? (const void*)k_cpqr_coop<48>
+                                 : (const void*)k_cpqr_coop<64>;
+  // The G workgroups must be resident together.  A cooperative launch
+  // guarantees it; a plain launch of at most 64 workgroups of 256 threads
+  // gets it on an otherwise idle device, and the bounded wait turns a
+  // failure into keff = -1 instead of a hang.
+  const hipError_t e = cooperative
+                           ? hipLaunchCooperativeKernel(kern, grid, block, args, 0, st)
+                           : hipLaunchKernel(kern, grid, block, args, 0, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mark_failure, dim3(1), dim3(64), 0, st, fail, keff);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Upper-triangular solves with many right-hand sides.
+// R11 (r x r, row-major ld r, r = *keff) gathered from the pivoted columns of
+// mgsqr's R: R11(a, b) = R(a, piv[b]).
+// ---------------------------------------------------------------------------
+__global__ void k_gather_r11(const double* __restrict__ R, int64_t ldr /* = nc */,
+                             const int64_t* __restrict__ piv, const int64_t* __restrict__ keff_p,
+                             int kcap, double* __restrict__ R11) {
+  const int keff = (int)*keff_p;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < kcap * kcap; e += gridDim.x * blockDim.x) {
+    const int a = e / kcap, b = e - a * kcap;
+    R11[e] = (a < keff && b < keff && b >= a) ? R[(int64_t)a * ldr + piv[b]] : 0.0;
+  }
+}
+
+// Solve R11 x = rhs_j for the columns j of a right-hand side.
+//  mode 0 (ID coefficients): rhs_j = R(0:keff, j) (R row-major ld nc); pivot
+//    columns get e_i; output Pd(:, j) (ld kcap) and P(:, j) (ld ldp, OutT).
+//  mode 1 (single-pass T): rhs_j = C(0:keff, j) (column-major ld ldc); x is
+//    scattered to T(piv[a], j) (ld ldt), other rows zero.
+// One thread per right-hand side; x in LDS (column of this thread).
+template <typename OutT, int MODE>
+__global__ __launch_bounds__(64) void k_trsv_multi(
+    const double* __restrict__ R11, int kcap, const int64_t* __restrict__ keff_p,
+    const int64_t* __restrict__ piv, const double* __restrict__ rhs, int64_t ldrhs, int ncols,
+    double* __restrict__ out64, int64_t ldo64, OutT* __restrict__ out, int64_t ldo) {
+  extern __shared__ double s_x[];  // kcap x 64
+  const int keff = (int)*keff_p;
+  const int t = threadIdx.x;
+  const int j = blockIdx.x * 64 + t;
+  if (j >= ncols) return;
+  int pos = -1;
+  if (MODE == 0)
+    for (int b = 0; b < keff; ++b)
+      if (piv[b] == j) pos = b;
+  if (pos < 0) {
+    for (int a = keff - 1; a >= 0; --a) {
+      double acc = (MODE == 0) ? rhs[(int64_t)a * ldrhs + j] : rhs[a + ldrhs * (int64_t)j];
+      const double* Ra = R11 + (int64_t)a * kcap;
+      for (int b = a + 1; b < keff; ++b) acc = fma(-Ra[b], s_x[b * 64 + t], acc);
+      s_x[a * 64 + t] = acc / Ra[a];
+    }
+  }
+  if (MODE == 0) {
+    double* x = out64 + ldo64 * j;
+    for (int a = 0; a < kcap; ++a) {
+      const double v = (pos >= 0) ? (a == pos ? 1.0 : 0.0) : (a < keff ? s_x[a * 64 + t] : 0.0);
+      x[a] = v;
+      if (out) out[a + ldo * j] = (OutT)v;
+    }
+  } else {
+    double* x = out64 + ldo64 * j;
+    for (int a = 0; a < kcap; ++a) x[a] = 0.0;
+    for (int a = 0; a < keff; ++a) x[piv[a]] = s_x[a * 64 + t];
+  }
+}
+
+template <typename OutT, int MODE>
+static hipError_t trsv_launch(hipStream_t st, const double* R11, int kcap, const int64_t* keff,
+                              const int64_t* piv, const double* rhs, int64_t ldrhs, int ncols,
+                              double* out64, int64_t ldo64, OutT* out, int64_t ldo) {
+  const size_t shm = sizeof(double) * (size_t)kcap * 64;
+  auto kern = k_trsv_multi<OutT, MODE>;
+  if (shm > 65536)
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL(kern, dim3((unsigned)((ncols + 63) / 64)), dim3(64), shm, st, R11, kcap, keff,
+                     piv, rhs, ldrhs, ncols, out64, ldo64, out, ldo);
+  return hipGetLastError();
+}
+
+hipError_t launch_id_coefficients(hipStream_t st, const double* R, int nc, const int64_t* piv,
+                                  const int64_t* keff, int kcap, double* R11, double* Pd,
+                                  void* P, int64_t ldp, bool p_is_f64) {
+  hipLaunchKernelGGL(k_gather_r11, dim3(64), dim3(256), 0, st, R, (int64_t)nc, piv, keff, kcap, R11);
+  if (p_is_f64)
+    return trsv_launch<double, 0>(st, R11, kcap, keff, piv, R, nc, nc, Pd, kcap, (double*)P, ldp);
+  return trsv_launch<float, 0>(st, R11, kcap, keff, piv, R, nc, nc, Pd, kcap, (float*)P, ldp);
+}
+
+hipError_t launch_small_solve(hipStream_t st, const double* RM, int l, const int64_t* pivM,
+                              const int64_t* rM, double* R11, const double* C, int64_t ldc, int kc,
+                              double* T) {
+  hipLaunchKernelGGL(k_gather_r11, dim3(64), dim3(256), 0, st, RM, (int64_t)l, pivM, rM, l, R11);
+  return trsv_launch<double, 1>(st, R11, l, rM, pivM, C, ldc, kc, T, l, (double*)nullptr, 0);
+}
+
+}  // namespace sid

@@ -51,4 +51,19 @@ hipError_t launch_sketch_fused_bf16(hipStream_t st, bool split, const float* A, 
                                     int64_t N, int n, int lq, int l, uint64_t seed,
                                     const float* omega, __bf16* omT, int num_cu, float* part,
                                     double* W, float* Y, int64_t* nparts_out);
+bool apply_t_mfma_supported(int k, int l, bool y_f64);
+bool cpqr_coop_supported(int m, int nc);
+size_t cpqr_coop_scratch_bytes(int m, int nc);
+hipError_t launch_cpqr_coop(hipStream_t st, const double* X, int64_t ldx, int m, int nc, int kmax,
+                            double rank_tol, void* scratch, unsigned int* sync2, int64_t* piv,
+                            double* R, double* Q, int64_t* keff, double* stats,
+                            bool cooperative);
+hipError_t launch_id_coefficients(hipStream_t st, const double* R, int nc, const int64_t* piv,
+                                  const int64_t* keff, int kcap, double* R11, double* Pd,
+                                  void* P, int64_t ldp, bool p_is_f64);
+hipError_t launch_small_solve(hipStream_t st, const double* RM, int l, const int64_t* pivM,
+                              const int64_t* rM, double* R11, const double* C, int64_t ldc, int kc,
+                              double* T);
+hipError_t launch_apply_t_mfma(hipStream_t st, const void* Y, bool y_f64, int64_t N, int l,
+                               const double* Tm, int k, void* AJ, bool aj_f64, int64_t ldaj);
 }  // namespace sid

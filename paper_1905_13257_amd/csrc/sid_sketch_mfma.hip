@@ -266,4 +266,144 @@ hipError_t launch_sketch_fused_bf16(hipStream_t st, bool split, const float* A, 
   return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------
+// Skeleton estimate of the single pass, AJ = Y T (N x k), on the matrix
+// cores.  Computed as AJ^T = T^T Y^T so that each MFMA output tile is
+// (16 skeleton columns) x (16 rows of A) and lands as coalesced column-major
+// stores.  v_mfma_{f32,f64}_16x16x4 layouts: A (16 x 4): lane l holds row
+// l%16, k = l/16; B (4 x 16): lane l holds col l%16, k = l/16; C: col l%16,
+// element t = row 4*(l/16) + t (f32) or row l/16 + 4*t (f64).  A lane reads 4 consecutive entries of one Y row at a
+// time; entry s of that quad feeds MFMA s, whose A operand therefore holds
+// T(kb + 4*(l/16) + s, m) -- the K order is permuted, the sum is the same.
+// T^T (kpad x lpad, zero padded) lives in LDS; each wave owns 32 rows of A
+// (two 16-row tiles) and all skeleton columns.
+// ---------------------------------------------------------------------------
+template <typename TE>
+struct MfmaK4;
+// crow(lg, t): output row held in accumulator element t by lanes 16*lg ..
+// 16*lg+15 (the FP32 and FP64 forms arrange the 16 x 16 result differently).
+template <>
+struct MfmaK4<float> {
+  typedef float acc_t __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc_t run(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int crow(int lg, int t) { return 4 * lg + t; }
+};
+template <>
+struct MfmaK4<double> {
+  typedef double acc_t __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc_t run(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int crow(int lg, int t) { return lg + 4 * t; }
+};
+
+constexpr int AT_WAVES = 4;
+constexpr int AT_RT = 2;  // 16-row tiles per wave
+
+template <typename TE, typename OutT, int CT>
+__global__ __launch_bounds__(64 * AT_WAVES) void k_apply_t_mfma(
+    const TE* __restrict__ Y, int64_t N, int l, const double* __restrict__ Tm /* l x k, ld l */,
+    int k, OutT* __restrict__ AJ, int64_t ldaj) {
+  using M = MfmaK4<TE>;
+  extern __shared__ __attribute__((aligned(16))) unsigned char s_raw[];
+  TE* s_tt = reinterpret_cast<TE*>(s_raw);  // T^T: [CT*16][lpad], m-major
+  const int lpad = (l + 15) & ~15;
+  for (int e = threadIdx.x; e < CT * 16 * lpad; e += blockDim.x) {
+    const int m = e / lpad, c = e - m * lpad;
+    s_tt[e] = (m < k && c < l) ? (TE)Tm[c + (int64_t)l * m] : TE(0);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int64_t row0 = ((int64_t)blockIdx.x * AT_WAVES + wave) * (AT_RT * 16);
+  typename M::acc_t acc[AT_RT][CT];
+#pragma unroll
+  for (int r = 0; r < AT_RT; ++r)
+#pragma unroll
+    for (int c = 0; c < CT; ++c) acc[r][c] = typename M::acc_t{0, 0, 0, 0};
+  const bool vec = (l % 4) == 0;
+  for (int kb = 0; kb < lpad; kb += 16) {
+    TE yv[AT_RT][4];
+#pragma unroll
+    for (int r = 0; r < AT_RT; ++r) {
+      const int64_t row = row0 + r * 16 + lr;
+      const int c0 = kb + 4 * lg;
+      if (row < N && vec && c0 + 4 <= l) {
+        const TE* src = Y + row * l + c0;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) yv[r][s] = src[s];
+      } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) yv[r][s] = (row < N && c0 + s < l) ? Y[row * l + c0 + s] : TE(0);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        const TE a = s_tt[(c * 16 + lr) * lpad + kb + 4 * lg + s];
+#pragma unroll
+        for (int r = 0; r < AT_RT; ++r) acc[r][c] = M::run(a, yv[r][s], acc[r][c]);
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < AT_RT; ++r) {
+    const int64_t row = row0 + r * 16 + lr;
+    if (row >= N) continue;
+#pragma unroll
+    for (int c = 0; c < CT; ++c)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int m = c * 16 + M::crow(lg, t);
+        if (m < k) AJ[row + ldaj * m] = (OutT)acc[r][c][t];
+      }
+  }
+}
+
+template <typename TE, typename OutT>
+static hipError_t apply_t_dispatch(hipStream_t st, const TE* Y, int64_t N, int l,
+                                   const double* Tm, int k, OutT* AJ, int64_t ldaj) {
+  const int ct = (k + 15) / 16;
+  const int lpad = (l + 15) & ~15;
+  const int64_t rows_per_block = AT_WAVES * AT_RT * 16;
+  const dim3 grid((unsigned)((N + rows_per_block - 1) / rows_per_block));
+#define SID_AT(CT_)                                                                        \
+  {                                                                                        \
+    const size_t shm = sizeof(TE) * (size_t)(CT_) * 16 * lpad;                             \
+    auto kern = k_apply_t_mfma<TE, OutT, CT_>;                                             \
+    if (shm > 65536) (void)hipFuncSetAttribute((const void*)kern,                          \
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                               (int)shm);                                  \
+    hipLaunchKernelGGL(kern, grid, dim3(64 * AT_WAVES), shm, st, Y, N, l, Tm, k, AJ, ldaj); \
+  }
+  if (ct <= 2) SID_AT(2)
+  else if (ct <= 4) SID_AT(4)
+  else if (ct <= 7) SID_AT(7)
+  else if (ct <= 10) SID_AT(10)
+  else return hipErrorInvalidValue;
+#undef SID_AT
+  return hipGetLastError();
+}
+
+bool apply_t_mfma_supported(int k, int l, bool y_f64) {
+  const int ct = (k + 15) / 16;
+  const int ctt = ct <= 2 ? 2 : ct <= 4 ? 4 : ct <= 7 ? 7 : 10;  // template tile count
+  const size_t shm = (y_f64 ? 8 : 4) * (size_t)ctt * 16 * ((l + 15) & ~15);
+  return ct <= 10 && shm <= 160 * 1024;
+}
+
+hipError_t launch_apply_t_mfma(hipStream_t st, const void* Y, bool y_f64, int64_t N, int l,
+                               const double* Tm, int k, void* AJ, bool aj_f64, int64_t ldaj) {
+  if (y_f64) {
+    if (aj_f64) return apply_t_dispatch<double, double>(st, (const double*)Y, N, l, Tm, k, (double*)AJ, ldaj);
+    return apply_t_dispatch<double, float>(st, (const double*)Y, N, l, Tm, k, (float*)AJ, ldaj);
+  }
+  if (aj_f64) return apply_t_dispatch<float, double>(st, (const float*)Y, N, l, Tm, k, (double*)AJ, ldaj);
+  return apply_t_dispatch<float, float>(st, (const float*)Y, N, l, Tm, k, (float*)AJ, ldaj);
+}
+
 }  // namespace sid
