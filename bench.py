@@ -34,7 +34,7 @@ PROFILE_DIR = os.path.join(ROOT, "profiles")
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("sid_kernels.hip", "sid_sketch_mfma.hip", "sid_device.hpp"):
+    for f in ("sid_kernels.hip", "sid_sketch_mfma.hip", "sid_cpqr.hip", "sid_device.hpp"):
         with open(os.path.join(ROOT, "paper_1905_13257_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

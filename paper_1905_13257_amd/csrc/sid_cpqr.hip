@@ -42,15 +42,19 @@ __device__ __forceinline__ void better(double& bv, int& bj, double ov, int oj) {
 }
 
 // device-wide barrier over G workgroups: counter value after the b-th
-// barrier is G*b.  Only thread 0 waits; returns false on spin timeout.
+// barrier is G*b.  Called by thread 0 after the workgroup's writers have
+// fenced their published data and the workgroup has synchronized; spins with
+// relaxed loads and acquires once.  Returns false on spin timeout.
 __device__ __forceinline__ bool grid_barrier(unsigned int* bar, unsigned target) {
-  __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   unsigned spins = 0;
-  while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-    if (++spins > CQ_SPIN_LIMIT) return false;
+  bool ok = true;
+  while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    if (++spins > CQ_SPIN_LIMIT) { ok = false; break; }
     __builtin_amdgcn_s_sleep(1);
   }
-  return true;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return ok;
 }
 
 template <int RPT>
@@ -104,10 +108,11 @@ __global__ __launch_bounds__(CQ_THREADS) void k_cpqr_coop(
     bv = s_wv[0];
     bj = s_wj[0];
     for (int u = 1; u < CQ_THREADS / 64; ++u) better(bv, bj, s_wv[u], s_wj[u]);
-    // 2. publish the candidate
+    // 2. publish the candidate (writers fence their own stores)
     if (tid == 0) {
       pub_v[par * G + g] = bv;
       pub_j[par * G + g] = bj;
+      __threadfence();
     }
     if (alive && j == bj) {
 #pragma unroll
@@ -115,24 +120,35 @@ __global__ __launch_bounds__(CQ_THREADS) void k_cpqr_coop(
         const int r = seg + CQ_TPC * i;
         if (r < m) pub_col[(int64_t)(par * G + g) * m + r] = w[i];
       }
+      __threadfence();
     }
-    __threadfence();
     __syncthreads();
-    // 3. barrier, 4. global winner
-    if (tid == 0) {
-      ok = grid_barrier(bar, (unsigned)G * (unsigned)(nbar + 1)) && ok;
-      double gv = -1.0;
-      int gj = 0x7fffffff, gg = 0;
-      for (int h = 0; h < G; ++h) {
-        const double v = ld_agent(&pub_v[par * G + h]);
-        const int jj = ld_agent(&pub_j[par * G + h]);
-        if (v > gv || (v == gv && jj < gj)) { gv = v; gj = jj; gg = h; }
-      }
-      s_win_v = gv;
-      s_win_j = gj;
-      s_win_g = gg;
-    }
+    // 3. barrier
+    if (tid == 0) ok = grid_barrier(bar, (unsigned)G * (unsigned)(nbar + 1)) && ok;
     ++nbar;
+    __syncthreads();
+    // 4. global winner: wave 0 fetches the G candidates in parallel
+    if (wv == 0) {
+      double v = -1.0;
+      int jj = 0x7fffffff, hh = 0x7fffffff;
+      if (lane < G) {
+        v = ld_agent(&pub_v[par * G + lane]);
+        jj = ld_agent(&pub_j[par * G + lane]);
+        hh = lane;
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(v, o, 64);
+        const int oj = __shfl_xor(jj, o, 64);
+        const int oh = __shfl_xor(hh, o, 64);
+        if (ov > v || (ov == v && oj < jj)) { v = ov; jj = oj; hh = oh; }
+      }
+      if (lane == 0) {
+        s_win_v = v;
+        s_win_j = jj;
+        s_win_g = hh;
+      }
+    }
     __syncthreads();
     const double vmax = s_win_v;
     const int p = s_win_j;

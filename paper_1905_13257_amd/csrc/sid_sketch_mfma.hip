@@ -7,19 +7,27 @@
 //   Y = A Omega (N x l, the range sketch of the two-sided single-pass sketch,
 //               Halko et al. Sec. 5.5 items (1)-(2), quoted in Sec. 2.3).
 //
-// Layout of the work.  One persistent 512-thread workgroup per CU owns a
-// contiguous range of rows of A and walks it in panels of 32 rows:
-//   * each wave loads its 64-column slice of the panel from HBM straight into
-//     registers in the MFMA B-operand layout (8 consecutive rows of one
-//     column per lane), splits FP32 -> bf16 hi (+ lo) and
-//       - accumulates W(:, slice) += Psi(:, panel) A(panel, slice) in
-//         registers (the W partial stays on chip for the whole row range);
-//       - writes the bf16 values transposed into LDS (row-major panel);
-//   * Psi(:, panel) is generated in place (Philox + Box-Muller, bf16) into
-//     LDS in the A-operand layout;
-//   * each wave then computes a 16 x 32 block of Y(panel, :) = A(panel, :)
-//     Omega from the row-major panel in LDS and Omega^T (bf16) read through
-//     L2, and stores it.
+// Layout of the work.  One persistent 256-thread workgroup per CU (one wave
+// per SIMD, so each wave can hold 256 VGPRs and 256 AGPRs) owns a contiguous
+// range of rows of A and walks it in panels of 64 rows.  A panel is consumed
+// in chunks of 64 columns; wave w owns columns 16w .. 16w+15 of every chunk.
+//   * Loads: each lane fetches 16 FP32 values of one column: four 64-byte
+//     runs per column, 256 contiguous bytes per column and chunk.  The loads
+//     of chunk c+1 are issued as soon as chunk c has been split into bf16,
+//     so they are in flight during chunk c's matrix products.
+//   * W(:, chunk) += Psi(:, panel) A(panel, chunk): the B operand comes
+//     straight from registers (hi and, in the split form, lo bf16 parts).
+//     The W partial of the whole row range stays on chip: W rows 0..127 in
+//     accumulation registers (8 x 8 tiles x 4 = 256 per lane, exactly the
+//     AGPR file), rows 128..lq-1 in an LDS array to which each chunk's
+//     product is added (one read-add-write per tile and chunk).
+//   * The same bf16 values are written transposed into a row-major chunk
+//     buffer in LDS; after one barrier per chunk each wave forms
+//     Y(panel, its column tiles) += A(panel, chunk) Omega(chunk, :) with
+//     Omega^T (bf16) read through L2.  The Y accumulators cover the panel
+//     and are stored after its last chunk.
+//   * Psi(:, next panel) is generated (Philox + Box-Muller, bf16) into the
+//     other half of a double-buffered LDS array, one slice per chunk.
 // The W partial of each workgroup is written once at the end (FP32) and the
 // partials are summed in a fixed order in FP64 by k_reduce_partials_f32.
 //
@@ -27,6 +35,13 @@
 //   A (16 x 32): lane l holds row l%16, k = 8*(l/16) .. +7
 //   B (32 x 16): lane l holds col l%16, k = 8*(l/16) .. +7
 //   C (16 x 16): lane l holds col l%16, rows 4*(l/16) .. +3
+// The contraction of W runs over panel rows in a permuted order: within a
+// 32-row step, operand slot 8g+i (g = l/16) holds row 4g+i for i < 4 and row
+// 16+4g+(i-4) for i >= 4, which makes every load instruction read 64
+// contiguous bytes per column.  Psi is stored in LDS in the same slot order,
+// so the products pair up as in the plain order.
+#include <type_traits>
+
 #include "sid_kernels.hpp"
 
 namespace sid {
@@ -36,24 +51,119 @@ typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 constexpr int FB_WAVES = 4;                  // one wave per SIMD
 constexpr int FB_THREADS = 64 * FB_WAVES;
-constexpr int FB_PB = 32;                    // rows per panel (one K step of 32)
-constexpr int FB_CTW = 8;                    // 16-column tiles per wave -> 128 columns per wave
-constexpr int FB_NPAD = FB_WAVES * 16 * FB_CTW;  // 512: max columns
-constexpr int FB_AROW = FB_NPAD + 8;      // LDS row stride of the panel (bf16), padded
-constexpr int FB_PROW = FB_PB + 8;        // LDS row stride of Psi (bf16), padded
+constexpr int FB_PR = 64;                    // rows per panel (two K steps of 32)
+constexpr int FB_CHUNK = 16 * FB_WAVES;      // columns per chunk
+constexpr int FB_NCH = 8;                    // max chunks
+constexpr int FB_NPAD = FB_CHUNK * FB_NCH;   // 512: max columns
+constexpr int FB_KS = FB_CHUNK / 32;         // K steps of the Y product per chunk
+constexpr int FB_CROW = FB_CHUNK + 8;        // LDS row stride of a chunk (bf16)
+constexpr int FB_PROW = FB_PR + 8;           // LDS row stride of Psi (bf16)
+constexpr int FB_MTR = 8;                    // W row tiles kept in registers
 
 __device__ __forceinline__ __bf16 to_bf16(float f) { return (__bf16)f; }
 
-// MT: 16-row tiles of W (lq <= 16*MT); LT: 16-column tiles of Y (l <= 16*LT)
-template <bool SPLIT, int MT, int LT>
+// Workgroup barrier that waits for this wave's LDS traffic only: global
+// loads issued before it (the next chunk) stay in flight.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_sched_barrier(0);
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// panel row of operand slot (ks, g, i)
+__device__ __forceinline__ int slot_row(int ks, int g, int i) {
+  return 32 * ks + (i < 4 ? 4 * g + i : 16 + 4 * g + (i - 4));
+}
+// operand slot of panel row r
+__device__ __forceinline__ int row_slot(int r) {
+  const int q = r & 31;
+  return (r & ~31) + 8 * ((q & 15) >> 2) + (q & 3) + 4 * (q >> 4);
+}
+
+// Chunk loads of one wave: lane (col lr, group lg) gets slots 0..15 of its
+// column (K steps 0 and 1).  pc = A + (first row of the panel); col is this
+// lane's column.  Columns at or beyond n read column n-1; the caller zeroes
+// them when it converts (a select here would wait for the load at once).
+__device__ __forceinline__ const float* chunk_col(const float* pc, int64_t lda, int n, int col,
+                                                  int lg) {
+  int colc = col < n ? col : n - 1;
+  // opaque: the 64-bit column offsets would otherwise be hoisted out of the
+  // panel loop (two registers per chunk); recomputing one is two
+  // multiply-adds
+  asm volatile("" : "+v"(colc));
+  return pc + (int64_t)colc * lda + 4 * lg;
+}
+
+// full panel: four 16-byte loads per lane, slot 4h+t = row 16h + 4lg + t
+__device__ __forceinline__ void load_chunk(const float* __restrict__ pc, int64_t lda, int n, int col,
+                                           int lg, float (&v)[16]) {
+  typedef const __attribute__((address_space(1))) f32x4_t* gptr4;
+  const float* base = chunk_col(pc, lda, n, col, lg);
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const f32x4_t a = __builtin_nontemporal_load((gptr4)(base + 16 * h));
+#pragma unroll
+    for (int t = 0; t < 4; ++t) v[4 * h + t] = a[t];
+  }
+}
+
+// ragged tail panel (rows_left < 64 rows exist): rows past the end read the
+// last row and are zeroed
+__device__ __forceinline__ void load_chunk_tail(const float* __restrict__ pc, int64_t lda, int n,
+                                                int col, int rows_left, int lg, float (&v)[16]) {
+  typedef const __attribute__((address_space(1))) float* gptr;
+  const gptr base = (gptr)(chunk_col(pc, lda, n, col, lg) - 4 * lg);
+#pragma unroll
+  for (int h = 0; h < 4; ++h)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int r = 16 * h + 4 * lg + t;
+      const bool ok = r < rows_left;
+      const float x = base[ok ? r : rows_left - 1];
+      v[4 * h + t] = ok ? x : 0.0f;
+    }
+}
+
+// Items [i0, i1) of Psi(0:lq, panel p0): item w covers panel row w % 64 and
+// rows 4*(w/64) .. +3 of Psi.  Written in operand-slot order.
+__device__ __forceinline__ void gen_psi(__bf16* __restrict__ s_psi, uint64_t seed, int64_t p0,
+                                        int64_t r1, int lq, int i0, int i1, int tid) {
+  // opaque thread index: the start items of the slices would otherwise be
+  // hoisted out of the panel loop and pin registers
+  asm volatile("" : "+v"(tid));
+#pragma unroll 1
+  for (int w = i0 + tid; w < i1; w += FB_THREADS) {
+    const int kk = w & (FB_PR - 1), g = w / FB_PR;
+    float z[4] = {0.f, 0.f, 0.f, 0.f};
+    if (p0 + kk < r1) gauss4(seed, 1u, (uint64_t)(p0 + kk), (uint32_t)g, z);
+    const int pos = row_slot(kk);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int m = 4 * g + e;
+      if (m < lq) s_psi[m * FB_PROW + pos] = to_bf16(z[e]);
+    }
+  }
+}
+
+// MT: 16-row tiles of W (lq <= 16*MT); LT: 16-column tiles of Y (l <= 16*LT);
+// NCH: chunks of 64 columns per panel (n <= 64*NCH, even); WANTY: form Y.
+// Every count that shapes the register state is a template argument, so the
+// chunk loop unrolls into straight-line code with no merges of accumulators.
+template <bool SPLIT, bool WANTY, int MT, int LT, int NCH>
 __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
     const float* __restrict__ A, int64_t lda, int64_t N, int n, int lq, int l, uint64_t seed,
     const __bf16* __restrict__ omT /* LT*16 x FB_NPAD, k contiguous, zero padded */,
     int64_t rows_per_wg, float* __restrict__ part /* grid x lq x n */, float* __restrict__ Y) {
-  static_assert((2 * LT) % FB_WAVES == 0, "Y tiles are split evenly over the waves");
-  __shared__ __attribute__((aligned(16))) __bf16 s_ahi[FB_PB * FB_AROW];
-  __shared__ __attribute__((aligned(16))) __bf16 s_alo[SPLIT ? FB_PB * FB_AROW : 8];
-  __shared__ __attribute__((aligned(16))) __bf16 s_psi[MT * 16 * FB_PROW];
+  static_assert(LT % FB_WAVES == 0, "Y column tiles are split evenly over the waves");
+  static_assert(NCH % 2 == 0 && NCH <= FB_NCH, "chunk count (even: two chunk buffers)");
+  constexpr int YC = LT / FB_WAVES;               // Y column tiles per wave (all 4 row tiles)
+  constexpr int NH = SPLIT ? 2 : 1;               // bf16 terms per value
+  constexpr int MTR = MT < FB_MTR ? MT : FB_MTR;  // W row tiles in registers
+  constexpr int MTX = MT - MTR;                   // W row tiles accumulated in LDS
+  __shared__ __attribute__((aligned(16))) __bf16 s_psi[2][MT * 16 * FB_PROW];
+  __shared__ __attribute__((aligned(16))) __bf16 s_chk[2][NH][FB_PR * FB_CROW];
+  // W rows 16 MTR .. 16 MT - 1, in C-fragment order: [mtx][chunk][wave][lane][4]
+  __shared__ __attribute__((aligned(16))) float s_wx[MTX > 0 ? MTX * NCH * FB_THREADS * 4 : 4];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -61,138 +171,201 @@ __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
   int64_t r1 = r0 + rows_per_wg;
   if (r1 > N) r1 = N;
-
-  // Psi rows >= lq stay zero for the whole kernel
-  for (int e = tid; e < MT * 16 * FB_PROW; e += FB_THREADS) s_psi[e] = to_bf16(0.0f);
-
-  f32x4_t wacc[MT][FB_CTW];
-#pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-    for (int ct = 0; ct < FB_CTW; ++ct) wacc[mt][ct] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-
-  // Y tiles of this wave: row tile yr (0/1), column tiles yc0 .. yc0 + YT - 1
-  constexpr int YT = 2 * LT / FB_WAVES;
-  const int yr = wave & 1;
-  const int yc0 = (wave >> 1) * YT;
+  constexpr int nch = NCH;  // chunks per panel
   const int lq4 = (lq + 3) >> 2;
+  const int gen_items = FB_PR * lq4;
 
-  for (int64_t p0 = r0; p0 < r1; p0 += FB_PB) {
-    const int nrow = (int)((r1 - p0 < FB_PB) ? (r1 - p0) : FB_PB);
-    __syncthreads();  // previous panel's LDS reads are done
+  // Psi rows >= lq stay zero for the whole kernel; the LDS part of W starts
+  // at zero
+  for (int e = tid; e < 2 * MT * 16 * FB_PROW; e += FB_THREADS) (&s_psi[0][0])[e] = to_bf16(0.0f);
+  if constexpr (MTX > 0)
+    for (int e = tid; e < MTX * NCH * FB_THREADS * 4; e += FB_THREADS) s_wx[e] = 0.0f;
 
-    // (1) issue the loads of this wave's A slice (B-operand layout: lane =
-    //     8 consecutive panel rows of one column), FP32 in registers
-    float v[FB_CTW][8];
-    const int rl = 8 * lg;  // first panel row of this lane
+  f32x4_t wacc[MTR][NCH];
 #pragma unroll
-    for (int ct = 0; ct < FB_CTW; ++ct) {
-      const int col = wave * (16 * FB_CTW) + ct * 16 + lr;
-      if (col < n && rl + 8 <= nrow) {
-        const f32x4_t* src = reinterpret_cast<const f32x4_t*>(A + (int64_t)col * lda + p0 + rl);
-        const f32x4_t a0 = __builtin_nontemporal_load(src);
-        const f32x4_t a1 = __builtin_nontemporal_load(src + 1);
+  for (int mt = 0; mt < MTR; ++mt)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          v[ct][t] = a0[t];
-          v[ct][4 + t] = a1[t];
+    for (int j = 0; j < NCH; ++j) wacc[mt][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  f32x4_t yacc[4][YC];
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+    for (int y = 0; y < YC; ++y) yacc[rt][y] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+  // full panels end at r1f; a ragged tail panel [r1f, r1) is handled last
+  const int64_t r1f = r0 + ((r1 - r0) / FB_PR) * FB_PR;
+  const int col_w = 16 * wave + lr;  // this lane's column within a chunk
+  float v[16];                       // this wave's slice of the chunk in flight
+  if (r0 < r1f) load_chunk(A + r0, lda, n, col_w, lg, v);
+  lds_barrier();  // zeroed Psi visible
+  if (r0 < r1) gen_psi(s_psi[0], seed, r0, r1, lq, 0, gen_items, tid);
+  lds_barrier();
+
+  // per-lane offset of this lane's Omega^T fragments (bf16 elements)
+  const uint32_t om_lane = (uint32_t)((wave * YC * 16 + lr) * FB_NPAD + 8 * lg);
+  typedef const __attribute__((address_space(1))) __bf16* gbf16p;
+  typedef const __attribute__((address_space(1))) bf16x8_t* gbf16x8p;
+
+  // One panel of FB_PR rows starting at p0 (Psi in buffer pb).  TAIL: the
+  // ragged last panel with `rows` < FB_PR rows; its chunks are loaded on the
+  // spot and nothing is prefetched.  Otherwise v holds chunk 0 on entry and
+  // the first chunk of the next full panel on exit.
+  auto panel = [&](auto tail_tag, int64_t p0, int pb) {
+    constexpr bool TAIL = decltype(tail_tag)::value;
+    const int64_t pn = p0 + FB_PR;
+    const int rows = TAIL ? (int)(r1 - p0) : FB_PR;
+    const __bf16* psi = s_psi[pb];
+#pragma unroll
+    for (int j = 0; j < NCH; ++j) {
+      const bool col_ok = col_w + FB_CHUNK * j < n;
+      __bf16* chk_hi = s_chk[j & 1][0];
+      __bf16* chk_lo = s_chk[j & 1][NH - 1];
+      if constexpr (TAIL) load_chunk_tail(A + p0, lda, n, col_w + FB_CHUNK * j, rows, lg, v);
+      // (1) Omega^T fragments of this chunk.  They are issued before the
+      //     next chunk's loads, so that waiting for them never waits for
+      //     those (vmcnt counts in issue order).  Omega^T is the same for
+      //     every panel; the opaque copy of its address keeps the compiler
+      //     from hoisting the fragments of all chunks out of the loop.
+      bf16x8_t of[FB_KS][YC];
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (WANTY) {
+        uintptr_t om_addr = (uintptr_t)omT;
+        asm volatile("" : "+s"(om_addr));
+        const gbf16p om = (gbf16p)om_addr;
+#pragma unroll
+        for (int ks = 0; ks < FB_KS; ++ks)
+#pragma unroll
+          for (int y = 0; y < YC; ++y)
+            of[ks][y] = *(gbf16x8p)(om + (om_lane + (uint32_t)(y * 16 * FB_NPAD + FB_CHUNK * j + 32 * ks)));
+      }
+      // (2) split into bf16 hi (+ lo) B operands and the transposed copy
+      bf16x8_t bh[2], bl[2];
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const float x = col_ok ? v[8 * ks + i] : 0.0f;
+          const __bf16 h = to_bf16(x);
+          bh[ks][i] = h;
+          const int ci = slot_row(ks, lg, i) * FB_CROW + col_w;
+          if constexpr (WANTY) chk_hi[ci] = h;
+          if constexpr (SPLIT) {
+            const __bf16 lo = to_bf16(x - (float)h);
+            bl[ks][i] = lo;
+            if constexpr (WANTY) chk_lo[ci] = lo;
+          }
         }
-      } else {
-#pragma unroll
-        for (int t = 0; t < 8; ++t)
-          v[ct][t] = (col < n && rl + t < nrow) ? A[(int64_t)col * lda + p0 + rl + t] : 0.0f;
-      }
-    }
-
-    // (2) Psi(0:lq, panel) in place, A-operand layout s_psi[m][k]
-#pragma unroll 1
-    for (int w = tid; w < FB_PB * lq4; w += FB_THREADS) {
-      const int kk = w / lq4, g = w - kk * lq4;
-      float z[4] = {0.f, 0.f, 0.f, 0.f};
-      if (kk < nrow) gauss4(seed, 1u, (uint64_t)(p0 + kk), (uint32_t)g, z);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int m = 4 * g + e;
-        if (m < lq) s_psi[m * FB_PROW + kk] = to_bf16(z[e]);
-      }
-    }
-    __syncthreads();
-
-    // (3) split to bf16 hi (+ lo), with a transposed copy into the row-major
-    //     panel for Y, then W(:, slice) += Psi(:, panel) A(panel, slice)
-    bf16x8_t bhi[FB_CTW], blo[FB_CTW];
-#pragma unroll
-    for (int ct = 0; ct < FB_CTW; ++ct) {
-      const int col = wave * (16 * FB_CTW) + ct * 16 + lr;
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const __bf16 h = to_bf16(v[ct][t]);
-        bhi[ct][t] = h;
-        s_ahi[(rl + t) * FB_AROW + col] = h;
-        if constexpr (SPLIT) {
-          const __bf16 lo = to_bf16(v[ct][t] - (float)h);
-          blo[ct][t] = lo;
-          s_alo[(rl + t) * FB_AROW + col] = lo;
+      // (3) the next chunk's loads: in flight during the products, the Psi
+      //     slice and the Y product below
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (!TAIL) {
+        if (j + 1 < NCH) {
+          load_chunk(A + p0, lda, n, col_w + FB_CHUNK * (j + 1), lg, v);
+        } else if (pn < r1f) {
+          load_chunk(A + pn, lda, n, col_w, lg, v);
         }
       }
-    }
+      __builtin_amdgcn_sched_barrier(0);
+      // (4) W(:, chunk) += Psi(:, panel) A(panel, chunk)
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      const bf16x8_t af = *reinterpret_cast<const bf16x8_t*>(&s_psi[(mt * 16 + lr) * FB_PROW + 8 * lg]);
+      for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
-      for (int ct = 0; ct < FB_CTW; ++ct) {
-        wacc[mt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bhi[ct], wacc[mt][ct], 0, 0, 0);
-        if constexpr (SPLIT)
-          wacc[mt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, blo[ct], wacc[mt][ct], 0, 0, 0);
-      }
-    }
-    __syncthreads();  // row-major panel complete
-
-    // (4) Y(panel rows yr*16.., cols yc..) = A(panel, :) Omega
-    if (Y) {
-      f32x4_t yacc[YT];
+        for (int mt = 0; mt < MTR; ++mt) {
+          const bf16x8_t af =
+              *reinterpret_cast<const bf16x8_t*>(&psi[(mt * 16 + lr) * FB_PROW + 32 * ks + 8 * lg]);
+          wacc[mt][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bh[ks], wacc[mt][j], 0, 0, 0);
+          if constexpr (SPLIT)
+            wacc[mt][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bl[ks], wacc[mt][j], 0, 0, 0);
+        }
+      if constexpr (MTX > 0) {
 #pragma unroll
-      for (int j = 0; j < YT; ++j) yacc[j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-      const int ncol_pad = (n + 31) & ~31;
-#pragma unroll 1
-      for (int k0 = 0; k0 < ncol_pad; k0 += 32) {
-        const bf16x8_t ah = *reinterpret_cast<const bf16x8_t*>(&s_ahi[(yr * 16 + lr) * FB_AROW + k0 + 8 * lg]);
-        bf16x8_t al;
-        if constexpr (SPLIT) al = *reinterpret_cast<const bf16x8_t*>(&s_alo[(yr * 16 + lr) * FB_AROW + k0 + 8 * lg]);
+        for (int mx = 0; mx < MTX; ++mx) {
+          f32x4_t* wx = reinterpret_cast<f32x4_t*>(&s_wx[(((mx * NCH + j) * FB_WAVES + wave) * 64 + lane) * 4]);
+          f32x4_t acc = f32x4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int j = 0; j < YT; ++j) {
-          const bf16x8_t of = *reinterpret_cast<const bf16x8_t*>(&omT[(int64_t)((yc0 + j) * 16 + lr) * FB_NPAD + k0 + 8 * lg]);
-          yacc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, of, yacc[j], 0, 0, 0);
-          if constexpr (SPLIT) yacc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, of, yacc[j], 0, 0, 0);
+          for (int ks = 0; ks < 2; ++ks) {
+            const bf16x8_t af = *reinterpret_cast<const bf16x8_t*>(
+                &psi[((MTR + mx) * 16 + lr) * FB_PROW + 32 * ks + 8 * lg]);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bh[ks], acc, 0, 0, 0);
+            if constexpr (SPLIT) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bl[ks], acc, 0, 0, 0);
+          }
+          *wx += acc;
         }
       }
+      // (5) slice j of Psi(:, next panel)
+      if (!TAIL && pn < r1)
+        gen_psi(s_psi[pb ^ 1], seed, pn, r1, lq, gen_items * j / NCH, gen_items * (j + 1) / NCH, tid);
+      lds_barrier();  // chunk buffer complete
+      // (6) Y(panel, this wave's tiles) += A(panel, chunk) Omega(chunk, :)
+      if constexpr (WANTY) {
 #pragma unroll
-      for (int j = 0; j < YT; ++j) {
-        const int c = (yc0 + j) * 16 + lr;
-        if (c < l) {
+        for (int ks = 0; ks < FB_KS; ++ks) {
 #pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int rr = yr * 16 + 4 * lg + t;
-            if (rr < nrow) Y[(p0 + rr) * (int64_t)l + c] = yacc[j][t];
+          for (int rt = 0; rt < 4; ++rt) {
+            const int ci = (rt * 16 + lr) * FB_CROW + 32 * ks + 8 * lg;
+            const bf16x8_t ah = *reinterpret_cast<const bf16x8_t*>(&chk_hi[ci]);
+#pragma unroll
+            for (int y = 0; y < YC; ++y)
+              yacc[rt][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, of[ks][y], yacc[rt][y], 0, 0, 0);
+            if constexpr (SPLIT) {
+              const bf16x8_t al = *reinterpret_cast<const bf16x8_t*>(&chk_lo[ci]);
+#pragma unroll
+              for (int y = 0; y < YC; ++y)
+                yacc[rt][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, of[ks][y], yacc[rt][y], 0, 0, 0);
+            }
           }
         }
       }
     }
-  }
+    // Y(panel, this wave's column tiles)
+    if constexpr (WANTY) {
+      // opaque 4lg: keeps the 64-bit row offsets from being hoisted out of
+      // the panel loop
+      int lg4 = 4 * lg;
+      asm volatile("" : "+v"(lg4));
+      float* yp = Y + p0 * (int64_t)l;
+#pragma unroll
+      for (int y = 0; y < YC; ++y) {
+        const int c = (wave * YC + y) * 16 + lr;
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int rr = rt * 16 + lg4 + t;
+            if (c < l && (!TAIL || rr < rows)) yp[rr * l + c] = yacc[rt][y][t];
+          }
+          yacc[rt][y] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        }
+      }
+    }
+  };
+
+  int pb = 0;  // Psi buffer of the current panel
+  int64_t p0 = r0;
+  for (; p0 < r1f; p0 += FB_PR, pb ^= 1) panel(std::false_type{}, p0, pb);
+  if (p0 < r1) panel(std::true_type{}, p0, pb);
 
   // W partial of this workgroup (FP32, column-major lq x n)
   float* dst = part + (int64_t)blockIdx.x * lq * n;
 #pragma unroll
-  for (int ct = 0; ct < FB_CTW; ++ct) {
-    const int col = wave * (16 * FB_CTW) + ct * 16 + lr;
+  for (int j = 0; j < NCH; ++j) {
+    const int col = FB_CHUNK * j + col_w;
     if (col >= n) continue;
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < MT; ++mt) {
+      f32x4_t w4;
+      if (mt < MTR) {
+        w4 = wacc[mt < MTR ? mt : 0][j];
+      } else {
+        w4 = *reinterpret_cast<const f32x4_t*>(
+            &s_wx[((((mt - MTR) * NCH + j) * FB_WAVES + wave) * 64 + lane) * 4]);
+      }
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int m = mt * 16 + 4 * lg + t;
-        if (m < lq) dst[m + (int64_t)lq * col] = wacc[mt][ct][t];
+        if (m < lq) dst[m + (int64_t)lq * col] = w4[t];
       }
+    }
   }
 }
 
@@ -223,8 +396,8 @@ bool fused_bf16_supported(int64_t n, int lq, int l, int64_t lda, const void* A, 
 int64_t fused_bf16_grid(int64_t N, int num_cu, int64_t* rows_per_wg) {
   int64_t g = num_cu;
   int64_t rpw = (N + g - 1) / g;
-  rpw = (rpw + FB_PB - 1) / FB_PB * FB_PB;
-  if (rpw < FB_PB) rpw = FB_PB;
+  rpw = (rpw + FB_PR - 1) / FB_PR * FB_PR;
+  if (rpw < FB_PR) rpw = FB_PR;
   g = (N + rpw - 1) / rpw;
   *rows_per_wg = rpw;
   return g;
@@ -234,7 +407,7 @@ hipError_t launch_sketch_fused_bf16(hipStream_t st, bool split, const float* A, 
                                     int64_t N, int n, int lq, int l, uint64_t seed,
                                     const float* omega, __bf16* omT, int num_cu, float* part,
                                     double* W, float* Y, int64_t* nparts_out) {
-  const int lpad = ((l + 63) / 64) * 64;  // Y tiles: multiple of 4 tiles of 16
+  const int lpad = ((l + 63) / 64) * 64;  // Y tiles: a multiple of 4 tiles of 16
   if (Y) {
     hipLaunchKernelGGL(k_omega_t_bf16, dim3(256), dim3(256), 0, st, omega, n, l, lpad, omT);
   }
@@ -242,19 +415,25 @@ hipError_t launch_sketch_fused_bf16(hipStream_t st, bool split, const float* A, 
   const int64_t grid = fused_bf16_grid(N, num_cu, &rpw);
   *nparts_out = grid;
   const int mt = (lq + 15) / 16;
-#define SID_FUSED(SP, MT_, LT_)                                                                   \
-  hipLaunchKernelGGL((k_sketch_fused_bf16<SP, MT_, LT_>), dim3((unsigned)grid), dim3(FB_THREADS), \
-                     0, st, A, lda, N, n, lq, l, seed, omT, rpw, part, Y)
-#define SID_FUSED_LT(SP, MT_) \
-  if (lpad <= 64) SID_FUSED(SP, MT_, 4); else SID_FUSED(SP, MT_, 8);
-#define SID_FUSED_MT(SP)                                 \
-  if (mt <= 4) { SID_FUSED_LT(SP, 4) }                   \
-  else if (mt <= 6) { SID_FUSED_LT(SP, 6) }              \
-  else if (mt <= 8) { SID_FUSED_LT(SP, 8) }              \
-  else { SID_FUSED_LT(SP, 10) }
-  if (split) { SID_FUSED_MT(true) } else { SID_FUSED_MT(false) }
+  const int nch = (n + FB_CHUNK - 1) / FB_CHUNK;
+#define SID_FUSED(SP, WY, MT_, LT_, NCH_)                                                  \
+  hipLaunchKernelGGL((k_sketch_fused_bf16<SP, WY, MT_, LT_, NCH_>), dim3((unsigned)grid), \
+                     dim3(FB_THREADS), 0, st, A, lda, N, n, lq, l, seed, omT, rpw, part, Y)
+#define SID_FUSED_NCH(SP, WY, MT_, LT_)              \
+  if (nch <= 2) SID_FUSED(SP, WY, MT_, LT_, 2);      \
+  else if (nch <= 4) SID_FUSED(SP, WY, MT_, LT_, 4); \
+  else SID_FUSED(SP, WY, MT_, LT_, 8);
+#define SID_FUSED_MT(SP, WY, LT_)                          \
+  if (mt <= 4) { SID_FUSED_NCH(SP, WY, 4, LT_) }           \
+  else { SID_FUSED_NCH(SP, WY, 10, LT_) }
+#define SID_FUSED_SP(SP)                                     \
+  if (!Y) { SID_FUSED_MT(SP, false, 4) }                     \
+  else if (lpad <= 64) { SID_FUSED_MT(SP, true, 4) }         \
+  else { SID_FUSED_MT(SP, true, 8) }
+  if (split) { SID_FUSED_SP(true) } else { SID_FUSED_SP(false) }
+#undef SID_FUSED_SP
 #undef SID_FUSED_MT
-#undef SID_FUSED_LT
+#undef SID_FUSED_NCH
 #undef SID_FUSED
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -309,10 +488,11 @@ __global__ __launch_bounds__(64 * AT_WAVES) void k_apply_t_mfma(
     int k, OutT* __restrict__ AJ, int64_t ldaj) {
   using M = MfmaK4<TE>;
   extern __shared__ __attribute__((aligned(16))) unsigned char s_raw[];
-  TE* s_tt = reinterpret_cast<TE*>(s_raw);  // T^T: [CT*16][lpad], m-major
+  TE* s_tt = reinterpret_cast<TE*>(s_raw);  // T^T: [CT*16][lst], m-major
   const int lpad = (l + 15) & ~15;
-  for (int e = threadIdx.x; e < CT * 16 * lpad; e += blockDim.x) {
-    const int m = e / lpad, c = e - m * lpad;
+  const int lst = lpad + 1;  // odd stride: the 16 rows read together hit 16 banks
+  for (int e = threadIdx.x; e < CT * 16 * lst; e += blockDim.x) {
+    const int m = e / lst, c = e - m * lst;
     s_tt[e] = (m < k && c < l) ? (TE)Tm[c + (int64_t)l * m] : TE(0);
   }
   __syncthreads();
@@ -332,9 +512,10 @@ __global__ __launch_bounds__(64 * AT_WAVES) void k_apply_t_mfma(
       const int64_t row = row0 + r * 16 + lr;
       const int c0 = kb + 4 * lg;
       if (row < N && vec && c0 + 4 <= l) {
-        const TE* src = Y + row * l + c0;
+        typedef TE te4 __attribute__((ext_vector_type(4)));
+        const te4 q4 = *reinterpret_cast<const te4*>(Y + row * l + c0);
 #pragma unroll
-        for (int s = 0; s < 4; ++s) yv[r][s] = src[s];
+        for (int s = 0; s < 4; ++s) yv[r][s] = q4[s];
       } else {
 #pragma unroll
         for (int s = 0; s < 4; ++s) yv[r][s] = (row < N && c0 + s < l) ? Y[row * l + c0 + s] : TE(0);
@@ -344,7 +525,7 @@ __global__ __launch_bounds__(64 * AT_WAVES) void k_apply_t_mfma(
     for (int s = 0; s < 4; ++s) {
 #pragma unroll
       for (int c = 0; c < CT; ++c) {
-        const TE a = s_tt[(c * 16 + lr) * lpad + kb + 4 * lg + s];
+        const TE a = s_tt[(c * 16 + lr) * lst + kb + 4 * lg + s];
 #pragma unroll
         for (int r = 0; r < AT_RT; ++r) acc[r][c] = M::run(a, yv[r][s], acc[r][c]);
       }
@@ -373,7 +554,7 @@ static hipError_t apply_t_dispatch(hipStream_t st, const TE* Y, int64_t N, int l
   const dim3 grid((unsigned)((N + rows_per_block - 1) / rows_per_block));
 #define SID_AT(CT_)                                                                        \
   {                                                                                        \
-    const size_t shm = sizeof(TE) * (size_t)(CT_) * 16 * lpad;                             \
+    const size_t shm = sizeof(TE) * (size_t)(CT_) * 16 * (lpad + 1);                       \
     auto kern = k_apply_t_mfma<TE, OutT, CT_>;                                             \
     if (shm > 65536) (void)hipFuncSetAttribute((const void*)kern,                          \
                                                hipFuncAttributeMaxDynamicSharedMemorySize, \
@@ -392,7 +573,7 @@ static hipError_t apply_t_dispatch(hipStream_t st, const TE* Y, int64_t N, int l
 bool apply_t_mfma_supported(int k, int l, bool y_f64) {
   const int ct = (k + 15) / 16;
   const int ctt = ct <= 2 ? 2 : ct <= 4 ? 4 : ct <= 7 ? 7 : 10;  // template tile count
-  const size_t shm = (y_f64 ? 8 : 4) * (size_t)ctt * 16 * ((l + 15) & ~15);
+  const size_t shm = (y_f64 ? 8 : 4) * (size_t)ctt * 16 * (((l + 15) & ~15) + 1);
   return ct <= 10 && shm <= 160 * 1024;
 }
 
