@@ -7,10 +7,11 @@
 //   Y = A Omega (N x l, the range sketch of the two-sided single-pass sketch,
 //               Halko et al. Sec. 5.5 items (1)-(2), quoted in Sec. 2.3).
 //
-// Layout of the work.  One persistent 256-thread workgroup per CU (one wave
-// per SIMD, so each wave can hold 256 VGPRs and 256 AGPRs) owns a contiguous
+// Layout of the work.  One persistent 512-thread workgroup per CU (two waves
+// per SIMD, 256 registers each, so that one wave's matrix products overlap
+// the other's loads, conversions and Gaussian generation) owns a contiguous
 // range of rows of A and walks it in panels of 64 rows.  A panel is consumed
-// in chunks of 64 columns; wave w owns columns 16w .. 16w+15 of every chunk.
+// in chunks of 128 columns; wave w owns columns 16w .. 16w+15 of every chunk.
 //   * Loads: each lane fetches 16 FP32 values of one column: four 64-byte
 //     runs per column, 256 contiguous bytes per column and chunk.  The loads
 //     of chunk c+1 are issued as soon as chunk c has been split into bf16,
@@ -18,14 +19,12 @@
 //   * W(:, chunk) += Psi(:, panel) A(panel, chunk): the B operand comes
 //     straight from registers (hi and, in the split form, lo bf16 parts).
 //     The W partial of the whole row range stays on chip: W rows 0..127 in
-//     accumulation registers (8 x 8 tiles x 4 = 256 per lane, exactly the
-//     AGPR file), rows 128..lq-1 in an LDS array to which each chunk's
-//     product is added (one read-add-write per tile and chunk).
+//     accumulators (8 tiles x 4 chunks x 4 = 128 registers per lane), rows
+//     128..lq-1 in an LDS array to which each chunk's product is added.
 //   * The same bf16 values are written transposed into a row-major chunk
-//     buffer in LDS; after one barrier per chunk each wave forms
-//     Y(panel, its column tiles) += A(panel, chunk) Omega(chunk, :) with
-//     Omega^T (bf16) read through L2.  The Y accumulators cover the panel
-//     and are stored after its last chunk.
+//     buffer in LDS; after a barrier each wave forms Y(panel, its tiles) +=
+//     A(panel, chunk) Omega(chunk, :) with Omega^T (bf16) read through L2.
+//     The Y accumulators cover the panel and are stored after its last chunk.
 //   * Psi(:, next panel) is generated (Philox + Box-Muller, bf16) into the
 //     other half of a double-buffered LDS array, one slice per chunk.
 // The W partial of each workgroup is written once at the end (FP32) and the
@@ -49,11 +48,11 @@ namespace sid {
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
-constexpr int FB_WAVES = 4;                  // one wave per SIMD
+constexpr int FB_WAVES = 8;                  // two waves per SIMD
 constexpr int FB_THREADS = 64 * FB_WAVES;
 constexpr int FB_PR = 64;                    // rows per panel (two K steps of 32)
 constexpr int FB_CHUNK = 16 * FB_WAVES;      // columns per chunk
-constexpr int FB_NCH = 8;                    // max chunks
+constexpr int FB_NCH = 4;                    // max chunks
 constexpr int FB_NPAD = FB_CHUNK * FB_NCH;   // 512: max columns
 constexpr int FB_KS = FB_CHUNK / 32;         // K steps of the Y product per chunk
 constexpr int FB_CROW = FB_CHUNK + 8;        // LDS row stride of a chunk (bf16)
@@ -146,7 +145,7 @@ __device__ __forceinline__ void gen_psi(__bf16* __restrict__ s_psi, uint64_t see
 }
 
 // MT: 16-row tiles of W (lq <= 16*MT); LT: 16-column tiles of Y (l <= 16*LT);
-// NCH: chunks of 64 columns per panel (n <= 64*NCH, even); WANTY: form Y.
+// NCH: chunks of 128 columns per panel (n <= 128*NCH); WANTY: form Y.
 // Every count that shapes the register state is a template argument, so the
 // chunk loop unrolls into straight-line code with no merges of accumulators.
 template <bool SPLIT, bool WANTY, int MT, int LT, int NCH>
@@ -154,14 +153,16 @@ __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
     const float* __restrict__ A, int64_t lda, int64_t N, int n, int lq, int l, uint64_t seed,
     const __bf16* __restrict__ omT /* LT*16 x FB_NPAD, k contiguous, zero padded */,
     int64_t rows_per_wg, float* __restrict__ part /* grid x lq x n */, float* __restrict__ Y) {
-  static_assert(LT % FB_WAVES == 0, "Y column tiles are split evenly over the waves");
-  static_assert(NCH % 2 == 0 && NCH <= FB_NCH, "chunk count (even: two chunk buffers)");
-  constexpr int YC = LT / FB_WAVES;               // Y column tiles per wave (all 4 row tiles)
+  static_assert(FB_WAVES % LT == 0 || LT % FB_WAVES == 0, "Y tiles split evenly over the waves");
+  static_assert(4 * LT >= FB_WAVES && NCH <= FB_NCH, "tile counts");
+  // Y tiles of a panel: 4 row tiles x LT column tiles; wave w owns column
+  // tile w % LT and YR row tiles from rt0 = (w / LT) YR
+  constexpr int YR = 4 * LT / FB_WAVES;
   constexpr int NH = SPLIT ? 2 : 1;               // bf16 terms per value
   constexpr int MTR = MT < FB_MTR ? MT : FB_MTR;  // W row tiles in registers
   constexpr int MTX = MT - MTR;                   // W row tiles accumulated in LDS
   __shared__ __attribute__((aligned(16))) __bf16 s_psi[2][MT * 16 * FB_PROW];
-  __shared__ __attribute__((aligned(16))) __bf16 s_chk[2][NH][FB_PR * FB_CROW];
+  __shared__ __attribute__((aligned(16))) __bf16 s_chk[NH][FB_PR * FB_CROW];
   // W rows 16 MTR .. 16 MT - 1, in C-fragment order: [mtx][chunk][wave][lane][4]
   __shared__ __attribute__((aligned(16))) float s_wx[MTX > 0 ? MTX * NCH * FB_THREADS * 4 : 4];
 
@@ -171,7 +172,6 @@ __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
   int64_t r1 = r0 + rows_per_wg;
   if (r1 > N) r1 = N;
-  constexpr int nch = NCH;  // chunks per panel
   const int lq4 = (lq + 3) >> 2;
   const int gen_items = FB_PR * lq4;
 
@@ -186,11 +186,10 @@ __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
   for (int mt = 0; mt < MTR; ++mt)
 #pragma unroll
     for (int j = 0; j < NCH; ++j) wacc[mt][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-  f32x4_t yacc[4][YC];
+  f32x4_t yacc[YR];
 #pragma unroll
-  for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-    for (int y = 0; y < YC; ++y) yacc[rt][y] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  for (int r = 0; r < YR; ++r) yacc[r] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  const int yc = wave % LT, rt0 = (wave / LT) * YR;
 
   // full panels end at r1f; a ragged tail panel [r1f, r1) is handled last
   const int64_t r1f = r0 + ((r1 - r0) / FB_PR) * FB_PR;
@@ -199,10 +198,9 @@ __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
   if (r0 < r1f) load_chunk(A + r0, lda, n, col_w, lg, v);
   lds_barrier();  // zeroed Psi visible
   if (r0 < r1) gen_psi(s_psi[0], seed, r0, r1, lq, 0, gen_items, tid);
-  lds_barrier();
 
   // per-lane offset of this lane's Omega^T fragments (bf16 elements)
-  const uint32_t om_lane = (uint32_t)((wave * YC * 16 + lr) * FB_NPAD + 8 * lg);
+  const uint32_t om_lane = (uint32_t)((yc * 16 + lr) * FB_NPAD + 8 * lg);
   typedef const __attribute__((address_space(1))) __bf16* gbf16p;
   typedef const __attribute__((address_space(1))) bf16x8_t* gbf16x8p;
 
@@ -218,25 +216,23 @@ __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
 #pragma unroll
     for (int j = 0; j < NCH; ++j) {
       const bool col_ok = col_w + FB_CHUNK * j < n;
-      __bf16* chk_hi = s_chk[j & 1][0];
-      __bf16* chk_lo = s_chk[j & 1][NH - 1];
       if constexpr (TAIL) load_chunk_tail(A + p0, lda, n, col_w + FB_CHUNK * j, rows, lg, v);
+      // the previous chunk's Y reads are done (and, at the start of a
+      // panel, its Psi is complete)
+      lds_barrier();
       // (1) Omega^T fragments of this chunk.  They are issued before the
       //     next chunk's loads, so that waiting for them never waits for
       //     those (vmcnt counts in issue order).  Omega^T is the same for
       //     every panel; the opaque copy of its address keeps the compiler
       //     from hoisting the fragments of all chunks out of the loop.
-      bf16x8_t of[FB_KS][YC];
-      __builtin_amdgcn_sched_barrier(0);
+      bf16x8_t of[FB_KS];
       if constexpr (WANTY) {
         uintptr_t om_addr = (uintptr_t)omT;
         asm volatile("" : "+s"(om_addr));
         const gbf16p om = (gbf16p)om_addr;
 #pragma unroll
         for (int ks = 0; ks < FB_KS; ++ks)
-#pragma unroll
-          for (int y = 0; y < YC; ++y)
-            of[ks][y] = *(gbf16x8p)(om + (om_lane + (uint32_t)(y * 16 * FB_NPAD + FB_CHUNK * j + 32 * ks)));
+          of[ks] = *(gbf16x8p)(om + (om_lane + (uint32_t)(FB_CHUNK * j + 32 * ks)));
       }
       // (2) split into bf16 hi (+ lo) B operands and the transposed copy
       bf16x8_t bh[2], bl[2];
@@ -248,11 +244,11 @@ __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
           const __bf16 h = to_bf16(x);
           bh[ks][i] = h;
           const int ci = slot_row(ks, lg, i) * FB_CROW + col_w;
-          if constexpr (WANTY) chk_hi[ci] = h;
+          if constexpr (WANTY) s_chk[0][ci] = h;
           if constexpr (SPLIT) {
             const __bf16 lo = to_bf16(x - (float)h);
             bl[ks][i] = lo;
-            if constexpr (WANTY) chk_lo[ci] = lo;
+            if constexpr (WANTY) s_chk[NH - 1][ci] = lo;
           }
         }
       // (3) the next chunk's loads: in flight during the products, the Psi
@@ -292,7 +288,7 @@ __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
           *wx += acc;
         }
       }
-      // (5) slice j of Psi(:, next panel)
+      // (5) slice j of Psi(:, next panel) (the buffer the previous panel used)
       if (!TAIL && pn < r1)
         gen_psi(s_psi[pb ^ 1], seed, pn, r1, lq, gen_items * j / NCH, gen_items * (j + 1) / NCH, tid);
       lds_barrier();  // chunk buffer complete
@@ -301,41 +297,34 @@ __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
 #pragma unroll
         for (int ks = 0; ks < FB_KS; ++ks) {
 #pragma unroll
-          for (int rt = 0; rt < 4; ++rt) {
-            const int ci = (rt * 16 + lr) * FB_CROW + 32 * ks + 8 * lg;
-            const bf16x8_t ah = *reinterpret_cast<const bf16x8_t*>(&chk_hi[ci]);
-#pragma unroll
-            for (int y = 0; y < YC; ++y)
-              yacc[rt][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, of[ks][y], yacc[rt][y], 0, 0, 0);
+          for (int r = 0; r < YR; ++r) {
+            const int ci = ((rt0 + r) * 16 + lr) * FB_CROW + 32 * ks + 8 * lg;
+            const bf16x8_t ah = *reinterpret_cast<const bf16x8_t*>(&s_chk[0][ci]);
+            yacc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, of[ks], yacc[r], 0, 0, 0);
             if constexpr (SPLIT) {
-              const bf16x8_t al = *reinterpret_cast<const bf16x8_t*>(&chk_lo[ci]);
-#pragma unroll
-              for (int y = 0; y < YC; ++y)
-                yacc[rt][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, of[ks][y], yacc[rt][y], 0, 0, 0);
+              const bf16x8_t al = *reinterpret_cast<const bf16x8_t*>(&s_chk[NH - 1][ci]);
+              yacc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, of[ks], yacc[r], 0, 0, 0);
             }
           }
         }
       }
     }
-    // Y(panel, this wave's column tiles)
+    // Y(panel, this wave's tiles)
     if constexpr (WANTY) {
       // opaque 4lg: keeps the 64-bit row offsets from being hoisted out of
       // the panel loop
       int lg4 = 4 * lg;
       asm volatile("" : "+v"(lg4));
       float* yp = Y + p0 * (int64_t)l;
+      const int c = yc * 16 + lr;
 #pragma unroll
-      for (int y = 0; y < YC; ++y) {
-        const int c = (wave * YC + y) * 16 + lr;
+      for (int r = 0; r < YR; ++r) {
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt) {
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int rr = rt * 16 + lg4 + t;
-            if (c < l && (!TAIL || rr < rows)) yp[rr * l + c] = yacc[rt][y][t];
-          }
-          yacc[rt][y] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < 4; ++t) {
+          const int rr = (rt0 + r) * 16 + lg4 + t;
+          if (c < l && (!TAIL || rr < rows)) yp[rr * l + c] = yacc[r][t];
         }
+        yacc[r] = f32x4_t{0.f, 0.f, 0.f, 0.f};
       }
     }
   };
@@ -419,15 +408,15 @@ hipError_t launch_sketch_fused_bf16(hipStream_t st, bool split, const float* A, 
 #define SID_FUSED(SP, WY, MT_, LT_, NCH_)                                                  \
   hipLaunchKernelGGL((k_sketch_fused_bf16<SP, WY, MT_, LT_, NCH_>), dim3((unsigned)grid), \
                      dim3(FB_THREADS), 0, st, A, lda, N, n, lq, l, seed, omT, rpw, part, Y)
-#define SID_FUSED_NCH(SP, WY, MT_, LT_)              \
-  if (nch <= 2) SID_FUSED(SP, WY, MT_, LT_, 2);      \
-  else if (nch <= 4) SID_FUSED(SP, WY, MT_, LT_, 4); \
-  else SID_FUSED(SP, WY, MT_, LT_, 8);
+#define SID_FUSED_NCH(SP, WY, MT_, LT_)         \
+  if (nch <= 1) SID_FUSED(SP, WY, MT_, LT_, 1); \
+  else if (nch <= 2) SID_FUSED(SP, WY, MT_, LT_, 2); \
+  else SID_FUSED(SP, WY, MT_, LT_, 4);
 #define SID_FUSED_MT(SP, WY, LT_)                          \
   if (mt <= 4) { SID_FUSED_NCH(SP, WY, 4, LT_) }           \
   else { SID_FUSED_NCH(SP, WY, 10, LT_) }
 #define SID_FUSED_SP(SP)                                     \
-  if (!Y) { SID_FUSED_MT(SP, false, 4) }                     \
+  if (!Y) { SID_FUSED_MT(SP, false, 8) }                     \
   else if (lpad <= 64) { SID_FUSED_MT(SP, true, 4) }         \
   else { SID_FUSED_MT(SP, true, 8) }
   if (split) { SID_FUSED_SP(true) } else { SID_FUSED_SP(false) }

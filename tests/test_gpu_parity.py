@@ -79,6 +79,34 @@ def test_sketch_parity(sid, oracle_mod, prec, shape):
     assert np.all(yerr <= RTOL[prec] * ybound + 1e-300), (yerr / ybound).max()
 
 
+@pytest.mark.parametrize("prec", ["bf16", "bf16x2"])
+@pytest.mark.parametrize("shape", [(2597, 500, 100, 20, 10), (49394, 500, 100, 20, 10),
+                                   (700, 129, 7, 3, 2), (5000, 300, 60, 10, 5)])
+def test_sketch_parity_streaming_sizes(sid, oracle_mod, prec, shape):
+    """Shapes that exercise the streaming matrix-core pass: n up to 512
+    (four 128-column chunks), lq up to 160 (W rows beyond 128 kept in LDS),
+    l up to 128, workgroups with full panels plus a ragged tail, and a
+    workgroup that owns only a tail."""
+    N, n, k, p, q = shape
+    say("sketch streaming", prec, shape)
+    rng = np.random.default_rng(N + 7 * n)
+    A64 = rng.standard_normal((N, n)).astype(np.float32).astype(np.float64)
+    A = to_gpu(A64, torch.float32)
+    seed = 11
+    W, Y = sid.sketch(A, k, p, seed=seed, prec=prec, probe_rows=q, want_y=True)
+    l = k + p
+    lq = l + p + q
+    Wo = oracle_mod.sketch_w(A64, None, lq, seed, prec)
+    bound = _absbound(A64, np.arange(N), lq, seed, prec, oracle_mod)
+    err = np.abs(host(W) - Wo)
+    assert np.all(err <= RTOL[prec] * bound), (err / bound).max()
+    Om = oracle_mod.omega(seed, n, l, prec)
+    Yo = oracle_mod.sketch_y(A64, Om, prec)
+    ybound = np.abs(oracle_mod.data_values(A64, prec)) @ np.abs(Om)
+    yerr = np.abs(host(Y).astype(np.float64) - Yo)
+    assert np.all(yerr <= RTOL[prec] * ybound), (yerr / ybound).max()
+
+
 def test_sketch_coarse_rows(sid, oracle_mod):
     N, n, k, p, q = 2000, 40, 5, 5, 4
     say("coarse sketch")
