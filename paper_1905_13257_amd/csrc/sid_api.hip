@@ -447,7 +447,11 @@ sid_status sid_compress(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N,
   s = run_sketch(ctx, A, dtype, lda, p, sh, w, w.W, sh.single ? w.Y : nullptr);
   if (s != SID_OK) return s;
   // (2) mgsqr on the selection rows of W
-  if (sid::cpqr_coop_supported(l, n_))
+  if (sid::cpqr_wg_supported(l, n_))
+    SID_CHECK(sid::launch_cpqr_wg(st, w.W, lq, l, n_, k, p->rank_tol, w.piv, w.R, w.Q, w.keff,
+                                  w.stats),
+              "pivoted QR");
+  else if (sid::cpqr_coop_supported(l, n_))
     SID_CHECK(sid::launch_cpqr_coop(st, w.W, lq, l, n_, k, p->rank_tol, w.coop, w.sync2, w.piv,
                                     w.R, w.Q, w.keff, w.stats, ctx->cooperative),
               "pivoted QR");
@@ -482,7 +486,11 @@ sid_status sid_compress(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N,
     if (q > 0)
       SID_CHECK(sid::launch_gemm64(st, q, l, n_, w.W + lz, lq, 0, w.om64, l, 1, w.Mpr, q),
                 "Mpr = Wpr Omega");
-    if (sid::cpqr_coop_supported(lz, l))
+    if (sid::cpqr_wg_supported(lz, l))
+      SID_CHECK(sid::launch_cpqr_wg(st, w.M, lz, lz, l, l, rcond, w.pivM, w.RM, w.QM, w.rkM,
+                                    w.statsM),
+                "pivoted QR of M");
+    else if (sid::cpqr_coop_supported(lz, l))
       SID_CHECK(sid::launch_cpqr_coop(st, w.M, lz, lz, l, l, rcond, w.coop, w.sync2, w.pivM, w.RM,
                                       w.QM, w.rkM, w.statsM, ctx->cooperative),
                 "pivoted QR of M");
@@ -495,7 +503,12 @@ sid_status sid_compress(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N,
     SID_CHECK(sid::launch_small_solve(st, w.RM, l, w.pivM, w.rkM, w.R11, w.C, l, k, w.T), "T");
     if (AJ) {
       const bool yf64 = sh.prec == SID_SK_F64;
-      if (sid::apply_t_mfma_supported(k, l, yf64))
+      const bool ybf = sh.prec == SID_SK_BF16 || sh.prec == SID_SK_BF16X2;
+      if (ybf && sid::apply_t_bf16_supported(k, l))
+        SID_CHECK(sid::launch_apply_t_bf16(st, (const float*)w.Y, sh.N, l, w.T, k, AJ, f64, ldaj,
+                                           ctx->num_cu),
+                  "AJ = Y T");
+      else if (sid::apply_t_mfma_supported(k, l, yf64))
         SID_CHECK(sid::launch_apply_t_mfma(st, w.Y, yf64, sh.N, l, w.T, k, AJ, f64, ldaj),
                   "AJ = Y T");
       else

@@ -15,6 +15,9 @@
 //      (R(i, j) = q^T r_j, r_j -= R(i, j) q, new norm^2 of r_j).
 // The participating workgroups are spread 8 block indices apart so that, with
 // the round-robin workgroup-to-XCD dispatch, they share one XCD's L2.
+// Workgroup barriers inside a step wait for LDS traffic only; the published
+// candidate data is ordered by its writers' fences, and the stores of R and Q
+// drain in the background.
 #include "sid_kernels.hpp"
 
 namespace sid {
@@ -23,6 +26,7 @@ constexpr int CQ_THREADS = 256;
 constexpr int CQ_TPC = 4;                    // threads per column
 constexpr int CQ_CPW = CQ_THREADS / CQ_TPC;  // columns per workgroup
 constexpr unsigned CQ_SPIN_LIMIT = 1u << 22; // bounded wait (~0.1 s); never reached when co-resident
+constexpr int CQ_MSTRIDE = 256;              // published column slot (rows, >= CQ_TPC * RPT)
 
 __global__ void k_zero_u32(unsigned int* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -34,11 +38,12 @@ __device__ __forceinline__ T ld_agent(const T* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// (ov, oj) replaces (bv, bj) if it has the larger norm, or the same norm and
+// the smaller column index; branch-free
 __device__ __forceinline__ void better(double& bv, int& bj, double ov, int oj) {
-  if (ov > bv || (ov == bv && oj < bj)) {
-    bv = ov;
-    bj = oj;
-  }
+  const bool take = (ov > bv) | ((ov == bv) & (oj < bj));
+  bv = take ? ov : bv;
+  bj = take ? oj : bj;
 }
 
 // device-wide barrier over G workgroups: counter value after the b-th
@@ -64,6 +69,7 @@ __global__ __launch_bounds__(CQ_THREADS) void k_cpqr_coop(
     double* __restrict__ pub_col, double* __restrict__ red, unsigned int* __restrict__ bar,
     unsigned int* __restrict__ fail, int64_t* __restrict__ piv, double* __restrict__ R,
     double* __restrict__ Q, int64_t* __restrict__ keff, double* __restrict__ stats) {
+  static_assert(CQ_TPC * RPT <= CQ_MSTRIDE, "published column slot");
   if (blockIdx.x % stride_blk) return;
   const int g = blockIdx.x / stride_blk;
   if (g >= G) return;
@@ -78,6 +84,9 @@ __global__ __launch_bounds__(CQ_THREADS) void k_cpqr_coop(
   const int cl = tid / CQ_TPC, seg = tid % CQ_TPC;
   const int j = g * CQ_CPW + cl;
   const bool mine = j < nc;
+  // rows m .. of q stay zero, so the update loops need no row guards (the
+  // matching entries of w are zero too)
+  for (int e = tid; e < RPT * CQ_TPC; e += CQ_THREADS) s_q[e] = 0.0;
 
   double w[RPT];
   double ps = 0.0;
@@ -104,7 +113,7 @@ __global__ __launch_bounds__(CQ_THREADS) void k_cpqr_coop(
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) better(bv, bj, __shfl_xor(bv, o, 64), __shfl_xor(bj, o, 64));
     if (lane == 0) { s_wv[wv] = bv; s_wj[wv] = bj; }
-    __syncthreads();
+    lds_barrier();
     bv = s_wv[0];
     bj = s_wj[0];
     for (int u = 1; u < CQ_THREADS / 64; ++u) better(bv, bj, s_wv[u], s_wj[u]);
@@ -115,18 +124,16 @@ __global__ __launch_bounds__(CQ_THREADS) void k_cpqr_coop(
       __threadfence();
     }
     if (alive && j == bj) {
+      // all RPT rows (zeros past m): no row guards on the critical path
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) {
-        const int r = seg + CQ_TPC * i;
-        if (r < m) pub_col[(int64_t)(par * G + g) * m + r] = w[i];
-      }
+      for (int i = 0; i < RPT; ++i) pub_col[(int64_t)(par * G + g) * CQ_MSTRIDE + seg + CQ_TPC * i] = w[i];
       __threadfence();
     }
-    __syncthreads();
+    lds_barrier();
     // 3. barrier
     if (tid == 0) ok = grid_barrier(bar, (unsigned)G * (unsigned)(nbar + 1)) && ok;
     ++nbar;
-    __syncthreads();
+    lds_barrier();
     // 4. global winner: wave 0 fetches the G candidates in parallel
     if (wv == 0) {
       double v = -1.0;
@@ -149,7 +156,7 @@ __global__ __launch_bounds__(CQ_THREADS) void k_cpqr_coop(
         s_win_g = hh;
       }
     }
-    __syncthreads();
+    lds_barrier();
     const double vmax = s_win_v;
     const int p = s_win_j;
     const int gp = s_win_g;
@@ -158,8 +165,8 @@ __global__ __launch_bounds__(CQ_THREADS) void k_cpqr_coop(
     if (first < 0.0) first = nu;
     else if (rank_tol > 0.0 && nu <= rank_tol * first) break;
     for (int r = tid; r < m; r += CQ_THREADS)
-      s_q[r] = ld_agent(&pub_col[(int64_t)(par * G + gp) * m + r]) / nu;
-    __syncthreads();
+      s_q[r] = ld_agent(&pub_col[(int64_t)(par * G + gp) * CQ_MSTRIDE + r]) / nu;
+    lds_barrier();
     if (g == 0) {
       if (tid == 0) piv[k] = p;
       for (int r = tid; r < m; r += CQ_THREADS) Q[r + (int64_t)m * k] = s_q[r];
@@ -167,10 +174,7 @@ __global__ __launch_bounds__(CQ_THREADS) void k_cpqr_coop(
     // update: R(k, j) = q^T r_j, r_j -= R(k, j) q
     double d = 0.0;
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-      const int r = seg + CQ_TPC * i;
-      if (r < m) d = fma(s_q[r], w[i], d);
-    }
+    for (int i = 0; i < RPT; ++i) d = fma(s_q[seg + CQ_TPC * i], w[i], d);
     d += __shfl_xor(d, 1, 64);
     d += __shfl_xor(d, 2, 64);
     if (mine && j == p) {
@@ -182,8 +186,7 @@ __global__ __launch_bounds__(CQ_THREADS) void k_cpqr_coop(
       ps = 0.0;
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
-        const int r = seg + CQ_TPC * i;
-        if (r < m) w[i] = fma(-d, s_q[r], w[i]);
+        w[i] = fma(-d, s_q[seg + CQ_TPC * i], w[i]);
         ps = fma(w[i], w[i], ps);
       }
       if (seg == 0) R[(int64_t)k * nc + j] = d;
@@ -227,6 +230,181 @@ __global__ __launch_bounds__(CQ_THREADS) void k_cpqr_coop(
   }
 }
 
+// ---------------------------------------------------------------------------
+// mgsqr in one workgroup (the same steps, no device-wide barrier): for
+// matrices whose residual fits in the registers of 512 threads (TPC threads
+// per column, RPT rows per thread).  Per step: each wave finds its best live
+// column, one barrier, every thread reduces the 8 wave candidates, the
+// pivot's owners write q into LDS, one barrier, every column is updated.
+// The wave candidates and q are double-buffered by step parity, so two
+// barriers per step suffice; they wait for LDS traffic only, so the stores of
+// R, Q and the pivots drain in the background.
+// ---------------------------------------------------------------------------
+constexpr int CW_THREADS = 512;
+constexpr int CW_WAVES = CW_THREADS / 64;
+constexpr int CW_MMAX = 256;
+
+template <int TPC, int RPT>
+__global__ __launch_bounds__(CW_THREADS) void k_cpqr_wg(
+    const double* __restrict__ X, int64_t ldx, int m, int nc, int kmax, double rank_tol,
+    int64_t* __restrict__ piv, double* __restrict__ R, double* __restrict__ Q,
+    int64_t* __restrict__ keff, double* __restrict__ stats) {
+  constexpr int QN = TPC * RPT;  // rows covered by a column's threads
+  __shared__ double s_q[2][QN];
+  __shared__ double s_wv[2][CW_WAVES];
+  __shared__ int s_wj[2][CW_WAVES];
+  __shared__ double s_sum[2][CW_WAVES];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int j = tid / TPC, seg = tid % TPC;
+  const bool mine = j < nc;
+  // rows m .. of q stay zero, so the loops below need no row guards (the
+  // matching entries of w are zero too)
+  for (int e = tid; e < 2 * QN; e += CW_THREADS) (&s_q[0][0])[e] = 0.0;
+
+  double w[RPT];
+  double ps = 0.0;
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int r = seg + TPC * i;
+    w[i] = (mine && r < m) ? X[r + ldx * j] : 0.0;
+    ps = fma(w[i], w[i], ps);
+  }
+  double nrm = ps;
+#pragma unroll
+  for (int o = 1; o < TPC; o <<= 1) nrm += __shfl_xor(nrm, o, 64);
+  const double tot_local = (seg == 0 && mine) ? nrm : 0.0;
+  bool alive = mine;
+  double first = -1.0;
+  int k = 0;
+  for (; k < kmax; ++k) {
+    const int par = k & 1;
+    // 1. this wave's best live column (ties: smallest index)
+    double bv = alive ? nrm : -1.0;
+    int bj = alive ? j : 0x7fffffff;
+#pragma unroll
+    for (int o = 32; o >= TPC; o >>= 1) better(bv, bj, __shfl_xor(bv, o, 64), __shfl_xor(bj, o, 64));
+    if (lane == 0) { s_wv[par][wv] = bv; s_wj[par][wv] = bj; }
+    lds_barrier();
+    // 2. the winner, found by every thread from the wave candidates (all
+    //    loaded first, then reduced without branches)
+    {
+      double cv[CW_WAVES];
+      int cj[CW_WAVES];
+#pragma unroll
+      for (int u = 0; u < CW_WAVES; ++u) { cv[u] = s_wv[par][u]; cj[u] = s_wj[par][u]; }
+#pragma unroll
+      for (int h = CW_WAVES / 2; h > 0; h >>= 1)
+#pragma unroll
+        for (int u = 0; u < h; ++u) better(cv[u], cj[u], cv[u + h], cj[u + h]);
+      bv = cv[0];
+      bj = cj[0];
+    }
+    if (!(bv > 0.0)) break;
+    const double nu = sqrt(bv);
+    if (first < 0.0) first = nu;
+    else if (rank_tol > 0.0 && nu <= rank_tol * first) break;
+    const int p = bj;
+    // 3. the pivot column, normalized, into LDS (rows >= m write the zeros
+    //    their w holds, so the owners need no row guards)
+    if (j == p) {
+      const double inv = 1.0 / nu;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        s_q[par][seg + TPC * i] = w[i] * inv;
+        w[i] = 0.0;
+      }
+      alive = false;
+      if (seg == 0) {
+        R[(int64_t)k * nc + j] = nu;
+        piv[k] = p;
+      }
+    }
+    lds_barrier();
+    for (int r = tid; r < m; r += CW_THREADS) Q[r + (int64_t)m * k] = s_q[par][r];
+    // 4. R(k, j) = q^T r_j, r_j -= R(k, j) q, new norm of r_j
+    const double* qv = &s_q[par][seg];  // q(seg + TPC i) = qv[TPC i]
+    double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+    for (int i = 0; i < RPT; i += 2) {
+      d0 = fma(qv[TPC * i], w[i], d0);
+      if (i + 1 < RPT) d1 = fma(qv[TPC * (i + 1)], w[i + 1], d1);
+    }
+    double d = d0 + d1;
+#pragma unroll
+    for (int o = 1; o < TPC; o <<= 1) d += __shfl_xor(d, o, 64);
+    if (alive) {
+      double p0 = 0.0, p1 = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPT; i += 2) {
+        w[i] = fma(-d, qv[TPC * i], w[i]);
+        p0 = fma(w[i], w[i], p0);
+        if (i + 1 < RPT) {
+          w[i + 1] = fma(-d, qv[TPC * (i + 1)], w[i + 1]);
+          p1 = fma(w[i + 1], w[i + 1], p1);
+        }
+      }
+      ps = p0 + p1;
+      if (seg == 0) R[(int64_t)k * nc + j] = d;
+    } else {
+      ps = 0.0;
+      if (mine && j != p && seg == 0) R[(int64_t)k * nc + j] = 0.0;
+    }
+    nrm = ps;
+#pragma unroll
+    for (int o = 1; o < TPC; o <<= 1) nrm += __shfl_xor(nrm, o, 64);
+  }
+
+  // statistics: final residual energy of live columns and ||X||_F^2
+  double a = (seg == 0 && alive) ? nrm : 0.0, b = tot_local;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o, 64);
+    b += __shfl_xor(b, o, 64);
+  }
+  if (lane == 0) { s_sum[0][wv] = a; s_sum[1][wv] = b; }
+  __syncthreads();
+  if (tid == 0) {
+    double sa = 0.0, sb = 0.0;
+    for (int u = 0; u < CW_WAVES; ++u) { sa += s_sum[0][u]; sb += s_sum[1][u]; }
+    stats[0] = sa;
+    stats[1] = sb;
+    *keff = k;
+  }
+  for (int i = k + tid; i < kmax; i += CW_THREADS) piv[i] = -1;
+}
+
+static int cw_tpc(int nc) { return nc <= 64 ? 8 : nc <= 128 ? 4 : nc <= 256 ? 2 : 1; }
+
+bool cpqr_wg_supported(int m, int nc) {
+  if (nc < 1 || nc > CW_THREADS || m < 1 || m > CW_MMAX) return false;
+  return (m + cw_tpc(nc) - 1) / cw_tpc(nc) <= 48;
+}
+
+hipError_t launch_cpqr_wg(hipStream_t st, const double* X, int64_t ldx, int m, int nc, int kmax,
+                          double rank_tol, int64_t* piv, double* R, double* Q, int64_t* keff,
+                          double* stats) {
+  if (!cpqr_wg_supported(m, nc)) return hipErrorInvalidValue;
+  const int tpc = cw_tpc(nc);
+  const int rpt = (m + tpc - 1) / tpc;
+#define SID_CW(TPC_, RPT_)                                                                    \
+  hipLaunchKernelGGL((k_cpqr_wg<TPC_, RPT_>), dim3(1), dim3(CW_THREADS), 0, st, X, ldx, m, nc, \
+                     kmax, rank_tol, piv, R, Q, keff, stats)
+#define SID_CW_R(TPC_)                    \
+  if (rpt <= 8) SID_CW(TPC_, 8);          \
+  else if (rpt <= 16) SID_CW(TPC_, 16);   \
+  else if (rpt <= 24) SID_CW(TPC_, 24);   \
+  else if (rpt <= 32) SID_CW(TPC_, 32);   \
+  else if (rpt <= 40) SID_CW(TPC_, 40);   \
+  else SID_CW(TPC_, 48);
+  if (tpc == 8) { SID_CW_R(8) }
+  else if (tpc == 4) { SID_CW_R(4) }
+  else if (tpc == 2) { SID_CW_R(2) }
+  else { SID_CW_R(1) }
+#undef SID_CW_R
+#undef SID_CW
+  return hipGetLastError();
+}
+
 // keff := -1 when a cooperative wait timed out (results invalid)
 __global__ void k_mark_failure(const unsigned int* fail, int64_t* keff) {
   if (threadIdx.x == 0 && blockIdx.x == 0 && *fail) *keff = -1;
@@ -236,8 +414,8 @@ bool cpqr_coop_supported(int m, int nc) { return m <= 256 && nc <= 64 * CQ_CPW &
 
 size_t cpqr_coop_scratch_bytes(int m, int nc) {
   const int G = (nc + CQ_CPW - 1) / CQ_CPW;
-  return sizeof(double) * (size_t)(2 * G + 2 * G * m + 2 * G) + sizeof(int) * (size_t)(2 * G) +
-         64;
+  return sizeof(double) * (size_t)(2 * G + 2 * G * CQ_MSTRIDE + 2 * G) +
+         sizeof(int) * (size_t)(2 * G) + 64;
 }
 
 hipError_t launch_cpqr_coop(hipStream_t st, const double* X, int64_t ldx, int m, int nc, int kmax,
@@ -247,7 +425,7 @@ hipError_t launch_cpqr_coop(hipStream_t st, const double* X, int64_t ldx, int m,
   const int G = (nc + CQ_CPW - 1) / CQ_CPW;
   double* pub_v = (double*)scratch;
   double* pub_col = pub_v + 2 * G;
-  double* red = pub_col + (size_t)2 * G * m;
+  double* red = pub_col + (size_t)2 * G * CQ_MSTRIDE;
   int* pub_j = (int*)(red + 2 * G);
   unsigned int* bar = sync2;
   unsigned int* fail = sync2 + 1;

@@ -159,6 +159,18 @@ __device__ __forceinline__ T data_value(In a) {
 }
 
 // ---------------------------------------------------------------------------
+// Workgroup barrier for LDS communication only: waits for this wave's LDS
+// operations, not for its global loads or stores (a plain __syncthreads also
+// waits for every outstanding global access of the wave).  The compiler
+// fences keep memory operations from being moved across it.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_sched_barrier(0);
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// ---------------------------------------------------------------------------
 // Reductions (wave64)
 // ---------------------------------------------------------------------------
 template <typename T>

@@ -66,4 +66,11 @@ hipError_t launch_small_solve(hipStream_t st, const double* RM, int l, const int
                               double* T);
 hipError_t launch_apply_t_mfma(hipStream_t st, const void* Y, bool y_f64, int64_t N, int l,
                                const double* Tm, int k, void* AJ, bool aj_f64, int64_t ldaj);
+bool apply_t_bf16_supported(int k, int l);
+hipError_t launch_apply_t_bf16(hipStream_t st, const float* Y, int64_t N, int l, const double* Tm,
+                               int k, void* AJ, bool aj_f64, int64_t ldaj, int num_cu);
+bool cpqr_wg_supported(int m, int nc);
+hipError_t launch_cpqr_wg(hipStream_t st, const double* X, int64_t ldx, int m, int nc, int kmax,
+                          double rank_tol, int64_t* piv, double* R, double* Q, int64_t* keff,
+                          double* stats);
 }  // namespace sid

@@ -61,14 +61,6 @@ constexpr int FB_MTR = 8;                    // W row tiles kept in registers
 
 __device__ __forceinline__ __bf16 to_bf16(float f) { return (__bf16)f; }
 
-// Workgroup barrier that waits for this wave's LDS traffic only: global
-// loads issued before it (the next chunk) stay in flight.
-__device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_sched_barrier(0);
-  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-  __builtin_amdgcn_sched_barrier(0);
-}
-
 // panel row of operand slot (ks, g, i)
 __device__ __forceinline__ int slot_row(int ks, int g, int i) {
   return 32 * ks + (i < 4 ? 4 * g + i : 16 + 4 * g + (i - 4));
@@ -574,6 +566,141 @@ hipError_t launch_apply_t_mfma(hipStream_t st, const void* Y, bool y_f64, int64_
   }
   if (aj_f64) return apply_t_dispatch<float, double>(st, (const float*)Y, N, l, Tm, k, (double*)AJ, ldaj);
   return apply_t_dispatch<float, float>(st, (const float*)Y, N, l, Tm, k, (float*)AJ, ldaj);
+}
+
+
+// ---------------------------------------------------------------------------
+// Skeleton estimate of the single pass for the bfloat16 sketch precisions,
+// AJ = Y T on the bf16 matrix cores.  Y (N x l, row-major FP32) and T (l x k,
+// FP64) are each split into bf16 hi + lo parts and the product is formed from
+// the three terms Y_hi T_hi + Y_hi T_lo + Y_lo T_hi (the dropped Y_lo T_lo is
+// below 2^-16 of the product), accumulated in FP32.  Orientation as in
+// k_apply_t_mfma: AJ^T = T^T Y^T, so a C tile is (16 skeleton columns) x
+// (16 rows of A) and its stores run down the columns of AJ.
+//   A operand: T^T tile (16 x 32) from LDS, lane = skeleton column l%16,
+//              entries 8*(l/16) .. +7 of a 32-wide slice of l;
+//   B operand: Y^T tile (32 x 16), lane = row l%16 of A, 8 consecutive Y
+//              entries of that row (two 16-byte loads).
+// Each wave owns 32 rows (two row tiles) of a 128-row block; workgroups loop
+// over blocks so that the T split is staged in LDS once per workgroup.
+// ---------------------------------------------------------------------------
+constexpr int AB_THREADS = 256;
+constexpr int AB_LPAD = 128;               // l <= 128: four K steps of 32
+constexpr int AB_LS = AB_LPAD + 8;         // LDS row stride (bf16)
+constexpr int AB_ROWS = 4 * 32;            // rows per block
+
+template <int KT, typename OutT>
+__global__ __launch_bounds__(AB_THREADS) void k_apply_t_bf16(
+    const float* __restrict__ Y, int64_t N, int l, const double* __restrict__ Tm /* l x k */,
+    int k, OutT* __restrict__ AJ, int64_t ldaj) {
+  __shared__ __attribute__((aligned(16))) __bf16 s_th[KT * 16 * AB_LS];
+  __shared__ __attribute__((aligned(16))) __bf16 s_tl[KT * 16 * AB_LS];
+  for (int e = threadIdx.x; e < KT * 16 * AB_LPAD; e += AB_THREADS) {
+    const int m = e / AB_LPAD, c = e - m * AB_LPAD;
+    const float x = (m < k && c < l) ? (float)Tm[c + (int64_t)l * m] : 0.0f;
+    const __bf16 h = to_bf16(x);
+    s_th[m * AB_LS + c] = h;
+    s_tl[m * AB_LS + c] = to_bf16(x - (float)h);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int nks = (l + 31) >> 5;
+  const int64_t nblk = (N + AB_ROWS - 1) / AB_ROWS;
+  typedef const __attribute__((address_space(1))) f32x4_t* gptr4;
+  // Y entries of one block for this lane: y[rt][ks] = Y(row0 + 16 rt + lr,
+  // 32 ks + 8 lg .. +7); the next block's are loaded while this one is
+  // multiplied
+  f32x4_t y[2][4][2];
+  auto load_block = [&](int64_t b) {
+    const int64_t row0 = b * AB_ROWS + wave * 32;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+      const int64_t row = row0 + rt * 16 + lr;
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int c = 32 * ks + 8 * lg + 4 * h;
+          y[rt][ks][h] = (row < N && c + 4 <= l) ? *(gptr4)(Y + row * l + c)
+                                                 : f32x4_t{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+  };
+  int64_t b = blockIdx.x;
+  if (b < nblk) load_block(b);
+  for (; b < nblk; b += gridDim.x) {
+    const int64_t row0 = b * AB_ROWS + wave * 32;
+    bf16x8_t bh[2][4], bl[2][4];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const float x = y[rt][ks][i >> 2][i & 3];
+          const __bf16 hv = to_bf16(x);
+          bh[rt][ks][i] = hv;
+          bl[rt][ks][i] = to_bf16(x - (float)hv);
+        }
+    if (b + gridDim.x < nblk) load_block(b + gridDim.x);
+    f32x4_t acc[2][KT];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int kt = 0; kt < KT; ++kt) acc[rt][kt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      if (ks >= nks) break;
+#pragma unroll
+      for (int kt = 0; kt < KT; ++kt) {
+        const int ti = (kt * 16 + lr) * AB_LS + 32 * ks + 8 * lg;
+        const bf16x8_t th = *reinterpret_cast<const bf16x8_t*>(&s_th[ti]);
+        const bf16x8_t tl = *reinterpret_cast<const bf16x8_t*>(&s_tl[ti]);
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) {
+          acc[rt][kt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(th, bh[rt][ks], acc[rt][kt], 0, 0, 0);
+          acc[rt][kt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(th, bl[rt][ks], acc[rt][kt], 0, 0, 0);
+          acc[rt][kt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(tl, bh[rt][ks], acc[rt][kt], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+      const int64_t row = row0 + rt * 16 + lr;
+      if (row >= N) continue;
+#pragma unroll
+      for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int m = kt * 16 + 4 * lg + t;
+          if (m < k) AJ[row + ldaj * m] = (OutT)acc[rt][kt][t];
+        }
+    }
+  }
+}
+
+bool apply_t_bf16_supported(int k, int l) {
+  return k >= 1 && k <= 128 && l >= 1 && l <= AB_LPAD && (l % 4) == 0;
+}
+
+hipError_t launch_apply_t_bf16(hipStream_t st, const float* Y, int64_t N, int l, const double* Tm,
+                               int k, void* AJ, bool aj_f64, int64_t ldaj, int num_cu) {
+  if (!apply_t_bf16_supported(k, l)) return hipErrorInvalidValue;
+  const int64_t nblk = (N + AB_ROWS - 1) / AB_ROWS;
+  int64_t g = (int64_t)num_cu * 4;
+  if (g > nblk) g = nblk;
+  const dim3 grid((unsigned)g), block(AB_THREADS);
+#define SID_AB(KT_)                                                                           \
+  if (aj_f64) hipLaunchKernelGGL((k_apply_t_bf16<KT_, double>), grid, block, 0, st, Y, N, l, \
+                                 Tm, k, (double*)AJ, ldaj);                                   \
+  else hipLaunchKernelGGL((k_apply_t_bf16<KT_, float>), grid, block, 0, st, Y, N, l, Tm, k,   \
+                          (float*)AJ, ldaj);
+  if (k <= 32) { SID_AB(2) }
+  else if (k <= 64) { SID_AB(4) }
+  else { SID_AB(8) }
+#undef SID_AB
+  return hipGetLastError();
 }
 
 }  // namespace sid
