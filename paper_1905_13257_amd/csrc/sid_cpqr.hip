@@ -511,6 +511,100 @@ __global__ __launch_bounds__(64) void k_trsv_multi(
   }
 }
 
+// The same solves with one wave per right-hand side (column-oriented back
+// substitution: x_a = rhs_a / R11(a, a), then rhs_b -= R11(b, a) x_a for
+// b < a in parallel over the lanes), R11 staged transposed in LDS.  For
+// kcap <= 128 (two rows per lane).
+constexpr int TW_WAVES = 8;
+
+template <typename OutT, int MODE>
+__global__ __launch_bounds__(64 * TW_WAVES) void k_trsv_wave(
+    const double* __restrict__ R11, int kcap, const int64_t* __restrict__ keff_p,
+    const int64_t* __restrict__ piv, const double* __restrict__ rhs, int64_t ldrhs, int ncols,
+    double* __restrict__ out64, int64_t ldo64, OutT* __restrict__ out, int64_t ldo) {
+  extern __shared__ double s_tw[];
+  double* s_rt = s_tw;                           // [a][b] = R11(b, a), kcap^2 (+128 pad)
+  double* s_dinv = s_rt + kcap * kcap + 128;     // 1 / R11(a, a)
+  double* s_x = s_dinv + kcap;                   // [wave][a]
+  int* s_inv = (int*)(s_x + TW_WAVES * kcap);    // inverse pivot permutation (mode 1)
+  const int keff = (int)*keff_p;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int e = tid; e < kcap * kcap + 128; e += 64 * TW_WAVES) {
+    const int a = e / kcap, b = e - a * kcap;
+    s_rt[e] = (a < keff && b < keff) ? R11[(int64_t)b * kcap + a] : 0.0;
+  }
+  for (int a = tid; a < kcap; a += 64 * TW_WAVES) {
+    s_dinv[a] = a < keff ? 1.0 / R11[(int64_t)a * kcap + a] : 0.0;
+    s_inv[a] = -1;
+  }
+  __syncthreads();
+  if (MODE == 1)
+    for (int a = tid; a < keff; a += 64 * TW_WAVES) s_inv[piv[a]] = a;
+  __syncthreads();
+  const int j = blockIdx.x * TW_WAVES + w;
+  if (j >= ncols) return;
+  const int b0 = lane, b1 = lane + 64;
+  auto rhs_at = [&](int a) -> double {
+    return MODE == 0 ? rhs[(int64_t)a * ldrhs + j] : rhs[a + ldrhs * (int64_t)j];
+  };
+  double v0 = b0 < keff ? rhs_at(b0) : 0.0;
+  double v1 = b1 < keff ? rhs_at(b1) : 0.0;
+  int pos = -1;
+  if (MODE == 0) {
+    const bool hit0 = b0 < keff && piv[b0] == j, hit1 = b1 < keff && piv[b1] == j;
+    const uint64_t m0 = __ballot(hit0), m1 = __ballot(hit1);
+    pos = m0 ? __ffsll((unsigned long long)m0) - 1 : m1 ? 64 + __ffsll((unsigned long long)m1) - 1 : -1;
+  }
+  if (pos < 0) {
+    for (int a = keff - 1; a >= 0; --a) {
+      // rhs_a (already reduced) from lane a & 63, as two 32-bit halves
+      const long long bits = __double_as_longlong(a < 64 ? v0 : v1);
+      const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)bits, a & 63);
+      const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(bits >> 32), a & 63);
+      const double xa = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo)) * s_dinv[a];
+      const double* col = s_rt + a * kcap;
+      const double u0 = fma(-col[b0], xa, v0), u1 = fma(-col[b1], xa, v1);
+      v0 = b0 < a ? u0 : (b0 == a ? xa : v0);
+      v1 = b1 < a ? u1 : (b1 == a ? xa : v1);
+    }
+  }
+  if (MODE == 0) {
+    double* x = out64 + ldo64 * j;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int a = h ? b1 : b0;
+      if (a >= kcap) continue;
+      const double v = pos >= 0 ? (a == pos ? 1.0 : 0.0) : (a < keff ? (h ? v1 : v0) : 0.0);
+      x[a] = v;
+      if (out) out[a + ldo * j] = (OutT)v;
+    }
+  } else {
+    if (b0 < keff) s_x[w * kcap + b0] = v0;
+    if (b1 < keff) s_x[w * kcap + b1] = v1;
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): this wave's LDS writes done
+    __builtin_amdgcn_wave_barrier();
+    double* x = out64 + ldo64 * j;
+    for (int r = lane; r < kcap; r += 64) {
+      const int a = s_inv[r];
+      x[r] = a >= 0 ? s_x[w * kcap + a] : 0.0;
+    }
+  }
+}
+
+template <typename OutT, int MODE>
+static hipError_t trsv_wave_launch(hipStream_t st, const double* R11, int kcap, const int64_t* keff,
+                                   const int64_t* piv, const double* rhs, int64_t ldrhs, int ncols,
+                                   double* out64, int64_t ldo64, OutT* out, int64_t ldo) {
+  const size_t shm = sizeof(double) * ((size_t)kcap * kcap + 128 + kcap + (size_t)TW_WAVES * kcap) +
+                     sizeof(int) * (size_t)kcap;
+  auto kern = k_trsv_wave<OutT, MODE>;
+  if (shm > 65536)
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL(kern, dim3((unsigned)((ncols + TW_WAVES - 1) / TW_WAVES)), dim3(64 * TW_WAVES),
+                     shm, st, R11, kcap, keff, piv, rhs, ldrhs, ncols, out64, ldo64, out, ldo);
+  return hipGetLastError();
+}
+
 template <typename OutT, int MODE>
 static hipError_t trsv_launch(hipStream_t st, const double* R11, int kcap, const int64_t* keff,
                               const int64_t* piv, const double* rhs, int64_t ldrhs, int ncols,
@@ -528,6 +622,11 @@ hipError_t launch_id_coefficients(hipStream_t st, const double* R, int nc, const
                                   const int64_t* keff, int kcap, double* R11, double* Pd,
                                   void* P, int64_t ldp, bool p_is_f64) {
   hipLaunchKernelGGL(k_gather_r11, dim3(64), dim3(256), 0, st, R, (int64_t)nc, piv, keff, kcap, R11);
+  if (kcap <= 128) {
+    if (p_is_f64)
+      return trsv_wave_launch<double, 0>(st, R11, kcap, keff, piv, R, nc, nc, Pd, kcap, (double*)P, ldp);
+    return trsv_wave_launch<float, 0>(st, R11, kcap, keff, piv, R, nc, nc, Pd, kcap, (float*)P, ldp);
+  }
   if (p_is_f64)
     return trsv_launch<double, 0>(st, R11, kcap, keff, piv, R, nc, nc, Pd, kcap, (double*)P, ldp);
   return trsv_launch<float, 0>(st, R11, kcap, keff, piv, R, nc, nc, Pd, kcap, (float*)P, ldp);
@@ -537,6 +636,8 @@ hipError_t launch_small_solve(hipStream_t st, const double* RM, int l, const int
                               const int64_t* rM, double* R11, const double* C, int64_t ldc, int kc,
                               double* T) {
   hipLaunchKernelGGL(k_gather_r11, dim3(64), dim3(256), 0, st, RM, (int64_t)l, pivM, rM, l, R11);
+  if (l <= 128)
+    return trsv_wave_launch<double, 1>(st, R11, l, rM, pivM, C, ldc, kc, T, l, (double*)nullptr, 0);
   return trsv_launch<double, 1>(st, R11, l, rM, pivM, C, ldc, kc, T, l, (double*)nullptr, 0);
 }
 
