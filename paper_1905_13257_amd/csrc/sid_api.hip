@@ -18,7 +18,7 @@ namespace {
 enum Slot {
   WS_OMEGA, WS_PART, WS_W, WS_WR, WS_NRM, WS_PIV, WS_R, WS_Q, WS_KEFF, WS_STATS, WS_PD,
   WS_ERR, WS_Y, WS_M, WS_MPR, WS_WJ, WS_PIVM, WS_RM, WS_QM, WS_RKM, WS_C, WS_T, WS_MIX,
-  WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COOP, WS_SYNC, WS_R11, WS_COUNT
+  WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COOP, WS_SYNC, WS_R11, WS_FITPART, WS_COUNT
 };
 
 struct Buf {
@@ -162,6 +162,7 @@ struct Work {
   void* coop;
   unsigned int* sync2;
   double* R11;
+  double* fitpart;
 };
 
 sid_status reserve(sid_ctx* c, const Shape& s, Work* w) {
@@ -179,6 +180,8 @@ sid_status reserve(sid_ctx* c, const Shape& s, Work* w) {
   w->stats = (double*)ws(c, WS_STATS, d * 2);
   w->Pd = (double*)ws(c, WS_PD, d * (size_t)(s.k * s.n));
   w->err = (double*)ws(c, WS_ERR, d * 2);
+  w->fitpart = (double*)ws(c, WS_FITPART, d * (size_t)(2 * ((s.q * s.n + 255) / 256) + 2));
+  if (!w->fitpart) return SID_ENOMEM;
   {
     const int mmax = (int)s.lz;
     const int ncmax = (int)(s.n > s.l ? s.n : s.l);
@@ -466,7 +469,7 @@ sid_status sid_compress(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N,
   SID_CHECK(sid::launch_ratio_sqrt(st, w.stats, w.err + 1), "sketch residual");
   if (!sh.single) {
     SID_CHECK(sid::launch_fit_residual(st, w.W, lq, l, q, n_, w.piv, w.keff, w.Pd, k, nullptr,
-                                       w.err),
+                                       w.fitpart, w.err),
               "probe residual");
     if (AJ)
       SID_CHECK(sid::launch_gather_cols(st, A, f64, lda, sh.N, w.piv, w.keff, k, AJ, f64, ldaj),
@@ -517,7 +520,7 @@ sid_status sid_compress(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N,
     if (q > 0)
       SID_CHECK(sid::launch_gemm64(st, q, k, l, w.Mpr, q, 0, w.T, l, 0, w.mix, q), "Mpr T");
     SID_CHECK(sid::launch_fit_residual(st, w.W, lq, lz, q, n_, w.piv, w.keff, w.Pd, k,
-                                       q > 0 ? w.mix : nullptr, w.err),
+                                       q > 0 ? w.mix : nullptr, w.fitpart, w.err),
               "probe residual");
   }
   if (J) SID_CHECK(hipMemcpyAsync(J, w.piv, sizeof(int64_t) * (size_t)k, hipMemcpyDeviceToDevice, st),

@@ -332,25 +332,34 @@ __global__ void k_backsolve(const double* __restrict__ R, const int64_t* __restr
 // (single pass), ||Wp - mix Pd||_F with mix (q x kcap, column-major ld q).
 // Single block; result to *out.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_fit_residual(
+__global__ __launch_bounds__(256) void k_fit_residual_part(
     const double* __restrict__ W, int lq, int r0, int q, int nc,
     const int64_t* __restrict__ piv, const int64_t* __restrict__ keff_p,
     const double* __restrict__ Pd, int kcap, const double* __restrict__ mix,
-    double* __restrict__ out) {
-  __shared__ double s_num[16], s_den[16];
+    double* __restrict__ part /* 2 x gridDim.x */) {
+  __shared__ double s_num[4], s_den[4];
   const int keff = (int)*keff_p;
   double num = 0.0, den = 0.0;
-  for (int e = threadIdx.x; e < q * nc; e += blockDim.x) {
-    const int j = e / q, r = r0 + (e - (e / q) * q);
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < q * nc) {
+    const int j = e / q, r = r0 + (e - j * q);
     const double w = W[r + (int64_t)lq * j];
-    double a = 0.0;
-    for (int t = 0; t < keff; ++t) {
-      const double basis = mix ? mix[(r - r0) + (int64_t)q * t] : W[r + (int64_t)lq * piv[t]];
-      a = fma(basis, Pd[t + (int64_t)kcap * j], a);
+    const double* pj = Pd + (int64_t)kcap * j;
+    double a0 = 0.0, a1 = 0.0;
+    int t = 0;
+    for (; t + 1 < keff; t += 2) {
+      const double b0 = mix ? mix[(r - r0) + (int64_t)q * t] : W[r + (int64_t)lq * piv[t]];
+      const double b1 = mix ? mix[(r - r0) + (int64_t)q * (t + 1)] : W[r + (int64_t)lq * piv[t + 1]];
+      a0 = fma(b0, pj[t], a0);
+      a1 = fma(b1, pj[t + 1], a1);
     }
-    const double d = w - a;
-    num = fma(d, d, num);
-    den = fma(w, w, den);
+    if (t < keff) {
+      const double b0 = mix ? mix[(r - r0) + (int64_t)q * t] : W[r + (int64_t)lq * piv[t]];
+      a0 = fma(b0, pj[t], a0);
+    }
+    const double d = w - (a0 + a1);
+    num = d * d;
+    den = w * w;
   }
   num = wave_sum(num);
   den = wave_sum(den);
@@ -359,8 +368,25 @@ __global__ __launch_bounds__(1024) void k_fit_residual(
   __syncthreads();
   if (threadIdx.x == 0) {
     double a = 0.0, b = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { a += s_num[w]; b += s_den[w]; }
-    *out = (q > 0 && b > 0.0) ? sqrt(a / b) : (q > 0 ? 0.0 : __longlong_as_double(0x7ff8000000000000ll));
+    for (int u = 0; u < 4; ++u) { a += s_num[u]; b += s_den[u]; }
+    part[2 * blockIdx.x] = a;
+    part[2 * blockIdx.x + 1] = b;
+  }
+}
+
+// partial sums in block order (fixed), then the ratio
+__global__ void k_fit_residual_final(const double* __restrict__ part, int nparts, int q,
+                                     double* __restrict__ out) {
+  __shared__ double s_a[64], s_b[64];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += 64) { a += part[2 * i]; b += part[2 * i + 1]; }
+  s_a[threadIdx.x] = a;
+  s_b[threadIdx.x] = b;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double ta = 0.0, tb = 0.0;
+    for (int u = 0; u < 64; ++u) { ta += s_a[u]; tb += s_b[u]; }
+    *out = (q > 0 && tb > 0.0) ? sqrt(ta / tb) : (q > 0 ? 0.0 : __longlong_as_double(0x7ff8000000000000ll));
   }
 }
 
@@ -696,9 +722,12 @@ hipError_t launch_backsolve(hipStream_t st, const double* R, const int64_t* piv,
 
 hipError_t launch_fit_residual(hipStream_t st, const double* W, int lq, int r0, int q, int nc,
                                const int64_t* piv, const int64_t* keff, const double* Pd, int kcap,
-                               const double* mix, double* out) {
-  hipLaunchKernelGGL(k_fit_residual, dim3(1), dim3(1024), 0, st, W, lq, r0, q, nc, piv, keff, Pd,
-                     kcap, mix, out);
+                               const double* mix, double* part, double* out) {
+  const int nparts = (q * nc + 255) / 256;
+  if (nparts > 0)
+    hipLaunchKernelGGL(k_fit_residual_part, dim3((unsigned)nparts), dim3(256), 0, st, W, lq, r0, q,
+                       nc, piv, keff, Pd, kcap, mix, part);
+  hipLaunchKernelGGL(k_fit_residual_final, dim3(1), dim3(64), 0, st, part, nparts, q, out);
   return hipGetLastError();
 }
 

@@ -19,7 +19,8 @@ hipError_t launch_backsolve(hipStream_t st, const double* R, const int64_t* piv,
                             int64_t ldp, bool p_is_f64);
 hipError_t launch_fit_residual(hipStream_t st, const double* W, int lq, int r0, int q, int nc,
                                const int64_t* piv, const int64_t* keff, const double* Pd, int kcap,
-                               const double* mix, double* out);
+                               const double* mix, double* part /* 2 * ceil(q nc / 256) */,
+                               double* out);
 hipError_t launch_omega_values(hipStream_t st, int prec, const float* z, int64_t count,
                                double* out);
 hipError_t launch_ratio_sqrt(hipStream_t st, const double* stats, double* out);

@@ -359,13 +359,19 @@ __global__ void k_omega_t_bf16(const float* __restrict__ omega /* n x l row-majo
   }
 }
 
+// W = sum of the workgroup partials, in FP64, in a fixed order (eight
+// interleaved running sums, then their sum), so the result is reproducible
 __global__ void k_reduce_partials_f32(const float* __restrict__ part, int64_t nparts, int64_t count,
                                       double* __restrict__ out) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
        e += (int64_t)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int64_t g = 0; g < nparts; ++g) s += (double)part[g * count + e];
-    out[e] = s;
+    double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int64_t g = 0;
+    for (; g + 8 <= nparts; g += 8)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s[u] += (double)part[(g + u) * count + e];
+    for (; g < nparts; ++g) s[0] += (double)part[g * count + e];
+    out[e] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
   }
 }
 
