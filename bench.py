@@ -92,6 +92,9 @@ def main() -> int:
     ap.add_argument("--cpu-rows", type=int, default=393216)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32-plain run")
+    ap.add_argument("--sketch-only", action="store_true",
+                    help="profiling aid for hardware counters: a plain 1 GiB device copy (the "
+                         "calibration kernel for FETCH_SIZE / WRITE_SIZE) and three sketch passes")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -111,6 +114,17 @@ def main() -> int:
     A = synth.spectral_snapshots(cfg, device="cuda")
     torch.cuda.synchronize()
     N, n = A.shape
+    if args.sketch_only:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            sid.sketch(A, k, p, seed=0, prec=args.prec, probe_rows=q, want_y=True)
+        torch.cuda.synchronize()
+        print(json.dumps({"sketch_only": True, "copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30,
+                          "A_bytes": N * n * 4, "Y_bytes": N * (k + p) * 4, "prec": args.prec}), flush=True)
+        return 0
     bytes_a = N * n * 4
     l = k + p
 
