@@ -236,3 +236,74 @@ def test_reconstruct_matches_oracle(sid, oracle_mod):
         out = sid.reconstruct(to_gpu(AJ64, dt), to_gpu(P64, dt))
         ref = oracle_mod.reconstruct(AJ64, P64)
         np.testing.assert_allclose(host(out), ref, rtol=0, atol=tol * np.abs(ref).max())
+
+
+
+@pytest.mark.timeout(400)
+def test_c2_full_size_sampled(sid, oracle_mod):
+    """The benchmarked workload at full size (1,572,864 x 500 FP32 channel-like
+    snapshots; single pass, bf16x2, k = 100, p = 20, e = 20, q = 10), in the
+    launch configuration the benchmark times.  The oracle forms W over every
+    row (its own Psi, row block by row block, with the |Psi||A| bound beside
+    it) and Y on sampled rows; J is compared up to the oracle's first
+    near-tie; P(:, J) = I exactly; the error of the returned decomposition is
+    compared with the oracle's error routine on sampled rows."""
+    k, p, q = 100, 20, 10
+    l, lz = k + p, k + 2 * p
+    lq = lz + q
+    seed, prec = 0, "bf16x2"
+    say("c2 full size: synthesizing")
+    A = synth.spectral_snapshots(synth.SpectralConfig(), device="cuda")
+    N, n = A.shape
+    assert (N, n) == (1572864, 500)
+    W, Y = sid.sketch(A, k, p, seed=seed, prec=prec, probe_rows=q, want_y=True)
+    out = sid.compress(A, k, p, seed=seed, mode="single_pass", prec=prec, probe_rows=q)
+    torch.cuda.synchronize()
+    Wg, Yg = host(W), host(Y)
+    Acpu = A.cpu()
+    say("c2 full size: oracle W over all rows")
+    Wo = np.zeros((lq, n))
+    Wb = np.zeros((lq, n))
+    blk = 1 << 16
+    for r0 in range(0, N, blk):
+        rows = np.arange(r0, min(N, r0 + blk))
+        M = oracle_mod.data_values(Acpu[r0:r0 + rows.size].double().numpy(), prec)
+        Ps = oracle_mod.psi(seed, rows, lq, prec)
+        Wo += Ps @ M
+        Wb += np.abs(Ps) @ np.abs(M)
+        if (r0 // blk) % 6 == 5:
+            say("c2 full size: oracle rows done", r0 + rows.size)
+    assert Wg.shape == (lq, n)
+    err = np.abs(Wg - Wo)
+    say("c2 full size: W max err / bound", (err / Wb).max())
+    assert np.all(err <= RTOL[prec] * Wb), (err / Wb).max()
+    say("c2 full size: Y on sampled rows")
+    rng = np.random.default_rng(12)
+    rows = np.sort(rng.choice(N, size=4096, replace=False))
+    A_rows = Acpu[rows].double().numpy()
+    Om = oracle_mod.omega(seed, n, l, prec)
+    Yo = oracle_mod.sketch_y(A_rows, Om, prec)
+    ybound = np.abs(oracle_mod.data_values(A_rows, prec)) @ np.abs(Om)
+    yerr = np.abs(Yg[rows].astype(np.float64) - Yo)
+    assert np.all(yerr <= RTOL[prec] * ybound), (yerr / ybound).max()
+    say("c2 full size: pivots against the oracle's mgsqr of its own W")
+    cp = oracle_mod.cpqr(Wo[:l], k)
+    assert cp.k_eff == k and int(host(out.k_eff)[0]) == k
+    J = host(out.J)
+    tie = np.nonzero(cp.margins <= 1e-4)[0]
+    ist = int(tie[0]) if tie.size else k
+    say("c2 full size: pivots compared up to", ist)
+    assert ist >= 10
+    assert J[:ist].tolist() == cp.J[:ist].tolist()
+    assert len(set(J.tolist())) == k and J.min() >= 0 and J.max() < n
+    P = host(out.P).astype(np.float64)
+    assert np.array_equal(P[:, J], np.eye(k))
+    say("c2 full size: error of the decomposition on sampled rows")
+    AJ = out.AJ[torch.from_numpy(rows).cuda()]
+    eg = sid.error_norms(A[torch.from_numpy(rows).cuda()], AJ, out.P)
+    eo = oracle_mod.error_norms(A_rows, host(AJ).astype(np.float64), P)
+    assert abs(eg["fro_err"] - eo["fro_err"]) <= 1e-9 * eo["fro_err"], (eg, eo)
+    assert abs(eg["fro_a"] - eo["fro_a"]) <= 1e-12 * eo["fro_a"], (eg, eo)
+    full = sid.error_norms(A, out.AJ, out.P)
+    say("c2 full size: rel_fro sampled", eo["rel_fro"], "whole", full["rel_fro"])
+    assert full["rel_fro"] < 1e-2 and eo["rel_fro"] < 1e-2
