@@ -87,6 +87,7 @@ def lib():
         L.oracle_round_bf16.restype = ctypes.c_double
         L.oracle_round_e4m3.argtypes = [ctypes.c_double]
         L.oracle_round_e4m3.restype = ctypes.c_double
+        L.oracle_round_e4m3_array.argtypes = [vp, i64]
         _LIB = L
     return _LIB
 
@@ -127,8 +128,8 @@ def round_values(x: np.ndarray, kind: str) -> np.ndarray:
         r = ((f + np.uint64(0x7FFF) + lsb) & np.uint64(0xFFFF0000)).astype(np.uint32)
         return r.view(np.float32).astype(np.float64)
     if kind == "e4m3":
-        fn = lib().oracle_round_e4m3
-        flat = np.array([fn(float(v)) for v in x.reshape(-1)])
+        flat = np.array(x, dtype=np.float64, copy=True).reshape(-1)
+        lib().oracle_round_e4m3_array(_ptr(flat), flat.size)
         return flat.reshape(x.shape)
     raise ValueError(kind)
 
@@ -150,7 +151,8 @@ def data_values(A: np.ndarray, prec: str) -> np.ndarray:
     f64: as given.  f32: rounded to single.  bf16: rounded to bfloat16.
     bf16x2: hi + lo with hi = bf16(a), lo = bf16(a - hi) (a two-term split of
     the single-precision value).  fp8 reads per-tile scaled e4m3 values
-    (see ``fp8_data_values``)."""
+    (see ``fp8_data_values``; A must then hold whole 64-row tiles from row
+    0 of the matrix)."""
     A = np.asarray(A, dtype=np.float64)
     if prec == "f64":
         return A
@@ -163,7 +165,36 @@ def data_values(A: np.ndarray, prec: str) -> np.ndarray:
         hi = round_values(a32, "bf16")
         lo = round_values((a32.astype(np.float64) - hi).astype(np.float32), "bf16")
         return hi + lo
+    if prec == "fp8":
+        return fp8_data_values(A)
     raise ValueError(prec)
+
+
+FP8_TILE_ROWS = 64
+
+
+def fp8_data_values(A: np.ndarray) -> np.ndarray:
+    """Values of FP32 data as the FP8 (e4m3) sketch reads them.
+
+    The rows of A are cut into tiles of 64 consecutive rows (the last one
+    ragged); each (tile, column) pair gets a power-of-two scale
+    s = 2^(E - 7), E = floor(log2 max|a|) over the tile's entries, clamped to
+    [-100, 120] (s = 1 for an all-zero tile), so that |a| / s < 256 <= 448,
+    the largest e4m3 value.  Each entry becomes s * e4m3(a / s), nearest with
+    ties to even.  The paper fixes no low-precision format; this per-tile
+    scaling is the usual way of putting data of any magnitude into e4m3's
+    narrow exponent range."""
+    A = np.asarray(A, dtype=np.float64).astype(np.float32).astype(np.float64)
+    N, n = A.shape
+    out = np.empty_like(A)
+    for t0 in range(0, N, FP8_TILE_ROWS):
+        blk = A[t0:t0 + FP8_TILE_ROWS]
+        amax = np.abs(blk).max(axis=0)
+        _, ex = np.frexp(amax)                 # amax = f 2^ex, f in [0.5, 1)
+        E = np.clip(ex - 1, -100, 120)
+        s = np.where(amax > 0, np.ldexp(1.0, E - 7), 1.0)
+        out[t0:t0 + FP8_TILE_ROWS] = round_values(blk / s, "e4m3") * s
+    return out
 
 
 def omega(seed: int, n: int, l: int, prec: str = "f64", col0: int = 0) -> np.ndarray:

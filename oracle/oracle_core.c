@@ -269,6 +269,11 @@ static double or_round_e4m3(double x)
 double oracle_round_bf16(double x) { return or_round_bf16(x); }
 double oracle_round_e4m3(double x) { return or_round_e4m3(x); }
 
+void oracle_round_e4m3_array(double *x, int64_t count)
+{
+    for (int64_t i = 0; i < count; ++i) x[i] = or_round_e4m3(x[i]);
+}
+
 static or_round_fn or_pick_round(int mode)
 {
     /* 0: FP32 single value as is; 1: bfloat16; 2: e4m3 */

@@ -121,6 +121,58 @@ def test_rounding_maps(oracle_mod):
     assert r(np.array([2 ** -9, 3 * 2 ** -10]), "e4m3").tolist() == [2 ** -9, 2 ** -8]
 
 
+def test_e4m3_matches_torch_cast(oracle_mod):
+    """The oracle's e4m3 rounding equals torch's float8_e4m3fn conversion (an
+    independent implementation) on every FP32 value of a wide sweep below the
+    saturation point, including the subnormal range and halfway cases."""
+    import torch
+    rng = np.random.default_rng(3)
+    x = np.concatenate([
+        rng.standard_normal(20000) * 10.0 ** rng.uniform(-4, 2.3, 20000),
+        np.arange(-2048, 2049) * 2.0 ** -12,                # subnormals and halfway points
+        # normal-range halfway points (1 + (2m + 1)/16) 2^e
+        ((1.0 + (2 * np.arange(8) + 1) / 16.0)[None, :] * 2.0 ** np.arange(-6, 8)[:, None]).ravel(),
+    ]).astype(np.float32)
+    x = x[np.abs(x) < 448.0]
+    ours = oracle_mod.round_values(x.astype(np.float64), "e4m3")
+    ref = torch.from_numpy(x).to(torch.float8_e4m3fn).float().numpy().astype(np.float64)
+    assert np.array_equal(ours, ref)
+
+
+def test_fp8_tile_scaled_values(oracle_mod):
+    """FP8 data values: every 64-row tile of a column is scaled by a power of
+    two that puts its largest magnitude in [128, 256); the result equals
+    torch's e4m3 cast of the scaled tile, scaled back; relative error <= 2^-4
+    for entries not in the subnormal range; scaling a tile by 2^m scales its
+    values by 2^m exactly; all-zero tiles stay zero."""
+    import torch
+    rng = np.random.default_rng(4)
+    N, n = 300, 6
+    A = (rng.standard_normal((N, n)) * np.array([1.0, 1e-3, 1e4, 0.0, 7.0, 2.0 ** -20])).astype(np.float32)
+    A[70:100, 4] = 0.0
+    A64 = A.astype(np.float64)
+    V = oracle_mod.data_values(A64, "fp8")
+    for t0 in range(0, N, 64):
+        blk = A64[t0:t0 + 64]
+        for j in range(n):
+            col = blk[:, j]
+            amax = np.abs(col).max()
+            if amax == 0:
+                assert np.all(V[t0:t0 + 64, j] == 0)
+                continue
+            s = 2.0 ** (math.floor(math.log2(amax)) - 7)
+            assert 128 <= amax / s < 256
+            ref = torch.from_numpy((col / s).astype(np.float32)).to(torch.float8_e4m3fn)
+            assert np.array_equal(V[t0:t0 + 64, j], ref.double().numpy() * s)
+            big = np.abs(col) >= s * 2.0 ** -6
+            assert np.all(np.abs(V[t0:t0 + 64, j][big] - col[big]) <= 2.0 ** -4 * np.abs(col[big]))
+    B = A64.copy()
+    B[64:128] *= 2.0 ** 5
+    VB = oracle_mod.data_values(B, "fp8")
+    assert np.array_equal(VB[64:128], V[64:128] * 2.0 ** 5)
+    assert np.array_equal(VB[:64], V[:64]) and np.array_equal(VB[128:], V[128:])
+
+
 # ---------------------------------------------------------------------------
 # Sketches
 # ---------------------------------------------------------------------------
@@ -141,6 +193,32 @@ def test_sketch_matches_matmul(oracle_mod):
     Om = oracle_mod.omega(4, n, l, "f64")
     Y = oracle_mod.sketch_y(A, Om, "f64")
     np.testing.assert_allclose(Y, A @ Om, rtol=1e-12, atol=1e-12)
+
+
+def test_fp8_sketch_matches_matmul(oracle_mod):
+    """FP8 sketches: W and Y equal a library matmul of the Gaussian draws cast
+    to e4m3 by torch and the tile-scaled e4m3 data; the FP8 ID of a
+    well-separated low-rank matrix stays within the e4m3 precision of it."""
+    import torch
+    A = _small(640, 24, 5)
+    N, n = A.shape
+    lq, l = 19, 12
+    z = oracle_mod.gaussian(9, 1, np.arange(N), 0, lq)
+    Psi = torch.from_numpy(z).to(torch.float8_e4m3fn).double().numpy().T
+    Ad = oracle_mod.data_values(A, "fp8")
+    W = oracle_mod.sketch_w(A, None, lq, 9, "fp8")
+    np.testing.assert_allclose(W, Psi @ Ad, rtol=1e-12, atol=1e-12)
+    zo = oracle_mod.gaussian(9, 0, np.arange(n), 0, l)
+    Om = torch.from_numpy(zo).to(torch.float8_e4m3fn).double().numpy()
+    assert np.array_equal(Om, oracle_mod.omega(9, n, l, "fp8"))
+    np.testing.assert_allclose(oracle_mod.sketch_y(A, Om, "fp8"), Ad @ Om, rtol=1e-12, atol=1e-12)
+    rng = np.random.default_rng(6)
+    L = rng.standard_normal((2000, 5)) @ rng.standard_normal((5, 40))
+    for mode in ("two_pass", "single_pass"):
+        res = oracle_mod.compress(L, k=5, oversample=5, seed=2, mode=mode, prec="fp8",
+                                  sp_rcond=1e-3)
+        e = oracle_mod.error_norms(L, res.AJ, res.P)
+        assert e["rel_fro"] < 0.1, (mode, e)
 
 
 def test_sketch_identity_and_scaling(oracle_mod):
