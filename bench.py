@@ -88,7 +88,9 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--prec", default="bf16x2", choices=["bf16x2", "bf16", "f32", "f64"])
+    ap.add_argument("--prec", default="bf16x2", choices=["bf16x2", "bf16", "fp8", "f32", "f64"])
+    ap.add_argument("--also", default="bf16,fp8",
+                    help="further sketch precisions timed beside the main one (comma list, '' for none)")
     ap.add_argument("--cpu-rows", type=int, default=393216)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32-plain run")
@@ -144,6 +146,9 @@ def main() -> int:
     cmp_r = None
     if not args.no_compare and args.prec != "f32":
         cmp_r = run_mode("f32", max(3, args.steps // 2), 1)
+    also = {}
+    for pr in [x for x in args.also.split(",") if x and x != args.prec]:
+        also[pr] = run_mode(pr, max(3, args.steps // 2), 1)
 
     # roofline of the sketch pass: algorithmic bytes = read A once + write Y
     alg_bytes = bytes_a + N * l * 4
@@ -169,11 +174,15 @@ def main() -> int:
     if cmp_r is not None:
         config["fp32_plain"] = {"value": round(cmp_r["gbs"], 2), "ms_per_step": round(cmp_r["ms"], 4),
                                 "rel_fro_error": cmp_r["rel_fro"], "sketch_ms": round(cmp_r["sketch_ms"], 4)}
+    for pr, r in also.items():
+        config[pr] = {"value": round(r["gbs"], 2), "ms_per_step": round(r["ms"], 4),
+                      "rel_fro_error": r["rel_fro"], "probe_estimate": r["est"],
+                      "sketch_ms": round(r["sketch_ms"], 4)}
     line = {
         "metric": METRIC, "value": round(main_r["gbs"], 2), "unit": "GB/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(main_r["ms"], 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"bf16x2": "bf16", "bf16": "bf16", "f32": "f32", "f64": "f64"}[args.prec],
+        "dtype": {"bf16x2": "bf16", "bf16": "bf16", "fp8": "fp8", "f32": "f32", "f64": "f64"}[args.prec],
         "data": "synthetic", "config": config, "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

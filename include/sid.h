@@ -72,12 +72,22 @@ typedef enum { SID_F64 = 0, SID_F32 = 1 } sid_dtype;
  *   BF16X2  Gaussians rounded to bfloat16; data split a = hi + lo, hi =
  *           bf16(a), lo = bf16(a - hi) (16 significant bits); FP32
  *           accumulation
- * The small factorizations after the pass are always FP64. */
+ *   FP8E4M3 Gaussians rounded to OCP e4m3 (nearest even, saturating at
+ *           448); data read as s * e4m3(a / s) with one power-of-two scale
+ *           s = 2^(E - 7) per tile of 64 consecutive rows (counted from row
+ *           0 of A) and column, E = floor(log2 max|a|) over the tile clamped
+ *           to [-100, 120] (s = 1 for a zero tile); exact products, FP32
+ *           accumulation.  Needs FP32 data with lda % 4 == 0 and a 16-byte
+ *           aligned A, all rows (no coarse set), n <= 512, l <= 128 and
+ *           l + co-range + probe rows <= 160; otherwise SID_EINVAL.
+ * The small factorizations after the pass are always FP64.  The paper names
+ * no low-precision format; these are this library's. */
 typedef enum {
     SID_SK_F64 = 0,
     SID_SK_F32 = 1,
     SID_SK_BF16 = 2,
-    SID_SK_BF16X2 = 3
+    SID_SK_BF16X2 = 3,
+    SID_SK_FP8E4M3 = 4
 } sid_sketch_prec;
 
 typedef enum { SID_TWO_PASS = 0, SID_SINGLE_PASS = 1 } sid_mode;

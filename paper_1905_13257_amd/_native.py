@@ -12,7 +12,7 @@ _LIBPATH = os.path.join(_HERE, "libsid.so")
 _LIB = None
 
 SID_F64, SID_F32 = 0, 1
-PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2, "bf16x2": 3}
+PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2, "bf16x2": 3, "fp8": 4}
 MODES = {"two_pass": 0, "single_pass": 1}
 _STATUS = {0: "SID_OK", -1: "SID_EINVAL", -2: "SID_ENOMEM", -3: "SID_EDEVICE",
            -4: "SID_ESTATE", -5: "SID_ENONFINITE", -6: "SID_ERANK"}

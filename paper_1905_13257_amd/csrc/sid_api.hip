@@ -102,6 +102,7 @@ double default_rcond(int prec) {
     case SID_SK_F64: return 1e-13;
     case SID_SK_F32: return 1e-6;
     case SID_SK_BF16X2: return 1e-5;
+    case SID_SK_FP8E4M3: return 1e-2;
     default: return 1e-3;
   }
 }
@@ -115,7 +116,7 @@ sid_status validate(sid_ctx* ctx, int64_t N, int64_t n, const sid_params* p, Sha
   if (p->k > n) return fail(ctx, SID_EINVAL, "k must not exceed the number of columns n");
   if (p->mode != SID_TWO_PASS && p->mode != SID_SINGLE_PASS)
     return fail(ctx, SID_EINVAL, "unknown mode");
-  if (p->prec < SID_SK_F64 || p->prec > SID_SK_BF16X2)
+  if (p->prec < SID_SK_F64 || p->prec > SID_SK_FP8E4M3)
     return fail(ctx, SID_EINVAL, "unknown sketch precision");
   if (!(p->rank_tol >= 0.0) || !(p->sp_rcond >= 0.0))
     return fail(ctx, SID_EINVAL, "rank_tol and sp_rcond must be >= 0");
@@ -383,9 +384,16 @@ static sid_status run_sketch(sid_ctx* ctx, const void* A, sid_dtype dtype, int64
               "omega generation");
   }
   const int64_t* rows = p->coarse ? p->coarse->d_rows : nullptr;
-  const bool bf = sh.prec == SID_SK_BF16 || sh.prec == SID_SK_BF16X2;
-  if (bf && dtype == SID_F32 &&
-      sid::fused_bf16_supported(sh.n, (int)sh.lq, (int)sh.l, lda, A, rows != nullptr)) {
+  const bool bf = sh.prec == SID_SK_BF16 || sh.prec == SID_SK_BF16X2 ||
+                  sh.prec == SID_SK_FP8E4M3;
+  const bool fused_ok =
+      dtype == SID_F32 &&
+      sid::fused_bf16_supported(sh.n, (int)sh.lq, (int)sh.l, lda, A, rows != nullptr);
+  if (sh.prec == SID_SK_FP8E4M3 && !fused_ok)
+    return fail(ctx, SID_EINVAL,
+                "the FP8 sketch needs FP32 data with 16-byte aligned columns (lda % 4 == 0), all "
+                "rows (no coarse set), n <= 512, l <= 128 and l + co-range + probe <= 160");
+  if (bf && fused_ok) {
     // one streaming pass on the matrix cores (W partials per workgroup, FP32)
     int64_t rpw = 0;
     const int64_t grid = sid::fused_bf16_grid(sh.N, ctx->num_cu, &rpw);
@@ -393,7 +401,10 @@ static sid_status run_sketch(sid_ctx* ctx, const void* A, sid_dtype dtype, int64
     __bf16* omT = (__bf16*)ws(ctx, WS_OMT, sizeof(uint16_t) * 128 * 512);
     if (!partf || !omT) return SID_ENOMEM;
     int64_t nparts = 0;
-    SID_CHECK(sid::launch_sketch_fused_bf16(st, sh.prec == SID_SK_BF16X2, (const float*)A, lda,
+    const int dmode = sh.prec == SID_SK_BF16X2   ? sid::FB_BF16X2
+                      : sh.prec == SID_SK_FP8E4M3 ? sid::FB_FP8
+                                                  : sid::FB_BF16;
+    SID_CHECK(sid::launch_sketch_fused_bf16(st, dmode, (const float*)A, lda,
                                             sh.N, (int)sh.n, (int)sh.lq, (int)sh.l, p->seed,
                                             w.omega, omT, ctx->num_cu, partf, W, (float*)Y,
                                             &nparts),
@@ -506,7 +517,8 @@ sid_status sid_compress(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N,
     SID_CHECK(sid::launch_small_solve(st, w.RM, l, w.pivM, w.rkM, w.R11, w.C, l, k, w.T), "T");
     if (AJ) {
       const bool yf64 = sh.prec == SID_SK_F64;
-      const bool ybf = sh.prec == SID_SK_BF16 || sh.prec == SID_SK_BF16X2;
+      const bool ybf = sh.prec == SID_SK_BF16 || sh.prec == SID_SK_BF16X2 ||
+                       sh.prec == SID_SK_FP8E4M3;
       if (ybf && sid::apply_t_bf16_supported(k, l))
         SID_CHECK(sid::launch_apply_t_bf16(st, (const float*)w.Y, sh.N, l, w.T, k, AJ, f64, ldaj,
                                            ctx->num_cu),

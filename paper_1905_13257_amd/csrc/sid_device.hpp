@@ -124,7 +124,7 @@ __device__ __forceinline__ void gauss4(uint64_t seed, uint32_t stream, uint64_t 
 // ---------------------------------------------------------------------------
 // Sketch precisions
 // ---------------------------------------------------------------------------
-enum Prec : int { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_BF16X2 = 3 };
+enum Prec : int { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_BF16X2 = 3, P_FP8 = 4 };
 
 // bfloat16 round to nearest even, returned as the (exact) float value
 __device__ __forceinline__ float bf16_value(float f) {
@@ -134,11 +134,37 @@ __device__ __forceinline__ float bf16_value(float f) {
   return __uint_as_float(b);
 }
 
+// OCP FP8 e4m3fn round to nearest even (3 fraction bits, bias 7, largest
+// value 448, subnormal step 2^-9), saturating; returned as the exact float.
+// Normal range: round the FP32 significand to 3 fraction bits on the bit
+// pattern; below 2^-6: a multiple of 2^-9 (rint is ties-to-even).
+__device__ __forceinline__ float e4m3_value(float x) {
+  const float ax = fabsf(x);
+  const float rs = rintf(ax * 512.0f) * 0.001953125f;  // branch-free: both forms, then select
+  uint32_t b = __float_as_uint(ax);
+  b = (b + 0x7FFFFu + ((b >> 20) & 1u)) & 0xFFF00000u;
+  const float rn = fminf(__uint_as_float(b), 448.0f);
+  return copysignf(ax < 0.015625f ? rs : rn, x);
+}
+
 // value a Gaussian draw takes in each precision
 template <int PREC>
 __device__ __forceinline__ float gauss_value(float z) {
   if constexpr (PREC == P_BF16 || PREC == P_BF16X2) return bf16_value(z);
+  else if constexpr (PREC == P_FP8) return e4m3_value(z);
   else return z;
+}
+
+// Power-of-two scale of an FP8 data tile with largest magnitude amax:
+// 2^(E - 7), E = floor(log2 amax) clamped to [-100, 120]; 1 for amax = 0.
+// Returns the scale and sets inv to its reciprocal (both exact).
+__device__ __forceinline__ float fp8_tile_scale(float amax, float& inv) {
+  int E = (int)((__float_as_uint(amax) >> 23) & 0xFFu) - 127;
+  E = E < -100 ? -100 : (E > 120 ? 120 : E);
+  const bool zero = !(amax > 0.0f);
+  const float s = zero ? 1.0f : __uint_as_float((uint32_t)(E - 7 + 127) << 23);
+  inv = zero ? 1.0f : __uint_as_float((uint32_t)(7 - E + 127) << 23);
+  return s;
 }
 
 // value a data entry takes in each precision (compute type T)

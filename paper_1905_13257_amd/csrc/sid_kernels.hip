@@ -746,6 +746,7 @@ hipError_t launch_omega_values(hipStream_t st, int prec, const float* z, int64_t
     case P_F32: hipLaunchKernelGGL(k_omega_values<P_F32>, dim3((unsigned)b), dim3(256), 0, st, z, count, out); break;
     case P_BF16: hipLaunchKernelGGL(k_omega_values<P_BF16>, dim3((unsigned)b), dim3(256), 0, st, z, count, out); break;
     case P_BF16X2: hipLaunchKernelGGL(k_omega_values<P_BF16X2>, dim3((unsigned)b), dim3(256), 0, st, z, count, out); break;
+    case P_FP8: hipLaunchKernelGGL(k_omega_values<P_FP8>, dim3((unsigned)b), dim3(256), 0, st, z, count, out); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

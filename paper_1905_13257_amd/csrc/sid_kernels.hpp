@@ -46,9 +46,11 @@ hipError_t launch_error_norms(hipStream_t st, bool f64, const void* A, int64_t l
 }  // namespace sid
 
 namespace sid {
+// how the fused pass feeds the data to the bf16 matrix products
+enum FusedData : int { FB_BF16 = 0, FB_BF16X2 = 1, FB_FP8 = 2 };
 bool fused_bf16_supported(int64_t n, int lq, int l, int64_t lda, const void* A, bool has_rows);
 int64_t fused_bf16_grid(int64_t N, int num_cu, int64_t* rows_per_wg);
-hipError_t launch_sketch_fused_bf16(hipStream_t st, bool split, const float* A, int64_t lda,
+hipError_t launch_sketch_fused_bf16(hipStream_t st, int dmode, const float* A, int64_t lda,
                                     int64_t N, int n, int lq, int l, uint64_t seed,
                                     const float* omega, __bf16* omT, int num_cu, float* part,
                                     double* W, float* Y, int64_t* nparts_out);

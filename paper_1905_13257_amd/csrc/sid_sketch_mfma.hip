@@ -117,6 +117,7 @@ __device__ __forceinline__ void load_chunk_tail(const float* __restrict__ pc, in
 
 // Items [i0, i1) of Psi(0:lq, panel p0): item w covers panel row w % 64 and
 // rows 4*(w/64) .. +3 of Psi.  Written in operand-slot order.
+template <bool FP8>
 __device__ __forceinline__ void gen_psi(__bf16* __restrict__ s_psi, uint64_t seed, int64_t p0,
                                         int64_t r1, int lq, int i0, int i1, int tid) {
   // opaque thread index: the start items of the slices would otherwise be
@@ -131,16 +132,19 @@ __device__ __forceinline__ void gen_psi(__bf16* __restrict__ s_psi, uint64_t see
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int m = 4 * g + e;
-      if (m < lq) s_psi[m * FB_PROW + pos] = to_bf16(z[e]);
+      if (m < lq) s_psi[m * FB_PROW + pos] = to_bf16(FP8 ? e4m3_value(z[e]) : z[e]);
     }
   }
 }
 
+// DM: how the data enter the products (FB_BF16: bf16(a); FB_BF16X2: hi + lo;
+// FB_FP8: the e4m3 value of a scaled by its tile's power of two, which is a
+// bfloat16 value, so the bf16 products are exact).
 // MT: 16-row tiles of W (lq <= 16*MT); LT: 16-column tiles of Y (l <= 16*LT);
 // NCH: chunks of 128 columns per panel (n <= 128*NCH); WANTY: form Y.
 // Every count that shapes the register state is a template argument, so the
 // chunk loop unrolls into straight-line code with no merges of accumulators.
-template <bool SPLIT, bool WANTY, int MT, int LT, int NCH>
+template <int DM, bool WANTY, int MT, int LT, int NCH>
 __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
     const float* __restrict__ A, int64_t lda, int64_t N, int n, int lq, int l, uint64_t seed,
     const __bf16* __restrict__ omT /* LT*16 x FB_NPAD, k contiguous, zero padded */,
@@ -150,6 +154,8 @@ __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
   // Y tiles of a panel: 4 row tiles x LT column tiles; wave w owns column
   // tile w % LT and YR row tiles from rt0 = (w / LT) YR
   constexpr int YR = 4 * LT / FB_WAVES;
+  constexpr bool SPLIT = DM == FB_BF16X2;
+  constexpr bool FP8 = DM == FB_FP8;
   constexpr int NH = SPLIT ? 2 : 1;               // bf16 terms per value
   constexpr int MTR = MT < FB_MTR ? MT : FB_MTR;  // W row tiles in registers
   constexpr int MTX = MT - MTR;                   // W row tiles accumulated in LDS
@@ -189,7 +195,7 @@ __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
   float v[16];                       // this wave's slice of the chunk in flight
   if (r0 < r1f) load_chunk(A + r0, lda, n, col_w, lg, v);
   lds_barrier();  // zeroed Psi visible
-  if (r0 < r1) gen_psi(s_psi[0], seed, r0, r1, lq, 0, gen_items, tid);
+  if (r0 < r1) gen_psi<FP8>(s_psi[0], seed, r0, r1, lq, 0, gen_items, tid);
 
   // per-lane offset of this lane's Omega^T fragments (bf16 elements)
   const uint32_t om_lane = (uint32_t)((yc * 16 + lr) * FB_NPAD + 8 * lg);
@@ -227,12 +233,24 @@ __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
           of[ks] = *(gbf16x8p)(om + (om_lane + (uint32_t)(FB_CHUNK * j + 32 * ks)));
       }
       // (2) split into bf16 hi (+ lo) B operands and the transposed copy
+      //     (FP8: the column's 64-row tile scale from the four lanes that
+      //     hold it)
+      float fs = 1.0f, fsi = 1.0f;
+      if constexpr (FP8) {
+        float amax = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) amax = fmaxf(amax, fabsf(v[i]));
+        amax = fmaxf(amax, __shfl_xor(amax, 16, 64));
+        amax = fmaxf(amax, __shfl_xor(amax, 32, 64));
+        fs = fp8_tile_scale(amax, fsi);
+      }
       bf16x8_t bh[2], bl[2];
 #pragma unroll
       for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-          const float x = col_ok ? v[8 * ks + i] : 0.0f;
+          float x = col_ok ? v[8 * ks + i] : 0.0f;
+          if constexpr (FP8) x = e4m3_value(x * fsi) * fs;
           const __bf16 h = to_bf16(x);
           bh[ks][i] = h;
           const int ci = slot_row(ks, lg, i) * FB_CROW + col_w;
@@ -282,7 +300,8 @@ __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
       }
       // (5) slice j of Psi(:, next panel) (the buffer the previous panel used)
       if (!TAIL && pn < r1)
-        gen_psi(s_psi[pb ^ 1], seed, pn, r1, lq, gen_items * j / NCH, gen_items * (j + 1) / NCH, tid);
+        gen_psi<FP8>(s_psi[pb ^ 1], seed, pn, r1, lq, gen_items * j / NCH, gen_items * (j + 1) / NCH,
+                     tid);
       lds_barrier();  // chunk buffer complete
       // (6) Y(panel, this wave's tiles) += A(panel, chunk) Omega(chunk, :)
       if constexpr (WANTY) {
@@ -350,12 +369,14 @@ __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
   }
 }
 
-// Omega^T in bfloat16, zero padded: out[c * FB_NPAD + k] = bf16(G(seed, 0, k, c))
+// Omega^T in bfloat16 (FP8 mode: the e4m3 values, exact in bfloat16), zero
+// padded: out[c * FB_NPAD + k] = value of G(seed, 0, k, c)
 __global__ void k_omega_t_bf16(const float* __restrict__ omega /* n x l row-major */, int n, int l,
-                               int lpad, __bf16* __restrict__ out) {
+                               int lpad, int fp8, __bf16* __restrict__ out) {
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < lpad * FB_NPAD; e += gridDim.x * blockDim.x) {
     const int c = e / FB_NPAD, k = e - c * FB_NPAD;
-    out[e] = to_bf16((c < l && k < n) ? omega[k * l + c] : 0.0f);
+    const float z = (c < l && k < n) ? omega[k * l + c] : 0.0f;
+    out[e] = to_bf16(fp8 ? e4m3_value(z) : z);
   }
 }
 
@@ -390,13 +411,14 @@ int64_t fused_bf16_grid(int64_t N, int num_cu, int64_t* rows_per_wg) {
   return g;
 }
 
-hipError_t launch_sketch_fused_bf16(hipStream_t st, bool split, const float* A, int64_t lda,
+hipError_t launch_sketch_fused_bf16(hipStream_t st, int dmode, const float* A, int64_t lda,
                                     int64_t N, int n, int lq, int l, uint64_t seed,
                                     const float* omega, __bf16* omT, int num_cu, float* part,
                                     double* W, float* Y, int64_t* nparts_out) {
   const int lpad = ((l + 63) / 64) * 64;  // Y tiles: a multiple of 4 tiles of 16
   if (Y) {
-    hipLaunchKernelGGL(k_omega_t_bf16, dim3(256), dim3(256), 0, st, omega, n, l, lpad, omT);
+    hipLaunchKernelGGL(k_omega_t_bf16, dim3(256), dim3(256), 0, st, omega, n, l, lpad,
+                       dmode == FB_FP8 ? 1 : 0, omT);
   }
   int64_t rpw = 0;
   const int64_t grid = fused_bf16_grid(N, num_cu, &rpw);
@@ -417,7 +439,9 @@ hipError_t launch_sketch_fused_bf16(hipStream_t st, bool split, const float* A, 
   if (!Y) { SID_FUSED_MT(SP, false, 8) }                     \
   else if (lpad <= 64) { SID_FUSED_MT(SP, true, 4) }         \
   else { SID_FUSED_MT(SP, true, 8) }
-  if (split) { SID_FUSED_SP(true) } else { SID_FUSED_SP(false) }
+  if (dmode == FB_BF16X2) { SID_FUSED_SP(FB_BF16X2) }
+  else if (dmode == FB_FP8) { SID_FUSED_SP(FB_FP8) }
+  else { SID_FUSED_SP(FB_BF16) }
 #undef SID_FUSED_SP
 #undef SID_FUSED_MT
 #undef SID_FUSED_NCH

@@ -26,9 +26,20 @@ def sid():
     return m
 
 
-def to_gpu(A64: np.ndarray, dtype=torch.float32) -> torch.Tensor:
+def to_gpu(A64: np.ndarray, dtype=torch.float32, ld: int | None = None) -> torch.Tensor:
+    """Column-major device copy; ld > N pads every column (leading dimension)."""
     t = torch.from_numpy(np.asfortranarray(A64)).to(dtype)
-    return synth.as_colmajor(t).cuda()
+    if ld is None:
+        return synth.as_colmajor(t).cuda()
+    N, n = A64.shape
+    store = torch.zeros((n, ld), dtype=dtype, device="cuda")
+    out = store.T[:N]
+    out.copy_(t.cuda())
+    return out
+
+
+def ld4(N: int) -> int:
+    return (N + 3) // 4 * 4
 
 
 def host(t: torch.Tensor) -> np.ndarray:
@@ -37,7 +48,7 @@ def host(t: torch.Tensor) -> np.ndarray:
 
 # sketch tolerance: relative to sum |Psi||A| per entry (accumulation error bound)
 # |err| <= 10 sqrt(L) u * sum|Psi||A| with L <= 8192 terms per partial sum
-RTOL = {"f64": 1e-13, "f32": 5e-5, "bf16": 5e-5, "bf16x2": 5e-5}
+RTOL = {"f64": 1e-13, "f32": 5e-5, "bf16": 5e-5, "bf16x2": 5e-5, "fp8": 5e-5}
 
 
 def _absbound(A64, rows, lq, seed, prec, oracle_mod):
@@ -79,19 +90,22 @@ def test_sketch_parity(sid, oracle_mod, prec, shape):
     assert np.all(yerr <= RTOL[prec] * ybound + 1e-300), (yerr / ybound).max()
 
 
-@pytest.mark.parametrize("prec", ["bf16", "bf16x2"])
+@pytest.mark.parametrize("prec", ["bf16", "bf16x2", "fp8"])
 @pytest.mark.parametrize("shape", [(2597, 500, 100, 20, 10), (49394, 500, 100, 20, 10),
                                    (700, 129, 7, 3, 2), (5000, 300, 60, 10, 5)])
 def test_sketch_parity_streaming_sizes(sid, oracle_mod, prec, shape):
-    """Shapes that exercise the streaming matrix-core pass: n up to 512
-    (four 128-column chunks), lq up to 160 (W rows beyond 128 kept in LDS),
-    l up to 128, workgroups with full panels plus a ragged tail, and a
-    workgroup that owns only a tail."""
+    """Shapes that exercise the streaming matrix-core pass (FP32 data with a
+    leading dimension padded to a multiple of 4): n up to 512 (four
+    128-column chunks), lq up to 160 (W rows beyond 128 kept in LDS), l up to
+    128, workgroups with full panels plus a ragged tail, and a workgroup that
+    owns only a tail.  The data span several decades per column so that the
+    FP8 tile scales differ from tile to tile."""
     N, n, k, p, q = shape
     say("sketch streaming", prec, shape)
     rng = np.random.default_rng(N + 7 * n)
-    A64 = rng.standard_normal((N, n)).astype(np.float32).astype(np.float64)
-    A = to_gpu(A64, torch.float32)
+    A64 = rng.standard_normal((N, n)) * np.exp(rng.uniform(-3, 3, (N // 64 + 1, n))).repeat(64, 0)[:N]
+    A64 = A64.astype(np.float32).astype(np.float64)
+    A = to_gpu(A64, torch.float32, ld=ld4(N))
     seed = 11
     W, Y = sid.sketch(A, k, p, seed=seed, prec=prec, probe_rows=q, want_y=True)
     l = k + p
@@ -157,7 +171,7 @@ def test_c1_fp64_bit_exact_pivots(sid, oracle_mod, mode):
     assert eg["rel_fro"] >= opt * (1 - 1e-6)
 
 
-@pytest.mark.parametrize("prec", ["f32", "bf16x2", "bf16"])
+@pytest.mark.parametrize("prec", ["f32", "bf16x2", "bf16", "fp8"])
 def test_low_precision_modes(sid, oracle_mod, prec):
     """FP32 data, low-precision sketches: pivots agree with the oracle (run
     in the same sketch precision) until its first near-tie, and the error is
@@ -172,12 +186,12 @@ def test_low_precision_modes(sid, oracle_mod, prec):
         torch.cuda.synchronize()
         ref = oracle_mod.compress(A64, k, p, seed=1, mode=mode, prec=prec, probe_rows=q)
         J = host(out.J)
-        tie = {"f32": 1e-5, "bf16x2": 1e-4, "bf16": 1e-2}[prec]
+        tie = {"f32": 1e-5, "bf16x2": 1e-4, "bf16": 1e-2, "fp8": 3e-2}[prec]
         ist = next((i for i, m in enumerate(ref.cp.margins) if m <= tie), k)
         assert J[:ist].tolist() == ref.J[:ist].tolist(), (prec, mode, ist)
         eg = sid.error_norms(A, out.AJ, out.P)["rel_fro"]
         eo = oracle_mod.error_norms(A64, ref.AJ, ref.P)["rel_fro"]
-        fac = {"f32": 1.01, "bf16x2": 1.05, "bf16": 1.5}[prec]
+        fac = {"f32": 1.01, "bf16x2": 1.05, "bf16": 1.5, "fp8": 1.5}[prec]
         assert eg <= fac * eo + 1e-6, (prec, mode, eg, eo)
 
 
@@ -307,3 +321,18 @@ def test_c2_full_size_sampled(sid, oracle_mod):
     full = sid.error_norms(A, out.AJ, out.P)
     say("c2 full size: rel_fro sampled", eo["rel_fro"], "whole", full["rel_fro"])
     assert full["rel_fro"] < 1e-2 and eo["rel_fro"] < 1e-2
+
+
+def test_fp8_requirements_rejected(sid):
+    """The FP8 sketch runs only on the streaming pass: an unpadded leading
+    dimension that is not a multiple of 4, FP64 data or a coarse row set are
+    rejected with SID_EINVAL and a message, before any work."""
+    rng = np.random.default_rng(8)
+    A64 = rng.standard_normal((333, 20))
+    for A, coarse in [(to_gpu(A64, torch.float32), None), (to_gpu(A64, torch.float64, ld=336), None),
+                      (to_gpu(A64, torch.float32, ld=336), sid.RowSet(np.arange(0, 333, 3), 333))]:
+        with pytest.raises(sid.SidError) as ei:
+            sid.compress(A, 5, 5, prec="fp8", coarse=coarse)
+        assert ei.value.status == -1 and "FP8" in str(ei.value)
+    out = sid.compress(to_gpu(A64, torch.float32, ld=336), 5, 5, prec="fp8", mode="single_pass")
+    assert int(host(out.k_eff)[0]) == 5
