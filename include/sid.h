@@ -50,6 +50,7 @@ extern "C" {
 
 typedef struct sid_ctx sid_ctx;
 typedef struct sid_rowset sid_rowset;
+typedef struct sid_stream sid_stream;
 
 typedef enum {
     SID_OK = 0,
@@ -78,7 +79,7 @@ typedef enum { SID_F64 = 0, SID_F32 = 1 } sid_dtype;
  *           0 of A) and column, E = floor(log2 max|a|) over the tile clamped
  *           to [-100, 120] (s = 1 for a zero tile); exact products, FP32
  *           accumulation.  Needs FP32 data with lda % 4 == 0 and a 16-byte
- *           aligned A, all rows (no coarse set), n <= 512, l <= 128 and
+ *           aligned A, all rows (no coarse set), l <= 128 and
  *           l + co-range + probe rows <= 160; otherwise SID_EINVAL.
  * The small factorizations after the pass are always FP64.  The paper names
  * no low-precision format; these are this library's. */
@@ -197,6 +198,56 @@ sid_status sid_fill_gaussian(sid_ctx *ctx, uint64_t seed, int stream, int64_t ma
  * FP64 for SID_SK_F64 else FP32) exactly as sid_compress forms them. */
 sid_status sid_sketch(sid_ctx *ctx, const void *A, sid_dtype dtype, int64_t N, int64_t n,
                       int64_t lda, const sid_params *p, double *W, void *Y);
+
+/*
+ * Streaming (snapshots that arrive a few at a time, the in-situ setting of
+ * Sec. 1 and Sec. 4).  Both sketches are linear in the columns: W(:, j) =
+ * Psi A(:, j) depends on column j alone and Y = A Omega is a sum over column
+ * blocks, so the sketches of the blocks seen so far are the sketches of the
+ * matrix so far, and finishing gives the result sid_compress gives for the
+ * concatenated columns (up to the order of FP32 sums in Y).  J indexes
+ * columns in arrival order.
+ *
+ * sid_stream_begin: N rows, at most n_max columns; params as for
+ *   sid_compress (k <= columns pushed is checked at finish).  The stream owns
+ *   device memory for W ((l+e+q) x n_max FP64), in single pass Y (N x l) and,
+ *   once a block smaller than 512 columns arrives, a stage of
+ *   N x min(n_max, 512) values of `dtype`.  A coarse row set in params must
+ *   outlive the stream.
+ * sid_stream_push: ncols >= 0 columns of N values (column-major, leading
+ *   dimension ld >= N, device memory, `dtype`).  Blocks are copied into the
+ *   stage and sketched 512 columns at a time; a push of 512 or more columns
+ *   with ld % 4 == 0 and a 16-byte aligned pointer is sketched in place.
+ *   The caller may reuse A_blk once the context's stream has passed this
+ *   call.  SID_EINVAL past n_max columns.
+ * sid_stream_finish: sketches what is staged, then forms J, P, AJ, err,
+ *   k_eff exactly as sid_compress (same meanings, layouts and NULL rules)
+ *   with n = the columns pushed.  Two-pass streams keep no columns: AJ must
+ *   be NULL (gather A(:, J) from the caller's own copy).  Frees the stream
+ *   on success and on error.
+ * sid_stream_info: rows N, columns pushed so far, k, data type and mode of
+ *   a stream (any output pointer may be NULL; host memory).
+ * sid_stream_abort: frees a stream without finishing it.
+ * sid_stream_save: checkpoint (sketches what is staged first).  With
+ *   host_buf NULL, sets *bytes to the size needed; otherwise writes the state
+ *   (a header, W and Y) into host_buf of *bytes bytes (SID_EINVAL and the
+ *   needed size in *bytes if too small).  Synchronizes the stream.  Streams
+ *   over a coarse row set cannot be saved (SID_EINVAL).
+ * sid_stream_restore: a new stream on ctx from a saved state (SID_EINVAL for
+ *   a buffer that is not one); pushing the remaining columns and finishing
+ *   gives the result of the uninterrupted stream.
+ */
+sid_status sid_stream_begin(sid_ctx *ctx, sid_dtype dtype, int64_t N, int64_t n_max,
+                            const sid_params *p, sid_stream **out);
+sid_status sid_stream_push(sid_stream *s, const void *A_blk, int64_t ncols, int64_t ld);
+sid_status sid_stream_finish(sid_stream *s, int64_t *J, void *P, int64_t ldp, void *AJ,
+                             int64_t ldaj, double *err, int64_t *k_eff);
+sid_status sid_stream_info(const sid_stream *s, int64_t *N, int64_t *cols, int64_t *k,
+                           int *dtype, int *mode);
+sid_status sid_stream_abort(sid_stream *s);
+sid_status sid_stream_save(sid_stream *s, void *host_buf, size_t *bytes);
+sid_status sid_stream_restore(sid_ctx *ctx, const void *host_buf, size_t bytes,
+                              sid_stream **out);
 
 #ifdef __cplusplus
 }

@@ -14,6 +14,6 @@ Sec. 2.3), here in column orientation: A (N x n, one snapshot per column)
 from __future__ import annotations
 
 from ._native import (  # noqa: F401
-    SID_F32, SID_F64, PRECISIONS, MODES, Context, Compressed, RowSet, SidError,
+    SID_F32, SID_F64, PRECISIONS, MODES, Context, Compressed, RowSet, SidError, Stream,
     compress, reconstruct, error_norms, fill_gaussian, sketch, library_path, load,
 )

@@ -21,6 +21,8 @@ EXPORTS = [
     "sid_params_init", "sid_create", "sid_destroy", "sid_last_error", "sid_workspace_bytes",
     "sid_set_workspace_limit", "sid_rowset_create", "sid_rowset_destroy", "sid_reserve",
     "sid_compress", "sid_reconstruct", "sid_error_norms", "sid_fill_gaussian", "sid_sketch",
+    "sid_stream_begin", "sid_stream_push", "sid_stream_finish", "sid_stream_info", "sid_stream_abort",
+    "sid_stream_save", "sid_stream_restore",
 ]
 
 
@@ -78,9 +80,20 @@ def load():
     L.sid_error_norms.argtypes = [vp, vp, i64, vp, i64, vp, i64, ctypes.c_int, i64, i64, i64, vp]
     L.sid_fill_gaussian.argtypes = [vp, u64, ctypes.c_int, i64, i64, i64, i64, vp]
     L.sid_sketch.argtypes = [vp, vp, ctypes.c_int, i64, i64, i64, pp, vp, vp]
+    L.sid_stream_begin.argtypes = [vp, ctypes.c_int, i64, i64, pp, ctypes.POINTER(vp)]
+    L.sid_stream_push.argtypes = [vp, vp, i64, i64]
+    L.sid_stream_finish.argtypes = [vp, vp, vp, i64, vp, i64, vp, vp]
+    L.sid_stream_abort.argtypes = [vp]
+    L.sid_stream_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    L.sid_stream_save.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.sid_stream_restore.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
     for name in ("sid_create", "sid_destroy", "sid_set_workspace_limit", "sid_rowset_create",
                  "sid_rowset_destroy", "sid_reserve", "sid_compress", "sid_reconstruct",
-                 "sid_error_norms", "sid_fill_gaussian", "sid_sketch"):
+                 "sid_error_norms", "sid_fill_gaussian", "sid_sketch", "sid_stream_begin",
+                 "sid_stream_push", "sid_stream_finish", "sid_stream_info", "sid_stream_abort",
+                 "sid_stream_save",
+                 "sid_stream_restore"):
         getattr(L, name).restype = ctypes.c_int
     _LIB = L
     return L
@@ -308,3 +321,90 @@ def fill_gaussian(seed: int, stream: int, major0: int, nmajor: int, minor0: int,
     ctx.check(ctx._lib.sid_fill_gaussian(ctx.handle, int(seed), int(stream), major0, nmajor,
                                          minor0, nminor, _ptr(out)))
     return out
+
+
+class Stream:
+    """Streaming compression: push column blocks, then finish (sid_stream_*).
+    J indexes columns in arrival order."""
+
+    def __init__(self, N: int, n_max: int, k: int, oversample: int = 10, seed: int = 0,
+                 dtype: torch.dtype = torch.float32, mode: str = "single_pass",
+                 prec: str = "f32", probe_rows: int = 10, rank_tol: float = 0.0,
+                 sp_rcond: float = 0.0, corange_rows: int = -1, coarse: RowSet | None = None,
+                 ctx: Context | None = None):
+        self.ctx = ctx or default_context()
+        self.N, self.k, self.dtype = N, k, dtype
+        self.mode = mode
+        self.coarse = coarse  # kept alive with the stream
+        p = _params(k, oversample, seed, coarse, mode, prec, probe_rows, rank_tol, sp_rcond,
+                    corange_rows)
+        h = ctypes.c_void_p()
+        code = SID_F64 if dtype == torch.float64 else SID_F32
+        self.ctx.check(self.ctx._lib.sid_stream_begin(self.ctx.handle, code, N, n_max,
+                                                      ctypes.byref(p), ctypes.byref(h)))
+        self._h = h
+
+    def push(self, block: torch.Tensor):
+        """block: N x c (any strides; copied to column-major if needed)."""
+        B, ld = _colmajor(block.to(self.dtype))
+        if B.shape[0] != self.N:
+            raise ValueError("block must have N rows")
+        self.ctx.check(self.ctx._lib.sid_stream_push(self._h, _ptr(B), B.shape[1], ld))
+        # the library reads B on the context's stream; keep it alive until then
+        self._last = B
+
+    def save(self) -> bytes:
+        nb = ctypes.c_size_t(0)
+        self.ctx.check(self.ctx._lib.sid_stream_save(self._h, None, ctypes.byref(nb)))
+        buf = ctypes.create_string_buffer(nb.value)
+        self.ctx.check(self.ctx._lib.sid_stream_save(self._h, buf, ctypes.byref(nb)))
+        return buf.raw[:nb.value]
+
+    def info(self) -> dict:
+        N, cols, k = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        dt, md = ctypes.c_int(), ctypes.c_int()
+        self.ctx.check(self.ctx._lib.sid_stream_info(self._h, ctypes.byref(N), ctypes.byref(cols),
+                                                     ctypes.byref(k), ctypes.byref(dt),
+                                                     ctypes.byref(md)))
+        return dict(N=N.value, cols=cols.value, k=k.value,
+                    dtype=torch.float64 if dt.value == SID_F64 else torch.float32,
+                    mode={v: kk for kk, v in MODES.items()}[md.value])
+
+    @classmethod
+    def restore(cls, state: bytes, ctx: Context | None = None) -> "Stream":
+        ctx = ctx or default_context()
+        h = ctypes.c_void_p()
+        buf = ctypes.create_string_buffer(state, len(state))
+        ctx.check(ctx._lib.sid_stream_restore(ctx.handle, buf, len(state), ctypes.byref(h)))
+        obj = cls.__new__(cls)
+        obj.ctx, obj._h, obj.coarse = ctx, h, None
+        inf = obj.info()
+        obj.N, obj.k, obj.dtype, obj.mode = inf["N"], inf["k"], inf["dtype"], inf["mode"]
+        return obj
+
+    def finish(self, want_skeleton: bool = True) -> Compressed:
+        dev = torch.device("cuda", self.ctx.device)
+        k, N = self.k, self.N
+        n = self.info()["cols"]
+        J = torch.empty(k, dtype=torch.int64, device=dev)
+        P = torch.empty((n, k), dtype=self.dtype, device=dev).T
+        AJ = (torch.empty((k, N), dtype=self.dtype, device=dev).T
+              if want_skeleton and self.mode == "single_pass" else None)
+        err = torch.empty(2, dtype=torch.float64, device=dev)
+        keff = torch.empty(1, dtype=torch.int64, device=dev)
+        h, self._h = self._h, None
+        self.ctx.check(self.ctx._lib.sid_stream_finish(
+            h, _ptr(J), _ptr(P), P.stride(1), _ptr(AJ), AJ.stride(1) if AJ is not None else 1,
+            _ptr(err), _ptr(keff)))
+        return Compressed(J, P, AJ, err, keff)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.ctx._lib.sid_stream_abort(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -18,7 +19,7 @@ namespace {
 enum Slot {
   WS_OMEGA, WS_PART, WS_W, WS_WR, WS_NRM, WS_PIV, WS_R, WS_Q, WS_KEFF, WS_STATS, WS_PD,
   WS_ERR, WS_Y, WS_M, WS_MPR, WS_WJ, WS_PIVM, WS_RM, WS_QM, WS_RKM, WS_C, WS_T, WS_MIX,
-  WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COOP, WS_SYNC, WS_R11, WS_FITPART, WS_COUNT
+  WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COOP, WS_SYNC, WS_R11, WS_FITPART, WS_YTMP, WS_COUNT
 };
 
 struct Buf {
@@ -44,6 +45,25 @@ struct sid_rowset {
   int64_t* d_rows = nullptr;
   int64_t count = 0;
   int64_t N = 0;
+};
+
+// Streaming state: the sketches of the columns seen so far, owned by the
+// stream (not by the context's workspace, which other calls reuse).
+struct sid_stream {
+  sid_ctx* ctx = nullptr;
+  sid_params p{};
+  sid_dtype dtype = SID_F32;
+  int64_t N = 0, n_max = 0;
+  int64_t lq = 0, l = 0;
+  bool single = false;
+  int64_t cols = 0;         // columns already sketched
+  int64_t staged = 0;       // columns copied into the stage, not yet sketched
+  int64_t stage_cols = 0;   // stage capacity (columns)
+  int64_t ld_stage = 0;     // stage leading dimension (multiple of 4)
+  void* stage = nullptr;    // N x stage_cols (data type), allocated on first use
+  double* W = nullptr;      // lq x n_max, column-major
+  void* Y = nullptr;        // N x l row-major (single pass), FP64 for F64 sketches else FP32
+  bool y_init = false;
 };
 
 namespace {
@@ -107,6 +127,17 @@ double default_rcond(int prec) {
   }
 }
 
+// row chunks of the generic sketch kernels (partials per chunk)
+int64_t nchunks_for(int64_t Ns, int64_t n) {
+  const int64_t ntiles = (n + 63) / 64;
+  int64_t nch = (Ns + 1023) / 1024;
+  int64_t cap = 2048 / ntiles;
+  if (cap < 1) cap = 1;
+  if (nch > cap) nch = cap;
+  if (nch < 1) nch = 1;
+  return nch;
+}
+
 sid_status validate(sid_ctx* ctx, int64_t N, int64_t n, const sid_params* p, Shape* sh) {
   if (!p) return fail(ctx, SID_EINVAL, "params is NULL");
   if (N <= 0 || n <= 0) return fail(ctx, SID_EINVAL, "N and n must be positive");
@@ -141,13 +172,7 @@ sid_status validate(sid_ctx* ctx, int64_t N, int64_t n, const sid_params* p, Sha
   sh->lz = lz;
   sh->lq = lq;
   sh->Ns = Ns;
-  const int64_t ntiles = (n + 63) / 64;
-  int64_t nch = (Ns + 1023) / 1024;
-  int64_t cap = 2048 / ntiles;
-  if (cap < 1) cap = 1;
-  if (nch > cap) nch = cap;
-  if (nch < 1) nch = 1;
-  sh->nchunks = nch;
+  sh->nchunks = nchunks_for(Ns, n);
   sh->single = p->mode == SID_SINGLE_PASS;
   sh->prec = p->prec;
   return SID_OK;
@@ -375,40 +400,63 @@ sid_status sid_reserve(sid_ctx* ctx, int64_t N, int64_t n, const sid_params* p) 
   return reserve(ctx, sh, &w);
 }
 
+static sid_status factor(sid_ctx* ctx, const sid_params* p, const Shape& sh, const Work& w,
+                         sid_dtype dtype, const void* A, int64_t lda, int64_t* J, void* P,
+                         int64_t ldp, void* AJ, int64_t ldaj, double* err, int64_t* k_eff);
+
+// The sketch pass over the columns col0 .. col0 + sh.n - 1 of the matrix
+// (A points at column col0): W (lq x sh.n) and, if Y is given, Y = A Omega
+// with Omega's rows col0 .. col0 + sh.n - 1.
 static sid_status run_sketch(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t lda,
                              const sid_params* p, const Shape& sh, const Work& w, double* W,
-                             void* Y) {
+                             void* Y, int64_t col0 = 0) {
   hipStream_t st = ctx->stream;
   if (Y) {
-    SID_CHECK(sid::launch_fill_gaussian(st, p->seed, 0u, 0, sh.n, 0, sh.l, w.omega),
+    SID_CHECK(sid::launch_fill_gaussian(st, p->seed, 0u, col0, sh.n, 0, sh.l, w.omega),
               "omega generation");
   }
   const int64_t* rows = p->coarse ? p->coarse->d_rows : nullptr;
   const bool bf = sh.prec == SID_SK_BF16 || sh.prec == SID_SK_BF16X2 ||
                   sh.prec == SID_SK_FP8E4M3;
+  // the streaming pass takes up to 512 columns per launch; wider matrices
+  // go through it in column slabs (W's columns are independent, Y sums the
+  // slabs' contributions)
+  const int64_t slab = sh.n < 512 ? sh.n : 512;
   const bool fused_ok =
       dtype == SID_F32 &&
-      sid::fused_bf16_supported(sh.n, (int)sh.lq, (int)sh.l, lda, A, rows != nullptr);
+      sid::fused_bf16_supported(slab, (int)sh.lq, (int)sh.l, lda, A, rows != nullptr);
   if (sh.prec == SID_SK_FP8E4M3 && !fused_ok)
     return fail(ctx, SID_EINVAL,
                 "the FP8 sketch needs FP32 data with 16-byte aligned columns (lda % 4 == 0), all "
-                "rows (no coarse set), n <= 512, l <= 128 and l + co-range + probe <= 160");
+                "rows (no coarse set), l <= 128 and l + co-range + probe <= 160");
   if (bf && fused_ok) {
     // one streaming pass on the matrix cores (W partials per workgroup, FP32)
     int64_t rpw = 0;
     const int64_t grid = sid::fused_bf16_grid(sh.N, ctx->num_cu, &rpw);
-    float* partf = (float*)ws(ctx, WS_PARTF, sizeof(float) * (size_t)(grid * sh.lq * sh.n));
+    float* partf = (float*)ws(ctx, WS_PARTF, sizeof(float) * (size_t)(grid * sh.lq * slab));
     __bf16* omT = (__bf16*)ws(ctx, WS_OMT, sizeof(uint16_t) * 128 * 512);
     if (!partf || !omT) return SID_ENOMEM;
-    int64_t nparts = 0;
+    float* ytmp = nullptr;
+    if (Y && sh.n > slab) {
+      ytmp = (float*)ws(ctx, WS_YTMP, sizeof(float) * (size_t)(sh.N * sh.l));
+      if (!ytmp) return SID_ENOMEM;
+    }
     const int dmode = sh.prec == SID_SK_BF16X2   ? sid::FB_BF16X2
                       : sh.prec == SID_SK_FP8E4M3 ? sid::FB_FP8
                                                   : sid::FB_BF16;
-    SID_CHECK(sid::launch_sketch_fused_bf16(st, dmode, (const float*)A, lda,
-                                            sh.N, (int)sh.n, (int)sh.lq, (int)sh.l, p->seed,
-                                            w.omega, omT, ctx->num_cu, partf, W, (float*)Y,
-                                            &nparts),
-              "fused sketch pass");
+    for (int64_t c0 = 0; c0 < sh.n; c0 += slab) {
+      const int64_t nb = sh.n - c0 < slab ? sh.n - c0 : slab;
+      float* yd = Y ? (c0 == 0 ? (float*)Y : ytmp) : nullptr;
+      int64_t nparts = 0;
+      SID_CHECK(sid::launch_sketch_fused_bf16(st, dmode, (const float*)A + c0 * lda, lda, sh.N,
+                                              (int)nb, (int)sh.lq, (int)sh.l, p->seed,
+                                              w.omega + c0 * sh.l, omT, ctx->num_cu, partf,
+                                              W + c0 * sh.lq, yd, &nparts),
+                "fused sketch pass");
+      if (Y && c0 > 0)
+        SID_CHECK(sid::launch_add_inplace(st, false, Y, ytmp, sh.N * sh.l, ctx->num_cu),
+                  "Y slab sum");
+    }
     return SID_OK;
   }
   SID_CHECK(sid::launch_sketch(st, sh.prec, dtype == SID_F64, A, lda, sh.N, sh.n, rows, sh.Ns,
@@ -452,14 +500,22 @@ sid_status sid_compress(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N,
   SID_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
   Work w;
   if (reserve(ctx, sh, &w) != SID_OK) return SID_ENOMEM;
+  // (1) sketch pass: W = Psi(:, S) A(S, :) and, single pass, Y = A Omega
+  s = run_sketch(ctx, A, dtype, lda, p, sh, w, w.W, sh.single ? w.Y : nullptr);
+  if (s != SID_OK) return s;
+  return factor(ctx, p, sh, w, dtype, A, lda, J, P, ldp, AJ, ldaj, err, k_eff);
+}
+
+// Everything after the sketch pass, from W (w.W, lq x n), single pass also
+// Y (w.Y) and Omega's values (w.omega, n x l): mgsqr, coefficients,
+// estimates and the skeleton.  A is read only by the two-pass gather.
+static sid_status factor(sid_ctx* ctx, const sid_params* p, const Shape& sh, const Work& w,
+                         sid_dtype dtype, const void* A, int64_t lda, int64_t* J, void* P,
+                         int64_t ldp, void* AJ, int64_t ldaj, double* err, int64_t* k_eff) {
   hipStream_t st = ctx->stream;
   const bool f64 = dtype == SID_F64;
   const int k = (int)sh.k, l = (int)sh.l, q = (int)sh.q, lz = (int)sh.lz, lq = (int)sh.lq,
             n_ = (int)sh.n;
-
-  // (1) sketch pass: W = Psi(:, S) A(S, :) and, single pass, Y = A Omega
-  s = run_sketch(ctx, A, dtype, lda, p, sh, w, w.W, sh.single ? w.Y : nullptr);
-  if (s != SID_OK) return s;
   // (2) mgsqr on the selection rows of W
   if (sid::cpqr_wg_supported(l, n_))
     SID_CHECK(sid::launch_cpqr_wg(st, w.W, lq, l, n_, k, p->rank_tol, w.piv, w.R, w.Q, w.keff,
@@ -600,6 +656,345 @@ sid_status sid_fill_gaussian(sid_ctx* ctx, uint64_t seed, int stream, int64_t ma
   SID_CHECK(sid::launch_fill_gaussian(ctx->stream, seed, (uint32_t)stream, major0, nmajor, minor0,
                                       nminor, out),
             "fill gaussian");
+  return SID_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Streaming: columns arrive in blocks; W's columns are independent of each
+// other and Y = A Omega is a sum over column blocks, so the sketches of the
+// blocks seen so far are exactly the sketches of the matrix so far.  Small
+// blocks are gathered into a stage of up to 512 columns before a sketch
+// pass (one pass per 512 columns instead of one per block: Y is read and
+// written once per pass).
+// ---------------------------------------------------------------------------
+namespace {
+
+size_t elem_size(sid_dtype d) { return d == SID_F64 ? sizeof(double) : sizeof(float); }
+
+size_t y_elem_size(const sid_stream* s) {
+  return s->p.prec == SID_SK_F64 ? sizeof(double) : sizeof(float);
+}
+
+void stream_free(sid_stream* s) {
+  if (!s) return;
+  if (s->ctx && s->ctx->device >= 0) {
+    (void)hipSetDevice(s->ctx->device);
+    (void)hipStreamSynchronize(s->ctx->stream);
+    if (s->stage) (void)hipFree(s->stage);
+    if (s->W) (void)hipFree(s->W);
+    if (s->Y) (void)hipFree(s->Y);
+  }
+  delete s;
+}
+
+sid_status stream_alloc(sid_ctx* ctx, sid_stream* s) {
+  const size_t wb = sizeof(double) * (size_t)(s->lq * s->n_max);
+  if (hipMalloc((void**)&s->W, wb) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, SID_ENOMEM, "stream: device allocation of W failed");
+  }
+  if (s->single) {
+    if (hipMalloc(&s->Y, y_elem_size(s) * (size_t)(s->N * s->l)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(ctx, SID_ENOMEM, "stream: device allocation of Y failed");
+    }
+  }
+  return SID_OK;
+}
+
+// sketch columns cols .. cols + ncols - 1 from src (leading dimension ld)
+sid_status stream_flush(sid_stream* s, const void* src, int64_t ld, int64_t ncols) {
+  sid_ctx* ctx = s->ctx;
+  if (ncols <= 0) return SID_OK;
+  Shape sh;
+  sid_status st = validate(ctx, s->N, s->n_max, &s->p, &sh);
+  if (st != SID_OK) return st;
+  sh.n = ncols;
+  sh.nchunks = nchunks_for(sh.Ns, ncols);
+  Work w;
+  if (reserve(ctx, sh, &w) != SID_OK) return SID_ENOMEM;
+  void* ydst = nullptr;
+  if (s->single) ydst = s->y_init ? w.Y : s->Y;
+  st = run_sketch(ctx, src, s->dtype, ld, &s->p, sh, w, s->W + s->lq * s->cols, ydst, s->cols);
+  if (st != SID_OK) return st;
+  if (s->single && s->y_init)
+    SID_CHECK(sid::launch_add_inplace(ctx->stream, s->p.prec == SID_SK_F64, s->Y, w.Y,
+                                      s->N * s->l, ctx->num_cu),
+              "stream: Y accumulation");
+  s->y_init = s->single;
+  s->cols += ncols;
+  return SID_OK;
+}
+
+sid_status stream_flush_stage(sid_stream* s) {
+  if (s->staged == 0) return SID_OK;
+  const int64_t n = s->staged;
+  s->staged = 0;
+  return stream_flush(s, s->stage, s->ld_stage, n);
+}
+
+struct StreamHeader {
+  char magic[8];
+  int64_t version, N, n_max, cols, dtype, y_init;
+  int64_t k, oversample, mode, prec, probe_rows, corange_rows;
+  uint64_t seed;
+  double rank_tol, sp_rcond;
+};
+
+const char kStreamMagic[8] = {'S', 'I', 'D', 'S', 'T', 'R', 'M', '1'};
+
+sid_status stream_make(sid_ctx* ctx, sid_dtype dtype, int64_t N, int64_t n_max,
+                       const sid_params* p, sid_stream** out) {
+  Shape sh;
+  sid_status st = validate(ctx, N, n_max, p, &sh);
+  if (st != SID_OK) return st;
+  sid_stream* s = new (std::nothrow) sid_stream();
+  if (!s) return fail(ctx, SID_ENOMEM, "host allocation failed");
+  s->ctx = ctx;
+  s->p = *p;
+  s->dtype = dtype;
+  s->N = N;
+  s->n_max = n_max;
+  s->lq = sh.lq;
+  s->l = sh.l;
+  s->single = sh.single;
+  s->stage_cols = n_max < 512 ? n_max : 512;
+  s->ld_stage = (N + 3) / 4 * 4;
+  st = stream_alloc(ctx, s);
+  if (st != SID_OK) {
+    stream_free(s);
+    return st;
+  }
+  *out = s;
+  return SID_OK;
+}
+
+}  // namespace
+
+sid_status sid_stream_begin(sid_ctx* ctx, sid_dtype dtype, int64_t N, int64_t n_max,
+                            const sid_params* p, sid_stream** out) {
+  if (!ctx) return SID_EINVAL;
+  if (!out) return fail(ctx, SID_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (dtype != SID_F32 && dtype != SID_F64) return fail(ctx, SID_EINVAL, "unknown dtype");
+  Shape sh;
+  const sid_status vs = validate(ctx, N, n_max, p, &sh);
+  if (vs != SID_OK) return vs;
+  SID_NEED_DEVICE(ctx);
+  SID_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+  return stream_make(ctx, dtype, N, n_max, p, out);
+}
+
+sid_status sid_stream_push(sid_stream* s, const void* A_blk, int64_t ncols, int64_t ld) {
+  if (!s) return SID_EINVAL;
+  sid_ctx* ctx = s->ctx;
+  if (ncols < 0) return fail(ctx, SID_EINVAL, "ncols < 0");
+  if (ncols == 0) return SID_OK;
+  if (!A_blk) return fail(ctx, SID_EINVAL, "A_blk is NULL");
+  if (ld < s->N) return fail(ctx, SID_EINVAL, "ld < N");
+  if (s->cols + s->staged + ncols > s->n_max)
+    return fail(ctx, SID_EINVAL, "more columns pushed than n_max");
+  SID_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+  const size_t esz = elem_size(s->dtype);
+  const char* src = (const char*)A_blk;
+  const bool aligned = (ld % 4) == 0 && ((uintptr_t)A_blk % 16) == 0;
+  int64_t done = 0;
+  while (done < ncols) {
+    const int64_t left = ncols - done;
+    if (s->staged == 0 && left >= s->stage_cols && aligned) {
+      // a whole pass straight from the caller's memory
+      sid_status st = stream_flush(s, src + (size_t)done * (size_t)ld * esz, ld, s->stage_cols);
+      if (st != SID_OK) return st;
+      done += s->stage_cols;
+      continue;
+    }
+    if (!s->stage) {
+      if (hipMalloc(&s->stage, esz * (size_t)(s->ld_stage * s->stage_cols)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, SID_ENOMEM, "stream: device allocation of the stage failed");
+      }
+    }
+    const int64_t take = left < s->stage_cols - s->staged ? left : s->stage_cols - s->staged;
+    SID_CHECK(hipMemcpy2DAsync((char*)s->stage + (size_t)s->staged * (size_t)s->ld_stage * esz,
+                               (size_t)s->ld_stage * esz, src + (size_t)done * (size_t)ld * esz,
+                               (size_t)ld * esz, (size_t)s->N * esz, (size_t)take,
+                               hipMemcpyDeviceToDevice, ctx->stream),
+              "stream: stage copy");
+    s->staged += take;
+    done += take;
+    if (s->staged == s->stage_cols) {
+      sid_status st = stream_flush_stage(s);
+      if (st != SID_OK) return st;
+    }
+  }
+  return SID_OK;
+}
+
+sid_status sid_stream_finish(sid_stream* s, int64_t* J, void* P, int64_t ldp, void* AJ,
+                             int64_t ldaj, double* err, int64_t* k_eff) {
+  if (!s) return SID_EINVAL;
+  sid_ctx* ctx = s->ctx;
+  sid_status st = SID_OK;
+  do {
+    if (hipSetDevice(ctx->device) != hipSuccess) {
+      st = fail(ctx, SID_EDEVICE, "hipSetDevice");
+      break;
+    }
+    if (!s->single && AJ) {
+      st = fail(ctx, SID_EINVAL,
+                "two-pass stream: AJ must be NULL (the stream keeps no columns; copy A(:, J) "
+                "from the caller's data)");
+      break;
+    }
+    st = stream_flush_stage(s);
+    if (st != SID_OK) break;
+    Shape sh;
+    st = validate(ctx, s->N, s->cols, &s->p, &sh);
+    if (st != SID_OK) break;
+    if (P && ldp < s->p.k) {
+      st = fail(ctx, SID_EINVAL, "ldp < k");
+      break;
+    }
+    if (AJ && ldaj < s->N) {
+      st = fail(ctx, SID_EINVAL, "ldaj < N");
+      break;
+    }
+    Work w;
+    if (reserve(ctx, sh, &w) != SID_OK) {
+      st = SID_ENOMEM;
+      break;
+    }
+    w.W = s->W;
+    if (s->single) {
+      w.Y = s->Y;
+      hipError_t e = sid::launch_fill_gaussian(ctx->stream, s->p.seed, 0u, 0, sh.n, 0, sh.l,
+                                               w.omega);
+      if (e != hipSuccess) {
+        st = hip_fail(ctx, e, "omega generation");
+        break;
+      }
+    }
+    st = factor(ctx, &s->p, sh, w, s->dtype, nullptr, 0, J, P, ldp, AJ, ldaj, err, k_eff);
+  } while (false);
+  stream_free(s);
+  return st;
+}
+
+sid_status sid_stream_info(const sid_stream* s, int64_t* N, int64_t* cols, int64_t* k,
+                           int* dtype, int* mode) {
+  if (!s) return SID_EINVAL;
+  if (N) *N = s->N;
+  if (cols) *cols = s->cols + s->staged;
+  if (k) *k = s->p.k;
+  if (dtype) *dtype = (int)s->dtype;
+  if (mode) *mode = (int)s->p.mode;
+  return SID_OK;
+}
+
+sid_status sid_stream_abort(sid_stream* s) {
+  if (!s) return SID_EINVAL;
+  stream_free(s);
+  return SID_OK;
+}
+
+sid_status sid_stream_save(sid_stream* s, void* host_buf, size_t* bytes) {
+  if (!s) return SID_EINVAL;
+  sid_ctx* ctx = s->ctx;
+  if (!bytes) return fail(ctx, SID_EINVAL, "bytes is NULL");
+  if (s->p.coarse)
+    return fail(ctx, SID_EINVAL, "a stream over a coarse row set cannot be saved");
+  SID_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+  sid_status st = stream_flush_stage(s);
+  if (st != SID_OK) return st;
+  const size_t wb = sizeof(double) * (size_t)(s->lq * s->cols);
+  const size_t yb = s->y_init ? y_elem_size(s) * (size_t)(s->N * s->l) : 0;
+  const size_t need = sizeof(StreamHeader) + wb + yb;
+  if (!host_buf) {
+    *bytes = need;
+    return SID_OK;
+  }
+  if (*bytes < need) {
+    *bytes = need;
+    return fail(ctx, SID_EINVAL, "buffer too small for the stream state");
+  }
+  StreamHeader h;
+  std::memset(&h, 0, sizeof(h));
+  std::memcpy(h.magic, kStreamMagic, 8);
+  h.version = 1;
+  h.N = s->N;
+  h.n_max = s->n_max;
+  h.cols = s->cols;
+  h.dtype = s->dtype;
+  h.y_init = s->y_init ? 1 : 0;
+  h.k = s->p.k;
+  h.oversample = s->p.oversample;
+  h.mode = s->p.mode;
+  h.prec = s->p.prec;
+  h.probe_rows = s->p.probe_rows;
+  h.corange_rows = s->p.corange_rows;
+  h.seed = s->p.seed;
+  h.rank_tol = s->p.rank_tol;
+  h.sp_rcond = s->p.sp_rcond;
+  char* out = (char*)host_buf;
+  std::memcpy(out, &h, sizeof(h));
+  if (wb) SID_CHECK(hipMemcpyAsync(out + sizeof(h), s->W, wb, hipMemcpyDeviceToHost, ctx->stream),
+                    "stream save: W");
+  if (yb)
+    SID_CHECK(hipMemcpyAsync(out + sizeof(h) + wb, s->Y, yb, hipMemcpyDeviceToHost, ctx->stream),
+              "stream save: Y");
+  SID_CHECK(hipStreamSynchronize(ctx->stream), "stream save: synchronize");
+  *bytes = need;
+  return SID_OK;
+}
+
+sid_status sid_stream_restore(sid_ctx* ctx, const void* host_buf, size_t bytes, sid_stream** out) {
+  if (!ctx) return SID_EINVAL;
+  if (!out || !host_buf) return fail(ctx, SID_EINVAL, "null argument");
+  *out = nullptr;
+  if (bytes < sizeof(StreamHeader)) return fail(ctx, SID_EINVAL, "stream state too short");
+  StreamHeader h;
+  std::memcpy(&h, host_buf, sizeof(h));
+  if (std::memcmp(h.magic, kStreamMagic, 8) != 0 || h.version != 1)
+    return fail(ctx, SID_EINVAL, "not a saved stream state");
+  if (h.dtype != SID_F32 && h.dtype != SID_F64) return fail(ctx, SID_EINVAL, "bad dtype in state");
+  SID_NEED_DEVICE(ctx);
+  SID_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+  sid_params p;
+  sid_params_init(&p, h.k);
+  p.oversample = h.oversample;
+  p.mode = (sid_mode)h.mode;
+  p.prec = (sid_sketch_prec)h.prec;
+  p.probe_rows = (int32_t)h.probe_rows;
+  p.corange_rows = (int32_t)h.corange_rows;
+  p.seed = h.seed;
+  p.rank_tol = h.rank_tol;
+  p.sp_rcond = h.sp_rcond;
+  sid_stream* s = nullptr;
+  sid_status st = stream_make(ctx, (sid_dtype)h.dtype, h.N, h.n_max, &p, &s);
+  if (st != SID_OK) return st;
+  if (h.cols < 0 || h.cols > h.n_max || (h.y_init != 0) != (s->single && h.cols > 0)) {
+    stream_free(s);
+    return fail(ctx, SID_EINVAL, "inconsistent stream state");
+  }
+  const size_t wb = sizeof(double) * (size_t)(s->lq * h.cols);
+  const size_t yb = h.y_init ? y_elem_size(s) * (size_t)(s->N * s->l) : 0;
+  if (bytes < sizeof(h) + wb + yb) {
+    stream_free(s);
+    return fail(ctx, SID_EINVAL, "stream state truncated");
+  }
+  const char* in = (const char*)host_buf;
+  hipError_t e = hipSuccess;
+  if (wb) e = hipMemcpyAsync(s->W, in + sizeof(h), wb, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess && yb)
+    e = hipMemcpyAsync(s->Y, in + sizeof(h) + wb, yb, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    stream_free(s);
+    return hip_fail(ctx, e, "stream restore: upload");
+  }
+  s->cols = h.cols;
+  s->y_init = h.y_init != 0;
+  *out = s;
   return SID_OK;
 }
 

@@ -759,6 +759,29 @@ hipError_t launch_gemm64(hipStream_t st, int M, int Nn, int K, const double* A, 
   return hipGetLastError();
 }
 
+// y += x elementwise (count entries); vector loads where both are aligned
+template <typename T>
+__global__ void k_add_inplace(T* __restrict__ y, const T* __restrict__ x, int64_t count) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x)
+    y[e] += x[e];
+}
+
+hipError_t launch_add_inplace(hipStream_t st, bool f64, void* y, const void* x, int64_t count,
+                              int num_cu) {
+  if (count <= 0) return hipSuccess;
+  int64_t b = (count + 255) / 256;
+  const int64_t cap = (int64_t)num_cu * 16;
+  if (b > cap) b = cap;
+  if (f64)
+    hipLaunchKernelGGL(k_add_inplace<double>, dim3((unsigned)b), dim3(256), 0, st, (double*)y,
+                       (const double*)x, count);
+  else
+    hipLaunchKernelGGL(k_add_inplace<float>, dim3((unsigned)b), dim3(256), 0, st, (float*)y,
+                       (const float*)x, count);
+  return hipGetLastError();
+}
+
 hipError_t launch_gather_cols(hipStream_t st, const void* src, bool src_f64, int64_t lds,
                               int64_t rows, const int64_t* piv, const int64_t* keff, int kcap,
                               void* dst, bool dst_f64, int64_t ldd) {

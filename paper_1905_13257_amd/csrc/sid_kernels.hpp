@@ -26,6 +26,8 @@ hipError_t launch_omega_values(hipStream_t st, int prec, const float* z, int64_t
 hipError_t launch_ratio_sqrt(hipStream_t st, const double* stats, double* out);
 hipError_t launch_gemm64(hipStream_t st, int M, int Nn, int K, const double* A, int64_t lda,
                          int tA, const double* B, int64_t ldb, int tB, double* C, int64_t ldc);
+hipError_t launch_add_inplace(hipStream_t st, bool f64, void* y, const void* x, int64_t count,
+                              int num_cu);
 hipError_t launch_gather_cols(hipStream_t st, const void* src, bool src_f64, int64_t lds,
                               int64_t rows, const int64_t* piv, const int64_t* keff, int kcap,
                               void* dst, bool dst_f64, int64_t ldd);

@@ -120,3 +120,25 @@ def test_other_calls_validate(vctx):
     assert L.sid_set_workspace_limit(h, 1 << 20) == 0
     assert L.sid_workspace_bytes(h) == 0
     assert L.sid_create(None, 0, None) == EINVAL
+
+
+def test_stream_calls_validate(vctx):
+    """Streaming entry points: parameters are checked before any device
+    work; a NULL stream and a buffer that is not a saved state are rejected."""
+    L, h = vctx
+    vp = ctypes.c_void_p
+    p = _params(L, 5)
+    out = vp()
+    assert L.sid_stream_begin(h, 1, 100, 20, ctypes.byref(p), ctypes.byref(out)) == ESTATE
+    assert L.sid_stream_begin(h, 1, 100, 2, ctypes.byref(p), ctypes.byref(out)) == EINVAL   # k > n_max
+    assert L.sid_stream_begin(h, 7, 100, 20, ctypes.byref(p), ctypes.byref(out)) == EINVAL  # dtype
+    assert L.sid_stream_begin(h, 1, 100, 20, ctypes.byref(p), None) == EINVAL
+    assert L.sid_stream_push(None, vp(1), 3, 100) == EINVAL
+    assert L.sid_stream_finish(None, None, None, 1, None, 1, None, None) == EINVAL
+    assert L.sid_stream_abort(None) == EINVAL
+    assert L.sid_stream_info(None, None, None, None, None, None) == EINVAL
+    nb = ctypes.c_size_t(0)
+    assert L.sid_stream_save(None, None, ctypes.byref(nb)) == EINVAL
+    junk = ctypes.create_string_buffer(b"not a stream state" * 10)
+    assert L.sid_stream_restore(h, junk, 180, ctypes.byref(out)) == EINVAL
+    assert L.sid_stream_restore(h, junk, 4, ctypes.byref(out)) == EINVAL

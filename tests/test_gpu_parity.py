@@ -1,5 +1,6 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
 same seeded inputs.  Marked gpu."""
+import ctypes
 import math
 import sys
 
@@ -92,14 +93,16 @@ def test_sketch_parity(sid, oracle_mod, prec, shape):
 
 @pytest.mark.parametrize("prec", ["bf16", "bf16x2", "fp8"])
 @pytest.mark.parametrize("shape", [(2597, 500, 100, 20, 10), (49394, 500, 100, 20, 10),
-                                   (700, 129, 7, 3, 2), (5000, 300, 60, 10, 5)])
+                                   (700, 129, 7, 3, 2), (5000, 300, 60, 10, 5),
+                                   (3001, 1100, 30, 10, 5)])
 def test_sketch_parity_streaming_sizes(sid, oracle_mod, prec, shape):
     """Shapes that exercise the streaming matrix-core pass (FP32 data with a
     leading dimension padded to a multiple of 4): n up to 512 (four
     128-column chunks), lq up to 160 (W rows beyond 128 kept in LDS), l up to
     128, workgroups with full panels plus a ragged tail, and a workgroup that
-    owns only a tail.  The data span several decades per column so that the
-    FP8 tile scales differ from tile to tile."""
+    owns only a tail; n = 1100 runs as three column slabs.  The data span
+    several decades per column so that the FP8 tile scales differ from tile
+    to tile."""
     N, n, k, p, q = shape
     say("sketch streaming", prec, shape)
     rng = np.random.default_rng(N + 7 * n)
@@ -336,3 +339,89 @@ def test_fp8_requirements_rejected(sid):
         assert ei.value.status == -1 and "FP8" in str(ei.value)
     out = sid.compress(to_gpu(A64, torch.float32, ld=336), 5, 5, prec="fp8", mode="single_pass")
     assert int(host(out.k_eff)[0]) == 5
+
+
+def _blocks(n, widths):
+    c0, out, i = 0, [], 0
+    while c0 < n:
+        w = min(widths[i % len(widths)], n - c0)
+        out.append((c0, w))
+        c0 += w
+        i += 1
+    return out
+
+
+@pytest.mark.parametrize("prec,dt", [("f64", torch.float64), ("f32", torch.float32),
+                                     ("bf16x2", torch.float32), ("fp8", torch.float32)])
+def test_stream_equals_whole_matrix(sid, oracle_mod, prec, dt):
+    """Single-pass stream of ragged column blocks (one wider than the
+    512-column stage, sketched in place) == sid_compress of the whole matrix:
+    identical pivots, P and AJ to rounding of the Y sums, and the oracle's
+    pivots until its first near-tie."""
+    N, n, k, p, q = 4096, 700, 24, 8, 6
+    say("stream", prec)
+    A64, _ = c1_matrix(N=N, n=n, seed=1002)
+    A64 = A64.astype(np.float32).astype(np.float64)
+    A = to_gpu(A64, dt)
+    st = sid.Stream(N, n, k, p, seed=4, dtype=dt, mode="single_pass", prec=prec, probe_rows=q)
+    for c0, w in _blocks(n, [530, 7, 1, 100, 33]):
+        st.push(A[:, c0:c0 + w])
+    assert st.info()["cols"] == n
+    got = st.finish()
+    ref = sid.compress(A, k, p, seed=4, mode="single_pass", prec=prec, probe_rows=q)
+    torch.cuda.synchronize()
+    assert host(got.J).tolist() == host(ref.J).tolist()
+    rt = 1e-9 if prec == "f64" else 2e-4
+    np.testing.assert_allclose(host(got.P), host(ref.P), rtol=0, atol=rt * np.abs(host(ref.P)).max())
+    np.testing.assert_allclose(host(got.AJ), host(ref.AJ), rtol=0,
+                               atol=rt * np.abs(host(ref.AJ)).max())
+    orc = oracle_mod.compress(A64, k, p, seed=4, mode="single_pass", prec=prec, probe_rows=q)
+    tie = {"f64": 1e-10, "f32": 1e-5, "bf16x2": 1e-4, "fp8": 3e-2}[prec]
+    ist = next((i for i, m in enumerate(orc.cp.margins) if m <= tie), k)
+    assert host(got.J)[:ist].tolist() == orc.J[:ist].tolist()
+
+
+def test_stream_save_restore_and_two_pass(sid):
+    """A stream checkpointed after part of the columns and restored into a
+    new stream finishes like the uninterrupted one; a two-pass stream gives
+    the two-pass J and P and refuses to return a skeleton; columns past n_max
+    are rejected."""
+    N, n, k, p = 3000, 260, 16, 8
+    rng = np.random.default_rng(12)
+    A64 = (rng.standard_normal((N, 30)) @ rng.standard_normal((30, n))) * np.exp(-np.arange(n) / 80)
+    A = to_gpu(A64, torch.float32)
+    kw = dict(seed=2, dtype=torch.float32, mode="single_pass", prec="bf16x2", probe_rows=5)
+    s1 = sid.Stream(N, n, k, p, **kw)
+    for c0, w in _blocks(n, [50, 13]):
+        s1.push(A[:, c0:c0 + w])
+    full = s1.finish()
+    s2 = sid.Stream(N, n, k, p, **kw)
+    for c0, w in _blocks(120, [50, 13]):
+        s2.push(A[:, c0:c0 + w])
+    state = s2.save()
+    s2.close()
+    s3 = sid.Stream.restore(state)
+    assert s3.info()["cols"] == 120
+    for c0, w in _blocks(n - 120, [50, 13]):
+        s3.push(A[:, 120 + c0:120 + c0 + w])
+    with pytest.raises(sid.SidError):
+        s3.push(A[:, :1])
+    res = s3.finish()
+    torch.cuda.synchronize()
+    assert host(res.J).tolist() == host(full.J).tolist()
+    np.testing.assert_allclose(host(res.P), host(full.P), atol=1e-4 * np.abs(host(full.P)).max())
+    np.testing.assert_allclose(host(res.AJ), host(full.AJ), atol=1e-4 * np.abs(host(full.AJ)).max())
+    tp = sid.Stream(N, n, k, p, seed=2, dtype=torch.float32, mode="two_pass", prec="f32")
+    for c0, w in _blocks(n, [64]):
+        tp.push(A[:, c0:c0 + w])
+    r2 = tp.finish(want_skeleton=False)
+    ref = sid.compress(A, k, p, seed=2, mode="two_pass", prec="f32")
+    assert host(r2.J).tolist() == host(ref.J).tolist()
+    np.testing.assert_allclose(host(r2.P), host(ref.P), atol=1e-5 * np.abs(host(ref.P)).max())
+    tp2 = sid.Stream(N, n, k, p, seed=2, dtype=torch.float32, mode="two_pass", prec="f32")
+    tp2.push(A)
+    AJ = torch.empty((k, N), dtype=torch.float32, device="cuda").T
+    L = sid.load()
+    st = L.sid_stream_finish(tp2._h, None, None, 1, ctypes.c_void_p(AJ.data_ptr()), N, None, None)
+    tp2._h = None
+    assert st == -1
