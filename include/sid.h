@@ -249,6 +249,34 @@ sid_status sid_stream_save(sid_stream *s, void *host_buf, size_t *bytes);
 sid_status sid_stream_restore(sid_ctx *ctx, const void *host_buf, size_t bytes,
                               sid_stream **out);
 
+/*
+ * Batched compression of independent matrices (one call for many problems,
+ * e.g. one per flow variable or dataset).  probs: host array of `count`
+ * problems, each with its own A (N x n, lda), parameters and outputs (same
+ * meanings, layouts and NULL rules as sid_compress); all share `dtype`.
+ * Every problem is validated before anything is launched (SID_EINVAL names
+ * the first bad problem in sid_last_error).  The problems run on up to four
+ * internal streams of the context (each with its own workspace), after the
+ * work already queued on the context's stream; the context's stream waits
+ * for all of them before the call returns, so later work on it sees every
+ * result.  A row set in a problem's params must belong to ctx.
+ */
+typedef struct {
+    const void *A;
+    int64_t N, n, lda;
+    sid_params params;
+    int64_t *J;
+    void *P;
+    int64_t ldp;
+    void *AJ;
+    int64_t ldaj;
+    double *err;
+    int64_t *k_eff;
+} sid_problem;
+
+sid_status sid_compress_batched(sid_ctx *ctx, const sid_problem *probs, int64_t count,
+                                sid_dtype dtype);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,7 +22,7 @@ EXPORTS = [
     "sid_set_workspace_limit", "sid_rowset_create", "sid_rowset_destroy", "sid_reserve",
     "sid_compress", "sid_reconstruct", "sid_error_norms", "sid_fill_gaussian", "sid_sketch",
     "sid_stream_begin", "sid_stream_push", "sid_stream_finish", "sid_stream_info", "sid_stream_abort",
-    "sid_stream_save", "sid_stream_restore",
+    "sid_stream_save", "sid_stream_restore", "sid_compress_batched",
 ]
 
 
@@ -84,6 +84,7 @@ def load():
     L.sid_stream_push.argtypes = [vp, vp, i64, i64]
     L.sid_stream_finish.argtypes = [vp, vp, vp, i64, vp, i64, vp, vp]
     L.sid_stream_abort.argtypes = [vp]
+    L.sid_compress_batched.argtypes = [vp, vp, i64, ctypes.c_int]
     L.sid_stream_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     L.sid_stream_save.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_size_t)]
@@ -92,7 +93,7 @@ def load():
                  "sid_rowset_destroy", "sid_reserve", "sid_compress", "sid_reconstruct",
                  "sid_error_norms", "sid_fill_gaussian", "sid_sketch", "sid_stream_begin",
                  "sid_stream_push", "sid_stream_finish", "sid_stream_info", "sid_stream_abort",
-                 "sid_stream_save",
+                 "sid_stream_save", "sid_compress_batched",
                  "sid_stream_restore"):
         getattr(L, name).restype = ctypes.c_int
     _LIB = L
@@ -229,6 +230,54 @@ class Compressed:
     AJ: torch.Tensor | None  # N x k skeleton (copy or single-pass estimate)
     err: torch.Tensor        # float64 [2]: probe estimate, sketch residual
     k_eff: torch.Tensor      # int64 [1]
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("N", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("lda", ctypes.c_int64), ("params", _Params), ("J", ctypes.c_void_p),
+                ("P", ctypes.c_void_p), ("ldp", ctypes.c_int64), ("AJ", ctypes.c_void_p),
+                ("ldaj", ctypes.c_int64), ("err", ctypes.c_void_p), ("k_eff", ctypes.c_void_p)]
+
+
+def _new_outputs(N: int, n: int, k: int, dtype, dev, want_skeleton: bool) -> Compressed:
+    J = torch.empty(k, dtype=torch.int64, device=dev)
+    P = torch.empty((n, k), dtype=dtype, device=dev).T
+    AJ = torch.empty((k, N), dtype=dtype, device=dev).T if want_skeleton else None
+    err = torch.empty(2, dtype=torch.float64, device=dev)
+    keff = torch.empty(1, dtype=torch.int64, device=dev)
+    return Compressed(J, P, AJ, err, keff)
+
+
+def compress_batched(mats: list, k, oversample=10, seed=0, mode: str = "two_pass",
+                     prec: str = "f32", probe_rows=10, rank_tol: float = 0.0,
+                     sp_rcond: float = 0.0, want_skeleton: bool = True,
+                     ctx: Context | None = None) -> list:
+    """Rank-k column IDs of several matrices in one call (sid_compress_batched).
+    k, oversample, seed and probe_rows may be scalars or one value per matrix;
+    all matrices share dtype, mode and precision."""
+    if not mats:
+        return []
+    ctx = ctx or default_context(mats[0].device)
+    m = len(mats)
+    per = lambda v: list(v) if isinstance(v, (list, tuple)) else [v] * m
+    ks, ovs, seeds, qs = per(k), per(oversample), per(seed), per(probe_rows)
+    dtype = mats[0].dtype
+    probs = (_Problem * m)()
+    keep, outs = [], []
+    for b, A in enumerate(mats):
+        if A.dtype != dtype:
+            raise ValueError("all matrices must share one dtype")
+        A, lda = _colmajor(A)
+        N, n = A.shape
+        o = _new_outputs(N, n, ks[b], dtype, A.device, want_skeleton)
+        p = _params(ks[b], ovs[b], seeds[b], None, mode, prec, qs[b], rank_tol, sp_rcond)
+        probs[b] = _Problem(ctypes.c_void_p(A.data_ptr()), N, n, lda, p, _ptr(o.J), _ptr(o.P),
+                            o.P.stride(1), _ptr(o.AJ), o.AJ.stride(1) if o.AJ is not None else 1,
+                            _ptr(o.err), _ptr(o.k_eff))
+        keep.append(A)
+        outs.append(o)
+    ctx.check(ctx._lib.sid_compress_batched(ctx.handle, probs, m, _dtype_code(mats[0])))
+    return outs
 
 
 def compress(A: torch.Tensor, k: int, oversample: int = 10, seed: int = 0,

@@ -38,6 +38,11 @@ struct sid_ctx {
   std::string err;
   Buf ws[WS_COUNT];
   size_t limit = 0;
+  // batched calls: child contexts (own stream and workspace each) and the
+  // events that order them after and before this context's stream
+  std::vector<sid_ctx*> children;
+  std::vector<hipEvent_t> child_done;
+  hipEvent_t fork = nullptr;
 };
 
 struct sid_rowset {
@@ -323,6 +328,9 @@ sid_status sid_destroy(sid_ctx* ctx) {
   }
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  for (sid_ctx* c : ctx->children) (void)sid_destroy(c);
+  for (hipEvent_t e : ctx->child_done) (void)hipEventDestroy(e);
+  if (ctx->fork) (void)hipEventDestroy(ctx->fork);
   for (Buf& b : ctx->ws)
     if (b.p) (void)hipFree(b.p);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
@@ -996,6 +1004,97 @@ sid_status sid_stream_restore(sid_ctx* ctx, const void* host_buf, size_t bytes, 
   s->y_init = h.y_init != 0;
   *out = s;
   return SID_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched compression: independent problems (Sec. 3 compresses each flow
+// variable / dataset separately).  Each problem's launches run on one of up
+// to SID_BATCH_STREAMS child streams, each with its own workspace, so the
+// latency-bound factorizations of different problems overlap one another
+// and the sketch passes; the children start after the work already queued
+// on the context's stream and the context's stream waits for all of them.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int SID_BATCH_STREAMS = 4;
+
+sid_status ensure_children(sid_ctx* ctx, int want) {
+  if (!ctx->fork) {
+    if (hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(ctx, SID_EDEVICE, "event creation failed");
+    }
+  }
+  while ((int)ctx->children.size() < want) {
+    sid_ctx* c = nullptr;
+    const sid_status st = sid_create(&c, ctx->device, nullptr);
+    if (st != SID_OK) return fail(ctx, st, "child context creation failed");
+    c->limit = ctx->limit;
+    c->cooperative = ctx->cooperative;
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)sid_destroy(c);
+      return fail(ctx, SID_EDEVICE, "event creation failed");
+    }
+    ctx->children.push_back(c);
+    ctx->child_done.push_back(e);
+  }
+  return SID_OK;
+}
+}  // namespace
+
+sid_status sid_compress_batched(sid_ctx* ctx, const sid_problem* probs, int64_t count,
+                                sid_dtype dtype) {
+  if (!ctx) return SID_EINVAL;
+  if (count < 0) return fail(ctx, SID_EINVAL, "count < 0");
+  if (count == 0) return SID_OK;
+  if (!probs) return fail(ctx, SID_EINVAL, "probs is NULL");
+  if (dtype != SID_F32 && dtype != SID_F64) return fail(ctx, SID_EINVAL, "unknown dtype");
+  // validate every problem before launching anything
+  for (int64_t b = 0; b < count; ++b) {
+    const sid_problem& q = probs[b];
+    Shape sh;
+    const std::string at = "problem " + std::to_string(b) + ": ";
+    if (!q.A) return fail(ctx, SID_EINVAL, at + "A is NULL");
+    if (q.lda < q.N) return fail(ctx, SID_EINVAL, at + "lda < N");
+    const sid_status vs = validate(ctx, q.N, q.n, &q.params, &sh);
+    if (vs != SID_OK) return fail(ctx, vs, at + ctx->err);
+    if (q.P && q.ldp < q.params.k) return fail(ctx, SID_EINVAL, at + "ldp < k");
+    if (q.AJ && q.ldaj < q.N) return fail(ctx, SID_EINVAL, at + "ldaj < N");
+    if (q.params.coarse && q.params.coarse->ctx != ctx)
+      return fail(ctx, SID_EINVAL, at + "row set belongs to another context");
+  }
+  SID_NEED_DEVICE(ctx);
+  SID_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+  const int nstreams = count < SID_BATCH_STREAMS ? (int)count : SID_BATCH_STREAMS;
+  sid_status st = ensure_children(ctx, nstreams);
+  if (st != SID_OK) return st;
+  SID_CHECK(hipEventRecord(ctx->fork, ctx->stream), "batched: fork event");
+  for (int c = 0; c < nstreams; ++c)
+    SID_CHECK(hipStreamWaitEvent(ctx->children[c]->stream, ctx->fork, 0), "batched: fork wait");
+  sid_status result = SID_OK;
+  for (int64_t b = 0; b < count && result == SID_OK; ++b) {
+    const sid_problem& q = probs[b];
+    sid_ctx* c = ctx->children[(size_t)(b % nstreams)];
+    // row sets are bound to the parent context; the child reads the same
+    // device array
+    sid_params pr = q.params;
+    sid_rowset tmp;
+    if (pr.coarse) {
+      tmp = *pr.coarse;
+      tmp.ctx = c;
+      pr.coarse = &tmp;
+    }
+    result = sid_compress(c, q.A, dtype, q.N, q.n, q.lda, &pr, q.J, q.P, q.ldp, q.AJ, q.ldaj,
+                          q.err, q.k_eff);
+    if (result != SID_OK) fail(ctx, result, "problem " + std::to_string(b) + ": " + c->err);
+  }
+  // join (also after a failure, so the context's stream never runs ahead)
+  for (int c = 0; c < nstreams; ++c) {
+    SID_CHECK(hipEventRecord(ctx->child_done[c], ctx->children[c]->stream), "batched: join event");
+    SID_CHECK(hipStreamWaitEvent(ctx->stream, ctx->child_done[c], 0), "batched: join wait");
+  }
+  return result;
 }
 
 }  // extern "C"

@@ -142,3 +142,42 @@ def test_stream_calls_validate(vctx):
     junk = ctypes.create_string_buffer(b"not a stream state" * 10)
     assert L.sid_stream_restore(h, junk, 180, ctypes.byref(out)) == EINVAL
     assert L.sid_stream_restore(h, junk, 4, ctypes.byref(out)) == EINVAL
+
+
+def test_problem_struct_layout(tmp_path):
+    """The binding's sid_problem / sid_params mirror the C layout (sizes and
+    field offsets from a C compiler)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "lay.c"
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "sid.h"\nint main(void){\n'
+                   'printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(sid_params), sizeof(sid_problem),'
+                   ' offsetof(sid_problem, params), offsetof(sid_problem, J),'
+                   ' offsetof(sid_problem, ldaj), offsetof(sid_problem, k_eff));\nreturn 0;}\n')
+    exe = tmp_path / "lay"
+    subprocess.check_call([cc, "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    P = _native._Problem
+    assert got == [ctypes.sizeof(_native._Params), ctypes.sizeof(P), P.params.offset, P.J.offset,
+                   P.ldaj.offset, P.k_eff.offset]
+
+
+def test_batched_validates_every_problem_first(vctx):
+    L, h = vctx
+    probs = (_native._Problem * 3)()
+    for b in range(3):
+        L.sid_params_init(ctypes.byref(probs[b].params), 5)
+        probs[b].A, probs[b].N, probs[b].n, probs[b].lda = 1, 100, 20, 100
+    assert L.sid_compress_batched(h, probs, 3, 1) == ESTATE
+    assert L.sid_compress_batched(h, probs, 0, 1) == 0
+    assert L.sid_compress_batched(h, None, 3, 1) == EINVAL
+    probs[2].n = 3                      # k = 5 > n
+    assert L.sid_compress_batched(h, probs, 3, 1) == EINVAL
+    assert b"problem 2" in L.sid_last_error(h)
+    probs[2].n = 20
+    probs[1].lda = 50                   # lda < N
+    assert L.sid_compress_batched(h, probs, 3, 1) == EINVAL
+    assert b"problem 1" in L.sid_last_error(h)

@@ -425,3 +425,40 @@ def test_stream_save_restore_and_two_pass(sid):
     st = L.sid_stream_finish(tp2._h, None, None, 1, ctypes.c_void_p(AJ.data_ptr()), N, None, None)
     tp2._h = None
     assert st == -1
+
+
+@pytest.mark.parametrize("mode,prec", [("single_pass", "bf16x2"), ("two_pass", "f32"),
+                                       ("single_pass", "fp8")])
+def test_batched_equals_individual(sid, oracle_mod, mode, prec):
+    """A batch of matrices of mixed shapes and ranks (spectrum j^-1.5, as in
+    the batched workload) == one sid_compress per matrix, bit for bit in J
+    and P (same kernels, own workspace per internal stream), and the
+    oracle's pivots until its first near-tie."""
+    rng = np.random.default_rng(21)
+    shapes = [(16384, 64, 8), (5120, 300, 40), (40000, 128, 20), (2048, 512, 64), (9000, 90, 12),
+              (30000, 200, 33), (4096, 77, 9)]
+    mats, A64s = [], []
+    for (N, n, k) in shapes:
+        sig = np.arange(1, n + 1) ** -1.5
+        A64 = np.asarray(synth.lowrank_exact_spectrum(N, n, sig, seed=int(rng.integers(1 << 30)),
+                                                      noise=0.0)).astype(np.float32).astype(np.float64)
+        A64s.append(A64)
+        mats.append(to_gpu(A64, torch.float32))
+    ks = [s[2] for s in shapes]
+    seeds = list(range(3, 3 + len(shapes)))
+    say("batched", mode, prec)
+    outs = sid.compress_batched(mats, ks, oversample=10, seed=seeds, mode=mode, prec=prec,
+                                probe_rows=6)
+    torch.cuda.synchronize()
+    for b, A in enumerate(mats):
+        ref = sid.compress(A, ks[b], 10, seed=seeds[b], mode=mode, prec=prec, probe_rows=6)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(outs[b].J), host(ref.J)), b
+        assert np.array_equal(host(outs[b].P), host(ref.P)), b
+        assert np.array_equal(host(outs[b].AJ), host(ref.AJ)), b
+        assert np.array_equal(host(outs[b].err), host(ref.err)), b
+    b = 2
+    orc = oracle_mod.compress(A64s[b], ks[b], 10, seed=seeds[b], mode=mode, prec=prec, probe_rows=6)
+    tie = {"f32": 1e-5, "bf16x2": 1e-4, "fp8": 3e-2}[prec]
+    ist = next((i for i, m in enumerate(orc.cp.margins) if m <= tie), ks[b])
+    assert host(outs[b].J)[:ist].tolist() == orc.J[:ist].tolist()
