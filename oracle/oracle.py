@@ -425,6 +425,45 @@ def compress(A, k: int, oversample: int, seed: int = 0, coarse_rows=None,
                   err_sketch=err_sketch, W=W, Y=Y, cp=cp)
 
 
+def refine(A, res: Result, seed: int, refine_prec: str, l: int, coarse_rows=None) -> np.ndarray:
+    """One refinement step of the coefficients P on a second, more precise
+    sketch of A.  The paper stops at the ID; this is this implementation's
+    reading of a refinement pass: one step of iterative refinement of the
+    least-squares problem min ||W'(:, J) P - W'|| that defines P on the
+    sketch W' = Psi_sel(:, S) A(S, :) taken in ``refine_prec``, reusing the
+    triangular factor R11 of the first (low-precision) mgsqr:
+
+      E   = A - A(:, J) P0             (residual of the ID, exact columns)
+      W_r = Psi_sel(:, S) E(S, :)      (formed as W' - W'(:, J) P0)
+      dP  = R11^-1 R11^-T W'(:, J)^T W_r   (corrected seminormal equations)
+      P1  = P0 + dP                    (dP vanishes on J, since W_r does)
+
+    Its fixed point is the least-squares solution on W'; with W' equal to
+    the first sketch the step changes nothing.  Returns P1 (k x n, rows past
+    k_eff zero)."""
+    A = np.asarray(A)
+    N, n = A.shape
+    rows = np.arange(N, dtype=np.int64) if coarse_rows is None else np.asarray(coarse_rows, np.int64)
+    ke = res.k_eff
+    P0 = res.P[:ke]
+    J = res.cp.J
+    Wp = sketch_w(A, rows, l, seed, refine_prec)
+    WpJ = Wp[:, J]
+    Wr = Wp - WpJ @ P0
+    G = WpJ.T @ Wr                               # k_eff x n
+    R11 = res.cp.R[:, J]
+    H = np.zeros_like(G)
+    for b in range(ke):                          # forward substitution with R11^T
+        H[b] = (G[b] - R11[:b, b] @ H[:b]) / R11[b, b]
+    dP = np.zeros_like(G)
+    for b in range(ke - 1, -1, -1):              # back substitution with R11
+        dP[b] = (H[b] - R11[b, b + 1:] @ dP[b + 1:]) / R11[b, b]
+    dP[:, J] = 0.0
+    P1 = np.zeros_like(res.P)
+    P1[:ke] = P0 + dP
+    return P1
+
+
 def reconstruct(AJ: np.ndarray, P: np.ndarray) -> np.ndarray:
     """A_hat = A_J P (the ID of eq. (ID), transposed)."""
     return np.asarray(AJ, np.float64) @ np.asarray(P, np.float64)

@@ -458,3 +458,32 @@ def test_compression_factor_printed_values(oracle_mod):
         cf = oracle_mod.compression_factor(int(nsp), int(m), int(k))
         assert round(cf / 10) * 10 == printed or abs(cf - printed) / printed < 0.002
     assert oracle_mod.temporal_compression_factor(10000, 100) == 100.0
+
+
+def test_refinement_fixed_point_and_noop(oracle_mod):
+    """Refinement of P: (1) with the refinement sketch equal to the first one
+    the step is a no-op (the first P already solves that least-squares
+    problem); (2) iterated, it converges to the least-squares coefficients of
+    the refinement sketch, lstsq(W'(:, J), W') (an independent library
+    solve), with P(:, J) = I kept exactly; (3) one step from an FP8 sketch
+    moves P toward that solution."""
+    rng = np.random.default_rng(31)
+    N, n, k, p = 3000, 60, 8, 6
+    A = (rng.standard_normal((N, 12)) @ rng.standard_normal((12, n))
+         * np.exp(-np.arange(n) / 15.0)).astype(np.float32).astype(np.float64)
+    l = k + p
+    res = oracle_mod.compress(A, k, p, seed=5, mode="two_pass", prec="bf16x2", probe_rows=0)
+    P1 = oracle_mod.refine(A, res, seed=5, refine_prec="bf16x2", l=l)
+    assert np.max(np.abs(P1 - res.P)) <= 1e-9 * np.max(np.abs(res.P))
+    res8 = oracle_mod.compress(A, k, p, seed=5, mode="two_pass", prec="fp8", probe_rows=0)
+    J = res8.cp.J
+    Wp = oracle_mod.sketch_w(A, None, l, 5, "f64")
+    target = np.linalg.lstsq(Wp[:, J], Wp, rcond=None)[0]
+    cur = oracle_mod.Result(**{**res8.__dict__})
+    d0 = np.max(np.abs(res8.P - target))
+    for it in range(40):
+        cur.P = oracle_mod.refine(A, cur, seed=5, refine_prec="f64", l=l)
+        if it == 0:
+            assert np.max(np.abs(cur.P - target)) < 0.5 * d0
+    assert np.max(np.abs(cur.P - target)) <= 1e-8 * np.max(np.abs(target))
+    assert np.array_equal(cur.P[:, J], np.eye(k))
