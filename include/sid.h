@@ -109,11 +109,21 @@ typedef struct {
                                   first pivot's (Remark 2.2), k_eff < k then      */
     double sp_rcond;           /* single pass: relative drop tolerance of the
                                   small solve (0: default for the precision)     */
+    int32_t refine;            /* 0: none; 1: one refinement pass of P (reads A
+                                  once more, sid_compress only)                  */
+    sid_sketch_prec refine_prec; /* precision of the refinement sketch          */
 } sid_params;
 
 /* Fill a parameter block with defaults: oversample 10, seed 0, all rows,
  * two-pass, F32 sketch, probe_rows 10, corange_rows -1, rank_tol 0,
- * sp_rcond 0.
+ * sp_rcond 0, refine 0, refine_prec BF16X2.
+ * Refinement (refine = 1; the paper stops at the ID): after J and P0 are
+ * chosen, A is sketched once more with Psi's selection rows in refine_prec,
+ * W' = Psi_sel A, and P0 takes one step of iterative refinement of the
+ * least-squares problem min ||W'(:, J) P - W'|| with the first pivoted QR's
+ * R11 (corrected seminormal equations): P1 = P0 + R11^-1 R11^-T W'(:, J)^T
+ * (W' - W'(:, J) P0).  P1(:, J) = I still holds exactly.  err and AJ are
+ * those of P0's fit.
  * Psi row layout: rows [0, l) select J and P (Alg. 4); in single pass rows
  * [l, l + e) are the extra co-range rows; the last q rows are the probe. */
 void sid_params_init(sid_params *p, int64_t k);

@@ -44,6 +44,8 @@ class _Params(ctypes.Structure):
         ("corange_rows", ctypes.c_int32),
         ("rank_tol", ctypes.c_double),
         ("sp_rcond", ctypes.c_double),
+        ("refine", ctypes.c_int32),
+        ("refine_prec", ctypes.c_int),
     ]
 
 
@@ -208,7 +210,7 @@ class RowSet:
 
 
 def _params(k, oversample, seed, coarse, mode, prec, probe_rows, rank_tol, sp_rcond,
-            corange_rows=-1) -> _Params:
+            corange_rows=-1, refine=False, refine_prec="bf16x2") -> _Params:
     p = _Params()
     load().sid_params_init(ctypes.byref(p), int(k))
     p.oversample = int(oversample)
@@ -220,6 +222,8 @@ def _params(k, oversample, seed, coarse, mode, prec, probe_rows, rank_tol, sp_rc
     p.corange_rows = int(corange_rows)
     p.rank_tol = float(rank_tol)
     p.sp_rcond = float(sp_rcond)
+    p.refine = 1 if refine else 0
+    p.refine_prec = PRECISIONS[refine_prec]
     return p
 
 
@@ -284,8 +288,10 @@ def compress(A: torch.Tensor, k: int, oversample: int = 10, seed: int = 0,
              coarse: RowSet | None = None, mode: str = "two_pass", prec: str = "f32",
              probe_rows: int = 10, rank_tol: float = 0.0, sp_rcond: float = 0.0,
              corange_rows: int = -1, want_skeleton: bool = True, ctx: Context | None = None,
-             out: Compressed | None = None) -> Compressed:
-    """Rank-k column ID of A (N x n, float32/float64 on the GPU)."""
+             out: Compressed | None = None, refine: bool = False,
+             refine_prec: str = "bf16x2") -> Compressed:
+    """Rank-k column ID of A (N x n, float32/float64 on the GPU); refine=True
+    adds one refinement pass of P on a refine_prec sketch."""
     ctx = ctx or default_context(A.device)
     A, lda = _colmajor(A)
     N, n = A.shape
@@ -298,7 +304,7 @@ def compress(A: torch.Tensor, k: int, oversample: int = 10, seed: int = 0,
         keff = torch.empty(1, dtype=torch.int64, device=dev)
         out = Compressed(J, P, AJ, err, keff)
     p = _params(k, oversample, seed, coarse, mode, prec, probe_rows, rank_tol, sp_rcond,
-                corange_rows)
+                corange_rows, refine, refine_prec)
     ldaj = out.AJ.stride(1) if out.AJ is not None else 1
     ctx.check(ctx._lib.sid_compress(
         ctx.handle, _ptr(A), _dtype_code(A), N, n, lda, ctypes.byref(p), _ptr(out.J),

@@ -19,7 +19,7 @@ namespace {
 enum Slot {
   WS_OMEGA, WS_PART, WS_W, WS_WR, WS_NRM, WS_PIV, WS_R, WS_Q, WS_KEFF, WS_STATS, WS_PD,
   WS_ERR, WS_Y, WS_M, WS_MPR, WS_WJ, WS_PIVM, WS_RM, WS_QM, WS_RKM, WS_C, WS_T, WS_MIX,
-  WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COOP, WS_SYNC, WS_R11, WS_FITPART, WS_YTMP, WS_COUNT
+  WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COOP, WS_SYNC, WS_R11, WS_FITPART, WS_YTMP, WS_REF_W, WS_REF_WJ, WS_REF_T, WS_REF_G, WS_COUNT
 };
 
 struct Buf {
@@ -156,6 +156,9 @@ sid_status validate(sid_ctx* ctx, int64_t N, int64_t n, const sid_params* p, Sha
     return fail(ctx, SID_EINVAL, "unknown sketch precision");
   if (!(p->rank_tol >= 0.0) || !(p->sp_rcond >= 0.0))
     return fail(ctx, SID_EINVAL, "rank_tol and sp_rcond must be >= 0");
+  if (p->refine != 0 && p->refine != 1) return fail(ctx, SID_EINVAL, "refine must be 0 or 1");
+  if (p->refine && (p->refine_prec < SID_SK_F64 || p->refine_prec > SID_SK_FP8E4M3))
+    return fail(ctx, SID_EINVAL, "unknown refinement precision");
   const int64_t l = p->k + p->oversample;
   const bool single = p->mode == SID_SINGLE_PASS;
   const int64_t e = single ? (p->corange_rows < 0 ? p->oversample : p->corange_rows) : 0;
@@ -277,6 +280,8 @@ void sid_params_init(sid_params* p, int64_t k) {
   p->corange_rows = -1;
   p->rank_tol = 0.0;
   p->sp_rcond = 0.0;
+  p->refine = 0;
+  p->refine_prec = SID_SK_BF16X2;
 }
 
 sid_status sid_create(sid_ctx** out, int device, void* hip_stream) {
@@ -411,6 +416,9 @@ sid_status sid_reserve(sid_ctx* ctx, int64_t N, int64_t n, const sid_params* p) 
 static sid_status factor(sid_ctx* ctx, const sid_params* p, const Shape& sh, const Work& w,
                          sid_dtype dtype, const void* A, int64_t lda, int64_t* J, void* P,
                          int64_t ldp, void* AJ, int64_t ldaj, double* err, int64_t* k_eff);
+static sid_status refine_pass(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t lda,
+                              const sid_params* p, const Shape& sh, const Work& w, void* P,
+                              int64_t ldp);
 
 // The sketch pass over the columns col0 .. col0 + sh.n - 1 of the matrix
 // (A points at column col0): W (lq x sh.n) and, if Y is given, Y = A Omega
@@ -511,7 +519,47 @@ sid_status sid_compress(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N,
   // (1) sketch pass: W = Psi(:, S) A(S, :) and, single pass, Y = A Omega
   s = run_sketch(ctx, A, dtype, lda, p, sh, w, w.W, sh.single ? w.Y : nullptr);
   if (s != SID_OK) return s;
-  return factor(ctx, p, sh, w, dtype, A, lda, J, P, ldp, AJ, ldaj, err, k_eff);
+  s = factor(ctx, p, sh, w, dtype, A, lda, J, P, ldp, AJ, ldaj, err, k_eff);
+  if (s != SID_OK || !p->refine) return s;
+  return refine_pass(ctx, A, dtype, lda, p, sh, w, P, ldp);
+}
+
+// One refinement step of P (corrected seminormal equations on a second
+// sketch W' = Psi(0:l, S) A(S, :) in refine_prec, with the first mgsqr's
+// R11): P1 = P0 + R11^-1 R11^-T W'(:, J)^T (W' - W'(:, J) P0).
+static sid_status refine_pass(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t lda,
+                              const sid_params* p, const Shape& sh, const Work& w, void* P,
+                              int64_t ldp) {
+  hipStream_t st = ctx->stream;
+  const int k = (int)sh.k, l = (int)sh.l, n_ = (int)sh.n;
+  sid_params pr = *p;
+  pr.prec = p->refine_prec;
+  pr.mode = SID_TWO_PASS;
+  pr.probe_rows = 0;
+  pr.refine = 0;
+  Shape shr = sh;
+  shr.prec = p->refine_prec;
+  shr.single = false;
+  shr.q = 0;
+  shr.lz = sh.l;
+  shr.lq = sh.l;
+  const size_t d = sizeof(double);
+  double* Wp = (double*)ws(ctx, WS_REF_W, d * (size_t)(l * n_));
+  double* WpJ = (double*)ws(ctx, WS_REF_WJ, d * (size_t)(l * k));
+  double* T1 = (double*)ws(ctx, WS_REF_T, d * (size_t)(l * n_));
+  double* G = (double*)ws(ctx, WS_REF_G, d * (size_t)(k * n_));
+  if (!Wp || !WpJ || !T1 || !G) return SID_ENOMEM;
+  sid_status s = run_sketch(ctx, A, dtype, lda, &pr, shr, w, Wp, nullptr);
+  if (s != SID_OK) return s;
+  SID_CHECK(sid::launch_gather_block(st, Wp, l, 0, l, w.piv, w.keff, k, WpJ), "W'(:, J)");
+  SID_CHECK(sid::launch_gemm64(st, l, n_, k, WpJ, l, 0, w.Pd, k, 0, T1, l), "W'(:, J) P0");
+  SID_CHECK(sid::launch_sub_from(st, Wp, T1, (int64_t)l * n_, ctx->num_cu), "W' - W'(:, J) P0");
+  SID_CHECK(sid::launch_gemm64(st, k, n_, l, WpJ, l, 1, T1, l, 0, G, k), "W'(:, J)^T W_r");
+  SID_CHECK(sid::launch_gather_r11(st, w.R, n_, w.piv, w.keff, k, w.R11), "R11");
+  SID_CHECK(sid::launch_csne_solve(st, w.R11, k, w.keff, G, k, n_), "R11^-1 R11^-T");
+  SID_CHECK(sid::launch_refine_store(st, w.Pd, G, k, n_, P, ldp, dtype == SID_F64),
+            "P0 + dP");
+  return SID_OK;
 }
 
 // Everything after the sketch pass, from W (w.W, lq x n), single pass also
@@ -788,6 +836,8 @@ sid_status sid_stream_begin(sid_ctx* ctx, sid_dtype dtype, int64_t N, int64_t n_
   Shape sh;
   const sid_status vs = validate(ctx, N, n_max, p, &sh);
   if (vs != SID_OK) return vs;
+  if (p->refine)
+    return fail(ctx, SID_EINVAL, "refinement re-reads A; a stream keeps no columns");
   SID_NEED_DEVICE(ctx);
   SID_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
   return stream_make(ctx, dtype, N, n_max, p, out);

@@ -618,6 +618,12 @@ static hipError_t trsv_launch(hipStream_t st, const double* R11, int kcap, const
   return hipGetLastError();
 }
 
+hipError_t launch_gather_r11(hipStream_t st, const double* R, int nc, const int64_t* piv,
+                             const int64_t* keff, int kcap, double* R11) {
+  hipLaunchKernelGGL(k_gather_r11, dim3(64), dim3(256), 0, st, R, (int64_t)nc, piv, keff, kcap, R11);
+  return hipGetLastError();
+}
+
 hipError_t launch_id_coefficients(hipStream_t st, const double* R, int nc, const int64_t* piv,
                                   const int64_t* keff, int kcap, double* R11, double* Pd,
                                   void* P, int64_t ldp, bool p_is_f64) {

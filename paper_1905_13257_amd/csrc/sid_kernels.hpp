@@ -28,6 +28,13 @@ hipError_t launch_gemm64(hipStream_t st, int M, int Nn, int K, const double* A, 
                          int tA, const double* B, int64_t ldb, int tB, double* C, int64_t ldc);
 hipError_t launch_add_inplace(hipStream_t st, bool f64, void* y, const void* x, int64_t count,
                               int num_cu);
+hipError_t launch_sub_from(hipStream_t st, const double* x, double* y, int64_t count, int num_cu);
+hipError_t launch_csne_solve(hipStream_t st, const double* R11, int kcap, const int64_t* keff,
+                             double* G, int64_t ldg, int n);
+hipError_t launch_refine_store(hipStream_t st, double* Pd, const double* dP, int k, int n, void* P,
+                               int64_t ldp, bool p_f64);
+hipError_t launch_gather_r11(hipStream_t st, const double* R, int nc, const int64_t* piv,
+                             const int64_t* keff, int kcap, double* R11);
 hipError_t launch_gather_cols(hipStream_t st, const void* src, bool src_f64, int64_t lds,
                               int64_t rows, const int64_t* piv, const int64_t* keff, int kcap,
                               void* dst, bool dst_f64, int64_t ldd);

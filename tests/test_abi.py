@@ -181,3 +181,19 @@ def test_batched_validates_every_problem_first(vctx):
     probs[1].lda = 50                   # lda < N
     assert L.sid_compress_batched(h, probs, 3, 1) == EINVAL
     assert b"problem 1" in L.sid_last_error(h)
+
+
+def test_refine_validation(vctx):
+    L, h = vctx
+    vp = ctypes.c_void_p
+    p = _params(L, 5)
+    p.refine = 2
+    assert L.sid_reserve(h, 100, 20, ctypes.byref(p)) == EINVAL
+    p.refine, p.refine_prec = 1, 9
+    assert L.sid_reserve(h, 100, 20, ctypes.byref(p)) == EINVAL
+    p.refine_prec = 3
+    assert L.sid_reserve(h, 100, 20, ctypes.byref(p)) == ESTATE
+    out = vp()
+    assert L.sid_stream_begin(h, 1, 100, 20, ctypes.byref(p), ctypes.byref(out)) == EINVAL
+    q = _params(L, 5)
+    assert q.refine == 0 and q.refine_prec == 3

@@ -462,3 +462,36 @@ def test_batched_equals_individual(sid, oracle_mod, mode, prec):
     tie = {"f32": 1e-5, "bf16x2": 1e-4, "fp8": 3e-2}[prec]
     ist = next((i for i, m in enumerate(orc.cp.margins) if m <= tie), ks[b])
     assert host(outs[b].J)[:ist].tolist() == orc.J[:ist].tolist()
+
+
+def test_refinement_pass(sid, oracle_mod):
+    """Refinement of P on a second sketch (both modes): the same precision is
+    a no-op; an FP8 first sketch refined on a bf16x2 sketch matches the
+    oracle's refinement step and does not increase the error of the ID."""
+    A64, _ = c1_matrix(N=4096, n=256, seed=1003)
+    A64 = A64.astype(np.float32).astype(np.float64)
+    A = to_gpu(A64, torch.float32)
+    k, p, q = 20, 10, 10
+    for mode in ("two_pass", "single_pass"):
+        say("refine", mode)
+        base = sid.compress(A, k, p, seed=6, mode=mode, prec="bf16x2", probe_rows=q)
+        same = sid.compress(A, k, p, seed=6, mode=mode, prec="bf16x2", probe_rows=q, refine=True,
+                            refine_prec="bf16x2")
+        torch.cuda.synchronize()
+        assert np.array_equal(host(same.J), host(base.J))
+        np.testing.assert_allclose(host(same.P), host(base.P), atol=1e-6 * np.abs(host(base.P)).max())
+        r0 = sid.compress(A, k, p, seed=6, mode=mode, prec="fp8", probe_rows=q)
+        r1 = sid.compress(A, k, p, seed=6, mode=mode, prec="fp8", probe_rows=q, refine=True,
+                          refine_prec="bf16x2")
+        torch.cuda.synchronize()
+        orc = oracle_mod.compress(A64, k, p, seed=6, mode=mode, prec="fp8", probe_rows=q)
+        assert orc.cp.margins.min() > 1e-4   # same e4m3 values on both sides; sums differ ~1e-6
+        assert host(r1.J).tolist() == orc.J.tolist()
+        P1o = oracle_mod.refine(A64, orc, seed=6, refine_prec="bf16x2", l=k + p)
+        P1 = host(r1.P).astype(np.float64)
+        np.testing.assert_allclose(P1, P1o, atol=2e-4 * np.abs(P1o).max())
+        assert np.array_equal(P1[:, orc.J], np.eye(k))
+        e0 = sid.error_norms(A, r0.AJ, r0.P)["rel_fro"]
+        e1 = sid.error_norms(A, r1.AJ, r1.P)["rel_fro"]
+        say("refine", mode, "fp8 error", e0, "refined", e1)
+        assert e1 <= e0 * 1.001
