@@ -43,6 +43,10 @@ struct sid_ctx {
   std::vector<sid_ctx*> children;
   std::vector<hipEvent_t> child_done;
   hipEvent_t fork = nullptr;
+  // single pass: the factorization of M (independent of the pivots of W)
+  // runs on a side stream while mgsqr of W runs on the main one
+  hipStream_t side = nullptr;
+  hipEvent_t side_fork = nullptr, side_join = nullptr;
 };
 
 struct sid_rowset {
@@ -334,6 +338,9 @@ sid_status sid_destroy(sid_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   for (sid_ctx* c : ctx->children) (void)sid_destroy(c);
+  if (ctx->side) (void)hipStreamDestroy(ctx->side);
+  if (ctx->side_fork) (void)hipEventDestroy(ctx->side_fork);
+  if (ctx->side_join) (void)hipEventDestroy(ctx->side_join);
   for (hipEvent_t e : ctx->child_done) (void)hipEventDestroy(e);
   if (ctx->fork) (void)hipEventDestroy(ctx->fork);
   for (Buf& b : ctx->ws)
@@ -572,12 +579,56 @@ static sid_status factor(sid_ctx* ctx, const sid_params* p, const Shape& sh, con
   const bool f64 = dtype == SID_F64;
   const int k = (int)sh.k, l = (int)sh.l, q = (int)sh.q, lz = (int)sh.lz, lq = (int)sh.lq,
             n_ = (int)sh.n;
+  // which mgsqr kernel each factorization uses (the cooperative and the
+  // general kernels use context scratch, so two of the same kind must not
+  // run at once)
+  auto kind = [](int m, int nc) {
+    return sid::cpqr_wg_supported(m, nc) ? 0 : (sid::cpqr_coop_supported(m, nc) ? 1 : 2);
+  };
+  const int w_kind = kind(l, n_);
+  const int m_kind = sh.single ? kind(lz, l) : 0;
+  const bool overlap = sh.single && (m_kind == 0 || m_kind != w_kind);
+  const double rcond = p->sp_rcond > 0.0 ? p->sp_rcond : default_rcond(sh.prec);
+  if (sh.single) {
+    // (5a) single pass, independent of the pivots: M = W(0:lz, :) Omega,
+    // Mpr = W_pr Omega and mgsqr of M, on a side stream when they can
+    // overlap mgsqr of W (step 2)
+    hipStream_t ms = st;
+    if (overlap) {
+      if (!ctx->side) {
+        SID_CHECK(hipStreamCreate(&ctx->side), "side stream");
+        SID_CHECK(hipEventCreateWithFlags(&ctx->side_fork, hipEventDisableTiming), "side event");
+        SID_CHECK(hipEventCreateWithFlags(&ctx->side_join, hipEventDisableTiming), "side event");
+      }
+      SID_CHECK(hipEventRecord(ctx->side_fork, st), "side fork");
+      SID_CHECK(hipStreamWaitEvent(ctx->side, ctx->side_fork, 0), "side fork wait");
+      ms = ctx->side;
+    }
+    SID_CHECK(sid::launch_omega_values(ms, sh.prec, w.omega, sh.n * sh.l, w.om64), "omega values");
+    SID_CHECK(sid::launch_gemm64(ms, lz, l, n_, w.W, lq, 0, w.om64, l, 1, w.M, lz), "M = W Omega");
+    if (q > 0)
+      SID_CHECK(sid::launch_gemm64(ms, q, l, n_, w.W + lz, lq, 0, w.om64, l, 1, w.Mpr, q),
+                "Mpr = Wpr Omega");
+    if (m_kind == 0)
+      SID_CHECK(sid::launch_cpqr_wg(ms, w.M, lz, lz, l, l, rcond, w.pivM, w.RM, w.QM, w.rkM,
+                                    w.statsM),
+                "pivoted QR of M");
+    else if (m_kind == 1)
+      SID_CHECK(sid::launch_cpqr_coop(ms, w.M, lz, lz, l, l, rcond, w.coop, w.sync2, w.pivM, w.RM,
+                                      w.QM, w.rkM, w.statsM, ctx->cooperative),
+                "pivoted QR of M");
+    else
+      SID_CHECK(sid::launch_cpqr(ms, w.M, lz, lz, l, l, rcond, w.Wr, w.nrm, w.pivM, w.RM, w.QM,
+                                 w.rkM, w.statsM),
+                "pivoted QR of M");
+    if (overlap) SID_CHECK(hipEventRecord(ctx->side_join, ctx->side), "side join");
+  }
   // (2) mgsqr on the selection rows of W
-  if (sid::cpqr_wg_supported(l, n_))
+  if (w_kind == 0)
     SID_CHECK(sid::launch_cpqr_wg(st, w.W, lq, l, n_, k, p->rank_tol, w.piv, w.R, w.Q, w.keff,
                                   w.stats),
               "pivoted QR");
-  else if (sid::cpqr_coop_supported(l, n_))
+  else if (w_kind == 1)
     SID_CHECK(sid::launch_cpqr_coop(st, w.W, lq, l, n_, k, p->rank_tol, w.coop, w.sync2, w.piv,
                                     w.R, w.Q, w.keff, w.stats, ctx->cooperative),
               "pivoted QR");
@@ -598,32 +649,15 @@ static sid_status factor(sid_ctx* ctx, const sid_params* p, const Shape& sh, con
       SID_CHECK(sid::launch_gather_cols(st, A, f64, lda, sh.N, w.piv, w.keff, k, AJ, f64, ldaj),
                 "skeleton gather");
   } else {
-    // (5) single pass.  Psi Y = Psi A Omega = W Omega, so the small matrix
+    // (5b) single pass.  Psi Y = Psi A Omega = W Omega, so the small matrix
     // M = W(0:lz, :) Omega plays the role of Z = Psi Q (up to the triangular
     // factor of Y), and the minimum-residual solve of the two-sided sketch
     // (Halko et al. Sec. 5.5 item (4)) becomes T = M^+ W(0:lz, J), AJ = Y T.
     // lz = l + e: the e extra co-range rows make M tall (the square form is
     // the ill-conditioned case the paper warns about in Sec. 2.3).  M^+ is
-    // applied through mgsqr of M truncated at sp_rcond (least squares on the
-    // pivoted columns).
-    const double rcond = p->sp_rcond > 0.0 ? p->sp_rcond : default_rcond(sh.prec);
-    SID_CHECK(sid::launch_omega_values(st, sh.prec, w.omega, sh.n * sh.l, w.om64), "omega values");
-    SID_CHECK(sid::launch_gemm64(st, lz, l, n_, w.W, lq, 0, w.om64, l, 1, w.M, lz), "M = W Omega");
-    if (q > 0)
-      SID_CHECK(sid::launch_gemm64(st, q, l, n_, w.W + lz, lq, 0, w.om64, l, 1, w.Mpr, q),
-                "Mpr = Wpr Omega");
-    if (sid::cpqr_wg_supported(lz, l))
-      SID_CHECK(sid::launch_cpqr_wg(st, w.M, lz, lz, l, l, rcond, w.pivM, w.RM, w.QM, w.rkM,
-                                    w.statsM),
-                "pivoted QR of M");
-    else if (sid::cpqr_coop_supported(lz, l))
-      SID_CHECK(sid::launch_cpqr_coop(st, w.M, lz, lz, l, l, rcond, w.coop, w.sync2, w.pivM, w.RM,
-                                      w.QM, w.rkM, w.statsM, ctx->cooperative),
-                "pivoted QR of M");
-    else
-      SID_CHECK(sid::launch_cpqr(st, w.M, lz, lz, l, l, rcond, w.Wr, w.nrm, w.pivM, w.RM, w.QM,
-                                 w.rkM, w.statsM),
-                "pivoted QR of M");
+    // applied through mgsqr of M (step 5a) truncated at sp_rcond (least
+    // squares on the pivoted columns).
+    if (overlap) SID_CHECK(hipStreamWaitEvent(st, ctx->side_join, 0), "side join wait");
     SID_CHECK(sid::launch_gather_block(st, w.W, lq, 0, lz, w.piv, w.keff, k, w.WJ), "W(:, J)");
     SID_CHECK(sid::launch_gemm64(st, l, k, lz, w.QM, lz, 1, w.WJ, lz, 0, w.C, l), "QM^T W(:, J)");
     SID_CHECK(sid::launch_small_solve(st, w.RM, l, w.pivM, w.rkM, w.R11, w.C, l, k, w.T), "T");
