@@ -371,6 +371,32 @@ class Result:
     cp: CPQR
 
 
+def compress_literal(A, k: int, coarse_rows, prec: str = "f64", rank_tol: float = 0.0) -> Result:
+    """The sub-sampled ID exactly as Alg. 5 writes it: mgsqr directly on the
+    coarse rows A(S, :) (no Gaussian sketch), P from its R, and the skeleton
+    columns A(:, J) copied from the full matrix (two-pass).  err_sketch is
+    the residual of the mgsqr fit on A(S, :); there are no probe rows
+    (err_probe = NaN)."""
+    A = np.asarray(A)
+    N, n = A.shape
+    rows = np.asarray(coarse_rows, np.int64)
+    if rows.size <= k or np.any(np.diff(rows) <= 0) or rows[0] < 0 or rows[-1] >= N:
+        raise ValueError("coarse rows must be sorted, unique, in range and more than k")
+    if prec not in ("f64", "f32"):
+        raise ValueError("the literal form reads the data in F64 or F32")
+    W = data_values(A[rows], prec)
+    cp = cpqr(W, k, rank_tol)
+    Pk = id_coefficients(cp.R, cp.J, n)
+    P = np.zeros((k, n))
+    P[:cp.k_eff] = Pk
+    J = np.full(k, -1, dtype=np.int64)
+    J[:cp.k_eff] = cp.J
+    AJk = np.zeros((N, k))
+    AJk[:, :cp.k_eff] = np.asarray(A, dtype=np.float64)[:, cp.J]
+    return Result(J=J, P=P, AJ=AJk, k_eff=cp.k_eff, err_probe=float("nan"),
+                  err_sketch=_rel_fit(W, W[:, cp.J] @ Pk), W=W, Y=None, cp=cp)
+
+
 def compress(A, k: int, oversample: int, seed: int = 0, coarse_rows=None,
              mode: str = "two_pass", prec: str = "f64", probe_rows: int = 10,
              rank_tol: float = 0.0, sp_rcond: float = 1e-12,

@@ -487,3 +487,21 @@ def test_refinement_fixed_point_and_noop(oracle_mod):
             assert np.max(np.abs(cur.P - target)) < 0.5 * d0
     assert np.max(np.abs(cur.P - target)) <= 1e-8 * np.max(np.abs(target))
     assert np.array_equal(cur.P[:, J], np.eye(k))
+
+
+def test_literal_subsampled_id_matches_lapack(oracle_mod):
+    """Alg. 5 literal: mgsqr directly on A(S, :).  With well-separated
+    pivots its J equals LAPACK's pivoted QR (dgeqp3) of A(S, :); with S all
+    rows and rank(A) <= k the ID is exact."""
+    rng = np.random.default_rng(41)
+    N, n, k = 400, 30, 6
+    A = rng.standard_normal((N, n)) * np.exp(-np.linspace(0, 4, n))[None, rng.permutation(n)]
+    S = np.arange(1, N, 3)
+    res = oracle_mod.compress_literal(A, k, S)
+    _, _, piv = scipy.linalg.qr(A[S], pivoting=True, mode="economic")
+    assert res.J.tolist() == piv[:k].tolist()
+    assert np.isnan(res.err_probe)
+    L = rng.standard_normal((N, 4)) @ rng.standard_normal((4, n))
+    r2 = oracle_mod.compress_literal(L, 6, np.arange(N), rank_tol=1e-10)
+    assert r2.k_eff == 4
+    assert oracle_mod.error_norms(L, r2.AJ[:, :4], r2.P[:4])["rel_fro"] < 1e-12
