@@ -93,6 +93,14 @@ typedef enum {
 
 typedef enum { SID_TWO_PASS = 0, SID_SINGLE_PASS = 1 } sid_mode;
 
+/* What mgsqr runs on.  GAUSS: the Gaussian sketch W = Psi(:, S) A(S, :)
+ * (Alg. 4; with a coarse set, the sketched form of Alg. 5).  ROWS_LITERAL:
+ * the coarse rows themselves, W_sel = A(S, :), as Alg. 5 writes the
+ * sub-sampled ID; needs a coarse set of at most 4096 rows, two-pass mode and
+ * an F64 or F32 precision; oversample and probe_rows are ignored (no probe
+ * rows: err[0] is NaN); no refinement, no streaming. */
+typedef enum { SID_SEL_GAUSS = 0, SID_SEL_ROWS_LITERAL = 1 } sid_select;
+
 typedef struct {
     int64_t k;                 /* target rank, 1 <= k <= min(n, k + oversample)   */
     int64_t oversample;        /* p >= 0; sketch rows l = k + p (Alg. 4)          */
@@ -112,11 +120,12 @@ typedef struct {
     int32_t refine;            /* 0: none; 1: one refinement pass of P (reads A
                                   once more, sid_compress only)                  */
     sid_sketch_prec refine_prec; /* precision of the refinement sketch          */
+    sid_select select;         /* SID_SEL_GAUSS (default) or SID_SEL_ROWS_LITERAL */
 } sid_params;
 
 /* Fill a parameter block with defaults: oversample 10, seed 0, all rows,
  * two-pass, F32 sketch, probe_rows 10, corange_rows -1, rank_tol 0,
- * sp_rcond 0, refine 0, refine_prec BF16X2.
+ * sp_rcond 0, refine 0, refine_prec BF16X2, select GAUSS.
  * Refinement (refine = 1; the paper stops at the ID): after J and P0 are
  * chosen, A is sketched once more with Psi's selection rows in refine_prec,
  * W' = Psi_sel A, and P0 takes one step of iterative refinement of the

@@ -14,6 +14,7 @@ _LIB = None
 SID_F64, SID_F32 = 0, 1
 PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2, "bf16x2": 3, "fp8": 4}
 MODES = {"two_pass": 0, "single_pass": 1}
+SELECT = {"gauss": 0, "literal": 1}
 _STATUS = {0: "SID_OK", -1: "SID_EINVAL", -2: "SID_ENOMEM", -3: "SID_EDEVICE",
            -4: "SID_ESTATE", -5: "SID_ENONFINITE", -6: "SID_ERANK"}
 
@@ -46,6 +47,7 @@ class _Params(ctypes.Structure):
         ("sp_rcond", ctypes.c_double),
         ("refine", ctypes.c_int32),
         ("refine_prec", ctypes.c_int),
+        ("select", ctypes.c_int),
     ]
 
 
@@ -210,7 +212,7 @@ class RowSet:
 
 
 def _params(k, oversample, seed, coarse, mode, prec, probe_rows, rank_tol, sp_rcond,
-            corange_rows=-1, refine=False, refine_prec="bf16x2") -> _Params:
+            corange_rows=-1, refine=False, refine_prec="bf16x2", select="gauss") -> _Params:
     p = _Params()
     load().sid_params_init(ctypes.byref(p), int(k))
     p.oversample = int(oversample)
@@ -224,6 +226,7 @@ def _params(k, oversample, seed, coarse, mode, prec, probe_rows, rank_tol, sp_rc
     p.sp_rcond = float(sp_rcond)
     p.refine = 1 if refine else 0
     p.refine_prec = PRECISIONS[refine_prec]
+    p.select = SELECT[select]
     return p
 
 
@@ -289,9 +292,10 @@ def compress(A: torch.Tensor, k: int, oversample: int = 10, seed: int = 0,
              probe_rows: int = 10, rank_tol: float = 0.0, sp_rcond: float = 0.0,
              corange_rows: int = -1, want_skeleton: bool = True, ctx: Context | None = None,
              out: Compressed | None = None, refine: bool = False,
-             refine_prec: str = "bf16x2") -> Compressed:
+             refine_prec: str = "bf16x2", select: str = "gauss") -> Compressed:
     """Rank-k column ID of A (N x n, float32/float64 on the GPU); refine=True
-    adds one refinement pass of P on a refine_prec sketch."""
+    adds one refinement pass of P on a refine_prec sketch; select="literal"
+    runs mgsqr on the coarse rows A(S, :) themselves (Alg. 5 as written)."""
     ctx = ctx or default_context(A.device)
     A, lda = _colmajor(A)
     N, n = A.shape
@@ -304,7 +308,7 @@ def compress(A: torch.Tensor, k: int, oversample: int = 10, seed: int = 0,
         keff = torch.empty(1, dtype=torch.int64, device=dev)
         out = Compressed(J, P, AJ, err, keff)
     p = _params(k, oversample, seed, coarse, mode, prec, probe_rows, rank_tol, sp_rcond,
-                corange_rows, refine, refine_prec)
+                corange_rows, refine, refine_prec, select)
     ldaj = out.AJ.stride(1) if out.AJ is not None else 1
     ctx.check(ctx._lib.sid_compress(
         ctx.handle, _ptr(A), _dtype_code(A), N, n, lda, ctypes.byref(p), _ptr(out.J),

@@ -163,6 +163,30 @@ sid_status validate(sid_ctx* ctx, int64_t N, int64_t n, const sid_params* p, Sha
   if (p->refine != 0 && p->refine != 1) return fail(ctx, SID_EINVAL, "refine must be 0 or 1");
   if (p->refine && (p->refine_prec < SID_SK_F64 || p->refine_prec > SID_SK_FP8E4M3))
     return fail(ctx, SID_EINVAL, "unknown refinement precision");
+  if (p->select != SID_SEL_GAUSS && p->select != SID_SEL_ROWS_LITERAL)
+    return fail(ctx, SID_EINVAL, "unknown select");
+  if (p->select == SID_SEL_ROWS_LITERAL) {
+    if (!p->coarse) return fail(ctx, SID_EINVAL, "literal selection needs a coarse row set");
+    if (p->mode != SID_TWO_PASS) return fail(ctx, SID_EINVAL, "literal selection is two-pass");
+    if (p->prec != SID_SK_F64 && p->prec != SID_SK_F32)
+      return fail(ctx, SID_EINVAL, "literal selection reads the data in F64 or F32");
+    if (p->refine) return fail(ctx, SID_EINVAL, "literal selection has no refinement pass");
+    if (p->coarse->ctx != ctx) return fail(ctx, SID_EINVAL, "row set belongs to another context");
+    if (p->coarse->N != N) return fail(ctx, SID_EINVAL, "row set was built for a different N");
+    const int64_t Ns = p->coarse->count;
+    if (Ns > 4096) return fail(ctx, SID_EINVAL, "literal selection takes at most 4096 coarse rows");
+    if (Ns <= p->k) return fail(ctx, SID_EINVAL, "coarse row count must exceed k");
+    sh->N = N;
+    sh->n = n;
+    sh->k = p->k;
+    sh->l = sh->lz = sh->lq = Ns;
+    sh->q = 0;
+    sh->Ns = Ns;
+    sh->nchunks = 1;
+    sh->single = false;
+    sh->prec = p->prec;
+    return SID_OK;
+  }
   const int64_t l = p->k + p->oversample;
   const bool single = p->mode == SID_SINGLE_PASS;
   const int64_t e = single ? (p->corange_rows < 0 ? p->oversample : p->corange_rows) : 0;
@@ -286,6 +310,7 @@ void sid_params_init(sid_params* p, int64_t k) {
   p->sp_rcond = 0.0;
   p->refine = 0;
   p->refine_prec = SID_SK_BF16X2;
+  p->select = SID_SEL_GAUSS;
 }
 
 sid_status sid_create(sid_ctx** out, int device, void* hip_stream) {
@@ -523,9 +548,16 @@ sid_status sid_compress(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N,
   SID_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
   Work w;
   if (reserve(ctx, sh, &w) != SID_OK) return SID_ENOMEM;
-  // (1) sketch pass: W = Psi(:, S) A(S, :) and, single pass, Y = A Omega
-  s = run_sketch(ctx, A, dtype, lda, p, sh, w, w.W, sh.single ? w.Y : nullptr);
-  if (s != SID_OK) return s;
+  if (p->select == SID_SEL_ROWS_LITERAL) {
+    // (1) Alg. 5 as written: mgsqr runs on the coarse rows themselves
+    SID_CHECK(sid::launch_gather_rows(ctx->stream, A, dtype == SID_F64, lda, p->coarse->d_rows,
+                                      sh.Ns, sh.n, p->prec == SID_SK_F32, w.W, sh.Ns),
+              "A(S, :)");
+  } else {
+    // (1) sketch pass: W = Psi(:, S) A(S, :) and, single pass, Y = A Omega
+    s = run_sketch(ctx, A, dtype, lda, p, sh, w, w.W, sh.single ? w.Y : nullptr);
+    if (s != SID_OK) return s;
+  }
   s = factor(ctx, p, sh, w, dtype, A, lda, J, P, ldp, AJ, ldaj, err, k_eff);
   if (s != SID_OK || !p->refine) return s;
   return refine_pass(ctx, A, dtype, lda, p, sh, w, P, ldp);
@@ -872,6 +904,8 @@ sid_status sid_stream_begin(sid_ctx* ctx, sid_dtype dtype, int64_t N, int64_t n_
   if (vs != SID_OK) return vs;
   if (p->refine)
     return fail(ctx, SID_EINVAL, "refinement re-reads A; a stream keeps no columns");
+  if (p->select != SID_SEL_GAUSS)
+    return fail(ctx, SID_EINVAL, "a stream sketches its blocks; literal selection needs all rows");
   SID_NEED_DEVICE(ctx);
   SID_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
   return stream_make(ctx, dtype, N, n_max, p, out);

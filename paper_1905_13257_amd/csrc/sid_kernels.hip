@@ -442,6 +442,19 @@ __global__ void k_gather_cols(const TS* __restrict__ src, int64_t lds, int64_t r
     d[i] = s ? (TD)s[i] : (TD)0;
 }
 
+// rows of the data as FP64 values: W(i, j) = A(rows[i], j) (rounded to
+// single precision first when to_f32)
+template <typename TS>
+__global__ void k_gather_rows(const TS* __restrict__ A, int64_t lda, const int64_t* __restrict__ rows,
+                              int64_t Ns, int64_t n, int to_f32, double* __restrict__ W, int64_t ldw) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < Ns * n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = e / Ns, i = e - j * Ns;
+    const TS a = A[rows[i] + lda * j];
+    W[i + ldw * j] = to_f32 ? (double)(float)a : (double)a;
+  }
+}
+
 // gather rows of a column-major FP64 matrix into a (q x k) block: out(r, t) = W(r0 + r, piv[t])
 __global__ void k_gather_block(const double* __restrict__ W, int lq, int r0, int q,
                                const int64_t* __restrict__ piv, const int64_t* __restrict__ keff_p,
@@ -873,6 +886,20 @@ hipError_t launch_gather_cols(hipStream_t st, const void* src, bool src_f64, int
   else
     hipLaunchKernelGGL((k_gather_cols<float, float>), grid, dim3(256), 0, st, (const float*)src,
                        lds, rows, piv, keff, kcap, (float*)dst, ldd);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(hipStream_t st, const void* A, bool f64, int64_t lda,
+                              const int64_t* rows, int64_t Ns, int64_t n, bool to_f32, double* W,
+                              int64_t ldw) {
+  int64_t b = (Ns * n + 255) / 256;
+  if (b > 4096) b = 4096;
+  if (f64)
+    hipLaunchKernelGGL(k_gather_rows<double>, dim3((unsigned)b), dim3(256), 0, st,
+                       (const double*)A, lda, rows, Ns, n, to_f32 ? 1 : 0, W, ldw);
+  else
+    hipLaunchKernelGGL(k_gather_rows<float>, dim3((unsigned)b), dim3(256), 0, st,
+                       (const float*)A, lda, rows, Ns, n, 0, W, ldw);
   return hipGetLastError();
 }
 

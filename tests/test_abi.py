@@ -197,3 +197,19 @@ def test_refine_validation(vctx):
     assert L.sid_stream_begin(h, 1, 100, 20, ctypes.byref(p), ctypes.byref(out)) == EINVAL
     q = _params(L, 5)
     assert q.refine == 0 and q.refine_prec == 3
+
+
+def test_literal_select_validation(vctx):
+    """Literal (Alg. 5) selection: needs a coarse set, two-pass, F64/F32, at
+    most 4096 coarse rows, no refinement, no stream; unknown select rejected."""
+    L, h = vctx
+    p = _params(L, 5)
+    assert p.select == 0
+    p.select = 1
+    assert L.sid_reserve(h, 100, 20, ctypes.byref(p)) == EINVAL       # no coarse set
+    assert b"coarse" in L.sid_last_error(h)
+    p.select = 7
+    assert L.sid_reserve(h, 100, 20, ctypes.byref(p)) == EINVAL
+    out = ctypes.c_void_p()
+    p.select = 1
+    assert L.sid_stream_begin(h, 1, 100, 20, ctypes.byref(p), ctypes.byref(out)) == EINVAL

@@ -495,3 +495,28 @@ def test_refinement_pass(sid, oracle_mod):
         e1 = sid.error_norms(A, r1.AJ, r1.P)["rel_fro"]
         say("refine", mode, "fp8 error", e0, "refined", e1)
         assert e1 <= e0 * 1.001
+
+
+@pytest.mark.parametrize("Ns_step,dt,prec", [(3, torch.float64, "f64"), (25, torch.float64, "f64"),
+                                             (3, torch.float32, "f32")])
+def test_literal_subsampled_id(sid, oracle_mod, Ns_step, dt, prec):
+    """Alg. 5 as written (mgsqr on the coarse rows A(S, :)): pivots equal the
+    oracle's, P to FP64 roundoff, AJ the exact columns, err[0] NaN."""
+    N, n, k = 5000, 60, 12
+    rng = np.random.default_rng(51)
+    A64 = (rng.standard_normal((N, n)) * np.exp(-np.linspace(0, 5, n))[None, rng.permutation(n)])
+    A64 = A64.astype(np.float32).astype(np.float64)
+    A = to_gpu(A64, dt)
+    S = np.arange(0, N, Ns_step).astype(np.int64)
+    say("literal", Ns_step, prec, S.size)
+    rs = sid.RowSet(S, N)
+    out = sid.compress(A, k, 0, coarse=rs, mode="two_pass", prec=prec, select="literal")
+    torch.cuda.synchronize()
+    ref = oracle_mod.compress_literal(A64, k, S, prec=prec)
+    assert ref.cp.margins.min() > 1e-8
+    assert host(out.J).tolist() == ref.J.tolist()
+    np.testing.assert_allclose(host(out.P), ref.P, atol=1e-9 * np.abs(ref.P).max())
+    assert np.array_equal(host(out.AJ).astype(np.float64), A64[:, ref.J])
+    e = host(out.err)
+    assert np.isnan(e[0])
+    assert abs(e[1] - ref.err_sketch) <= 1e-8 * max(ref.err_sketch, 1e-300)
