@@ -91,7 +91,8 @@ def main() -> int:
     ap.add_argument("--prec", default="bf16x2", choices=["bf16x2", "bf16", "fp8", "f32", "f64"])
     ap.add_argument("--also", default="bf16,fp8",
                     help="further sketch precisions timed beside the main one (comma list, '' for none)")
-    ap.add_argument("--cpu-rows", type=int, default=393216)
+    ap.add_argument("--cpu-rows", type=int, default=1572864,
+                    help="rows of the matrix the oracle baseline compresses (default: all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32-plain run")
     ap.add_argument("--sketch-only", action="store_true",
