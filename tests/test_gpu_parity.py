@@ -520,3 +520,72 @@ def test_literal_subsampled_id(sid, oracle_mod, Ns_step, dt, prec):
     e = host(out.err)
     assert np.isnan(e[0])
     assert abs(e[1] - ref.err_sketch) <= 1e-8 * max(ref.err_sketch, 1e-300)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16x2", "fp8"])
+def test_streaming_pass_edge_shapes(sid, oracle_mod, prec):
+    """The matrix-core pass on degenerate shapes: fewer rows than one panel,
+    one column, k = n, no probe rows, all-zero columns (FP8 tiles with scale
+    1), exact-rank data; W and Y within the per-entry bound and compress
+    equal to the oracle up to its first near-tie."""
+    rng = np.random.default_rng(61)
+    for (N, n, k, p, q) in [(8, 5, 2, 1, 1), (64, 1, 1, 0, 0), (200, 12, 12, 0, 3), (1000, 40, 5, 5, 0),
+                            (65, 129, 9, 4, 2)]:
+        say("edge streaming", prec, N, n, k, p, q)
+        A64 = rng.standard_normal((N, n)).astype(np.float32).astype(np.float64)
+        if n > 3:
+            A64[:, 2] = 0.0
+        A = to_gpu(A64, torch.float32, ld=ld4(N))
+        l = k + p
+        lq = l + p + q
+        W, Y = sid.sketch(A, k, p, seed=3, prec=prec, probe_rows=q, want_y=True)
+        Wo = oracle_mod.sketch_w(A64, None, lq, 3, prec)
+        bound = _absbound(A64, np.arange(N), lq, 3, prec, oracle_mod)
+        assert np.all(np.abs(host(W) - Wo) <= RTOL[prec] * bound + 1e-30)
+        Om = oracle_mod.omega(3, n, l, prec)
+        Yo = oracle_mod.sketch_y(A64, Om, prec)
+        ybound = np.abs(oracle_mod.data_values(A64, prec)) @ np.abs(Om)
+        assert np.all(np.abs(host(Y).astype(np.float64) - Yo) <= RTOL[prec] * ybound + 1e-30)
+        for mode in ("two_pass", "single_pass"):
+            out = sid.compress(A, k, p, seed=3, mode=mode, prec=prec, probe_rows=q)
+            torch.cuda.synchronize()
+            ref = oracle_mod.compress(A64, k, p, seed=3, mode=mode, prec=prec, probe_rows=q)
+            ke = int(host(out.k_eff)[0])
+            assert ke == ref.k_eff
+            tie = next((i for i, m in enumerate(ref.cp.margins) if m <= 1e-3), ref.k_eff)
+            assert host(out.J)[:tie].tolist() == ref.J[:tie].tolist()
+            J = host(out.J)[:ke]
+            assert np.array_equal(host(out.P)[:ke][:, J], np.eye(ke))
+
+
+def test_graph_capture_replay(sid, oracle_mod):
+    """sid_compress captured into a HIP graph (after sid_reserve-style
+    warm-up) and replayed several times, with eager work and host
+    synchronization between replays, reproduces the eager results bit for
+    bit."""
+    A64, _ = c1_matrix(N=4096, n=256, seed=1004)
+    A = to_gpu(A64.astype(np.float32).astype(np.float64), torch.float32)
+    k, p, q = 20, 10, 10
+    stream = torch.cuda.Stream()
+    for mode, prec in [("single_pass", "bf16x2"), ("two_pass", "f32")]:
+        say("graph", mode, prec)
+        with torch.cuda.stream(stream):
+            ctx = sid.Context(stream=stream)
+            eager = sid.compress(A, k, p, seed=2, mode=mode, prec=prec, probe_rows=q, ctx=ctx)
+            out = sid.compress(A, k, p, seed=2, mode=mode, prec=prec, probe_rows=q, ctx=ctx)
+        torch.cuda.synchronize()
+        ref = [host(t).copy() for t in (eager.J, eager.P, eager.AJ, eager.err)]
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            sid.compress(A, k, p, seed=2, mode=mode, prec=prec, probe_rows=q, ctx=ctx, out=out)
+        for rep in range(3):
+            for t in (out.J, out.P, out.AJ, out.err):
+                t.zero_()
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            got = [host(t) for t in (out.J, out.P, out.AJ, out.err)]
+            for a, b in zip(got, ref):
+                assert np.array_equal(a, b), (mode, prec, rep)
+            _ = (A * 2.0).sum().item()  # unrelated eager work between replays
+        ctx.close()
