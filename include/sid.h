@@ -165,8 +165,9 @@ sid_status sid_rowset_create(sid_ctx *ctx, const int64_t *host_rows, int64_t cou
                              int64_t N, sid_rowset **out);
 sid_status sid_rowset_destroy(sid_rowset *rs);
 
-/* Grow the workspace for compress calls of this shape ahead of time.  After
- * it (or after one call of the same shape), sid_compress on the context's
+/* Grow the workspace (and create the internal side stream) for compress
+ * calls of this shape and these parameters ahead of time.  After it (or
+ * after one call of the same shape), sid_compress on the context's
  * stream allocates nothing and synchronizes nothing, so it can be captured
  * into a HIP graph and replayed (the library records no memset nodes; the
  * single-pass side stream joins the capture through events). */

@@ -15,6 +15,7 @@ from __future__ import annotations
 
 from ._native import (  # noqa: F401
     SID_F32, SID_F64, PRECISIONS, MODES, Context, Compressed, RowSet, SidError, Stream,
-    compress, compress_batched, reconstruct, error_norms, fill_gaussian, sketch, library_path,
+    compress, compress_batched, reconstruct, reserve, error_norms, fill_gaussian, sketch,
+    library_path,
     load,
 )

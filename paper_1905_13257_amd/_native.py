@@ -316,6 +316,18 @@ def compress(A: torch.Tensor, k: int, oversample: int = 10, seed: int = 0,
     return out
 
 
+def reserve(N: int, n: int, k: int, oversample: int = 10, mode: str = "two_pass",
+            prec: str = "f32", probe_rows: int = 10, coarse: RowSet | None = None,
+            corange_rows: int = -1, refine: bool = False, refine_prec: str = "bf16x2",
+            select: str = "gauss", ctx: Context | None = None) -> None:
+    """Allocate ahead of time everything a compress of this shape needs
+    (sid_reserve); later compress calls allocate nothing (graph capture)."""
+    ctx = ctx or default_context()
+    p = _params(k, oversample, 0, coarse, mode, prec, probe_rows, 0.0, 0.0, corange_rows,
+                refine, refine_prec, select)
+    ctx.check(ctx._lib.sid_reserve(ctx.handle, N, n, ctypes.byref(p)))
+
+
 def sketch(A: torch.Tensor, k: int, oversample: int = 10, seed: int = 0,
            coarse: RowSet | None = None, prec: str = "f32", probe_rows: int = 10,
            want_y: bool = True, corange_rows: int = -1, ctx: Context | None = None):

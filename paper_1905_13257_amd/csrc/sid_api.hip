@@ -442,7 +442,33 @@ sid_status sid_reserve(sid_ctx* ctx, int64_t N, int64_t n, const sid_params* p) 
   SID_NEED_DEVICE(ctx);
   SID_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
   Work w;
-  return reserve(ctx, sh, &w);
+  if (reserve(ctx, sh, &w) != SID_OK) return SID_ENOMEM;
+  // everything else a compress call of this shape would allocate or create:
+  // the streaming pass's partials and Omega^T, the slab sum of Y, the
+  // refinement buffers and the single-pass side stream
+  const bool bf = sh.prec == SID_SK_BF16 || sh.prec == SID_SK_BF16X2 || sh.prec == SID_SK_FP8E4M3;
+  if (bf && p->select == SID_SEL_GAUSS) {
+    int64_t rpw = 0;
+    const int64_t grid = sid::fused_bf16_grid(sh.N, ctx->num_cu, &rpw);
+    const int64_t slab = sh.n < 512 ? sh.n : 512;
+    if (!ws(ctx, WS_PARTF, sizeof(float) * (size_t)(grid * sh.lq * slab)) ||
+        !ws(ctx, WS_OMT, sizeof(uint16_t) * 128 * 512))
+      return SID_ENOMEM;
+    if (sh.single && sh.n > slab && !ws(ctx, WS_YTMP, sizeof(float) * (size_t)(sh.N * sh.l)))
+      return SID_ENOMEM;
+  }
+  if (p->refine) {
+    const size_t d = sizeof(double);
+    if (!ws(ctx, WS_REF_W, d * (size_t)(sh.l * sh.n)) || !ws(ctx, WS_REF_WJ, d * (size_t)(sh.l * sh.k)) ||
+        !ws(ctx, WS_REF_T, d * (size_t)(sh.l * sh.n)) || !ws(ctx, WS_REF_G, d * (size_t)(sh.k * sh.n)))
+      return SID_ENOMEM;
+  }
+  if (sh.single && !ctx->side) {
+    SID_CHECK(hipStreamCreate(&ctx->side), "side stream");
+    SID_CHECK(hipEventCreateWithFlags(&ctx->side_fork, hipEventDisableTiming), "side event");
+    SID_CHECK(hipEventCreateWithFlags(&ctx->side_join, hipEventDisableTiming), "side event");
+  }
+  return SID_OK;
 }
 
 static sid_status factor(sid_ctx* ctx, const sid_params* p, const Shape& sh, const Work& w,

@@ -559,10 +559,10 @@ def test_streaming_pass_edge_shapes(sid, oracle_mod, prec):
 
 
 def test_graph_capture_replay(sid, oracle_mod):
-    """sid_compress captured into a HIP graph (after sid_reserve-style
-    warm-up) and replayed several times, with eager work and host
-    synchronization between replays, reproduces the eager results bit for
-    bit."""
+    """sid_reserve covers every allocation of a compress call; the call is
+    then captured into a HIP graph and replayed several times, with eager
+    work and host synchronization between replays, and reproduces the eager
+    results bit for bit."""
     A64, _ = c1_matrix(N=4096, n=256, seed=1004)
     A = to_gpu(A64.astype(np.float32).astype(np.float64), torch.float32)
     k, p, q = 20, 10, 10
@@ -571,13 +571,17 @@ def test_graph_capture_replay(sid, oracle_mod):
         say("graph", mode, prec)
         with torch.cuda.stream(stream):
             ctx = sid.Context(stream=stream)
-            eager = sid.compress(A, k, p, seed=2, mode=mode, prec=prec, probe_rows=q, ctx=ctx)
+            sid.reserve(A.shape[0], A.shape[1], k, p, mode=mode, prec=prec, probe_rows=q, ctx=ctx)
+            held = ctx.workspace_bytes()
             out = sid.compress(A, k, p, seed=2, mode=mode, prec=prec, probe_rows=q, ctx=ctx)
+            assert ctx.workspace_bytes() == held       # the reservation covered the call
+            eager = sid.compress(A, k, p, seed=2, mode=mode, prec=prec, probe_rows=q, ctx=ctx)
         torch.cuda.synchronize()
         ref = [host(t).copy() for t in (eager.J, eager.P, eager.AJ, eager.err)]
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, stream=stream):
             sid.compress(A, k, p, seed=2, mode=mode, prec=prec, probe_rows=q, ctx=ctx, out=out)
+        assert ctx.workspace_bytes() == held
         for rep in range(3):
             for t in (out.J, out.P, out.AJ, out.err):
                 t.zero_()
