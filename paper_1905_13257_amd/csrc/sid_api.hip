@@ -19,7 +19,7 @@ namespace {
 enum Slot {
   WS_OMEGA, WS_PART, WS_W, WS_WR, WS_NRM, WS_PIV, WS_R, WS_Q, WS_KEFF, WS_STATS, WS_PD,
   WS_ERR, WS_Y, WS_M, WS_MPR, WS_WJ, WS_PIVM, WS_RM, WS_QM, WS_RKM, WS_C, WS_T, WS_MIX,
-  WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COOP, WS_SYNC, WS_R11, WS_FITPART, WS_YTMP, WS_REF_W, WS_REF_WJ, WS_REF_T, WS_REF_G, WS_COUNT
+  WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COOP, WS_SYNC, WS_R11, WS_FITPART, WS_YTMP, WS_REF_W, WS_REF_WJ, WS_REF_T, WS_REF_G, WS_OMP, WS_COUNT
 };
 
 struct Buf {
@@ -447,12 +447,12 @@ sid_status sid_reserve(sid_ctx* ctx, int64_t N, int64_t n, const sid_params* p) 
   // the streaming pass's partials and Omega^T, the slab sum of Y, the
   // refinement buffers and the single-pass side stream
   const bool bf = sh.prec == SID_SK_BF16 || sh.prec == SID_SK_BF16X2 || sh.prec == SID_SK_FP8E4M3;
-  if (bf && p->select == SID_SEL_GAUSS) {
+  if ((bf || sh.prec == SID_SK_F32) && p->select == SID_SEL_GAUSS) {
     int64_t rpw = 0;
     const int64_t grid = sid::fused_bf16_grid(sh.N, ctx->num_cu, &rpw);
     const int64_t slab = sh.n < 512 ? sh.n : 512;
     if (!ws(ctx, WS_PARTF, sizeof(float) * (size_t)(grid * sh.lq * slab)) ||
-        !ws(ctx, WS_OMT, sizeof(uint16_t) * 128 * 512))
+        !ws(ctx, bf ? WS_OMT : WS_OMP, bf ? sizeof(uint16_t) * 128 * 512 : sizeof(float) * 128 * 512))
       return SID_ENOMEM;
     if (sh.single && sh.n > slab && !ws(ctx, WS_YTMP, sizeof(float) * (size_t)(sh.N * sh.l)))
       return SID_ENOMEM;
@@ -503,13 +503,17 @@ static sid_status run_sketch(sid_ctx* ctx, const void* A, sid_dtype dtype, int64
     return fail(ctx, SID_EINVAL,
                 "the FP8 sketch needs FP32 data with 16-byte aligned columns (lda % 4 == 0), all "
                 "rows (no coarse set), l <= 128 and l + co-range + probe <= 160");
-  if (bf && fused_ok) {
+  const bool f32mfma = sh.prec == SID_SK_F32;
+  if ((bf || f32mfma) && fused_ok) {
     // one streaming pass on the matrix cores (W partials per workgroup, FP32)
     int64_t rpw = 0;
     const int64_t grid = sid::fused_bf16_grid(sh.N, ctx->num_cu, &rpw);
     float* partf = (float*)ws(ctx, WS_PARTF, sizeof(float) * (size_t)(grid * sh.lq * slab));
-    __bf16* omT = (__bf16*)ws(ctx, WS_OMT, sizeof(uint16_t) * 128 * 512);
-    if (!partf || !omT) return SID_ENOMEM;
+    __bf16* omT = nullptr;
+    float* omP = nullptr;
+    if (f32mfma) omP = (float*)ws(ctx, WS_OMP, sizeof(float) * 128 * 512);
+    else omT = (__bf16*)ws(ctx, WS_OMT, sizeof(uint16_t) * 128 * 512);
+    if (!partf || (!omT && !omP)) return SID_ENOMEM;
     float* ytmp = nullptr;
     if (Y && sh.n > slab) {
       ytmp = (float*)ws(ctx, WS_YTMP, sizeof(float) * (size_t)(sh.N * sh.l));
@@ -522,11 +526,18 @@ static sid_status run_sketch(sid_ctx* ctx, const void* A, sid_dtype dtype, int64
       const int64_t nb = sh.n - c0 < slab ? sh.n - c0 : slab;
       float* yd = Y ? (c0 == 0 ? (float*)Y : ytmp) : nullptr;
       int64_t nparts = 0;
-      SID_CHECK(sid::launch_sketch_fused_bf16(st, dmode, (const float*)A + c0 * lda, lda, sh.N,
-                                              (int)nb, (int)sh.lq, (int)sh.l, p->seed,
-                                              w.omega + c0 * sh.l, omT, ctx->num_cu, partf,
-                                              W + c0 * sh.lq, yd, &nparts),
-                "fused sketch pass");
+      if (f32mfma)
+        SID_CHECK(sid::launch_sketch_fused_f32(st, (const float*)A + c0 * lda, lda, sh.N, (int)nb,
+                                               (int)sh.lq, (int)sh.l, p->seed,
+                                               w.omega + c0 * sh.l, omP, ctx->num_cu, partf,
+                                               W + c0 * sh.lq, yd),
+                  "fused FP32 sketch pass");
+      else
+        SID_CHECK(sid::launch_sketch_fused_bf16(st, dmode, (const float*)A + c0 * lda, lda, sh.N,
+                                                (int)nb, (int)sh.lq, (int)sh.l, p->seed,
+                                                w.omega + c0 * sh.l, omT, ctx->num_cu, partf,
+                                                W + c0 * sh.lq, yd, &nparts),
+                  "fused sketch pass");
       if (Y && c0 > 0)
         SID_CHECK(sid::launch_add_inplace(st, false, Y, ytmp, sh.N * sh.l, ctx->num_cu),
                   "Y slab sum");

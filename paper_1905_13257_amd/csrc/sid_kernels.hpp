@@ -66,6 +66,9 @@ hipError_t launch_sketch_fused_bf16(hipStream_t st, int dmode, const float* A, i
                                     int64_t N, int n, int lq, int l, uint64_t seed,
                                     const float* omega, __bf16* omT, int num_cu, float* part,
                                     double* W, float* Y, int64_t* nparts_out);
+hipError_t launch_sketch_fused_f32(hipStream_t st, const float* A, int64_t lda, int64_t N, int n,
+                                   int lq, int l, uint64_t seed, const float* omega, float* omP,
+                                   int num_cu, float* part, double* W, float* Y);
 bool apply_t_mfma_supported(int k, int l, bool y_f64);
 bool cpqr_coop_supported(int m, int nc);
 size_t cpqr_coop_scratch_bytes(int m, int nc);

@@ -369,6 +369,249 @@ __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
   }
 }
 
+// ---------------------------------------------------------------------------
+// The FP32 sketch pass ("FP32 plain": FP32 data, Gaussians and products,
+// FP32 accumulation within a workgroup, FP64 across) on the FP32 matrix
+// instruction v_mfma_f32_16x16x4_f32 (K = 4).  The work layout is the one
+// of the bf16 pass above, with 32-row panels (eight K steps of 4) so that
+// Psi in FP32 fits LDS twice:
+//   A (16 x 4): lane l holds row l%16, k = l/16;  B (4 x 16): col l%16,
+//   k = l/16;  C as above.
+// W: the K order within a panel is permuted so that K step s = 4h + t pairs
+// lane group g with panel row 16h + 4g + t: a lane's two 16-byte loads
+// (rows 16h + 4g .. +3 of its column) are exactly its B operands.  Psi is
+// stored in LDS in slot order 4s + g.
+// Y: the chunk is written to LDS row-major in FP32; the B operand (Omega)
+// comes from a copy of Omega^T whose k index is permuted per chunk so that a
+// lane's 32 values for the chunk's 32 K steps are contiguous
+// (omP[c][128 j + 32 g + s] = Omega(128 j + 4 s + g, c)).
+// ---------------------------------------------------------------------------
+constexpr int F3_PR = 32;                    // rows per panel
+constexpr int F3_KSW = F3_PR / 4;            // K steps of W per panel
+constexpr int F3_KSY = FB_CHUNK / 4;         // K steps of Y per chunk
+constexpr int F3_PROW = F3_PR + 4;           // LDS row stride of Psi (floats)
+constexpr int F3_CROW = FB_CHUNK + 4;        // LDS row stride of a chunk (floats)
+
+// slot of panel row r (r = 16h + 4g + t -> K step s = 4h + t, slot 4s + g)
+__device__ __forceinline__ int f3_slot(int r) {
+  const int h = r >> 4, g = (r >> 2) & 3, t = r & 3;
+  return 4 * (4 * h + t) + g;
+}
+
+__device__ __forceinline__ void gen_psi_f32(float* __restrict__ s_psi, uint64_t seed, int64_t p0,
+                                            int64_t r1, int lq, int i0, int i1, int tid) {
+  asm volatile("" : "+v"(tid));
+#pragma unroll 1
+  for (int w = i0 + tid; w < i1; w += FB_THREADS) {
+    const int kk = w & (F3_PR - 1), g = w / F3_PR;
+    float z[4] = {0.f, 0.f, 0.f, 0.f};
+    if (p0 + kk < r1) gauss4(seed, 1u, (uint64_t)(p0 + kk), (uint32_t)g, z);
+    const int pos = f3_slot(kk);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int m = 4 * g + e;
+      if (m < lq) s_psi[m * F3_PROW + pos] = z[e];
+    }
+  }
+}
+
+template <bool WANTY, int MT, int LT, int NCH>
+__global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_f32(
+    const float* __restrict__ A, int64_t lda, int64_t N, int n, int lq, int l, uint64_t seed,
+    const float* __restrict__ omP /* LT*16 x FB_NPAD, permuted per chunk, zero padded */,
+    int64_t rows_per_wg, float* __restrict__ part /* grid x lq x n */, float* __restrict__ Y) {
+  static_assert(FB_WAVES % LT == 0 || LT % FB_WAVES == 0, "Y tiles split evenly over the waves");
+  static_assert(2 * LT >= FB_WAVES && NCH <= FB_NCH, "tile counts");
+  constexpr int YR = 2 * LT / FB_WAVES;           // Y row tiles per wave (2 per panel)
+  constexpr int MTR = MT < FB_MTR ? MT : FB_MTR;  // W row tiles in registers
+  constexpr int MTX = MT - MTR;                   // W row tiles accumulated in LDS
+  __shared__ __attribute__((aligned(16))) float s_psi[2][MT * 16 * F3_PROW];
+  __shared__ __attribute__((aligned(16))) float s_chk[F3_PR * F3_CROW];
+  __shared__ __attribute__((aligned(16))) float s_wx[MTX > 0 ? MTX * NCH * FB_THREADS * 4 : 4];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
+  int64_t r1 = r0 + rows_per_wg;
+  if (r1 > N) r1 = N;
+  const int lq4 = (lq + 3) >> 2;
+  const int gen_items = F3_PR * lq4;
+
+  for (int e = tid; e < 2 * MT * 16 * F3_PROW; e += FB_THREADS) (&s_psi[0][0])[e] = 0.0f;
+  if constexpr (MTX > 0)
+    for (int e = tid; e < MTX * NCH * FB_THREADS * 4; e += FB_THREADS) s_wx[e] = 0.0f;
+
+  f32x4_t wacc[MTR][NCH];
+#pragma unroll
+  for (int mt = 0; mt < MTR; ++mt)
+#pragma unroll
+    for (int j = 0; j < NCH; ++j) wacc[mt][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  f32x4_t yacc[YR];
+#pragma unroll
+  for (int r = 0; r < YR; ++r) yacc[r] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  const int yc = wave % LT, rt0 = (wave / LT) * YR;
+
+  const int64_t r1f = r0 + ((r1 - r0) / F3_PR) * F3_PR;
+  const int col_w = 16 * wave + lr;
+  typedef const __attribute__((address_space(1))) f32x4_t* gptr4;
+  // a lane's 8 values of its column: v[4h + t] = row 16h + 4lg + t
+  auto load8 = [&](const float* pc, int col, float (&v)[8]) {
+    const float* base = chunk_col(pc, lda, n, col, lg);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const f32x4_t a = __builtin_nontemporal_load((gptr4)(base + 16 * h));
+#pragma unroll
+      for (int t = 0; t < 4; ++t) v[4 * h + t] = a[t];
+    }
+  };
+  auto load8_tail = [&](const float* pc, int col, int rows_left, float (&v)[8]) {
+    typedef const __attribute__((address_space(1))) float* gptr;
+    const gptr base = (gptr)(chunk_col(pc, lda, n, col, lg) - 4 * lg);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r = 16 * h + 4 * lg + t;
+        const bool ok = r < rows_left;
+        const float x = base[ok ? r : rows_left - 1];
+        v[4 * h + t] = ok ? x : 0.0f;
+      }
+  };
+  float v[8];
+  if (r0 < r1f) load8(A + r0, col_w, v);
+  lds_barrier();
+  if (r0 < r1) gen_psi_f32(s_psi[0], seed, r0, r1, lq, 0, gen_items, tid);
+  const uint32_t om_lane = (uint32_t)((yc * 16 + lr) * FB_NPAD + 32 * lg);
+
+  auto panel = [&](auto tail_tag, int64_t p0, int pb) {
+    constexpr bool TAIL = decltype(tail_tag)::value;
+    const int64_t pn = p0 + F3_PR;
+    const int rows = TAIL ? (int)(r1 - p0) : F3_PR;
+    const float* psi = s_psi[pb];
+#pragma unroll
+    for (int j = 0; j < NCH; ++j) {
+      const bool col_ok = col_w + FB_CHUNK * j < n;
+      if constexpr (TAIL) load8_tail(A + p0, col_w + FB_CHUNK * j, rows, v);
+      lds_barrier();
+      // (1) Omega fragments of this chunk (32 K steps)
+      f32x4_t of[F3_KSY / 4];
+      if constexpr (WANTY) {
+        uintptr_t om_addr = (uintptr_t)omP;
+        asm volatile("" : "+s"(om_addr));
+        const gptr4 om = (gptr4)(om_addr + 4u * (om_lane + (uint32_t)(FB_CHUNK * j)));
+#pragma unroll
+        for (int u = 0; u < F3_KSY / 4; ++u) of[u] = om[u];
+      }
+      // (2) B operands of W and the row-major chunk copy for Y
+      float b[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        b[i] = col_ok ? v[i] : 0.0f;
+        if constexpr (WANTY) s_chk[(16 * (i >> 2) + 4 * lg + (i & 3)) * F3_CROW + col_w] = b[i];
+      }
+      // (3) the next chunk's loads
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (!TAIL) {
+        if (j + 1 < NCH) load8(A + p0, col_w + FB_CHUNK * (j + 1), v);
+        else if (pn < r1f) load8(A + pn, col_w, v);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      // (4) W(:, chunk) += Psi(:, panel) A(panel, chunk)
+#pragma unroll
+      for (int s = 0; s < F3_KSW; ++s)
+#pragma unroll
+        for (int mt = 0; mt < MTR; ++mt) {
+          const float a = psi[(mt * 16 + lr) * F3_PROW + 4 * s + lg];
+          wacc[mt][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[s], wacc[mt][j], 0, 0, 0);
+        }
+      if constexpr (MTX > 0) {
+#pragma unroll
+        for (int mx = 0; mx < MTX; ++mx) {
+          f32x4_t* wx = reinterpret_cast<f32x4_t*>(&s_wx[(((mx * NCH + j) * FB_WAVES + wave) * 64 + lane) * 4]);
+          f32x4_t acc = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int s = 0; s < F3_KSW; ++s) {
+            const float a = psi[((MTR + mx) * 16 + lr) * F3_PROW + 4 * s + lg];
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[s], acc, 0, 0, 0);
+          }
+          *wx += acc;
+        }
+      }
+      // (5) slice j of Psi(:, next panel)
+      if (!TAIL && pn < r1)
+        gen_psi_f32(s_psi[pb ^ 1], seed, pn, r1, lq, gen_items * j / NCH, gen_items * (j + 1) / NCH,
+                    tid);
+      lds_barrier();  // chunk buffer complete
+      // (6) Y(panel, this wave's tiles) += A(panel, chunk) Omega(chunk, :)
+      if constexpr (WANTY) {
+#pragma unroll
+        for (int s = 0; s < F3_KSY; ++s) {
+#pragma unroll
+          for (int r = 0; r < YR; ++r) {
+            const float a = s_chk[((rt0 + r) * 16 + lr) * F3_CROW + 4 * s + lg];
+            yacc[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, of[s >> 2][s & 3], yacc[r], 0, 0, 0);
+          }
+        }
+      }
+    }
+    if constexpr (WANTY) {
+      int lg4 = 4 * lg;
+      asm volatile("" : "+v"(lg4));
+      float* yp = Y + p0 * (int64_t)l;
+      const int c = yc * 16 + lr;
+#pragma unroll
+      for (int r = 0; r < YR; ++r) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int rr = (rt0 + r) * 16 + lg4 + t;
+          if (c < l && (!TAIL || rr < rows)) yp[rr * l + c] = yacc[r][t];
+        }
+        yacc[r] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+      }
+    }
+  };
+
+  int pb = 0;
+  int64_t p0 = r0;
+  for (; p0 < r1f; p0 += F3_PR, pb ^= 1) panel(std::false_type{}, p0, pb);
+  if (p0 < r1) panel(std::true_type{}, p0, pb);
+
+  float* dst = part + (int64_t)blockIdx.x * lq * n;
+#pragma unroll
+  for (int j = 0; j < NCH; ++j) {
+    const int col = FB_CHUNK * j + col_w;
+    if (col >= n) continue;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      f32x4_t w4;
+      if (mt < MTR) {
+        w4 = wacc[mt < MTR ? mt : 0][j];
+      } else {
+        w4 = *reinterpret_cast<const f32x4_t*>(
+            &s_wx[((((mt - MTR) * NCH + j) * FB_WAVES + wave) * 64 + lane) * 4]);
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int m = mt * 16 + 4 * lg + t;
+        if (m < lq) dst[m + (int64_t)lq * col] = w4[t];
+      }
+    }
+  }
+}
+
+// Omega^T in FP32, k permuted per 128-column chunk: out[c * FB_NPAD + 128 j + 32 g + s] =
+// Omega(128 j + 4 s + g, c), zero padded
+__global__ void k_omega_p_f32(const float* __restrict__ omega /* n x l row-major */, int n, int l,
+                              int lpad, float* __restrict__ out) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < lpad * FB_NPAD; e += gridDim.x * blockDim.x) {
+    const int c = e / FB_NPAD, q = e - c * FB_NPAD;
+    const int j = q / FB_CHUNK, rem = q - j * FB_CHUNK, g = rem / 32, s = rem - 32 * g;
+    const int k = FB_CHUNK * j + 4 * s + g;
+    out[e] = (c < l && k < n) ? omega[k * l + c] : 0.0f;
+  }
+}
+
 // Omega^T in bfloat16 (FP8 mode: the e4m3 values, exact in bfloat16), zero
 // padded: out[c * FB_NPAD + k] = value of G(seed, 0, k, c)
 __global__ void k_omega_t_bf16(const float* __restrict__ omega /* n x l row-major */, int n, int l,
@@ -394,6 +637,41 @@ __global__ void k_reduce_partials_f32(const float* __restrict__ part, int64_t np
     for (; g < nparts; ++g) s[0] += (double)part[g * count + e];
     out[e] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
   }
+}
+
+hipError_t launch_sketch_fused_f32(hipStream_t st, const float* A, int64_t lda, int64_t N, int n,
+                                   int lq, int l, uint64_t seed, const float* omega, float* omP,
+                                   int num_cu, float* part, double* W, float* Y) {
+  const int lpad = ((l + 63) / 64) * 64;
+  if (Y)
+    hipLaunchKernelGGL(k_omega_p_f32, dim3(256), dim3(256), 0, st, omega, n, l, lpad, omP);
+  int64_t rpw = 0;
+  const int64_t grid = fused_bf16_grid(N, num_cu, &rpw);  // rows per workgroup: a multiple of 64
+  const int mt = (lq + 15) / 16;
+  const int nch = (n + FB_CHUNK - 1) / FB_CHUNK;
+#define SID_F3(WY, MT_, LT_, NCH_)                                                      \
+  hipLaunchKernelGGL((k_sketch_fused_f32<WY, MT_, LT_, NCH_>), dim3((unsigned)grid),   \
+                     dim3(FB_THREADS), 0, st, A, lda, N, n, lq, l, seed, omP, rpw, part, Y)
+#define SID_F3_NCH(WY, MT_, LT_)                   \
+  if (nch <= 1) SID_F3(WY, MT_, LT_, 1);           \
+  else if (nch <= 2) SID_F3(WY, MT_, LT_, 2);      \
+  else SID_F3(WY, MT_, LT_, 4);
+#define SID_F3_MT(WY, LT_)                                 \
+  if (mt <= 4) { SID_F3_NCH(WY, 4, LT_) }                  \
+  else { SID_F3_NCH(WY, 10, LT_) }
+  if (!Y) { SID_F3_MT(false, 8) }
+  else if (lpad <= 64) { SID_F3_MT(true, 4) }
+  else { SID_F3_MT(true, 8) }
+#undef SID_F3_MT
+#undef SID_F3_NCH
+#undef SID_F3
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t count = (int64_t)lq * n;
+  int64_t b = (count + 255) / 256;
+  if (b > 2048) b = 2048;
+  hipLaunchKernelGGL(k_reduce_partials_f32, dim3((unsigned)b), dim3(256), 0, st, part, grid, count, W);
+  return hipGetLastError();
 }
 
 bool fused_bf16_supported(int64_t n, int lq, int l, int64_t lda, const void* A, bool has_rows) {

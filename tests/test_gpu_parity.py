@@ -91,7 +91,7 @@ def test_sketch_parity(sid, oracle_mod, prec, shape):
     assert np.all(yerr <= RTOL[prec] * ybound + 1e-300), (yerr / ybound).max()
 
 
-@pytest.mark.parametrize("prec", ["bf16", "bf16x2", "fp8"])
+@pytest.mark.parametrize("prec", ["bf16", "bf16x2", "fp8", "f32"])
 @pytest.mark.parametrize("shape", [(2597, 500, 100, 20, 10), (49394, 500, 100, 20, 10),
                                    (700, 129, 7, 3, 2), (5000, 300, 60, 10, 5),
                                    (3001, 1100, 30, 10, 5)])
@@ -522,7 +522,7 @@ def test_literal_subsampled_id(sid, oracle_mod, Ns_step, dt, prec):
     assert abs(e[1] - ref.err_sketch) <= 1e-8 * max(ref.err_sketch, 1e-300)
 
 
-@pytest.mark.parametrize("prec", ["bf16", "bf16x2", "fp8"])
+@pytest.mark.parametrize("prec", ["bf16", "bf16x2", "fp8", "f32"])
 def test_streaming_pass_edge_shapes(sid, oracle_mod, prec):
     """The matrix-core pass on degenerate shapes: fewer rows than one panel,
     one column, k = n, no probe rows, all-zero columns (FP8 tiles with scale
