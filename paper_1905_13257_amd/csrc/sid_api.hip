@@ -739,7 +739,8 @@ static sid_status factor(sid_ctx* ctx, const sid_params* p, const Shape& sh, con
                                            ctx->num_cu),
                   "AJ = Y T");
       else if (sid::apply_t_mfma_supported(k, l, yf64))
-        SID_CHECK(sid::launch_apply_t_mfma(st, w.Y, yf64, sh.N, l, w.T, k, AJ, f64, ldaj),
+        SID_CHECK(sid::launch_apply_t_mfma(st, w.Y, yf64, sh.N, l, w.T, k, AJ, f64, ldaj,
+                                           ctx->num_cu),
                   "AJ = Y T");
       else
         SID_CHECK(sid::launch_apply_t(st, w.Y, yf64, sh.N, l, w.T, k, AJ, f64, ldaj), "AJ = Y T");

@@ -83,7 +83,7 @@ hipError_t launch_small_solve(hipStream_t st, const double* RM, int l, const int
                               const int64_t* rM, double* R11, const double* C, int64_t ldc, int kc,
                               double* T);
 hipError_t launch_apply_t_mfma(hipStream_t st, const void* Y, bool y_f64, int64_t N, int l,
-                               const double* Tm, int k, void* AJ, bool aj_f64, int64_t ldaj);
+                               const double* Tm, int k, void* AJ, bool aj_f64, int64_t ldaj, int num_cu);
 bool apply_t_bf16_supported(int k, int l);
 hipError_t launch_apply_t_bf16(hipStream_t st, const float* Y, int64_t N, int l, const double* Tm,
                                int k, void* AJ, bool aj_f64, int64_t ldaj, int num_cu);

@@ -787,13 +787,17 @@ __global__ __launch_bounds__(64 * AT_WAVES) void k_apply_t_mfma(
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lr = lane & 15, lg = lane >> 4;
-  const int64_t row0 = ((int64_t)blockIdx.x * AT_WAVES + wave) * (AT_RT * 16);
+  const bool vec = (l % 4) == 0;
+  // persistent workgroups: T^T is staged once and the row blocks are walked
+  // with a grid stride
+  const int64_t nblk = (N + AT_WAVES * AT_RT * 16 - 1) / (AT_WAVES * AT_RT * 16);
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+  const int64_t row0 = (blk * AT_WAVES + wave) * (AT_RT * 16);
   typename M::acc_t acc[AT_RT][CT];
 #pragma unroll
   for (int r = 0; r < AT_RT; ++r)
 #pragma unroll
     for (int c = 0; c < CT; ++c) acc[r][c] = typename M::acc_t{0, 0, 0, 0};
-  const bool vec = (l % 4) == 0;
   for (int kb = 0; kb < lpad; kb += 16) {
     TE yv[AT_RT][4];
 #pragma unroll
@@ -832,15 +836,18 @@ __global__ __launch_bounds__(64 * AT_WAVES) void k_apply_t_mfma(
         if (m < k) AJ[row + ldaj * m] = (OutT)acc[r][c][t];
       }
   }
+  }
 }
 
 template <typename TE, typename OutT>
 static hipError_t apply_t_dispatch(hipStream_t st, const TE* Y, int64_t N, int l,
-                                   const double* Tm, int k, OutT* AJ, int64_t ldaj) {
+                                   const double* Tm, int k, OutT* AJ, int64_t ldaj, int num_cu) {
   const int ct = (k + 15) / 16;
   const int lpad = (l + 15) & ~15;
   const int64_t rows_per_block = AT_WAVES * AT_RT * 16;
-  const dim3 grid((unsigned)((N + rows_per_block - 1) / rows_per_block));
+  int64_t nblk = (N + rows_per_block - 1) / rows_per_block;
+  if (nblk > (int64_t)num_cu * 4) nblk = (int64_t)num_cu * 4;  // persistent: a few per CU
+  const dim3 grid((unsigned)nblk);
 #define SID_AT(CT_)                                                                        \
   {                                                                                        \
     const size_t shm = sizeof(TE) * (size_t)(CT_) * 16 * (lpad + 1);                       \
@@ -867,13 +874,13 @@ bool apply_t_mfma_supported(int k, int l, bool y_f64) {
 }
 
 hipError_t launch_apply_t_mfma(hipStream_t st, const void* Y, bool y_f64, int64_t N, int l,
-                               const double* Tm, int k, void* AJ, bool aj_f64, int64_t ldaj) {
+                               const double* Tm, int k, void* AJ, bool aj_f64, int64_t ldaj, int num_cu) {
   if (y_f64) {
-    if (aj_f64) return apply_t_dispatch<double, double>(st, (const double*)Y, N, l, Tm, k, (double*)AJ, ldaj);
-    return apply_t_dispatch<double, float>(st, (const double*)Y, N, l, Tm, k, (float*)AJ, ldaj);
+    if (aj_f64) return apply_t_dispatch<double, double>(st, (const double*)Y, N, l, Tm, k, (double*)AJ, ldaj, num_cu);
+    return apply_t_dispatch<double, float>(st, (const double*)Y, N, l, Tm, k, (float*)AJ, ldaj, num_cu);
   }
-  if (aj_f64) return apply_t_dispatch<float, double>(st, (const float*)Y, N, l, Tm, k, (double*)AJ, ldaj);
-  return apply_t_dispatch<float, float>(st, (const float*)Y, N, l, Tm, k, (float*)AJ, ldaj);
+  if (aj_f64) return apply_t_dispatch<float, double>(st, (const float*)Y, N, l, Tm, k, (double*)AJ, ldaj, num_cu);
+  return apply_t_dispatch<float, float>(st, (const float*)Y, N, l, Tm, k, (float*)AJ, ldaj, num_cu);
 }
 
 
