@@ -5,7 +5,8 @@
 // mgsqr is a chain of k dependent steps (argmax of the residual column norms,
 // normalize the pivot, project it out of every other column), so its cost is
 // latency, not flops.  Here the residual matrix stays in registers, spread
-// over G cooperating workgroups (64 columns each, 4 threads per column), and
+// over G cooperating workgroups (128 columns each with 2 threads per column
+// for up to 128 rows, else 64 columns with 4 threads per column), and
 // every step crosses exactly one device-wide barrier:
 //   1. each workgroup finds its best live column (ties: smallest index),
 //   2. publishes (norm^2, index, residual column) into a double-buffered slot,
@@ -23,10 +24,12 @@
 namespace sid {
 
 constexpr int CQ_THREADS = 256;
-constexpr int CQ_TPC = 4;                    // threads per column
-constexpr int CQ_CPW = CQ_THREADS / CQ_TPC;  // columns per workgroup
+// threads per column TPC (template): 2 for m <= 128 (fewer workgroups take
+// part in each step's synchronization), else 4; columns per workgroup
+// CQ_THREADS / TPC
+constexpr int CQ_MINCPW = CQ_THREADS / 4;    // fewest columns per workgroup
 constexpr unsigned CQ_SPIN_LIMIT = 1u << 22; // bounded wait (~0.1 s); never reached when co-resident
-constexpr int CQ_MSTRIDE = 256;              // published column slot (rows, >= CQ_TPC * RPT)
+constexpr int CQ_MSTRIDE = 256;              // published column slot (rows, >= TPC * RPT)
 
 __global__ void k_zero_u32(unsigned int* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -62,14 +65,16 @@ __device__ __forceinline__ bool grid_barrier(unsigned int* bar, unsigned target)
   return ok;
 }
 
-template <int RPT>
+template <int TPC, int RPT>
 __global__ __launch_bounds__(CQ_THREADS) void k_cpqr_coop(
     const double* __restrict__ X, int64_t ldx, int m, int nc, int kmax, double rank_tol, int G,
     int stride_blk, double* __restrict__ pub_v, int* __restrict__ pub_j,
     double* __restrict__ pub_col, double* __restrict__ red, unsigned int* __restrict__ bar,
     unsigned int* __restrict__ fail, int64_t* __restrict__ piv, double* __restrict__ R,
     double* __restrict__ Q, int64_t* __restrict__ keff, double* __restrict__ stats) {
-  static_assert(CQ_TPC * RPT <= CQ_MSTRIDE, "published column slot");
+  static_assert(TPC * RPT <= CQ_MSTRIDE, "published column slot");
+  constexpr int CQ_TPC = TPC;
+  constexpr int CQ_CPW = CQ_THREADS / TPC;
   if (blockIdx.x % stride_blk) return;
   const int g = blockIdx.x / stride_blk;
   if (g >= G) return;
@@ -97,8 +102,8 @@ __global__ __launch_bounds__(CQ_THREADS) void k_cpqr_coop(
     ps = fma(w[i], w[i], ps);
   }
   double nrm = ps;
-  nrm += __shfl_xor(nrm, 1, 64);
-  nrm += __shfl_xor(nrm, 2, 64);
+#pragma unroll
+  for (int o = 1; o < CQ_TPC; o <<= 1) nrm += __shfl_xor(nrm, o, 64);
   const double tot_local = (seg == 0 && mine) ? nrm : 0.0;
   bool alive = mine;
   bool ok = true;
@@ -175,8 +180,8 @@ __global__ __launch_bounds__(CQ_THREADS) void k_cpqr_coop(
     double d = 0.0;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) d = fma(s_q[seg + CQ_TPC * i], w[i], d);
-    d += __shfl_xor(d, 1, 64);
-    d += __shfl_xor(d, 2, 64);
+#pragma unroll
+    for (int o = 1; o < CQ_TPC; o <<= 1) d += __shfl_xor(d, o, 64);
     if (mine && j == p) {
       alive = false;
 #pragma unroll
@@ -195,8 +200,8 @@ __global__ __launch_bounds__(CQ_THREADS) void k_cpqr_coop(
       if (seg == 0) R[(int64_t)k * nc + j] = 0.0;
     }
     nrm = ps;
-    nrm += __shfl_xor(nrm, 1, 64);
-    nrm += __shfl_xor(nrm, 2, 64);
+#pragma unroll
+    for (int o = 1; o < CQ_TPC; o <<= 1) nrm += __shfl_xor(nrm, o, 64);
   }
 
   // statistics: final residual energy of live columns and ||X||_F^2
@@ -410,10 +415,15 @@ __global__ void k_mark_failure(const unsigned int* fail, int64_t* keff) {
   if (threadIdx.x == 0 && blockIdx.x == 0 && *fail) *keff = -1;
 }
 
-bool cpqr_coop_supported(int m, int nc) { return m <= 256 && nc <= 64 * CQ_CPW && nc >= 1; }
+bool cpqr_coop_supported(int m, int nc) { return m <= 256 && nc <= 64 * CQ_MINCPW && nc >= 1; }
+
+static int coop_tpc(int m, int nc) {
+  const int cpw2 = CQ_THREADS / 2;
+  return (m <= 128 && (nc + cpw2 - 1) / cpw2 <= 64) ? 2 : 4;
+}
 
 size_t cpqr_coop_scratch_bytes(int m, int nc) {
-  const int G = (nc + CQ_CPW - 1) / CQ_CPW;
+  const int G = (nc + CQ_MINCPW - 1) / CQ_MINCPW;  // the most workgroups either layout uses
   return sizeof(double) * (size_t)(2 * G + 2 * G * CQ_MSTRIDE + 2 * G) +
          sizeof(int) * (size_t)(2 * G) + 64;
 }
@@ -422,7 +432,9 @@ hipError_t launch_cpqr_coop(hipStream_t st, const double* X, int64_t ldx, int m,
                             double rank_tol, void* scratch, unsigned int* sync2, int64_t* piv,
                             double* R, double* Q, int64_t* keff, double* stats,
                             bool cooperative) {
-  const int G = (nc + CQ_CPW - 1) / CQ_CPW;
+  const int tpc = coop_tpc(m, nc);
+  const int cpw = CQ_THREADS / tpc;
+  const int G = (nc + cpw - 1) / cpw;
   double* pub_v = (double*)scratch;
   double* pub_col = pub_v + 2 * G;
   double* red = pub_col + (size_t)2 * G * CQ_MSTRIDE;
@@ -436,12 +448,18 @@ hipError_t launch_cpqr_coop(hipStream_t st, const double* X, int64_t ldx, int m,
                   (void*)&G, (void*)&stride, (void*)&pub_v, (void*)&pub_j, (void*)&pub_col,
                   (void*)&red, (void*)&bar, (void*)&fail, (void*)&piv, (void*)&R, (void*)&Q,
                   (void*)&keff, (void*)&stats};
-  const int rpt = (m + CQ_TPC - 1) / CQ_TPC;
-  const void* kern = rpt <= 8    ? (const void*)k_cpqr_coop<8>
-                     : rpt <= 16 ? (const void*)k_cpqr_coop<16>
-                     : rpt <= 32 ? (const void*)k_cpqr_coop<32>
-                     : rpt <= 48 ? (const void*)k_cpqr_coop<48>
-                                 : (const void*)k_cpqr_coop<64>;
+  const int rpt = (m + tpc - 1) / tpc;
+  const void* kern =
+      tpc == 2 ? (rpt <= 8    ? (const void*)k_cpqr_coop<2, 8>
+                  : rpt <= 16 ? (const void*)k_cpqr_coop<2, 16>
+                  : rpt <= 32 ? (const void*)k_cpqr_coop<2, 32>
+                  : rpt <= 48 ? (const void*)k_cpqr_coop<2, 48>
+                              : (const void*)k_cpqr_coop<2, 64>)
+               : (rpt <= 8    ? (const void*)k_cpqr_coop<4, 8>
+                  : rpt <= 16 ? (const void*)k_cpqr_coop<4, 16>
+                  : rpt <= 32 ? (const void*)k_cpqr_coop<4, 32>
+                  : rpt <= 48 ? (const void*)k_cpqr_coop<4, 48>
+                              : (const void*)k_cpqr_coop<4, 64>);
   // The G workgroups must be resident together.  A cooperative launch
   // guarantees it; a plain launch of at most 64 workgroups of 256 threads
   // gets it on an otherwise idle device, and the bounded wait turns a
