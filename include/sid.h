@@ -78,9 +78,10 @@ typedef enum { SID_F64 = 0, SID_F32 = 1 } sid_dtype;
  *           s = 2^(E - 7) per tile of 64 consecutive rows (counted from row
  *           0 of A) and column, E = floor(log2 max|a|) over the tile clamped
  *           to [-100, 120] (s = 1 for a zero tile); exact products, FP32
- *           accumulation.  Needs FP32 data with lda % 4 == 0 and a 16-byte
- *           aligned A, all rows (no coarse set), l <= 128 and
- *           l + co-range + probe rows <= 160; otherwise SID_EINVAL.
+ *           accumulation.  FP32 data with lda % 4 == 0, a 16-byte aligned A,
+ *           all rows, l <= 128 and l + co-range + probe rows <= 160 take the
+ *           streaming matrix-core pass; other inputs are quantized by one
+ *           more pass into an N x n FP32 workspace copy first.
  * The small factorizations after the pass are always FP64.  The paper names
  * no low-precision format; these are this library's. */
 typedef enum {

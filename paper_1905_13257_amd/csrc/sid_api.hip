@@ -19,7 +19,7 @@ namespace {
 enum Slot {
   WS_OMEGA, WS_PART, WS_W, WS_WR, WS_NRM, WS_PIV, WS_R, WS_Q, WS_KEFF, WS_STATS, WS_PD,
   WS_ERR, WS_Y, WS_M, WS_MPR, WS_WJ, WS_PIVM, WS_RM, WS_QM, WS_RKM, WS_C, WS_T, WS_MIX,
-  WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COOP, WS_SYNC, WS_R11, WS_FITPART, WS_YTMP, WS_REF_W, WS_REF_WJ, WS_REF_T, WS_REF_G, WS_OMP, WS_COUNT
+  WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COOP, WS_SYNC, WS_R11, WS_FITPART, WS_YTMP, WS_REF_W, WS_REF_WJ, WS_REF_T, WS_REF_G, WS_OMP, WS_A8, WS_COUNT
 };
 
 struct Buf {
@@ -499,10 +499,18 @@ static sid_status run_sketch(sid_ctx* ctx, const void* A, sid_dtype dtype, int64
   const bool fused_ok =
       dtype == SID_F32 &&
       sid::fused_bf16_supported(slab, (int)sh.lq, (int)sh.l, lda, A, rows != nullptr);
-  if (sh.prec == SID_SK_FP8E4M3 && !fused_ok)
-    return fail(ctx, SID_EINVAL,
-                "the FP8 sketch needs FP32 data with 16-byte aligned columns (lda % 4 == 0), all "
-                "rows (no coarse set), l <= 128 and l + co-range + probe <= 160");
+  if (sh.prec == SID_SK_FP8E4M3 && !fused_ok) {
+    // general kernels: the e4m3 data values are formed first (one more pass
+    // over A and an N x n FP32 copy in the workspace)
+    float* a8 = (float*)ws(ctx, WS_A8, sizeof(float) * (size_t)(sh.N * sh.n));
+    if (!a8) return SID_ENOMEM;
+    SID_CHECK(sid::launch_fp8_quantize(st, A, dtype == SID_F64, lda, sh.N, sh.n, a8, sh.N),
+              "FP8 data values");
+    SID_CHECK(sid::launch_sketch(st, sh.prec, false, a8, sh.N, sh.N, sh.n, rows, sh.Ns, (int)sh.lq,
+                                 p->seed, sh.nchunks, w.part, W, w.omega, (int)sh.l, Y),
+              "sketch pass");
+    return SID_OK;
+  }
   const bool f32mfma = sh.prec == SID_SK_F32;
   if ((bf || f32mfma) && fused_ok) {
     // one streaming pass on the matrix cores (W partials per workgroup, FP32)

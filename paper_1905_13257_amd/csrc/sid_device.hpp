@@ -175,6 +175,7 @@ __device__ __forceinline__ T data_value(In a) {
   } else {
     const float f = (float)a;
     if constexpr (PREC == P_F32) return (T)f;
+    else if constexpr (PREC == P_FP8) return (T)f;  // the general kernels get pre-quantized data
     else if constexpr (PREC == P_BF16) return (T)bf16_value(f);
     else {
       const float hi = bf16_value(f);

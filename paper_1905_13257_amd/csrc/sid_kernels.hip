@@ -698,6 +698,7 @@ hipError_t launch_sketch(hipStream_t st, int prec, bool a_is_f64, const void* A,
     case P_F32: SID_DISPATCH(P_F32); break;
     case P_BF16: SID_DISPATCH(P_BF16); break;
     case P_BF16X2: SID_DISPATCH(P_BF16X2); break;
+    case P_FP8: SID_DISPATCH(P_FP8); break;  // A holds the e4m3 values (launch_fp8_quantize)
     default: return hipErrorInvalidValue;
   }
 #undef SID_DISPATCH
@@ -865,6 +866,33 @@ hipError_t launch_refine_store(hipStream_t st, double* Pd, const double* dP, int
     hipLaunchKernelGGL(k_refine_store<double>, dim3(b), dim3(256), 0, st, Pd, dP, k, n, (double*)P, ldp);
   else
     hipLaunchKernelGGL(k_refine_store<float>, dim3(b), dim3(256), 0, st, Pd, dP, k, n, (float*)P, ldp);
+  return hipGetLastError();
+}
+
+// FP8 data values for the general sketch kernels: one block of 64 threads
+// per (64-row tile, column); out = s e4m3(a / s) with the tile's power-of-two
+// scale (the same values the streaming pass forms in registers)
+template <typename In>
+__global__ __launch_bounds__(64) void k_fp8_quantize(const In* __restrict__ A, int64_t lda, int64_t N,
+                                                     float* __restrict__ out, int64_t ldo) {
+  const int64_t r = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  const int64_t j = blockIdx.y;
+  const float a = r < N ? (float)A[r + lda * j] : 0.0f;
+  float amax = fabsf(a);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+  float inv;
+  const float sc = fp8_tile_scale(amax, inv);
+  if (r < N) out[r + ldo * j] = e4m3_value(a * inv) * sc;
+}
+
+hipError_t launch_fp8_quantize(hipStream_t st, const void* A, bool f64, int64_t lda, int64_t N,
+                               int64_t n, float* out, int64_t ldo) {
+  const dim3 grid((unsigned)((N + 63) / 64), (unsigned)n);
+  if (f64)
+    hipLaunchKernelGGL(k_fp8_quantize<double>, grid, dim3(64), 0, st, (const double*)A, lda, N, out, ldo);
+  else
+    hipLaunchKernelGGL(k_fp8_quantize<float>, grid, dim3(64), 0, st, (const float*)A, lda, N, out, ldo);
   return hipGetLastError();
 }
 

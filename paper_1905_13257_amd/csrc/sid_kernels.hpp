@@ -38,6 +38,8 @@ hipError_t launch_gather_r11(hipStream_t st, const double* R, int nc, const int6
 hipError_t launch_gather_cols(hipStream_t st, const void* src, bool src_f64, int64_t lds,
                               int64_t rows, const int64_t* piv, const int64_t* keff, int kcap,
                               void* dst, bool dst_f64, int64_t ldd);
+hipError_t launch_fp8_quantize(hipStream_t st, const void* A, bool f64, int64_t lda, int64_t N,
+                               int64_t n, float* out, int64_t ldo);
 hipError_t launch_gather_rows(hipStream_t st, const void* A, bool f64, int64_t lda,
                               const int64_t* rows, int64_t Ns, int64_t n, bool to_f32, double* W,
                               int64_t ldw);

@@ -326,20 +326,42 @@ def test_c2_full_size_sampled(sid, oracle_mod):
     assert full["rel_fro"] < 1e-2 and eo["rel_fro"] < 1e-2
 
 
-def test_fp8_requirements_rejected(sid):
-    """The FP8 sketch runs only on the streaming pass: an unpadded leading
-    dimension that is not a multiple of 4, FP64 data or a coarse row set are
-    rejected with SID_EINVAL and a message, before any work."""
+def test_fp8_general_path(sid, oracle_mod):
+    """FP8 where the streaming pass does not apply (an unpadded leading
+    dimension that is not a multiple of 4, FP64 data, a coarse row set, and
+    l = 180 > 128 as in the streaming FP8 workload): the e4m3 data values
+    are formed by a quantizing pass and the general kernels sketch them;
+    W and Y within the per-entry bound of the oracle, and compress runs."""
     rng = np.random.default_rng(8)
-    A64 = rng.standard_normal((333, 20))
-    for A, coarse in [(to_gpu(A64, torch.float32), None), (to_gpu(A64, torch.float64, ld=336), None),
-                      (to_gpu(A64, torch.float32, ld=336), sid.RowSet(np.arange(0, 333, 3), 333))]:
-        with pytest.raises(sid.SidError) as ei:
-            sid.compress(A, 5, 5, prec="fp8", coarse=coarse)
-        assert ei.value.status == -1 and "FP8" in str(ei.value)
-    out = sid.compress(to_gpu(A64, torch.float32, ld=336), 5, 5, prec="fp8", mode="single_pass")
-    assert int(host(out.k_eff)[0]) == 5
-
+    cases = []
+    A64 = (rng.standard_normal((333, 20)) * np.exp(rng.uniform(-3, 3, 20))).astype(np.float32).astype(np.float64)
+    cases.append(("lda333", A64, to_gpu(A64, torch.float32), None, 5, 5, 3))
+    cases.append(("f64", A64, to_gpu(A64, torch.float64, ld=336), None, 5, 5, 3))
+    S = np.arange(0, 333, 3).astype(np.int64)
+    cases.append(("coarse", A64, to_gpu(A64, torch.float32, ld=336), S, 5, 5, 3))
+    B64 = rng.standard_normal((4096, 300)).astype(np.float32).astype(np.float64)
+    cases.append(("l180", B64, to_gpu(B64, torch.float32), None, 150, 30, 10))
+    for name, X64, X, rows, k, p, q in cases:
+        say("fp8 general", name)
+        rs = sid.RowSet(rows, X64.shape[0]) if rows is not None else None
+        W, Y = sid.sketch(X, k, p, seed=6, prec="fp8", probe_rows=q, coarse=rs, want_y=True)
+        l = k + p
+        lq = l + p + q
+        Wo = oracle_mod.sketch_w(X64, rows, lq, 6, "fp8")
+        rr = np.arange(X64.shape[0]) if rows is None else rows
+        Psi = oracle_mod.psi(6, rr, lq, "fp8")
+        bound = np.abs(Psi) @ np.abs(oracle_mod.data_values(X64, "fp8")[rr])
+        assert np.all(np.abs(host(W) - Wo) <= RTOL["fp8"] * bound + 1e-30), name
+        Om = oracle_mod.omega(6, X64.shape[1], l, "fp8")
+        Yo = oracle_mod.sketch_y(X64, Om, "fp8")
+        yb = np.abs(oracle_mod.data_values(X64, "fp8")) @ np.abs(Om)
+        assert np.all(np.abs(host(Y).astype(np.float64) - Yo) <= RTOL["fp8"] * yb + 1e-30), name
+        mode = "two_pass" if rows is not None else "single_pass"
+        out = sid.compress(X, k, p, seed=6, prec="fp8", probe_rows=q, coarse=rs, mode=mode)
+        torch.cuda.synchronize()
+        ref = oracle_mod.compress(X64, k, p, seed=6, prec="fp8", probe_rows=q, coarse_rows=rows, mode=mode)
+        ist = next((i for i, m in enumerate(ref.cp.margins) if m <= 1e-3), k)
+        assert host(out.J)[:ist].tolist() == ref.J[:ist].tolist(), name
 
 def _blocks(n, widths):
     c0, out, i = 0, [], 0
