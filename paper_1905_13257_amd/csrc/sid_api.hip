@@ -449,7 +449,7 @@ sid_status sid_reserve(sid_ctx* ctx, int64_t N, int64_t n, const sid_params* p) 
   const bool bf = sh.prec == SID_SK_BF16 || sh.prec == SID_SK_BF16X2 || sh.prec == SID_SK_FP8E4M3;
   if ((bf || sh.prec == SID_SK_F32) && p->select == SID_SEL_GAUSS) {
     int64_t rpw = 0;
-    const int64_t grid = sid::fused_bf16_grid(sh.N, ctx->num_cu, &rpw);
+    const int64_t grid = sid::fused_bf16_grid(sh.N, ctx->num_cu, &rpw);  // N >= Ns: the larger
     const int64_t slab = sh.n < 512 ? sh.n : 512;
     if (!ws(ctx, WS_PARTF, sizeof(float) * (size_t)(grid * sh.lq * slab)) ||
         !ws(ctx, bf ? WS_OMT : WS_OMP, bf ? sizeof(uint16_t) * 128 * 512 : sizeof(float) * 128 * 512))
@@ -496,8 +496,11 @@ static sid_status run_sketch(sid_ctx* ctx, const void* A, sid_dtype dtype, int64
   // go through it in column slabs (W's columns are independent, Y sums the
   // slabs' contributions)
   const int64_t slab = sh.n < 512 ? sh.n : 512;
+  // a coarse row list runs on the streaming pass for the bf16 forms of the
+  // two-pass (W only) sketch
+  const bool rows_ok = !rows || (!Y && (sh.prec == SID_SK_BF16 || sh.prec == SID_SK_BF16X2));
   const bool fused_ok =
-      dtype == SID_F32 &&
+      dtype == SID_F32 && rows_ok &&
       sid::fused_bf16_supported(slab, (int)sh.lq, (int)sh.l, lda, A, rows != nullptr);
   if (sh.prec == SID_SK_FP8E4M3 && !fused_ok) {
     // general kernels: the e4m3 data values are formed first (one more pass
@@ -515,7 +518,7 @@ static sid_status run_sketch(sid_ctx* ctx, const void* A, sid_dtype dtype, int64
   if ((bf || f32mfma) && fused_ok) {
     // one streaming pass on the matrix cores (W partials per workgroup, FP32)
     int64_t rpw = 0;
-    const int64_t grid = sid::fused_bf16_grid(sh.N, ctx->num_cu, &rpw);
+    const int64_t grid = sid::fused_bf16_grid(sh.Ns, ctx->num_cu, &rpw);
     float* partf = (float*)ws(ctx, WS_PARTF, sizeof(float) * (size_t)(grid * sh.lq * slab));
     __bf16* omT = nullptr;
     float* omP = nullptr;
@@ -541,10 +544,10 @@ static sid_status run_sketch(sid_ctx* ctx, const void* A, sid_dtype dtype, int64
                                                W + c0 * sh.lq, yd),
                   "fused FP32 sketch pass");
       else
-        SID_CHECK(sid::launch_sketch_fused_bf16(st, dmode, (const float*)A + c0 * lda, lda, sh.N,
+        SID_CHECK(sid::launch_sketch_fused_bf16(st, dmode, (const float*)A + c0 * lda, lda, sh.Ns,
                                                 (int)nb, (int)sh.lq, (int)sh.l, p->seed,
                                                 w.omega + c0 * sh.l, omT, ctx->num_cu, partf,
-                                                W + c0 * sh.lq, yd, &nparts),
+                                                W + c0 * sh.lq, yd, &nparts, rows),
                   "fused sketch pass");
       if (Y && c0 > 0)
         SID_CHECK(sid::launch_add_inplace(st, false, Y, ytmp, sh.N * sh.l, ctx->num_cu),

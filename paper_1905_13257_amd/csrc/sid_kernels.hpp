@@ -67,7 +67,8 @@ int64_t fused_bf16_grid(int64_t N, int num_cu, int64_t* rows_per_wg);
 hipError_t launch_sketch_fused_bf16(hipStream_t st, int dmode, const float* A, int64_t lda,
                                     int64_t N, int n, int lq, int l, uint64_t seed,
                                     const float* omega, __bf16* omT, int num_cu, float* part,
-                                    double* W, float* Y, int64_t* nparts_out);
+                                    double* W, float* Y, int64_t* nparts_out,
+                                    const int64_t* rows = nullptr);
 hipError_t launch_sketch_fused_f32(hipStream_t st, const float* A, int64_t lda, int64_t N, int n,
                                    int lq, int l, uint64_t seed, const float* omega, float* omP,
                                    int num_cu, float* part, double* W, float* Y);

@@ -115,11 +115,33 @@ __device__ __forceinline__ void load_chunk_tail(const float* __restrict__ pc, in
     }
 }
 
+// Chunk loads through a row list (coarse rows S, Alg. 5): slot 4h + t of the
+// lane is row sr[16h + 4lg + t] of A; rows at or past rows_left read the last
+// listed row and are zeroed.
+__device__ __forceinline__ void load_chunk_rows(const float* __restrict__ A, int64_t lda, int n,
+                                                int col, const int64_t* sr, int rows_left, int lg,
+                                                float (&v)[16]) {
+  typedef const __attribute__((address_space(1))) float* gptr;
+  int colc = col < n ? col : n - 1;
+  asm volatile("" : "+v"(colc));
+  const gptr base = (gptr)(A + (int64_t)colc * lda);
+#pragma unroll
+  for (int h = 0; h < 4; ++h)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int r = 16 * h + 4 * lg + t;
+      const bool ok = r < rows_left;
+      const float x = base[sr[ok ? r : rows_left - 1]];
+      v[4 * h + t] = ok ? x : 0.0f;
+    }
+}
+
 // Items [i0, i1) of Psi(0:lq, panel p0): item w covers panel row w % 64 and
 // rows 4*(w/64) .. +3 of Psi.  Written in operand-slot order.
 template <bool FP8>
 __device__ __forceinline__ void gen_psi(__bf16* __restrict__ s_psi, uint64_t seed, int64_t p0,
-                                        int64_t r1, int lq, int i0, int i1, int tid) {
+                                        int64_t r1, int lq, int i0, int i1, int tid,
+                                        const int64_t* sr = nullptr) {
   // opaque thread index: the start items of the slices would otherwise be
   // hoisted out of the panel loop and pin registers
   asm volatile("" : "+v"(tid));
@@ -127,7 +149,8 @@ __device__ __forceinline__ void gen_psi(__bf16* __restrict__ s_psi, uint64_t see
   for (int w = i0 + tid; w < i1; w += FB_THREADS) {
     const int kk = w & (FB_PR - 1), g = w / FB_PR;
     float z[4] = {0.f, 0.f, 0.f, 0.f};
-    if (p0 + kk < r1) gauss4(seed, 1u, (uint64_t)(p0 + kk), (uint32_t)g, z);
+    // Psi is keyed by the global row of A (the coarse row list when given)
+    if (p0 + kk < r1) gauss4(seed, 1u, (uint64_t)(sr ? sr[kk] : p0 + kk), (uint32_t)g, z);
     const int pos = row_slot(kk);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -144,11 +167,15 @@ __device__ __forceinline__ void gen_psi(__bf16* __restrict__ s_psi, uint64_t see
 // NCH: chunks of 128 columns per panel (n <= 128*NCH); WANTY: form Y.
 // Every count that shapes the register state is a template argument, so the
 // chunk loop unrolls into straight-line code with no merges of accumulators.
-template <int DM, bool WANTY, int MT, int LT, int NCH>
+// ROWS: W = Psi(:, S) A(S, :) over the coarse row list `rows` (N = |S|; two
+// pass only, no Y); the list of each panel is staged in LDS.
+template <int DM, bool WANTY, int MT, int LT, int NCH, bool ROWS = false>
 __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
     const float* __restrict__ A, int64_t lda, int64_t N, int n, int lq, int l, uint64_t seed,
     const __bf16* __restrict__ omT /* LT*16 x FB_NPAD, k contiguous, zero padded */,
-    int64_t rows_per_wg, float* __restrict__ part /* grid x lq x n */, float* __restrict__ Y) {
+    int64_t rows_per_wg, float* __restrict__ part /* grid x lq x n */, float* __restrict__ Y,
+    const int64_t* __restrict__ rows = nullptr) {
+  static_assert(!(ROWS && WANTY), "a row list sketches W only");
   static_assert(FB_WAVES % LT == 0 || LT % FB_WAVES == 0, "Y tiles split evenly over the waves");
   static_assert(4 * LT >= FB_WAVES && NCH <= FB_NCH, "tile counts");
   // Y tiles of a panel: 4 row tiles x LT column tiles; wave w owns column
@@ -163,6 +190,7 @@ __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
   __shared__ __attribute__((aligned(16))) __bf16 s_chk[NH][FB_PR * FB_CROW];
   // W rows 16 MTR .. 16 MT - 1, in C-fragment order: [mtx][chunk][wave][lane][4]
   __shared__ __attribute__((aligned(16))) float s_wx[MTX > 0 ? MTX * NCH * FB_THREADS * 4 : 4];
+  __shared__ int64_t s_rows[2][ROWS ? FB_PR : 1];  // row lists of this and the next panel
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -172,6 +200,15 @@ __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
   if (r1 > N) r1 = N;
   const int lq4 = (lq + 3) >> 2;
   const int gen_items = FB_PR * lq4;
+  // wave 0 stages the row list of the panel starting at q0 (clamped to r1)
+  auto stage_rows = [&](int64_t q0, int buf) {
+    if constexpr (ROWS) {
+      if (tid < FB_PR && q0 < r1) {
+        const int64_t q = q0 + tid < r1 ? q0 + tid : r1 - 1;
+        s_rows[buf][tid] = rows[q];
+      }
+    }
+  };
 
   // Psi rows >= lq stay zero for the whole kernel; the LDS part of W starts
   // at zero
@@ -193,9 +230,16 @@ __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
   const int64_t r1f = r0 + ((r1 - r0) / FB_PR) * FB_PR;
   const int col_w = 16 * wave + lr;  // this lane's column within a chunk
   float v[16];                       // this wave's slice of the chunk in flight
-  if (r0 < r1f) load_chunk(A + r0, lda, n, col_w, lg, v);
-  lds_barrier();  // zeroed Psi visible
-  if (r0 < r1) gen_psi<FP8>(s_psi[0], seed, r0, r1, lq, 0, gen_items, tid);
+  if constexpr (ROWS) {
+    stage_rows(r0, 0);
+    lds_barrier();  // zeroed Psi and the first row list visible
+    if (r0 < r1f) load_chunk_rows(A, lda, n, col_w, s_rows[0], FB_PR, lg, v);
+    if (r0 < r1) gen_psi<FP8>(s_psi[0], seed, r0, r1, lq, 0, gen_items, tid, s_rows[0]);
+  } else {
+    if (r0 < r1f) load_chunk(A + r0, lda, n, col_w, lg, v);
+    lds_barrier();  // zeroed Psi visible
+    if (r0 < r1) gen_psi<FP8>(s_psi[0], seed, r0, r1, lq, 0, gen_items, tid);
+  }
 
   // per-lane offset of this lane's Omega^T fragments (bf16 elements)
   const uint32_t om_lane = (uint32_t)((yc * 16 + lr) * FB_NPAD + 8 * lg);
@@ -214,7 +258,14 @@ __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
 #pragma unroll
     for (int j = 0; j < NCH; ++j) {
       const bool col_ok = col_w + FB_CHUNK * j < n;
-      if constexpr (TAIL) load_chunk_tail(A + p0, lda, n, col_w + FB_CHUNK * j, rows, lg, v);
+      if constexpr (TAIL) {
+        if constexpr (ROWS) load_chunk_rows(A, lda, n, col_w + FB_CHUNK * j, s_rows[pb], rows, lg, v);
+        else load_chunk_tail(A + p0, lda, n, col_w + FB_CHUNK * j, rows, lg, v);
+      }
+      // the next panel's row list goes into the other buffer, whose last
+      // readers (the loads of this panel's chunks) finished before the
+      // previous panel's last barrier
+      if (!TAIL && j == 0) stage_rows(pn, pb ^ 1);
       // the previous chunk's Y reads are done (and, at the start of a
       // panel, its Psi is complete)
       lds_barrier();
@@ -265,10 +316,17 @@ __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
       //     slice and the Y product below
       __builtin_amdgcn_sched_barrier(0);
       if constexpr (!TAIL) {
-        if (j + 1 < NCH) {
-          load_chunk(A + p0, lda, n, col_w + FB_CHUNK * (j + 1), lg, v);
-        } else if (pn < r1f) {
-          load_chunk(A + pn, lda, n, col_w, lg, v);
+        if constexpr (ROWS) {
+          if (j + 1 < NCH)
+            load_chunk_rows(A, lda, n, col_w + FB_CHUNK * (j + 1), s_rows[pb], FB_PR, lg, v);
+          else if (pn < r1f)
+            load_chunk_rows(A, lda, n, col_w, s_rows[pb ^ 1], FB_PR, lg, v);
+        } else {
+          if (j + 1 < NCH) {
+            load_chunk(A + p0, lda, n, col_w + FB_CHUNK * (j + 1), lg, v);
+          } else if (pn < r1f) {
+            load_chunk(A + pn, lda, n, col_w, lg, v);
+          }
         }
       }
       __builtin_amdgcn_sched_barrier(0);
@@ -301,7 +359,7 @@ __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
       // (5) slice j of Psi(:, next panel) (the buffer the previous panel used)
       if (!TAIL && pn < r1)
         gen_psi<FP8>(s_psi[pb ^ 1], seed, pn, r1, lq, gen_items * j / NCH, gen_items * (j + 1) / NCH,
-                     tid);
+                     tid, ROWS ? s_rows[pb ^ 1] : nullptr);
       lds_barrier();  // chunk buffer complete
       // (6) Y(panel, this wave's tiles) += A(panel, chunk) Omega(chunk, :)
       if constexpr (WANTY) {
@@ -675,8 +733,9 @@ hipError_t launch_sketch_fused_f32(hipStream_t st, const float* A, int64_t lda, 
 }
 
 bool fused_bf16_supported(int64_t n, int lq, int l, int64_t lda, const void* A, bool has_rows) {
-  return !has_rows && n <= FB_NPAD && lq <= 160 && l <= 128 && (lda % 4) == 0 &&
-         ((uintptr_t)A % 16) == 0;
+  // a row list gathers single values: no alignment needed (W only; checked by the caller)
+  return n <= FB_NPAD && lq <= 160 && l <= 128 &&
+         (has_rows || ((lda % 4) == 0 && ((uintptr_t)A % 16) == 0));
 }
 
 int64_t fused_bf16_grid(int64_t N, int num_cu, int64_t* rows_per_wg) {
@@ -692,7 +751,9 @@ int64_t fused_bf16_grid(int64_t N, int num_cu, int64_t* rows_per_wg) {
 hipError_t launch_sketch_fused_bf16(hipStream_t st, int dmode, const float* A, int64_t lda,
                                     int64_t N, int n, int lq, int l, uint64_t seed,
                                     const float* omega, __bf16* omT, int num_cu, float* part,
-                                    double* W, float* Y, int64_t* nparts_out) {
+                                    double* W, float* Y, int64_t* nparts_out,
+                                    const int64_t* rows) {
+  if (rows && (Y || dmode == FB_FP8)) return hipErrorInvalidValue;  // row lists: W only, bf16
   const int lpad = ((l + 63) / 64) * 64;  // Y tiles: a multiple of 4 tiles of 16
   if (Y) {
     hipLaunchKernelGGL(k_omega_t_bf16, dim3(256), dim3(256), 0, st, omega, n, l, lpad,
@@ -705,7 +766,19 @@ hipError_t launch_sketch_fused_bf16(hipStream_t st, int dmode, const float* A, i
   const int nch = (n + FB_CHUNK - 1) / FB_CHUNK;
 #define SID_FUSED(SP, WY, MT_, LT_, NCH_)                                                  \
   hipLaunchKernelGGL((k_sketch_fused_bf16<SP, WY, MT_, LT_, NCH_>), dim3((unsigned)grid), \
-                     dim3(FB_THREADS), 0, st, A, lda, N, n, lq, l, seed, omT, rpw, part, Y)
+                     dim3(FB_THREADS), 0, st, A, lda, N, n, lq, l, seed, omT, rpw, part, Y,  \
+                     nullptr)
+#define SID_FUSED_R(SP, MT_, NCH_)                                                          \
+  hipLaunchKernelGGL((k_sketch_fused_bf16<SP, false, MT_, 8, NCH_, true>),                  \
+                     dim3((unsigned)grid), dim3(FB_THREADS), 0, st, A, lda, N, n, lq, l, seed, \
+                     omT, rpw, part, Y, rows)
+#define SID_FUSED_RN(SP, MT_)                   \
+  if (nch <= 1) SID_FUSED_R(SP, MT_, 1);        \
+  else if (nch <= 2) SID_FUSED_R(SP, MT_, 2);   \
+  else SID_FUSED_R(SP, MT_, 4);
+#define SID_FUSED_RM(SP)                        \
+  if (mt <= 4) { SID_FUSED_RN(SP, 4) }          \
+  else { SID_FUSED_RN(SP, 10) }
 #define SID_FUSED_NCH(SP, WY, MT_, LT_)         \
   if (nch <= 1) SID_FUSED(SP, WY, MT_, LT_, 1); \
   else if (nch <= 2) SID_FUSED(SP, WY, MT_, LT_, 2); \
@@ -717,9 +790,15 @@ hipError_t launch_sketch_fused_bf16(hipStream_t st, int dmode, const float* A, i
   if (!Y) { SID_FUSED_MT(SP, false, 8) }                     \
   else if (lpad <= 64) { SID_FUSED_MT(SP, true, 4) }         \
   else { SID_FUSED_MT(SP, true, 8) }
-  if (dmode == FB_BF16X2) { SID_FUSED_SP(FB_BF16X2) }
+  if (rows) {
+    if (dmode == FB_BF16X2) { SID_FUSED_RM(FB_BF16X2) }
+    else { SID_FUSED_RM(FB_BF16) }
+  } else if (dmode == FB_BF16X2) { SID_FUSED_SP(FB_BF16X2) }
   else if (dmode == FB_FP8) { SID_FUSED_SP(FB_FP8) }
   else { SID_FUSED_SP(FB_BF16) }
+#undef SID_FUSED_RM
+#undef SID_FUSED_RN
+#undef SID_FUSED_R
 #undef SID_FUSED_SP
 #undef SID_FUSED_MT
 #undef SID_FUSED_NCH

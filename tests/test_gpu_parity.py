@@ -615,3 +615,33 @@ def test_graph_capture_replay(sid, oracle_mod):
                 assert np.array_equal(a, b), (mode, prec, rep)
             _ = (A * 2.0).sum().item()  # unrelated eager work between replays
         ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16x2"])
+@pytest.mark.parametrize("shape", [(50000, 300, 20, 10, 5, 2), (9001, 700, 30, 10, 4, 3), (4000, 64, 8, 4, 2, 0)])
+def test_coarse_rows_streaming_pass(sid, oracle_mod, prec, shape):
+    """The sub-sampled sketch W = Psi(:, S) A(S, :) on the matrix-core pass
+    (row list staged per panel, Psi keyed by the global row): every-other
+    rows, every-third rows, and random rows (step 0), including n = 700 in
+    column slabs and workgroups with ragged tails; then the two-pass
+    compression on it against the oracle."""
+    N, n, k, p, q, step = shape
+    say("coarse streaming", prec, shape)
+    rng = np.random.default_rng(N + n)
+    A64 = (rng.standard_normal((N, 40)) @ rng.standard_normal((40, n))
+           + 0.01 * rng.standard_normal((N, n))).astype(np.float32).astype(np.float64)
+    A = to_gpu(A64, torch.float32)
+    S = (np.arange(1, N, step) if step else np.sort(rng.choice(N, size=N // 5, replace=False))).astype(np.int64)
+    rs = sid.RowSet(S, N)
+    lq = k + p + q
+    W, _ = sid.sketch(A, k, p, seed=13, coarse=rs, prec=prec, probe_rows=q, want_y=False)
+    Wo = oracle_mod.sketch_w(A64, S, lq, 13, prec)
+    bound = np.abs(oracle_mod.psi(13, S, lq, prec)) @ np.abs(oracle_mod.data_values(A64[S], prec))
+    err = np.abs(host(W) - Wo)
+    assert np.all(err <= RTOL[prec] * bound + 1e-30), (err / bound).max()
+    out = sid.compress(A, k, p, seed=13, coarse=rs, mode="two_pass", prec=prec, probe_rows=q)
+    torch.cuda.synchronize()
+    ref = oracle_mod.compress(A64, k, p, seed=13, coarse_rows=S, mode="two_pass", prec=prec, probe_rows=q)
+    ist = next((i for i, m in enumerate(ref.cp.margins) if m <= 1e-3), k)
+    assert host(out.J)[:ist].tolist() == ref.J[:ist].tolist()
+    assert np.array_equal(host(out.AJ).astype(np.float64)[:, :ist], A64[:, ref.J[:ist]])
