@@ -741,6 +741,20 @@ static sid_status factor(sid_ctx* ctx, const sid_params* p, const Shape& sh, con
     SID_CHECK(sid::launch_gather_block(st, w.W, lq, 0, lz, w.piv, w.keff, k, w.WJ), "W(:, J)");
     SID_CHECK(sid::launch_gemm64(st, l, k, lz, w.QM, lz, 1, w.WJ, lz, 0, w.C, l), "QM^T W(:, J)");
     SID_CHECK(sid::launch_small_solve(st, w.RM, l, w.pivM, w.rkM, w.R11, w.C, l, k, w.T), "T");
+    // the probe estimate needs T but not AJ: on the side stream it runs
+    // during AJ = Y T (and the err / J copies below wait for it)
+    hipStream_t es = st;
+    if (overlap && AJ) {
+      SID_CHECK(hipEventRecord(ctx->side_fork, st), "side fork");
+      SID_CHECK(hipStreamWaitEvent(ctx->side, ctx->side_fork, 0), "side fork wait");
+      es = ctx->side;
+    }
+    if (q > 0)
+      SID_CHECK(sid::launch_gemm64(es, q, k, l, w.Mpr, q, 0, w.T, l, 0, w.mix, q), "Mpr T");
+    SID_CHECK(sid::launch_fit_residual(es, w.W, lq, lz, q, n_, w.piv, w.keff, w.Pd, k,
+                                       q > 0 ? w.mix : nullptr, w.fitpart, w.err),
+              "probe residual");
+    if (es != st) SID_CHECK(hipEventRecord(ctx->side_join, es), "side join");
     if (AJ) {
       const bool yf64 = sh.prec == SID_SK_F64;
       const bool ybf = sh.prec == SID_SK_BF16 || sh.prec == SID_SK_BF16X2 ||
@@ -756,11 +770,7 @@ static sid_status factor(sid_ctx* ctx, const sid_params* p, const Shape& sh, con
       else
         SID_CHECK(sid::launch_apply_t(st, w.Y, yf64, sh.N, l, w.T, k, AJ, f64, ldaj), "AJ = Y T");
     }
-    if (q > 0)
-      SID_CHECK(sid::launch_gemm64(st, q, k, l, w.Mpr, q, 0, w.T, l, 0, w.mix, q), "Mpr T");
-    SID_CHECK(sid::launch_fit_residual(st, w.W, lq, lz, q, n_, w.piv, w.keff, w.Pd, k,
-                                       q > 0 ? w.mix : nullptr, w.fitpart, w.err),
-              "probe residual");
+    if (es != st) SID_CHECK(hipStreamWaitEvent(st, ctx->side_join, 0), "side join wait");
   }
   if (J) SID_CHECK(hipMemcpyAsync(J, w.piv, sizeof(int64_t) * (size_t)k, hipMemcpyDeviceToDevice, st),
                    "copy J");
