@@ -213,3 +213,53 @@ def coarse_rows_every_other(nx: int, ny: int, nz: int, ncomp: int = 3) -> np.nda
     k = np.arange(0, nz, 2)[None, None, None, :]
     rows = ((c * nx + i) * ny + j) * nz + k
     return np.sort(rows.reshape(-1)).astype(np.int64)
+
+
+@dataclass(frozen=True)
+class StructuredMesh:
+    """A tensor-product grid and a coarse subset of it, described as input
+    data only (coordinates and index lists; no interpolation weights).
+
+    Rows of a field on this grid are ordered ((c * nx + i) * ny + j) * nz + k
+    for component c, x index i, y index j, z index k (z fastest), as in
+    ``spectral_snapshots``.  ``coarse[d]`` lists the kept indices of
+    dimension d (strictly increasing); ``period[d] > 0`` marks dimension d as
+    periodic with that period (0: bounded)."""
+    ncomp: int
+    n: tuple
+    coords: tuple
+    coarse: tuple
+    period: tuple
+
+    @property
+    def rows(self) -> int:
+        return self.ncomp * self.n[0] * self.n[1] * self.n[2]
+
+    @property
+    def coarse_rows(self) -> np.ndarray:
+        """Global row indices of the coarse grid points, sorted ascending."""
+        nx, ny, nz = self.n
+        cx, cy, cz = (np.asarray(c, np.int64) for c in self.coarse)
+        c = np.arange(self.ncomp, dtype=np.int64)[:, None, None, None]
+        r = ((c * nx + cx[None, :, None, None]) * ny + cy[None, None, :, None]) * nz \
+            + cz[None, None, None, :]
+        return r.reshape(-1)
+
+
+def channel_mesh(cfg: SpectralConfig, stride=(2, 2, 2), periodic: bool = False,
+                 keep_last: bool = False) -> StructuredMesh:
+    """The grid of ``spectral_snapshots`` (uniform x and z, wall-clustered y)
+    with every stride-th point kept per dimension (indices 0, s, 2s, ...;
+    with ``keep_last`` the last index is added when the stride skips it).
+    ``periodic`` marks x and z periodic with the box lengths."""
+    x = np.arange(cfg.nx, dtype=np.float64) * (cfg.lx / cfg.nx)
+    y = -np.cos(np.pi * np.arange(cfg.ny, dtype=np.float64) / max(cfg.ny - 1, 1))
+    z = np.arange(cfg.nz, dtype=np.float64) * (cfg.lz / cfg.nz)
+    coarse = []
+    for n_d, s in zip((cfg.nx, cfg.ny, cfg.nz), stride):
+        idx = list(range(0, n_d, s))
+        if keep_last and idx[-1] != n_d - 1:
+            idx.append(n_d - 1)
+        coarse.append(np.asarray(idx, np.int64))
+    period = (cfg.lx, 0.0, cfg.lz) if periodic else (0.0, 0.0, 0.0)
+    return StructuredMesh(3, (cfg.nx, cfg.ny, cfg.nz), (x, y, z), tuple(coarse), period)
