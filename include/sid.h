@@ -92,7 +92,15 @@ typedef enum {
     SID_SK_FP8E4M3 = 4
 } sid_sketch_prec;
 
-typedef enum { SID_TWO_PASS = 0, SID_SINGLE_PASS = 1 } sid_mode;
+/* TWO_PASS: Alg. 4/5 with the skeleton A(:, J) read in a second pass.
+ * SINGLE_PASS: the skeleton estimated from the sketches (Sec. 2.3).
+ * COARSE_SKELETON: Alg. 6 (Sec. 2.6, eq. (single_ID)): needs a coarse row set
+ *   S; J and P are exactly those of TWO_PASS with the same parameters (the
+ *   ID of A(S, :)), and the skeleton kept is the coarse one, AJ = A(S, J)
+ *   (|S| x k, ldaj >= |S|): no row outside S is ever read.  The fine field is
+ *   recovered with an interpolation operator, sid_interp_reconstruct.  Not
+ *   for streams. */
+typedef enum { SID_TWO_PASS = 0, SID_SINGLE_PASS = 1, SID_COARSE_SKELETON = 2 } sid_mode;
 
 /* What mgsqr runs on.  GAUSS: the Gaussian sketch W = Psi(:, S) A(S, :)
  * (Alg. 4; with a coarse set, the sketched form of Alg. 5).  ROWS_LITERAL:
@@ -182,7 +190,9 @@ sid_status sid_reserve(sid_ctx *ctx, int64_t N, int64_t n, const sid_params *p);
  *         beyond k_eff zero.
  *   AJ    N x k (ldaj), element type `dtype`, or NULL.  Two-pass: the copy
  *         A(:, J) (second pass, Sec. 2.6).  Single-pass: the estimate of
- *         A(:, J) from the sketches (columns beyond k_eff zero).
+ *         A(:, J) from the sketches (columns beyond k_eff zero).  Coarse
+ *         skeleton: |S| x k (ldaj >= |S|), the copy A(S, J) (columns beyond
+ *         k_eff zero).
  *   err   [2] double: err[0] = relative Frobenius residual of the held-out
  *         probe rows (an estimate of ||A - AJ P||_F / ||A||_F; NaN when
  *         probe_rows = 0), err[1] = relative residual of the sketch fit.
@@ -196,7 +206,7 @@ sid_status sid_compress(sid_ctx *ctx, const void *A, sid_dtype dtype, int64_t N,
                         void *AJ, int64_t ldaj, double *err, int64_t *k_eff);
 
 /* Reconstruct Ahat = AJ P (eq. (ID)); AJ N x k (ldaj), P k x n (ldp), Ahat
- * N x n (ldo), all of element type `dtype`. */
+ * N x n (ldo), all of element type `dtype`; 1 <= k <= 256. */
 sid_status sid_reconstruct(sid_ctx *ctx, const void *AJ, int64_t ldaj, const void *P,
                            int64_t ldp, sid_dtype dtype, int64_t N, int64_t k, int64_t n,
                            void *Ahat, int64_t ldo);
@@ -204,7 +214,7 @@ sid_status sid_reconstruct(sid_ctx *ctx, const void *AJ, int64_t ldaj, const voi
 /* Error of an ID against the data without forming Ahat (Sec. 3: relative
  * Frobenius error, Tables 4-7; relative entry-wise max error, Sec. 3.1).
  * out4 (host, 4 doubles): ||A - AJ P||_F, ||A||_F, max |A - Ahat|/|A| over
- * A != 0, max |A - Ahat|.  Synchronizes the stream. */
+ * A != 0, max |A - Ahat|.  1 <= k <= 256.  Synchronizes the stream. */
 sid_status sid_error_norms(sid_ctx *ctx, const void *A, int64_t lda, const void *AJ,
                            int64_t ldaj, const void *P, int64_t ldp, sid_dtype dtype,
                            int64_t N, int64_t k, int64_t n, double *out4);
@@ -273,6 +283,73 @@ sid_status sid_stream_abort(sid_stream *s);
 sid_status sid_stream_save(sid_stream *s, void *host_buf, size_t *bytes);
 sid_status sid_stream_restore(sid_ctx *ctx, const void *host_buf, size_t bytes,
                               sid_stream **out);
+
+/*
+ * Single-pass ID with interpolation (Alg. 6, Sec. 2.6).  A structured grid
+ * of ncomp field components on nx x ny x nz points; rows of A are ordered
+ * ((c * nx + i) * ny + j) * nz + kz (z fastest), N = ncomp nx ny nz.  The
+ * coarse grid keeps, per dimension d, the indices coarse[d] (strictly
+ * increasing in [0, n[d])); its rows S are the tensor product of those lists
+ * in the same order (row set sid_interp_rowset).  The coarse-to-fine
+ * operator Mf (N x |S|, the paper's M transposed) is piecewise linear in
+ * each dimension (Sec. 3 uses piecewise linear interpolation), applied as a
+ * tensor product: trilinear, t = 8 coarse points per fine point.  Per
+ * dimension a fine point lying between two coarse nodes takes the linear
+ * weights of their coordinates; beyond the outermost nodes of a bounded
+ * dimension the end element's line is continued (linear extrapolation); a
+ * periodic dimension (period > 0) joins its last node to the first one
+ * shifted by the period; a dimension with one coarse node is constant.
+ *   coord[d]  host, n[d] strictly increasing coordinates (NULL: 0, 1, 2, ...);
+ *             periodic: the span of the coarse nodes must be < period
+ *   coarse[d] host, ncoarse[d] >= 1 indices
+ * The operator is never formed: sid_interp_create builds three small 1-D
+ * tables (two node indices and a weight per fine index) on the host and
+ * copies them to the device; the kernels form the 8 weights of a fine point
+ * from them.  N and |S| must be below 2^31.  The object and its row set
+ * belong to ctx and must be destroyed before it.
+ */
+typedef struct sid_interp sid_interp;
+
+typedef struct {
+    int32_t ncomp;
+    int32_t reserved;           /* 0 */
+    int64_t n[3];
+    const double *coord[3];
+    const int64_t *coarse[3];
+    int64_t ncoarse[3];
+    double period[3];
+} sid_mesh;
+
+sid_status sid_interp_create(sid_ctx *ctx, const sid_mesh *mesh, sid_interp **out);
+sid_status sid_interp_destroy(sid_interp *ip);
+/* The coarse row set S of the mesh (owned by the interp object), for
+ * sid_params.coarse; N (fine rows) and Nc = |S| on the host (NULL allowed). */
+const sid_rowset *sid_interp_rowset(const sid_interp *ip);
+sid_status sid_interp_info(const sid_interp *ip, int64_t *N, int64_t *Nc);
+
+/* Ahat = Mf ACJ P (eq. (single_ID)): ACJ the coarse skeleton (Nc x k,
+ * ldacj >= Nc, from a COARSE_SKELETON compress), P k x n (ldp >= k), Ahat
+ * N x n (ldo >= N), all of element type `dtype`, device memory.
+ * Arithmetic: F64 throughout for SID_F64.  SID_F32 with k <= 128: the
+ * interpolated skeleton rows are formed in FP32, split into two bfloat16
+ * parts (hi + lo) as are P's entries, and multiplied on the matrix cores
+ * as hi*hi + hi*lo + lo*hi with FP32 accumulation (relative error of a
+ * product about 2^-16); SID_F32 with k > 128: FP32 fused multiply-adds.
+ * Asynchronous on the context's stream; may grow the workspace (a row-major
+ * copy of ACJ and a packed copy of P, or for the FMA path Mf ACJ itself).
+ * 1 <= k <= 256. */
+sid_status sid_interp_reconstruct(sid_ctx *ctx, const sid_interp *ip, const void *ACJ,
+                                  int64_t ldacj, const void *P, int64_t ldp, sid_dtype dtype,
+                                  int64_t k, int64_t n, void *Ahat, int64_t ldo);
+
+/* Error of Ahat = Mf ACJ P against the fine data A (N x n, lda) without
+ * forming Ahat, with the arithmetic of sid_interp_reconstruct.  out4 (host):
+ * ||A - Ahat||_F, ||A||_F, max |A - Ahat|/|A| over A != 0, max |A - Ahat|
+ * (as sid_error_norms).  Synchronizes the stream. */
+sid_status sid_interp_error_norms(sid_ctx *ctx, const sid_interp *ip, const void *A,
+                                  int64_t lda, const void *ACJ, int64_t ldacj, const void *P,
+                                  int64_t ldp, sid_dtype dtype, int64_t k, int64_t n,
+                                  double *out4);
 
 /*
  * Batched compression of independent matrices (one call for many problems,

@@ -93,6 +93,26 @@ def interp_operator(mesh) -> sp.csr_matrix:
     return sp.kron(sp.identity(mesh.ncomp, format="csr"), Mf, format="csr")
 
 
+def interp_rows(mesh, rows) -> sp.csr_matrix:
+    """Selected rows of Mf (len(rows) x N_c) without forming Mf: row
+    ((c * nx + i) * ny + j) * nz + k is e_c (x) Mx[i] (x) My[j] (x) Mz[k]."""
+    Hs = [hat_matrix(mesh.coords[d], mesh.coarse[d], mesh.period[d]) for d in range(3)]
+    nx, ny, nz = mesh.n
+    blk = Hs[0].shape[1] * Hs[1].shape[1] * Hs[2].shape[1]
+    out = []
+    for r in np.asarray(rows, np.int64):
+        c, rem = divmod(int(r), nx * ny * nz)
+        i, rem = divmod(rem, ny * nz)
+        j, k = divmod(rem, nz)
+        row = sp.kron(sp.csr_matrix(Hs[0][i:i + 1]),
+                      sp.kron(sp.csr_matrix(Hs[1][j:j + 1]), sp.csr_matrix(Hs[2][k:k + 1])))
+        e = sp.csr_matrix(([1.0], ([0], [c])), shape=(1, mesh.ncomp))
+        out.append(sp.kron(e, row, format="csr"))
+    M = sp.vstack(out, format="csr")
+    assert M.shape[1] == mesh.ncomp * blk
+    return M
+
+
 @dataclass
 class SPIDResult:
     J: np.ndarray            # k skeleton snapshot indices (pivot order; -1 past k_eff)
@@ -127,9 +147,10 @@ def spid_reconstruct(Mf, ACJ: np.ndarray, P: np.ndarray) -> np.ndarray:
 
 
 def spid_rows(Mf, ACJ: np.ndarray, P: np.ndarray, rows) -> np.ndarray:
-    """Selected rows of A_hat, one fine row at a time (for samples of a matrix
-    too large to reconstruct): A_hat(i, :) = Mf(i, :) A(S, J) P."""
-    Mr = Mf[np.asarray(rows, np.int64)]
+    """Selected rows of A_hat (for samples of a matrix too large to
+    reconstruct): A_hat(i, :) = Mf(i, :) A(S, J) P.  ``Mf`` is the operator
+    or the rows of it (``interp_rows``) already selected (rows=None)."""
+    Mr = Mf if rows is None else Mf[np.asarray(rows, np.int64)]
     return np.asarray(Mr @ np.asarray(ACJ, np.float64)) @ np.asarray(P, np.float64)
 
 

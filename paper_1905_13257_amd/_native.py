@@ -13,7 +13,7 @@ _LIB = None
 
 SID_F64, SID_F32 = 0, 1
 PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2, "bf16x2": 3, "fp8": 4}
-MODES = {"two_pass": 0, "single_pass": 1}
+MODES = {"two_pass": 0, "single_pass": 1, "coarse_skeleton": 2}
 SELECT = {"gauss": 0, "literal": 1}
 _STATUS = {0: "SID_OK", -1: "SID_EINVAL", -2: "SID_ENOMEM", -3: "SID_EDEVICE",
            -4: "SID_ESTATE", -5: "SID_ENONFINITE", -6: "SID_ERANK"}
@@ -24,6 +24,8 @@ EXPORTS = [
     "sid_compress", "sid_reconstruct", "sid_error_norms", "sid_fill_gaussian", "sid_sketch",
     "sid_stream_begin", "sid_stream_push", "sid_stream_finish", "sid_stream_info", "sid_stream_abort",
     "sid_stream_save", "sid_stream_restore", "sid_compress_batched",
+    "sid_interp_create", "sid_interp_destroy", "sid_interp_rowset", "sid_interp_info",
+    "sid_interp_reconstruct", "sid_interp_error_norms",
 ]
 
 
@@ -48,6 +50,18 @@ class _Params(ctypes.Structure):
         ("refine", ctypes.c_int32),
         ("refine_prec", ctypes.c_int),
         ("select", ctypes.c_int),
+    ]
+
+
+class _Mesh(ctypes.Structure):
+    _fields_ = [
+        ("ncomp", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("n", ctypes.c_int64 * 3),
+        ("coord", ctypes.c_void_p * 3),
+        ("coarse", ctypes.c_void_p * 3),
+        ("ncoarse", ctypes.c_int64 * 3),
+        ("period", ctypes.c_double * 3),
     ]
 
 
@@ -93,12 +107,22 @@ def load():
                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     L.sid_stream_save.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_size_t)]
     L.sid_stream_restore.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
+    L.sid_interp_create.argtypes = [vp, ctypes.POINTER(_Mesh), ctypes.POINTER(vp)]
+    L.sid_interp_destroy.argtypes = [vp]
+    L.sid_interp_rowset.argtypes = [vp]
+    L.sid_interp_rowset.restype = vp
+    L.sid_interp_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.sid_interp_reconstruct.argtypes = [vp, vp, vp, i64, vp, i64, ctypes.c_int, i64, i64, vp,
+                                         i64]
+    L.sid_interp_error_norms.argtypes = [vp, vp, vp, i64, vp, i64, vp, i64, ctypes.c_int, i64,
+                                         i64, vp]
     for name in ("sid_create", "sid_destroy", "sid_set_workspace_limit", "sid_rowset_create",
                  "sid_rowset_destroy", "sid_reserve", "sid_compress", "sid_reconstruct",
                  "sid_error_norms", "sid_fill_gaussian", "sid_sketch", "sid_stream_begin",
                  "sid_stream_push", "sid_stream_finish", "sid_stream_info", "sid_stream_abort",
                  "sid_stream_save", "sid_compress_batched",
-                 "sid_stream_restore"):
+                 "sid_stream_restore", "sid_interp_create", "sid_interp_destroy",
+                 "sid_interp_info", "sid_interp_reconstruct", "sid_interp_error_norms"):
         getattr(L, name).restype = ctypes.c_int
     _LIB = L
     return L
@@ -303,7 +327,9 @@ def compress(A: torch.Tensor, k: int, oversample: int = 10, seed: int = 0,
     if out is None:
         J = torch.empty(k, dtype=torch.int64, device=dev)
         P = torch.empty((n, k), dtype=A.dtype, device=dev).T
-        AJ = torch.empty((k, N), dtype=A.dtype, device=dev).T if want_skeleton else None
+        # the coarse skeleton (Alg. 6) has the coarse rows only
+        rows = coarse.count if (mode == "coarse_skeleton" and coarse is not None) else N
+        AJ = torch.empty((k, rows), dtype=A.dtype, device=dev).T if want_skeleton else None
         err = torch.empty(2, dtype=torch.float64, device=dev)
         keff = torch.empty(1, dtype=torch.int64, device=dev)
         out = Compressed(J, P, AJ, err, keff)
@@ -479,3 +505,93 @@ class Stream:
             self.close()
         except Exception:
             pass
+
+
+class _BorrowedRowSet:
+    """A row set owned by another object (an Interp's coarse rows)."""
+
+    def __init__(self, h, count: int, N: int, owner):
+        self._h, self.count, self.N, self._owner = h, count, N, owner
+
+
+class Interp:
+    """Structured grid and coarse subset for the single-pass ID with
+    interpolation (Alg. 6): the trilinear coarse-to-fine operator Mf and the
+    coarse row set S (``rowset``, for compress(..., coarse=...)).
+
+    ``mesh`` has attributes ncomp, n (3 sizes), coords (3 arrays or None),
+    coarse (3 index arrays) and period (3 floats, 0 = bounded)."""
+
+    def __init__(self, mesh, ctx: Context | None = None):
+        import numpy as np
+        self.ctx = ctx or default_context()
+        m = _Mesh()
+        m.ncomp = int(mesh.ncomp)
+        m.reserved = 0
+        keep = []
+        for d in range(3):
+            m.n[d] = int(mesh.n[d])
+            c = np.ascontiguousarray(np.asarray(mesh.coarse[d], dtype=np.int64))
+            keep.append(c)
+            m.coarse[d] = c.ctypes.data
+            m.ncoarse[d] = c.size
+            x = mesh.coords[d] if mesh.coords is not None else None
+            if x is None:
+                m.coord[d] = None
+            else:
+                xa = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+                keep.append(xa)
+                m.coord[d] = xa.ctypes.data
+            m.period[d] = float(mesh.period[d]) if mesh.period is not None else 0.0
+        h = ctypes.c_void_p()
+        self.ctx.check(self.ctx._lib.sid_interp_create(self.ctx.handle, ctypes.byref(m),
+                                                       ctypes.byref(h)))
+        self._h = h
+        N, Nc = ctypes.c_int64(), ctypes.c_int64()
+        self.ctx.check(self.ctx._lib.sid_interp_info(h, ctypes.byref(N), ctypes.byref(Nc)))
+        self.N, self.Nc = N.value, Nc.value
+        self.rowset = _BorrowedRowSet(ctypes.c_void_p(self.ctx._lib.sid_interp_rowset(h)),
+                                      self.Nc, self.N, self)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.ctx._lib.sid_interp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def interp_reconstruct(ip: Interp, ACJ: torch.Tensor, P: torch.Tensor,
+                       out: torch.Tensor | None = None, ctx: Context | None = None) -> torch.Tensor:
+    """Ahat = Mf ACJ P (N x n) from the coarse skeleton ACJ (Nc x k)."""
+    ctx = ctx or ip.ctx
+    ACJ, ldc = _colmajor(ACJ)
+    P, ldp = _colmajor(P.to(ACJ.dtype))
+    k = ACJ.shape[1]
+    n = P.shape[1]
+    if out is None:
+        out = torch.empty((n, ip.N), dtype=ACJ.dtype, device=ACJ.device).T
+    ctx.check(ctx._lib.sid_interp_reconstruct(ctx.handle, ip._h, _ptr(ACJ), ldc, _ptr(P), ldp,
+                                              _dtype_code(ACJ), k, n, _ptr(out), out.stride(1)))
+    return out
+
+
+def interp_error_norms(ip: Interp, A: torch.Tensor, ACJ: torch.Tensor, P: torch.Tensor,
+                       ctx: Context | None = None) -> dict:
+    """Errors of Mf ACJ P against A without forming it (as error_norms)."""
+    ctx = ctx or ip.ctx
+    A, lda = _colmajor(A)
+    ACJ, ldc = _colmajor(ACJ.to(A.dtype))
+    P, ldp = _colmajor(P.to(A.dtype))
+    k = ACJ.shape[1]
+    n = A.shape[1]
+    out = (ctypes.c_double * 4)()
+    ctx.check(ctx._lib.sid_interp_error_norms(ctx.handle, ip._h, _ptr(A), lda, _ptr(ACJ), ldc,
+                                              _ptr(P), ldp, _dtype_code(A), k, n, out))
+    fe, fa = out[0], out[1]
+    return dict(fro_err=fe, fro_a=fa, rel_fro=fe / fa if fa > 0 else 0.0, rel_max=out[2],
+                max_abs=out[3])

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/sid.h"
+#include "sid_interp.hpp"
 #include "sid_kernels.hpp"
 
 namespace {
@@ -19,7 +20,7 @@ namespace {
 enum Slot {
   WS_OMEGA, WS_PART, WS_W, WS_WR, WS_NRM, WS_PIV, WS_R, WS_Q, WS_KEFF, WS_STATS, WS_PD,
   WS_ERR, WS_Y, WS_M, WS_MPR, WS_WJ, WS_PIVM, WS_RM, WS_QM, WS_RKM, WS_C, WS_T, WS_MIX,
-  WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COOP, WS_SYNC, WS_R11, WS_FITPART, WS_YTMP, WS_REF_W, WS_REF_WJ, WS_REF_T, WS_REF_G, WS_OMP, WS_A8, WS_COUNT
+  WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COOP, WS_SYNC, WS_R11, WS_FITPART, WS_YTMP, WS_REF_W, WS_REF_WJ, WS_REF_T, WS_REF_G, WS_OMP, WS_A8, WS_IACJT, WS_IPB, WS_IB, WS_IPART, WS_COUNT
 };
 
 struct Buf {
@@ -154,8 +155,10 @@ sid_status validate(sid_ctx* ctx, int64_t N, int64_t n, const sid_params* p, Sha
   if (p->oversample < 0) return fail(ctx, SID_EINVAL, "oversample must be >= 0");
   if (p->probe_rows < 0) return fail(ctx, SID_EINVAL, "probe_rows must be >= 0");
   if (p->k > n) return fail(ctx, SID_EINVAL, "k must not exceed the number of columns n");
-  if (p->mode != SID_TWO_PASS && p->mode != SID_SINGLE_PASS)
+  if (p->mode != SID_TWO_PASS && p->mode != SID_SINGLE_PASS && p->mode != SID_COARSE_SKELETON)
     return fail(ctx, SID_EINVAL, "unknown mode");
+  if (p->mode == SID_COARSE_SKELETON && !p->coarse)
+    return fail(ctx, SID_EINVAL, "the coarse-skeleton mode needs a coarse row set");
   if (p->prec < SID_SK_F64 || p->prec > SID_SK_FP8E4M3)
     return fail(ctx, SID_EINVAL, "unknown sketch precision");
   if (!(p->rank_tol >= 0.0) || !(p->sp_rcond >= 0.0))
@@ -167,7 +170,8 @@ sid_status validate(sid_ctx* ctx, int64_t N, int64_t n, const sid_params* p, Sha
     return fail(ctx, SID_EINVAL, "unknown select");
   if (p->select == SID_SEL_ROWS_LITERAL) {
     if (!p->coarse) return fail(ctx, SID_EINVAL, "literal selection needs a coarse row set");
-    if (p->mode != SID_TWO_PASS) return fail(ctx, SID_EINVAL, "literal selection is two-pass");
+    if (p->mode == SID_SINGLE_PASS)
+      return fail(ctx, SID_EINVAL, "literal selection has no single-pass form");
     if (p->prec != SID_SK_F64 && p->prec != SID_SK_F32)
       return fail(ctx, SID_EINVAL, "literal selection reads the data in F64 or F32");
     if (p->refine) return fail(ctx, SID_EINVAL, "literal selection has no refinement pass");
@@ -212,6 +216,11 @@ sid_status validate(sid_ctx* ctx, int64_t N, int64_t n, const sid_params* p, Sha
   sh->single = p->mode == SID_SINGLE_PASS;
   sh->prec = p->prec;
   return SID_OK;
+}
+
+// rows of the skeleton output AJ: |S| for the coarse skeleton (Alg. 6), else N
+int64_t skeleton_rows(const sid_params* p, int64_t N) {
+  return (p->mode == SID_COARSE_SKELETON && p->coarse) ? p->coarse->count : N;
 }
 
 struct Work {
@@ -591,7 +600,8 @@ sid_status sid_compress(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N,
   sid_status s = validate(ctx, N, n, p, &sh);
   if (s != SID_OK) return s;
   if (P && ldp < p->k) return fail(ctx, SID_EINVAL, "ldp < k");
-  if (AJ && ldaj < N) return fail(ctx, SID_EINVAL, "ldaj < N");
+  if (AJ && ldaj < skeleton_rows(p, N))
+    return fail(ctx, SID_EINVAL, "ldaj < rows of the skeleton (N, or |S| for the coarse skeleton)");
   SID_NEED_DEVICE(ctx);
   SID_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
   Work w;
@@ -725,7 +735,12 @@ static sid_status factor(sid_ctx* ctx, const sid_params* p, const Shape& sh, con
     SID_CHECK(sid::launch_fit_residual(st, w.W, lq, l, q, n_, w.piv, w.keff, w.Pd, k, nullptr,
                                        w.fitpart, w.err),
               "probe residual");
-    if (AJ)
+    if (AJ && p->mode == SID_COARSE_SKELETON)
+      // Alg. 6: keep the coarse skeleton A(S, J); no fine row is read
+      SID_CHECK(sid::launch_gather_coarse_skeleton(st, A, f64, lda, p->coarse->d_rows, sh.Ns,
+                                                   w.piv, w.keff, k, AJ, ldaj),
+                "coarse skeleton gather");
+    else if (AJ)
       SID_CHECK(sid::launch_gather_cols(st, A, f64, lda, sh.N, w.piv, w.keff, k, AJ, f64, ldaj),
                 "skeleton gather");
   } else {
@@ -791,7 +806,7 @@ sid_status sid_reconstruct(sid_ctx* ctx, const void* AJ, int64_t ldaj, const voi
   if (dtype != SID_F32 && dtype != SID_F64) return fail(ctx, SID_EINVAL, "unknown dtype");
   if (N <= 0 || n <= 0 || k <= 0) return fail(ctx, SID_EINVAL, "N, n, k must be positive");
   if (ldaj < N || ldo < N || ldp < k) return fail(ctx, SID_EINVAL, "leading dimension too small");
-  if (k > 4096) return fail(ctx, SID_EINVAL, "k too large");
+  if (k > 256) return fail(ctx, SID_EINVAL, "k must be <= 256");
   SID_NEED_DEVICE(ctx);
   SID_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
   SID_CHECK(sid::launch_reconstruct(ctx->stream, dtype == SID_F64, AJ, ldaj, P, ldp, N, (int)k, n,
@@ -808,7 +823,7 @@ sid_status sid_error_norms(sid_ctx* ctx, const void* A, int64_t lda, const void*
   if (dtype != SID_F32 && dtype != SID_F64) return fail(ctx, SID_EINVAL, "unknown dtype");
   if (N <= 0 || n <= 0 || k <= 0) return fail(ctx, SID_EINVAL, "N, n, k must be positive");
   if (lda < N || ldaj < N || ldp < k) return fail(ctx, SID_EINVAL, "leading dimension too small");
-  if (k > 1024) return fail(ctx, SID_EINVAL, "k too large");
+  if (k > 256) return fail(ctx, SID_EINVAL, "k must be <= 256");
   SID_NEED_DEVICE(ctx);
   SID_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
   const int64_t nb = ((N + 63) / 64) * ((n + 31) / 32);
@@ -965,6 +980,8 @@ sid_status sid_stream_begin(sid_ctx* ctx, sid_dtype dtype, int64_t N, int64_t n_
     return fail(ctx, SID_EINVAL, "refinement re-reads A; a stream keeps no columns");
   if (p->select != SID_SEL_GAUSS)
     return fail(ctx, SID_EINVAL, "a stream sketches its blocks; literal selection needs all rows");
+  if (p->mode == SID_COARSE_SKELETON)
+    return fail(ctx, SID_EINVAL, "the coarse-skeleton mode is not streamed (a stream keeps no rows)");
   SID_NEED_DEVICE(ctx);
   SID_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
   return stream_make(ctx, dtype, N, n_max, p, out);
@@ -1237,7 +1254,8 @@ sid_status sid_compress_batched(sid_ctx* ctx, const sid_problem* probs, int64_t 
     const sid_status vs = validate(ctx, q.N, q.n, &q.params, &sh);
     if (vs != SID_OK) return fail(ctx, vs, at + ctx->err);
     if (q.P && q.ldp < q.params.k) return fail(ctx, SID_EINVAL, at + "ldp < k");
-    if (q.AJ && q.ldaj < q.N) return fail(ctx, SID_EINVAL, at + "ldaj < N");
+    if (q.AJ && q.ldaj < skeleton_rows(&q.params, q.N))
+      return fail(ctx, SID_EINVAL, at + "ldaj < rows of the skeleton");
     if (q.params.coarse && q.params.coarse->ctx != ctx)
       return fail(ctx, SID_EINVAL, at + "row set belongs to another context");
   }
@@ -1272,6 +1290,327 @@ sid_status sid_compress_batched(sid_ctx* ctx, const sid_problem* probs, int64_t 
     SID_CHECK(hipStreamWaitEvent(ctx->stream, ctx->child_done[c], 0), "batched: join wait");
   }
   return result;
+}
+
+
+// ---------------------------------------------------------------------------
+// Single-pass ID with interpolation (Alg. 6): the structured mesh, its
+// coarse row set and the coarse-to-fine reconstruction.
+// ---------------------------------------------------------------------------
+struct sid_interp {
+  sid_ctx* ctx = nullptr;
+  sid::InterpDev dev{};
+  void* d_tables = nullptr;
+  sid_rowset* rs = nullptr;
+  int64_t N = 0, Nc = 0;
+};
+
+namespace {
+
+// One dimension of the operator: for every fine index the element of coarse
+// nodes it lies in (the first element whose closed interval contains it; the
+// end elements continued outside a bounded dimension, the element from the
+// last node to the first one shifted by the period closing a periodic one)
+// and the local coordinate in it, the weight of the element's second node.
+bool build_dim(int64_t n, const double* coord, const int64_t* coarse, int64_t m, double period,
+               int32_t* lo, int32_t* hi, double* w, std::string* why) {
+  auto xc = [&](int64_t i) { return coord ? coord[i] : (double)i; };
+  for (int64_t i = 1; i < n; ++i)
+    if (!(xc(i) > xc(i - 1))) {
+      *why = "coordinates must be strictly increasing";
+      return false;
+    }
+  for (int64_t a = 0; a < m; ++a) {
+    if (coarse[a] < 0 || coarse[a] >= n || (a > 0 && coarse[a] <= coarse[a - 1])) {
+      *why = "coarse indices must be strictly increasing and within the dimension";
+      return false;
+    }
+  }
+  if (!(period >= 0.0) || !std::isfinite(period)) {
+    *why = "period must be finite and >= 0";
+    return false;
+  }
+  const double X0 = xc(coarse[0]), Xl = xc(coarse[m - 1]);
+  if (period > 0.0 && !(Xl - X0 < period)) {
+    *why = "the coarse nodes of a periodic dimension must span less than its period";
+    return false;
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    if (m == 1) {
+      lo[i] = hi[i] = 0;
+      w[i] = 0.0;
+      continue;
+    }
+    double x = xc(i);
+    int64_t a = -1;
+    double xa = 0.0, xb = 0.0;
+    int64_t b = 0;
+    if (period > 0.0) {
+      x = X0 + std::fmod(x - X0, period);
+      if (x < X0) x += period;
+      for (int64_t e = 0; e < m && a < 0; ++e) {
+        const double l = xc(coarse[e]);
+        const double r = (e + 1 < m) ? xc(coarse[e + 1]) : X0 + period;
+        if (l <= x && x <= r) {
+          a = e;
+          b = (e + 1 < m) ? e + 1 : 0;
+          xa = l;
+          xb = r;
+        }
+      }
+      if (a < 0) {  // rounding at the top of the period: the closing element's end
+        a = m - 1;
+        b = 0;
+        xa = Xl;
+        xb = X0 + period;
+        x = xb;
+      }
+    } else {
+      if (x < X0) {
+        a = 0;
+      } else if (x > Xl) {
+        a = m - 2;
+      } else {
+        for (int64_t e = 0; e + 1 < m && a < 0; ++e)
+          if (xc(coarse[e]) <= x && x <= xc(coarse[e + 1])) a = e;
+      }
+      b = a + 1;
+      xa = xc(coarse[a]);
+      xb = xc(coarse[b]);
+    }
+    lo[i] = (int32_t)a;
+    hi[i] = (int32_t)b;
+    w[i] = (x - xa) / (xb - xa);
+  }
+  return true;
+}
+
+}  // namespace
+
+sid_status sid_interp_create(sid_ctx* ctx, const sid_mesh* mesh, sid_interp** out) {
+  if (!ctx) return SID_EINVAL;
+  if (!mesh || !out) return fail(ctx, SID_EINVAL, "null argument");
+  *out = nullptr;
+  if (mesh->ncomp < 1 || mesh->reserved != 0)
+    return fail(ctx, SID_EINVAL, "ncomp must be >= 1 and reserved 0");
+  int64_t N = mesh->ncomp, Nc = mesh->ncomp, ntot = 0;
+  for (int d = 0; d < 3; ++d) {
+    if (mesh->n[d] < 1 || mesh->ncoarse[d] < 1 || mesh->ncoarse[d] > mesh->n[d] ||
+        !mesh->coarse[d])
+      return fail(ctx, SID_EINVAL, "every dimension needs n >= ncoarse >= 1 and a coarse list");
+    if (mesh->n[d] > ((int64_t)1 << 31) || N > ((int64_t)1 << 31))
+      return fail(ctx, SID_EINVAL, "the grid must have fewer than 2^31 points");
+    N *= mesh->n[d];
+    Nc *= mesh->ncoarse[d];
+    ntot += mesh->n[d];
+  }
+  if (N >= ((int64_t)1 << 31)) return fail(ctx, SID_EINVAL, "the grid must have fewer than 2^31 points");
+  std::vector<int32_t> lo((size_t)ntot), hi((size_t)ntot);
+  std::vector<double> w64((size_t)ntot);
+  int64_t off = 0;
+  for (int d = 0; d < 3; ++d) {
+    std::string why;
+    if (!build_dim(mesh->n[d], mesh->coord[d], mesh->coarse[d], mesh->ncoarse[d],
+                   mesh->period[d], lo.data() + off, hi.data() + off, w64.data() + off, &why))
+      return fail(ctx, SID_EINVAL, "dimension " + std::to_string(d) + ": " + why);
+    off += mesh->n[d];
+  }
+  std::vector<float> w32((size_t)ntot);
+  for (int64_t i = 0; i < ntot; ++i) w32[(size_t)i] = (float)w64[(size_t)i];
+  // coarse rows: the tensor product of the coarse lists, component-major
+  std::vector<int64_t> rows((size_t)Nc);
+  {
+    const int64_t* cx = mesh->coarse[0];
+    const int64_t* cy = mesh->coarse[1];
+    const int64_t* cz = mesh->coarse[2];
+    size_t e = 0;
+    for (int64_t c = 0; c < mesh->ncomp; ++c)
+      for (int64_t a = 0; a < mesh->ncoarse[0]; ++a)
+        for (int64_t b = 0; b < mesh->ncoarse[1]; ++b)
+          for (int64_t z = 0; z < mesh->ncoarse[2]; ++z)
+            rows[e++] = ((c * mesh->n[0] + cx[a]) * mesh->n[1] + cy[b]) * mesh->n[2] + cz[z];
+  }
+  SID_NEED_DEVICE(ctx);
+  sid_interp* ip = new (std::nothrow) sid_interp();
+  if (!ip) return fail(ctx, SID_ENOMEM, "host allocation failed");
+  sid_status st = sid_rowset_create(ctx, rows.data(), Nc, N, &ip->rs);
+  if (st != SID_OK) {
+    delete ip;
+    return st;
+  }
+  const size_t bi = sizeof(int32_t) * (size_t)ntot, bf = sizeof(float) * (size_t)ntot,
+               bd = sizeof(double) * (size_t)ntot;
+  // layout: w64 | lo | hi | w32 (the doubles first keep every part aligned)
+  std::vector<unsigned char> host(bd + 2 * bi + bf);
+  std::memcpy(host.data(), w64.data(), bd);
+  std::memcpy(host.data() + bd, lo.data(), bi);
+  std::memcpy(host.data() + bd + bi, hi.data(), bi);
+  std::memcpy(host.data() + bd + 2 * bi, w32.data(), bf);
+  if (hipMalloc(&ip->d_tables, host.size()) != hipSuccess) {
+    (void)hipGetLastError();
+    sid_rowset_destroy(ip->rs);
+    delete ip;
+    return fail(ctx, SID_ENOMEM, "device allocation failed");
+  }
+  hipError_t e = hipMemcpy(ip->d_tables, host.data(), host.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(ip->d_tables);
+    sid_rowset_destroy(ip->rs);
+    delete ip;
+    return hip_fail(ctx, e, "interpolation table upload");
+  }
+  unsigned char* base = (unsigned char*)ip->d_tables;
+  ip->ctx = ctx;
+  ip->N = N;
+  ip->Nc = Nc;
+  sid::InterpDev& t = ip->dev;
+  t.w64 = (const double*)base;
+  t.lo = (const int32_t*)(base + bd);
+  t.hi = (const int32_t*)(base + bd + bi);
+  t.w32 = (const float*)(base + bd + 2 * bi);
+  t.nx = (int32_t)mesh->n[0];
+  t.ny = (int32_t)mesh->n[1];
+  t.nz = (int32_t)mesh->n[2];
+  t.mx = (int32_t)mesh->ncoarse[0];
+  t.my = (int32_t)mesh->ncoarse[1];
+  t.mz = (int32_t)mesh->ncoarse[2];
+  t.ncomp = mesh->ncomp;
+  t.N = N;
+  t.Nc = Nc;
+  *out = ip;
+  return SID_OK;
+}
+
+sid_status sid_interp_destroy(sid_interp* ip) {
+  if (!ip) return SID_EINVAL;
+  if (ip->d_tables) {
+    (void)hipSetDevice(ip->ctx->device);
+    (void)hipStreamSynchronize(ip->ctx->stream);
+    (void)hipFree(ip->d_tables);
+  }
+  if (ip->rs) (void)sid_rowset_destroy(ip->rs);
+  delete ip;
+  return SID_OK;
+}
+
+const sid_rowset* sid_interp_rowset(const sid_interp* ip) { return ip ? ip->rs : nullptr; }
+
+sid_status sid_interp_info(const sid_interp* ip, int64_t* N, int64_t* Nc) {
+  if (!ip) return SID_EINVAL;
+  if (N) *N = ip->N;
+  if (Nc) *Nc = ip->Nc;
+  return SID_OK;
+}
+
+namespace {
+
+sid_status interp_check(sid_ctx* ctx, const sid_interp* ip, const void* ACJ, int64_t ldacj,
+                        const void* P, int64_t ldp, sid_dtype dtype, int64_t k, int64_t n) {
+  if (!ip) return fail(ctx, SID_EINVAL, "interp is NULL");
+  if (ip->ctx != ctx) return fail(ctx, SID_EINVAL, "interp belongs to another context");
+  if (!ACJ || !P) return fail(ctx, SID_EINVAL, "null pointer");
+  if (dtype != SID_F32 && dtype != SID_F64) return fail(ctx, SID_EINVAL, "unknown dtype");
+  if (k < 1 || n < 1) return fail(ctx, SID_EINVAL, "k and n must be positive");
+  if (k > 256) return fail(ctx, SID_EINVAL, "k must be <= 256");
+  if (ldacj < ip->Nc || ldp < k) return fail(ctx, SID_EINVAL, "leading dimension too small");
+  return SID_OK;
+}
+
+// FP32 with k <= 128 takes the matrix-core path: pack ACJ row-major and P
+// as bfloat16 hi/lo operands.  Returns kp (0: FMA path).
+sid_status interp_prepare(sid_ctx* ctx, const sid_interp* ip, const void* ACJ, int64_t ldacj,
+                          const void* P, int64_t ldp, sid_dtype dtype, int64_t k, int64_t n,
+                          int* kp_out, float** acjt, void** pb) {
+  *kp_out = 0;
+  if (dtype != SID_F32 || k > 128) return SID_OK;
+  const int kp = (int)((k + 31) / 32 * 32);
+  *acjt = (float*)ws(ctx, WS_IACJT, sizeof(float) * (size_t)ip->Nc * (size_t)kp);
+  *pb = ws(ctx, WS_IPB, sid::interp_pb_bytes(n, kp));
+  if (!*acjt || !*pb) return SID_ENOMEM;
+  SID_CHECK(sid::launch_interp_pack(ctx->stream, (const float*)ACJ, ldacj, ip->Nc, (int)k, kp,
+                                    *acjt, (const float*)P, ldp, n, *pb),
+            "interpolation operands");
+  *kp_out = kp;
+  return SID_OK;
+}
+
+}  // namespace
+
+sid_status sid_interp_reconstruct(sid_ctx* ctx, const sid_interp* ip, const void* ACJ,
+                                  int64_t ldacj, const void* P, int64_t ldp, sid_dtype dtype,
+                                  int64_t k, int64_t n, void* Ahat, int64_t ldo) {
+  if (!ctx) return SID_EINVAL;
+  sid_status s = interp_check(ctx, ip, ACJ, ldacj, P, ldp, dtype, k, n);
+  if (s != SID_OK) return s;
+  if (!Ahat) return fail(ctx, SID_EINVAL, "Ahat is NULL");
+  if (ldo < ip->N) return fail(ctx, SID_EINVAL, "ldo < N");
+  SID_NEED_DEVICE(ctx);
+  SID_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+  int kp = 0;
+  float* acjt = nullptr;
+  void* pb = nullptr;
+  s = interp_prepare(ctx, ip, ACJ, ldacj, P, ldp, dtype, k, n, &kp, &acjt, &pb);
+  if (s != SID_OK) return s;
+  if (kp) {
+    SID_CHECK(sid::launch_interp_mfma(ctx->stream, ip->dev, kp, acjt, pb, n, (float*)Ahat, ldo,
+                                      nullptr, 0, nullptr, 0, nullptr),
+              "interpolated reconstruction");
+    return SID_OK;
+  }
+  const size_t es = dtype == SID_F64 ? sizeof(double) : sizeof(float);
+  void* B = ws(ctx, WS_IB, es * (size_t)ip->N * (size_t)k);
+  if (!B) return SID_ENOMEM;
+  SID_CHECK(sid::launch_interp_apply(ctx->stream, ip->dev, dtype == SID_F64, ACJ, ldacj, (int)k, B,
+                                     ip->N),
+            "Mf ACJ");
+  SID_CHECK(sid::launch_reconstruct(ctx->stream, dtype == SID_F64, B, ip->N, P, ldp, ip->N,
+                                    (int)k, n, Ahat, ldo),
+            "reconstruct");
+  return SID_OK;
+}
+
+sid_status sid_interp_error_norms(sid_ctx* ctx, const sid_interp* ip, const void* A,
+                                  int64_t lda, const void* ACJ, int64_t ldacj, const void* P,
+                                  int64_t ldp, sid_dtype dtype, int64_t k, int64_t n,
+                                  double* out4) {
+  if (!ctx) return SID_EINVAL;
+  sid_status s = interp_check(ctx, ip, ACJ, ldacj, P, ldp, dtype, k, n);
+  if (s != SID_OK) return s;
+  if (!A || !out4) return fail(ctx, SID_EINVAL, "null pointer");
+  if (lda < ip->N) return fail(ctx, SID_EINVAL, "lda < N");
+  SID_NEED_DEVICE(ctx);
+  SID_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+  double* dout = (double*)ws(ctx, WS_NORMOUT, sizeof(double) * 4);
+  if (!dout) return SID_ENOMEM;
+  int kp = 0;
+  float* acjt = nullptr;
+  void* pb = nullptr;
+  s = interp_prepare(ctx, ip, ACJ, ldacj, P, ldp, dtype, k, n, &kp, &acjt, &pb);
+  if (s != SID_OK) return s;
+  if (kp) {
+    const int64_t nb = sid::interp_mfma_blocks(ip->N);
+    double* part = (double*)ws(ctx, WS_IPART, sizeof(double) * 4 * (size_t)nb);
+    if (!part) return SID_ENOMEM;
+    SID_CHECK(sid::launch_interp_mfma(ctx->stream, ip->dev, kp, acjt, pb, n, nullptr, 0,
+                                      (const float*)A, lda, part, nb, dout),
+              "interpolated error norms");
+  } else {
+    const size_t es = dtype == SID_F64 ? sizeof(double) : sizeof(float);
+    void* B = ws(ctx, WS_IB, es * (size_t)ip->N * (size_t)k);
+    const int64_t nb = ((ip->N + 63) / 64) * ((n + 31) / 32);
+    double* part = (double*)ws(ctx, WS_NORMPART, sizeof(double) * 4 * (size_t)nb);
+    if (!B || !part) return SID_ENOMEM;
+    SID_CHECK(sid::launch_interp_apply(ctx->stream, ip->dev, dtype == SID_F64, ACJ, ldacj, (int)k,
+                                       B, ip->N),
+              "Mf ACJ");
+    SID_CHECK(sid::launch_error_norms(ctx->stream, dtype == SID_F64, A, lda, B, ip->N, P, ldp,
+                                      ip->N, (int)k, n, part, nb, dout),
+              "error norms");
+  }
+  SID_CHECK(hipMemcpyAsync(out4, dout, 4 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
+            "copy norms");
+  SID_CHECK(hipStreamSynchronize(ctx->stream), "synchronize");
+  return SID_OK;
 }
 
 }  // extern "C"

@@ -213,3 +213,90 @@ def test_literal_select_validation(vctx):
     out = ctypes.c_void_p()
     p.select = 1
     assert L.sid_stream_begin(h, 1, 100, 20, ctypes.byref(p), ctypes.byref(out)) == EINVAL
+
+
+def _mesh(n=(6, 5, 4), coarse=((0, 2, 4), (0, 2, 4), (0, 3)), coords=(None, None, None),
+          period=(0.0, 0.0, 0.0), ncomp=2):
+    m = _native._Mesh()
+    m.ncomp = ncomp
+    keep = []
+    for d in range(3):
+        m.n[d] = n[d]
+        c = np.asarray(coarse[d], dtype=np.int64)
+        keep.append(c)
+        m.coarse[d] = c.ctypes.data
+        m.ncoarse[d] = c.size
+        if coords[d] is not None:
+            x = np.asarray(coords[d], dtype=np.float64)
+            keep.append(x)
+            m.coord[d] = x.ctypes.data
+        m.period[d] = period[d]
+    return m, keep
+
+
+@pytest.mark.parametrize("kw,code", [
+    ({}, ESTATE),                                                   # valid: no device
+    (dict(ncomp=0), EINVAL),
+    (dict(coarse=((0, 2, 2), (0, 2, 4), (0, 3))), EINVAL),          # not increasing
+    (dict(coarse=((0, 2, 6), (0, 2, 4), (0, 3))), EINVAL),          # out of range
+    (dict(coarse=((), (0, 2, 4), (0, 3))), EINVAL),                 # empty
+    (dict(coords=((0, 1, 2, 2, 4, 5), None, None)), EINVAL),        # coordinates not increasing
+    (dict(period=(4.0, 0.0, 0.0)), EINVAL),                         # coarse span 4 >= period
+    (dict(period=(4.5, 0.0, -1.0)), EINVAL),                        # negative period
+    (dict(period=(4.5, 0.0, 0.0)), ESTATE),                         # periodic x, valid
+    (dict(n=(1 << 20, 1 << 10, 4), coarse=((0,), (0,), (0,))), EINVAL),  # N >= 2^31
+])
+def test_interp_mesh_validation(vctx, kw, code):
+    """The structured grid of Alg. 6 is checked on the host before anything
+    touches a device."""
+    L, h = vctx
+    m, keep = _mesh(**kw)
+    out = ctypes.c_void_p()
+    assert L.sid_interp_create(h, ctypes.byref(m), ctypes.byref(out)) == code, L.sid_last_error(h)
+    m.reserved = 1
+    assert L.sid_interp_create(h, ctypes.byref(m), ctypes.byref(out)) == EINVAL
+
+
+def test_interp_calls_validate(vctx):
+    L, h = vctx
+    vp = ctypes.c_void_p
+    out4 = (ctypes.c_double * 4)()
+    assert L.sid_interp_reconstruct(h, None, vp(1), 10, vp(1), 3, 1, 3, 5, vp(1), 10) == EINVAL
+    assert L.sid_interp_error_norms(h, None, vp(1), 10, vp(1), 10, vp(1), 3, 1, 3, 5,
+                                    out4) == EINVAL
+    assert L.sid_interp_destroy(None) == EINVAL
+    assert L.sid_interp_info(None, None, None) == EINVAL
+    assert L.sid_interp_rowset(None) is None
+    assert L.sid_interp_create(h, None, ctypes.byref(vp())) == EINVAL
+
+
+def test_coarse_skeleton_mode_validation(vctx):
+    """Alg. 6 mode: needs a coarse row set and is not streamed."""
+    L, h = vctx
+    p = _params(L, 5)
+    p.mode = 2
+    assert L.sid_reserve(h, 100, 20, ctypes.byref(p)) == EINVAL
+    assert b"coarse" in L.sid_last_error(h)
+    out = ctypes.c_void_p()
+    assert L.sid_stream_begin(h, 1, 100, 20, ctypes.byref(p), ctypes.byref(out)) == EINVAL
+    p.mode = 3
+    assert L.sid_reserve(h, 100, 20, ctypes.byref(p)) == EINVAL
+
+
+def test_mesh_struct_layout(tmp_path):
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "mesh.c"
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "sid.h"\nint main(void){\n'
+                   'printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(sid_mesh), offsetof(sid_mesh, n),'
+                   ' offsetof(sid_mesh, coord), offsetof(sid_mesh, coarse),'
+                   ' offsetof(sid_mesh, ncoarse), offsetof(sid_mesh, period));\nreturn 0;}\n')
+    exe = tmp_path / "mesh"
+    subprocess.check_call([cc, "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    M = _native._Mesh
+    assert got == [ctypes.sizeof(M), M.n.offset, M.coord.offset, M.coarse.offset,
+                   M.ncoarse.offset, M.period.offset]

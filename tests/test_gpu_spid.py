@@ -1,0 +1,275 @@
+"""GPU parity of the single-pass ID with interpolation (Alg. 6): the
+coarse-skeleton compression mode, the trilinear coarse-to-fine operator and
+the fused reconstruction / error kernels, against the CPU oracle
+(``oracle.spid``) on the same seeded inputs.  Marked gpu.
+
+Tolerance of the FP32 matrix-core reconstruction, derived from its
+arithmetic: an entry sum_t b_t p_t with b = Mf ACJ formed in FP32 from 8
+terms, both factors split into bfloat16 hi + lo (each split leaves at most
+2^-18 of the value) and the lo*lo product dropped, accumulated in FP32 over
+3 kp products: |error| <= (3 * 2^-18 + (3 kp + 8) 2^-24) * sum_t |b|_t |p_t|
+with |b| = |Mf| |ACJ|; the tests allow twice that.  FP64: 1e-13 of the
+same bound."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sid():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1905_13257_amd as m
+    m.load()
+    return m
+
+
+@pytest.fixture(scope="module")
+def spid():
+    import oracle
+    oracle.build()
+    from oracle import spid as s
+    return s
+
+
+def to_gpu(A64, dtype=torch.float32):
+    return synth.as_colmajor(torch.from_numpy(np.asfortranarray(A64)).to(dtype)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def tol(dtype, kp):
+    if dtype == torch.float64:
+        return 1e-13
+    return 2.0 * (3 * 2.0 ** -18 + (3 * kp + 8) * 2.0 ** -24)
+
+
+def bound(Mf, ACJ, P):
+    return np.asarray(abs(Mf) @ np.abs(ACJ)) @ np.abs(P)
+
+
+def _meshes():
+    rng = np.random.default_rng(21)
+    out = []
+    cfg = synth.SpectralConfig(nx=10, ny=7, nz=9)
+    out.append(("channel 2x2x2", synth.channel_mesh(cfg, (2, 2, 2))))
+    out.append(("channel periodic keep-last", synth.channel_mesh(cfg, (3, 2, 4), periodic=True,
+                                                                 keep_last=True)))
+    xs = tuple(np.sort(rng.uniform(0.0, 1.0, n)) for n in (11, 6, 13))
+    out.append(("nonuniform", synth.StructuredMesh(
+        2, (11, 6, 13), xs, (np.array([1, 4, 5, 9]), np.array([0, 5]), np.arange(0, 13, 3)),
+        (1.3, 0.0, 0.0))))
+    out.append(("single node y", synth.StructuredMesh(
+        1, (9, 3, 17), (None, None, None), (np.arange(0, 9, 2), np.array([1]), np.arange(0, 17, 4)),
+        (0.0, 0.0, 0.0))))
+    return out
+
+
+def _coords(mesh):
+    return synth.StructuredMesh(mesh.ncomp, mesh.n,
+                                tuple(np.arange(n, dtype=np.float64) if c is None else c
+                                      for n, c in zip(mesh.n, mesh.coords)),
+                                mesh.coarse, mesh.period)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("case", range(4))
+def test_interp_operator(sid, spid, dtype, case):
+    """Mf X for P = I (k = n): the trilinear operator alone, against the
+    oracle's explicit sparse Mf, on bounded, periodic, non-uniform and
+    single-node dimensions with ragged row counts."""
+    name, mesh = _meshes()[case]
+    say("interp operator", name, dtype)
+    om = _coords(mesh)
+    Mf = spid.interp_operator(om)
+    ip = sid.Interp(mesh)
+    assert (ip.N, ip.Nc) == Mf.shape
+    rng = np.random.default_rng(case)
+    for k in (5, 32, 100, 128):
+        X = rng.standard_normal((ip.Nc, k)).astype(np.float32).astype(np.float64)
+        I = np.eye(k)
+        got = host(sid.interp_reconstruct(ip, to_gpu(X, dtype), to_gpu(I, dtype)))
+        ref = np.asarray(Mf @ X)
+        kp = (k + 31) // 32 * 32
+        err = np.abs(got - ref)
+        b = bound(Mf, X, I)
+        assert np.all(err <= tol(dtype, kp) * b + 1e-300), (k, (err / b).max())
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_coarse_skeleton_mode(sid, spid, dtype):
+    """Alg. 6 compression: J, P and err bit-identical to the two-pass
+    sub-sampled ID with the same parameters; the coarse skeleton is exactly
+    A(S, J); J agrees with the oracle up to near-ties."""
+    cfg = synth.SpectralConfig(nx=24, ny=12, nz=16, n_snapshots=90, n_modes=60, drift=0.02,
+                               seed=5)
+    A64 = synth.spectral_snapshots(cfg, dtype=torch.float64).numpy()
+    A = to_gpu(A64, dtype)
+    mesh = synth.channel_mesh(cfg, (2, 2, 2))
+    ip = sid.Interp(mesh)
+    S = mesh.coarse_rows
+    k, p, q = 20, 10, 5
+    for prec in (["f64"] if dtype == torch.float64 else ["f32", "bf16x2"]):
+        say("coarse skeleton", dtype, prec)
+        a = sid.compress(A, k, p, seed=4, coarse=ip.rowset, mode="coarse_skeleton", prec=prec,
+                         probe_rows=q)
+        b = sid.compress(A, k, p, seed=4, coarse=ip.rowset, mode="two_pass", prec=prec,
+                         probe_rows=q)
+        torch.cuda.synchronize()
+        assert a.AJ.shape == (S.size, k)
+        assert np.array_equal(host(a.J), host(b.J))
+        assert np.array_equal(host(a.P), host(b.P))
+        assert np.array_equal(host(a.err), host(b.err), equal_nan=True)
+        J = host(a.J)
+        ke = int(host(a.k_eff)[0])
+        Ad = A64.astype(np.float32).astype(np.float64) if dtype == torch.float32 else A64
+        assert np.array_equal(host(a.AJ).astype(np.float64)[:, :ke], Ad[np.ix_(S, J[:ke])])
+        ref = spid.spid_compress(Ad, mesh, k, p, seed=4, prec=prec, probe_rows=q)
+        ist = next((i for i, m in enumerate(ref.base.cp.margins) if m <= 1e-3), k)
+        assert J[:ist].tolist() == ref.J[:ist].tolist()
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("k,n", [(20, 45), (40, 64), (100, 130), (150, 170)])
+def test_interp_reconstruct_and_errors(sid, spid, dtype, k, n):
+    """The fused reconstruction Mf ACJ P (matrix-core path for FP32 with
+    k <= 128 at kp = 32, 64, 128; FMA path beyond) against the oracle on the
+    GPU's own ACJ and P, and the fused error kernel against the norms of
+    the GPU's own reconstruction."""
+    say("interp reconstruct", dtype, k, n)
+    cfg = synth.SpectralConfig(nx=20, ny=10, nz=12, n_snapshots=n, n_modes=60, drift=0.02,
+                               seed=9)
+    A64 = synth.spectral_snapshots(cfg, dtype=torch.float64).numpy()
+    A = to_gpu(A64, dtype)
+    mesh = synth.channel_mesh(cfg, (2, 2, 2), periodic=(k == 40))
+    Mf = spid.interp_operator(mesh)
+    ip = sid.Interp(mesh)
+    prec = "f64" if dtype == torch.float64 else "f32"
+    c = sid.compress(A, k, 10, seed=1, coarse=ip.rowset, mode="coarse_skeleton", prec=prec,
+                     probe_rows=0)
+    Ahat = sid.interp_reconstruct(ip, c.AJ, c.P)
+    torch.cuda.synchronize()
+    ACJ, P = host(c.AJ).astype(np.float64), host(c.P).astype(np.float64)
+    ref = spid.spid_reconstruct(Mf, ACJ, P)
+    kp = (k + 31) // 32 * 32 if k <= 128 else k
+    b = bound(Mf, ACJ, P)
+    err = np.abs(host(Ahat) - ref)
+    assert np.all(err <= tol(dtype, kp) * b + 1e-300), (err / np.maximum(b, 1e-300)).max()
+    # the error kernel = the norms of the reconstruction it would form (the
+    # same products; the FP32 FMA path beyond k = 128 accumulates the error
+    # kernel's products in FP64 and the reconstruction's in FP32)
+    e = sid.interp_error_norms(ip, A, c.AJ, c.P)
+    Ad = host(A).astype(np.float64)
+    D = Ad - host(Ahat).astype(np.float64)
+    same = dtype == torch.float64 or k <= 128
+    assert e["fro_a"] == pytest.approx(np.linalg.norm(Ad), rel=1e-12)
+    assert e["fro_err"] == pytest.approx(np.linalg.norm(D), rel=1e-9 if same else 1e-4)
+    assert e["max_abs"] == pytest.approx(np.abs(D).max(), rel=1e-12 if same else 1e-3)
+    if same:
+        nz = Ad != 0
+        assert e["rel_max"] == pytest.approx((np.abs(D[nz]) / np.abs(Ad[nz])).max(), rel=1e-12)
+    # and against the oracle's error of the oracle's reconstruction
+    o = spid.error_norms(A64 if dtype == torch.float64 else Ad, ref)
+    assert e["rel_fro"] == pytest.approx(o["rel_fro"], rel=1e-3 if dtype == torch.float32 else 1e-10)
+
+
+def test_interp_workspace_layouts(sid, spid):
+    """Leading dimensions larger than the rows for ACJ, P and Ahat (a
+    strided output leaves the padding untouched), and an Ahat with ldo not a
+    multiple of 4 (the scalar store path)."""
+    say("interp layouts")
+    cfg = synth.SpectralConfig(nx=8, ny=6, nz=10)
+    mesh = synth.channel_mesh(cfg, (2, 3, 3))
+    Mf = spid.interp_operator(mesh)
+    ip = sid.Interp(mesh)
+    rng = np.random.default_rng(2)
+    k, n = 24, 37
+    X = rng.standard_normal((ip.Nc, k)).astype(np.float32).astype(np.float64)
+    P = rng.standard_normal((k, n)).astype(np.float32).astype(np.float64)
+    ref = spid.spid_reconstruct(Mf, X, P)
+    b = bound(Mf, X, P)
+    Xs = torch.zeros((k, ip.Nc + 7), device="cuda").T[:ip.Nc]
+    Xs.copy_(torch.from_numpy(X).float())
+    Ps = torch.zeros((n, k + 3), device="cuda").T[:k]
+    Ps.copy_(torch.from_numpy(P).float())
+    for pad in (0, 5, 8):
+        store = torch.full((n, ip.N + pad), 7.0, device="cuda")
+        out = store.T[:ip.N]
+        sid.interp_reconstruct(ip, Xs, Ps, out=out)
+        torch.cuda.synchronize()
+        err = np.abs(host(out) - ref)
+        assert np.all(err <= tol(torch.float32, 32) * b), pad
+        if pad:
+            assert torch.all(store[:, ip.N:] == 7.0)
+
+
+def test_c3_full_size_sampled(sid, spid):
+    """The 12,582,912 x 1000 FP32 channel-like workload (3 x 256x128x128
+    grid, every other point kept, k = 100, bf16x2 sketch) at full size, in
+    the configuration the benchmark times: the coarse-skeleton compression
+    (P identical to the two-pass sub-sampled ID), the coarse skeleton on
+    sampled rows, the fused reconstruction on 96 sampled fine rows against
+    the oracle's rows of Mf, and the error kernel's norms against torch's
+    norms of the reconstruction."""
+    say("c3 full size: synthesizing")
+    cfg = synth.SpectralConfig(nx=256, ny=128, nz=128, n_snapshots=1000, seed=1002, drift=0.0095)
+    A = synth.spectral_snapshots(cfg, device="cuda")
+    mesh = synth.channel_mesh(cfg, (2, 2, 2))
+    ip = sid.Interp(mesh)
+    N, n = A.shape
+    k, p, q = 100, 20, 10
+    say("c3 full size: compress")
+    c = sid.compress(A, k, p, seed=0, coarse=ip.rowset, mode="coarse_skeleton", prec="bf16x2",
+                     probe_rows=q)
+    b = sid.compress(A, k, p, seed=0, coarse=ip.rowset, mode="two_pass", prec="bf16x2",
+                     probe_rows=q, want_skeleton=False)
+    torch.cuda.synchronize()
+    assert torch.equal(c.P, b.P) and torch.equal(c.J, b.J)
+    S = mesh.coarse_rows
+    J = host(c.J)
+    rng = np.random.default_rng(0)
+    srows = np.sort(rng.choice(S.size, 64, replace=False))
+    got = host(c.AJ[torch.from_numpy(srows).cuda()])
+    want = host(A[torch.from_numpy(S[srows]).cuda()][:, torch.from_numpy(J).cuda()])
+    assert np.array_equal(got, want)
+    say("c3 full size: reconstruct")
+    Ahat = sid.interp_reconstruct(ip, c.AJ, c.P)
+    torch.cuda.synchronize()
+    frows = np.sort(np.concatenate([rng.choice(N, 90, replace=False), [0, 1, N - 1],
+                                    [N // 3 - 1, N // 3, 2 * N // 3 + 5]]))
+    Mr = spid.interp_rows(mesh, frows)
+    ACJ = host(c.AJ).astype(np.float64)
+    P = host(c.P).astype(np.float64)
+    ref = spid.spid_rows(Mr, ACJ, P, None)
+    gotr = host(Ahat[torch.from_numpy(frows).cuda()]).astype(np.float64)
+    bb = bound(Mr, ACJ, P)
+    err = np.abs(gotr - ref)
+    # (rows on the walls are exactly zero for the wall-normal component: bound 0)
+    say("c3 full size: max err / bound", (err[bb > 0] / bb[bb > 0]).max())
+    assert np.all(err <= tol(torch.float32, 128) * bb)
+    say("c3 full size: error kernel")
+    e = sid.interp_error_norms(ip, A, c.AJ, c.P)
+    fa = fe = 0.0
+    for j0 in range(0, n, 50):
+        a = A[:, j0:j0 + 50].double()
+        fa += float(torch.sum(a * a))
+        fe += float(torch.sum((a - Ahat[:, j0:j0 + 50].double()) ** 2))
+        del a
+    fa = fa ** 0.5
+    say("c3 full size: rel_fro", e["rel_fro"], "torch", fe ** 0.5 / fa)
+    assert e["fro_a"] == pytest.approx(fa, rel=1e-9)
+    assert e["fro_err"] == pytest.approx(fe ** 0.5, rel=1e-7)
+    assert e["rel_fro"] < 0.2

@@ -187,3 +187,10 @@ def test_rows_sampler_matches_full_reconstruction():
     rows = np.array([0, 5, 17, mesh.rows - 1])
     np.testing.assert_allclose(spid.spid_rows(Mf, res.ACJ, res.P, rows), Ahat[rows],
                                rtol=1e-13, atol=1e-13)
+
+
+def test_interp_rows_match_operator():
+    mesh = _mesh(2, (6, 5, 7), (2, 3, 2), period=(1.5, 0.0, 0.0))
+    Mf = spid.interp_operator(mesh)
+    rows = np.array([0, 1, 37, 104, 105, mesh.rows - 1])
+    np.testing.assert_array_equal(spid.interp_rows(mesh, rows).toarray(), Mf[rows].toarray())
