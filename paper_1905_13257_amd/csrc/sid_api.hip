@@ -1523,7 +1523,7 @@ sid_status interp_prepare(sid_ctx* ctx, const sid_interp* ip, const void* ACJ, i
                           int* kp_out, float** acjt, void** pb) {
   *kp_out = 0;
   if (dtype != SID_F32 || k > 128) return SID_OK;
-  const int kp = (int)((k + 31) / 32 * 32);
+  const int kp = (int)((k + 15) / 16 * 16);
   *acjt = (float*)ws(ctx, WS_IACJT, sizeof(float) * (size_t)ip->Nc * (size_t)kp);
   *pb = ws(ctx, WS_IPB, sid::interp_pb_bytes(n, kp));
   if (!*acjt || !*pb) return SID_ENOMEM;

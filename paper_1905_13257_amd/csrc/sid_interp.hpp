@@ -28,15 +28,16 @@ hipError_t launch_gather_coarse_skeleton(hipStream_t st, const void* A, bool f64
 hipError_t launch_interp_apply(hipStream_t st, const InterpDev& t, bool f64, const void* ACJ,
                                int64_t ldacj, int k, void* B, int64_t ldb);
 
-// Matrix-core path (FP32, k <= 128): kp = k rounded up to 32.
+// Matrix-core path (FP32, k <= 128): kp = k rounded up to 16.
 //   acjt: Nc x kp row-major FP32 copy of ACJ (zero padded)
-//   pb:   P packed as bfloat16 hi/lo operand tiles, ceil(n/16) * kp/32 * 2 KiB
+//   pb:   P packed as bfloat16 hi/lo operand tiles, (ceil(n/32) + 3) * kp/16 * 2 KiB
 size_t interp_pb_bytes(int64_t n, int kp);
 hipError_t launch_interp_pack(hipStream_t st, const float* ACJ, int64_t ldacj, int64_t Nc, int k,
                               int kp, float* acjt, const float* P, int64_t ldp, int64_t n,
                               void* pb);
 // out = Mf ACJ P (out != NULL), or, with A != NULL, 4 error partials per
-// 256-row block into part (part_cap entries of 4) reduced into out4.
+// row block (interp_mfma_blocks) into part (part_cap entries of 4) reduced
+// into out4.
 int64_t interp_mfma_blocks(int64_t N);
 hipError_t launch_interp_mfma(hipStream_t st, const InterpDev& t, int kp, const float* acjt,
                               const void* pb, int64_t n, float* out, int64_t ldo, const float* A,

@@ -999,9 +999,4 @@ hipError_t launch_error_norms(hipStream_t st, bool f64, const void* A, int64_t l
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_norms(hipStream_t st, const double* part, int64_t nb, double* out4) {
-  hipLaunchKernelGGL(k_reduce_norms, dim3(1), dim3(256), 0, st, part, nb, out4);
-  return hipGetLastError();
-}
-
 }  // namespace sid

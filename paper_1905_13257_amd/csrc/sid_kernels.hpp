@@ -56,9 +56,6 @@ hipError_t launch_reconstruct(hipStream_t st, bool f64, const void* AJ, int64_t 
 hipError_t launch_error_norms(hipStream_t st, bool f64, const void* A, int64_t lda,
                               const void* AJ, int64_t ldaj, const void* P, int64_t ldp, int64_t N,
                               int k, int64_t n, double* part, int64_t part_cap, double* out4);
-// sums of the first two and maxima of the last two of nb groups of 4 partials
-// -> out4 = (sqrt(sum0), sqrt(sum1), max2, max3)
-hipError_t launch_reduce_norms(hipStream_t st, const double* part, int64_t nb, double* out4);
 
 }  // namespace sid
 

@@ -7,7 +7,8 @@ Tolerance of the FP32 matrix-core reconstruction, derived from its
 arithmetic: an entry sum_t b_t p_t with b = Mf ACJ formed in FP32 from 8
 terms, both factors split into bfloat16 hi + lo (each split leaves at most
 2^-18 of the value) and the lo*lo product dropped, accumulated in FP32 over
-3 kp products: |error| <= (3 * 2^-18 + (3 kp + 8) 2^-24) * sum_t |b|_t |p_t|
+3 kp products (kp = k rounded up to 16): |error| <= (3 * 2^-18 + (3 kp + 8) 2^-24)
+* sum_t |b|_t |p_t|
 with |b| = |Mf| |ACJ|; the tests allow twice that.  FP64: 1e-13 of the
 same bound."""
 import sys
@@ -98,12 +99,12 @@ def test_interp_operator(sid, spid, dtype, case):
     ip = sid.Interp(mesh)
     assert (ip.N, ip.Nc) == Mf.shape
     rng = np.random.default_rng(case)
-    for k in (5, 32, 100, 128):
+    for k in (5, 32, 48, 64, 80, 90, 100, 128):   # kp/16 = 1 .. 8
         X = rng.standard_normal((ip.Nc, k)).astype(np.float32).astype(np.float64)
         I = np.eye(k)
         got = host(sid.interp_reconstruct(ip, to_gpu(X, dtype), to_gpu(I, dtype)))
         ref = np.asarray(Mf @ X)
-        kp = (k + 31) // 32 * 32
+        kp = (k + 15) // 16 * 16
         err = np.abs(got - ref)
         b = bound(Mf, X, I)
         assert np.all(err <= tol(dtype, kp) * b + 1e-300), (k, (err / b).max())
@@ -146,7 +147,7 @@ def test_coarse_skeleton_mode(sid, spid, dtype):
 @pytest.mark.parametrize("k,n", [(20, 45), (40, 64), (100, 130), (150, 170)])
 def test_interp_reconstruct_and_errors(sid, spid, dtype, k, n):
     """The fused reconstruction Mf ACJ P (matrix-core path for FP32 with
-    k <= 128 at kp = 32, 64, 128; FMA path beyond) against the oracle on the
+    k <= 128 at kp = 32, 48, 112; FMA path beyond) against the oracle on the
     GPU's own ACJ and P, and the fused error kernel against the norms of
     the GPU's own reconstruction."""
     say("interp reconstruct", dtype, k, n)
@@ -164,7 +165,7 @@ def test_interp_reconstruct_and_errors(sid, spid, dtype, k, n):
     torch.cuda.synchronize()
     ACJ, P = host(c.AJ).astype(np.float64), host(c.P).astype(np.float64)
     ref = spid.spid_reconstruct(Mf, ACJ, P)
-    kp = (k + 31) // 32 * 32 if k <= 128 else k
+    kp = (k + 15) // 16 * 16 if k <= 128 else k
     b = bound(Mf, ACJ, P)
     err = np.abs(host(Ahat) - ref)
     assert np.all(err <= tol(dtype, kp) * b + 1e-300), (err / np.maximum(b, 1e-300)).max()
@@ -259,7 +260,7 @@ def test_c3_full_size_sampled(sid, spid):
     err = np.abs(gotr - ref)
     # (rows on the walls are exactly zero for the wall-normal component: bound 0)
     say("c3 full size: max err / bound", (err[bb > 0] / bb[bb > 0]).max())
-    assert np.all(err <= tol(torch.float32, 128) * bb)
+    assert np.all(err <= tol(torch.float32, 112) * bb)
     say("c3 full size: error kernel")
     e = sid.interp_error_norms(ip, A, c.AJ, c.P)
     fa = fe = 0.0
