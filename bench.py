@@ -208,6 +208,43 @@ def spid_main(args, torch, sid, synth) -> int:
     return 0
 
 
+def adaptive_main(args, torch, sid, synth) -> int:
+    """Tolerance-driven rank (Remark 2.2, probe estimator as the stopping
+    test) on the headline matrix: single pass at k <= 100, p = 20, q = 10,
+    for a few tolerances; the step includes the prefix-error pass."""
+    cfg = synth.SpectralConfig()
+    k, p, q = 100, 20, 10
+    A = synth.spectral_snapshots(cfg, device="cuda")
+    torch.cuda.synchronize()
+    N, n = A.shape
+    kw = dict(seed=0, mode="single_pass", prec=args.prec, probe_rows=q)
+    base = sid.compress(A, k, p, **kw)
+    ms_fixed = time_steps(lambda: sid.compress(A, k, p, out=base, **kw), args.steps, args.warmup,
+                          torch)
+    rows = []
+    for tol in (3e-2, 1e-2, 5e-3):
+        out = sid.compress(A, k, p, probe_tol=tol, **kw)
+        ms = time_steps(lambda: sid.compress(A, k, p, out=out, probe_tol=tol, **kw), args.steps,
+                        args.warmup, torch)
+        ke = int(out.k_eff[0])
+        err = sid.error_norms(A, out.AJ[:, :ke], out.P[:ke])
+        rows.append({"probe_tol": tol, "k_eff": ke, "ms_per_step": round(ms, 4),
+                     "probe_estimate": float(out.err[0]), "rel_fro_error": err["rel_fro"]})
+    first = rows[0]
+    line = {
+        "metric": "snapshot GB/s compressed (single-pass ID, rank chosen by probe_tol)",
+        "value": round(N * n * 4 / (first["ms_per_step"] * 1e-3) / 1e9, 2), "unit": "GB/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": first["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
+        "config": {"workload": "channel-like snapshots 1572864 x 500 fp32, single-pass ID, "
+                               "k <= 100 p=20 q=10, probe_tol 3e-2 (value) / 1e-2 / 5e-3",
+                   "tolerances": rows, "fixed_k100_ms": round(ms_fixed, 4)},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -234,6 +271,10 @@ def main() -> int:
                          "interpolation (Alg. 6) on the 256 x 128 x 128 grid (12,582,912 x 1000 "
                          "FP32), coarse rows = every other grid point, k=100 p=20: compression, "
                          "trilinear reconstruction of the fine matrix, and its error")
+    ap.add_argument("--adaptive", action="store_true",
+                    help="auxiliary measurement instead of the headline: the rank chosen by the "
+                         "held-out probe estimate (probe_tol 3e-2, 1e-2, 5e-3) on the headline "
+                         "matrix, single pass, k <= 100")
     ap.add_argument("--sketch-only", action="store_true",
                     help="profiling aid for hardware counters: a plain 1 GiB device copy (the "
                          "calibration kernel for FETCH_SIZE / WRITE_SIZE) and three sketch passes")
@@ -257,6 +298,8 @@ def main() -> int:
         return coarse_main(args, torch, sid, synth)
     if args.spid:
         return spid_main(args, torch, sid, synth)
+    if args.adaptive:
+        return adaptive_main(args, torch, sid, synth)
     cfg = synth.SpectralConfig()
     k, p, q = 100, 20, 10
     A = synth.spectral_snapshots(cfg, device="cuda")

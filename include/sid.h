@@ -130,11 +130,24 @@ typedef struct {
                                   once more, sid_compress only)                  */
     sid_sketch_prec refine_prec; /* precision of the refinement sketch          */
     sid_select select;         /* SID_SEL_GAUSS (default) or SID_SEL_ROWS_LITERAL */
+    double probe_tol;          /* 0: off; > 0: the smallest rank k_eff whose ID fits
+                                  the held-out probe rows to probe_tol (Remark 2.2
+                                  with the probe rows as the stopping test); needs
+                                  probe_rows > 0 and select GAUSS               */
 } sid_params;
 
 /* Fill a parameter block with defaults: oversample 10, seed 0, all rows,
  * two-pass, F32 sketch, probe_rows 10, corange_rows -1, rank_tol 0,
- * sp_rcond 0, refine 0, refine_prec BF16X2, select GAUSS.
+ * sp_rcond 0, refine 0, refine_prec BF16X2, select GAUSS, probe_tol 0.
+ * Adaptive rank (probe_tol > 0): mgsqr runs to k (or to its rank_tol stop);
+ * then, with Z = W_pr(:, J) R11^-1, the probe fit of the first k' pivots is
+ * Z(:, 0:k') R(0:k', :) for every k', and k_eff becomes the smallest k' with
+ * ||W_pr - Z(:, 0:k') R(0:k', :)||_F <= probe_tol ||W_pr||_F (k_eff stays at
+ * mgsqr's count when none qualifies).  J, P, AJ and err then follow k_eff;
+ * err[1] is the sketch fit at that rank.  In two-pass modes err[0] is that
+ * same probe fit (so err[0] <= probe_tol when a rank qualified); in single
+ * pass err[0] also carries the error of the estimated skeleton and can be
+ * larger.
  * Refinement (refine = 1; the paper stops at the ID): after J and P0 are
  * chosen, A is sketched once more with Psi's selection rows in refine_prec,
  * W' = Psi_sel A, and P0 takes one step of iterative refinement of the

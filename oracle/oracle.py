@@ -353,6 +353,35 @@ def skeleton_single_pass(Y: np.ndarray, W: np.ndarray, J: np.ndarray, lz: int, r
     return Q @ X, Zfull, X
 
 
+def probe_prefix_errors(cp: CPQR, Wpr: np.ndarray, n: int) -> np.ndarray:
+    """Relative probe fit of every prefix of the pivots: entry k' (1 <= k' <=
+    k_eff) is ||W_pr - W_pr(:, J') P'|| / ||W_pr|| with J' the first k'
+    pivots and P' their ID coefficients (from the first k' rows of R), each
+    formed from its definition."""
+    out = np.full(cp.k_eff + 1, np.nan)
+    out[0] = 1.0
+    for kp in range(1, cp.k_eff + 1):
+        Jp = cp.J[:kp]
+        Pp = id_coefficients(cp.R[:kp], Jp, n)
+        out[kp] = _rel_fit(Wpr, Wpr[:, Jp] @ Pp)
+    return out
+
+
+def adaptive_rank(cp: CPQR, Wpr: np.ndarray, n: int, tol: float) -> CPQR:
+    """Tolerance-driven rank (Remark 2.2: ID stops on a criterion instead of
+    a fixed k), with the held-out probe rows as the stopping test: the
+    smallest k' whose relative probe fit is <= tol (k_eff unchanged when no
+    prefix meets it); the first k' pivot steps of mgsqr are those of a run
+    stopped at k'."""
+    e = probe_prefix_errors(cp, Wpr, n)
+    hit = [kp for kp in range(1, cp.k_eff + 1) if e[kp] <= tol]
+    if not hit:
+        return cp
+    kp = hit[0]
+    return CPQR(J=cp.J[:kp], R=cp.R[:kp], Q=cp.Q[:, :kp], k_eff=kp, margins=cp.margins[:kp],
+                pivot_norms=cp.pivot_norms[:kp], final_residual=None)
+
+
 def _rel_fit(Wpart: np.ndarray, approx: np.ndarray) -> float:
     den = np.linalg.norm(Wpart)
     return float(np.linalg.norm(Wpart - approx) / den) if den > 0 else 0.0
@@ -400,7 +429,7 @@ def compress_literal(A, k: int, coarse_rows, prec: str = "f64", rank_tol: float 
 def compress(A, k: int, oversample: int, seed: int = 0, coarse_rows=None,
              mode: str = "two_pass", prec: str = "f64", probe_rows: int = 10,
              rank_tol: float = 0.0, sp_rcond: float = 1e-12,
-             corange_extra: int | None = None) -> Result:
+             corange_extra: int | None = None, probe_tol: float = 0.0) -> Result:
     """Randomized / sub-sampled ID (Alg. 4-5) or its single-pass form.
 
     A: N x n array (any float type; FP32 data are promoted exactly).
@@ -431,6 +460,8 @@ def compress(A, k: int, oversample: int, seed: int = 0, coarse_rows=None,
     if mode == "single_pass":
         Y = sketch_y(A, omega(seed, n, l, prec), prec)
     cp = cpqr(W[:l], k, rank_tol)
+    if probe_tol > 0.0:
+        cp = adaptive_rank(cp, W[lz:], n, probe_tol)
     Pk = id_coefficients(cp.R, cp.J, n)
     P = np.zeros((k, n))
     P[:cp.k_eff] = Pk

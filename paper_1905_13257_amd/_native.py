@@ -50,6 +50,7 @@ class _Params(ctypes.Structure):
         ("refine", ctypes.c_int32),
         ("refine_prec", ctypes.c_int),
         ("select", ctypes.c_int),
+        ("probe_tol", ctypes.c_double),
     ]
 
 
@@ -236,7 +237,8 @@ class RowSet:
 
 
 def _params(k, oversample, seed, coarse, mode, prec, probe_rows, rank_tol, sp_rcond,
-            corange_rows=-1, refine=False, refine_prec="bf16x2", select="gauss") -> _Params:
+            corange_rows=-1, refine=False, refine_prec="bf16x2", select="gauss",
+            probe_tol=0.0) -> _Params:
     p = _Params()
     load().sid_params_init(ctypes.byref(p), int(k))
     p.oversample = int(oversample)
@@ -251,6 +253,7 @@ def _params(k, oversample, seed, coarse, mode, prec, probe_rows, rank_tol, sp_rc
     p.refine = 1 if refine else 0
     p.refine_prec = PRECISIONS[refine_prec]
     p.select = SELECT[select]
+    p.probe_tol = float(probe_tol)
     return p
 
 
@@ -282,7 +285,7 @@ def _new_outputs(N: int, n: int, k: int, dtype, dev, want_skeleton: bool) -> Com
 def compress_batched(mats: list, k, oversample=10, seed=0, mode: str = "two_pass",
                      prec: str = "f32", probe_rows=10, rank_tol: float = 0.0,
                      sp_rcond: float = 0.0, want_skeleton: bool = True,
-                     ctx: Context | None = None) -> list:
+                     ctx: Context | None = None, probe_tol: float = 0.0) -> list:
     """Rank-k column IDs of several matrices in one call (sid_compress_batched).
     k, oversample, seed and probe_rows may be scalars or one value per matrix;
     all matrices share dtype, mode and precision."""
@@ -301,7 +304,8 @@ def compress_batched(mats: list, k, oversample=10, seed=0, mode: str = "two_pass
         A, lda = _colmajor(A)
         N, n = A.shape
         o = _new_outputs(N, n, ks[b], dtype, A.device, want_skeleton)
-        p = _params(ks[b], ovs[b], seeds[b], None, mode, prec, qs[b], rank_tol, sp_rcond)
+        p = _params(ks[b], ovs[b], seeds[b], None, mode, prec, qs[b], rank_tol, sp_rcond,
+                    probe_tol=probe_tol)
         probs[b] = _Problem(ctypes.c_void_p(A.data_ptr()), N, n, lda, p, _ptr(o.J), _ptr(o.P),
                             o.P.stride(1), _ptr(o.AJ), o.AJ.stride(1) if o.AJ is not None else 1,
                             _ptr(o.err), _ptr(o.k_eff))
@@ -316,10 +320,13 @@ def compress(A: torch.Tensor, k: int, oversample: int = 10, seed: int = 0,
              probe_rows: int = 10, rank_tol: float = 0.0, sp_rcond: float = 0.0,
              corange_rows: int = -1, want_skeleton: bool = True, ctx: Context | None = None,
              out: Compressed | None = None, refine: bool = False,
-             refine_prec: str = "bf16x2", select: str = "gauss") -> Compressed:
+             refine_prec: str = "bf16x2", select: str = "gauss",
+             probe_tol: float = 0.0) -> Compressed:
     """Rank-k column ID of A (N x n, float32/float64 on the GPU); refine=True
     adds one refinement pass of P on a refine_prec sketch; select="literal"
-    runs mgsqr on the coarse rows A(S, :) themselves (Alg. 5 as written)."""
+    runs mgsqr on the coarse rows A(S, :) themselves (Alg. 5 as written);
+    probe_tol > 0 picks the smallest rank <= k whose probe estimate meets it
+    (out.k_eff)."""
     ctx = ctx or default_context(A.device)
     A, lda = _colmajor(A)
     N, n = A.shape
@@ -334,7 +341,7 @@ def compress(A: torch.Tensor, k: int, oversample: int = 10, seed: int = 0,
         keff = torch.empty(1, dtype=torch.int64, device=dev)
         out = Compressed(J, P, AJ, err, keff)
     p = _params(k, oversample, seed, coarse, mode, prec, probe_rows, rank_tol, sp_rcond,
-                corange_rows, refine, refine_prec, select)
+                corange_rows, refine, refine_prec, select, probe_tol)
     ldaj = out.AJ.stride(1) if out.AJ is not None else 1
     ctx.check(ctx._lib.sid_compress(
         ctx.handle, _ptr(A), _dtype_code(A), N, n, lda, ctypes.byref(p), _ptr(out.J),
@@ -345,12 +352,13 @@ def compress(A: torch.Tensor, k: int, oversample: int = 10, seed: int = 0,
 def reserve(N: int, n: int, k: int, oversample: int = 10, mode: str = "two_pass",
             prec: str = "f32", probe_rows: int = 10, coarse: RowSet | None = None,
             corange_rows: int = -1, refine: bool = False, refine_prec: str = "bf16x2",
-            select: str = "gauss", ctx: Context | None = None) -> None:
+            select: str = "gauss", probe_tol: float = 0.0,
+            ctx: Context | None = None) -> None:
     """Allocate ahead of time everything a compress of this shape needs
     (sid_reserve); later compress calls allocate nothing (graph capture)."""
     ctx = ctx or default_context()
     p = _params(k, oversample, 0, coarse, mode, prec, probe_rows, 0.0, 0.0, corange_rows,
-                refine, refine_prec, select)
+                refine, refine_prec, select, probe_tol)
     ctx.check(ctx._lib.sid_reserve(ctx.handle, N, n, ctypes.byref(p)))
 
 
@@ -428,13 +436,13 @@ class Stream:
                  dtype: torch.dtype = torch.float32, mode: str = "single_pass",
                  prec: str = "f32", probe_rows: int = 10, rank_tol: float = 0.0,
                  sp_rcond: float = 0.0, corange_rows: int = -1, coarse: RowSet | None = None,
-                 ctx: Context | None = None):
+                 ctx: Context | None = None, probe_tol: float = 0.0):
         self.ctx = ctx or default_context()
         self.N, self.k, self.dtype = N, k, dtype
         self.mode = mode
         self.coarse = coarse  # kept alive with the stream
         p = _params(k, oversample, seed, coarse, mode, prec, probe_rows, rank_tol, sp_rcond,
-                    corange_rows)
+                    corange_rows, probe_tol=probe_tol)
         h = ctypes.c_void_p()
         code = SID_F64 if dtype == torch.float64 else SID_F32
         self.ctx.check(self.ctx._lib.sid_stream_begin(self.ctx.handle, code, N, n_max,

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/sid.h"
+#include "sid_adaptive.hpp"
 #include "sid_interp.hpp"
 #include "sid_kernels.hpp"
 
@@ -20,7 +21,7 @@ namespace {
 enum Slot {
   WS_OMEGA, WS_PART, WS_W, WS_WR, WS_NRM, WS_PIV, WS_R, WS_Q, WS_KEFF, WS_STATS, WS_PD,
   WS_ERR, WS_Y, WS_M, WS_MPR, WS_WJ, WS_PIVM, WS_RM, WS_QM, WS_RKM, WS_C, WS_T, WS_MIX,
-  WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COOP, WS_SYNC, WS_R11, WS_FITPART, WS_YTMP, WS_REF_W, WS_REF_WJ, WS_REF_T, WS_REF_G, WS_OMP, WS_A8, WS_IACJT, WS_IPB, WS_IB, WS_IPART, WS_COUNT
+  WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COOP, WS_SYNC, WS_R11, WS_FITPART, WS_YTMP, WS_REF_W, WS_REF_WJ, WS_REF_T, WS_REF_G, WS_OMP, WS_A8, WS_IACJT, WS_IPB, WS_IB, WS_IPART, WS_AZ, WS_AE2, WS_APART, WS_COUNT
 };
 
 struct Buf {
@@ -168,6 +169,10 @@ sid_status validate(sid_ctx* ctx, int64_t N, int64_t n, const sid_params* p, Sha
     return fail(ctx, SID_EINVAL, "unknown refinement precision");
   if (p->select != SID_SEL_GAUSS && p->select != SID_SEL_ROWS_LITERAL)
     return fail(ctx, SID_EINVAL, "unknown select");
+  if (!(p->probe_tol >= 0.0) || !std::isfinite(p->probe_tol))
+    return fail(ctx, SID_EINVAL, "probe_tol must be finite and >= 0");
+  if (p->probe_tol > 0.0 && (p->probe_rows < 1 || p->select != SID_SEL_GAUSS))
+    return fail(ctx, SID_EINVAL, "an adaptive rank (probe_tol > 0) needs probe rows");
   if (p->select == SID_SEL_ROWS_LITERAL) {
     if (!p->coarse) return fail(ctx, SID_EINVAL, "literal selection needs a coarse row set");
     if (p->mode == SID_SINGLE_PASS)
@@ -224,6 +229,7 @@ int64_t skeleton_rows(const sid_params* p, int64_t N) {
 }
 
 struct Work {
+  double *az, *ae2, *apart;  // adaptive rank: Z (q x k), prefix errors (k + 1), partials
   float* omega;
   double *part, *W, *Wr, *nrm, *R, *Q, *stats, *Pd, *err;
   int64_t *piv, *keff;
@@ -251,7 +257,11 @@ sid_status reserve(sid_ctx* c, const Shape& s, Work* w) {
   w->stats = (double*)ws(c, WS_STATS, d * 2);
   w->Pd = (double*)ws(c, WS_PD, d * (size_t)(s.k * s.n));
   w->err = (double*)ws(c, WS_ERR, d * 2);
-  w->fitpart = (double*)ws(c, WS_FITPART, d * (size_t)(2 * ((s.q * s.n + 255) / 256) + 2));
+  {
+    // the probe rows, or (adaptive rank) the selection rows at the chosen rank
+    const int64_t fr = s.q > s.l ? s.q : s.l;
+    w->fitpart = (double*)ws(c, WS_FITPART, d * (size_t)(2 * ((fr * s.n + 255) / 256) + 2));
+  }
   if (!w->fitpart) return SID_ENOMEM;
   {
     const int mmax = (int)s.lz;
@@ -265,6 +275,11 @@ sid_status reserve(sid_ctx* c, const Shape& s, Work* w) {
   if (!w->omega || !w->part || !w->W || !w->Wr || !w->nrm || !w->piv || !w->R || !w->Q ||
       !w->keff || !w->stats || !w->Pd || !w->err)
     return SID_ENOMEM;
+  w->az = (double*)ws(c, WS_AZ, d * (size_t)((s.q > 0 ? s.q : 1) * s.k));
+  w->ae2 = (double*)ws(c, WS_AE2, d * (size_t)(s.k + 1));
+  w->apart = (double*)ws(c, WS_APART, d * (size_t)(sid::probe_adapt_blocks((int)(s.q > 0 ? s.q : 1),
+                                                                           (int)s.n) * (s.k + 1)));
+  if (!w->az || !w->ae2 || !w->apart) return SID_ENOMEM;
   w->Y = nullptr;
   if (s.single) {
     const size_t ye = (s.prec == SID_SK_F64) ? d : sizeof(float);
@@ -320,6 +335,7 @@ void sid_params_init(sid_params* p, int64_t k) {
   p->refine = 0;
   p->refine_prec = SID_SK_BF16X2;
   p->select = SID_SEL_GAUSS;
+  p->probe_tol = 0.0;
 }
 
 sid_status sid_create(sid_ctx** out, int device, void* hip_stream) {
@@ -726,11 +742,24 @@ static sid_status factor(sid_ctx* ctx, const sid_params* p, const Shape& sh, con
     SID_CHECK(sid::launch_cpqr(st, w.W, lq, l, n_, k, p->rank_tol, w.Wr, w.nrm, w.piv, w.R, w.Q,
                                w.keff, w.stats),
               "pivoted QR");
+  // (2b) adaptive rank: the smallest prefix of the pivots whose probe fit
+  // meets probe_tol (Remark 2.2 with the probe estimator)
+  const bool adaptive = p->probe_tol > 0.0;
+  if (adaptive)
+    SID_CHECK(sid::launch_probe_adapt(st, w.W, lq, lz, q, n_, w.piv, w.keff, w.R, k, w.R11, w.az,
+                                      w.apart, w.ae2, p->probe_tol),
+              "adaptive rank");
   // (3) coefficients P = R11^{-1} R(:, j) on the non-pivot columns
   SID_CHECK(sid::launch_id_coefficients(st, w.R, n_, w.piv, w.keff, k, w.R11, w.Pd, P, ldp, f64),
             "coefficients");
-  // (4) estimates: err[1] sketch fit (final residual of mgsqr), err[0] probe rows
-  SID_CHECK(sid::launch_ratio_sqrt(st, w.stats, w.err + 1), "sketch residual");
+  // (4) estimates: err[1] sketch fit (final residual of mgsqr, or at an
+  // adaptive rank the fit of the selection rows), err[0] probe rows
+  if (adaptive)
+    SID_CHECK(sid::launch_fit_residual(st, w.W, lq, 0, l, n_, w.piv, w.keff, w.Pd, k, nullptr,
+                                       w.fitpart, w.err + 1),
+              "sketch residual");
+  else
+    SID_CHECK(sid::launch_ratio_sqrt(st, w.stats, w.err + 1), "sketch residual");
   if (!sh.single) {
     SID_CHECK(sid::launch_fit_residual(st, w.W, lq, l, q, n_, w.piv, w.keff, w.Pd, k, nullptr,
                                        w.fitpart, w.err),
@@ -934,7 +963,7 @@ struct StreamHeader {
   int64_t version, N, n_max, cols, dtype, y_init;
   int64_t k, oversample, mode, prec, probe_rows, corange_rows;
   uint64_t seed;
-  double rank_tol, sp_rcond;
+  double rank_tol, sp_rcond, probe_tol;
 };
 
 const char kStreamMagic[8] = {'S', 'I', 'D', 'S', 'T', 'R', 'M', '1'};
@@ -1122,7 +1151,7 @@ sid_status sid_stream_save(sid_stream* s, void* host_buf, size_t* bytes) {
   StreamHeader h;
   std::memset(&h, 0, sizeof(h));
   std::memcpy(h.magic, kStreamMagic, 8);
-  h.version = 1;
+  h.version = 2;
   h.N = s->N;
   h.n_max = s->n_max;
   h.cols = s->cols;
@@ -1137,6 +1166,7 @@ sid_status sid_stream_save(sid_stream* s, void* host_buf, size_t* bytes) {
   h.seed = s->p.seed;
   h.rank_tol = s->p.rank_tol;
   h.sp_rcond = s->p.sp_rcond;
+  h.probe_tol = s->p.probe_tol;
   char* out = (char*)host_buf;
   std::memcpy(out, &h, sizeof(h));
   if (wb) SID_CHECK(hipMemcpyAsync(out + sizeof(h), s->W, wb, hipMemcpyDeviceToHost, ctx->stream),
@@ -1156,7 +1186,7 @@ sid_status sid_stream_restore(sid_ctx* ctx, const void* host_buf, size_t bytes, 
   if (bytes < sizeof(StreamHeader)) return fail(ctx, SID_EINVAL, "stream state too short");
   StreamHeader h;
   std::memcpy(&h, host_buf, sizeof(h));
-  if (std::memcmp(h.magic, kStreamMagic, 8) != 0 || h.version != 1)
+  if (std::memcmp(h.magic, kStreamMagic, 8) != 0 || h.version != 2)
     return fail(ctx, SID_EINVAL, "not a saved stream state");
   if (h.dtype != SID_F32 && h.dtype != SID_F64) return fail(ctx, SID_EINVAL, "bad dtype in state");
   SID_NEED_DEVICE(ctx);
@@ -1171,6 +1201,7 @@ sid_status sid_stream_restore(sid_ctx* ctx, const void* host_buf, size_t bytes, 
   p.seed = h.seed;
   p.rank_tol = h.rank_tol;
   p.sp_rcond = h.sp_rcond;
+  p.probe_tol = h.probe_tol;
   sid_stream* s = nullptr;
   sid_status st = stream_make(ctx, (sid_dtype)h.dtype, h.N, h.n_max, &p, &s);
   if (st != SID_OK) return st;

@@ -300,3 +300,19 @@ def test_mesh_struct_layout(tmp_path):
     M = _native._Mesh
     assert got == [ctypes.sizeof(M), M.n.offset, M.coord.offset, M.coarse.offset,
                    M.ncoarse.offset, M.period.offset]
+
+
+def test_probe_tol_validation(vctx):
+    """Adaptive rank: probe_tol finite and >= 0; > 0 needs probe rows and
+    the Gaussian selection."""
+    L, h = vctx
+    p = _params(L, 5)
+    assert p.probe_tol == 0.0
+    for bad in (-1e-3, float("nan"), float("inf")):
+        p.probe_tol = bad
+        assert L.sid_reserve(h, 100, 20, ctypes.byref(p)) == EINVAL
+    p.probe_tol = 1e-3
+    assert L.sid_reserve(h, 100, 20, ctypes.byref(p)) == ESTATE
+    p.probe_rows = 0
+    assert L.sid_reserve(h, 100, 20, ctypes.byref(p)) == EINVAL
+    assert b"probe" in L.sid_last_error(h)

@@ -505,3 +505,49 @@ def test_literal_subsampled_id_matches_lapack(oracle_mod):
     r2 = oracle_mod.compress_literal(L, 6, np.arange(N), rank_tol=1e-10)
     assert r2.k_eff == 4
     assert oracle_mod.error_norms(L, r2.AJ[:, :4], r2.P[:4])["rel_fro"] < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Tolerance-driven rank from the probe rows (Remark 2.2)
+# ---------------------------------------------------------------------------
+
+def test_adaptive_rank_exact_rank_matrix(oracle_mod):
+    """A matrix of exact rank r: every pivot prefix shorter than r leaves a
+    probe error of the order of the next singular value, the prefix of length
+    r leaves rounding only, so any tolerance between them selects k_eff = r."""
+    r = 12
+    sig = 0.7 ** np.arange(r)
+    A = synth.lowrank_exact_spectrum(700, 90, sig, seed=31).numpy()
+    for tol in (1e-9, 1e-7):
+        res = oracle_mod.compress(A, 30, 10, seed=2, mode="two_pass", prec="f64", probe_rows=10,
+                              probe_tol=tol)
+        assert res.k_eff == r, (tol, res.k_eff)
+        assert res.err_probe <= tol
+        assert np.all(res.J[r:] == -1) and np.all(res.P[r:] == 0.0)
+    # a loose tolerance stops at the first prefix that meets it
+    res = oracle_mod.compress(A, 30, 10, seed=2, mode="two_pass", prec="f64", probe_rows=10,
+                          probe_tol=10.0)
+    assert res.k_eff == 1
+
+
+def test_adaptive_rank_prefix_errors_two_formulations(oracle_mod):
+    """The prefix errors from the definition (coefficients of every prefix)
+    equal the one-solve form ||W_pr - Z(:, :k') R(:k', :)|| with
+    Z = W_pr(:, J) R11^-1 (a triangular inverse restricted to a leading block
+    is that block's inverse); and the chosen rank is the first prefix under
+    the tolerance."""
+    sig = np.arange(1, 61, dtype=np.float64) ** -2.0
+    A = synth.lowrank_exact_spectrum(500, 60, sig, seed=5, noise=1e-6).numpy()
+    W = oracle_mod.sketch_w(A, np.arange(500), 30 + 10, 4, "f64")
+    cp = oracle_mod.cpqr(W[:30], 25)
+    Wpr = W[30:]
+    e = oracle_mod.probe_prefix_errors(cp, Wpr, 60)
+    R11 = cp.R[:, cp.J]
+    Z = np.linalg.solve(R11.T, Wpr[:, cp.J].T).T
+    nrm = np.linalg.norm(Wpr)
+    for kp in range(1, cp.k_eff + 1):
+        alt = np.linalg.norm(Wpr - Z[:, :kp] @ cp.R[:kp]) / nrm
+        assert alt == pytest.approx(e[kp], rel=1e-9, abs=1e-13)
+    tol = 0.5 * (e[8] + e[9]) if e[9] < e[8] else e[9]
+    cp2 = oracle_mod.adaptive_rank(cp, Wpr, 60, tol)
+    assert e[cp2.k_eff] <= tol and all(e[i] > tol for i in range(1, cp2.k_eff))
