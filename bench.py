@@ -245,6 +245,57 @@ def adaptive_main(args, torch, sid, synth) -> int:
     return 0
 
 
+def sweep_main(args, torch, sid, synth) -> int:
+    """Error against the sub-sampling factor (the paper's Fig. 4, right): a
+    channel-like field resolved on coarse grids (at most 1.5 wavelengths per
+    extent) on 3 x 257 x 33 x 257 points x 200 snapshots, x and z sub-sampled
+    by s = 1, 2, 4, 8, 16 (factor s^2), at rank 100 (above the field's 80
+    components: the interpolation error dominates) and rank 20 (the
+    truncation dominates): the single-pass ID with interpolation (Alg. 6),
+    the sub-sampled ID with the fine skeleton (Alg. 5), and the interpolation
+    error ||A - Mf A(S, :)|| itself."""
+    cfg = synth.SpectralConfig(nx=257, ny=33, nz=257, n_snapshots=200, n_modes=40, drift=0.3,
+                               seed=77, kmax=1.5)
+    A = synth.spectral_snapshots(cfg, device="cuda")
+    torch.cuda.synchronize()
+    N, n = A.shape
+    q = 10
+    rows = []
+    for (k, p), st in [((k_, p_), st_) for (k_, p_) in ((100, 20), (20, 10))
+                       for st_ in (1, 2, 4, 8, 16)]:
+        mesh = synth.channel_mesh(cfg, (st, 1, st), keep_last=True)
+        ip = sid.Interp(mesh)
+        kw = dict(seed=1, coarse=ip.rowset, prec=args.prec, probe_rows=q)
+        c = sid.compress(A, k, p, mode="coarse_skeleton", **kw)
+        ms = time_steps(lambda: sid.compress(A, k, p, mode="coarse_skeleton", out=c, **kw),
+                        args.steps, args.warmup, torch)
+        e_spid = sid.interp_error_norms(ip, A, c.AJ, c.P)["rel_fro"]
+        b = sid.compress(A, k, p, mode="two_pass", **kw)
+        e_sub = sid.error_norms(A, b.AJ, b.P)["rel_fro"]
+        S = torch.from_numpy(mesh.coarse_rows).cuda()
+        AS = A[S]
+        eye = torch.eye(n, dtype=torch.float32, device="cuda")
+        e_int = sid.interp_error_norms(ip, A, AS, eye)["rel_fro"]
+        rows.append({"k": k, "stride_xz": st, "factor": st * st, "coarse_rows": int(ip.Nc),
+                     "rel_fro_single_pass_interp": e_spid, "rel_fro_subsampled": e_sub,
+                     "rel_fro_interpolation": e_int, "compress_ms": round(ms, 4)})
+        del AS, ip
+    at16 = next(r for r in rows if r["factor"] == 16 and r["k"] == 100)
+    line = {
+        "metric": "rel. Frobenius error of the single-pass ID with interpolation vs sub-sampling "
+                  "factor (value: factor 16, k=100)",
+        "value": at16["rel_fro_single_pass_interp"], "unit": "relative error", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": at16["compress_ms"],
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": args.prec,
+        "data": "synthetic",
+        "config": {"workload": "channel-like snapshots 6539622 x 200 fp32 (3 x 257x33x257 grid, "
+                               "at most 1.5 wavelengths per extent), x and z sub-sampled by "
+                               "1/2/4/8/16, k=100 p=20 and k=20 p=10, q=10", "sweep": rows},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -275,6 +326,10 @@ def main() -> int:
                     help="auxiliary measurement instead of the headline: the rank chosen by the "
                          "held-out probe estimate (probe_tol 3e-2, 1e-2, 5e-3) on the headline "
                          "matrix, single pass, k <= 100")
+    ap.add_argument("--sweep", action="store_true",
+                    help="auxiliary measurement instead of the headline: error of the single-pass "
+                         "ID with interpolation and of the sub-sampled ID against the sub-sampling "
+                         "factor on a field resolved on coarse grids")
     ap.add_argument("--sketch-only", action="store_true",
                     help="profiling aid for hardware counters: a plain 1 GiB device copy (the "
                          "calibration kernel for FETCH_SIZE / WRITE_SIZE) and three sketch passes")
@@ -300,6 +355,8 @@ def main() -> int:
         return spid_main(args, torch, sid, synth)
     if args.adaptive:
         return adaptive_main(args, torch, sid, synth)
+    if args.sweep:
+        return sweep_main(args, torch, sid, synth)
     cfg = synth.SpectralConfig()
     k, p, q = 100, 20, 10
     A = synth.spectral_snapshots(cfg, device="cuda")

@@ -58,6 +58,8 @@ class SpectralConfig:
     decorrelation: float = 0.1   # relative random drift per mode
     lx: float = 4.0 * math.pi
     lz: float = 4.0 * math.pi / 3.0
+    kmax: float = 0.0            # largest wavelength count of a mode per extent (0: nz / 4);
+                                 # small values give fields resolved on coarse grids
 
     @property
     def rows(self) -> int:
@@ -67,7 +69,7 @@ class SpectralConfig:
 def _modes(cfg: SpectralConfig):
     rng = np.random.default_rng(cfg.seed)
     q = cfg.n_modes
-    mmax = max(cfg.nz / 4.0, 1.5)
+    mmax = cfg.kmax if cfg.kmax > 0.0 else max(cfg.nz / 4.0, 1.5)
     m = rng.uniform(1.0, mmax, size=q)                       # |kappa| in domain units
     d = rng.normal(size=(q, 3))
     d /= np.linalg.norm(d, axis=1, keepdims=True)            # direction on the sphere
