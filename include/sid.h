@@ -365,6 +365,44 @@ sid_status sid_interp_error_norms(sid_ctx *ctx, const sid_interp *ip, const void
                                   double *out4);
 
 /*
+ * Single-pass blocked randomized SVD (SBR-SVD, Alg. 2; the paper's other
+ * single-pass method, Sec. 2.3).  In the paper's orientation A_p = A^T
+ * (snapshots in rows) with Gaussian Omega = Psi^T (the ID's Psi: stream 1,
+ * keyed by the global row), one pass over A forms G = A_p Omega = (Psi A)^T
+ * and H = A_p^T G = A G (N x l, l = k + oversample); then for each of the
+ * l / block blocks of Omega's columns: Y_i = G_i - Q (B Omega_i),
+ * (Q_i, R_i) = qr(Y_i), (Q_i, R~_i) = qr(Q_i - Q Q^T Q_i), R_i = R~_i R_i,
+ * B_i = R_i^-T (H_i^T - Y_i^T Q B - Omega_i^T B^T B), Q = [Q, Q_i],
+ * B = [B; B_i]; finally B = U~ S V^T, U = Q U~.  Output A ~ V S U^T
+ * (A_p ~ U S V^T):
+ *   S  [k] FP64 singular values, descending (device)
+ *   U  n x k (ldu >= n) temporal factor, element type `dtype` (device)
+ *   V  N x k (ldv >= N) spatial factor, element type `dtype` (device)
+ *   rank (host, may be NULL): rows of B formed (l, or fewer when a block's
+ *        R_i is numerically singular, i.e. A_p Omega has rank < l; the
+ *        loop then stops and S, U, V past it are zero)
+ * Arithmetic: G in the sketch precision `prec` (as sid_compress), H, the
+ * block loop and the SVD in FP64 (H from FP32 products for FP32 data);
+ * the SVD of B via the eigendecomposition of B B^T (Jacobi).  The products
+ * with N rows run as library (rocBLAS) GEMMs.  Limits: l <= min(n, 256),
+ * l % block == 0, block <= 64.  Synchronizes the stream.  Workspace about
+ * (2 l + 1.5 block) N doubles.
+ */
+typedef struct {
+    int64_t k;              /* target rank >= 1                       */
+    int64_t oversample;     /* p >= 0, l = k + p                      */
+    int64_t block;          /* b >= 1 with l % b == 0, b <= 64        */
+    uint64_t seed;          /* Omega = Psi^T of this seed             */
+    sid_sketch_prec prec;   /* arithmetic of the pass forming G       */
+} sid_svd_params;
+
+/* defaults: oversample 10, block 10, seed 0, prec BF16X2 */
+void sid_svd_params_init(sid_svd_params *p, int64_t k);
+sid_status sid_sbr_svd(sid_ctx *ctx, const void *A, sid_dtype dtype, int64_t N, int64_t n,
+                       int64_t lda, const sid_svd_params *p, double *S, void *U, int64_t ldu,
+                       void *V, int64_t ldv, int64_t *rank);
+
+/*
  * Batched compression of independent matrices (one call for many problems,
  * e.g. one per flow variable or dataset).  probs: host array of `count`
  * problems, each with its own A (N x n, lda), parameters and outputs (same

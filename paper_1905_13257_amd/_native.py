@@ -25,7 +25,7 @@ EXPORTS = [
     "sid_stream_begin", "sid_stream_push", "sid_stream_finish", "sid_stream_info", "sid_stream_abort",
     "sid_stream_save", "sid_stream_restore", "sid_compress_batched",
     "sid_interp_create", "sid_interp_destroy", "sid_interp_rowset", "sid_interp_info",
-    "sid_interp_reconstruct", "sid_interp_error_norms",
+    "sid_interp_reconstruct", "sid_interp_error_norms", "sid_svd_params_init", "sid_sbr_svd",
 ]
 
 
@@ -51,6 +51,16 @@ class _Params(ctypes.Structure):
         ("refine_prec", ctypes.c_int),
         ("select", ctypes.c_int),
         ("probe_tol", ctypes.c_double),
+    ]
+
+
+class _SvdParams(ctypes.Structure):
+    _fields_ = [
+        ("k", ctypes.c_int64),
+        ("oversample", ctypes.c_int64),
+        ("block", ctypes.c_int64),
+        ("seed", ctypes.c_uint64),
+        ("prec", ctypes.c_int),
     ]
 
 
@@ -108,6 +118,10 @@ def load():
                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     L.sid_stream_save.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_size_t)]
     L.sid_stream_restore.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
+    L.sid_svd_params_init.argtypes = [ctypes.POINTER(_SvdParams), i64]
+    L.sid_svd_params_init.restype = None
+    L.sid_sbr_svd.argtypes = [vp, vp, ctypes.c_int, i64, i64, i64, ctypes.POINTER(_SvdParams), vp,
+                              vp, i64, vp, i64, ctypes.POINTER(i64)]
     L.sid_interp_create.argtypes = [vp, ctypes.POINTER(_Mesh), ctypes.POINTER(vp)]
     L.sid_interp_destroy.argtypes = [vp]
     L.sid_interp_rowset.argtypes = [vp]
@@ -123,7 +137,8 @@ def load():
                  "sid_stream_push", "sid_stream_finish", "sid_stream_info", "sid_stream_abort",
                  "sid_stream_save", "sid_compress_batched",
                  "sid_stream_restore", "sid_interp_create", "sid_interp_destroy",
-                 "sid_interp_info", "sid_interp_reconstruct", "sid_interp_error_norms"):
+                 "sid_interp_info", "sid_interp_reconstruct", "sid_interp_error_norms",
+                 "sid_sbr_svd"):
         getattr(L, name).restype = ctypes.c_int
     _LIB = L
     return L
@@ -603,3 +618,32 @@ def interp_error_norms(ip: Interp, A: torch.Tensor, ACJ: torch.Tensor, P: torch.
     fe, fa = out[0], out[1]
     return dict(fro_err=fe, fro_a=fa, rel_fro=fe / fa if fa > 0 else 0.0, rel_max=out[2],
                 max_abs=out[3])
+
+
+@dataclass
+class SVD:
+    U: torch.Tensor   # n x k temporal factor
+    S: torch.Tensor   # k singular values (float64), descending
+    V: torch.Tensor   # N x k spatial factor (A ~ V diag(S) U^T)
+    rank: int         # rows of B formed (k + oversample unless A has lower rank)
+
+
+def sbr_svd(A: torch.Tensor, k: int, oversample: int = 10, block: int = 10, seed: int = 0,
+            prec: str = "bf16x2", ctx: Context | None = None) -> SVD:
+    """Single-pass blocked randomized SVD (Alg. 2) of A (N x n, snapshots as
+    columns): A ~ V diag(S) U^T (sid_sbr_svd)."""
+    ctx = ctx or default_context(A.device)
+    A, lda = _colmajor(A)
+    N, n = A.shape
+    p = _SvdParams()
+    ctx._lib.sid_svd_params_init(ctypes.byref(p), int(k))
+    p.oversample, p.block, p.seed, p.prec = int(oversample), int(block), int(seed), PRECISIONS[prec]
+    dev = A.device
+    S = torch.empty(k, dtype=torch.float64, device=dev)
+    U = torch.empty((k, n), dtype=A.dtype, device=dev).T
+    V = torch.empty((k, N), dtype=A.dtype, device=dev).T
+    rank = ctypes.c_int64(0)
+    ctx.check(ctx._lib.sid_sbr_svd(ctx.handle, _ptr(A), _dtype_code(A), N, n, lda, ctypes.byref(p),
+                                   _ptr(S), _ptr(U), U.stride(1), _ptr(V), V.stride(1),
+                                   ctypes.byref(rank)))
+    return SVD(U=U, S=S, V=V, rank=int(rank.value))

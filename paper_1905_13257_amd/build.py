@@ -10,7 +10,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["csrc/sid_kernels.hip", "csrc/sid_sketch_mfma.hip", "csrc/sid_cpqr.hip",
-           "csrc/sid_interp.hip", "csrc/sid_adaptive.hip", "csrc/sid_api.hip"]
+           "csrc/sid_interp.hip", "csrc/sid_adaptive.hip", "csrc/sid_svd.hip",
+           "csrc/sid_api.hip"]
 LIB = os.path.join(HERE, "libsid.so")
 
 HIPCC_FLAGS = [
@@ -25,7 +26,8 @@ def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     srcs = [os.path.join(HERE, s) for s in SOURCES]
     tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-o", tmp, *srcs]
+    # rocBLAS for the plain N-length GEMMs of SBR-SVD
+    cmd = [hipcc, *HIPCC_FLAGS, "-o", tmp, *srcs, "-L/opt/rocm/lib", "-lrocblas"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

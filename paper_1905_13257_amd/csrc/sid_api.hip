@@ -12,7 +12,10 @@
 #include <vector>
 
 #include "../../include/sid.h"
+#include <rocblas/rocblas.h>
+
 #include "sid_adaptive.hpp"
+#include "sid_svd.hpp"
 #include "sid_interp.hpp"
 #include "sid_kernels.hpp"
 
@@ -21,7 +24,8 @@ namespace {
 enum Slot {
   WS_OMEGA, WS_PART, WS_W, WS_WR, WS_NRM, WS_PIV, WS_R, WS_Q, WS_KEFF, WS_STATS, WS_PD,
   WS_ERR, WS_Y, WS_M, WS_MPR, WS_WJ, WS_PIVM, WS_RM, WS_QM, WS_RKM, WS_C, WS_T, WS_MIX,
-  WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COOP, WS_SYNC, WS_R11, WS_FITPART, WS_YTMP, WS_REF_W, WS_REF_WJ, WS_REF_T, WS_REF_G, WS_OMP, WS_A8, WS_IACJT, WS_IPB, WS_IB, WS_IPART, WS_AZ, WS_AE2, WS_APART, WS_COUNT
+  WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COOP, WS_SYNC, WS_R11, WS_FITPART, WS_YTMP, WS_REF_W, WS_REF_WJ, WS_REF_T, WS_REF_G, WS_OMP, WS_A8, WS_IACJT, WS_IPB, WS_IB, WS_IPART, WS_AZ, WS_AE2, WS_APART, WS_SV_H, WS_SV_H32, WS_SV_B, WS_SV_Q, WS_SV_OM32,
+  WS_SV_OM, WS_SV_SMALL, WS_SV_W32, WS_COUNT
 };
 
 struct Buf {
@@ -49,6 +53,8 @@ struct sid_ctx {
   // runs on a side stream while mgsqr of W runs on the main one
   hipStream_t side = nullptr;
   hipEvent_t side_fork = nullptr, side_join = nullptr;
+  // library GEMMs of SBR-SVD (created on first use)
+  rocblas_handle blas = nullptr;
 };
 
 struct sid_rowset {
@@ -392,6 +398,7 @@ sid_status sid_destroy(sid_ctx* ctx) {
   if (ctx->side_fork) (void)hipEventDestroy(ctx->side_fork);
   if (ctx->side_join) (void)hipEventDestroy(ctx->side_join);
   for (hipEvent_t e : ctx->child_done) (void)hipEventDestroy(e);
+  if (ctx->blas) (void)rocblas_destroy_handle(ctx->blas);
   if (ctx->fork) (void)hipEventDestroy(ctx->fork);
   for (Buf& b : ctx->ws)
     if (b.p) (void)hipFree(b.p);
@@ -1641,6 +1648,201 @@ sid_status sid_interp_error_norms(sid_ctx* ctx, const sid_interp* ip, const void
   SID_CHECK(hipMemcpyAsync(out4, dout, 4 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
             "copy norms");
   SID_CHECK(hipStreamSynchronize(ctx->stream), "synchronize");
+  return SID_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// SBR-SVD (Alg. 2)
+// ---------------------------------------------------------------------------
+void sid_svd_params_init(sid_svd_params* p, int64_t k) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->k = k;
+  p->oversample = 10;
+  p->block = 10;
+  p->seed = 0;
+  p->prec = SID_SK_BF16X2;
+}
+
+#define SID_BLAS(expr, where)                                                         \
+  do {                                                                               \
+    rocblas_status b_ = (expr);                                                      \
+    if (b_ != rocblas_status_success)                                                \
+      return fail(ctx, SID_EDEVICE, std::string(where) + ": rocBLAS status " +        \
+                                        std::to_string((int)b_));                    \
+  } while (0)
+
+sid_status sid_sbr_svd(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N, int64_t n,
+                       int64_t lda, const sid_svd_params* sp, double* S, void* U, int64_t ldu,
+                       void* V, int64_t ldv, int64_t* rank) {
+  if (!ctx) return SID_EINVAL;
+  if (!sp || !A || !S || !U || !V) return fail(ctx, SID_EINVAL, "null argument");
+  if (dtype != SID_F32 && dtype != SID_F64) return fail(ctx, SID_EINVAL, "unknown dtype");
+  const int64_t k = sp->k, b = sp->block, l = sp->k + sp->oversample;
+  if (k < 1 || sp->oversample < 0 || b < 1 || b > 64)
+    return fail(ctx, SID_EINVAL, "need k >= 1, oversample >= 0, 1 <= block <= 64");
+  if (l % b != 0) return fail(ctx, SID_EINVAL, "k + oversample must be a multiple of block");
+  if (l > 256 || l > n || l > N) return fail(ctx, SID_EINVAL, "k + oversample must be <= min(n, N, 256)");
+  if (lda < N || ldu < n || ldv < N) return fail(ctx, SID_EINVAL, "leading dimension too small");
+  if (sp->prec < SID_SK_F64 || sp->prec > SID_SK_FP8E4M3)
+    return fail(ctx, SID_EINVAL, "unknown sketch precision");
+  // (1) the pass over A for G: the ID's sketch with l selection rows
+  sid_params gp;
+  sid_params_init(&gp, l);
+  gp.oversample = 0;
+  gp.seed = sp->seed;
+  gp.mode = SID_TWO_PASS;
+  gp.prec = sp->prec;
+  gp.probe_rows = 0;
+  Shape sh;
+  sid_status st = validate(ctx, N, n, &gp, &sh);
+  if (st != SID_OK) return st;
+  SID_NEED_DEVICE(ctx);
+  SID_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+  Work w;
+  if (reserve(ctx, sh, &w) != SID_OK) return SID_ENOMEM;
+  hipStream_t hs = ctx->stream;
+  const size_t d = sizeof(double);
+  double* H = (double*)ws(ctx, WS_SV_H, d * (size_t)N * (size_t)l);
+  double* Bt = (double*)ws(ctx, WS_SV_B, d * (size_t)N * (size_t)l);
+  double* Q = (double*)ws(ctx, WS_SV_Q, d * (size_t)n * (size_t)l);
+  float* om32 = (float*)ws(ctx, WS_SV_OM32, sizeof(float) * (size_t)N * (size_t)b);
+  double* om = (double*)ws(ctx, WS_SV_OM, d * (size_t)N * (size_t)b);
+  // small buffers: Y0, Y (n x b), C, Z (l x b), R, Rt (b x b), Gram, Vj (l x l),
+  // Us, Uv (l x k), mindiag, Uout (n x k)
+  const size_t nsmall = 2 * (size_t)(n * b) + 2 * (size_t)(l * b) + 2 * (size_t)(b * b) +
+                        2 * (size_t)(l * l) + 2 * (size_t)(l * k) + 4 + (size_t)(n * k);
+  double* sm = (double*)ws(ctx, WS_SV_SMALL, d * nsmall);
+  if (!H || !Bt || !Q || !om32 || !om || !sm) return SID_ENOMEM;
+  double* Y0 = sm;
+  double* Y = Y0 + n * b;
+  double* C = Y + n * b;
+  double* Z = C + l * b;
+  double* R = Z + l * b;
+  double* Rt = R + b * b;
+  double* Gm = Rt + b * b;
+  double* Vj = Gm + l * l;
+  double* Us = Vj + l * l;
+  double* Uv = Us + l * k;
+  double* mind = Uv + l * k;
+  double* Uo = mind + 4;
+  st = run_sketch(ctx, A, dtype, lda, &gp, sh, w, w.W, nullptr);  // W = Psi A (l x n, ld l)
+  if (st != SID_OK) return st;
+  if (!ctx->blas) {
+    if (rocblas_create_handle(&ctx->blas) != rocblas_status_success) {
+      ctx->blas = nullptr;
+      return fail(ctx, SID_EDEVICE, "rocblas_create_handle failed");
+    }
+  }
+  rocblas_handle bh = ctx->blas;
+  SID_BLAS(rocblas_set_stream(bh, hs), "set stream");
+  SID_BLAS(rocblas_set_pointer_mode(bh, rocblas_pointer_mode_host), "pointer mode");
+  const double one = 1.0, zero = 0.0, mone = -1.0;
+  // (1) H = A G = A W^T (N x l)
+  if (dtype == SID_F32) {
+    float* w32 = (float*)ws(ctx, WS_SV_W32, sizeof(float) * (size_t)(l * n));
+    float* h32 = (float*)ws(ctx, WS_SV_H32, sizeof(float) * (size_t)N * (size_t)l);
+    if (!w32 || !h32) return SID_ENOMEM;
+    SID_CHECK(sid::launch_convert(hs, w.W, true, l, n, l, w32, false, l), "W in FP32");
+    const float fone = 1.0f, fzero = 0.0f;
+    SID_BLAS(rocblas_sgemm(bh, rocblas_operation_none, rocblas_operation_transpose, (int)N, (int)l,
+                           (int)n, &fone, (const float*)A, (int)lda, w32, (int)l, &fzero, h32,
+                           (int)N),
+             "H = A W^T");
+    SID_CHECK(sid::launch_convert(hs, h32, false, N, l, N, H, true, N), "H in FP64");
+  } else {
+    SID_BLAS(rocblas_dgemm(bh, rocblas_operation_none, rocblas_operation_transpose, (int)N, (int)l,
+                           (int)n, &one, (const double*)A, (int)lda, w.W, (int)l, &zero, H,
+                           (int)N),
+             "H = A W^T");
+  }
+  double gnorm = 0.0;
+  SID_BLAS(rocblas_dnrm2(bh, (int)(l * n), w.W, 1, &gnorm), "||G||");
+  // (2) the blocks
+  int64_t j = 0;
+  const int64_t s = l / b;
+  for (int64_t i = 0; i < s; ++i) {
+    // Omega_i = Psi(i b .. i b + b, :)^T, rounded as the sketch read it,
+    // stored b x N (ld b)
+    SID_CHECK(sid::launch_fill_gaussian(hs, sp->seed, 1u, 0, N, i * b, b, om32), "Omega_i");
+    SID_CHECK(sid::launch_omega_values(hs, sh.prec, om32, N * b, om), "Omega_i values");
+    // Y_i = G_i - Q (B Omega_i), G_i = W(i b .. i b + b, :)^T
+    SID_CHECK(sid::launch_transpose64(hs, w.W + i * b, b, n, l, Y0, n), "G_i");
+    if (j > 0) {
+      SID_BLAS(rocblas_dgemm(bh, rocblas_operation_transpose, rocblas_operation_transpose,
+                             (int)j, (int)b, (int)N, &one, Bt, (int)N, om, (int)b, &zero, C,
+                             (int)l),
+               "B Omega_i");
+      SID_BLAS(rocblas_dgemm(bh, rocblas_operation_none, rocblas_operation_none, (int)n, (int)b,
+                             (int)j, &mone, Q, (int)n, C, (int)l, &one, Y0, (int)n),
+               "G_i - Q B Omega_i");
+    }
+    // (Q_i, R_i) = qr(Y_i), then against Q once more: (Q_i, R~_i)
+    SID_CHECK(hipMemcpyAsync(Y, Y0, d * (size_t)(n * b), hipMemcpyDeviceToDevice, hs), "copy Y");
+    SID_CHECK(sid::launch_small_qr(hs, Y, (int)n, (int)b, R), "qr(Y_i)");
+    if (j > 0) {
+      SID_BLAS(rocblas_dgemm(bh, rocblas_operation_transpose, rocblas_operation_none, (int)j,
+                             (int)b, (int)n, &one, Q, (int)n, Y, (int)n, &zero, Z, (int)l),
+               "Q^T Q_i");
+      SID_BLAS(rocblas_dgemm(bh, rocblas_operation_none, rocblas_operation_none, (int)n, (int)b,
+                             (int)j, &mone, Q, (int)n, Z, (int)l, &one, Y, (int)n),
+               "Q_i - Q Q^T Q_i");
+    }
+    SID_CHECK(sid::launch_small_qr(hs, Y, (int)n, (int)b, Rt), "qr again");
+    SID_CHECK(sid::launch_trmul(hs, Rt, R, (int)b, mind), "R_i = R~_i R_i");
+    double mdiag = 0.0;
+    SID_CHECK(hipMemcpyAsync(&mdiag, mind, d, hipMemcpyDeviceToHost, hs), "min diag");
+    SID_CHECK(hipStreamSynchronize(hs), "synchronize");
+    // A_p Omega of rank below l: the blocks so far span it (stop)
+    if (!(mdiag > 1e-12 * gnorm)) break;
+    // B_i^T = (H_i - B^T (Q^T Y_i + B Omega_i)) R_i^-1, written in place into
+    // the next b columns of B^T
+    double* Bi = Bt + j * N;
+    SID_CHECK(hipMemcpyAsync(Bi, H + i * b * N, d * (size_t)(N * b), hipMemcpyDeviceToDevice, hs),
+              "H_i");
+    if (j > 0) {
+      SID_BLAS(rocblas_dgemm(bh, rocblas_operation_transpose, rocblas_operation_none, (int)j,
+                             (int)b, (int)n, &one, Q, (int)n, Y0, (int)n, &one, C, (int)l),
+               "Q^T Y_i + B Omega_i");
+      SID_BLAS(rocblas_dgemm(bh, rocblas_operation_none, rocblas_operation_none, (int)N, (int)b,
+                             (int)j, &mone, Bt, (int)N, C, (int)l, &one, Bi, (int)N),
+               "H_i - B^T M_i");
+    }
+    SID_BLAS(rocblas_dtrsm(bh, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
+                           rocblas_diagonal_non_unit, (int)N, (int)b, &one, R, (int)b, Bi,
+                           (int)N),
+             "B_i^T = (.) R_i^-1");
+    SID_CHECK(hipMemcpyAsync(Q + j * n, Y, d * (size_t)(n * b), hipMemcpyDeviceToDevice, hs),
+              "Q_i");
+    j += b;
+  }
+  if (rank) *rank = j;
+  if (j == 0) {
+    SID_CHECK(hipMemsetAsync(S, 0, d * (size_t)k, hs), "S");
+    const size_t es = dtype == SID_F64 ? d : sizeof(float);
+    SID_CHECK(hipMemset2DAsync(U, es * (size_t)ldu, 0, es * (size_t)n, (size_t)k, hs), "U");
+    SID_CHECK(hipMemset2DAsync(V, es * (size_t)ldv, 0, es * (size_t)N, (size_t)k, hs), "V");
+    SID_CHECK(hipStreamSynchronize(hs), "synchronize");
+    return SID_OK;
+  }
+  // (3) B = U~ S V^T from B B^T = U~ S^2 U~^T (Jacobi); V_k = B^T U~_k S_k^-1,
+  // U_k = Q U~_k
+  SID_BLAS(rocblas_dgemm(bh, rocblas_operation_transpose, rocblas_operation_none, (int)j, (int)j,
+                         (int)N, &one, Bt, (int)N, Bt, (int)N, &zero, Gm, (int)j),
+           "B B^T");
+  SID_CHECK(sid::launch_jacobi(hs, Gm, (int)j, Vj), "eigenvalues of B B^T");
+  SID_CHECK(sid::launch_eig_sort(hs, Gm, (int)j, Vj, (int)k, S, Us, Uv), "sort");
+  // (columns of Us, Uv past j are zero)
+  SID_BLAS(rocblas_dgemm(bh, rocblas_operation_none, rocblas_operation_none, (int)N, (int)k,
+                         (int)j, &one, Bt, (int)N, Us, (int)j, &zero, H, (int)N),
+           "V = B^T U~ S^-1");
+  SID_BLAS(rocblas_dgemm(bh, rocblas_operation_none, rocblas_operation_none, (int)n, (int)k,
+                         (int)j, &one, Q, (int)n, Uv, (int)j, &zero, Uo, (int)n),
+           "U = Q U~");
+  SID_CHECK(sid::launch_convert(hs, H, true, N, k, N, V, dtype == SID_F64, ldv), "V out");
+  SID_CHECK(sid::launch_convert(hs, Uo, true, n, k, n, U, dtype == SID_F64, ldu), "U out");
+  SID_CHECK(hipStreamSynchronize(hs), "synchronize");
   return SID_OK;
 }
 

@@ -1,0 +1,26 @@
+// sid_svd.hpp -- small FP64 kernels of SBR-SVD (Alg. 2).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sid {
+
+// in-place thin QR (CGS2) of Y (n x b, ld n), R (b x b, ld b); b <= 64
+hipError_t launch_small_qr(hipStream_t st, double* Y, int n, int b, double* R);
+// R = Rt R for b x b upper triangular factors (ld b); min |R(c, c)| into *mindiag
+hipError_t launch_trmul(hipStream_t st, const double* Rt, double* R, int b, double* mindiag);
+// Jacobi eigensolver of a symmetric m x m matrix (ld m, m <= 256): M becomes
+// diagonal (eigenvalues), V the eigenvectors
+hipError_t launch_jacobi(hipStream_t st, double* M, int m, double* V);
+// S[0:k] = sqrt of the eigenvalues in descending order (0 past m); Uv (m x k)
+// the matching eigenvectors, Us = Uv / S column by column (0 where S = 0)
+hipError_t launch_eig_sort(hipStream_t st, const double* M, int m, const double* V, int k,
+                           double* S, double* Us, double* Uv);
+// dst = src (rows x cols), element type conversion between FP32 / FP64
+hipError_t launch_convert(hipStream_t st, const void* src, bool src_f64, int64_t rows,
+                          int64_t cols, int64_t lds, void* dst, bool dst_f64, int64_t ldd);
+// dst (cols x rows, ld ldd) = src^T (rows x cols, ld lds), FP64
+hipError_t launch_transpose64(hipStream_t st, const double* src, int64_t rows, int64_t cols,
+                              int64_t lds, double* dst, int64_t ldd);
+
+}  // namespace sid

@@ -316,3 +316,38 @@ def test_probe_tol_validation(vctx):
     p.probe_rows = 0
     assert L.sid_reserve(h, 100, 20, ctypes.byref(p)) == EINVAL
     assert b"probe" in L.sid_last_error(h)
+
+
+def test_sbr_svd_validation(vctx, tmp_path):
+    """SBR-SVD arguments are checked before any device work; the parameter
+    struct mirrors the C layout."""
+    L, h = vctx
+    vp = ctypes.c_void_p
+    p = _native._SvdParams()
+    L.sid_svd_params_init(ctypes.byref(p), 20)
+    assert (p.k, p.oversample, p.block, p.seed, p.prec) == (20, 10, 10, 0, 3)
+    r = ctypes.c_int64()
+    call = lambda N=1000, n=200, lda=1000, A=1: L.sid_sbr_svd(
+        h, vp(A), 1, N, n, lda, ctypes.byref(p), vp(1), vp(1), n, vp(1), N, ctypes.byref(r))
+    assert call() == ESTATE
+    assert call(A=0) == EINVAL
+    assert call(lda=10) == EINVAL
+    assert call(n=25) == EINVAL                 # l = 30 > n
+    p.block = 7
+    assert call() == EINVAL                     # l % block
+    p.block, p.oversample = 10, 250
+    assert call() == EINVAL                     # l > 256
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        return
+    src = tmp_path / "svdp.c"
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "sid.h"\nint main(void){\n'
+                   'printf("%zu %zu %zu\\n", sizeof(sid_svd_params), offsetof(sid_svd_params, seed),'
+                   ' offsetof(sid_svd_params, prec));\nreturn 0;}\n')
+    exe = tmp_path / "svdp"
+    subprocess.check_call([cc, "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    S = _native._SvdParams
+    assert got == [ctypes.sizeof(S), S.seed.offset, S.prec.offset]
