@@ -296,6 +296,47 @@ def sweep_main(args, torch, sid, synth) -> int:
     return 0
 
 
+def svd_main(args, torch, sid, synth) -> int:
+    """SBR-SVD (Alg. 2) on the headline matrix: k = 100, p = 20, block 20,
+    one pass for G = (Psi A)^T, H = A G and the block loop in FP64.  The
+    line is the FP64-sketch run; the FP32 and BF16x2 sketches are timed
+    beside it, with the error ||A - V S U^T||_F / ||A||_F of each and the
+    single-pass ID's on the same matrix."""
+    cfg = synth.SpectralConfig()
+    A = synth.spectral_snapshots(cfg, device="cuda")
+    torch.cuda.synchronize()
+    N, n = A.shape
+    k, p, b = 100, 20, 20
+    runs = {}
+    for prec in ("f64", "f32", "bf16x2"):
+        out = sid.sbr_svd(A, k, p, b, seed=0, prec=prec)
+        ms = time_steps(lambda: sid.sbr_svd(A, k, p, b, seed=0, prec=prec), args.steps,
+                        args.warmup, torch)
+        err = sid.error_norms(A, out.V * out.S.float()[None, :], out.U.T.contiguous())
+        runs[prec] = (ms, err["rel_fro"], out)
+        print(f"# sbr_svd prec={prec}: {ms:.3f} ms, rel_fro {err['rel_fro']:.4e}, "
+              f"rank {out.rank}", file=sys.stderr, flush=True)
+    ide = sid.compress(A, k, p, seed=0, mode="single_pass", prec="bf16x2", probe_rows=10)
+    err_id = sid.error_norms(A, ide.AJ, ide.P)
+    ms, rel, out = runs["f64"]
+    line = {
+        "metric": "snapshot GB/s compressed (SBR-SVD, Alg. 2, k=100)",
+        "value": round(N * n * 4 / (ms * 1e-3) / 1e9, 2), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "channel-like snapshots 1572864 x 500 fp32, SBR-SVD k=100 p=20 "
+                               "block 20",
+                   "rel_fro_error": rel, "rank": out.rank,
+                   "sigma_1": float(out.S[0]), "sigma_k": float(out.S[k - 1]),
+                   "by_sketch_prec": {q: {"ms_per_step": round(v[0], 4), "rel_fro_error": v[1]}
+                                      for q, v in runs.items()},
+                   "rel_fro_error_single_pass_id_bf16x2": err_id["rel_fro"]},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -330,6 +371,9 @@ def main() -> int:
                     help="auxiliary measurement instead of the headline: error of the single-pass "
                          "ID with interpolation and of the sub-sampled ID against the sub-sampling "
                          "factor on a field resolved on coarse grids")
+    ap.add_argument("--svd", action="store_true",
+                    help="auxiliary measurement instead of the headline: SBR-SVD (Alg. 2) of the "
+                         "headline matrix at k=100, p=20, block 20")
     ap.add_argument("--sketch-only", action="store_true",
                     help="profiling aid for hardware counters: a plain 1 GiB device copy (the "
                          "calibration kernel for FETCH_SIZE / WRITE_SIZE) and three sketch passes")
@@ -357,6 +401,8 @@ def main() -> int:
         return adaptive_main(args, torch, sid, synth)
     if args.sweep:
         return sweep_main(args, torch, sid, synth)
+    if args.svd:
+        return svd_main(args, torch, sid, synth)
     cfg = synth.SpectralConfig()
     k, p, q = 100, 20, 10
     A = synth.spectral_snapshots(cfg, device="cuda")

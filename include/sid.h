@@ -381,12 +381,16 @@ sid_status sid_interp_error_norms(sid_ctx *ctx, const sid_interp *ip, const void
  *   rank (host, may be NULL): rows of B formed (l, or fewer when a block's
  *        R_i is numerically singular, i.e. A_p Omega has rank < l; the
  *        loop then stops and S, U, V past it are zero)
- * Arithmetic: G in the sketch precision `prec` (as sid_compress), H, the
- * block loop and the SVD in FP64 (H from FP32 products for FP32 data);
- * the SVD of B via the eigendecomposition of B B^T (Jacobi).  The products
- * with N rows run as library (rocBLAS) GEMMs.  Limits: l <= min(n, 256),
- * l % block == 0, block <= 64.  Synchronizes the stream.  Workspace about
- * (2 l + 1.5 block) N doubles.
+ * Arithmetic: G in the sketch precision `prec` (as sid_compress); H (FP32
+ * data promoted exactly), the block loop and the SVD in FP64; the SVD of B
+ * via the eigendecomposition of B B^T (Jacobi).  The block loop subtracts
+ * terms of size sigma_1^2 to leave ones of size sigma_j^2, so an error e
+ * (relative) in G reaches B_i as about e (sigma_1 / sigma_j)^2: the default
+ * F64 is the precision that keeps the method's accuracy; the low-precision
+ * modes are for well-separated spectra only.  The products with N rows run
+ * as rocBLAS GEMMs, except B Omega_i (a split reduction over the rows).
+ * Limits: l <= min(n, 256), l % block == 0, block <= 64.  Synchronizes the
+ * stream.  Workspace about (2 l + 1.5 block) N doubles.
  */
 typedef struct {
     int64_t k;              /* target rank >= 1                       */
@@ -396,7 +400,7 @@ typedef struct {
     sid_sketch_prec prec;   /* arithmetic of the pass forming G       */
 } sid_svd_params;
 
-/* defaults: oversample 10, block 10, seed 0, prec BF16X2 */
+/* defaults: oversample 10, block 10, seed 0, prec F64 */
 void sid_svd_params_init(sid_svd_params *p, int64_t k);
 sid_status sid_sbr_svd(sid_ctx *ctx, const void *A, sid_dtype dtype, int64_t N, int64_t n,
                        int64_t lda, const sid_svd_params *p, double *S, void *U, int64_t ldu,

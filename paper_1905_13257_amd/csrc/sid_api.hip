@@ -24,8 +24,8 @@ namespace {
 enum Slot {
   WS_OMEGA, WS_PART, WS_W, WS_WR, WS_NRM, WS_PIV, WS_R, WS_Q, WS_KEFF, WS_STATS, WS_PD,
   WS_ERR, WS_Y, WS_M, WS_MPR, WS_WJ, WS_PIVM, WS_RM, WS_QM, WS_RKM, WS_C, WS_T, WS_MIX,
-  WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COOP, WS_SYNC, WS_R11, WS_FITPART, WS_YTMP, WS_REF_W, WS_REF_WJ, WS_REF_T, WS_REF_G, WS_OMP, WS_A8, WS_IACJT, WS_IPB, WS_IB, WS_IPART, WS_AZ, WS_AE2, WS_APART, WS_SV_H, WS_SV_H32, WS_SV_B, WS_SV_Q, WS_SV_OM32,
-  WS_SV_OM, WS_SV_SMALL, WS_SV_W32, WS_COUNT
+  WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COOP, WS_SYNC, WS_R11, WS_FITPART, WS_YTMP, WS_REF_W, WS_REF_WJ, WS_REF_T, WS_REF_G, WS_OMP, WS_A8, WS_IACJT, WS_IPB, WS_IB, WS_IPART, WS_AZ, WS_AE2, WS_APART, WS_SV_H, WS_SV_PART, WS_SV_B, WS_SV_Q, WS_SV_OM32,
+  WS_SV_OM, WS_SV_SMALL, WS_COUNT
 };
 
 struct Buf {
@@ -1662,7 +1662,7 @@ void sid_svd_params_init(sid_svd_params* p, int64_t k) {
   p->oversample = 10;
   p->block = 10;
   p->seed = 0;
-  p->prec = SID_SK_BF16X2;
+  p->prec = SID_SK_F64;
 }
 
 #define SID_BLAS(expr, where)                                                         \
@@ -1709,12 +1709,16 @@ sid_status sid_sbr_svd(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N, 
   double* Q = (double*)ws(ctx, WS_SV_Q, d * (size_t)n * (size_t)l);
   float* om32 = (float*)ws(ctx, WS_SV_OM32, sizeof(float) * (size_t)N * (size_t)b);
   double* om = (double*)ws(ctx, WS_SV_OM, d * (size_t)N * (size_t)b);
+  double* part = (double*)ws(ctx, WS_SV_PART, d * (size_t)sid::tsprod_blocks(N) * (size_t)(l * b));
   // small buffers: Y0, Y (n x b), C, Z (l x b), R, Rt (b x b), Gram, Vj (l x l),
-  // Us, Uv (l x k), mindiag, Uout (n x k)
+  // Us, Uv (l x k), mindiag (+ Jacobi's sweep count), Uout (n x k), Jacobi
+  // work (l' x l', l' = l rounded up to even) and rotation records
+  const size_t le = (size_t)(l + (l & 1));
   const size_t nsmall = 2 * (size_t)(n * b) + 2 * (size_t)(l * b) + 2 * (size_t)(b * b) +
-                        2 * (size_t)(l * l) + 2 * (size_t)(l * k) + 4 + (size_t)(n * k);
+                        2 * (size_t)(l * l) + 2 * (size_t)(l * k) + 4 + (size_t)(n * k) + le * le +
+                        sid::jacobi_rot_doubles((int)l);
   double* sm = (double*)ws(ctx, WS_SV_SMALL, d * nsmall);
-  if (!H || !Bt || !Q || !om32 || !om || !sm) return SID_ENOMEM;
+  if (!H || !Bt || !Q || !om32 || !om || !part || !sm) return SID_ENOMEM;
   double* Y0 = sm;
   double* Y = Y0 + n * b;
   double* C = Y + n * b;
@@ -1727,6 +1731,8 @@ sid_status sid_sbr_svd(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N, 
   double* Uv = Us + l * k;
   double* mind = Uv + l * k;
   double* Uo = mind + 4;
+  double* Jw = Uo + n * k;  // Jacobi's working matrix when l > 128
+  double* Jrot = Jw + le * le;  // Jacobi's rotation records
   st = run_sketch(ctx, A, dtype, lda, &gp, sh, w, w.W, nullptr);  // W = Psi A (l x n, ld l)
   if (st != SID_OK) return st;
   if (!ctx->blas) {
@@ -1739,18 +1745,18 @@ sid_status sid_sbr_svd(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N, 
   SID_BLAS(rocblas_set_stream(bh, hs), "set stream");
   SID_BLAS(rocblas_set_pointer_mode(bh, rocblas_pointer_mode_host), "pointer mode");
   const double one = 1.0, zero = 0.0, mone = -1.0;
-  // (1) H = A G = A W^T (N x l)
+  // (1) H = A G = A W^T (N x l) in FP64; FP32 data is promoted exactly, l
+  // columns at a time, through B^T's storage (not yet in use)
   if (dtype == SID_F32) {
-    float* w32 = (float*)ws(ctx, WS_SV_W32, sizeof(float) * (size_t)(l * n));
-    float* h32 = (float*)ws(ctx, WS_SV_H32, sizeof(float) * (size_t)N * (size_t)l);
-    if (!w32 || !h32) return SID_ENOMEM;
-    SID_CHECK(sid::launch_convert(hs, w.W, true, l, n, l, w32, false, l), "W in FP32");
-    const float fone = 1.0f, fzero = 0.0f;
-    SID_BLAS(rocblas_sgemm(bh, rocblas_operation_none, rocblas_operation_transpose, (int)N, (int)l,
-                           (int)n, &fone, (const float*)A, (int)lda, w32, (int)l, &fzero, h32,
-                           (int)N),
-             "H = A W^T");
-    SID_CHECK(sid::launch_convert(hs, h32, false, N, l, N, H, true, N), "H in FP64");
+    for (int64_t c0 = 0; c0 < n; c0 += l) {
+      const int64_t cw = n - c0 < l ? n - c0 : l;
+      SID_CHECK(sid::launch_convert(hs, (const float*)A + c0 * lda, false, N, cw, lda, Bt, true, N),
+                "A columns in FP64");
+      SID_BLAS(rocblas_dgemm(bh, rocblas_operation_none, rocblas_operation_transpose, (int)N,
+                             (int)l, (int)cw, &one, Bt, (int)N, w.W + c0 * l, (int)l,
+                             c0 == 0 ? &zero : &one, H, (int)N),
+               "H = A W^T");
+    }
   } else {
     SID_BLAS(rocblas_dgemm(bh, rocblas_operation_none, rocblas_operation_transpose, (int)N, (int)l,
                            (int)n, &one, (const double*)A, (int)lda, w.W, (int)l, &zero, H,
@@ -1770,10 +1776,9 @@ sid_status sid_sbr_svd(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N, 
     // Y_i = G_i - Q (B Omega_i), G_i = W(i b .. i b + b, :)^T
     SID_CHECK(sid::launch_transpose64(hs, w.W + i * b, b, n, l, Y0, n), "G_i");
     if (j > 0) {
-      SID_BLAS(rocblas_dgemm(bh, rocblas_operation_transpose, rocblas_operation_transpose,
-                             (int)j, (int)b, (int)N, &one, Bt, (int)N, om, (int)b, &zero, C,
-                             (int)l),
-               "B Omega_i");
+      // B Omega_i (j x b): a reduction over the N rows, split across blocks
+      SID_CHECK(sid::launch_tsprod(hs, Bt, N, (int)j, om, b, 1, (int)b, N, part, C, l),
+                "B Omega_i");
       SID_BLAS(rocblas_dgemm(bh, rocblas_operation_none, rocblas_operation_none, (int)n, (int)b,
                              (int)j, &mone, Q, (int)n, C, (int)l, &one, Y0, (int)n),
                "G_i - Q B Omega_i");
@@ -1831,7 +1836,8 @@ sid_status sid_sbr_svd(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N, 
   SID_BLAS(rocblas_dgemm(bh, rocblas_operation_transpose, rocblas_operation_none, (int)j, (int)j,
                          (int)N, &one, Bt, (int)N, Bt, (int)N, &zero, Gm, (int)j),
            "B B^T");
-  SID_CHECK(sid::launch_jacobi(hs, Gm, (int)j, Vj), "eigenvalues of B B^T");
+  SID_CHECK(sid::launch_jacobi(hs, Gm, (int)j, Vj, Jw, Jrot, (int*)(mind + 2)),
+            "eigen-decomposition of B B^T");
   SID_CHECK(sid::launch_eig_sort(hs, Gm, (int)j, Vj, (int)k, S, Us, Uv), "sort");
   // (columns of Us, Uv past j are zero)
   SID_BLAS(rocblas_dgemm(bh, rocblas_operation_none, rocblas_operation_none, (int)N, (int)k,

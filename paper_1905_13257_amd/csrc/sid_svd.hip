@@ -24,36 +24,66 @@ __device__ double block_sum(double v, double* red) {
   return s;
 }
 
-// In-place thin QR of Y (n x b, column-major, ld n) by Gram-Schmidt with one
-// reorthogonalization per column (CGS2): Y becomes Q, R (b x b, ld b) upper
-// triangular.  A column whose norm after the projections is zero gets a
-// zero Q column and R(c, c) = 0.
-__global__ __launch_bounds__(SV_THREADS) void k_small_qr(double* __restrict__ Y, int n, int b,
+// In-place thin QR of Y (n x b, column-major, ld n) by classical
+// Gram-Schmidt applied twice per column (CGS2): Y becomes Q, R (b x b, ld b)
+// upper triangular.  Per column and pass, the projections on all earlier
+// columns are formed at once (wave w takes columns w, w + 16, ...) and then
+// subtracted together.  Y is worked on in LDS when n b <= QR_LDS, else in
+// place.  A column whose norm after the projections is zero gets a zero Q
+// column and R(c, c) = 0.
+constexpr int QR_THREADS = 1024;
+constexpr int QR_LDS = 14336;  // doubles (112 KiB)
+
+template <bool SH>
+__global__ __launch_bounds__(QR_THREADS) void k_small_qr(double* __restrict__ Y, int n, int b,
                                                          double* __restrict__ R) {
-  __shared__ double red[SV_THREADS / 64];
-  for (int e = threadIdx.x; e < b * b; e += SV_THREADS) R[e] = 0.0;
+  __shared__ double sy[SH ? QR_LDS : 1];
+  __shared__ double sr[64 * 64];
+  __shared__ double sd[64];
+  __shared__ double red[QR_THREADS / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double* W = SH ? sy : Y;
+  if (SH)
+    for (int e = threadIdx.x; e < n * b; e += QR_THREADS) sy[e] = Y[e];
+  for (int e = threadIdx.x; e < b * b; e += QR_THREADS) sr[e] = 0.0;
   __syncthreads();
   for (int c = 0; c < b; ++c) {
-    double* y = Y + (int64_t)n * c;
-    for (int pass = 0; pass < 2; ++pass) {
-      for (int d = 0; d < c; ++d) {
-        const double* qd = Y + (int64_t)n * d;
-        double s = 0.0;
-        for (int r = threadIdx.x; r < n; r += SV_THREADS) s = fma(qd[r], y[r], s);
-        s = block_sum(s, red);
-        for (int r = threadIdx.x; r < n; r += SV_THREADS) y[r] = fma(-s, qd[r], y[r]);
-        if (threadIdx.x == 0) R[d + b * c] += s;
-        __syncthreads();
+    double* y = W + (int64_t)n * c;
+    for (int pass = 0; pass < 2 && c > 0; ++pass) {
+      for (int d = wave; d < c; d += QR_THREADS / 64) {
+        const double* qd = W + (int64_t)n * d;
+        double t = 0.0;
+        for (int r = lane; r < n; r += 64) t = fma(qd[r], y[r], t);
+        t = wave_sum(t);
+        if (lane == 0) {
+          sd[d] = t;
+          sr[d + b * c] += t;
+        }
       }
+      __syncthreads();
+      for (int r = threadIdx.x; r < n; r += QR_THREADS) {
+        double v = y[r];
+        for (int d = 0; d < c; ++d) v = fma(-sd[d], W[r + (int64_t)n * d], v);
+        y[r] = v;
+      }
+      __syncthreads();
     }
-    double s = 0.0;
-    for (int r = threadIdx.x; r < n; r += SV_THREADS) s = fma(y[r], y[r], s);
-    const double nrm = sqrt(block_sum(s, red));
+    double t = 0.0;
+    for (int r = threadIdx.x; r < n; r += QR_THREADS) t = fma(y[r], y[r], t);
+    t = wave_sum(t);
+    if (lane == 0) red[wave] = t;
+    __syncthreads();
+    double ss = 0.0;
+    for (int w = 0; w < QR_THREADS / 64; ++w) ss += red[w];
+    const double nrm = sqrt(ss);
     const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-    for (int r = threadIdx.x; r < n; r += SV_THREADS) y[r] *= inv;
-    if (threadIdx.x == 0) R[c + b * c] = nrm;
+    for (int r = threadIdx.x; r < n; r += QR_THREADS) y[r] *= inv;
+    if (threadIdx.x == 0) sr[c + b * c] = nrm;
     __syncthreads();
   }
+  if (SH)
+    for (int e = threadIdx.x; e < n * b; e += QR_THREADS) Y[e] = sy[e];
+  for (int e = threadIdx.x; e < b * b; e += QR_THREADS) R[e] = sr[e];
 }
 
 // R = Rt R (both b x b upper triangular, column-major), in place in R;
@@ -78,88 +108,152 @@ __global__ __launch_bounds__(SV_THREADS) void k_trmul(const double* __restrict__
   }
 }
 
-// Cyclic Jacobi eigensolver of a symmetric M (m x m, column-major, ld m,
-// m <= 256) in place, eigenvectors into V.  Each sweep visits every pair
-// once in m' - 1 rounds of a round-robin tournament (m' = m rounded up to
-// even; index m' - 1 is a dummy when m is odd), the pairs of a round being
-// disjoint, so their rotations are applied in parallel: first to the rows
-// of M, then to its columns and to the columns of V.  Stops when the
-// off-diagonal Frobenius norm is below 1e-15 of the whole, or after 40
-// sweeps.
-__global__ __launch_bounds__(SV_THREADS) void k_jacobi(double* __restrict__ M, int m,
-                                                       double* __restrict__ V) {
+// Cyclic Jacobi eigenvalues of a symmetric M (m x m, column-major, ld m,
+// m <= 256) in place.  The matrix is worked on padded to m' = m rounded up
+// to even (index m' - 1 a zero dummy when m is odd, never rotated), in LDS
+// when m' <= 128, else in `work` (m'^2 doubles).  A sweep visits every pair
+// once in m' - 1 rounds of a round-robin tournament; the pairs of a round are
+// disjoint, so each 2 x 2 block M(P, R) of two pairs P, R becomes
+// R_P M(P, R) R_R^T independently of the others (one thread per block).  A
+// pair is rotated only while |a_pq| > 1e-15 sqrt(|a_pp a_qq|) and
+// |a_pq| > 1e-300; the loop ends after a sweep without rotations, or after
+// JAC_SWEEPS sweeps.  Every round's (c, s) per pair goes to rot (round t,
+// pair k at rot[2 (t npairs + k)]) and the number of sweeps to *nsweeps, for
+// the eigenvectors.
+constexpr int JAC_THREADS = 1024;
+constexpr int JAC_SWEEPS = 40;
+
+__device__ inline int jac_slot(int pos, int round, int me) {
+  return pos == 0 ? 0 : 1 + (pos - 1 + round) % (me - 1);
+}
+
+template <bool SH>
+__global__ __launch_bounds__(JAC_THREADS) void k_jacobi(double* __restrict__ M, int m,
+                                                        double* __restrict__ work,
+                                                        double* __restrict__ rot,
+                                                        int* __restrict__ nsweeps) {
+  __shared__ double sm[SH ? 128 * 128 : 1];
   __shared__ int pp[128], qq[128];
   __shared__ double cc[128], ss[128];
-  __shared__ double red[SV_THREADS / 64];
+  __shared__ int rotated;
   const int me = m + (m & 1);
   const int npairs = me / 2;
-  for (int e = threadIdx.x; e < m * m; e += SV_THREADS) V[e] = (e % m == e / m) ? 1.0 : 0.0;
+  double* W = SH ? sm : work;
+  for (int e = threadIdx.x; e < me * me; e += JAC_THREADS) {
+    const int i = e % me, j = e / me;
+    W[e] = (i < m && j < m) ? M[i + (int64_t)m * j] : 0.0;
+  }
+  if (threadIdx.x == 0) rotated = 0;
   __syncthreads();
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int e = threadIdx.x; e < m * m; e += SV_THREADS) {
-      const double v = M[e];
-      tot = fma(v, v, tot);
-      if (e % m != e / m) off = fma(v, v, off);
-    }
-    off = block_sum(off, red);
-    tot = block_sum(tot, red);
-    if (off <= 1e-30 * tot || tot == 0.0) break;
+  int sweep = 0;
+  while (sweep < JAC_SWEEPS) {
     for (int round = 0; round < me - 1; ++round) {
-      // tournament pairing: position 0 fixed, the others rotate
-      for (int k = threadIdx.x; k < npairs; k += SV_THREADS) {
-        auto slot = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (me - 1); };
-        int p = slot(k), q = slot(me - 1 - k);
+      double* rr = rot + 2 * ((int64_t)(sweep * (me - 1) + round) * npairs);
+      for (int k = threadIdx.x; k < npairs; k += JAC_THREADS) {
+        int p = jac_slot(k, round, me), q = jac_slot(me - 1 - k, round, me);
         if (p > q) { const int t = p; p = q; q = t; }
-        double c = 1.0, s = 0.0;
-        if (q < m) {
-          const double apq = M[p + (int64_t)m * q];
-          if (apq != 0.0) {
-            const double app = M[p + (int64_t)m * p], aqq = M[q + (int64_t)m * q];
-            const double tau = (aqq - app) / (2.0 * apq);
-            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
-          }
+        double c = 1.0, sn = 0.0;
+        const double apq = W[p + me * q];
+        const double app = W[p + me * p], aqq = W[q + me * q];
+        const double ab = fabs(apq);
+        if (ab > 1e-300 && ab > 1e-15 * sqrt(fabs(app) * fabs(aqq))) {
+          const double tau = (aqq - app) / (2.0 * apq);
+          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + t * t);
+          sn = t * c;
+          rotated = 1;
         }
         pp[k] = p;
         qq[k] = q;
         cc[k] = c;
-        ss[k] = s;
+        ss[k] = sn;
+        rr[2 * k] = c;
+        rr[2 * k + 1] = sn;
       }
       __syncthreads();
-      // rows p, q of M
-      for (int e = threadIdx.x; e < npairs * m; e += SV_THREADS) {
-        const int k = e / m, x = e - k * m;
-        const int p = pp[k], q = qq[k];
-        if (q >= m) continue;
-        const double c = cc[k], s = ss[k];
-        const double mp = M[p + (int64_t)m * x], mq = M[q + (int64_t)m * x];
-        M[p + (int64_t)m * x] = c * mp - s * mq;
-        M[q + (int64_t)m * x] = s * mp + c * mq;
+      for (int e = threadIdx.x; e < npairs * npairs; e += JAC_THREADS) {
+        const int a = e % npairs, b = e / npairs;
+        const double c1 = cc[a], s1 = ss[a], c2 = cc[b], s2 = ss[b];
+        if (s1 == 0.0 && s2 == 0.0) continue;
+        const int p = pp[a], q = qq[a], r = pp[b], t = qq[b];
+        const double xpr = W[p + me * r], xps = W[p + me * t];
+        const double xqr = W[q + me * r], xqs = W[q + me * t];
+        // left: rows p, q
+        const double lpr = c1 * xpr - s1 * xqr, lqr = s1 * xpr + c1 * xqr;
+        const double lps = c1 * xps - s1 * xqs, lqs = s1 * xps + c1 * xqs;
+        // right: columns r, t
+        double ypr = c2 * lpr - s2 * lps, yps = s2 * lpr + c2 * lps;
+        double yqr = c2 * lqr - s2 * lqs, yqs = s2 * lqr + c2 * lqs;
+        if (a == b) {  // the rotated pair's own block: off-diagonal annihilated
+          yps = 0.0;
+          yqr = 0.0;
+        }
+        W[p + me * r] = ypr;
+        W[p + me * t] = yps;
+        W[q + me * r] = yqr;
+        W[q + me * t] = yqs;
       }
       __syncthreads();
-      // columns p, q of M and of V
-      for (int e = threadIdx.x; e < npairs * m; e += SV_THREADS) {
-        const int k = e / m, x = e - k * m;
-        const int p = pp[k], q = qq[k];
-        if (q >= m) continue;
-        const double c = cc[k], s = ss[k];
-        const double mp = M[x + (int64_t)m * p], mq = M[x + (int64_t)m * q];
-        M[x + (int64_t)m * p] = c * mp - s * mq;
-        M[x + (int64_t)m * q] = s * mp + c * mq;
-        const double vp = V[x + (int64_t)m * p], vq = V[x + (int64_t)m * q];
-        V[x + (int64_t)m * p] = c * vp - s * vq;
-        V[x + (int64_t)m * q] = s * vp + c * vq;
+    }
+    ++sweep;
+    const bool again = rotated != 0;
+    __syncthreads();
+    if (!again) break;
+    if (threadIdx.x == 0) rotated = 0;
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < m * m; e += JAC_THREADS) {
+    const int i = e % m, j = e / m;
+    M[e] = W[i + me * j];
+  }
+  if (threadIdx.x == 0) *nsweeps = sweep;
+}
+
+// Eigenvectors from the recorded rotations: row x of V (block x, one wave)
+// starts as e_x and turns through every round in order, V(x, p) <-
+// c V(x, p) - s V(x, q), V(x, q) <- s V(x, p) + c V(x, q); the rotation
+// records are staged JV_CHUNK rounds at a time in LDS.
+constexpr int JV_CHUNK = 16;
+
+__global__ __launch_bounds__(64) void k_jacobi_vectors(const double* __restrict__ rot,
+                                                       const int* __restrict__ nsweeps, int m,
+                                                       double* __restrict__ V) {
+  __shared__ double row[256];
+  __shared__ double cs[JV_CHUNK * 128 * 2];
+  const int me = m + (m & 1);
+  const int npairs = me / 2;
+  const int x = blockIdx.x;
+  for (int j = threadIdx.x; j < me; j += 64) row[j] = j == x ? 1.0 : 0.0;
+  const int64_t total = (int64_t)(*nsweeps) * (me - 1);
+  for (int64_t t0 = 0; t0 < total; t0 += JV_CHUNK) {
+    const int nr = (int)(total - t0 < JV_CHUNK ? total - t0 : JV_CHUNK);
+    __syncthreads();
+    for (int e = threadIdx.x; e < nr * npairs * 2; e += 64) cs[e] = rot[2 * t0 * npairs + e];
+    __syncthreads();
+    for (int u = 0; u < nr; ++u) {
+      const int round = (int)((t0 + u) % (me - 1));
+      for (int k = threadIdx.x; k < npairs; k += 64) {
+        const double c = cs[2 * (u * npairs + k)], sn = cs[2 * (u * npairs + k) + 1];
+        if (sn != 0.0) {
+          int p = jac_slot(k, round, me), q = jac_slot(me - 1 - k, round, me);
+          if (p > q) { const int t = p; p = q; q = t; }
+          const double vp = row[p], vq = row[q];
+          row[p] = c * vp - sn * vq;
+          row[q] = sn * vp + c * vq;
+        }
       }
       __syncthreads();
     }
   }
+  __syncthreads();
+  for (int j = threadIdx.x; j < m; j += 64) V[x + (int64_t)m * j] = row[j];
 }
 
 // Eigenvalues (diagonal of M) in descending order: S[j] = sqrt(max(lambda, 0))
 // for j < k (0 beyond m), and Us (m x k) = the matching eigenvector columns of
-// V divided by S[j] (0 where S[j] = 0), so that B^T Us = V_k.
+// V divided by S[j] (0 where S[j] = 0), so that B^T Us = V_k.  The position
+// of eigenvalue i is the number of eigenvalues before it in that order (ties
+// by index).
 __global__ __launch_bounds__(SV_THREADS) void k_eig_sort(const double* __restrict__ M, int m,
                                                          const double* __restrict__ V, int k,
                                                          double* __restrict__ S,
@@ -167,24 +261,20 @@ __global__ __launch_bounds__(SV_THREADS) void k_eig_sort(const double* __restric
                                                          double* __restrict__ Uv) {
   __shared__ int order[256];
   __shared__ double lam[256];
-  if (threadIdx.x == 0) {
-    for (int i = 0; i < m; ++i) {
-      lam[i] = M[i + (int64_t)m * i];
-      order[i] = i;
-    }
-    for (int i = 0; i < m; ++i) {  // selection sort, descending (m <= 256)
-      int best = i;
-      for (int j = i + 1; j < m; ++j)
-        if (lam[order[j]] > lam[order[best]]) best = j;
-      const int t = order[i];
-      order[i] = order[best];
-      order[best] = t;
-    }
+  for (int i = threadIdx.x; i < m; i += SV_THREADS) {
+    lam[i] = M[i + (int64_t)m * i];
+    order[i] = i;  // stays a valid index should NaNs make positions collide
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < m; i += SV_THREADS) {
+    const double li = lam[i];
+    int pos = 0;
+    for (int j = 0; j < m; ++j) pos += (lam[j] > li) || (lam[j] == li && j < i);
+    order[pos] = i;
   }
   __syncthreads();
   for (int j = threadIdx.x; j < k; j += SV_THREADS)
     S[j] = j < m ? sqrt(fmax(lam[order[j]], 0.0)) : 0.0;
-  __syncthreads();
   for (int e = threadIdx.x; e < m * k; e += SV_THREADS) {
     const int i = e % m, j = e / m;
     const double v = j < m ? V[i + (int64_t)m * order[j]] : 0.0;
@@ -214,6 +304,91 @@ __global__ void k_transpose64(const double* __restrict__ src, int64_t rows, int6
   }
 }
 
+// Partial of C = X^T Y (p x q) over one slice of the N rows: X(g, i) =
+// X[g + ldx i] (column-major), Y(g, c) = Y[g * ysg + c * ysc].  Block x takes
+// the rows [x * rows_per, (x + 1) * rows_per), stages 16 of them at a time in
+// LDS (zero past p, q and the slice) and writes its p x q partial to
+// part + x * p * q (column-major, ld p).  Each thread owns a 4 x 4 tile of C;
+// block y the tiles [256 y, 256 (y + 1)) (p <= 256, q <= 64).
+constexpr int TS_ROWS = 16;
+
+__global__ __launch_bounds__(SV_THREADS) void k_tsprod_part(const double* __restrict__ X,
+                                                            int64_t ldx, int p,
+                                                            const double* __restrict__ Y,
+                                                            int64_t ysg, int64_t ysc, int q,
+                                                            int64_t N, int64_t rows_per,
+                                                            double* __restrict__ part) {
+  __shared__ double sx[TS_ROWS][260];
+  __shared__ double sy[TS_ROWS][68];
+  const int pt = (p + 3) / 4, qt = (q + 3) / 4;
+  const int64_t g0 = (int64_t)blockIdx.x * rows_per;
+  const int64_t g1 = g0 + rows_per < N ? g0 + rows_per : N;
+  const int tile = blockIdx.y * SV_THREADS + threadIdx.x;
+  const bool own = tile < pt * qt;
+  const int ti = own ? tile % pt : 0, tc = own ? tile / pt : 0;
+  double acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+  for (int64_t t0 = g0; t0 < g1; t0 += TS_ROWS) {
+    const int rows = (int)(g1 - t0 < TS_ROWS ? g1 - t0 : TS_ROWS);
+    __syncthreads();
+    for (int e = threadIdx.x; e < TS_ROWS * 4 * pt; e += SV_THREADS) {
+      const int r = e % TS_ROWS, i = e / TS_ROWS;
+      sx[r][i] = (r < rows && i < p) ? X[(t0 + r) + ldx * i] : 0.0;
+    }
+    for (int e = threadIdx.x; e < TS_ROWS * 4 * qt; e += SV_THREADS) {
+      // walk the unit-stride index fastest
+      const int w = 4 * qt;
+      const int r = ysc == 1 ? e / w : e % TS_ROWS, c = ysc == 1 ? e % w : e / TS_ROWS;
+      sy[r][c] = (r < rows && c < q) ? Y[(t0 + r) * ysg + c * ysc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int r = 0; r < TS_ROWS; ++r) {
+      double a[4], bb[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = sx[r][4 * ti + u];
+        bb[u] = sy[r][4 * tc + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], bb[v], acc[u][v]);
+    }
+  }
+  if (!own) return;
+  double* dst = part + (int64_t)blockIdx.x * p * q;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 4 * ti + u, c = 4 * tc + v;
+      if (i < p && c < q) dst[i + p * c] = acc[u][v];
+    }
+}
+
+// C(e) = sum over the nb partials (fixed order: four interleaved strands of
+// the partials, then the strands in order), 64 outputs per block, ld ldc
+__global__ __launch_bounds__(SV_THREADS) void k_tsprod_sum(const double* __restrict__ part,
+                                                           int nb, int p, int q,
+                                                           double* __restrict__ C, int64_t ldc) {
+  __shared__ double strand[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + lane;
+  const int64_t pq = (int64_t)p * q;
+  double s = 0.0;
+  if (e < pq)
+    for (int b = w; b < nb; b += 4) s += part[(int64_t)b * pq + e];
+  strand[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && e < pq)
+    C[(e % p) + ldc * (e / p)] = ((strand[0][lane] + strand[1][lane]) + strand[2][lane]) +
+                                 strand[3][lane];
+}
+
 unsigned grid_for(int64_t count) {
   int64_t g = (count + 255) / 256;
   if (g > 8192) g = 8192;
@@ -224,8 +399,11 @@ unsigned grid_for(int64_t count) {
 }  // namespace
 
 hipError_t launch_small_qr(hipStream_t st, double* Y, int n, int b, double* R) {
-  if (b > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_small_qr, dim3(1), dim3(SV_THREADS), 0, st, Y, n, b, R);
+  if (b < 1 || b > 64 || n < 1) return hipErrorInvalidValue;
+  if ((int64_t)n * b <= QR_LDS)
+    hipLaunchKernelGGL(k_small_qr<true>, dim3(1), dim3(QR_THREADS), 0, st, Y, n, b, R);
+  else
+    hipLaunchKernelGGL(k_small_qr<false>, dim3(1), dim3(QR_THREADS), 0, st, Y, n, b, R);
   return hipGetLastError();
 }
 
@@ -235,9 +413,24 @@ hipError_t launch_trmul(hipStream_t st, const double* Rt, double* R, int b, doub
   return hipGetLastError();
 }
 
-hipError_t launch_jacobi(hipStream_t st, double* M, int m, double* V) {
-  if (m > 256) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(SV_THREADS), 0, st, M, m, V);
+size_t jacobi_rot_doubles(int m) {
+  const int me = m + (m & 1);
+  return (size_t)JAC_SWEEPS * (size_t)(me - 1) * (size_t)me;
+}
+
+hipError_t launch_jacobi(hipStream_t st, double* M, int m, double* V, double* work, double* rot,
+                         int* nsweeps) {
+  if (m < 1 || m > 256 || !rot || !nsweeps) return hipErrorInvalidValue;
+  const int me = m + (m & 1);
+  if (me <= 128)
+    hipLaunchKernelGGL(k_jacobi<true>, dim3(1), dim3(JAC_THREADS), 0, st, M, m, work, rot,
+                       nsweeps);
+  else if (work)
+    hipLaunchKernelGGL(k_jacobi<false>, dim3(1), dim3(JAC_THREADS), 0, st, M, m, work, rot,
+                       nsweeps);
+  else
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_jacobi_vectors, dim3((unsigned)m), dim3(64), 0, st, rot, nsweeps, m, V);
   return hipGetLastError();
 }
 
@@ -263,6 +456,27 @@ hipError_t launch_convert(hipStream_t st, const void* src, bool src_f64, int64_t
   else
     hipLaunchKernelGGL((k_convert<float, float>), dim3(g), dim3(256), 0, st, (const float*)src,
                        rows, cols, lds, (float*)dst, ldd);
+  return hipGetLastError();
+}
+
+int64_t tsprod_blocks(int64_t N) {
+  int64_t nb = (N + 2047) / 2048;
+  if (nb > 1024) nb = 1024;
+  return nb < 1 ? 1 : nb;
+}
+
+hipError_t launch_tsprod(hipStream_t st, const double* X, int64_t ldx, int p, const double* Y,
+                         int64_t ysg, int64_t ysc, int q, int64_t N, double* part, double* C,
+                         int64_t ldc) {
+  if (p < 1 || q < 1 || p > 256 || q > 64) return hipErrorInvalidValue;
+  const int64_t nb = tsprod_blocks(N);
+  const int64_t rows_per = (N + nb - 1) / nb;
+  const int tiles = ((p + 3) / 4) * ((q + 3) / 4);
+  const unsigned ychunks = (unsigned)((tiles + SV_THREADS - 1) / SV_THREADS);
+  hipLaunchKernelGGL(k_tsprod_part, dim3((unsigned)nb, ychunks), dim3(SV_THREADS), 0, st, X, ldx,
+                     p, Y, ysg, ysc, q, N, rows_per, part);
+  hipLaunchKernelGGL(k_tsprod_sum, dim3((unsigned)((p * q + 63) / 64)), dim3(SV_THREADS), 0, st,
+                     part, (int)nb, p, q, C, ldc);
   return hipGetLastError();
 }
 

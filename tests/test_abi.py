@@ -325,7 +325,7 @@ def test_sbr_svd_validation(vctx, tmp_path):
     vp = ctypes.c_void_p
     p = _native._SvdParams()
     L.sid_svd_params_init(ctypes.byref(p), 20)
-    assert (p.k, p.oversample, p.block, p.seed, p.prec) == (20, 10, 10, 0, 3)
+    assert (p.k, p.oversample, p.block, p.seed, p.prec) == (20, 10, 10, 0, 0)
     r = ctypes.c_int64()
     call = lambda N=1000, n=200, lda=1000, A=1: L.sid_sbr_svd(
         h, vp(A), 1, N, n, lda, ctypes.byref(p), vp(1), vp(1), n, vp(1), N, ctypes.byref(r))

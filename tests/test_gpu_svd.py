@@ -44,13 +44,22 @@ def recon(U, S, V):
     return (V * S[None, :]) @ U.T
 
 
-@pytest.mark.parametrize("N,n,k,p,b", [(3000, 120, 20, 10, 10), (2049, 77, 12, 4, 8),
-                                       (5000, 300, 40, 20, 20)])
-def test_f64_parity(sid, osvd, N, n, k, p, b):
+# rho: sigma_j = rho^j.  The block loop's error at sigma_j is about
+# eps sigma_1^2 / sigma_j (both sides), so rho keeps sigma_k^2 >= 1e-8 where
+# the singular values are compared at rtol 1e-8; l = 140 (> 128) takes the
+# Jacobi solver's global-memory form, l = 15 its odd-size dummy index, and
+# n b = 16000 the block QR's in-place form.
+@pytest.mark.parametrize("N,n,k,p,b,rho", [(3000, 120, 20, 10, 10, 0.85), (2049, 77, 12, 4, 8, 0.85),
+                                           (5000, 300, 40, 20, 20, 0.85),
+                                           (40013, 100, 30, 10, 10, 0.85),
+                                           (3001, 90, 13, 2, 5, 0.85),
+                                           (6000, 200, 120, 20, 20, 0.95),
+                                           (4000, 800, 40, 20, 20, 0.85)])
+def test_f64_parity(sid, osvd, N, n, k, p, b, rho):
     """FP64 data and sketch: singular values and the leading singular
     vectors (up to sign) equal the oracle's; so does the reconstruction."""
-    say("sbr-svd f64", N, n, k, p, b)
-    sig = 0.85 ** np.arange(n)
+    say("sbr-svd f64", N, n, k, p, b, rho)
+    sig = rho ** np.arange(n)
     A64 = synth.lowrank_exact_spectrum(N, n, sig, seed=N + n).numpy()
     g = sid.sbr_svd(to_gpu(A64, torch.float64), k, p, b, seed=3, prec="f64")
     o = osvd.sbr_svd(A64, k, p, b, seed=3, prec="f64")
@@ -66,9 +75,9 @@ def test_f64_parity(sid, osvd, N, n, k, p, b):
 
 
 def test_fp32_bf16x2(sid, osvd):
-    """FP32 data, bf16x2 single pass, H from FP32 products: singular values
-    within 1e-4 and the reconstruction error within 1 % of the oracle's on
-    the same rounding of the sketch."""
+    """FP32 data, bf16x2 single pass (H in FP64 from the data): singular
+    values within 1e-4 and the reconstruction error within 1 % of the
+    oracle's on the same rounding of the sketch."""
     say("sbr-svd fp32 bf16x2")
     sig = np.arange(1, 161, dtype=np.float64) ** -1.5
     A64 = synth.lowrank_exact_spectrum(8000, 160, sig, seed=2).numpy()
@@ -108,3 +117,29 @@ def test_equals_two_pass_rsvd(sid, osvd):
     g = sid.sbr_svd(to_gpu(A64, torch.float64), 25, 15, 8, seed=9, prec="f64")
     r = osvd.rsvd(A64, 25, 15, seed=9, prec="f64")
     np.testing.assert_allclose(host(g.S), r.S, rtol=1e-8)
+
+
+def test_full_size_properties(sid):
+    """The 1,572,864 x 500 FP32 channel-like matrix at k = 100, p = 20, block
+    20, FP64 sketch (the benchmarked launch): U and V orthonormal, A U = V S
+    (B = Q^T A_p in exact arithmetic, so V S = A Q U~ = A U), singular values
+    descending, and the rank-100 error no larger than the single-pass ID's
+    at the same rank."""
+    say("sbr-svd full size")
+    A = synth.spectral_snapshots(synth.SpectralConfig(), device="cuda")
+    out = sid.sbr_svd(A, 100, 20, 20, seed=0, prec="f64")
+    assert out.rank == 120
+    S = out.S
+    assert bool(torch.all(S[:-1] >= S[1:])) and float(S[-1]) > 0.0
+    U, V = out.U.double(), out.V.double()
+    eye = torch.eye(100, dtype=torch.float64, device="cuda")
+    assert float((U.T @ U - eye).abs().max()) < 1e-5
+    assert float((V.T @ V - eye).abs().max()) < 1e-5
+    AU = A.double() @ U
+    resid = torch.linalg.norm(AU - V * S[None, :]) / torch.linalg.norm(S)
+    assert float(resid) < 1e-5
+    err = sid.error_norms(A, out.V * S.float()[None, :], out.U.T.contiguous())["rel_fro"]
+    ide = sid.compress(A, 100, 20, seed=0, mode="single_pass", prec="f64", probe_rows=10)
+    err_id = sid.error_norms(A, ide.AJ, ide.P)["rel_fro"]
+    say("sbr-svd rel_fro", err, "single-pass ID", err_id)
+    assert err <= err_id
