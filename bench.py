@@ -318,6 +318,10 @@ def svd_main(args, torch, sid, synth) -> int:
               f"rank {out.rank}", file=sys.stderr, flush=True)
     ide = sid.compress(A, k, p, seed=0, mode="single_pass", prec="bf16x2", probe_rows=10)
     err_id = sid.error_norms(A, ide.AJ, ide.P)
+    # the optimal rank-k error (Eckart-Young) from the eigenvalues of A^T A in FP64
+    import numpy as np
+    lam = np.linalg.eigvalsh((A.double().T @ A.double()).cpu().numpy())[::-1].clip(min=0)
+    opt = float(np.sqrt(lam[k:].sum() / lam.sum()))
     ms, rel, out = runs["f64"]
     line = {
         "metric": "snapshot GB/s compressed (SBR-SVD, Alg. 2, k=100)",
@@ -331,6 +335,7 @@ def svd_main(args, torch, sid, synth) -> int:
                    "sigma_1": float(out.S[0]), "sigma_k": float(out.S[k - 1]),
                    "by_sketch_prec": {q: {"ms_per_step": round(v[0], 4), "rel_fro_error": v[1]}
                                       for q, v in runs.items()},
+                   "rel_fro_error_optimal_rank_k": opt,
                    "rel_fro_error_single_pass_id_bf16x2": err_id["rel_fro"]},
     }
     print(json.dumps(line), flush=True)

@@ -383,12 +383,14 @@ sid_status sid_interp_error_norms(sid_ctx *ctx, const sid_interp *ip, const void
  *        loop then stops and S, U, V past it are zero)
  * Arithmetic: G in the sketch precision `prec` (as sid_compress); H (FP32
  * data promoted exactly), the block loop and the SVD in FP64; the SVD of B
- * via the eigendecomposition of B B^T (Jacobi).  The block loop subtracts
- * terms of size sigma_1^2 to leave ones of size sigma_j^2, so an error e
- * (relative) in G reaches B_i as about e (sigma_1 / sigma_j)^2: the default
- * F64 is the precision that keeps the method's accuracy; the low-precision
- * modes are for well-separated spectra only.  The products with N rows run
- * as rocBLAS GEMMs, except B Omega_i (a split reduction over the rows).
+ * via the eigendecomposition of B B^T (cyclic Jacobi).  The block loop
+ * subtracts terms of size sigma_1^2 from H to leave ones of size sigma_j^2,
+ * so H's rounding reaches B_i amplified by about (sigma_1 / sigma_j)^2:
+ * hence H in FP64.  The loop is exact for whichever G the pass produced as
+ * long as H = A_p^T G with that same G (the Y_i^T Q B term takes up the
+ * difference between G and A_p Omega), so `prec` matters as it does for the
+ * ID's sketch, not through that amplification.  The products with N rows
+ * run as rocBLAS GEMMs, except B Omega_i (a split reduction over the rows).
  * Limits: l <= min(n, 256), l % block == 0, block <= 64.  Synchronizes the
  * stream.  Workspace about (2 l + 1.5 block) N doubles.
  */

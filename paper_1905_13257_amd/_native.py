@@ -632,8 +632,7 @@ def sbr_svd(A: torch.Tensor, k: int, oversample: int = 10, block: int = 10, seed
             prec: str = "f64", ctx: Context | None = None) -> SVD:
     """Single-pass blocked randomized SVD (Alg. 2) of A (N x n, snapshots as
     columns): A ~ V diag(S) U^T (sid_sbr_svd).  `prec` is the arithmetic of
-    the pass forming G; the block loop amplifies its error by about
-    (sigma_1 / sigma_l)^2, hence the FP64 default."""
+    the pass forming G; H and the block loop are FP64 whatever it is."""
     ctx = ctx or default_context(A.device)
     A, lda = _colmajor(A)
     N, n = A.shape

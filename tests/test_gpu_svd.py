@@ -141,5 +141,11 @@ def test_full_size_properties(sid):
     err = sid.error_norms(A, out.V * S.float()[None, :], out.U.T.contiguous())["rel_fro"]
     ide = sid.compress(A, 100, 20, seed=0, mode="single_pass", prec="f64", probe_rows=10)
     err_id = sid.error_norms(A, ide.AJ, ide.P)["rel_fro"]
-    say("sbr-svd rel_fro", err, "single-pass ID", err_id)
+    # the optimal rank-100 error from the spectrum of A^T A (FP64)
+    lam = np.linalg.eigvalsh(host(A.double().T @ A.double()))[::-1]
+    opt = float(np.sqrt(lam[100:].clip(min=0).sum() / lam.clip(min=0).sum()))
+    say("sbr-svd rel_fro", err, "single-pass ID", err_id, "optimal", opt)
     assert err <= err_id
+    # the expected-error bound of Sec. 2.3: factor (1 + k / (p - 1))^(1/2) over the
+    # optimum (which the error, formed from FP32 factors, may undercut by rounding only)
+    assert opt * (1 - 1e-4) <= err <= np.sqrt(1 + 100 / 19) * opt
