@@ -25,7 +25,7 @@ enum Slot {
   WS_OMEGA, WS_PART, WS_W, WS_WR, WS_NRM, WS_PIV, WS_R, WS_Q, WS_KEFF, WS_STATS, WS_PD,
   WS_ERR, WS_Y, WS_M, WS_MPR, WS_WJ, WS_PIVM, WS_RM, WS_QM, WS_RKM, WS_C, WS_T, WS_MIX,
   WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COOP, WS_SYNC, WS_R11, WS_FITPART, WS_YTMP, WS_REF_W, WS_REF_WJ, WS_REF_T, WS_REF_G, WS_OMP, WS_A8, WS_IACJT, WS_IPB, WS_IB, WS_IPART, WS_AZ, WS_AE2, WS_APART, WS_SV_H, WS_SV_PART, WS_SV_B, WS_SV_Q, WS_SV_OM32,
-  WS_SV_OM, WS_SV_SMALL, WS_COUNT
+  WS_SV_OM, WS_SV_SMALL, WS_SV_WP, WS_COUNT
 };
 
 struct Buf {
@@ -1745,23 +1745,15 @@ sid_status sid_sbr_svd(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N, 
   SID_BLAS(rocblas_set_stream(bh, hs), "set stream");
   SID_BLAS(rocblas_set_pointer_mode(bh, rocblas_pointer_mode_host), "pointer mode");
   const double one = 1.0, zero = 0.0, mone = -1.0;
-  // (1) H = A G = A W^T (N x l) in FP64; FP32 data is promoted exactly, l
-  // columns at a time, through B^T's storage (not yet in use)
-  if (dtype == SID_F32) {
-    for (int64_t c0 = 0; c0 < n; c0 += l) {
-      const int64_t cw = n - c0 < l ? n - c0 : l;
-      SID_CHECK(sid::launch_convert(hs, (const float*)A + c0 * lda, false, N, cw, lda, Bt, true, N),
-                "A columns in FP64");
-      SID_BLAS(rocblas_dgemm(bh, rocblas_operation_none, rocblas_operation_transpose, (int)N,
-                             (int)l, (int)cw, &one, Bt, (int)N, w.W + c0 * l, (int)l,
-                             c0 == 0 ? &zero : &one, H, (int)N),
-               "H = A W^T");
-    }
-  } else {
-    SID_BLAS(rocblas_dgemm(bh, rocblas_operation_none, rocblas_operation_transpose, (int)N, (int)l,
-                           (int)n, &one, (const double*)A, (int)lda, w.W, (int)l, &zero, H,
-                           (int)N),
-             "H = A W^T");
+  // (1) H = A G = A W^T (N x l) in FP64, FP32 data promoted exactly; W copied
+  // with its leading dimension rounded up to 16 for the kernel's column groups
+  {
+    const int64_t lp = (l + 15) / 16 * 16;
+    double* wp = (double*)ws(ctx, WS_SV_WP, d * (size_t)(lp * n));
+    if (!wp) return SID_ENOMEM;
+    SID_CHECK(sid::launch_convert(hs, w.W, true, l, n, l, wp, true, lp), "W padded");
+    SID_CHECK(sid::launch_h_gemm(hs, A, dtype == SID_F64, lda, N, (int)n, wp, lp, (int)l, H, N),
+              "H = A W^T");
   }
   double gnorm = 0.0;
   SID_BLAS(rocblas_dnrm2(bh, (int)(l * n), w.W, 1, &gnorm), "||G||");

@@ -389,6 +389,90 @@ __global__ __launch_bounds__(SV_THREADS) void k_tsprod_sum(const double* __restr
                                  strand[3][lane];
 }
 
+// H (N x l, column-major, ld ldh) = A W^T in FP64: A (N x n, column-major,
+// ld lda, FP32 promoted exactly or FP64), W (l x n, column-major, ld ldw >=
+// l rounded up to 16, FP64; the rows past l are read, not used).  A workgroup of eight waves owns 128 rows and 128 columns of H
+// (block y: columns 128 y ..); wave v the columns 16 v .. 16 v + 15, each
+// lane two consecutive rows of them (32 accumulators).  Every step over the
+// n columns of A loads one pair of entries per lane and the 16 W entries of
+// the wave through the scalar cache (uniform addresses), then does 32 FMAs
+// per lane in the order c = 0, 1, ..., n - 1.
+constexpr int HG_ROWS = 128;
+constexpr int HG_COLS = 16;
+constexpr int HG_PF = 8;
+
+template <typename T>
+__global__ __launch_bounds__(512) void k_h_gemm(const T* __restrict__ A, int64_t lda,
+                                                int64_t N, int n, const double* __restrict__ W,
+                                                int64_t ldw, int l, double* __restrict__ H,
+                                                int64_t ldh) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int col0 = blockIdx.y * 128 + wave * HG_COLS;
+  if (col0 >= l) return;
+  const int ncol = l - col0 < HG_COLS ? l - col0 : HG_COLS;
+  const int64_t g = (int64_t)blockIdx.x * HG_ROWS + 2 * lane;
+  const bool r0 = g < N, r1 = g + 1 < N;
+  // branch-free loop: rows past N read row N - 1, and W's rows l .. (l
+  // rounded up to 16) - 1 are read (in bounds, ldw >= that) but never stored
+  const int64_t ga = r0 ? g : N - 1, gb = r1 ? g + 1 : N - 1;
+  double acc0[HG_COLS], acc1[HG_COLS];
+#pragma unroll
+  for (int j = 0; j < HG_COLS; ++j) {
+    acc0[j] = 0.0;
+    acc1[j] = 0.0;
+  }
+  const double* w = W + col0;
+  // A's entries run HG_PF columns ahead of the FMAs (a register ring; the
+  // column index is clamped to n - 1 past the end, so every load is in bounds
+  // and the loop has no branch around a memory access)
+  T ra[HG_PF], rb[HG_PF];
+#pragma unroll
+  for (int u = 0; u < HG_PF; ++u) {
+    const int64_t cc = u < n ? u : n - 1;
+    ra[u] = A[ga + lda * cc];
+    rb[u] = A[gb + lda * cc];
+  }
+  const int nfull = n - n % HG_PF;
+  for (int c0 = 0; c0 < nfull; c0 += HG_PF) {
+#pragma unroll
+    for (int u = 0; u < HG_PF; ++u) {
+      const int c = c0 + u;
+      const double a0 = (double)ra[u], a1 = (double)rb[u];
+      const int64_t cn = c + HG_PF < n ? c + HG_PF : n - 1;
+      ra[u] = A[ga + lda * cn];
+      rb[u] = A[gb + lda * cn];
+      const double* wc = w + ldw * (int64_t)c;
+#pragma unroll
+      for (int j = 0; j < HG_COLS; ++j) {
+        acc0[j] = fma(a0, wc[j], acc0[j]);
+        acc1[j] = fma(a1, wc[j], acc1[j]);
+      }
+    }
+  }
+  // the last n % HG_PF columns are already in the ring
+#pragma unroll
+  for (int u = 0; u < HG_PF; ++u) {
+    if (nfull + u < n) {
+      const double a0 = (double)ra[u], a1 = (double)rb[u];
+      const double* wc = w + ldw * (int64_t)(nfull + u);
+#pragma unroll
+      for (int j = 0; j < HG_COLS; ++j) {
+        acc0[j] = fma(a0, wc[j], acc0[j]);
+        acc1[j] = fma(a1, wc[j], acc1[j]);
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < HG_COLS; ++j) {
+    if (j < ncol) {
+      double* h = H + ldh * (int64_t)(col0 + j) + g;
+      if (r0) h[0] = acc0[j];
+      if (r1) h[1] = acc1[j];
+    }
+  }
+}
+
 unsigned grid_for(int64_t count) {
   int64_t g = (count + 255) / 256;
   if (g > 8192) g = 8192;
@@ -456,6 +540,20 @@ hipError_t launch_convert(hipStream_t st, const void* src, bool src_f64, int64_t
   else
     hipLaunchKernelGGL((k_convert<float, float>), dim3(g), dim3(256), 0, st, (const float*)src,
                        rows, cols, lds, (float*)dst, ldd);
+  return hipGetLastError();
+}
+
+hipError_t launch_h_gemm(hipStream_t st, const void* A, bool a_f64, int64_t lda, int64_t N, int n,
+                         const double* W, int64_t ldw, int l, double* H, int64_t ldh) {
+  if (N < 1 || n < 1 || l < 1 || l > 256 || ldw < (l + 15) / 16 * 16 || ldh < N || lda < N)
+    return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((N + HG_ROWS - 1) / HG_ROWS), (unsigned)((l + 127) / 128));
+  if (a_f64)
+    hipLaunchKernelGGL(k_h_gemm<double>, grid, dim3(512), 0, st, (const double*)A, lda, N, n, W,
+                       ldw, l, H, ldh);
+  else
+    hipLaunchKernelGGL(k_h_gemm<float>, grid, dim3(512), 0, st, (const float*)A, lda, N, n, W, ldw,
+                       l, H, ldh);
   return hipGetLastError();
 }
 

@@ -31,6 +31,11 @@ int64_t tsprod_blocks(int64_t N);
 hipError_t launch_tsprod(hipStream_t st, const double* X, int64_t ldx, int p, const double* Y,
                          int64_t ysg, int64_t ysc, int q, int64_t N, double* part, double* C,
                          int64_t ldc);
+// H (N x l, ld ldh) = A W^T in FP64 (A: N x n, ld lda, FP32 promoted exactly
+// or FP64; W: l x n FP64, ld ldw >= l rounded up to 16, the rows past l read
+// but unused); l <= 256
+hipError_t launch_h_gemm(hipStream_t st, const void* A, bool a_f64, int64_t lda, int64_t N, int n,
+                         const double* W, int64_t ldw, int l, double* H, int64_t ldh);
 // dst (cols x rows, ld ldd) = src^T (rows x cols, ld lds), FP64
 hipError_t launch_transpose64(hipStream_t st, const double* src, int64_t rows, int64_t cols,
                               int64_t lds, double* dst, int64_t ldd);
