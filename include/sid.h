@@ -389,10 +389,11 @@ sid_status sid_interp_error_norms(sid_ctx *ctx, const sid_interp *ip, const void
  * hence H in FP64.  The loop is exact for whichever G the pass produced as
  * long as H = A_p^T G with that same G (the Y_i^T Q B term takes up the
  * difference between G and A_p Omega), so `prec` matters as it does for the
- * ID's sketch, not through that amplification.  The products with N rows
- * run as rocBLAS GEMMs, except B Omega_i (a split reduction over the rows).
- * Limits: l <= min(n, 256), l % block == 0, block <= 64.  Synchronizes the
- * stream.  Workspace about (2 l + 1.5 block) N doubles.
+ * ID's sketch, not through that amplification.  H and each block row of B
+ * (H_i - B^T M_i) R_i^-1 are one pass over the rows each (this library's
+ * kernels); B Omega_i, B B^T and V run as rocBLAS GEMMs.  Limits: l <=
+ * min(n, 256), l % block == 0, block <= 64.  Synchronizes the stream once
+ * per block (the stop test).  Workspace about (2 l + 2.5 block) N doubles.
  */
 typedef struct {
     int64_t k;              /* target rank >= 1                       */

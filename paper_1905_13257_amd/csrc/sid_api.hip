@@ -24,8 +24,8 @@ namespace {
 enum Slot {
   WS_OMEGA, WS_PART, WS_W, WS_WR, WS_NRM, WS_PIV, WS_R, WS_Q, WS_KEFF, WS_STATS, WS_PD,
   WS_ERR, WS_Y, WS_M, WS_MPR, WS_WJ, WS_PIVM, WS_RM, WS_QM, WS_RKM, WS_C, WS_T, WS_MIX,
-  WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COOP, WS_SYNC, WS_R11, WS_FITPART, WS_YTMP, WS_REF_W, WS_REF_WJ, WS_REF_T, WS_REF_G, WS_OMP, WS_A8, WS_IACJT, WS_IPB, WS_IB, WS_IPART, WS_AZ, WS_AE2, WS_APART, WS_SV_H, WS_SV_PART, WS_SV_B, WS_SV_Q, WS_SV_OM32,
-  WS_SV_OM, WS_SV_SMALL, WS_SV_WP, WS_COUNT
+  WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COOP, WS_SYNC, WS_R11, WS_FITPART, WS_YTMP, WS_REF_W, WS_REF_WJ, WS_REF_T, WS_REF_G, WS_OMP, WS_A8, WS_IACJT, WS_IPB, WS_IB, WS_IPART, WS_AZ, WS_AE2, WS_APART, WS_SV_H, WS_SV_B, WS_SV_Q, WS_SV_OM32,
+  WS_SV_OM, WS_SV_SMALL, WS_SV_WP, WS_SV_OMN, WS_COUNT
 };
 
 struct Buf {
@@ -1709,7 +1709,7 @@ sid_status sid_sbr_svd(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N, 
   double* Q = (double*)ws(ctx, WS_SV_Q, d * (size_t)n * (size_t)l);
   float* om32 = (float*)ws(ctx, WS_SV_OM32, sizeof(float) * (size_t)N * (size_t)b);
   double* om = (double*)ws(ctx, WS_SV_OM, d * (size_t)N * (size_t)b);
-  double* part = (double*)ws(ctx, WS_SV_PART, d * (size_t)sid::tsprod_blocks(N) * (size_t)(l * b));
+  double* omn = (double*)ws(ctx, WS_SV_OMN, d * (size_t)N * (size_t)b);
   // small buffers: Y0, Y (n x b), C, Z (l x b), R, Rt (b x b), Gram, Vj (l x l),
   // Us, Uv (l x k), mindiag (+ Jacobi's sweep count), Uout (n x k), Jacobi
   // work (l' x l', l' = l rounded up to even) and rotation records
@@ -1718,7 +1718,7 @@ sid_status sid_sbr_svd(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N, 
                         2 * (size_t)(l * l) + 2 * (size_t)(l * k) + 4 + (size_t)(n * k) + le * le +
                         sid::jacobi_rot_doubles((int)l);
   double* sm = (double*)ws(ctx, WS_SV_SMALL, d * nsmall);
-  if (!H || !Bt || !Q || !om32 || !om || !part || !sm) return SID_ENOMEM;
+  if (!H || !Bt || !Q || !om32 || !om || !omn || !sm) return SID_ENOMEM;
   double* Y0 = sm;
   double* Y = Y0 + n * b;
   double* C = Y + n * b;
@@ -1768,9 +1768,11 @@ sid_status sid_sbr_svd(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N, 
     // Y_i = G_i - Q (B Omega_i), G_i = W(i b .. i b + b, :)^T
     SID_CHECK(sid::launch_transpose64(hs, w.W + i * b, b, n, l, Y0, n), "G_i");
     if (j > 0) {
-      // B Omega_i (j x b): a reduction over the N rows, split across blocks
-      SID_CHECK(sid::launch_tsprod(hs, Bt, N, (int)j, om, b, 1, (int)b, N, part, C, l),
-                "B Omega_i");
+      // B Omega_i (j x b): Omega_i transposed to N x b, then a split-K GEMM
+      SID_CHECK(sid::launch_transpose64(hs, om, b, N, b, omn, N), "Omega_i (N x b)");
+      SID_BLAS(rocblas_dgemm(bh, rocblas_operation_transpose, rocblas_operation_none, (int)j,
+                             (int)b, (int)N, &one, Bt, (int)N, omn, (int)N, &zero, C, (int)l),
+               "B Omega_i");
       SID_BLAS(rocblas_dgemm(bh, rocblas_operation_none, rocblas_operation_none, (int)n, (int)b,
                              (int)j, &mone, Q, (int)n, C, (int)l, &one, Y0, (int)n),
                "G_i - Q B Omega_i");
@@ -1793,23 +1795,15 @@ sid_status sid_sbr_svd(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N, 
     SID_CHECK(hipStreamSynchronize(hs), "synchronize");
     // A_p Omega of rank below l: the blocks so far span it (stop)
     if (!(mdiag > 1e-12 * gnorm)) break;
-    // B_i^T = (H_i - B^T (Q^T Y_i + B Omega_i)) R_i^-1, written in place into
-    // the next b columns of B^T
+    // B_i^T = (H_i - B^T (Q^T Y_i + B Omega_i)) R_i^-1 into the next b columns
+    // of B^T, one pass over the rows
     double* Bi = Bt + j * N;
-    SID_CHECK(hipMemcpyAsync(Bi, H + i * b * N, d * (size_t)(N * b), hipMemcpyDeviceToDevice, hs),
-              "H_i");
-    if (j > 0) {
+    if (j > 0)
       SID_BLAS(rocblas_dgemm(bh, rocblas_operation_transpose, rocblas_operation_none, (int)j,
                              (int)b, (int)n, &one, Q, (int)n, Y0, (int)n, &one, C, (int)l),
                "Q^T Y_i + B Omega_i");
-      SID_BLAS(rocblas_dgemm(bh, rocblas_operation_none, rocblas_operation_none, (int)N, (int)b,
-                             (int)j, &mone, Bt, (int)N, C, (int)l, &one, Bi, (int)N),
-               "H_i - B^T M_i");
-    }
-    SID_BLAS(rocblas_dtrsm(bh, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
-                           rocblas_diagonal_non_unit, (int)N, (int)b, &one, R, (int)b, Bi,
-                           (int)N),
-             "B_i^T = (.) R_i^-1");
+    SID_CHECK(sid::launch_block_update(hs, Bt, N, (int)j, H + i * b * N, C, l, R, (int)b, Bi),
+              "B_i^T = (H_i - B^T M_i) R_i^-1");
     SID_CHECK(hipMemcpyAsync(Q + j * n, Y, d * (size_t)(n * b), hipMemcpyDeviceToDevice, hs),
               "Q_i");
     j += b;

@@ -304,91 +304,6 @@ __global__ void k_transpose64(const double* __restrict__ src, int64_t rows, int6
   }
 }
 
-// Partial of C = X^T Y (p x q) over one slice of the N rows: X(g, i) =
-// X[g + ldx i] (column-major), Y(g, c) = Y[g * ysg + c * ysc].  Block x takes
-// the rows [x * rows_per, (x + 1) * rows_per), stages 16 of them at a time in
-// LDS (zero past p, q and the slice) and writes its p x q partial to
-// part + x * p * q (column-major, ld p).  Each thread owns a 4 x 4 tile of C;
-// block y the tiles [256 y, 256 (y + 1)) (p <= 256, q <= 64).
-constexpr int TS_ROWS = 16;
-
-__global__ __launch_bounds__(SV_THREADS) void k_tsprod_part(const double* __restrict__ X,
-                                                            int64_t ldx, int p,
-                                                            const double* __restrict__ Y,
-                                                            int64_t ysg, int64_t ysc, int q,
-                                                            int64_t N, int64_t rows_per,
-                                                            double* __restrict__ part) {
-  __shared__ double sx[TS_ROWS][260];
-  __shared__ double sy[TS_ROWS][68];
-  const int pt = (p + 3) / 4, qt = (q + 3) / 4;
-  const int64_t g0 = (int64_t)blockIdx.x * rows_per;
-  const int64_t g1 = g0 + rows_per < N ? g0 + rows_per : N;
-  const int tile = blockIdx.y * SV_THREADS + threadIdx.x;
-  const bool own = tile < pt * qt;
-  const int ti = own ? tile % pt : 0, tc = own ? tile / pt : 0;
-  double acc[4][4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-  for (int64_t t0 = g0; t0 < g1; t0 += TS_ROWS) {
-    const int rows = (int)(g1 - t0 < TS_ROWS ? g1 - t0 : TS_ROWS);
-    __syncthreads();
-    for (int e = threadIdx.x; e < TS_ROWS * 4 * pt; e += SV_THREADS) {
-      const int r = e % TS_ROWS, i = e / TS_ROWS;
-      sx[r][i] = (r < rows && i < p) ? X[(t0 + r) + ldx * i] : 0.0;
-    }
-    for (int e = threadIdx.x; e < TS_ROWS * 4 * qt; e += SV_THREADS) {
-      // walk the unit-stride index fastest
-      const int w = 4 * qt;
-      const int r = ysc == 1 ? e / w : e % TS_ROWS, c = ysc == 1 ? e % w : e / TS_ROWS;
-      sy[r][c] = (r < rows && c < q) ? Y[(t0 + r) * ysg + c * ysc] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int r = 0; r < TS_ROWS; ++r) {
-      double a[4], bb[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        a[u] = sx[r][4 * ti + u];
-        bb[u] = sy[r][4 * tc + u];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], bb[v], acc[u][v]);
-    }
-  }
-  if (!own) return;
-  double* dst = part + (int64_t)blockIdx.x * p * q;
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = 4 * ti + u, c = 4 * tc + v;
-      if (i < p && c < q) dst[i + p * c] = acc[u][v];
-    }
-}
-
-// C(e) = sum over the nb partials (fixed order: four interleaved strands of
-// the partials, then the strands in order), 64 outputs per block, ld ldc
-__global__ __launch_bounds__(SV_THREADS) void k_tsprod_sum(const double* __restrict__ part,
-                                                           int nb, int p, int q,
-                                                           double* __restrict__ C, int64_t ldc) {
-  __shared__ double strand[4][64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int e = blockIdx.x * 64 + lane;
-  const int64_t pq = (int64_t)p * q;
-  double s = 0.0;
-  if (e < pq)
-    for (int b = w; b < nb; b += 4) s += part[(int64_t)b * pq + e];
-  strand[w][lane] = s;
-  __syncthreads();
-  if (w == 0 && e < pq)
-    C[(e % p) + ldc * (e / p)] = ((strand[0][lane] + strand[1][lane]) + strand[2][lane]) +
-                                 strand[3][lane];
-}
-
 // H (N x l, column-major, ld ldh) = A W^T in FP64: A (N x n, column-major,
 // ld lda, FP32 promoted exactly or FP64), W (l x n, column-major, ld ldw >=
 // l rounded up to 16, FP64; the rows past l are read, not used).  A workgroup of eight waves owns 128 rows and 128 columns of H
@@ -471,6 +386,61 @@ __global__ __launch_bounds__(512) void k_h_gemm(const T* __restrict__ A, int64_t
       if (r1) h[1] = acc1[j];
     }
   }
+}
+
+// One block row of B^T: Bi(g, :) = (Hi(g, :) - sum_{t<j} Bt(g, t) M(t, :)) R^-1
+// for every row g (N rows; Bt, Hi, Bi column-major with ld N; M j x b with
+// ld ldm; R b x b upper triangular with ld b and a nonzero diagonal).  One
+// thread per row with b accumulators; M passes through LDS 64 rows at a
+// time and R is held in LDS; the triangular solve is forward substitution
+// over the columns.  Bi may not overlap Bt(:, 0:j) or Hi.
+constexpr int BU_THREADS = 256;
+
+template <int BMAX>
+__global__ __launch_bounds__(BU_THREADS) void k_block_update(const double* __restrict__ Bt,
+                                                             int64_t N, int j,
+                                                             const double* __restrict__ Hi,
+                                                             const double* __restrict__ M,
+                                                             int64_t ldm,
+                                                             const double* __restrict__ R, int b,
+                                                             double* __restrict__ Bi) {
+  __shared__ double sm[64 * BMAX];
+  __shared__ double sr[BMAX * BMAX];
+  for (int e = threadIdx.x; e < b * b; e += BU_THREADS) sr[e] = R[e];
+  const int64_t g = (int64_t)blockIdx.x * BU_THREADS + threadIdx.x;
+  const int64_t gl = g < N ? g : N - 1;  // rows past N compute on row N - 1, store nothing
+  double x[BMAX];
+#pragma unroll
+  for (int c = 0; c < BMAX; ++c) x[c] = c < b ? Hi[gl + N * c] : 0.0;
+  for (int t0 = 0; t0 < j; t0 += 64) {
+    const int tn = j - t0 < 64 ? j - t0 : 64;
+    __syncthreads();
+    for (int e = threadIdx.x; e < tn * b; e += BU_THREADS) {
+      const int t = e % tn, c = e / tn;
+      sm[t * BMAX + c] = M[(t0 + t) + ldm * c];
+    }
+    __syncthreads();
+    for (int t = 0; t < tn; ++t) {
+      const double v = Bt[gl + N * (int64_t)(t0 + t)];
+#pragma unroll
+      for (int c = 0; c < BMAX; ++c) x[c] = fma(-v, sm[t * BMAX + c], x[c]);
+    }
+  }
+  __syncthreads();
+  // x R^-1 by forward substitution: y_c = (x_c - sum_{t<c} y_t R(t, c)) / R(c, c)
+#pragma unroll
+  for (int c = 0; c < BMAX; ++c) {
+    if (c < b) {
+      double v = x[c];
+#pragma unroll
+      for (int t = 0; t < c; ++t) v = fma(-x[t], sr[t + b * c], v);
+      x[c] = v / sr[c + b * c];
+    }
+  }
+  if (g < N)
+#pragma unroll
+    for (int c = 0; c < BMAX; ++c)
+      if (c < b) Bi[g + N * c] = x[c];
 }
 
 unsigned grid_for(int64_t count) {
@@ -557,24 +527,26 @@ hipError_t launch_h_gemm(hipStream_t st, const void* A, bool a_f64, int64_t lda,
   return hipGetLastError();
 }
 
-int64_t tsprod_blocks(int64_t N) {
-  int64_t nb = (N + 2047) / 2048;
-  if (nb > 1024) nb = 1024;
-  return nb < 1 ? 1 : nb;
-}
-
-hipError_t launch_tsprod(hipStream_t st, const double* X, int64_t ldx, int p, const double* Y,
-                         int64_t ysg, int64_t ysc, int q, int64_t N, double* part, double* C,
-                         int64_t ldc) {
-  if (p < 1 || q < 1 || p > 256 || q > 64) return hipErrorInvalidValue;
-  const int64_t nb = tsprod_blocks(N);
-  const int64_t rows_per = (N + nb - 1) / nb;
-  const int tiles = ((p + 3) / 4) * ((q + 3) / 4);
-  const unsigned ychunks = (unsigned)((tiles + SV_THREADS - 1) / SV_THREADS);
-  hipLaunchKernelGGL(k_tsprod_part, dim3((unsigned)nb, ychunks), dim3(SV_THREADS), 0, st, X, ldx,
-                     p, Y, ysg, ysc, q, N, rows_per, part);
-  hipLaunchKernelGGL(k_tsprod_sum, dim3((unsigned)((p * q + 63) / 64)), dim3(SV_THREADS), 0, st,
-                     part, (int)nb, p, q, C, ldc);
+hipError_t launch_block_update(hipStream_t st, const double* Bt, int64_t N, int j,
+                               const double* Hi, const double* M, int64_t ldm, const double* R,
+                               int b, double* Bi) {
+  if (N < 1 || j < 0 || b < 1 || b > 64 || (j > 0 && ldm < j)) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((N + BU_THREADS - 1) / BU_THREADS));
+  if (b <= 8)
+    hipLaunchKernelGGL(k_block_update<8>, grid, dim3(BU_THREADS), 0, st, Bt, N, j, Hi, M, ldm, R,
+                       b, Bi);
+  else if (b <= 16)
+    hipLaunchKernelGGL(k_block_update<16>, grid, dim3(BU_THREADS), 0, st, Bt, N, j, Hi, M, ldm, R,
+                       b, Bi);
+  else if (b <= 20)
+    hipLaunchKernelGGL(k_block_update<20>, grid, dim3(BU_THREADS), 0, st, Bt, N, j, Hi, M, ldm, R,
+                       b, Bi);
+  else if (b <= 32)
+    hipLaunchKernelGGL(k_block_update<32>, grid, dim3(BU_THREADS), 0, st, Bt, N, j, Hi, M, ldm, R,
+                       b, Bi);
+  else
+    hipLaunchKernelGGL(k_block_update<64>, grid, dim3(BU_THREADS), 0, st, Bt, N, j, Hi, M, ldm, R,
+                       b, Bi);
   return hipGetLastError();
 }
 

@@ -23,19 +23,17 @@ hipError_t launch_eig_sort(hipStream_t st, const double* M, int m, const double*
 // dst = src (rows x cols), element type conversion between FP32 / FP64
 hipError_t launch_convert(hipStream_t st, const void* src, bool src_f64, int64_t rows,
                           int64_t cols, int64_t lds, void* dst, bool dst_f64, int64_t ldd);
-// C (p x q, ld ldc) = X^T Y over N rows, X(g, i) = X[g + ldx i],
-// Y(g, c) = Y[g ysg + c ysc]; split over tsprod_blocks(N) row slices with
-// partials (part: tsprod_blocks(N) p q doubles) summed in a fixed order.
-// p <= 256, q <= 64.
-int64_t tsprod_blocks(int64_t N);
-hipError_t launch_tsprod(hipStream_t st, const double* X, int64_t ldx, int p, const double* Y,
-                         int64_t ysg, int64_t ysc, int q, int64_t N, double* part, double* C,
-                         int64_t ldc);
 // H (N x l, ld ldh) = A W^T in FP64 (A: N x n, ld lda, FP32 promoted exactly
 // or FP64; W: l x n FP64, ld ldw >= l rounded up to 16, the rows past l read
 // but unused); l <= 256
 hipError_t launch_h_gemm(hipStream_t st, const void* A, bool a_f64, int64_t lda, int64_t N, int n,
                          const double* W, int64_t ldw, int l, double* H, int64_t ldh);
+// Bi (N x b, ld N) = (Hi - Bt(:, 0:j) M) R^-1: Bt, Hi column-major with ld N,
+// M j x b (ld ldm), R b x b upper triangular (ld b, nonzero diagonal);
+// b <= 64; Bi must not overlap Bt(:, 0:j) or Hi
+hipError_t launch_block_update(hipStream_t st, const double* Bt, int64_t N, int j,
+                               const double* Hi, const double* M, int64_t ldm, const double* R,
+                               int b, double* Bi);
 // dst (cols x rows, ld ldd) = src^T (rows x cols, ld lds), FP64
 hipError_t launch_transpose64(hipStream_t st, const double* src, int64_t rows, int64_t cols,
                               int64_t lds, double* dst, int64_t ldd);
