@@ -410,6 +410,27 @@ sid_status sid_sbr_svd(sid_ctx *ctx, const void *A, sid_dtype dtype, int64_t N, 
                        void *V, int64_t ldv, int64_t *rank);
 
 /*
+ * SBR-SVD over snapshots that arrive in blocks (Alg. 2's single pass: each
+ * snapshot is read once, its row of G = A_p Omega formed and H += a^T g
+ * added while it is resident).  sid_svd_stream_begin: as sid_sbr_svd for
+ * an N x n_max matrix (parameter rules with n = n_max); the stream holds
+ * W = Psi A (l x n_max FP64), H (N x l FP64) and a stage of
+ * N x min(n_max, 512) values of `dtype`.  Columns are pushed with
+ * sid_stream_push (same rules as for an ID stream); each sketched block of
+ * up to 512 columns also adds its part of H in column order, so the result
+ * is bitwise that of sid_sbr_svd on the whole matrix.  sid_stream_info and
+ * sid_stream_abort apply; sid_stream_finish and sid_stream_save reject an
+ * SBR-SVD stream (SID_EINVAL).  sid_svd_stream_finish: sketches what is
+ * staged, then runs the block loop and the SVD of B with n = the columns
+ * pushed (k + oversample <= n); outputs as sid_sbr_svd.  Frees the stream on
+ * success and on error.
+ */
+sid_status sid_svd_stream_begin(sid_ctx *ctx, sid_dtype dtype, int64_t N, int64_t n_max,
+                                const sid_svd_params *p, sid_stream **out);
+sid_status sid_svd_stream_finish(sid_stream *s, double *S, void *U, int64_t ldu, void *V,
+                                 int64_t ldv, int64_t *rank);
+
+/*
  * Batched compression of independent matrices (one call for many problems,
  * e.g. one per flow variable or dataset).  probs: host array of `count`
  * problems, each with its own A (N x n, lda), parameters and outputs (same

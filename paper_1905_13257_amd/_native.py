@@ -26,6 +26,7 @@ EXPORTS = [
     "sid_stream_save", "sid_stream_restore", "sid_compress_batched",
     "sid_interp_create", "sid_interp_destroy", "sid_interp_rowset", "sid_interp_info",
     "sid_interp_reconstruct", "sid_interp_error_norms", "sid_svd_params_init", "sid_sbr_svd",
+    "sid_svd_stream_begin", "sid_svd_stream_finish",
 ]
 
 
@@ -122,6 +123,9 @@ def load():
     L.sid_svd_params_init.restype = None
     L.sid_sbr_svd.argtypes = [vp, vp, ctypes.c_int, i64, i64, i64, ctypes.POINTER(_SvdParams), vp,
                               vp, i64, vp, i64, ctypes.POINTER(i64)]
+    L.sid_svd_stream_begin.argtypes = [vp, ctypes.c_int, i64, i64, ctypes.POINTER(_SvdParams),
+                                       ctypes.POINTER(vp)]
+    L.sid_svd_stream_finish.argtypes = [vp, vp, vp, i64, vp, i64, ctypes.POINTER(i64)]
     L.sid_interp_create.argtypes = [vp, ctypes.POINTER(_Mesh), ctypes.POINTER(vp)]
     L.sid_interp_destroy.argtypes = [vp]
     L.sid_interp_rowset.argtypes = [vp]
@@ -138,7 +142,7 @@ def load():
                  "sid_stream_save", "sid_compress_batched",
                  "sid_stream_restore", "sid_interp_create", "sid_interp_destroy",
                  "sid_interp_info", "sid_interp_reconstruct", "sid_interp_error_norms",
-                 "sid_sbr_svd"):
+                 "sid_sbr_svd", "sid_svd_stream_begin", "sid_svd_stream_finish"):
         getattr(L, name).restype = ctypes.c_int
     _LIB = L
     return L
@@ -628,6 +632,72 @@ class SVD:
     rank: int         # rows of B formed (k + oversample unless A has lower rank)
 
 
+def _svd_params(ctx: Context, k: int, oversample: int, block: int, seed: int,
+                prec: str) -> "_SvdParams":
+    p = _SvdParams()
+    ctx._lib.sid_svd_params_init(ctypes.byref(p), int(k))
+    p.oversample, p.block, p.seed, p.prec = int(oversample), int(block), int(seed), PRECISIONS[prec]
+    return p
+
+
+class SvdStream:
+    """SBR-SVD over column blocks pushed in arrival order (Alg. 2's single
+    pass; sid_svd_stream_begin, sid_stream_push, sid_svd_stream_finish)."""
+
+    def __init__(self, N: int, n_max: int, k: int, oversample: int = 10, block: int = 10,
+                 seed: int = 0, prec: str = "f64", dtype: torch.dtype = torch.float32,
+                 ctx: Context | None = None):
+        self.ctx = ctx or default_context()
+        self.N, self.k, self.dtype = N, k, dtype
+        p = _svd_params(self.ctx, k, oversample, block, seed, prec)
+        h = ctypes.c_void_p()
+        code = SID_F64 if dtype == torch.float64 else SID_F32
+        self.ctx.check(self.ctx._lib.sid_svd_stream_begin(self.ctx.handle, code, N, n_max,
+                                                          ctypes.byref(p), ctypes.byref(h)))
+        self._h = h
+        self._keep = []
+
+    def push(self, block: torch.Tensor):
+        """block: N x c (any strides; copied to column-major if needed)."""
+        B, ld = _colmajor(block.to(self.dtype))
+        if B.shape[0] != self.N:
+            raise ValueError("block must have N rows")
+        self.ctx.check(self.ctx._lib.sid_stream_push(self._h, _ptr(B), B.shape[1], ld))
+        self._keep.append(B)  # read on the context's stream; kept until finish
+
+    def cols(self) -> int:
+        c = ctypes.c_int64()
+        self.ctx.check(self.ctx._lib.sid_stream_info(self._h, None, ctypes.byref(c), None, None,
+                                                     None))
+        return c.value
+
+    def finish(self) -> SVD:
+        dev = torch.device("cuda", self.ctx.device)
+        k, N, n = self.k, self.N, self.cols()
+        S = torch.empty(k, dtype=torch.float64, device=dev)
+        U = torch.empty((k, n), dtype=self.dtype, device=dev).T
+        V = torch.empty((k, N), dtype=self.dtype, device=dev).T
+        rank = ctypes.c_int64(0)
+        h, self._h = self._h, None
+        self.ctx.check(self.ctx._lib.sid_svd_stream_finish(h, _ptr(S), _ptr(U), U.stride(1),
+                                                           _ptr(V), V.stride(1),
+                                                           ctypes.byref(rank)))
+        self._keep = []
+        return SVD(U=U, S=S, V=V, rank=int(rank.value))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.ctx._lib.sid_stream_abort(self._h)
+            self._h = None
+        self._keep = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def sbr_svd(A: torch.Tensor, k: int, oversample: int = 10, block: int = 10, seed: int = 0,
             prec: str = "f64", ctx: Context | None = None) -> SVD:
     """Single-pass blocked randomized SVD (Alg. 2) of A (N x n, snapshots as
@@ -636,9 +706,7 @@ def sbr_svd(A: torch.Tensor, k: int, oversample: int = 10, block: int = 10, seed
     ctx = ctx or default_context(A.device)
     A, lda = _colmajor(A)
     N, n = A.shape
-    p = _SvdParams()
-    ctx._lib.sid_svd_params_init(ctypes.byref(p), int(k))
-    p.oversample, p.block, p.seed, p.prec = int(oversample), int(block), int(seed), PRECISIONS[prec]
+    p = _svd_params(ctx, k, oversample, block, seed, prec)
     dev = A.device
     S = torch.empty(k, dtype=torch.float64, device=dev)
     U = torch.empty((k, n), dtype=A.dtype, device=dev).T

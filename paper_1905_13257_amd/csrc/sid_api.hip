@@ -81,6 +81,13 @@ struct sid_stream {
   double* W = nullptr;      // lq x n_max, column-major
   void* Y = nullptr;        // N x l row-major (single pass), FP64 for F64 sketches else FP32
   bool y_init = false;
+  // SBR-SVD streams (sid_svd_stream_begin): the ID fields above run the pass
+  // forming G = W^T (two-pass mode, l selection rows); every sketched block
+  // also updates H += A_blk G_blk
+  bool svd = false;
+  sid_svd_params sp{};
+  double* H = nullptr;      // N x l, column-major
+  double* Wp = nullptr;     // one block of W with its leading dimension rounded up to 16
 };
 
 namespace {
@@ -915,6 +922,8 @@ void stream_free(sid_stream* s) {
     if (s->stage) (void)hipFree(s->stage);
     if (s->W) (void)hipFree(s->W);
     if (s->Y) (void)hipFree(s->Y);
+    if (s->H) (void)hipFree(s->H);
+    if (s->Wp) (void)hipFree(s->Wp);
   }
   delete s;
 }
@@ -934,7 +943,12 @@ sid_status stream_alloc(sid_ctx* ctx, sid_stream* s) {
   return SID_OK;
 }
 
-// sketch columns cols .. cols + ncols - 1 from src (leading dimension ld)
+sid_status svd_h_update(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t lda, int64_t N,
+                        int64_t ncols, const double* W, int64_t l, double* wp, double* H,
+                        bool accumulate);
+
+// sketch columns cols .. cols + ncols - 1 from src (leading dimension ld);
+// an SBR-SVD stream then adds them to H while they are resident
 sid_status stream_flush(sid_stream* s, const void* src, int64_t ld, int64_t ncols) {
   sid_ctx* ctx = s->ctx;
   if (ncols <= 0) return SID_OK;
@@ -953,6 +967,11 @@ sid_status stream_flush(sid_stream* s, const void* src, int64_t ld, int64_t ncol
     SID_CHECK(sid::launch_add_inplace(ctx->stream, s->p.prec == SID_SK_F64, s->Y, w.Y,
                                       s->N * s->l, ctx->num_cu),
               "stream: Y accumulation");
+  if (s->svd) {
+    st = svd_h_update(ctx, src, s->dtype, ld, s->N, ncols, s->W + s->lq * s->cols, s->lq, s->Wp,
+                      s->H, s->cols > 0);
+    if (st != SID_OK) return st;
+  }
   s->y_init = s->single;
   s->cols += ncols;
   return SID_OK;
@@ -1072,6 +1091,7 @@ sid_status sid_stream_finish(sid_stream* s, int64_t* J, void* P, int64_t ldp, vo
                              int64_t ldaj, double* err, int64_t* k_eff) {
   if (!s) return SID_EINVAL;
   sid_ctx* ctx = s->ctx;
+  if (s->svd) return fail(ctx, SID_EINVAL, "an SBR-SVD stream ends with sid_svd_stream_finish");
   sid_status st = SID_OK;
   do {
     if (hipSetDevice(ctx->device) != hipSuccess) {
@@ -1138,6 +1158,7 @@ sid_status sid_stream_abort(sid_stream* s) {
 sid_status sid_stream_save(sid_stream* s, void* host_buf, size_t* bytes) {
   if (!s) return SID_EINVAL;
   sid_ctx* ctx = s->ctx;
+  if (s->svd) return fail(ctx, SID_EINVAL, "SBR-SVD streams cannot be saved");
   if (!bytes) return fail(ctx, SID_EINVAL, "bytes is NULL");
   if (s->p.coarse)
     return fail(ctx, SID_EINVAL, "a stream over a coarse row set cannot be saved");
@@ -1673,38 +1694,68 @@ void sid_svd_params_init(sid_svd_params* p, int64_t k) {
                                         std::to_string((int)b_));                    \
   } while (0)
 
-sid_status sid_sbr_svd(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N, int64_t n,
-                       int64_t lda, const sid_svd_params* sp, double* S, void* U, int64_t ldu,
-                       void* V, int64_t ldv, int64_t* rank) {
-  if (!ctx) return SID_EINVAL;
-  if (!sp || !A || !S || !U || !V) return fail(ctx, SID_EINVAL, "null argument");
-  if (dtype != SID_F32 && dtype != SID_F64) return fail(ctx, SID_EINVAL, "unknown dtype");
+}  // extern "C"
+
+namespace {
+
+// Parameters of SBR-SVD on an N x n matrix (n: snapshots; for a stream, its
+// n_max), and the ID parameters of the pass forming G (l selection rows).
+sid_status svd_check(sid_ctx* ctx, const sid_svd_params* sp, int64_t N, int64_t n,
+                     sid_params* gp) {
   const int64_t k = sp->k, b = sp->block, l = sp->k + sp->oversample;
   if (k < 1 || sp->oversample < 0 || b < 1 || b > 64)
     return fail(ctx, SID_EINVAL, "need k >= 1, oversample >= 0, 1 <= block <= 64");
   if (l % b != 0) return fail(ctx, SID_EINVAL, "k + oversample must be a multiple of block");
-  if (l > 256 || l > n || l > N) return fail(ctx, SID_EINVAL, "k + oversample must be <= min(n, N, 256)");
-  if (lda < N || ldu < n || ldv < N) return fail(ctx, SID_EINVAL, "leading dimension too small");
+  if (l > 256 || l > n || l > N)
+    return fail(ctx, SID_EINVAL, "k + oversample must be <= min(n, N, 256)");
   if (sp->prec < SID_SK_F64 || sp->prec > SID_SK_FP8E4M3)
     return fail(ctx, SID_EINVAL, "unknown sketch precision");
-  // (1) the pass over A for G: the ID's sketch with l selection rows
-  sid_params gp;
-  sid_params_init(&gp, l);
-  gp.oversample = 0;
-  gp.seed = sp->seed;
-  gp.mode = SID_TWO_PASS;
-  gp.prec = sp->prec;
-  gp.probe_rows = 0;
+  sid_params_init(gp, l);
+  gp->oversample = 0;
+  gp->seed = sp->seed;
+  gp->mode = SID_TWO_PASS;
+  gp->prec = sp->prec;
+  gp->probe_rows = 0;
   Shape sh;
-  sid_status st = validate(ctx, N, n, &gp, &sh);
-  if (st != SID_OK) return st;
-  SID_NEED_DEVICE(ctx);
-  SID_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
-  Work w;
-  if (reserve(ctx, sh, &w) != SID_OK) return SID_ENOMEM;
+  return validate(ctx, N, n, gp, &sh);
+}
+
+sid_status svd_blas(sid_ctx* ctx) {
+  if (!ctx->blas) {
+    if (rocblas_create_handle(&ctx->blas) != rocblas_status_success) {
+      ctx->blas = nullptr;
+      return fail(ctx, SID_EDEVICE, "rocblas_create_handle failed");
+    }
+  }
+  if (rocblas_set_stream(ctx->blas, ctx->stream) != rocblas_status_success ||
+      rocblas_set_pointer_mode(ctx->blas, rocblas_pointer_mode_host) != rocblas_status_success)
+    return fail(ctx, SID_EDEVICE, "rocBLAS handle set-up failed");
+  return SID_OK;
+}
+
+// H (ld N) = A W^T, or H += A W^T (accumulate), for the ncols columns of A
+// (ld lda) and of W (l x ncols, ld l); W is copied with its leading dimension
+// rounded up to 16 into wp (that many times ncols doubles).
+sid_status svd_h_update(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t lda, int64_t N,
+                        int64_t ncols, const double* W, int64_t l, double* wp, double* H,
+                        bool accumulate) {
+  hipStream_t hs = ctx->stream;
+  const int64_t lp = (l + 15) / 16 * 16;
+  SID_CHECK(sid::launch_convert(hs, W, true, l, ncols, l, wp, true, lp), "W padded");
+  SID_CHECK(sid::launch_h_gemm(hs, A, dtype == SID_F64, lda, N, (int)ncols, wp, lp, (int)l, H, N,
+                               accumulate),
+            "H = A W^T");
+  return SID_OK;
+}
+
+// The block loop and the SVD of B (Alg. 2 after the pass) from W = Psi A
+// (l x n, ld l: G = W^T) and H = A G (N x l, ld N; overwritten).
+sid_status svd_blocks(sid_ctx* ctx, const sid_svd_params* sp, sid_dtype dtype, int64_t N,
+                      int64_t n, const double* W, double* H, double* S, void* U, int64_t ldu,
+                      void* V, int64_t ldv, int64_t* rank) {
+  const int64_t k = sp->k, b = sp->block, l = sp->k + sp->oversample;
   hipStream_t hs = ctx->stream;
   const size_t d = sizeof(double);
-  double* H = (double*)ws(ctx, WS_SV_H, d * (size_t)N * (size_t)l);
   double* Bt = (double*)ws(ctx, WS_SV_B, d * (size_t)N * (size_t)l);
   double* Q = (double*)ws(ctx, WS_SV_Q, d * (size_t)n * (size_t)l);
   float* om32 = (float*)ws(ctx, WS_SV_OM32, sizeof(float) * (size_t)N * (size_t)b);
@@ -1718,7 +1769,7 @@ sid_status sid_sbr_svd(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N, 
                         2 * (size_t)(l * l) + 2 * (size_t)(l * k) + 4 + (size_t)(n * k) + le * le +
                         sid::jacobi_rot_doubles((int)l);
   double* sm = (double*)ws(ctx, WS_SV_SMALL, d * nsmall);
-  if (!H || !Bt || !Q || !om32 || !om || !omn || !sm) return SID_ENOMEM;
+  if (!Bt || !Q || !om32 || !om || !omn || !sm) return SID_ENOMEM;
   double* Y0 = sm;
   double* Y = Y0 + n * b;
   double* C = Y + n * b;
@@ -1733,30 +1784,12 @@ sid_status sid_sbr_svd(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N, 
   double* Uo = mind + 4;
   double* Jw = Uo + n * k;  // Jacobi's working matrix when l > 128
   double* Jrot = Jw + le * le;  // Jacobi's rotation records
-  st = run_sketch(ctx, A, dtype, lda, &gp, sh, w, w.W, nullptr);  // W = Psi A (l x n, ld l)
+  sid_status st = svd_blas(ctx);
   if (st != SID_OK) return st;
-  if (!ctx->blas) {
-    if (rocblas_create_handle(&ctx->blas) != rocblas_status_success) {
-      ctx->blas = nullptr;
-      return fail(ctx, SID_EDEVICE, "rocblas_create_handle failed");
-    }
-  }
   rocblas_handle bh = ctx->blas;
-  SID_BLAS(rocblas_set_stream(bh, hs), "set stream");
-  SID_BLAS(rocblas_set_pointer_mode(bh, rocblas_pointer_mode_host), "pointer mode");
   const double one = 1.0, zero = 0.0, mone = -1.0;
-  // (1) H = A G = A W^T (N x l) in FP64, FP32 data promoted exactly; W copied
-  // with its leading dimension rounded up to 16 for the kernel's column groups
-  {
-    const int64_t lp = (l + 15) / 16 * 16;
-    double* wp = (double*)ws(ctx, WS_SV_WP, d * (size_t)(lp * n));
-    if (!wp) return SID_ENOMEM;
-    SID_CHECK(sid::launch_convert(hs, w.W, true, l, n, l, wp, true, lp), "W padded");
-    SID_CHECK(sid::launch_h_gemm(hs, A, dtype == SID_F64, lda, N, (int)n, wp, lp, (int)l, H, N),
-              "H = A W^T");
-  }
   double gnorm = 0.0;
-  SID_BLAS(rocblas_dnrm2(bh, (int)(l * n), w.W, 1, &gnorm), "||G||");
+  SID_BLAS(rocblas_dnrm2(bh, (int)(l * n), W, 1, &gnorm), "||G||");
   // (2) the blocks
   int64_t j = 0;
   const int64_t s = l / b;
@@ -1764,9 +1797,9 @@ sid_status sid_sbr_svd(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N, 
     // Omega_i = Psi(i b .. i b + b, :)^T, rounded as the sketch read it,
     // stored b x N (ld b)
     SID_CHECK(sid::launch_fill_gaussian(hs, sp->seed, 1u, 0, N, i * b, b, om32), "Omega_i");
-    SID_CHECK(sid::launch_omega_values(hs, sh.prec, om32, N * b, om), "Omega_i values");
+    SID_CHECK(sid::launch_omega_values(hs, sp->prec, om32, N * b, om), "Omega_i values");
     // Y_i = G_i - Q (B Omega_i), G_i = W(i b .. i b + b, :)^T
-    SID_CHECK(sid::launch_transpose64(hs, w.W + i * b, b, n, l, Y0, n), "G_i");
+    SID_CHECK(sid::launch_transpose64(hs, W + i * b, b, n, l, Y0, n), "G_i");
     if (j > 0) {
       // B Omega_i (j x b): Omega_i transposed to N x b, then a split-K GEMM
       SID_CHECK(sid::launch_transpose64(hs, om, b, N, b, omn, N), "Omega_i (N x b)");
@@ -1836,6 +1869,108 @@ sid_status sid_sbr_svd(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N, 
   SID_CHECK(sid::launch_convert(hs, Uo, true, n, k, n, U, dtype == SID_F64, ldu), "U out");
   SID_CHECK(hipStreamSynchronize(hs), "synchronize");
   return SID_OK;
+}
+
+
+}  // namespace
+
+extern "C" {
+
+sid_status sid_sbr_svd(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N, int64_t n,
+                       int64_t lda, const sid_svd_params* sp, double* S, void* U, int64_t ldu,
+                       void* V, int64_t ldv, int64_t* rank) {
+  if (!ctx) return SID_EINVAL;
+  if (!sp || !A || !S || !U || !V) return fail(ctx, SID_EINVAL, "null argument");
+  if (dtype != SID_F32 && dtype != SID_F64) return fail(ctx, SID_EINVAL, "unknown dtype");
+  sid_params gp;
+  sid_status st = svd_check(ctx, sp, N, n, &gp);
+  if (st != SID_OK) return st;
+  if (lda < N || ldu < n || ldv < N) return fail(ctx, SID_EINVAL, "leading dimension too small");
+  const int64_t l = sp->k + sp->oversample;
+  Shape sh;
+  st = validate(ctx, N, n, &gp, &sh);
+  if (st != SID_OK) return st;
+  SID_NEED_DEVICE(ctx);
+  SID_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+  Work w;
+  if (reserve(ctx, sh, &w) != SID_OK) return SID_ENOMEM;
+  const size_t d = sizeof(double);
+  double* H = (double*)ws(ctx, WS_SV_H, d * (size_t)N * (size_t)l);
+  double* wp = (double*)ws(ctx, WS_SV_WP, d * (size_t)((l + 15) / 16 * 16) * (size_t)n);
+  if (!H || !wp) return SID_ENOMEM;
+  // (1) the pass over A: G = W^T from the ID's sketch with l selection rows
+  // (W = Psi A, l x n, ld l), then H = A G in FP64 (FP32 data promoted exactly)
+  st = run_sketch(ctx, A, dtype, lda, &gp, sh, w, w.W, nullptr);
+  if (st != SID_OK) return st;
+  st = svd_h_update(ctx, A, dtype, lda, N, n, w.W, l, wp, H, false);
+  if (st != SID_OK) return st;
+  // (2) the blocks and the SVD of B
+  return svd_blocks(ctx, sp, dtype, N, n, w.W, H, S, U, ldu, V, ldv, rank);
+}
+
+sid_status sid_svd_stream_begin(sid_ctx* ctx, sid_dtype dtype, int64_t N, int64_t n_max,
+                                const sid_svd_params* sp, sid_stream** out) {
+  if (!ctx) return SID_EINVAL;
+  if (!out) return fail(ctx, SID_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!sp) return fail(ctx, SID_EINVAL, "null argument");
+  if (dtype != SID_F32 && dtype != SID_F64) return fail(ctx, SID_EINVAL, "unknown dtype");
+  sid_params gp;
+  sid_status st = svd_check(ctx, sp, N, n_max, &gp);
+  if (st != SID_OK) return st;
+  SID_NEED_DEVICE(ctx);
+  SID_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+  sid_stream* s = nullptr;
+  st = stream_make(ctx, dtype, N, n_max, &gp, &s);
+  if (st != SID_OK) return st;
+  const int64_t l = sp->k + sp->oversample;
+  if (s->lq != l) {
+    stream_free(s);
+    return fail(ctx, SID_EINVAL, "internal: G's sketch rows differ from k + oversample");
+  }
+  s->svd = true;
+  s->sp = *sp;
+  const size_t d = sizeof(double);
+  const int64_t lp = (l + 15) / 16 * 16;
+  if (hipMalloc((void**)&s->H, d * (size_t)N * (size_t)l) != hipSuccess ||
+      hipMalloc((void**)&s->Wp, d * (size_t)lp * (size_t)s->stage_cols) != hipSuccess) {
+    (void)hipGetLastError();
+    stream_free(s);
+    return fail(ctx, SID_ENOMEM, "stream: device allocation of H failed");
+  }
+  *out = s;
+  return SID_OK;
+}
+
+sid_status sid_svd_stream_finish(sid_stream* s, double* S, void* U, int64_t ldu, void* V,
+                                 int64_t ldv, int64_t* rank) {
+  if (!s) return SID_EINVAL;
+  sid_ctx* ctx = s->ctx;
+  if (!s->svd) return fail(ctx, SID_EINVAL, "not an SBR-SVD stream (sid_stream_finish ends it)");
+  sid_status st = SID_OK;
+  do {
+    if (!S || !U || !V) {
+      st = fail(ctx, SID_EINVAL, "null argument");
+      break;
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) {
+      st = fail(ctx, SID_EDEVICE, "hipSetDevice");
+      break;
+    }
+    st = stream_flush_stage(s);
+    if (st != SID_OK) break;
+    const int64_t n = s->cols;
+    sid_params gp;
+    st = svd_check(ctx, &s->sp, s->N, n, &gp);
+    if (st != SID_OK) break;
+    if (ldu < n || ldv < s->N) {
+      st = fail(ctx, SID_EINVAL, "leading dimension too small");
+      break;
+    }
+    st = svd_blocks(ctx, &s->sp, s->dtype, s->N, n, s->W, s->H, S, U, ldu, V, ldv, rank);
+  } while (false);
+  stream_free(s);
+  return st;
 }
 
 }  // extern "C"

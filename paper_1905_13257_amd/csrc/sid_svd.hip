@@ -304,7 +304,7 @@ __global__ void k_transpose64(const double* __restrict__ src, int64_t rows, int6
   }
 }
 
-// H (N x l, column-major, ld ldh) = A W^T in FP64: A (N x n, column-major,
+// H (N x l, column-major, ld ldh) = A W^T (or H += A W^T) in FP64: A (N x n, column-major,
 // ld lda, FP32 promoted exactly or FP64), W (l x n, column-major, ld ldw >=
 // l rounded up to 16, FP64; the rows past l are read, not used).  A workgroup of eight waves owns 128 rows and 128 columns of H
 // (block y: columns 128 y ..); wave v the columns 16 v .. 16 v + 15, each
@@ -320,7 +320,7 @@ template <typename T>
 __global__ __launch_bounds__(512) void k_h_gemm(const T* __restrict__ A, int64_t lda,
                                                 int64_t N, int n, const double* __restrict__ W,
                                                 int64_t ldw, int l, double* __restrict__ H,
-                                                int64_t ldh) {
+                                                int64_t ldh, bool accumulate) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int col0 = blockIdx.y * 128 + wave * HG_COLS;
@@ -331,11 +331,14 @@ __global__ __launch_bounds__(512) void k_h_gemm(const T* __restrict__ A, int64_t
   // branch-free loop: rows past N read row N - 1, and W's rows l .. (l
   // rounded up to 16) - 1 are read (in bounds, ldw >= that) but never stored
   const int64_t ga = r0 ? g : N - 1, gb = r1 ? g + 1 : N - 1;
+  // accumulate: the sums continue from H's entries (so H += A W^T over
+  // successive column blocks gives the bits of one call over all of them)
   double acc0[HG_COLS], acc1[HG_COLS];
 #pragma unroll
   for (int j = 0; j < HG_COLS; ++j) {
-    acc0[j] = 0.0;
-    acc1[j] = 0.0;
+    const double* h = H + ldh * (int64_t)(col0 + (j < ncol ? j : ncol - 1));
+    acc0[j] = (accumulate && r0) ? h[g] : 0.0;
+    acc1[j] = (accumulate && r1) ? h[g + 1] : 0.0;
   }
   const double* w = W + col0;
   // A's entries run HG_PF columns ahead of the FMAs (a register ring; the
@@ -514,16 +517,17 @@ hipError_t launch_convert(hipStream_t st, const void* src, bool src_f64, int64_t
 }
 
 hipError_t launch_h_gemm(hipStream_t st, const void* A, bool a_f64, int64_t lda, int64_t N, int n,
-                         const double* W, int64_t ldw, int l, double* H, int64_t ldh) {
+                         const double* W, int64_t ldw, int l, double* H, int64_t ldh,
+                         bool accumulate) {
   if (N < 1 || n < 1 || l < 1 || l > 256 || ldw < (l + 15) / 16 * 16 || ldh < N || lda < N)
     return hipErrorInvalidValue;
   const dim3 grid((unsigned)((N + HG_ROWS - 1) / HG_ROWS), (unsigned)((l + 127) / 128));
   if (a_f64)
     hipLaunchKernelGGL(k_h_gemm<double>, grid, dim3(512), 0, st, (const double*)A, lda, N, n, W,
-                       ldw, l, H, ldh);
+                       ldw, l, H, ldh, accumulate);
   else
     hipLaunchKernelGGL(k_h_gemm<float>, grid, dim3(512), 0, st, (const float*)A, lda, N, n, W, ldw,
-                       l, H, ldh);
+                       l, H, ldh, accumulate);
   return hipGetLastError();
 }
 

@@ -23,11 +23,13 @@ hipError_t launch_eig_sort(hipStream_t st, const double* M, int m, const double*
 // dst = src (rows x cols), element type conversion between FP32 / FP64
 hipError_t launch_convert(hipStream_t st, const void* src, bool src_f64, int64_t rows,
                           int64_t cols, int64_t lds, void* dst, bool dst_f64, int64_t ldd);
-// H (N x l, ld ldh) = A W^T in FP64 (A: N x n, ld lda, FP32 promoted exactly
-// or FP64; W: l x n FP64, ld ldw >= l rounded up to 16, the rows past l read
-// but unused); l <= 256
+// H (N x l, ld ldh) = A W^T, or H += A W^T with accumulate (continuing each
+// sum from H's entry: column blocks in order give the bits of one call), in
+// FP64 (A: N x n, ld lda, FP32 promoted exactly or FP64; W: l x n FP64, ld
+// ldw >= l rounded up to 16, the rows past l read but unused); l <= 256
 hipError_t launch_h_gemm(hipStream_t st, const void* A, bool a_f64, int64_t lda, int64_t N, int n,
-                         const double* W, int64_t ldw, int l, double* H, int64_t ldh);
+                         const double* W, int64_t ldw, int l, double* H, int64_t ldh,
+                         bool accumulate);
 // Bi (N x b, ld N) = (Hi - Bt(:, 0:j) M) R^-1: Bt, Hi column-major with ld N,
 // M j x b (ld ldm), R b x b upper triangular (ld b, nonzero diagonal);
 // b <= 64; Bi must not overlap Bt(:, 0:j) or Hi

@@ -337,6 +337,17 @@ def test_sbr_svd_validation(vctx, tmp_path):
     assert call() == EINVAL                     # l % block
     p.block, p.oversample = 10, 250
     assert call() == EINVAL                     # l > 256
+    # the streamed form checks the same rules against n_max
+    p.oversample = 10
+    out = vp()
+    begin = lambda N=1000, n_max=200, dt=1: L.sid_svd_stream_begin(h, dt, N, n_max,
+                                                                   ctypes.byref(p),
+                                                                   ctypes.byref(out))
+    assert begin() == ESTATE
+    assert begin(n_max=25) == EINVAL            # l = 30 > n_max
+    assert begin(dt=7) == EINVAL
+    assert L.sid_svd_stream_begin(h, 1, 1000, 200, ctypes.byref(p), None) == EINVAL
+    assert L.sid_svd_stream_finish(None, vp(1), vp(1), 1, vp(1), 1, None) == EINVAL
     import shutil
     import subprocess
     cc = shutil.which("gcc") or shutil.which("cc")

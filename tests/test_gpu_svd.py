@@ -1,4 +1,5 @@
 """GPU parity of SBR-SVD (Alg. 2) against the oracle.  Marked gpu."""
+import ctypes
 import sys
 
 import numpy as np
@@ -149,3 +150,51 @@ def test_full_size_properties(sid):
     # the expected-error bound of Sec. 2.3: factor (1 + k / (p - 1))^(1/2) over the
     # optimum (which the error, formed from FP32 factors, may undercut by rounding only)
     assert opt * (1 - 1e-4) <= err <= np.sqrt(1 + 100 / 19) * opt
+
+
+@pytest.mark.parametrize("dt,prec,blocks", [
+    (torch.float32, "bf16x2", [37, 200, 1, 300, 162]),      # stage flushes at 512, then 188
+    (torch.float64, "f64", [600, 100]),                      # 512 sketched in place, stage 188
+    (torch.float32, "f32", [50, 150]),                        # one flush at finish
+])
+def test_stream_equals_whole(sid, dt, prec, blocks):
+    """Alg. 2's single pass over column blocks (sid_svd_stream_*): each
+    sketched block adds its part of H in column order, so S, U, V equal the
+    whole-matrix sid_sbr_svd bit for bit."""
+    say("sbr-svd stream", dt, prec, blocks)
+    n = sum(blocks)
+    sig = 0.9 ** np.arange(n)
+    A64 = synth.lowrank_exact_spectrum(20000, n, sig, seed=n, noise=1e-7).numpy()
+    A = to_gpu(A64, dt)
+    whole = sid.sbr_svd(A, 24, 16, 8, seed=7, prec=prec)
+    st = sid.SvdStream(20000, n, 24, 16, 8, seed=7, prec=prec, dtype=dt)
+    c0 = 0
+    for nb in blocks:
+        st.push(A[:, c0:c0 + nb])
+        c0 += nb
+    assert st.cols() == n
+    out = st.finish()
+    assert out.rank == whole.rank == 40
+    assert torch.equal(out.S, whole.S)
+    assert torch.equal(out.U, whole.U)
+    assert torch.equal(out.V, whole.V)
+
+
+def test_stream_rules(sid):
+    """An SBR-SVD stream cannot be ended as an ID stream or saved, and needs
+    k + oversample <= the columns pushed."""
+    say("sbr-svd stream rules")
+    A = to_gpu(np.random.default_rng(0).standard_normal((3000, 60)), torch.float32)
+    st = sid.SvdStream(3000, 60, 10, 10, 10)
+    st.push(A[:, :15])
+    L, h = st.ctx._lib, st._h
+    assert L.sid_stream_save(h, None, ctypes.byref(ctypes.c_size_t(0))) == -1
+    with pytest.raises(sid.SidError):
+        st.finish()                                 # 15 columns < l = 20
+    st2 = sid.SvdStream(3000, 60, 10, 10, 10)
+    st2.push(A)
+    z = torch.zeros(1, dtype=torch.int64, device="cuda")
+    assert L.sid_stream_finish(st2._h, ctypes.c_void_p(z.data_ptr()), None, 1, None, 1, None,
+                               None) == -1
+    out = st2.finish()
+    assert out.rank == 20
