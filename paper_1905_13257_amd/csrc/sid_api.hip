@@ -15,6 +15,7 @@
 #include <rocblas/rocblas.h>
 
 #include "sid_adaptive.hpp"
+#include "sid_apply.hpp"
 #include "sid_svd.hpp"
 #include "sid_interp.hpp"
 #include "sid_kernels.hpp"
@@ -817,7 +818,11 @@ static sid_status factor(sid_ctx* ctx, const sid_params* p, const Shape& sh, con
       const bool yf64 = sh.prec == SID_SK_F64;
       const bool ybf = sh.prec == SID_SK_BF16 || sh.prec == SID_SK_BF16X2 ||
                        sh.prec == SID_SK_FP8E4M3;
-      if (ybf && sid::apply_t_bf16_supported(k, l))
+      if (ybf && !f64 && sid::apply_t_bf16_runs_supported(k, l))
+        SID_CHECK(sid::launch_apply_t_bf16_runs(st, (const float*)w.Y, sh.N, l, w.T, k,
+                                                (float*)AJ, ldaj, ctx->num_cu),
+                  "AJ = Y T");
+      else if (ybf && sid::apply_t_bf16_supported(k, l))
         SID_CHECK(sid::launch_apply_t_bf16(st, (const float*)w.Y, sh.N, l, w.T, k, AJ, f64, ldaj,
                                            ctx->num_cu),
                   "AJ = Y T");

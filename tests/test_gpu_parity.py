@@ -645,3 +645,27 @@ def test_coarse_rows_streaming_pass(sid, oracle_mod, prec, shape):
     ist = next((i for i, m in enumerate(ref.cp.margins) if m <= 1e-3), k)
     assert host(out.J)[:ist].tolist() == ref.J[:ist].tolist()
     assert np.array_equal(host(out.AJ).astype(np.float64)[:, :ist], A64[:, ref.J[:ist]])
+
+
+@pytest.mark.parametrize("N,k", [(3001, 16), (4097, 40), (2113, 70), (3001, 90), (4093, 100),
+                                 (2113, 128)])
+def test_single_pass_skeleton_store_paths(sid, N, k):
+    """AJ = Y T of the bf16 sketch precisions: FP32 data takes the kernel that
+    stores 256-byte column runs, FP64 data holding the same values takes the
+    one that stores straight from the matrix tiles; their FP32 sums are
+    formed in the same order, so the two AJ agree bit for bit (k from 16 to
+    128 covers every column-tile count; N leaves a ragged last row block).
+    N is odd so that both inputs reach the sketch through the same FP32
+    staging copy and the two Y are identical."""
+    say("skeleton store paths", N, k)
+    rng = np.random.default_rng(N + k)
+    n = 160
+    A64 = (rng.standard_normal((N, n)) @ np.diag(0.97 ** np.arange(n))).astype(np.float32)
+    A64 = A64.astype(np.float64)
+    o32 = sid.compress(to_gpu(A64, torch.float32), k, 0, seed=5, mode="single_pass",
+                       prec="bf16x2", probe_rows=0)
+    o64 = sid.compress(to_gpu(A64, torch.float64), k, 0, seed=5, mode="single_pass",
+                       prec="bf16x2", probe_rows=0)
+    torch.cuda.synchronize()
+    assert torch.equal(o32.J, o64.J)
+    assert torch.equal(o32.AJ.double(), o64.AJ)
