@@ -109,7 +109,7 @@ __global__ __launch_bounds__(SV_THREADS) void k_trmul(const double* __restrict__
 }
 
 // Cyclic Jacobi eigenvalues of a symmetric M (m x m, column-major, ld m,
-// m <= 256) in place.  The matrix is worked on padded to m' = m rounded up
+// m <= 256; only its upper triangle is read) in place.  The matrix is worked on padded to m' = m rounded up
 // to even (index m' - 1 a zero dummy when m is odd, never rotated), in LDS
 // when m' <= 128, else in `work` (m'^2 doubles).  A sweep visits every pair
 // once in m' - 1 rounds of a round-robin tournament; the pairs of a round are
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(double* __restrict__ M, 
   double* W = SH ? sm : work;
   for (int e = threadIdx.x; e < me * me; e += JAC_THREADS) {
     const int i = e % me, j = e / me;
-    W[e] = (i < m && j < m) ? M[i + (int64_t)m * j] : 0.0;
+    W[e] = (i < m && j < m) ? M[(i < j ? i : j) + (int64_t)m * (i < j ? j : i)] : 0.0;
   }
   if (threadIdx.x == 0) rotated = 0;
   __syncthreads();

@@ -9,7 +9,8 @@ namespace sid {
 hipError_t launch_small_qr(hipStream_t st, double* Y, int n, int b, double* R);
 // R = Rt R for b x b upper triangular factors (ld b); min |R(c, c)| into *mindiag
 hipError_t launch_trmul(hipStream_t st, const double* Rt, double* R, int b, double* mindiag);
-// Jacobi eigensolver of a symmetric m x m matrix (ld m, m <= 256): M becomes
+// Jacobi eigensolver of a symmetric m x m matrix (ld m, m <= 256; the upper
+// triangle is read): M becomes
 // diagonal (eigenvalues), V (m x m, ld m) the eigenvectors; work: (m rounded
 // up to even)^2 doubles, used when that exceeds 128 (else may be NULL); rot:
 // jacobi_rot_doubles(m) doubles of rotation records; nsweeps: one int
