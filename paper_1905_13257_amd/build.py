@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["csrc/sid_kernels.hip", "csrc/sid_sketch_mfma.hip", "csrc/sid_cpqr.hip",
            "csrc/sid_interp.hip", "csrc/sid_adaptive.hip", "csrc/sid_svd.hip",
-           "csrc/sid_apply.hip", "csrc/sid_api.hip"]
+           "csrc/sid_apply.hip", "csrc/sid_sketch_f64.hip", "csrc/sid_api.hip"]
 LIB = os.path.join(HERE, "libsid.so")
 
 HIPCC_FLAGS = [

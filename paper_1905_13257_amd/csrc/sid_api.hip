@@ -16,6 +16,7 @@
 
 #include "sid_adaptive.hpp"
 #include "sid_apply.hpp"
+#include "sid_sketch_f64.hpp"
 #include "sid_svd.hpp"
 #include "sid_interp.hpp"
 #include "sid_kernels.hpp"
@@ -593,6 +594,13 @@ static sid_status run_sketch(sid_ctx* ctx, const void* A, sid_dtype dtype, int64
         SID_CHECK(sid::launch_add_inplace(st, false, Y, ytmp, sh.N * sh.l, ctx->num_cu),
                   "Y slab sum");
     }
+    return SID_OK;
+  }
+  if (sh.prec == SID_SK_F64 && !Y && !rows) {
+    // W only, all rows: the register-tiled FP64 pass (same bits)
+    SID_CHECK(sid::launch_sketch_w_f64(st, A, dtype == SID_F64, lda, sh.N, sh.n, (int)sh.lq,
+                                       p->seed, sh.nchunks, w.part, W),
+              "FP64 sketch pass");
     return SID_OK;
   }
   SID_CHECK(sid::launch_sketch(st, sh.prec, dtype == SID_F64, A, lda, sh.N, sh.n, rows, sh.Ns,
