@@ -596,11 +596,16 @@ static sid_status run_sketch(sid_ctx* ctx, const void* A, sid_dtype dtype, int64
     }
     return SID_OK;
   }
-  if (sh.prec == SID_SK_F64 && !Y && !rows) {
-    // W only, all rows: the register-tiled FP64 pass (same bits)
+  if (sh.prec == SID_SK_F64 && !rows) {
+    // all rows: the register-tiled FP64 passes (the same bits as the general
+    // kernels)
     SID_CHECK(sid::launch_sketch_w_f64(st, A, dtype == SID_F64, lda, sh.N, sh.n, (int)sh.lq,
                                        p->seed, sh.nchunks, w.part, W),
-              "FP64 sketch pass");
+              "FP64 sketch pass (W)");
+    if (Y)
+      SID_CHECK(sid::launch_sketch_y_f64(st, A, dtype == SID_F64, lda, sh.N, sh.n, w.omega,
+                                         (int)sh.l, (double*)Y),
+                "FP64 sketch pass (Y)");
     return SID_OK;
   }
   SID_CHECK(sid::launch_sketch(st, sh.prec, dtype == SID_F64, A, lda, sh.N, sh.n, rows, sh.Ns,

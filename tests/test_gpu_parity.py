@@ -674,26 +674,33 @@ def test_single_pass_skeleton_store_paths(sid, N, k):
 @pytest.mark.parametrize("N,n,k,p,q,dt", [(5000, 77, 20, 10, 10, torch.float32),
                                           (20011, 300, 100, 20, 10, torch.float32),
                                           (3001, 200, 40, 20, 0, torch.float64),
-                                          (70000, 130, 100, 20, 10, torch.float64)])
+                                          (70000, 130, 100, 20, 10, torch.float64),
+                                          (4099, 90, 30, 10, 5, torch.float32),
+                                          (9001, 260, 150, 20, 10, torch.float32)])
 def test_f64_sketch_tiled_equals_general(sid, oracle_mod, N, n, k, p, q, dt):
-    """The F64 sketch of W alone runs on the register-tiled kernel, W with Y
-    on the general one; both sum each row chunk in order with the same FMAs
-    and the chunks in order, so the selection rows of the two W agree bit for
-    bit (several row and column tiles, lq above 128, ragged edges), and the
-    tiled W is within the F64 bound of the oracle's."""
+    """The F64 sketches over all rows run on the register-tiled kernels; a
+    row set holding every row sends the same sketch through the general
+    kernels.  Both sum each entry in the same order with the same FMAs (W:
+    row chunks, then the chunks in order), so W and Y agree bit for bit
+    (row tiles of 64, 128 and 160 rows and two-tile cases, several column
+    tiles, l above 64 and above 128, ragged edges);
+    the tiled W is also within the F64 bound of the oracle's."""
     say("f64 tiled sketch", N, n, k, p, q, dt)
     rng = np.random.default_rng(N)
     A64 = rng.standard_normal((N, n))
     if dt == torch.float32:
         A64 = A64.astype(np.float32).astype(np.float64)
     A = to_gpu(A64, dt)
+    every = sid.RowSet(np.arange(N, dtype=np.int64), N)
+    for want_y in (False, True):
+        Wt, Yt = sid.sketch(A, k, p, seed=4, prec="f64", probe_rows=q, want_y=want_y)
+        Wg, Yg = sid.sketch(A, k, p, seed=4, prec="f64", probe_rows=q, want_y=want_y,
+                            coarse=every)
+        torch.cuda.synchronize()
+        assert torch.equal(Wt, Wg)
+        if want_y:
+            assert torch.equal(Yt, Yg)
     Wt, _ = sid.sketch(A, k, p, seed=4, prec="f64", probe_rows=q, want_y=False)
-    Wg, _ = sid.sketch(A, k, p, seed=4, prec="f64", probe_rows=q, want_y=True)
-    torch.cuda.synchronize()
-    # rows 0 .. l - 1 are Psi's selection rows in both (the single-pass W
-    # puts its co-range rows before the probe rows)
-    l = k + p
-    assert torch.equal(Wt[:l], Wg[:l])
     lq = Wt.shape[0]
     Wo = oracle_mod.sketch_w(A64, None, lq, 4, "f64")
     bound = _absbound(A64, np.arange(N), lq, 4, "f64", oracle_mod)
