@@ -124,7 +124,10 @@ constexpr int JAC_THREADS = 1024;
 constexpr int JAC_SWEEPS = 40;
 
 __device__ inline int jac_slot(int pos, int round, int me) {
-  return pos == 0 ? 0 : 1 + (pos - 1 + round) % (me - 1);
+  // (pos - 1 + round) mod (me - 1) with both terms below me - 1
+  int v = pos - 1 + round;
+  v = v >= me - 1 ? v - (me - 1) : v;
+  return pos == 0 ? 0 : 1 + v;
 }
 
 template <bool SH>
@@ -133,8 +136,8 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(double* __restrict__ M, 
                                                         double* __restrict__ rot,
                                                         int* __restrict__ nsweeps) {
   __shared__ double sm[SH ? 128 * 128 : 1];
-  __shared__ int pp[128], qq[128];
-  __shared__ double cc[128], ss[128];
+  __shared__ int2 pq[128];     // the pair (p, q) of slot k
+  __shared__ double2 cs[128];  // its rotation (c, s)
   __shared__ int rotated;
   const int me = m + (m & 1);
   const int npairs = me / 2;
@@ -163,19 +166,19 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(double* __restrict__ M, 
           sn = t * c;
           rotated = 1;
         }
-        pp[k] = p;
-        qq[k] = q;
-        cc[k] = c;
-        ss[k] = sn;
+        pq[k] = make_int2(p, q);
+        cs[k] = make_double2(c, sn);
         rr[2 * k] = c;
         rr[2 * k + 1] = sn;
       }
       __syncthreads();
       for (int e = threadIdx.x; e < npairs * npairs; e += JAC_THREADS) {
         const int a = e % npairs, b = e / npairs;
-        const double c1 = cc[a], s1 = ss[a], c2 = cc[b], s2 = ss[b];
+        const double2 ra = cs[a], rb = cs[b];
+        const double c1 = ra.x, s1 = ra.y, c2 = rb.x, s2 = rb.y;
         if (s1 == 0.0 && s2 == 0.0) continue;
-        const int p = pp[a], q = qq[a], r = pp[b], t = qq[b];
+        const int2 pa = pq[a], pb = pq[b];
+        const int p = pa.x, q = pa.y, r = pb.x, t = pb.y;
         const double xpr = W[p + me * r], xps = W[p + me * t];
         const double xqr = W[q + me * r], xqs = W[q + me * t];
         // left: rows p, q
