@@ -67,20 +67,54 @@ def time_steps(fn, steps: int, warmup: int, torch) -> float:
     return start.elapsed_time(end) / steps
 
 
-def cpu_baseline(A, k, p, q, rows: int):
-    """The oracle (FP64, plain loops, OpenMP) on the first `rows` rows."""
+def _oracle_single_thread(sample_path: str, k: int, p: int, q: int) -> float:
+    """Seconds of the oracle on the saved sample with one OpenMP thread (a
+    child process that touches no GPU)."""
+    import subprocess
+    code = ("import sys, time, numpy as np; sys.path.insert(0, %r); import oracle; "
+            "A = np.load(%r); t = time.perf_counter(); "
+            "oracle.compress(A, %d, %d, seed=0, mode='single_pass', prec='f64', probe_rows=%d); "
+            "print(time.perf_counter() - t)" % (ROOT, sample_path, k, p, q))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                         timeout=600)
+    return float(res.stdout.strip().splitlines()[-1])
+
+
+def cpu_baseline(A, k, p, q, rows: int, st_rows: int):
+    """The oracle (FP64, plain loops, OpenMP) on the first `rows` rows, with
+    its per-phase times and the relative Frobenius error of its result, and
+    the same oracle on one thread on the first `st_rows` rows."""
+    import tempfile
     import numpy as np
     import oracle
     oracle.build()
     sample = A[:rows].cpu().numpy().astype(np.float64)
+    phases = {}
     t0 = time.perf_counter()
-    oracle.compress(sample, k, p, seed=0, mode="single_pass", prec="f64", probe_rows=q)
+    res = oracle.compress(sample, k, p, seed=0, mode="single_pass", prec="f64", probe_rows=q,
+                          timings=phases)
     dt = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    err = oracle.error_norms(sample, res.AJ, res.P)
+    t_err = time.perf_counter() - t1
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    st = None
+    if st_rows > 0:
+        with tempfile.TemporaryDirectory() as d:
+            path = os.path.join(d, "sample.npy")
+            np.save(path, np.ascontiguousarray(sample[:st_rows]))
+            del res
+            st_s = _oracle_single_thread(path, k, p, q)
+        st = {"value": st_rows * A.shape[1] * 4 / st_s / 1e9, "unit": "GB/s", "cores": 1,
+              "sample": f"first {st_rows} rows x {A.shape[1]} snapshots, same call; {st_s:.1f} s"}
     return {"value": rows * A.shape[1] * 4 / dt / 1e9, "unit": "GB/s", "cores": threads,
             "kind": "oracle",
             "sample": f"first {rows} of {A.shape[0]} rows x {A.shape[1]} snapshots, single-pass "
-                      f"k={k} p={p} q={q}, FP64; {dt:.1f} s"}
+                      f"k={k} p={p} q={q}, FP64; {dt:.1f} s",
+            "phase_s": {kk: round(v, 3) for kk, v in phases.items()},
+            "rel_fro_error": err["rel_fro"], "error_norms_s": round(t_err, 2),
+            "single_thread": st}
 
 
 def batched_main(args, torch, sid, synth) -> int:
@@ -350,6 +384,8 @@ def main() -> int:
     ap.add_argument("--prec", default="bf16x2", choices=["bf16x2", "bf16", "fp8", "f32", "f64"])
     ap.add_argument("--also", default="bf16,fp8",
                     help="further sketch precisions timed beside the main one (comma list, '' for none)")
+    ap.add_argument("--cpu-st-rows", type=int, default=49152,
+                    help="rows of the single-thread oracle sample (0: skip)")
     ap.add_argument("--cpu-rows", type=int, default=1572864,
                     help="rows of the matrix the oracle baseline compresses (default: all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -436,7 +472,7 @@ def main() -> int:
         sk = lambda: sid.sketch(A, k, p, seed=0, prec=prec, probe_rows=q, want_y=True)
         sketch_ms = time_steps(sk, max(3, steps // 2), 1, torch)
         return dict(ms=ms, gbs=bytes_a / (ms * 1e-3) / 1e9, rel_fro=err["rel_fro"],
-                    rel_max=err["rel_max"], est=float(out.err[0]), sketch_ms=sketch_ms,
+                    max_abs=err["max_abs"], est=float(out.err[0]), sketch_ms=sketch_ms,
                     k_eff=int(out.k_eff[0]))
 
     main_r = run_mode(args.prec, args.steps, args.warmup)
@@ -458,16 +494,19 @@ def main() -> int:
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(A, k, p, q, min(args.cpu_rows, N))
+        cpu = cpu_baseline(A, k, p, q, min(args.cpu_rows, N), min(args.cpu_st_rows, N))
 
     config = {
         "workload": "channel-like snapshots 1572864 x 500 fp32 (3 x 128x64x64 grid), single-pass "
                     "ID k=100 p=20 q=10",
         "N": N, "n": n, "k": k, "oversample": p, "probe_rows": q, "corange_rows": p,
         "sketch_precision": args.prec, "rel_fro_error": main_r["rel_fro"],
-        "rel_max_error": main_r["rel_max"], "probe_estimate": main_r["est"],
+        "max_abs_error": main_r["max_abs"], "probe_estimate": main_r["est"],
         "k_eff": main_r["k_eff"], "sketch_ms": round(main_r["sketch_ms"], 4),
     }
+    if cpu is not None and min(args.cpu_rows, N) == N:
+        # the oracle's own FP64 compression of the same matrix, beside the GPU's
+        config["oracle_rel_fro_error"] = cpu["rel_fro_error"]
     if cmp_r is not None:
         config["fp32_plain"] = {"value": round(cmp_r["gbs"], 2), "ms_per_step": round(cmp_r["ms"], 4),
                                 "rel_fro_error": cmp_r["rel_fro"], "sketch_ms": round(cmp_r["sketch_ms"], 4)}
@@ -479,7 +518,7 @@ def main() -> int:
         "metric": METRIC, "value": round(main_r["gbs"], 2), "unit": "GB/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(main_r["ms"], 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"bf16x2": "bf16", "bf16": "bf16", "fp8": "fp8", "f32": "f32", "f64": "f64"}[args.prec],
+        "dtype": args.prec,
         "data": "synthetic", "config": config, "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -176,6 +176,16 @@ size_t sid_workspace_bytes(const sid_ctx *ctx);
 /* Cap on workspace growth in bytes (0 = none); growth beyond it fails with
  * SID_ENOMEM. */
 sid_status sid_set_workspace_limit(sid_ctx *ctx, size_t bytes);
+/* Wait for all work queued on the context (and its batched children), then
+ * report device-side failures since the previous sid_sync: the
+ * multi-workgroup pivoted QR needs its workgroups resident together; it is
+ * launched cooperatively (which guarantees that) except under graph
+ * capture, where a plain launch is used and a bounded wait that times out
+ * (other work kept some workgroups from starting) sets k_eff = -1 for that
+ * compression and a flag this call reads and clears.  Returns SID_OK, or
+ * SID_EDEVICE with sid_last_error naming the failure (the results with
+ * k_eff = -1 are then invalid). */
+sid_status sid_sync(sid_ctx *ctx);
 
 /* Coarse row set S (Sec. 2.5 eq. (A_c): the sub-sampled degrees of freedom).
  * `host_rows` (host) must be strictly increasing, within [0, N), and count >
@@ -188,11 +198,17 @@ sid_status sid_rowset_create(sid_ctx *ctx, const int64_t *host_rows, int64_t cou
 sid_status sid_rowset_destroy(sid_rowset *rs);
 
 /* Grow the workspace (and create the internal side stream) for compress
- * calls of this shape and these parameters ahead of time.  After it (or
- * after one call of the same shape), sid_compress on the context's
- * stream allocates nothing and synchronizes nothing, so it can be captured
- * into a HIP graph and replayed (the library records no memset nodes; the
- * single-pass side stream joins the capture through events). */
+ * calls of this shape and these parameters ahead of time, including the
+ * sketch buffers of the refinement precision when p->refine is set.  It
+ * sizes for FP32 data with a 16-byte aligned base and lda % 4 == 0 (the
+ * layout of a device allocation); other layouts with the FP8 sketch take a
+ * quantized copy of the data that is sized on first use.  After it (or
+ * after one call of the same shape), sid_compress on the context's stream
+ * allocates nothing and synchronizes nothing, so it can be captured into a
+ * HIP graph and replayed (the library records no memset nodes; the
+ * single-pass side stream joins the capture through events).  A call under
+ * capture whose workspace would have to grow fails with SID_ENOMEM and a
+ * message naming the capture, instead of allocating. */
 sid_status sid_reserve(sid_ctx *ctx, int64_t N, int64_t n, const sid_params *p);
 
 /*
@@ -209,7 +225,11 @@ sid_status sid_reserve(sid_ctx *ctx, int64_t N, int64_t n, const sid_params *p);
  *   err   [2] double: err[0] = relative Frobenius residual of the held-out
  *         probe rows (an estimate of ||A - AJ P||_F / ||A||_F; NaN when
  *         probe_rows = 0), err[1] = relative residual of the sketch fit.
- *   k_eff [1] int64: number of skeleton columns actually chosen.
+ *         With refine = 1 both are fitted with the refined P that is
+ *         returned (on the rows of the first sketch).
+ *   k_eff [1] int64: number of skeleton columns actually chosen; -1 marks a
+ *         failed device-wide wait of the pivoted QR (results invalid; see
+ *         sid_sync).
  * Any of J, P, err, k_eff may be NULL when not wanted.
  * Errors: SID_EINVAL for bad shapes/parameters/null A; SID_ENOMEM when the
  * workspace cannot grow; SID_EDEVICE for a launch failure.

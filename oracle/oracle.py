@@ -429,7 +429,8 @@ def compress_literal(A, k: int, coarse_rows, prec: str = "f64", rank_tol: float 
 def compress(A, k: int, oversample: int, seed: int = 0, coarse_rows=None,
              mode: str = "two_pass", prec: str = "f64", probe_rows: int = 10,
              rank_tol: float = 0.0, sp_rcond: float = 1e-12,
-             corange_extra: int | None = None, probe_tol: float = 0.0) -> Result:
+             corange_extra: int | None = None, probe_tol: float = 0.0,
+             timings: dict | None = None) -> Result:
     """Randomized / sub-sampled ID (Alg. 4-5) or its single-pass form.
 
     A: N x n array (any float type; FP32 data are promoted exactly).
@@ -440,7 +441,17 @@ def compress(A, k: int, oversample: int, seed: int = 0, coarse_rows=None,
     Returns J (pivot order), P (k x n; rows beyond k_eff zero), the skeleton
     (two_pass: A(:, J) copied; single_pass: estimated from the sketches),
     and the two error estimates (err_probe: held-out probe rows; err_sketch:
-    residual of the sketch fit itself)."""
+    residual of the sketch fit itself).  If `timings` is a dict, the wall
+    time of each phase (sketch, mgsqr, coefficients, skeleton) is added to
+    it in seconds."""
+    import time as _time
+    tick = [_time.perf_counter()]
+
+    def phase(name):
+        if timings is not None:
+            t = _time.perf_counter()
+            timings[name] = timings.get(name, 0.0) + t - tick[0]
+            tick[0] = t
     A = np.asarray(A)
     N, n = A.shape
     l = k + oversample
@@ -459,10 +470,13 @@ def compress(A, k: int, oversample: int, seed: int = 0, coarse_rows=None,
     Y = None
     if mode == "single_pass":
         Y = sketch_y(A, omega(seed, n, l, prec), prec)
+    phase("sketch")
     cp = cpqr(W[:l], k, rank_tol)
     if probe_tol > 0.0:
         cp = adaptive_rank(cp, W[lz:], n, probe_tol)
+    phase("mgsqr")
     Pk = id_coefficients(cp.R, cp.J, n)
+    phase("coefficients")
     P = np.zeros((k, n))
     P[:cp.k_eff] = Pk
     J = np.full(k, -1, dtype=np.int64)
@@ -478,6 +492,7 @@ def compress(A, k: int, oversample: int, seed: int = 0, coarse_rows=None,
         raise ValueError(mode)
     AJk = np.zeros((N, k))
     AJk[:, :cp.k_eff] = AJ
+    phase("skeleton")
     return Result(J=J, P=P, AJ=AJk, k_eff=cp.k_eff, err_probe=err_probe,
                   err_sketch=err_sketch, W=W, Y=Y, cp=cp)
 

@@ -26,7 +26,7 @@ EXPORTS = [
     "sid_stream_save", "sid_stream_restore", "sid_compress_batched",
     "sid_interp_create", "sid_interp_destroy", "sid_interp_rowset", "sid_interp_info",
     "sid_interp_reconstruct", "sid_interp_error_norms", "sid_svd_params_init", "sid_sbr_svd",
-    "sid_svd_stream_begin", "sid_svd_stream_finish",
+    "sid_svd_stream_begin", "sid_svd_stream_finish", "sid_sync",
 ]
 
 
@@ -101,6 +101,7 @@ def load():
     L.sid_workspace_bytes.argtypes = [vp]
     L.sid_workspace_bytes.restype = ctypes.c_size_t
     L.sid_set_workspace_limit.argtypes = [vp, ctypes.c_size_t]
+    L.sid_sync.argtypes = [vp]
     L.sid_rowset_create.argtypes = [vp, vp, i64, i64, ctypes.POINTER(vp)]
     L.sid_rowset_destroy.argtypes = [vp]
     L.sid_reserve.argtypes = [vp, i64, i64, pp]
@@ -204,6 +205,11 @@ class Context:
     def set_workspace_limit(self, nbytes: int):
         self.check(self._lib.sid_set_workspace_limit(self._h, nbytes))
 
+    def sync(self):
+        """Wait for the context's work; raises if a device-side wait failed
+        since the last sync (sid_sync)."""
+        self.check(self._lib.sid_sync(self._h))
+
     def close(self):
         if getattr(self, "_h", None):
             self._lib.sid_destroy(self._h)
@@ -227,6 +233,11 @@ def default_context(device: torch.device | int | None = None) -> Context:
     if key not in _CTX:
         _CTX[key] = Context(idx, stream)
     return _CTX[key]
+
+
+def sync(device: torch.device | int | None = None):
+    """sid_sync on the default context of `device` (current stream)."""
+    default_context(device).sync()
 
 
 class RowSet:
@@ -282,7 +293,14 @@ class Compressed:
     P: torch.Tensor          # k x n
     AJ: torch.Tensor | None  # N x k skeleton (copy or single-pass estimate)
     err: torch.Tensor        # float64 [2]: probe estimate, sketch residual
-    k_eff: torch.Tensor      # int64 [1]
+    k_eff: torch.Tensor      # int64 [1]; -1: a device-wide wait failed (invalid)
+
+    def rank(self) -> int:
+        """k_eff as an int (synchronizes); raises on a failed result."""
+        r = int(self.k_eff.item())
+        if r < 0:
+            raise SidError(-3, "k_eff = -1: a device-wide wait of the pivoted QR timed out")
+        return r
 
 
 class _Problem(ctypes.Structure):

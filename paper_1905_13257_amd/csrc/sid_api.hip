@@ -40,7 +40,17 @@ struct Buf {
 struct sid_ctx {
   int device = 0;
   int num_cu = 1;
-  bool cooperative = false;  // SID_COOPERATIVE=1: cooperative launch of the pivoted QR
+  // cooperative launch of the multi-workgroup pivoted QR outside graph
+  // capture (SID_COOPERATIVE=0 turns it off)
+  bool cooperative = true;
+  // sticky device flag: a device-wide wait of the pivoted QR timed out
+  // (set by the kernels, read and cleared by sid_sync)
+  unsigned int* fail_flag = nullptr;
+  // SID_SKETCH_PAIRS=1: the bfloat16 sketch forms take the workgroup-pair
+  // pass also where the one-workgroup-per-row-range pass applies (for
+  // comparison; by default the pair pass serves the shapes the other one
+  // does not take: l > 128 or l + e + q > 160)
+  bool sketch_pairs = false;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::string err;
@@ -115,6 +125,14 @@ void* ws(sid_ctx* c, Slot s, size_t bytes) {
   if (bytes == 0) bytes = 16;
   Buf& b = c->ws[s];
   if (b.bytes >= bytes) return b.p;
+  // growing synchronizes, frees and allocates: none of that may happen while
+  // the stream is being captured into a graph
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(c->stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+    c->err = "the workspace would have to grow while the stream is being captured; call "
+             "sid_reserve with the same shape and parameters before capture";
+    return nullptr;
+  }
   const size_t want = bytes + bytes / 8;
   if (c->limit && held_bytes(c) - b.bytes + want > c->limit) {
     c->err = "workspace limit exceeded";
@@ -318,6 +336,71 @@ sid_status reserve(sid_ctx* c, const Shape& s, Work* w) {
   return SID_OK;
 }
 
+// Which kernels a sketch pass of this shape takes (run_sketch) and what it
+// needs in the workspace (sid_reserve, which assumes FP32 data with a
+// 16-byte aligned base and lda % 4 == 0).
+enum class SketchPath { PAIR_BF16, FUSED_BF16, FUSED_F32, FP8_GENERAL, F64_TILED, GENERAL };
+
+SketchPath plan_sketch(const sid_ctx* ctx, sid_dtype dtype, int64_t lda, const void* A, int prec,
+                       const Shape& sh, bool has_rows, bool want_y) {
+  const bool bf = prec == SID_SK_BF16 || prec == SID_SK_BF16X2 || prec == SID_SK_FP8E4M3;
+  const int64_t slab = sh.n < 512 ? sh.n : 512;
+  // a coarse row list runs on the streaming pass for the bf16 forms of the
+  // two-pass (W only) sketch
+  const bool rows_ok = !has_rows || (!want_y && (prec == SID_SK_BF16 || prec == SID_SK_BF16X2));
+  const bool fused_ok = dtype == SID_F32 && rows_ok &&
+                        sid::fused_bf16_supported(slab, (int)sh.lq, (int)sh.l, lda, A, has_rows);
+  if (bf && fused_ok && !ctx->sketch_pairs) return SketchPath::FUSED_BF16;
+  // the workgroup-pair pass (all rows, FP32 data, column slabs of up to
+  // sketch_v2_slab columns; Y's offsets fit 32 bits): l up to 256 and
+  // l + e + q up to 256, e.g. k = 150, p = 30
+  if (bf && !has_rows && dtype == SID_F32 &&
+      (!want_y || (uint64_t)sh.N * (uint64_t)sh.l * 4u < (1ull << 32))) {
+    const int vslab = sid::sketch_v2_slab((int)sh.lq, (int)sh.l, want_y);
+    if (vslab > 0) {
+      const int64_t vs = sh.n < vslab ? sh.n : vslab;
+      if (sid::sketch_v2_supported(vs, (int)sh.lq, (int)sh.l, want_y, lda, A))
+        return SketchPath::PAIR_BF16;
+    }
+  }
+  if (bf && fused_ok) return SketchPath::FUSED_BF16;
+  if (prec == SID_SK_FP8E4M3) return SketchPath::FP8_GENERAL;
+  if (prec == SID_SK_F32 && fused_ok) return SketchPath::FUSED_F32;
+  if (prec == SID_SK_F64 && !has_rows) return SketchPath::F64_TILED;
+  return SketchPath::GENERAL;
+}
+
+// reserve what run_sketch takes beyond reserve(): the matrix-core pass's
+// partials and Omega^T, the slab sum of Y, the FP8 data copy
+sid_status reserve_sketch(sid_ctx* ctx, const Shape& sh, int prec, bool has_rows,
+                                 bool want_y) {
+  const SketchPath path = plan_sketch(ctx, SID_F32, 4, nullptr, prec, sh, has_rows, want_y);
+  const int64_t slab = sh.n < 512 ? sh.n : 512;
+  if (path == SketchPath::PAIR_BF16) {
+    const int vslab = sid::sketch_v2_slab((int)sh.lq, (int)sh.l, want_y);
+    const int64_t vs = sh.n < vslab ? sh.n : vslab;
+    int64_t rpp = 0;
+    const int64_t pairs = sid::sketch_v2_pairs(sh.N, ctx->num_cu, &rpp);
+    if (!ws(ctx, WS_PARTF, sizeof(float) * (size_t)(pairs * sh.lq * vs)) ||
+        !ws(ctx, WS_OMT, sizeof(uint16_t) * sid::sketch_v2_omt_elems((int)sh.l, (int)vs)))
+      return SID_ENOMEM;
+    if (want_y && sh.n > vs && !ws(ctx, WS_YTMP, sizeof(float) * (size_t)(sh.N * sh.l)))
+      return SID_ENOMEM;
+  } else if (path == SketchPath::FUSED_BF16 || path == SketchPath::FUSED_F32) {
+    int64_t rpw = 0;
+    const int64_t grid = sid::fused_bf16_grid(sh.N, ctx->num_cu, &rpw);  // N >= Ns: the larger
+    const bool bf = path == SketchPath::FUSED_BF16;
+    if (!ws(ctx, WS_PARTF, sizeof(float) * (size_t)(grid * sh.lq * slab)) ||
+        !ws(ctx, bf ? WS_OMT : WS_OMP, bf ? sizeof(uint16_t) * 128 * 512 : sizeof(float) * 128 * 512))
+      return SID_ENOMEM;
+    if (want_y && sh.n > slab && !ws(ctx, WS_YTMP, sizeof(float) * (size_t)(sh.N * sh.l)))
+      return SID_ENOMEM;
+  } else if (path == SketchPath::FP8_GENERAL) {
+    if (!ws(ctx, WS_A8, sizeof(float) * (size_t)(sh.N * sh.n))) return SID_ENOMEM;
+  }
+  return SID_OK;
+}
+
 #define SID_NEED_DEVICE(ctx)                                                        \
   do {                                                                              \
     if ((ctx)->device < 0)                                                          \
@@ -375,12 +458,20 @@ sid_status sid_create(sid_ctx** out, int device, void* hip_stream) {
   c->device = device;
   {
     const char* env = std::getenv("SID_COOPERATIVE");
-    c->cooperative = env && env[0] == '1';
+    c->cooperative = !(env && env[0] == '0');
+    const char* vp = std::getenv("SID_SKETCH_PAIRS");
+    c->sketch_pairs = vp && vp[0] == '1';
   }
   int ncu = 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
       ncu > 0)
     c->num_cu = ncu;
+  if (hipMalloc(&c->fail_flag, 64) != hipSuccess || hipMemset(c->fail_flag, 0, 64) != hipSuccess) {
+    (void)hipGetLastError();
+    if (c->fail_flag) (void)hipFree(c->fail_flag);
+    delete c;
+    return SID_ENOMEM;
+  }
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
   } else {
@@ -411,6 +502,7 @@ sid_status sid_destroy(sid_ctx* ctx) {
   if (ctx->fork) (void)hipEventDestroy(ctx->fork);
   for (Buf& b : ctx->ws)
     if (b.p) (void)hipFree(b.p);
+  if (ctx->fail_flag) (void)hipFree(ctx->fail_flag);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return SID_OK;
@@ -422,6 +514,30 @@ const char* sid_last_error(const sid_ctx* ctx) {
 }
 
 size_t sid_workspace_bytes(const sid_ctx* ctx) { return ctx ? held_bytes(ctx) : 0; }
+
+sid_status sid_sync(sid_ctx* ctx) {
+  if (!ctx) return SID_EINVAL;
+  if (ctx->device < 0) return SID_OK;
+  SID_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+  SID_CHECK(hipStreamSynchronize(ctx->stream), "synchronize");
+  bool failed = false;
+  std::vector<sid_ctx*> all{ctx};
+  for (sid_ctx* c : ctx->children) all.push_back(c);
+  for (sid_ctx* c : all) {
+    if (c != ctx) SID_CHECK(hipStreamSynchronize(c->stream), "synchronize");
+    unsigned int f = 0;
+    SID_CHECK(hipMemcpy(&f, c->fail_flag, sizeof(f), hipMemcpyDeviceToHost), "read failure flag");
+    if (f) {
+      failed = true;
+      SID_CHECK(hipMemset(c->fail_flag, 0, sizeof(f)), "clear failure flag");
+    }
+  }
+  if (failed)
+    return fail(ctx, SID_EDEVICE,
+                "a device-wide wait of the pivoted QR timed out (its workgroups were not resident "
+                "together); the affected results have k_eff = -1 and are invalid");
+  return SID_OK;
+}
 
 sid_status sid_set_workspace_limit(sid_ctx* ctx, size_t bytes) {
   if (!ctx) return SID_EINVAL;
@@ -484,25 +600,25 @@ sid_status sid_reserve(sid_ctx* ctx, int64_t N, int64_t n, const sid_params* p) 
   SID_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
   Work w;
   if (reserve(ctx, sh, &w) != SID_OK) return SID_ENOMEM;
-  // everything else a compress call of this shape would allocate or create:
-  // the streaming pass's partials and Omega^T, the slab sum of Y, the
-  // refinement buffers and the single-pass side stream
-  const bool bf = sh.prec == SID_SK_BF16 || sh.prec == SID_SK_BF16X2 || sh.prec == SID_SK_FP8E4M3;
-  if ((bf || sh.prec == SID_SK_F32) && p->select == SID_SEL_GAUSS) {
-    int64_t rpw = 0;
-    const int64_t grid = sid::fused_bf16_grid(sh.N, ctx->num_cu, &rpw);  // N >= Ns: the larger
-    const int64_t slab = sh.n < 512 ? sh.n : 512;
-    if (!ws(ctx, WS_PARTF, sizeof(float) * (size_t)(grid * sh.lq * slab)) ||
-        !ws(ctx, bf ? WS_OMT : WS_OMP, bf ? sizeof(uint16_t) * 128 * 512 : sizeof(float) * 128 * 512))
-      return SID_ENOMEM;
-    if (sh.single && sh.n > slab && !ws(ctx, WS_YTMP, sizeof(float) * (size_t)(sh.N * sh.l)))
-      return SID_ENOMEM;
-  }
+  // everything else a compress call of this shape would allocate or create
+  // (for FP32 data with a 16-byte aligned base and lda % 4 == 0): the
+  // sketch kernels' buffers for the sketch precision and, with refine, for
+  // the refinement precision; the refinement buffers; the single-pass side
+  // stream
+  const bool has_rows = p->coarse != nullptr;
+  if (p->select == SID_SEL_GAUSS && reserve_sketch(ctx, sh, sh.prec, has_rows, sh.single) != SID_OK)
+    return SID_ENOMEM;
   if (p->refine) {
     const size_t d = sizeof(double);
     if (!ws(ctx, WS_REF_W, d * (size_t)(sh.l * sh.n)) || !ws(ctx, WS_REF_WJ, d * (size_t)(sh.l * sh.k)) ||
         !ws(ctx, WS_REF_T, d * (size_t)(sh.l * sh.n)) || !ws(ctx, WS_REF_G, d * (size_t)(sh.k * sh.n)))
       return SID_ENOMEM;
+    Shape shr = sh;
+    shr.prec = p->refine_prec;
+    shr.single = false;
+    shr.q = 0;
+    shr.lz = shr.lq = sh.l;
+    if (reserve_sketch(ctx, shr, p->refine_prec, has_rows, false) != SID_OK) return SID_ENOMEM;
   }
   if (sh.single && !ctx->side) {
     SID_CHECK(hipStreamCreate(&ctx->side), "side stream");
@@ -517,7 +633,7 @@ static sid_status factor(sid_ctx* ctx, const sid_params* p, const Shape& sh, con
                          int64_t ldp, void* AJ, int64_t ldaj, double* err, int64_t* k_eff);
 static sid_status refine_pass(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t lda,
                               const sid_params* p, const Shape& sh, const Work& w, void* P,
-                              int64_t ldp);
+                              int64_t ldp, double* err);
 
 // The sketch pass over the columns col0 .. col0 + sh.n - 1 of the matrix
 // (A points at column col0): W (lq x sh.n) and, if Y is given, Y = A Omega
@@ -531,19 +647,45 @@ static sid_status run_sketch(sid_ctx* ctx, const void* A, sid_dtype dtype, int64
               "omega generation");
   }
   const int64_t* rows = p->coarse ? p->coarse->d_rows : nullptr;
-  const bool bf = sh.prec == SID_SK_BF16 || sh.prec == SID_SK_BF16X2 ||
-                  sh.prec == SID_SK_FP8E4M3;
   // the streaming pass takes up to 512 columns per launch; wider matrices
   // go through it in column slabs (W's columns are independent, Y sums the
   // slabs' contributions)
   const int64_t slab = sh.n < 512 ? sh.n : 512;
-  // a coarse row list runs on the streaming pass for the bf16 forms of the
-  // two-pass (W only) sketch
-  const bool rows_ok = !rows || (!Y && (sh.prec == SID_SK_BF16 || sh.prec == SID_SK_BF16X2));
-  const bool fused_ok =
-      dtype == SID_F32 && rows_ok &&
-      sid::fused_bf16_supported(slab, (int)sh.lq, (int)sh.l, lda, A, rows != nullptr);
-  if (sh.prec == SID_SK_FP8E4M3 && !fused_ok) {
+  const SketchPath path =
+      plan_sketch(ctx, dtype, lda, A, sh.prec, sh, rows != nullptr, Y != nullptr);
+  if (path == SketchPath::PAIR_BF16) {
+    // the workgroup-pair pass, in column slabs (W's columns are independent,
+    // Y sums the slabs' contributions)
+    const int vslab = sid::sketch_v2_slab((int)sh.lq, (int)sh.l, Y != nullptr);
+    const int64_t vs = sh.n < vslab ? sh.n : vslab;
+    int64_t rpp = 0;
+    const int64_t pairs = sid::sketch_v2_pairs(sh.N, ctx->num_cu, &rpp);
+    float* partf = (float*)ws(ctx, WS_PARTF, sizeof(float) * (size_t)(pairs * sh.lq * vs));
+    __bf16* omT = (__bf16*)ws(ctx, WS_OMT, sizeof(uint16_t) * sid::sketch_v2_omt_elems((int)sh.l, (int)vs));
+    if (!partf || !omT) return SID_ENOMEM;
+    float* ytmp = nullptr;
+    if (Y && sh.n > vs) {
+      ytmp = (float*)ws(ctx, WS_YTMP, sizeof(float) * (size_t)(sh.N * sh.l));
+      if (!ytmp) return SID_ENOMEM;
+    }
+    const int dmode = sh.prec == SID_SK_BF16X2   ? sid::FB_BF16X2
+                      : sh.prec == SID_SK_FP8E4M3 ? sid::FB_FP8
+                                                  : sid::FB_BF16;
+    for (int64_t c0 = 0; c0 < sh.n; c0 += vs) {
+      const int64_t nb = sh.n - c0 < vs ? sh.n - c0 : vs;
+      float* yd = Y ? (c0 == 0 ? (float*)Y : ytmp) : nullptr;
+      int64_t nparts = 0;
+      SID_CHECK(sid::launch_sketch_v2(st, dmode, (const float*)A + c0 * lda, lda, sh.N, (int)nb,
+                                      (int)sh.lq, (int)sh.l, p->seed, w.omega + c0 * sh.l, omT,
+                                      ctx->num_cu, partf, W + c0 * sh.lq, yd, &nparts),
+                "sketch pass (workgroup pairs)");
+      if (Y && c0 > 0)
+        SID_CHECK(sid::launch_add_inplace(st, false, Y, ytmp, sh.N * sh.l, ctx->num_cu),
+                  "Y slab sum");
+    }
+    return SID_OK;
+  }
+  if (path == SketchPath::FP8_GENERAL) {
     // general kernels: the e4m3 data values are formed first (one more pass
     // over A and an N x n FP32 copy in the workspace)
     float* a8 = (float*)ws(ctx, WS_A8, sizeof(float) * (size_t)(sh.N * sh.n));
@@ -555,8 +697,8 @@ static sid_status run_sketch(sid_ctx* ctx, const void* A, sid_dtype dtype, int64
               "sketch pass");
     return SID_OK;
   }
-  const bool f32mfma = sh.prec == SID_SK_F32;
-  if ((bf || f32mfma) && fused_ok) {
+  const bool f32mfma = path == SketchPath::FUSED_F32;
+  if (path == SketchPath::FUSED_BF16 || path == SketchPath::FUSED_F32) {
     // one streaming pass on the matrix cores (W partials per workgroup, FP32)
     int64_t rpw = 0;
     const int64_t grid = sid::fused_bf16_grid(sh.Ns, ctx->num_cu, &rpw);
@@ -596,7 +738,7 @@ static sid_status run_sketch(sid_ctx* ctx, const void* A, sid_dtype dtype, int64
     }
     return SID_OK;
   }
-  if (sh.prec == SID_SK_F64 && !rows) {
+  if (path == SketchPath::F64_TILED) {
     // all rows: the register-tiled FP64 passes (the same bits as the general
     // kernels)
     SID_CHECK(sid::launch_sketch_w_f64(st, A, dtype == SID_F64, lda, sh.N, sh.n, (int)sh.lq,
@@ -662,7 +804,7 @@ sid_status sid_compress(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N,
   }
   s = factor(ctx, p, sh, w, dtype, A, lda, J, P, ldp, AJ, ldaj, err, k_eff);
   if (s != SID_OK || !p->refine) return s;
-  return refine_pass(ctx, A, dtype, lda, p, sh, w, P, ldp);
+  return refine_pass(ctx, A, dtype, lda, p, sh, w, P, ldp, err);
 }
 
 // One refinement step of P (corrected seminormal equations on a second
@@ -670,7 +812,7 @@ sid_status sid_compress(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N,
 // R11): P1 = P0 + R11^-1 R11^-T W'(:, J)^T (W' - W'(:, J) P0).
 static sid_status refine_pass(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t lda,
                               const sid_params* p, const Shape& sh, const Work& w, void* P,
-                              int64_t ldp) {
+                              int64_t ldp, double* err) {
   hipStream_t st = ctx->stream;
   const int k = (int)sh.k, l = (int)sh.l, n_ = (int)sh.n;
   sid_params pr = *p;
@@ -700,6 +842,18 @@ static sid_status refine_pass(sid_ctx* ctx, const void* A, sid_dtype dtype, int6
   SID_CHECK(sid::launch_csne_solve(st, w.R11, k, w.keff, G, k, n_), "R11^-1 R11^-T");
   SID_CHECK(sid::launch_refine_store(st, w.Pd, G, k, n_, P, ldp, dtype == SID_F64),
             "P0 + dP");
+  // the estimates describe the P handed back: the probe rows and the
+  // selection rows of the first sketch are fitted again with P0 + dP (w.Pd)
+  SID_CHECK(sid::launch_fit_residual(st, w.W, sh.lq, sh.lz, (int)sh.q, n_, w.piv, w.keff, w.Pd,
+                                     k, (sh.single && sh.q > 0) ? w.mix : nullptr, w.fitpart,
+                                     w.err),
+            "probe residual (refined P)");
+  SID_CHECK(sid::launch_fit_residual(st, w.W, sh.lq, 0, l, n_, w.piv, w.keff, w.Pd, k, nullptr,
+                                     w.fitpart, w.err + 1),
+            "sketch residual (refined P)");
+  if (err)
+    SID_CHECK(hipMemcpyAsync(err, w.err, 2 * sizeof(double), hipMemcpyDeviceToDevice, st),
+              "copy err");
   return SID_OK;
 }
 
@@ -720,6 +874,15 @@ static sid_status factor(sid_ctx* ctx, const sid_params* p, const Shape& sh, con
     return sid::cpqr_wg_supported(m, nc) ? 0 : (sid::cpqr_coop_supported(m, nc) ? 1 : 2);
   };
   const int w_kind = kind(l, n_);
+  // a cooperative launch cannot be recorded into a graph: under capture the
+  // multi-workgroup QR is a plain launch (its bounded waits report through
+  // the sticky flag)
+  bool coop_launch = ctx->cooperative;
+  {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+      coop_launch = false;
+  }
   const int m_kind = sh.single ? kind(lz, l) : 0;
   const bool overlap = sh.single && (m_kind == 0 || m_kind != w_kind);
   const double rcond = p->sp_rcond > 0.0 ? p->sp_rcond : default_rcond(sh.prec);
@@ -749,7 +912,7 @@ static sid_status factor(sid_ctx* ctx, const sid_params* p, const Shape& sh, con
                 "pivoted QR of M");
     else if (m_kind == 1)
       SID_CHECK(sid::launch_cpqr_coop(ms, w.M, lz, lz, l, l, rcond, w.coop, w.sync2, w.pivM, w.RM,
-                                      w.QM, w.rkM, w.statsM, ctx->cooperative),
+                                      w.QM, w.rkM, w.statsM, coop_launch, ctx->fail_flag),
                 "pivoted QR of M");
     else
       SID_CHECK(sid::launch_cpqr(ms, w.M, lz, lz, l, l, rcond, w.Wr, w.nrm, w.pivM, w.RM, w.QM,
@@ -764,7 +927,7 @@ static sid_status factor(sid_ctx* ctx, const sid_params* p, const Shape& sh, con
               "pivoted QR");
   else if (w_kind == 1)
     SID_CHECK(sid::launch_cpqr_coop(st, w.W, lq, l, n_, k, p->rank_tol, w.coop, w.sync2, w.piv,
-                                    w.R, w.Q, w.keff, w.stats, ctx->cooperative),
+                                    w.R, w.Q, w.keff, w.stats, coop_launch, ctx->fail_flag),
               "pivoted QR");
   else
     SID_CHECK(sid::launch_cpqr(st, w.W, lq, l, n_, k, p->rank_tol, w.Wr, w.nrm, w.piv, w.R, w.Q,
@@ -973,8 +1136,10 @@ sid_status stream_flush(sid_stream* s, const void* src, int64_t ld, int64_t ncol
   Shape sh;
   sid_status st = validate(ctx, s->N, s->n_max, &s->p, &sh);
   if (st != SID_OK) return st;
+  // row chunks of the general kernels as for the resident call over n_max
+  // columns (validate set sh.nchunks from n_max), so a stream's W is that
+  // call's W bit for bit
   sh.n = ncols;
-  sh.nchunks = nchunks_for(sh.Ns, ncols);
   Work w;
   if (reserve(ctx, sh, &w) != SID_OK) return SID_ENOMEM;
   void* ydst = nullptr;

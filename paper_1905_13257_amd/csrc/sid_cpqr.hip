@@ -410,9 +410,13 @@ hipError_t launch_cpqr_wg(hipStream_t st, const double* X, int64_t ldx, int m, i
   return hipGetLastError();
 }
 
-// keff := -1 when a cooperative wait timed out (results invalid)
-__global__ void k_mark_failure(const unsigned int* fail, int64_t* keff) {
-  if (threadIdx.x == 0 && blockIdx.x == 0 && *fail) *keff = -1;
+// keff := -1 when a cooperative wait timed out (results invalid); the
+// context's sticky flag records it until the host reads it (sid_sync)
+__global__ void k_mark_failure(const unsigned int* fail, int64_t* keff, unsigned int* sticky) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && *fail) {
+    *keff = -1;
+    if (sticky) *sticky = 1u;
+  }
 }
 
 bool cpqr_coop_supported(int m, int nc) { return m <= 256 && nc <= 64 * CQ_MINCPW && nc >= 1; }
@@ -431,7 +435,7 @@ size_t cpqr_coop_scratch_bytes(int m, int nc) {
 hipError_t launch_cpqr_coop(hipStream_t st, const double* X, int64_t ldx, int m, int nc, int kmax,
                             double rank_tol, void* scratch, unsigned int* sync2, int64_t* piv,
                             double* R, double* Q, int64_t* keff, double* stats,
-                            bool cooperative) {
+                            bool cooperative, unsigned int* sticky) {
   const int tpc = coop_tpc(m, nc);
   const int cpw = CQ_THREADS / tpc;
   const int G = (nc + cpw - 1) / cpw;
@@ -461,14 +465,17 @@ hipError_t launch_cpqr_coop(hipStream_t st, const double* X, int64_t ldx, int m,
                   : rpt <= 48 ? (const void*)k_cpqr_coop<4, 48>
                               : (const void*)k_cpqr_coop<4, 64>);
   // The G workgroups must be resident together.  A cooperative launch
-  // guarantees it; a plain launch of at most 64 workgroups of 256 threads
-  // gets it on an otherwise idle device, and the bounded wait turns a
-  // failure into keff = -1 instead of a hang.
+  // guarantees it (the default outside graph capture); a plain launch (used
+  // under capture, where cooperative launches cannot be recorded) of at most
+  // 256 workgroups of 256 threads fits the device at once, and if other work
+  // keeps some of them waiting for longer than the bounded spin, the wait
+  // gives up: keff = -1 and the context's sticky flag, which sid_sync
+  // reports, instead of a hang.
   const hipError_t e = cooperative
                            ? hipLaunchCooperativeKernel(kern, grid, block, args, 0, st)
                            : hipLaunchKernel(kern, grid, block, args, 0, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_mark_failure, dim3(1), dim3(64), 0, st, fail, keff);
+  hipLaunchKernelGGL(k_mark_failure, dim3(1), dim3(64), 0, st, fail, keff, sticky);
   return hipGetLastError();
 }
 

@@ -63,6 +63,15 @@ namespace sid {
 // how the fused pass feeds the data to the bf16 matrix products
 enum FusedData : int { FB_BF16 = 0, FB_BF16X2 = 1, FB_FP8 = 2 };
 bool fused_bf16_supported(int64_t n, int lq, int l, int64_t lda, const void* A, bool has_rows);
+// the 32x32x16 pass over workgroup pairs (sid_sketch_v2.*): widest column
+// slab for a shape (0: does not apply), applicability, Omega^T size, pairs
+int sketch_v2_slab(int lq, int l, bool wanty);
+bool sketch_v2_supported(int64_t n, int lq, int l, bool wanty, int64_t lda, const void* A);
+size_t sketch_v2_omt_elems(int l, int n);
+int64_t sketch_v2_pairs(int64_t N, int num_cu, int64_t* rows_per_pair);
+hipError_t launch_sketch_v2(hipStream_t st, int dmode, const float* A, int64_t lda, int64_t N,
+                            int n, int lq, int l, uint64_t seed, const float* omega, __bf16* omT,
+                            int num_cu, float* part, double* W, float* Y, int64_t* nparts_out);
 int64_t fused_bf16_grid(int64_t N, int num_cu, int64_t* rows_per_wg);
 hipError_t launch_sketch_fused_bf16(hipStream_t st, int dmode, const float* A, int64_t lda,
                                     int64_t N, int n, int lq, int l, uint64_t seed,
@@ -78,7 +87,7 @@ size_t cpqr_coop_scratch_bytes(int m, int nc);
 hipError_t launch_cpqr_coop(hipStream_t st, const double* X, int64_t ldx, int m, int nc, int kmax,
                             double rank_tol, void* scratch, unsigned int* sync2, int64_t* piv,
                             double* R, double* Q, int64_t* keff, double* stats,
-                            bool cooperative);
+                            bool cooperative, unsigned int* sticky);
 hipError_t launch_id_coefficients(hipStream_t st, const double* R, int nc, const int64_t* piv,
                                   const int64_t* keff, int kcap, double* R11, double* Pd,
                                   void* P, int64_t ldp, bool p_is_f64);

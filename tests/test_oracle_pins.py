@@ -551,3 +551,55 @@ def test_adaptive_rank_prefix_errors_two_formulations(oracle_mod):
     tol = 0.5 * (e[8] + e[9]) if e[9] < e[8] else e[9]
     cp2 = oracle_mod.adaptive_rank(cp, Wpr, 60, tol)
     assert e[cp2.k_eff] <= tol and all(e[i] > tol for i in range(1, cp2.k_eff))
+
+
+def test_err_sketch_hand_case_and_mgs_residual(oracle_mod):
+    """err_sketch (the sketch-fit estimate, Remark 2.2) pinned two ways.
+
+    Hand case: W = [[3, 0, 1], [4, 0, 0]], k = 1.  mgsqr picks column 0
+    (norm 5), q = (0.6, 0.8); column 2 gets the coefficient (q . w_2) / 5 =
+    0.12 and keeps the residual (0.64, -0.48) of norm 0.8, so ||W - W(:, J) P||_F / ||W||_F = 0.8 / sqrt(26).
+    Generic case: the same ratio equals ||R22||_F / ||W||_F, the norm of
+    mgsqr's own final residual (the columns it did not pick, after k
+    projections), computed without P."""
+    W = np.array([[3.0, 0.0, 1.0], [4.0, 0.0, 0.0]])
+    cp = oracle_mod.cpqr(W, 1)
+    assert cp.J.tolist() == [0]
+    np.testing.assert_allclose(cp.final_residual[:, 2], [0.64, -0.48], rtol=0, atol=1e-15)
+    P = oracle_mod.id_coefficients(cp.R, cp.J, 3)
+    np.testing.assert_allclose(P, [[1.0, 0.0, 0.12]], rtol=0, atol=1e-15)  # (q . w_2) / 5
+    # compress() reports the ratio on the selection rows of its own sketch;
+    # feed the hand matrix through the same fit
+    fit = np.linalg.norm(W - W[:, cp.J] @ P) / np.linalg.norm(W)
+    assert abs(fit - 0.8 / math.sqrt(26.0)) <= 1e-15
+    rng = np.random.default_rng(41)
+    A = rng.standard_normal((400, 9)) @ rng.standard_normal((9, 60)) + 1e-3 * rng.standard_normal((400, 60))
+    for mode in ("two_pass", "single_pass"):
+        k, p = 7, 5
+        res = oracle_mod.compress(A, k, p, seed=4, mode=mode, prec="f64", probe_rows=6)
+        Wsel = res.W[:k + p]
+        r22 = np.linalg.norm(res.cp.final_residual) / np.linalg.norm(Wsel)
+        assert abs(res.err_sketch - r22) <= 1e-12 * r22, (mode, res.err_sketch, r22)
+
+
+def test_error_norms_relative_max_hand_case(oracle_mod):
+    """Relative entry-wise error (Sec. 3.1): max |A_ij - Ahat_ij| / |A_ij| over
+    the nonzero entries of A, with the absolute maximum beside it.  Hand case
+    with Ahat = AJ P = [[1.1, 0.5], [2, 3]] against A = [[1, 0], [2, 4]]:
+    relative errors 0.1 and 0.25 (the zero entry, absolute error 0.5, is
+    excluded), absolute maximum 1; ||A - Ahat||_F^2 = 0.01 + 0.25 + 1."""
+    A = np.array([[1.0, 0.0], [2.0, 4.0]])
+    AJ = np.array([[1.1, 0.5], [2.0, 3.0]])
+    P = np.eye(2)
+    e = oracle_mod.error_norms(A, AJ, P)
+    assert abs(e["rel_max"] - 0.25) <= 1e-15
+    assert abs(e["max_abs"] - 1.0) <= 1e-15
+    assert abs(e["fro_err"] - math.sqrt(1.26)) <= 1e-15
+    assert abs(e["fro_a"] - math.sqrt(21.0)) <= 1e-15
+    # all-zero column and a rank-1 product: the zero entries never enter
+    A = np.array([[0.0, 2.0], [0.0, -4.0]])
+    AJ = np.array([[1.0], [1.0]])
+    P = np.array([[1.0, 2.5]])
+    e = oracle_mod.error_norms(A, AJ, P)
+    assert abs(e["rel_max"] - 1.625) <= 1e-15      # |-4 - 2.5| / 4
+    assert abs(e["max_abs"] - 6.5) <= 1e-15
