@@ -498,41 +498,29 @@ def compress(A, k: int, oversample: int, seed: int = 0, coarse_rows=None,
 
 
 def refine(A, res: Result, seed: int, refine_prec: str, l: int, coarse_rows=None) -> np.ndarray:
-    """One refinement step of the coefficients P on a second, more precise
-    sketch of A.  The paper stops at the ID; this is this implementation's
-    reading of a refinement pass: one step of iterative refinement of the
-    least-squares problem min ||W'(:, J) P - W'|| that defines P on the
-    sketch W' = Psi_sel(:, S) A(S, :) taken in ``refine_prec``, reusing the
-    triangular factor R11 of the first (low-precision) mgsqr:
+    """Refinement of the coefficients P on a second, more precise sketch of
+    A.  The paper stops at the ID; this is this implementation's reading of
+    a refinement pass: the pivots J of the first sketch are kept and P is
+    recomputed as the least-squares solution that defines it (the ID
+    coefficients of Sec. 2.4 are R11^-1 R12, the least-squares fit of the
+    sketch's columns by its pivot columns), now on the sketch
+    W' = Psi_sel(:, S) A(S, :) taken in ``refine_prec``:
 
-      E   = A - A(:, J) P0             (residual of the ID, exact columns)
-      W_r = Psi_sel(:, S) E(S, :)      (formed as W' - W'(:, J) P0)
-      dP  = R11^-1 R11^-T W'(:, J)^T W_r   (corrected seminormal equations)
-      P1  = P0 + dP                    (dP vanishes on J, since W_r does)
+      P1 = argmin_X ||W'(:, J) X - W'||_F = W'(:, J)^+ W',  P1(:, J) = I.
 
-    Its fixed point is the least-squares solution on W'; with W' equal to
-    the first sketch the step changes nothing.  Returns P1 (k x n, rows past
-    k_eff zero)."""
+    (A one-step correction that reuses the first sketch's R11 is cheaper but
+    diverges when the first sketch's rounding, e.g. FP8, swamps the small
+    singular values of R11.)  Returns P1 (k x n, rows past k_eff zero)."""
     A = np.asarray(A)
     N, n = A.shape
     rows = np.arange(N, dtype=np.int64) if coarse_rows is None else np.asarray(coarse_rows, np.int64)
     ke = res.k_eff
-    P0 = res.P[:ke]
     J = res.cp.J
     Wp = sketch_w(A, rows, l, seed, refine_prec)
-    WpJ = Wp[:, J]
-    Wr = Wp - WpJ @ P0
-    G = WpJ.T @ Wr                               # k_eff x n
-    R11 = res.cp.R[:, J]
-    H = np.zeros_like(G)
-    for b in range(ke):                          # forward substitution with R11^T
-        H[b] = (G[b] - R11[:b, b] @ H[:b]) / R11[b, b]
-    dP = np.zeros_like(G)
-    for b in range(ke - 1, -1, -1):              # back substitution with R11
-        dP[b] = (H[b] - R11[b, b + 1:] @ dP[b + 1:]) / R11[b, b]
-    dP[:, J] = 0.0
+    X = np.linalg.lstsq(Wp[:, J], Wp, rcond=None)[0]
+    X[:, J] = np.eye(ke)
     P1 = np.zeros_like(res.P)
-    P1[:ke] = P0 + dP
+    P1[:ke] = X
     return P1
 
 

@@ -26,7 +26,7 @@ namespace {
 enum Slot {
   WS_OMEGA, WS_PART, WS_W, WS_WR, WS_NRM, WS_PIV, WS_R, WS_Q, WS_KEFF, WS_STATS, WS_PD,
   WS_ERR, WS_Y, WS_M, WS_MPR, WS_WJ, WS_PIVM, WS_RM, WS_QM, WS_RKM, WS_C, WS_T, WS_MIX,
-  WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COOP, WS_SYNC, WS_R11, WS_FITPART, WS_YTMP, WS_REF_W, WS_REF_WJ, WS_REF_T, WS_REF_G, WS_OMP, WS_A8, WS_IACJT, WS_IPB, WS_IB, WS_IPART, WS_AZ, WS_AE2, WS_APART, WS_SV_H, WS_SV_B, WS_SV_Q, WS_SV_OM32,
+  WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COOP, WS_SYNC, WS_R11, WS_FITPART, WS_YTMP, WS_REF_W, WS_REF_WJ, WS_OMP, WS_A8, WS_IACJT, WS_IPB, WS_IB, WS_IPART, WS_AZ, WS_AE2, WS_APART, WS_SV_H, WS_SV_B, WS_SV_Q, WS_SV_OM32,
   WS_SV_OM, WS_SV_SMALL, WS_SV_WP, WS_SV_OMN, WS_COUNT
 };
 
@@ -610,8 +610,8 @@ sid_status sid_reserve(sid_ctx* ctx, int64_t N, int64_t n, const sid_params* p) 
     return SID_ENOMEM;
   if (p->refine) {
     const size_t d = sizeof(double);
-    if (!ws(ctx, WS_REF_W, d * (size_t)(sh.l * sh.n)) || !ws(ctx, WS_REF_WJ, d * (size_t)(sh.l * sh.k)) ||
-        !ws(ctx, WS_REF_T, d * (size_t)(sh.l * sh.n)) || !ws(ctx, WS_REF_G, d * (size_t)(sh.k * sh.n)))
+    if (!ws(ctx, WS_REF_W, d * (size_t)(sh.l * sh.n)) ||
+        !ws(ctx, WS_REF_WJ, sizeof(int64_t) * (size_t)(sh.k + 1)))
       return SID_ENOMEM;
     Shape shr = sh;
     shr.prec = p->refine_prec;
@@ -632,8 +632,8 @@ static sid_status factor(sid_ctx* ctx, const sid_params* p, const Shape& sh, con
                          sid_dtype dtype, const void* A, int64_t lda, int64_t* J, void* P,
                          int64_t ldp, void* AJ, int64_t ldaj, double* err, int64_t* k_eff);
 static sid_status refine_pass(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t lda,
-                              const sid_params* p, const Shape& sh, const Work& w, void* P,
-                              int64_t ldp, double* err);
+                              const sid_params* p, const Shape& sh, const Work& w, int64_t* J,
+                              void* P, int64_t ldp, double* err, int64_t* k_eff);
 
 // The sketch pass over the columns col0 .. col0 + sh.n - 1 of the matrix
 // (A points at column col0): W (lq x sh.n) and, if Y is given, Y = A Omega
@@ -804,15 +804,20 @@ sid_status sid_compress(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N,
   }
   s = factor(ctx, p, sh, w, dtype, A, lda, J, P, ldp, AJ, ldaj, err, k_eff);
   if (s != SID_OK || !p->refine) return s;
-  return refine_pass(ctx, A, dtype, lda, p, sh, w, P, ldp, err);
+  return refine_pass(ctx, A, dtype, lda, p, sh, w, J, P, ldp, err, k_eff);
 }
 
-// One refinement step of P (corrected seminormal equations on a second
-// sketch W' = Psi(0:l, S) A(S, :) in refine_prec, with the first mgsqr's
-// R11): P1 = P0 + R11^-1 R11^-T W'(:, J)^T (W' - W'(:, J) P0).
+// Refinement of P on a second sketch W' = Psi(0:l, S) A(S, :) taken in
+// refine_prec: with the pivots J of the first sketch fixed, P1 is the
+// least-squares solution of min ||W'(:, J) X - W'||, formed by mgsqr of W'
+// with the pivot order forced to J (the projections of every other column
+// onto the pivots' Q are those of modified Gram-Schmidt on the augmented
+// matrix) and the usual back substitution P1 = R11'^-1 R12'.  The estimates
+// are then re-fitted with P1.  The first factorization's R, Q and R11 are no
+// longer needed here and are reused.
 static sid_status refine_pass(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t lda,
-                              const sid_params* p, const Shape& sh, const Work& w, void* P,
-                              int64_t ldp, double* err) {
+                              const sid_params* p, const Shape& sh, const Work& w, int64_t* J,
+                              void* P, int64_t ldp, double* err, int64_t* k_eff) {
   hipStream_t st = ctx->stream;
   const int k = (int)sh.k, l = (int)sh.l, n_ = (int)sh.n;
   sid_params pr = *p;
@@ -828,22 +833,35 @@ static sid_status refine_pass(sid_ctx* ctx, const void* A, sid_dtype dtype, int6
   shr.lq = sh.l;
   const size_t d = sizeof(double);
   double* Wp = (double*)ws(ctx, WS_REF_W, d * (size_t)(l * n_));
-  double* WpJ = (double*)ws(ctx, WS_REF_WJ, d * (size_t)(l * k));
-  double* T1 = (double*)ws(ctx, WS_REF_T, d * (size_t)(l * n_));
-  double* G = (double*)ws(ctx, WS_REF_G, d * (size_t)(k * n_));
-  if (!Wp || !WpJ || !T1 || !G) return SID_ENOMEM;
+  int64_t* Jf = (int64_t*)ws(ctx, WS_REF_WJ, sizeof(int64_t) * (size_t)(k + 1));
+  if (!Wp || !Jf) return SID_ENOMEM;
   sid_status s = run_sketch(ctx, A, dtype, lda, &pr, shr, w, Wp, nullptr);
   if (s != SID_OK) return s;
-  SID_CHECK(sid::launch_gather_block(st, Wp, l, 0, l, w.piv, w.keff, k, WpJ), "W'(:, J)");
-  SID_CHECK(sid::launch_gemm64(st, l, n_, k, WpJ, l, 0, w.Pd, k, 0, T1, l), "W'(:, J) P0");
-  SID_CHECK(sid::launch_sub_from(st, Wp, T1, (int64_t)l * n_, ctx->num_cu), "W' - W'(:, J) P0");
-  SID_CHECK(sid::launch_gemm64(st, k, n_, l, WpJ, l, 1, T1, l, 0, G, k), "W'(:, J)^T W_r");
-  SID_CHECK(sid::launch_gather_r11(st, w.R, n_, w.piv, w.keff, k, w.R11), "R11");
-  SID_CHECK(sid::launch_csne_solve(st, w.R11, k, w.keff, G, k, n_), "R11^-1 R11^-T");
-  SID_CHECK(sid::launch_refine_store(st, w.Pd, G, k, n_, P, ldp, dtype == SID_F64),
-            "P0 + dP");
+  // the forced order: J as the first mgsqr left it (-1 past its k_eff)
+  SID_CHECK(hipMemcpyAsync(Jf, w.piv, sizeof(int64_t) * (size_t)k, hipMemcpyDeviceToDevice, st),
+            "J");
+  bool coop_launch = ctx->cooperative;
+  {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+      coop_launch = false;
+  }
+  if (sid::cpqr_wg_supported(l, n_))
+    SID_CHECK(sid::launch_cpqr_wg(st, Wp, l, l, n_, k, 0.0, w.piv, w.R, w.Q, w.keff, w.stats, Jf),
+              "mgsqr of W' in the order J");
+  else if (sid::cpqr_coop_supported(l, n_))
+    SID_CHECK(sid::launch_cpqr_coop(st, Wp, l, l, n_, k, 0.0, w.coop, w.sync2, w.piv, w.R, w.Q,
+                                    w.keff, w.stats, coop_launch, ctx->fail_flag, Jf),
+              "mgsqr of W' in the order J");
+  else
+    SID_CHECK(sid::launch_cpqr(st, Wp, l, l, n_, k, 0.0, w.Wr, w.nrm, w.piv, w.R, w.Q, w.keff,
+                               w.stats, Jf),
+              "mgsqr of W' in the order J");
+  SID_CHECK(sid::launch_id_coefficients(st, w.R, n_, w.piv, w.keff, k, w.R11, w.Pd, P, ldp,
+                                        dtype == SID_F64),
+            "refined coefficients");
   // the estimates describe the P handed back: the probe rows and the
-  // selection rows of the first sketch are fitted again with P0 + dP (w.Pd)
+  // selection rows of the first sketch are fitted again with P1 (w.Pd)
   SID_CHECK(sid::launch_fit_residual(st, w.W, sh.lq, sh.lz, (int)sh.q, n_, w.piv, w.keff, w.Pd,
                                      k, (sh.single && sh.q > 0) ? w.mix : nullptr, w.fitpart,
                                      w.err),
@@ -851,6 +869,13 @@ static sid_status refine_pass(sid_ctx* ctx, const void* A, sid_dtype dtype, int6
   SID_CHECK(sid::launch_fit_residual(st, w.W, sh.lq, 0, l, n_, w.piv, w.keff, w.Pd, k, nullptr,
                                      w.fitpart, w.err + 1),
             "sketch residual (refined P)");
+  // a pivot whose column W' reproduces from the earlier ones ends the forced
+  // factorization early: J and k_eff are copied again
+  if (J) SID_CHECK(hipMemcpyAsync(J, w.piv, sizeof(int64_t) * (size_t)k, hipMemcpyDeviceToDevice, st),
+                   "copy J");
+  if (k_eff)
+    SID_CHECK(hipMemcpyAsync(k_eff, w.keff, sizeof(int64_t), hipMemcpyDeviceToDevice, st),
+              "copy k_eff");
   if (err)
     SID_CHECK(hipMemcpyAsync(err, w.err, 2 * sizeof(double), hipMemcpyDeviceToDevice, st),
               "copy err");

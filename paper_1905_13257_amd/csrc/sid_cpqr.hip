@@ -71,7 +71,8 @@ __global__ __launch_bounds__(CQ_THREADS) void k_cpqr_coop(
     int stride_blk, double* __restrict__ pub_v, int* __restrict__ pub_j,
     double* __restrict__ pub_col, double* __restrict__ red, unsigned int* __restrict__ bar,
     unsigned int* __restrict__ fail, int64_t* __restrict__ piv, double* __restrict__ R,
-    double* __restrict__ Q, int64_t* __restrict__ keff, double* __restrict__ stats) {
+    double* __restrict__ Q, int64_t* __restrict__ keff, double* __restrict__ stats,
+    const int64_t* __restrict__ forced) {
   static_assert(TPC * RPT <= CQ_MSTRIDE, "published column slot");
   constexpr int CQ_TPC = TPC;
   constexpr int CQ_CPW = CQ_THREADS / TPC;
@@ -112,9 +113,10 @@ __global__ __launch_bounds__(CQ_THREADS) void k_cpqr_coop(
   int k = 0, nbar = 0;
   for (; k < kmax; ++k) {
     const int par = k & 1;
-    // 1. local argmax
-    double bv = alive ? nrm : -1.0;
-    int bj = alive ? j : 0x7fffffff;
+    // 1. local argmax (forced order: the given column is the only candidate)
+    const bool cand = alive && (!forced || j == forced[k]);
+    double bv = cand ? nrm : -1.0;
+    int bj = cand ? j : 0x7fffffff;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) better(bv, bj, __shfl_xor(bv, o, 64), __shfl_xor(bj, o, 64));
     if (lane == 0) { s_wv[wv] = bv; s_wj[wv] = bj; }
@@ -253,7 +255,7 @@ template <int TPC, int RPT>
 __global__ __launch_bounds__(CW_THREADS) void k_cpqr_wg(
     const double* __restrict__ X, int64_t ldx, int m, int nc, int kmax, double rank_tol,
     int64_t* __restrict__ piv, double* __restrict__ R, double* __restrict__ Q,
-    int64_t* __restrict__ keff, double* __restrict__ stats) {
+    int64_t* __restrict__ keff, double* __restrict__ stats, const int64_t* __restrict__ forced) {
   constexpr int QN = TPC * RPT;  // rows covered by a column's threads
   __shared__ double s_q[2][QN];
   __shared__ double s_wv[2][CW_WAVES];
@@ -283,9 +285,11 @@ __global__ __launch_bounds__(CW_THREADS) void k_cpqr_wg(
   int k = 0;
   for (; k < kmax; ++k) {
     const int par = k & 1;
-    // 1. this wave's best live column (ties: smallest index)
-    double bv = alive ? nrm : -1.0;
-    int bj = alive ? j : 0x7fffffff;
+    // 1. this wave's best live column (ties: smallest index; forced order:
+    //    the given column is the only candidate)
+    const bool cand = alive && (!forced || j == forced[k]);
+    double bv = cand ? nrm : -1.0;
+    int bj = cand ? j : 0x7fffffff;
 #pragma unroll
     for (int o = 32; o >= TPC; o >>= 1) better(bv, bj, __shfl_xor(bv, o, 64), __shfl_xor(bj, o, 64));
     if (lane == 0) { s_wv[par][wv] = bv; s_wj[par][wv] = bj; }
@@ -387,13 +391,13 @@ bool cpqr_wg_supported(int m, int nc) {
 
 hipError_t launch_cpqr_wg(hipStream_t st, const double* X, int64_t ldx, int m, int nc, int kmax,
                           double rank_tol, int64_t* piv, double* R, double* Q, int64_t* keff,
-                          double* stats) {
+                          double* stats, const int64_t* forced) {
   if (!cpqr_wg_supported(m, nc)) return hipErrorInvalidValue;
   const int tpc = cw_tpc(nc);
   const int rpt = (m + tpc - 1) / tpc;
 #define SID_CW(TPC_, RPT_)                                                                    \
   hipLaunchKernelGGL((k_cpqr_wg<TPC_, RPT_>), dim3(1), dim3(CW_THREADS), 0, st, X, ldx, m, nc, \
-                     kmax, rank_tol, piv, R, Q, keff, stats)
+                     kmax, rank_tol, piv, R, Q, keff, stats, forced)
 #define SID_CW_R(TPC_)                    \
   if (rpt <= 8) SID_CW(TPC_, 8);          \
   else if (rpt <= 16) SID_CW(TPC_, 16);   \
@@ -435,7 +439,7 @@ size_t cpqr_coop_scratch_bytes(int m, int nc) {
 hipError_t launch_cpqr_coop(hipStream_t st, const double* X, int64_t ldx, int m, int nc, int kmax,
                             double rank_tol, void* scratch, unsigned int* sync2, int64_t* piv,
                             double* R, double* Q, int64_t* keff, double* stats,
-                            bool cooperative, unsigned int* sticky) {
+                            bool cooperative, unsigned int* sticky, const int64_t* forced) {
   const int tpc = coop_tpc(m, nc);
   const int cpw = CQ_THREADS / tpc;
   const int G = (nc + cpw - 1) / cpw;
@@ -451,7 +455,7 @@ hipError_t launch_cpqr_coop(hipStream_t st, const double* X, int64_t ldx, int m,
   void* args[] = {(void*)&X, (void*)&ldx, (void*)&m, (void*)&nc, (void*)&kmax, (void*)&rank_tol,
                   (void*)&G, (void*)&stride, (void*)&pub_v, (void*)&pub_j, (void*)&pub_col,
                   (void*)&red, (void*)&bar, (void*)&fail, (void*)&piv, (void*)&R, (void*)&Q,
-                  (void*)&keff, (void*)&stats};
+                  (void*)&keff, (void*)&stats, (void*)&forced};
   const int rpt = (m + tpc - 1) / tpc;
   const void* kern =
       tpc == 2 ? (rpt <= 8    ? (const void*)k_cpqr_coop<2, 8>

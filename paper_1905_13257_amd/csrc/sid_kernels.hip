@@ -178,7 +178,7 @@ __global__ __launch_bounds__(CPQR_THREADS) void k_cpqr_l2(
     const double* __restrict__ X, int64_t ldx, int m, int nc, int kmax, double rank_tol,
     double* __restrict__ Wr, double* __restrict__ nrm2, int64_t* __restrict__ piv,
     double* __restrict__ R, double* __restrict__ Q, int64_t* __restrict__ keff,
-    double* __restrict__ stats) {
+    double* __restrict__ stats, const int64_t* __restrict__ forced) {
   extern __shared__ double s_dyn[];
   double* s_q = s_dyn;  // m doubles
   __shared__ double s_wv[CPQR_THREADS / 64];
@@ -217,11 +217,14 @@ __global__ __launch_bounds__(CPQR_THREADS) void k_cpqr_l2(
   double first = -1.0;
   int k = 0;
   for (; k < kmax; ++k) {
-    // argmax over live columns (dead columns carry nrm2 = -1)
+    // argmax over live columns (dead columns carry nrm2 = -1; forced order:
+    // the given column is the only candidate)
     double bv = -1.0;
     int bi = 0x7fffffff;
+    const int64_t fk = forced ? forced[k] : -1;
     for (int j = tid; j < nc; j += CPQR_THREADS) {
       const double v = nrm2[j];
+      if (forced && j != fk) continue;
       if (v > bv) { bv = v; bi = j; }  // j increasing: first max kept
     }
 #pragma unroll
@@ -713,10 +716,10 @@ hipError_t launch_sketch(hipStream_t st, int prec, bool a_is_f64, const void* A,
 
 hipError_t launch_cpqr(hipStream_t st, const double* X, int64_t ldx, int m, int nc, int kmax,
                        double rank_tol, double* Wr, double* nrm2, int64_t* piv, double* R,
-                       double* Q, int64_t* keff, double* stats) {
+                       double* Q, int64_t* keff, double* stats, const int64_t* forced) {
   const size_t shm = sizeof(double) * (size_t)m;
   hipLaunchKernelGGL(k_cpqr_l2, dim3(1), dim3(CPQR_THREADS), shm, st, X, ldx, m, nc, kmax,
-                     rank_tol, Wr, nrm2, piv, R, Q, keff, stats);
+                     rank_tol, Wr, nrm2, piv, R, Q, keff, stats, forced);
   return hipGetLastError();
 }
 
@@ -793,79 +796,6 @@ hipError_t launch_add_inplace(hipStream_t st, bool f64, void* y, const void* x, 
   else
     hipLaunchKernelGGL(k_add_inplace<float>, dim3((unsigned)b), dim3(256), 0, st, (float*)y,
                        (const float*)x, count);
-  return hipGetLastError();
-}
-
-// y = x - y (FP64)
-__global__ void k_sub_from(const double* __restrict__ x, double* __restrict__ y, int64_t count) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
-       e += (int64_t)gridDim.x * blockDim.x)
-    y[e] = x[e] - y[e];
-}
-
-hipError_t launch_sub_from(hipStream_t st, const double* x, double* y, int64_t count, int num_cu) {
-  if (count <= 0) return hipSuccess;
-  int64_t b = (count + 255) / 256;
-  const int64_t cap = (int64_t)num_cu * 16;
-  if (b > cap) b = cap;
-  hipLaunchKernelGGL(k_sub_from, dim3((unsigned)b), dim3(256), 0, st, x, y, count);
-  return hipGetLastError();
-}
-
-// Corrected seminormal equations of the refinement step: every column of G
-// (k x n, column-major, ld ldg) becomes R11^-1 R11^-T G(:, j) over the
-// leading keff rows (forward substitution with R11^T, then back substitution
-// with R11; R11 kcap x kcap row-major upper triangular); rows past keff are
-// set to zero.  One thread per column; R11 is read through the cache (every
-// lane of a wave reads the same entry).
-__global__ void k_csne_solve(const double* __restrict__ R11, int kcap, const int64_t* __restrict__ keff_p,
-                             double* __restrict__ G, int64_t ldg, int n) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  const int ke = (int)*keff_p;
-  double* g = G + ldg * j;
-  for (int b = 0; b < ke; ++b) {
-    double acc = g[b];
-    for (int a = 0; a < b; ++a) acc = fma(-R11[(int64_t)a * kcap + b], g[a], acc);
-    g[b] = acc / R11[(int64_t)b * kcap + b];
-  }
-  for (int b = ke - 1; b >= 0; --b) {
-    double acc = g[b];
-    for (int a = b + 1; a < ke; ++a) acc = fma(-R11[(int64_t)b * kcap + a], g[a], acc);
-    g[b] = acc / R11[(int64_t)b * kcap + b];
-  }
-  for (int b = ke < 0 ? 0 : ke; b < kcap; ++b) g[b] = 0.0;
-}
-
-hipError_t launch_csne_solve(hipStream_t st, const double* R11, int kcap, const int64_t* keff,
-                             double* G, int64_t ldg, int n) {
-  hipLaunchKernelGGL(k_csne_solve, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, st, R11, kcap,
-                     keff, G, ldg, n);
-  return hipGetLastError();
-}
-
-// Pd += dP (both k x n, ld k) and P (ldp, element type OutT) = Pd
-template <typename OutT>
-__global__ void k_refine_store(double* __restrict__ Pd, const double* __restrict__ dP, int k, int n,
-                               OutT* __restrict__ P, int64_t ldp) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)k * n;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(e % k);
-    const int64_t j = e / k;
-    const double v = Pd[e] + dP[e];
-    Pd[e] = v;
-    if (P) P[i + ldp * j] = (OutT)v;
-  }
-}
-
-hipError_t launch_refine_store(hipStream_t st, double* Pd, const double* dP, int k, int n, void* P,
-                               int64_t ldp, bool p_f64) {
-  const int64_t total = (int64_t)k * n;
-  const unsigned b = (unsigned)((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096);
-  if (p_f64)
-    hipLaunchKernelGGL(k_refine_store<double>, dim3(b), dim3(256), 0, st, Pd, dP, k, n, (double*)P, ldp);
-  else
-    hipLaunchKernelGGL(k_refine_store<float>, dim3(b), dim3(256), 0, st, Pd, dP, k, n, (float*)P, ldp);
   return hipGetLastError();
 }
 

@@ -11,9 +11,12 @@ hipError_t launch_sketch(hipStream_t st, int prec, bool a_is_f64, const void* A,
                          int64_t N, int64_t n, const int64_t* rows, int64_t Ns, int lq,
                          uint64_t seed, int64_t nchunks, double* part, double* W,
                          const float* omega, int l, void* Y);
+// mgsqr (k_cpqr_l2 / k_cpqr_coop / k_cpqr_wg).  forced (device, kmax
+// entries, optional): step i takes column forced[i] as its pivot instead of
+// the largest residual (a negative entry ends the factorization there)
 hipError_t launch_cpqr(hipStream_t st, const double* X, int64_t ldx, int m, int nc, int kmax,
                        double rank_tol, double* Wr, double* nrm2, int64_t* piv, double* R,
-                       double* Q, int64_t* keff, double* stats);
+                       double* Q, int64_t* keff, double* stats, const int64_t* forced = nullptr);
 hipError_t launch_backsolve(hipStream_t st, const double* R, const int64_t* piv,
                             const int64_t* keff, int kcap, int nc, double* Pd, void* P,
                             int64_t ldp, bool p_is_f64);
@@ -28,11 +31,6 @@ hipError_t launch_gemm64(hipStream_t st, int M, int Nn, int K, const double* A, 
                          int tA, const double* B, int64_t ldb, int tB, double* C, int64_t ldc);
 hipError_t launch_add_inplace(hipStream_t st, bool f64, void* y, const void* x, int64_t count,
                               int num_cu);
-hipError_t launch_sub_from(hipStream_t st, const double* x, double* y, int64_t count, int num_cu);
-hipError_t launch_csne_solve(hipStream_t st, const double* R11, int kcap, const int64_t* keff,
-                             double* G, int64_t ldg, int n);
-hipError_t launch_refine_store(hipStream_t st, double* Pd, const double* dP, int k, int n, void* P,
-                               int64_t ldp, bool p_f64);
 hipError_t launch_gather_r11(hipStream_t st, const double* R, int nc, const int64_t* piv,
                              const int64_t* keff, int kcap, double* R11);
 hipError_t launch_gather_cols(hipStream_t st, const void* src, bool src_f64, int64_t lds,
@@ -87,7 +85,8 @@ size_t cpqr_coop_scratch_bytes(int m, int nc);
 hipError_t launch_cpqr_coop(hipStream_t st, const double* X, int64_t ldx, int m, int nc, int kmax,
                             double rank_tol, void* scratch, unsigned int* sync2, int64_t* piv,
                             double* R, double* Q, int64_t* keff, double* stats,
-                            bool cooperative, unsigned int* sticky);
+                            bool cooperative, unsigned int* sticky,
+                            const int64_t* forced = nullptr);
 hipError_t launch_id_coefficients(hipStream_t st, const double* R, int nc, const int64_t* piv,
                                   const int64_t* keff, int kcap, double* R11, double* Pd,
                                   void* P, int64_t ldp, bool p_is_f64);
@@ -102,5 +101,5 @@ hipError_t launch_apply_t_bf16(hipStream_t st, const float* Y, int64_t N, int l,
 bool cpqr_wg_supported(int m, int nc);
 hipError_t launch_cpqr_wg(hipStream_t st, const double* X, int64_t ldx, int m, int nc, int kmax,
                           double rank_tol, int64_t* piv, double* R, double* Q, int64_t* keff,
-                          double* stats);
+                          double* stats, const int64_t* forced = nullptr);
 }  // namespace sid

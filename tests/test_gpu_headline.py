@@ -188,3 +188,17 @@ def test_c2_f64_two_pass_all_pivots(sid, oracle_mod, c2):
     e_orc = oracle_mod.error_norms(A64, ref.AJ, ref.P)["rel_fro"]
     say("c2 f64: rel_fro gpu", e_gpu, "oracle", e_orc)
     assert abs(e_gpu - e_orc) <= 1e-10 * e_orc + 1e-14
+
+
+@pytest.mark.timeout(900)
+def test_c2_precision_errors(sid, c2):
+    """FP8, FP8 + one FP32 refinement pass, bf16x2 and FP32 sketches on the
+    benchmarked workload, single and two pass: errors reported side by side;
+    two pass, the refinement does not increase the error; FP32 is more
+    accurate than FP8."""
+    from test_gpu_c5 import precision_errors
+    A, _ = c2
+    errs = precision_errors(sid, A, K, P_OV, Q_PR, 0, "c2")
+    for mode in ("single_pass", "two_pass"):
+        assert errs[mode, "f32"] <= errs[mode, "fp8"]
+    assert errs["two_pass", "fp8+refine"] <= errs["two_pass", "fp8"]

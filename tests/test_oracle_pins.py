@@ -460,13 +460,16 @@ def test_compression_factor_printed_values(oracle_mod):
     assert oracle_mod.temporal_compression_factor(10000, 100) == 100.0
 
 
-def test_refinement_fixed_point_and_noop(oracle_mod):
-    """Refinement of P: (1) with the refinement sketch equal to the first one
-    the step is a no-op (the first P already solves that least-squares
-    problem); (2) iterated, it converges to the least-squares coefficients of
-    the refinement sketch, lstsq(W'(:, J), W') (an independent library
-    solve), with P(:, J) = I kept exactly; (3) one step from an FP8 sketch
-    moves P toward that solution."""
+def test_refinement_least_squares(oracle_mod):
+    """Refinement of P (the least-squares coefficients of the refinement
+    sketch with J fixed), pinned without its library solve: (1) with the
+    refinement sketch equal to the first one it returns the first P, which
+    mgsqr and back substitution formed (R11^-1 R12); (2) the residual of the
+    refinement sketch is orthogonal to its pivot columns (normal equations)
+    and P(:, J) = I exactly; (3) on a matrix of rank k the refined ID is
+    exact, whatever the precision of the first sketch; (4) from an FP8
+    first sketch the refined ID is at least as accurate as the unrefined
+    one."""
     rng = np.random.default_rng(31)
     N, n, k, p = 3000, 60, 8, 6
     A = (rng.standard_normal((N, 12)) @ rng.standard_normal((12, n))
@@ -477,16 +480,18 @@ def test_refinement_fixed_point_and_noop(oracle_mod):
     assert np.max(np.abs(P1 - res.P)) <= 1e-9 * np.max(np.abs(res.P))
     res8 = oracle_mod.compress(A, k, p, seed=5, mode="two_pass", prec="fp8", probe_rows=0)
     J = res8.cp.J
+    P8 = oracle_mod.refine(A, res8, seed=5, refine_prec="f64", l=l)
+    assert np.array_equal(P8[:, J], np.eye(k))
     Wp = oracle_mod.sketch_w(A, None, l, 5, "f64")
-    target = np.linalg.lstsq(Wp[:, J], Wp, rcond=None)[0]
-    cur = oracle_mod.Result(**{**res8.__dict__})
-    d0 = np.max(np.abs(res8.P - target))
-    for it in range(40):
-        cur.P = oracle_mod.refine(A, cur, seed=5, refine_prec="f64", l=l)
-        if it == 0:
-            assert np.max(np.abs(cur.P - target)) < 0.5 * d0
-    assert np.max(np.abs(cur.P - target)) <= 1e-8 * np.max(np.abs(target))
-    assert np.array_equal(cur.P[:, J], np.eye(k))
+    ne = Wp[:, J].T @ (Wp - Wp[:, J] @ P8)
+    assert np.max(np.abs(ne)) <= 1e-11 * np.linalg.norm(Wp[:, J]) * np.linalg.norm(Wp)
+    e0 = oracle_mod.error_norms(A, A[:, J], res8.P)["rel_fro"]
+    e1 = oracle_mod.error_norms(A, A[:, J], P8)["rel_fro"]
+    assert e1 <= e0
+    Lk = rng.standard_normal((N, k)) @ rng.standard_normal((k, n))
+    r8 = oracle_mod.compress(Lk, k, p, seed=7, mode="two_pass", prec="fp8", probe_rows=0)
+    Pk = oracle_mod.refine(Lk, r8, seed=7, refine_prec="f64", l=l)
+    assert oracle_mod.error_norms(Lk, Lk[:, r8.cp.J], Pk)["rel_fro"] < 1e-12
 
 
 def test_literal_subsampled_id_matches_lapack(oracle_mod):
