@@ -267,6 +267,26 @@ sid_status sid_fill_gaussian(sid_ctx *ctx, uint64_t seed, int stream, int64_t ma
 sid_status sid_sketch(sid_ctx *ctx, const void *A, sid_dtype dtype, int64_t N, int64_t n,
                       int64_t lda, const sid_params *p, double *W, void *Y);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): sid_sketch with all of its
+ * scratch (Omega's values, Omega^T in bfloat16, the per-workgroup-pair FP32
+ * partials of W) in a static device array of 80 MiB that each device holds
+ * from the library's load until the process ends; the call itself allocates
+ * nothing (no hipMalloc, no hipFree, no allocating library routine) and
+ * leaves the context's workspace untouched.  Same arguments, outputs and
+ * results (bit for bit) as sid_sketch, restricted to FP32 data in device
+ * memory with a 16-byte aligned base and lda % 4 == 0, all rows (no coarse
+ * set), the BF16 / BF16X2 / FP8E4M3 sketch forms and n within one launch of
+ * the matrix-core pass sid_sketch takes (512 columns up to l = 128 and
+ * l + e + q = 160; narrower beyond, e.g. 384 columns for k = 150, p = 30).
+ * Errors: SID_EINVAL for other inputs, and for shapes whose scratch exceeds
+ * the static array (the message gives both sizes).  Every call on a device
+ * shares that device's array, which keeps the last call's contents: two
+ * calls that overlap on one device (two streams, two threads) race and give
+ * wrong results. */
+sid_status sid_sketch_noalloc(sid_ctx *ctx, const void *A, sid_dtype dtype, int64_t N, int64_t n,
+                              int64_t lda, const sid_params *p, double *W, void *Y);
+
 /*
  * Streaming (snapshots that arrive a few at a time, the in-situ setting of
  * Sec. 1 and Sec. 4).  Both sketches are linear in the columns: W(:, j) =

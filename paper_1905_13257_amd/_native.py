@@ -26,7 +26,7 @@ EXPORTS = [
     "sid_stream_save", "sid_stream_restore", "sid_compress_batched",
     "sid_interp_create", "sid_interp_destroy", "sid_interp_rowset", "sid_interp_info",
     "sid_interp_reconstruct", "sid_interp_error_norms", "sid_svd_params_init", "sid_sbr_svd",
-    "sid_svd_stream_begin", "sid_svd_stream_finish", "sid_sync",
+    "sid_svd_stream_begin", "sid_svd_stream_finish", "sid_sync", "sid_sketch_noalloc",
 ]
 
 
@@ -111,6 +111,7 @@ def load():
     L.sid_error_norms.argtypes = [vp, vp, i64, vp, i64, vp, i64, ctypes.c_int, i64, i64, i64, vp]
     L.sid_fill_gaussian.argtypes = [vp, u64, ctypes.c_int, i64, i64, i64, i64, vp]
     L.sid_sketch.argtypes = [vp, vp, ctypes.c_int, i64, i64, i64, pp, vp, vp]
+    L.sid_sketch_noalloc.argtypes = [vp, vp, ctypes.c_int, i64, i64, i64, pp, vp, vp]
     L.sid_stream_begin.argtypes = [vp, ctypes.c_int, i64, i64, pp, ctypes.POINTER(vp)]
     L.sid_stream_push.argtypes = [vp, vp, i64, i64]
     L.sid_stream_finish.argtypes = [vp, vp, vp, i64, vp, i64, vp, vp]
@@ -419,6 +420,24 @@ def sketch(A: torch.Tensor, k: int, oversample: int = 10, seed: int = 0,
                 probe_rows, 0.0, 0.0, corange_rows)
     ctx.check(ctx._lib.sid_sketch(ctx.handle, _ptr(A), _dtype_code(A), N, n, lda,
                                   ctypes.byref(p), _ptr(W), _ptr(Y)))
+    return W, Y
+
+
+def sketch_noalloc(A: torch.Tensor, k: int, W: torch.Tensor, Y: torch.Tensor | None = None,
+                   oversample: int = 10, seed: int = 0, prec: str = "bf16x2",
+                   probe_rows: int = 10, corange_rows: int = -1, ctx: Context | None = None):
+    """sid_sketch_noalloc: sid_sketch without any allocation (scratch in the
+    library's static device array).  The caller passes the outputs: W (lw x n
+    float64, column-major, lw = l + e + q with e only when Y is given) and
+    optionally Y (N x l float32, row-major)."""
+    ctx = ctx or default_context(A.device)
+    if A.stride(0) != 1:
+        raise ValueError("A must be column-major")
+    N, n = A.shape
+    p = _params(k, oversample, seed, None, "single_pass" if Y is not None else "two_pass", prec,
+                probe_rows, 0.0, 0.0, corange_rows)
+    ctx.check(ctx._lib.sid_sketch_noalloc(ctx.handle, _ptr(A), _dtype_code(A), N, n, A.stride(1),
+                                          ctypes.byref(p), _ptr(W), _ptr(Y)))
     return W, Y
 
 

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -21,7 +22,37 @@
 #include "sid_interp.hpp"
 #include "sid_kernels.hpp"
 
+// ---------------------------------------------------------------------------
+// Allocation-free sketch (sid_sketch_noalloc): the pass's scratch (Omega's
+// values, Omega^T in bfloat16, the per-workgroup-pair W partials) lives in
+// this file-scope device array.  Host code never passes the array's name to
+// a kernel: its device address is taken once per device at set-up
+// (hipGetSymbolAddress in sid_create) and kept in noalloc_ptr[device].
+// ---------------------------------------------------------------------------
+#define SID_NOALLOC_SCRATCH_BYTES (80u << 20)
+static __device__ __align__(256) unsigned char scratch[SID_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex noalloc_mu;
+void* noalloc_ptr[kMaxDevices] = {};
+
+// the device address of `scratch` on the current device (set-up only: the
+// device must be current); nullptr on failure
+void* noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> g(noalloc_mu);
+  if (!noalloc_ptr[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    noalloc_ptr[device] = p;
+  }
+  return noalloc_ptr[device];
+}
 
 enum Slot {
   WS_OMEGA, WS_PART, WS_W, WS_WR, WS_NRM, WS_PIV, WS_R, WS_Q, WS_KEFF, WS_STATS, WS_PD,
@@ -466,6 +497,10 @@ sid_status sid_create(sid_ctx** out, int device, void* hip_stream) {
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
       ncu > 0)
     c->num_cu = ncu;
+  if (!noalloc_scratch_init(device)) {
+    delete c;
+    return SID_EDEVICE;
+  }
   if (hipMalloc(&c->fail_flag, 64) != hipSuccess || hipMemset(c->fail_flag, 0, 64) != hipSuccess) {
     (void)hipGetLastError();
     if (c->fail_flag) (void)hipFree(c->fail_flag);
@@ -773,6 +808,72 @@ sid_status sid_sketch(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N, i
   Work w;
   if (reserve(ctx, sh2, &w) != SID_OK) return SID_ENOMEM;
   return run_sketch(ctx, A, dtype, lda, p, sh, w, W, Y);
+}
+
+sid_status sid_sketch_noalloc(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N, int64_t n,
+                              int64_t lda, const sid_params* p, double* W, void* Y) {
+  if (!ctx) return SID_EINVAL;
+  if (!A || !W) return fail(ctx, SID_EINVAL, "A and W must be non-NULL");
+  if (dtype != SID_F32) return fail(ctx, SID_EINVAL, "the allocation-free sketch reads FP32 data");
+  if (lda < N) return fail(ctx, SID_EINVAL, "lda < N");
+  Shape sh;
+  sid_status s = validate(ctx, N, n, p, &sh);
+  if (s != SID_OK) return s;
+  if (p->coarse) return fail(ctx, SID_EINVAL, "the allocation-free sketch reads all rows");
+  if (p->select != SID_SEL_GAUSS) return fail(ctx, SID_EINVAL, "literal selection has no sketch");
+  if (sh.prec != SID_SK_BF16 && sh.prec != SID_SK_BF16X2 && sh.prec != SID_SK_FP8E4M3)
+    return fail(ctx, SID_EINVAL, "the allocation-free sketch runs the bf16 / bf16x2 / fp8 forms");
+  const bool want_y = Y != nullptr;
+  // the same kernels as sid_sketch takes for this input, in one launch
+  const SketchPath path = plan_sketch(ctx, dtype, lda, A, sh.prec, sh, false, want_y);
+  const bool pairs_path = path == SketchPath::PAIR_BF16;
+  if ((path != SketchPath::FUSED_BF16 && !pairs_path) ||
+      sh.n > (pairs_path ? sid::sketch_v2_slab((int)sh.lq, (int)sh.l, want_y) : 512))
+    return fail(ctx, SID_EINVAL,
+                "the allocation-free sketch needs a 16-byte aligned A, lda % 4 == 0 and a shape "
+                "the matrix-core passes take in one launch");
+  // the scratch this call needs, carved in 256-byte aligned pieces: Omega's
+  // values, Omega^T in bfloat16, the per-workgroup (pair) W partials
+  int64_t rows = 0;
+  const int64_t nparts = pairs_path ? sid::sketch_v2_pairs(sh.N, ctx->num_cu, &rows)
+                                    : sid::fused_bf16_grid(sh.N, ctx->num_cu, &rows);
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t omt_elems =
+      pairs_path ? sid::sketch_v2_omt_elems((int)sh.l, (int)sh.n) : (size_t)128 * 512;
+  const size_t b_om = want_y ? up(sizeof(float) * (size_t)(sh.n * sh.l)) : 0;
+  const size_t b_omt = want_y ? up(sizeof(uint16_t) * omt_elems) : 0;
+  const size_t b_part = up(sizeof(float) * (size_t)(nparts * sh.lq * sh.n));
+  const size_t need = b_om + b_omt + b_part;
+  if (need > SID_NOALLOC_SCRATCH_BYTES)
+    return fail(ctx, SID_EINVAL,
+                "input too large for the allocation-free sketch: it needs " + std::to_string(need) +
+                    " bytes of scratch, the static scratch holds " +
+                    std::to_string((size_t)SID_NOALLOC_SCRATCH_BYTES));
+  SID_NEED_DEVICE(ctx);
+  SID_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+  unsigned char* base = (unsigned char*)noalloc_ptr[ctx->device];
+  if (!base) return fail(ctx, SID_ESTATE, "no scratch address for this device");
+  float* om = want_y ? (float*)base : nullptr;
+  __bf16* omt = want_y ? (__bf16*)(base + b_om) : nullptr;
+  float* part = (float*)(base + b_om + b_omt);
+  hipStream_t st = ctx->stream;
+  if (want_y)
+    SID_CHECK(sid::launch_fill_gaussian(st, p->seed, 0u, 0, sh.n, 0, sh.l, om), "omega generation");
+  const int dmode = sh.prec == SID_SK_BF16X2   ? sid::FB_BF16X2
+                    : sh.prec == SID_SK_FP8E4M3 ? sid::FB_FP8
+                                                : sid::FB_BF16;
+  int64_t np = 0;
+  if (pairs_path)
+    SID_CHECK(sid::launch_sketch_v2(st, dmode, (const float*)A, lda, sh.N, (int)sh.n, (int)sh.lq,
+                                    (int)sh.l, p->seed, om, omt, ctx->num_cu, part, W, (float*)Y,
+                                    &np),
+              "sketch pass (allocation-free)");
+  else
+    SID_CHECK(sid::launch_sketch_fused_bf16(st, dmode, (const float*)A, lda, sh.N, (int)sh.n,
+                                            (int)sh.lq, (int)sh.l, p->seed, om, omt, ctx->num_cu,
+                                            part, W, (float*)Y, &np, nullptr),
+              "sketch pass (allocation-free)");
+  return SID_OK;
 }
 
 sid_status sid_compress(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t N, int64_t n,
