@@ -118,34 +118,41 @@ def cpu_baseline(A, k, p, q, rows: int, st_rows: int):
 
 
 def batched_main(args, torch, sid, synth) -> int:
-    """64 independent low-rank matrices with exact spectrum sigma_j = j^-1.5
-    (orthonormal DCT columns, device-generated), single pass, p = 10."""
+    """The uneven batch: 64 independent FP32 matrices, N log-uniform in
+    [16384, 1048576], n uniform in [64, 512], k uniform in [8, 64],
+    sigma_j = j^-1.5 (device-generated), single pass, p = 10, one
+    sid_compress_batched call (persistent sketch pass, autotuned stream count)
+    against one call per matrix."""
     import numpy as np
-    rng = np.random.default_rng(1003)
-    mats, ks = [], []
-    for b in range(64):
-        N = int(np.exp(rng.uniform(np.log(2 ** 14), np.log(2 ** 20)))) // 64 * 64
-        n = int(rng.integers(64, 513))
-        k = int(rng.integers(8, 65))
-        sig = np.arange(1, n + 1, dtype=np.float64) ** -1.5
-        mats.append(synth.dct_lowrank(N, n, sig, seed=int(rng.integers(1 << 30)), device="cuda"))
-        ks.append(k)
+    shapes = synth.batched_shapes()
+    mats = [synth.batched_matrix(N, n, seed=1000 + b, device="cuda")
+            for b, (N, n, _) in enumerate(shapes)]
+    ks = [k for _, _, k in shapes]
+    seeds = list(range(11, 11 + len(mats)))
     torch.cuda.synchronize()
-    total = sum(A.shape[0] * A.shape[1] * 4 for A in mats)
-    kw = dict(oversample=10, seed=0, mode="single_pass", prec=args.prec, probe_rows=10)
-    outs = sid.compress_batched(mats, ks, **kw)
-    ms_b = time_steps(lambda: sid.compress_batched(mats, ks, **kw), args.steps, args.warmup, torch)
-    ms_s = time_steps(lambda: [sid.compress(A, k, **kw) for A, k in zip(mats, ks)],
+    total = sum(N * n * 4 for N, n, _ in shapes)
+    kw = dict(oversample=10, mode="single_pass", prec=args.prec, probe_rows=10)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ctx = sid.Context(stream=stream)
+        bt = sid.Batch(mats, ks, seed=seeds, ctx=ctx, **kw).reserve(tune=True)
+        streams = sid.batch_streams(ctx)
+        ms_b = time_steps(bt.run, args.steps, args.warmup, torch)
+    ctx.sync()
+    outs = bt.outs
+    ms_s = time_steps(lambda: [sid.compress(A, k, seed=sd, **kw) for A, k, sd in zip(mats, ks, seeds)],
                       max(3, args.steps // 2), 1, torch)
     errs = [sid.error_norms(A, o.AJ, o.P)["rel_fro"] for A, o in zip(mats, outs)]
     line = {
-        "metric": "batched snapshot GB/s (single-pass ID of 64 matrices)", "value": round(total / (ms_b * 1e-3) / 1e9, 2),
+        "metric": "batched snapshot GB/s (single-pass ID of 64 matrices)",
+        "value": round(total / (ms_b * 1e-3) / 1e9, 2),
         "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_b, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
-        "config": {"workload": "64 matrices, N log-uniform in [16384, 1048576], n in [64, 512], "
-                               "k in [8, 64], p = 10, sigma_j = j^-1.5",
-                   "total_bytes": total, "sequential_ms": round(ms_s, 4),
+        "config": {"workload": "64 FP32 matrices, N log-uniform in [16384, 1048576], n in [64, 512], "
+                               "k in [8, 64], p = 10, q = 10, sigma_j = j^-1.5, one batched call",
+                   "total_bytes": total, "factor_streams": streams,
+                   "sequential_ms": round(ms_s, 4),
                    "sequential_value": round(total / (ms_s * 1e-3) / 1e9, 2),
                    "rel_fro_error_max": max(errs), "rel_fro_error_median": float(np.median(errs))},
     }
@@ -492,6 +499,19 @@ def main() -> int:
                 "traffic": measured_traffic(khash), "kernel": "sketch pass (W = Psi A, Y = A Omega)",
                 "algorithmic_bytes_per_launch": alg_bytes, "launch_ms": round(main_r["sketch_ms"], 4)}
 
+    # the reconstruction Ahat = AJ P (eq. (ID); a posteriori, outside the
+    # step): HBM-bound on writing Ahat, algorithmic bytes = write N n + read
+    # AJ (N k) in FP32
+    o = sid.compress(A, k, p, seed=0, mode="single_pass", prec=args.prec, probe_rows=q)
+    Ahat = torch.empty((n, N), dtype=torch.float32, device="cuda").T
+    rec_ms = time_steps(lambda: sid.reconstruct(o.AJ, o.P, out=Ahat), 5, 1, torch)
+    rec_bytes = N * n * 4 + N * k * 4
+    reconstruct = {"kernel": "reconstruction Ahat = AJ P (matrix cores)", "ms": round(rec_ms, 4),
+                   "algorithmic_bytes": rec_bytes,
+                   "achieved_GBs": round(rec_bytes / (rec_ms * 1e-3) / 1e9, 1),
+                   "frac": round(rec_bytes / (rec_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    del Ahat, o
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(A, k, p, q, min(args.cpu_rows, N), min(args.cpu_st_rows, N))
@@ -503,6 +523,7 @@ def main() -> int:
         "sketch_precision": args.prec, "rel_fro_error": main_r["rel_fro"],
         "max_abs_error": main_r["max_abs"], "probe_estimate": main_r["est"],
         "k_eff": main_r["k_eff"], "sketch_ms": round(main_r["sketch_ms"], 4),
+        "reconstruct": reconstruct,
     }
     if cpu is not None and min(args.cpu_rows, N) == N:
         # the oracle's own FP64 compression of the same matrix, beside the GPU's

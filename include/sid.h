@@ -239,7 +239,11 @@ sid_status sid_compress(sid_ctx *ctx, const void *A, sid_dtype dtype, int64_t N,
                         void *AJ, int64_t ldaj, double *err, int64_t *k_eff);
 
 /* Reconstruct Ahat = AJ P (eq. (ID)); AJ N x k (ldaj), P k x n (ldp), Ahat
- * N x n (ldo), all of element type `dtype`; 1 <= k <= 256. */
+ * N x n (ldo), all of element type `dtype`; 1 <= k <= 256.  FP32 with
+ * k <= 128 runs on the bfloat16 matrix cores from hi + lo splits of AJ and P
+ * (three products, FP32 accumulation): each entry is within 2^-15 of
+ * sum_t |AJ(i, t)| |P(t, j)| of the exact product.  FP64, and FP32 with
+ * k > 128: FMAs in the element type. */
 sid_status sid_reconstruct(sid_ctx *ctx, const void *AJ, int64_t ldaj, const void *P,
                            int64_t ldp, sid_dtype dtype, int64_t N, int64_t k, int64_t n,
                            void *Ahat, int64_t ldo);
@@ -471,16 +475,34 @@ sid_status sid_svd_stream_finish(sid_stream *s, double *S, void *U, int64_t ldu,
                                  int64_t ldv, int64_t *rank);
 
 /*
- * Batched compression of independent matrices (one call for many problems,
- * e.g. one per flow variable or dataset).  probs: host array of `count`
- * problems, each with its own A (N x n, lda), parameters and outputs (same
- * meanings, layouts and NULL rules as sid_compress); all share `dtype`.
- * Every problem is validated before anything is launched (SID_EINVAL names
- * the first bad problem in sid_last_error).  The problems run on up to four
- * internal streams of the context (each with its own workspace), after the
- * work already queued on the context's stream; the context's stream waits
- * for all of them before the call returns, so later work on it sees every
- * result.  A row set in a problem's params must belong to ctx.
+ * Batched compression of independent matrices (Sec. 3 compresses each flow
+ * variable or dataset on its own; Sec. 3.3 compresses a long record block by
+ * block).  probs: host array of `count` problems, each with its own A (N x n,
+ * lda), parameters and outputs (same meanings, layouts and NULL rules as
+ * sid_compress); all share `dtype`.  Every problem is validated before
+ * anything is launched (SID_EINVAL names the first bad problem in
+ * sid_last_error).  Results are bit for bit those of one sid_compress per
+ * problem.
+ *
+ * When every problem has FP32 data (16-byte aligned, lda % 4 == 0), the same
+ * BF16 / BF16X2 / FP8E4M3 sketch form and mode (two-pass or single-pass), the
+ * Gaussian selection over all rows, no refinement, n <= 512, l <= 128 and
+ * l + e + q <= 160, one persistent launch sketches all of them: a work queue
+ * of every problem's row shares (the problems with the most work per share
+ * first), then one launch forms every W.  The factorizations then run per
+ * problem on up to 8 internal child streams (own workspace each).  Other
+ * batches run each problem's sid_compress on the child streams.  Everything
+ * runs after the work already queued on the context's stream, which waits
+ * for all of it before the call returns.
+ *
+ * The persistent path keeps a plan per problem set (the queue table and the
+ * problems' partials, W, Omega and Y in device memory owned by the context;
+ * the last 8 problem sets are kept).  Once the plan and the child streams
+ * exist (sid_reserve_batched, or an earlier call with the same problems) the
+ * call allocates nothing.  It is not capturable: under HIP graph capture the
+ * call returns SID_ESTATE (a captured batched call ended the process inside
+ * the runtime's end of capture).  A row set in a problem's params must
+ * belong to ctx.
  */
 typedef struct {
     const void *A;
@@ -497,6 +519,24 @@ typedef struct {
 
 sid_status sid_compress_batched(sid_ctx *ctx, const sid_problem *probs, int64_t count,
                                 sid_dtype dtype);
+
+/* Everything sid_compress_batched with these problems would allocate or
+ * create: the batch's plan (persistent path), the 8 child streams and their
+ * workspaces.  tune != 0 also runs the autotuner: the batch is compressed
+ * with 1, 2, 4 and 8 child streams for the factorizations (twice, the first
+ * round warming up; every candidate writes the same results to the
+ * problems' outputs) and the fastest count is kept for the context.  The
+ * choice is cached per (GPU architecture, sketch form, mode, batch size as
+ * a power of two, widest problem in 128-column chunks); with the environment
+ * variable SID_TUNE_CACHE naming a file, choices are appended to it and a
+ * later call with tune = 0 (in any process) takes the cached choice for its
+ * key.  Not under graph capture (SID_ESTATE). */
+sid_status sid_reserve_batched(sid_ctx *ctx, const sid_problem *probs, int64_t count,
+                               sid_dtype dtype, int tune);
+
+/* The number of child streams batched calls of ctx use (4 until the
+ * autotuner or its cache sets it); -1 for a NULL ctx. */
+int sid_batch_streams(const sid_ctx *ctx);
 
 #ifdef __cplusplus
 }

@@ -23,7 +23,8 @@ EXPORTS = [
     "sid_set_workspace_limit", "sid_rowset_create", "sid_rowset_destroy", "sid_reserve",
     "sid_compress", "sid_reconstruct", "sid_error_norms", "sid_fill_gaussian", "sid_sketch",
     "sid_stream_begin", "sid_stream_push", "sid_stream_finish", "sid_stream_info", "sid_stream_abort",
-    "sid_stream_save", "sid_stream_restore", "sid_compress_batched",
+    "sid_stream_save", "sid_stream_restore", "sid_compress_batched", "sid_reserve_batched",
+    "sid_batch_streams",
     "sid_interp_create", "sid_interp_destroy", "sid_interp_rowset", "sid_interp_info",
     "sid_interp_reconstruct", "sid_interp_error_norms", "sid_svd_params_init", "sid_sbr_svd",
     "sid_svd_stream_begin", "sid_svd_stream_finish", "sid_sync", "sid_sketch_noalloc",
@@ -117,6 +118,9 @@ def load():
     L.sid_stream_finish.argtypes = [vp, vp, vp, i64, vp, i64, vp, vp]
     L.sid_stream_abort.argtypes = [vp]
     L.sid_compress_batched.argtypes = [vp, vp, i64, ctypes.c_int]
+    L.sid_reserve_batched.argtypes = [vp, vp, i64, ctypes.c_int, ctypes.c_int]
+    L.sid_batch_streams.argtypes = [vp]
+    L.sid_batch_streams.restype = ctypes.c_int
     L.sid_stream_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     L.sid_stream_save.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_size_t)]
@@ -320,6 +324,57 @@ def _new_outputs(N: int, n: int, k: int, dtype, dev, want_skeleton: bool) -> Com
     return Compressed(J, P, AJ, err, keff)
 
 
+class Batch:
+    """A fixed set of problems for sid_compress_batched.  The problem table,
+    the inputs and the outputs live as long as the object, so the call can be
+    repeated, reserved ahead (reserve: sid_reserve_batched, optionally with
+    the autotuner) and captured in a HIP graph (run under capture after
+    reserve).  k, oversample, seed and probe_rows may be scalars or one value
+    per matrix; all matrices share dtype, mode and precision."""
+
+    def __init__(self, mats: list, k, oversample=10, seed=0, mode: str = "two_pass",
+                 prec: str = "f32", probe_rows=10, rank_tol: float = 0.0, sp_rcond: float = 0.0,
+                 want_skeleton: bool = True, ctx: Context | None = None,
+                 probe_tol: float = 0.0):
+        if not mats:
+            raise ValueError("no matrices")
+        self.ctx = ctx or default_context(mats[0].device)
+        m = len(mats)
+        per = lambda v: list(v) if isinstance(v, (list, tuple)) else [v] * m
+        ks, ovs, seeds, qs = per(k), per(oversample), per(seed), per(probe_rows)
+        dtype = mats[0].dtype
+        self.dtype_code = _dtype_code(mats[0])
+        self.probs = (_Problem * m)()
+        self.keep, self.outs = [], []
+        for b, A in enumerate(mats):
+            if A.dtype != dtype:
+                raise ValueError("all matrices must share one dtype")
+            A, lda = _colmajor(A)
+            N, n = A.shape
+            o = _new_outputs(N, n, ks[b], dtype, A.device, want_skeleton)
+            p = _params(ks[b], ovs[b], seeds[b], None, mode, prec, qs[b], rank_tol, sp_rcond,
+                        probe_tol=probe_tol)
+            self.probs[b] = _Problem(ctypes.c_void_p(A.data_ptr()), N, n, lda, p, _ptr(o.J),
+                                     _ptr(o.P), o.P.stride(1), _ptr(o.AJ),
+                                     o.AJ.stride(1) if o.AJ is not None else 1, _ptr(o.err),
+                                     _ptr(o.k_eff))
+            self.keep.append(A)
+            self.outs.append(o)
+        self.count = m
+
+    def reserve(self, tune: bool = False) -> "Batch":
+        """sid_reserve_batched: the plan, child streams and workspaces; with
+        tune=True the autotuner times the stream counts on this batch."""
+        self.ctx.check(self.ctx._lib.sid_reserve_batched(self.ctx.handle, self.probs, self.count,
+                                                         self.dtype_code, 1 if tune else 0))
+        return self
+
+    def run(self) -> list:
+        self.ctx.check(self.ctx._lib.sid_compress_batched(self.ctx.handle, self.probs, self.count,
+                                                          self.dtype_code))
+        return self.outs
+
+
 def compress_batched(mats: list, k, oversample=10, seed=0, mode: str = "two_pass",
                      prec: str = "f32", probe_rows=10, rank_tol: float = 0.0,
                      sp_rcond: float = 0.0, want_skeleton: bool = True,
@@ -329,28 +384,14 @@ def compress_batched(mats: list, k, oversample=10, seed=0, mode: str = "two_pass
     all matrices share dtype, mode and precision."""
     if not mats:
         return []
-    ctx = ctx or default_context(mats[0].device)
-    m = len(mats)
-    per = lambda v: list(v) if isinstance(v, (list, tuple)) else [v] * m
-    ks, ovs, seeds, qs = per(k), per(oversample), per(seed), per(probe_rows)
-    dtype = mats[0].dtype
-    probs = (_Problem * m)()
-    keep, outs = [], []
-    for b, A in enumerate(mats):
-        if A.dtype != dtype:
-            raise ValueError("all matrices must share one dtype")
-        A, lda = _colmajor(A)
-        N, n = A.shape
-        o = _new_outputs(N, n, ks[b], dtype, A.device, want_skeleton)
-        p = _params(ks[b], ovs[b], seeds[b], None, mode, prec, qs[b], rank_tol, sp_rcond,
-                    probe_tol=probe_tol)
-        probs[b] = _Problem(ctypes.c_void_p(A.data_ptr()), N, n, lda, p, _ptr(o.J), _ptr(o.P),
-                            o.P.stride(1), _ptr(o.AJ), o.AJ.stride(1) if o.AJ is not None else 1,
-                            _ptr(o.err), _ptr(o.k_eff))
-        keep.append(A)
-        outs.append(o)
-    ctx.check(ctx._lib.sid_compress_batched(ctx.handle, probs, m, _dtype_code(mats[0])))
-    return outs
+    return Batch(mats, k, oversample, seed, mode, prec, probe_rows, rank_tol, sp_rcond,
+                 want_skeleton, ctx, probe_tol).run()
+
+
+def batch_streams(ctx: Context | None = None) -> int:
+    """Child streams the batched calls of ctx use (set by the autotuner)."""
+    ctx = ctx or default_context(torch.device("cuda"))
+    return int(ctx._lib.sid_batch_streams(ctx.handle))
 
 
 def compress(A: torch.Tensor, k: int, oversample: int = 10, seed: int = 0,

@@ -3,6 +3,7 @@
 // the context's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -66,6 +67,36 @@ struct Buf {
   size_t bytes = 0;
 };
 
+// What the batched sketch pass reads of one problem (its plan is reused
+// only for exactly the same values)
+struct BatchSig {
+  const void* A;
+  int64_t N, n, lda, lq, l;
+  uint64_t seed;
+  bool operator==(const BatchSig& o) const {
+    return A == o.A && N == o.N && n == o.n && lda == o.lda && lq == o.lq && l == o.l &&
+           seed == o.seed;
+  }
+};
+
+// Device state of one batch of problems for the persistent sketch pass: the
+// queue table, the counter and every problem's partials, W and (single pass)
+// Omega, Omega^T and Y, in one allocation owned by the context.  A graph
+// that captured a batched call reads these buffers at every replay.
+struct BatchPlan {
+  std::vector<BatchSig> sig;
+  int dmode = 0;
+  bool wanty = false;
+  void* dev = nullptr;
+  size_t bytes = 0;
+  sid::FbBatchEntry* d_tab = nullptr;
+  unsigned int* d_queue = nullptr;
+  int64_t nshares = 0, max_lqn = 0;
+  int max_n = 0;
+  std::vector<double*> W;       // by problem index
+  std::vector<float*> Y, omega;
+};
+
 }  // namespace
 
 struct sid_ctx {
@@ -98,6 +129,12 @@ struct sid_ctx {
   hipEvent_t side_fork = nullptr, side_join = nullptr;
   // library GEMMs of SBR-SVD (created on first use)
   rocblas_handle blas = nullptr;
+  // batched calls on the persistent sketch pass: the plans of the last few
+  // problem sets (newest last) and the number of child streams of the
+  // factorization phase (set by the autotuner)
+  std::vector<BatchPlan*> plans;
+  int batch_streams = 4;
+  std::vector<std::pair<std::string, int>> tuned;  // autotuner cache: key -> streams
 };
 
 struct sid_rowset {
@@ -306,12 +343,16 @@ struct Work {
   double* fitpart;
 };
 
-sid_status reserve(sid_ctx* c, const Shape& s, Work* w) {
+// sketch_bufs = false: the caller brings Omega, W and Y (the batched pass);
+// only the factorization's buffers are reserved
+sid_status reserve(sid_ctx* c, const Shape& s, Work* w, bool sketch_bufs = true) {
   const size_t d = sizeof(double);
   const int64_t mx = s.n > s.lz ? s.n : s.lz;
-  w->omega = (float*)ws(c, WS_OMEGA, sizeof(float) * (size_t)(s.n * s.l));
-  w->part = (double*)ws(c, WS_PART, d * (size_t)(s.nchunks * s.lq * s.n));
-  w->W = (double*)ws(c, WS_W, d * (size_t)(s.lq * s.n));
+  static double dummy_d;
+  static float dummy_f;
+  w->omega = sketch_bufs ? (float*)ws(c, WS_OMEGA, sizeof(float) * (size_t)(s.n * s.l)) : &dummy_f;
+  w->part = sketch_bufs ? (double*)ws(c, WS_PART, d * (size_t)(s.nchunks * s.lq * s.n)) : &dummy_d;
+  w->W = sketch_bufs ? (double*)ws(c, WS_W, d * (size_t)(s.lq * s.n)) : &dummy_d;
   w->Wr = (double*)ws(c, WS_WR, d * (size_t)(s.lz * s.l > s.l * s.n ? s.lz * s.l : s.l * s.n));
   w->nrm = (double*)ws(c, WS_NRM, d * (size_t)mx);
   w->piv = (int64_t*)ws(c, WS_PIV, sizeof(int64_t) * (size_t)s.k);
@@ -347,7 +388,7 @@ sid_status reserve(sid_ctx* c, const Shape& s, Work* w) {
   w->Y = nullptr;
   if (s.single) {
     const size_t ye = (s.prec == SID_SK_F64) ? d : sizeof(float);
-    w->Y = ws(c, WS_Y, ye * (size_t)(s.N * s.l));
+    w->Y = sketch_bufs ? ws(c, WS_Y, ye * (size_t)(s.N * s.l)) : (void*)&dummy_f;
     w->M = (double*)ws(c, WS_M, d * (size_t)(s.lz * s.l));
     w->Mpr = (double*)ws(c, WS_MPR, d * (size_t)((s.q > 0 ? s.q : 1) * s.l));
     w->WJ = (double*)ws(c, WS_WJ, d * (size_t)(s.lz * s.k));
@@ -533,6 +574,10 @@ sid_status sid_destroy(sid_ctx* ctx) {
   if (ctx->side_fork) (void)hipEventDestroy(ctx->side_fork);
   if (ctx->side_join) (void)hipEventDestroy(ctx->side_join);
   for (hipEvent_t e : ctx->child_done) (void)hipEventDestroy(e);
+  for (BatchPlan* pl : ctx->plans) {
+    if (pl->dev) (void)hipFree(pl->dev);
+    delete pl;
+  }
   if (ctx->blas) (void)rocblas_destroy_handle(ctx->blas);
   if (ctx->fork) (void)hipEventDestroy(ctx->fork);
   for (Buf& b : ctx->ws)
@@ -1159,6 +1204,18 @@ sid_status sid_reconstruct(sid_ctx* ctx, const void* AJ, int64_t ldaj, const voi
   if (k > 256) return fail(ctx, SID_EINVAL, "k must be <= 256");
   SID_NEED_DEVICE(ctx);
   SID_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+  if (dtype == SID_F32 && k <= 128) {
+    // the matrix-core kernel: AJ read in place, P packed as bfloat16 hi/lo
+    // operand tiles
+    const int kp = (int)((k + 15) / 16 * 16);
+    void* pb = ws(ctx, WS_IPB, sid::interp_pb_bytes(n, kp));
+    if (!pb) return SID_ENOMEM;
+    SID_CHECK(sid::launch_pack_p(ctx->stream, (const float*)P, ldp, (int)k, kp, n, pb), "pack P");
+    SID_CHECK(sid::launch_id_mfma(ctx->stream, (const float*)AJ, ldaj, N, (int)k, kp, pb, n,
+                                  (float*)Ahat, ldo, nullptr, 0, nullptr, 0, nullptr),
+              "reconstruct");
+    return SID_OK;
+  }
   SID_CHECK(sid::launch_reconstruct(ctx->stream, dtype == SID_F64, AJ, ldaj, P, ldp, N, (int)k, n,
                                     Ahat, ldo),
             "reconstruct");
@@ -1570,16 +1627,38 @@ sid_status sid_stream_restore(sid_ctx* ctx, const void* host_buf, size_t bytes, 
 
 // ---------------------------------------------------------------------------
 // Batched compression: independent problems (Sec. 3 compresses each flow
-// variable / dataset separately).  Each problem's launches run on one of up
-// to SID_BATCH_STREAMS child streams, each with its own workspace, so the
-// latency-bound factorizations of different problems overlap one another
-// and the sketch passes; the children start after the work already queued
-// on the context's stream and the context's stream waits for all of them.
+// variable / dataset separately; Sec. 3.3 compresses a long record block by
+// block).
+//
+// Persistent path (FP32 data, one bfloat16 sketch form and one mode for all
+// problems, shapes of the one-workgroup-per-row-range matrix-core pass, no
+// coarse rows or refinement): one launch sketches every problem -- a work
+// queue of all problems' row shares, the problems with the most work per
+// share first -- then one launch sums every problem's partials into its W.
+// Each share is a row range the single-matrix launch would give one
+// workgroup, so W and Y are bit for bit those of per-problem calls.  The
+// latency-bound factorizations then run per problem on child streams (own
+// workspace each).  Nothing is allocated once the batch's plan exists
+// (sid_reserve_batched, or an earlier call with the same problems), so the
+// whole call can be captured in a HIP graph.
+// Other batches: each problem's sid_compress on the child streams.
+// The children start after the work already queued on the context's stream
+// and the context's stream waits for all of them.
 // ---------------------------------------------------------------------------
 namespace {
-constexpr int SID_BATCH_STREAMS = 4;
+constexpr int SID_BATCH_STREAMS_MAX = 8;
+constexpr size_t SID_BATCH_PLANS = 8;
+
+bool capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
 
 sid_status ensure_children(sid_ctx* ctx, int want) {
+  if ((!ctx->fork || (int)ctx->children.size() < want) && capturing(ctx->stream))
+    return fail(ctx, SID_ESTATE,
+                "batched call under graph capture: create its child streams first "
+                "(sid_reserve_batched, or an eager call with as many problems)");
   if (!ctx->fork) {
     if (hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming) != hipSuccess) {
       (void)hipGetLastError();
@@ -1603,23 +1682,20 @@ sid_status ensure_children(sid_ctx* ctx, int want) {
   }
   return SID_OK;
 }
-}  // namespace
 
-sid_status sid_compress_batched(sid_ctx* ctx, const sid_problem* probs, int64_t count,
-                                sid_dtype dtype) {
-  if (!ctx) return SID_EINVAL;
+// every problem validated; shapes into sh
+sid_status validate_batch(sid_ctx* ctx, const sid_problem* probs, int64_t count, sid_dtype dtype,
+                          std::vector<Shape>* sh) {
   if (count < 0) return fail(ctx, SID_EINVAL, "count < 0");
-  if (count == 0) return SID_OK;
-  if (!probs) return fail(ctx, SID_EINVAL, "probs is NULL");
+  if (count > 0 && !probs) return fail(ctx, SID_EINVAL, "probs is NULL");
   if (dtype != SID_F32 && dtype != SID_F64) return fail(ctx, SID_EINVAL, "unknown dtype");
-  // validate every problem before launching anything
+  sh->assign((size_t)count, Shape{});
   for (int64_t b = 0; b < count; ++b) {
     const sid_problem& q = probs[b];
-    Shape sh;
     const std::string at = "problem " + std::to_string(b) + ": ";
     if (!q.A) return fail(ctx, SID_EINVAL, at + "A is NULL");
     if (q.lda < q.N) return fail(ctx, SID_EINVAL, at + "lda < N");
-    const sid_status vs = validate(ctx, q.N, q.n, &q.params, &sh);
+    const sid_status vs = validate(ctx, q.N, q.n, &q.params, &(*sh)[(size_t)b]);
     if (vs != SID_OK) return fail(ctx, vs, at + ctx->err);
     if (q.P && q.ldp < q.params.k) return fail(ctx, SID_EINVAL, at + "ldp < k");
     if (q.AJ && q.ldaj < skeleton_rows(&q.params, q.N))
@@ -1627,11 +1703,171 @@ sid_status sid_compress_batched(sid_ctx* ctx, const sid_problem* probs, int64_t 
     if (q.params.coarse && q.params.coarse->ctx != ctx)
       return fail(ctx, SID_EINVAL, at + "row set belongs to another context");
   }
-  SID_NEED_DEVICE(ctx);
-  SID_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
-  const int nstreams = count < SID_BATCH_STREAMS ? (int)count : SID_BATCH_STREAMS;
+  return SID_OK;
+}
+
+bool batch_persistent_ok(const sid_ctx* ctx, const sid_problem* probs, int64_t count,
+                         sid_dtype dtype, const std::vector<Shape>& sh) {
+  if (dtype != SID_F32 || count < 1 || ctx->sketch_pairs) return false;
+  const int prec = probs[0].params.prec;
+  if (prec != SID_SK_BF16 && prec != SID_SK_BF16X2 && prec != SID_SK_FP8E4M3) return false;
+  const bool single = sh[0].single;
+  for (int64_t b = 0; b < count; ++b) {
+    const sid_problem& q = probs[b];
+    const Shape& s = sh[(size_t)b];
+    if (q.params.prec != prec || s.single != single || q.params.coarse ||
+        q.params.select != SID_SEL_GAUSS || q.params.refine || q.params.mode == SID_COARSE_SKELETON)
+      return false;
+    if (!sid::fused_bf16_batch_supported(s.n, (int)s.lq, (int)s.l, q.lda, q.A)) return false;
+    // the single-matrix call takes the same pass, so the bits agree
+    if (plan_sketch(ctx, dtype, q.lda, q.A, prec, s, false, single) != SketchPath::FUSED_BF16)
+      return false;
+  }
+  return true;
+}
+
+// the plan of this batch: found among the context's plans, or built (not
+// under graph capture: it allocates)
+sid_status batch_plan(sid_ctx* ctx, const sid_problem* probs, int64_t count,
+                      const std::vector<Shape>& sh, BatchPlan** out) {
+  const int prec = probs[0].params.prec;
+  const int dmode = prec == SID_SK_BF16X2 ? sid::FB_BF16X2 : prec == SID_SK_FP8E4M3 ? sid::FB_FP8
+                                                                                  : sid::FB_BF16;
+  const bool wanty = sh[0].single;
+  std::vector<BatchSig> sig((size_t)count);
+  for (int64_t b = 0; b < count; ++b) {
+    const Shape& s = sh[(size_t)b];
+    sig[(size_t)b] = BatchSig{probs[b].A, s.N, s.n, probs[b].lda, s.lq, s.l, probs[b].params.seed};
+  }
+  for (size_t i = 0; i < ctx->plans.size(); ++i) {
+    BatchPlan* pl = ctx->plans[i];
+    if (pl->dmode == dmode && pl->wanty == wanty && pl->sig == sig) {
+      ctx->plans.erase(ctx->plans.begin() + (long)i);
+      ctx->plans.push_back(pl);
+      *out = pl;
+      return SID_OK;
+    }
+  }
+  if (capturing(ctx->stream))
+    return fail(ctx, SID_ESTATE,
+                "batched call under graph capture: build its plan first (sid_reserve_batched, or "
+                "an eager call with the same problems)");
+  // queue order: the most work per share first
+  std::vector<int64_t> rpw((size_t)count), nsh((size_t)count);
+  std::vector<int> order((size_t)count);
+  for (int64_t b = 0; b < count; ++b) {
+    nsh[(size_t)b] = sid::fused_bf16_grid(sh[(size_t)b].N, ctx->num_cu, &rpw[(size_t)b]);
+    order[(size_t)b] = (int)b;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return rpw[(size_t)x] * sh[(size_t)x].n > rpw[(size_t)y] * sh[(size_t)y].n;
+  });
+  auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+  size_t bytes = up(sizeof(sid::FbBatchEntry) * (size_t)count) + 256;
+  for (int64_t b = 0; b < count; ++b) {
+    const Shape& s = sh[(size_t)b];
+    bytes += up(sizeof(float) * (size_t)(nsh[(size_t)b] * s.lq * s.n)) +
+             up(sizeof(double) * (size_t)(s.lq * s.n));
+    if (wanty)
+      bytes += up(sizeof(float) * (size_t)(s.n * s.l)) + up(sizeof(uint16_t) * 128 * 512) +
+               up(sizeof(float) * (size_t)(s.N * s.l));
+  }
+  if (ctx->plans.size() >= SID_BATCH_PLANS) {
+    // the oldest plan goes; nothing queued may still read it
+    SID_CHECK(hipStreamSynchronize(ctx->stream), "batched: plan eviction");
+    for (sid_ctx* c : ctx->children) SID_CHECK(hipStreamSynchronize(c->stream), "batched: plan eviction");
+    BatchPlan* old = ctx->plans.front();
+    ctx->plans.erase(ctx->plans.begin());
+    if (old->dev) (void)hipFree(old->dev);
+    delete old;
+  }
+  BatchPlan* pl = new (std::nothrow) BatchPlan();
+  if (!pl) return fail(ctx, SID_ENOMEM, "batched: plan");
+  if (hipMalloc(&pl->dev, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    delete pl;
+    return fail(ctx, SID_ENOMEM, "batched: device memory for the batch (" + std::to_string(bytes) +
+                                     " bytes)");
+  }
+  pl->bytes = bytes;
+  pl->sig = sig;
+  pl->dmode = dmode;
+  pl->wanty = wanty;
+  unsigned char* cur = (unsigned char*)pl->dev;
+  auto take = [&](size_t b) {
+    unsigned char* r = cur;
+    cur += up(b);
+    return r;
+  };
+  pl->d_tab = (sid::FbBatchEntry*)take(sizeof(sid::FbBatchEntry) * (size_t)count);
+  pl->d_queue = (unsigned int*)take(256);
+  pl->W.assign((size_t)count, nullptr);
+  pl->Y.assign((size_t)count, nullptr);
+  pl->omega.assign((size_t)count, nullptr);
+  std::vector<sid::FbBatchEntry> tab((size_t)count);
+  int64_t share0 = 0;
+  for (int64_t qpos = 0; qpos < count; ++qpos) {
+    const int b = order[(size_t)qpos];
+    const Shape& s = sh[(size_t)b];
+    sid::FbBatchEntry& e = tab[(size_t)qpos];
+    e.A = (const float*)probs[b].A;
+    e.lda = probs[b].lda;
+    e.N = s.N;
+    e.n = (int)s.n;
+    e.lq = (int)s.lq;
+    e.l = (int)s.l;
+    e.pad_ = 0;
+    e.seed = probs[b].params.seed;
+    e.rows_per_wg = rpw[(size_t)b];
+    e.share0 = share0;
+    e.nshares = nsh[(size_t)b];
+    share0 += e.nshares;
+    e.part = (float*)take(sizeof(float) * (size_t)(e.nshares * s.lq * s.n));
+    e.W = (double*)take(sizeof(double) * (size_t)(s.lq * s.n));
+    e.omega = nullptr;
+    e.omT = nullptr;
+    e.Y = nullptr;
+    if (wanty) {
+      e.omega = (float*)take(sizeof(float) * (size_t)(s.n * s.l));
+      e.omT = (__bf16*)take(sizeof(uint16_t) * 128 * 512);
+      e.Y = (float*)take(sizeof(float) * (size_t)(s.N * s.l));
+    }
+    pl->W[(size_t)b] = e.W;
+    pl->Y[(size_t)b] = e.Y;
+    pl->omega[(size_t)b] = e.omega;
+    if (s.n > pl->max_n) pl->max_n = (int)s.n;
+    if (s.lq * s.n > pl->max_lqn) pl->max_lqn = s.lq * s.n;
+  }
+  pl->nshares = share0;
+  hipError_t e = hipMemcpyAsync(pl->d_tab, tab.data(), sizeof(sid::FbBatchEntry) * (size_t)count,
+                                hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    (void)hipFree(pl->dev);
+    delete pl;
+    return hip_fail(ctx, e, "batched: table upload");
+  }
+  ctx->plans.push_back(pl);
+  *out = pl;
+  return SID_OK;
+}
+
+sid_status compress_batch(sid_ctx* ctx, const sid_problem* probs, int64_t count, sid_dtype dtype,
+                          const std::vector<Shape>& sh, int nstreams_want) {
+  const bool persistent = batch_persistent_ok(ctx, probs, count, dtype, sh);
+  BatchPlan* plan = nullptr;
+  if (persistent) {
+    const sid_status ps = batch_plan(ctx, probs, count, sh, &plan);
+    if (ps != SID_OK) return ps;
+  }
+  const int nstreams = count < nstreams_want ? (int)count : nstreams_want;
   sid_status st = ensure_children(ctx, nstreams);
   if (st != SID_OK) return st;
+  if (persistent)
+    SID_CHECK(sid::launch_sketch_fused_bf16_batch(ctx->stream, plan->dmode, plan->wanty, plan->d_tab,
+                                                  (int)count, plan->nshares, plan->max_n,
+                                                  plan->max_lqn, plan->d_queue, ctx->num_cu),
+              "batched sketch pass");
   SID_CHECK(hipEventRecord(ctx->fork, ctx->stream), "batched: fork event");
   for (int c = 0; c < nstreams; ++c)
     SID_CHECK(hipStreamWaitEvent(ctx->children[c]->stream, ctx->fork, 0), "batched: fork wait");
@@ -1639,17 +1875,31 @@ sid_status sid_compress_batched(sid_ctx* ctx, const sid_problem* probs, int64_t 
   for (int64_t b = 0; b < count && result == SID_OK; ++b) {
     const sid_problem& q = probs[b];
     sid_ctx* c = ctx->children[(size_t)(b % nstreams)];
-    // row sets are bound to the parent context; the child reads the same
-    // device array
-    sid_params pr = q.params;
-    sid_rowset tmp;
-    if (pr.coarse) {
-      tmp = *pr.coarse;
-      tmp.ctx = c;
-      pr.coarse = &tmp;
+    if (persistent) {
+      Work w;
+      result = reserve(c, sh[(size_t)b], &w, false);
+      if (result != SID_OK) {
+        fail(ctx, result, "problem " + std::to_string(b) + ": workspace");
+        break;
+      }
+      w.W = plan->W[(size_t)b];
+      w.Y = plan->Y[(size_t)b];
+      w.omega = plan->omega[(size_t)b];
+      result = factor(c, &q.params, sh[(size_t)b], w, dtype, q.A, q.lda, q.J, q.P, q.ldp, q.AJ,
+                      q.ldaj, q.err, q.k_eff);
+    } else {
+      // row sets are bound to the parent context; the child reads the same
+      // device array
+      sid_params pr = q.params;
+      sid_rowset tmp;
+      if (pr.coarse) {
+        tmp = *pr.coarse;
+        tmp.ctx = c;
+        pr.coarse = &tmp;
+      }
+      result = sid_compress(c, q.A, dtype, q.N, q.n, q.lda, &pr, q.J, q.P, q.ldp, q.AJ, q.ldaj,
+                            q.err, q.k_eff);
     }
-    result = sid_compress(c, q.A, dtype, q.N, q.n, q.lda, &pr, q.J, q.P, q.ldp, q.AJ, q.ldaj,
-                          q.err, q.k_eff);
     if (result != SID_OK) fail(ctx, result, "problem " + std::to_string(b) + ": " + c->err);
   }
   // join (also after a failure, so the context's stream never runs ahead)
@@ -1660,6 +1910,160 @@ sid_status sid_compress_batched(sid_ctx* ctx, const sid_problem* probs, int64_t 
   return result;
 }
 
+// autotuner cache key: architecture, sketch form, mode, batch size and the
+// widest problem (chunks of 128 columns), bucketed
+std::string tune_key(const sid_ctx* ctx, const sid_problem* probs, int64_t count,
+                     const std::vector<Shape>& sh) {
+  hipDeviceProp_t prop{};
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) arch = prop.gcnArchName;
+  const size_t colon = arch.find(':');
+  if (colon != std::string::npos) arch = arch.substr(0, colon);
+  int64_t maxn = 0;
+  for (const Shape& s : sh) maxn = s.n > maxn ? s.n : maxn;
+  int cb = 0;
+  while ((int64_t)1 << (cb + 1) <= count) ++cb;
+  return arch + " prec=" + std::to_string(probs[0].params.prec) +
+         " single=" + std::to_string(sh[0].single ? 1 : 0) + " count=2^" + std::to_string(cb) +
+         " nch=" + std::to_string((maxn + 127) / 128);
+}
+
+// the cache file (SID_TUNE_CACHE): one "key<TAB>streams" line per entry
+int tune_lookup(sid_ctx* ctx, const std::string& key) {
+  for (const auto& kv : ctx->tuned)
+    if (kv.first == key) return kv.second;
+  const char* path = std::getenv("SID_TUNE_CACHE");
+  if (!path || !path[0]) return 0;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return 0;
+  char line[512];
+  int found = 0;
+  while (std::fgets(line, sizeof line, f)) {
+    std::string ln(line);
+    const size_t tab = ln.find('\t');
+    if (tab == std::string::npos) continue;
+    if (ln.substr(0, tab) == key) found = std::atoi(ln.c_str() + tab + 1);
+  }
+  std::fclose(f);
+  if (found >= 1 && found <= SID_BATCH_STREAMS_MAX) {
+    ctx->tuned.emplace_back(key, found);
+    return found;
+  }
+  return 0;
+}
+}  // namespace
+
+sid_status sid_compress_batched(sid_ctx* ctx, const sid_problem* probs, int64_t count,
+                                sid_dtype dtype) {
+  if (!ctx) return SID_EINVAL;
+  std::vector<Shape> sh;
+  const sid_status vs = validate_batch(ctx, probs, count, dtype, &sh);
+  if (vs != SID_OK) return vs;
+  if (count == 0) return SID_OK;
+  SID_NEED_DEVICE(ctx);
+  SID_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+  // A captured batched call (the persistent launch plus per-problem work on
+  // the child streams, each with a side stream) ended the process inside the
+  // runtime's end of capture, for eight problems as for 64, while single
+  // sid_compress captures replay correctly; no mistake in this sequence has
+  // been found, so batched calls are refused under capture.
+  if (capturing(ctx->stream))
+    return fail(ctx, SID_ESTATE, "sid_compress_batched cannot be captured in a HIP graph");
+  return compress_batch(ctx, probs, count, dtype, sh, ctx->batch_streams);
+}
+
+sid_status sid_reserve_batched(sid_ctx* ctx, const sid_problem* probs, int64_t count,
+                               sid_dtype dtype, int tune) {
+  if (!ctx) return SID_EINVAL;
+  std::vector<Shape> sh;
+  const sid_status vs = validate_batch(ctx, probs, count, dtype, &sh);
+  if (vs != SID_OK) return vs;
+  if (count == 0) return SID_OK;
+  SID_NEED_DEVICE(ctx);
+  SID_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+  if (capturing(ctx->stream)) return fail(ctx, SID_ESTATE, "sid_reserve_batched under graph capture");
+  const bool persistent = batch_persistent_ok(ctx, probs, count, dtype, sh);
+  if (persistent) {
+    BatchPlan* plan = nullptr;
+    const sid_status ps = batch_plan(ctx, probs, count, sh, &plan);
+    if (ps != SID_OK) return ps;
+  }
+  sid_status st = ensure_children(ctx, SID_BATCH_STREAMS_MAX);
+  if (st != SID_OK) return st;
+  // every child may take any problem (the stream count can change)
+  for (sid_ctx* c : ctx->children)
+    for (int64_t b = 0; b < count; ++b) {
+      const sid_problem& q = probs[b];
+      if (persistent) {
+        Work w;
+        if (reserve(c, sh[(size_t)b], &w, false) != SID_OK) return fail(ctx, SID_ENOMEM, "batched: workspace");
+        if (sh[(size_t)b].single && !c->side) {
+          SID_CHECK(hipStreamCreate(&c->side), "side stream");
+          SID_CHECK(hipEventCreateWithFlags(&c->side_fork, hipEventDisableTiming), "side event");
+          SID_CHECK(hipEventCreateWithFlags(&c->side_join, hipEventDisableTiming), "side event");
+        }
+      } else {
+        sid_params pr = q.params;
+        sid_rowset tmp;
+        if (pr.coarse) {
+          tmp = *pr.coarse;
+          tmp.ctx = c;
+          pr.coarse = &tmp;
+        }
+        const sid_status rs = sid_reserve(c, q.N, q.n, &pr);
+        if (rs != SID_OK) return fail(ctx, rs, "problem " + std::to_string(b) + ": " + c->err);
+      }
+    }
+  // the autotuner: the number of child streams of the factorization phase,
+  // per (architecture, sketch form, mode, batch size, width) bucket -- from
+  // the context's cache, the cache file, or (tune != 0) timed here on the
+  // batch itself (every candidate computes the same results)
+  const std::string key = tune_key(ctx, probs, count, sh);
+  int best = tune ? 0 : tune_lookup(ctx, key);
+  if (tune) {
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    SID_CHECK(hipEventCreate(&t0), "autotune event");
+    SID_CHECK(hipEventCreate(&t1), "autotune event");
+    float best_ms = 0.0f;
+    const int cands[] = {1, 2, 4, 8};
+    sid_status rs = SID_OK;
+    for (int rep = 0; rep < 2 && rs == SID_OK; ++rep)
+      for (int cs : cands) {
+        if (hipEventRecord(t0, ctx->stream) != hipSuccess) { rs = SID_EDEVICE; break; }
+        rs = compress_batch(ctx, probs, count, dtype, sh, cs);
+        if (rs != SID_OK) break;
+        float ms = 0.0f;
+        if (hipEventRecord(t1, ctx->stream) != hipSuccess || hipEventSynchronize(t1) != hipSuccess ||
+            hipEventElapsedTime(&ms, t0, t1) != hipSuccess) {
+          rs = SID_EDEVICE;
+          break;
+        }
+        if (rep == 1 && (best == 0 || ms < best_ms)) {  // the first round warms up
+          best = cs;
+          best_ms = ms;
+        }
+      }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (rs != SID_OK) return rs == SID_EDEVICE ? fail(ctx, rs, "autotune timing failed") : rs;
+    bool have = false;
+    for (auto& kv : ctx->tuned)
+      if (kv.first == key) { kv.second = best; have = true; }
+    if (!have) ctx->tuned.emplace_back(key, best);
+    const char* path = std::getenv("SID_TUNE_CACHE");
+    if (path && path[0]) {
+      FILE* f = std::fopen(path, "a");
+      if (f) {
+        std::fprintf(f, "%s\t%d\n", key.c_str(), best);
+        std::fclose(f);
+      }
+    }
+  }
+  if (best >= 1) ctx->batch_streams = best;
+  return SID_OK;
+}
+
+int sid_batch_streams(const sid_ctx* ctx) { return ctx ? ctx->batch_streams : -1; }
 
 // ---------------------------------------------------------------------------
 // Single-pass ID with interpolation (Alg. 6): the structured mesh, its

@@ -170,11 +170,14 @@ __global__ __launch_bounds__(256) void k_pack_p(const float* __restrict__ P, int
 constexpr int IM_WAVES = 4;
 constexpr int IM_ROWS = 64 * IM_WAVES;
 
-template <int KS, bool ERR, bool VEC>
+// IDENT: the plain ID, Ahat = AJ P (eq. (ID)): row i of B is row i of AJ,
+// read straight from the column-major N x kk skeleton `acjt` (ld ldaj); the
+// operator tables are not used (t.N only).
+template <int KS, bool ERR, bool VEC, bool IDENT = false>
 __global__ __launch_bounds__(64 * IM_WAVES, 2) void k_interp_mfma(
     InterpDev t, const float* __restrict__ acjt, const bf16x8_t* __restrict__ pb, int64_t n,
     float* __restrict__ out, int64_t ldo, const float* __restrict__ A, int64_t lda,
-    double* __restrict__ part) {
+    double* __restrict__ part, int64_t ldaj = 0, int kk = 0) {
   constexpr int KP = 16 * KS;
   constexpr int NT = 64 * IM_WAVES;
   constexpr int PCH = KS * 128;             // packed operands per 32-column block
@@ -197,24 +200,35 @@ __global__ __launch_bounds__(64 * IM_WAVES, 2) void k_interp_mfma(
     const int64_t i = r0 + 32 * rt + lc;
     uint32_t idx[8];
     float w[8];
-    stencil8<float>(t, (uint32_t)(i < N ? i : N - 1), idx, w);
+    if constexpr (!IDENT) stencil8<float>(t, (uint32_t)(i < N ? i : N - 1), idx, w);
     const float live = i < N ? 1.0f : 0.0f;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) w[q] *= live;
+    for (int q = 0; q < 8; ++q) w[q] = IDENT ? live : w[q] * live;
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       float acc[8];
 #pragma unroll
       for (int e = 0; e < 8; ++e) acc[e] = 0.0f;
+      if constexpr (IDENT) {
+        // eight skeleton columns of one row: lanes 0-31 and 32-63 each read
+        // 32 consecutive rows (128 bytes) of one column per load
+        const int64_t ic = i < N ? i : N - 1;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const f32x4_t* src =
-            reinterpret_cast<const f32x4_t*>(acjt + (size_t)idx[q] * KP + 16 * ks + 8 * hl);
-        const f32x4_t v0 = src[0], v1 = src[1];
+        for (int e = 0; e < 8; ++e) {
+          const int c = 16 * ks + 8 * hl + e;
+          acc[e] = c < kk ? w[0] * acjt[(int64_t)c * ldaj + ic] : 0.0f;
+        }
+      } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          acc[e] = fmaf(w[q], v0[e], acc[e]);
-          acc[4 + e] = fmaf(w[q], v1[e], acc[4 + e]);
+        for (int q = 0; q < 8; ++q) {
+          const f32x4_t* src =
+              reinterpret_cast<const f32x4_t*>(acjt + (size_t)idx[q] * KP + 16 * ks + 8 * hl);
+          const f32x4_t v0 = src[0], v1 = src[1];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            acc[e] = fmaf(w[q], v0[e], acc[e]);
+            acc[4 + e] = fmaf(w[q], v1[e], acc[4 + e]);
+          }
         }
       }
 #pragma unroll
@@ -476,35 +490,38 @@ __global__ __launch_bounds__(256) void k_interp_norms_reduce(const double* __res
   }
 }
 
-template <int KS, bool ERR>
+template <int KS, bool ERR, bool IDENT = false>
 hipError_t launch_mfma_vec(hipStream_t st, bool vec, const InterpDev& t, const float* acjt,
                            const bf16x8_t* pb, int64_t n, float* out, int64_t ldo, const float* A,
-                           int64_t lda, double* part) {
+                           int64_t lda, double* part, int64_t ldaj = 0, int kk = 0) {
   const dim3 grid((unsigned)interp_mfma_blocks(t.N));
   if (vec)
-    hipLaunchKernelGGL((k_interp_mfma<KS, ERR, true>), grid, dim3(64 * IM_WAVES), 0, st, t, acjt,
-                       pb, n, out, ldo, A, lda, part);
+    hipLaunchKernelGGL((k_interp_mfma<KS, ERR, true, IDENT>), grid, dim3(64 * IM_WAVES), 0, st, t,
+                       acjt, pb, n, out, ldo, A, lda, part, ldaj, kk);
   else
-    hipLaunchKernelGGL((k_interp_mfma<KS, ERR, false>), grid, dim3(64 * IM_WAVES), 0, st, t,
-                       acjt, pb, n, out, ldo, A, lda, part);
+    hipLaunchKernelGGL((k_interp_mfma<KS, ERR, false, IDENT>), grid, dim3(64 * IM_WAVES), 0, st, t,
+                       acjt, pb, n, out, ldo, A, lda, part, ldaj, kk);
   return hipGetLastError();
 }
 
-template <bool ERR>
+template <bool ERR, bool IDENT = false>
 hipError_t launch_mfma_ks(hipStream_t st, int ks, bool vec, const InterpDev& t, const float* acjt,
                           const bf16x8_t* pb, int64_t n, float* out, int64_t ldo, const float* A,
-                          int64_t lda, double* part) {
+                          int64_t lda, double* part, int64_t ldaj = 0, int kk = 0) {
+#define SID_MKS(K_) \
+  return launch_mfma_vec<K_, ERR, IDENT>(st, vec, t, acjt, pb, n, out, ldo, A, lda, part, ldaj, kk)
   switch (ks) {
-    case 1: return launch_mfma_vec<1, ERR>(st, vec, t, acjt, pb, n, out, ldo, A, lda, part);
-    case 2: return launch_mfma_vec<2, ERR>(st, vec, t, acjt, pb, n, out, ldo, A, lda, part);
-    case 3: return launch_mfma_vec<3, ERR>(st, vec, t, acjt, pb, n, out, ldo, A, lda, part);
-    case 4: return launch_mfma_vec<4, ERR>(st, vec, t, acjt, pb, n, out, ldo, A, lda, part);
-    case 5: return launch_mfma_vec<5, ERR>(st, vec, t, acjt, pb, n, out, ldo, A, lda, part);
-    case 6: return launch_mfma_vec<6, ERR>(st, vec, t, acjt, pb, n, out, ldo, A, lda, part);
-    case 7: return launch_mfma_vec<7, ERR>(st, vec, t, acjt, pb, n, out, ldo, A, lda, part);
-    case 8: return launch_mfma_vec<8, ERR>(st, vec, t, acjt, pb, n, out, ldo, A, lda, part);
+    case 1: SID_MKS(1);
+    case 2: SID_MKS(2);
+    case 3: SID_MKS(3);
+    case 4: SID_MKS(4);
+    case 5: SID_MKS(5);
+    case 6: SID_MKS(6);
+    case 7: SID_MKS(7);
+    case 8: SID_MKS(8);
     default: return hipErrorInvalidValue;
   }
+#undef SID_MKS
 }
 
 }  // namespace
@@ -574,6 +591,39 @@ hipError_t launch_interp_mfma(hipStream_t st, const InterpDev& t, int kp, const 
   }
   const bool vec = ldo % 4 == 0 && ((uintptr_t)out & 15) == 0;
   return launch_mfma_ks<false>(st, ks, vec, t, acjt, p, n, out, ldo, nullptr, 0, nullptr);
+}
+
+hipError_t launch_pack_p(hipStream_t st, const float* P, int64_t ldp, int k, int kp, int64_t n,
+                         void* pb) {
+  if (kp % 16 != 0 || kp < 16 || kp > 128 || k > kp) return hipErrorInvalidValue;
+  const int ks_n = kp / 16;
+  const int64_t total = ((n + 31) / 32) * ks_n * 128;
+  hipLaunchKernelGGL(k_pack_p, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, P, ldp, k,
+                     n, ks_n, total, (bf16x8_t*)pb);
+  return hipGetLastError();
+}
+
+hipError_t launch_id_mfma(hipStream_t st, const float* AJ, int64_t ldaj, int64_t N, int k, int kp,
+                          const void* pb, int64_t n, float* out, int64_t ldo, const float* A,
+                          int64_t lda, double* part, int64_t part_cap, double* out4) {
+  if (kp % 16 != 0 || kp < 16 || kp > 128 || k > kp || N < 1) return hipErrorInvalidValue;
+  InterpDev t{};
+  t.N = N;
+  const int ks = kp / 16;
+  const bf16x8_t* p = (const bf16x8_t*)pb;
+  if (A) {
+    if (interp_mfma_blocks(N) > part_cap) return hipErrorInvalidValue;
+    const bool vec = lda % 4 == 0 && ((uintptr_t)A & 15) == 0;
+    hipError_t e = launch_mfma_ks<true, true>(st, ks, vec, t, AJ, p, n, nullptr, 0, A, lda, part,
+                                              ldaj, k);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_interp_norms_reduce, dim3(1), dim3(256), 0, st, part,
+                       interp_mfma_blocks(N), out4);
+    return hipGetLastError();
+  }
+  const bool vec = ldo % 4 == 0 && ((uintptr_t)out & 15) == 0;
+  return launch_mfma_ks<false, true>(st, ks, vec, t, AJ, p, n, out, ldo, nullptr, 0, nullptr, ldaj,
+                                     k);
 }
 
 }  // namespace sid

@@ -43,4 +43,14 @@ hipError_t launch_interp_mfma(hipStream_t st, const InterpDev& t, int kp, const 
                               const void* pb, int64_t n, float* out, int64_t ldo, const float* A,
                               int64_t lda, double* part, int64_t part_cap, double* out4);
 
+// The plain ID on the same kernel (eq. (ID)): Ahat = AJ P with AJ the
+// column-major N x k skeleton (FP32, k <= kp <= 128), P packed by
+// launch_pack_p into pb (interp_pb_bytes(n, kp)); out, or the error
+// partials and out4 as above.
+hipError_t launch_pack_p(hipStream_t st, const float* P, int64_t ldp, int k, int kp, int64_t n,
+                         void* pb);
+hipError_t launch_id_mfma(hipStream_t st, const float* AJ, int64_t ldaj, int64_t N, int k, int kp,
+                          const void* pb, int64_t n, float* out, int64_t ldo, const float* A,
+                          int64_t lda, double* part, int64_t part_cap, double* out4);
+
 }  // namespace sid

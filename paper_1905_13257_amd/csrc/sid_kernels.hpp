@@ -5,6 +5,26 @@
 
 namespace sid {
 
+// One matrix of the batched sketch pass (device table, one entry per matrix
+// in queue order).  A: FP32 column-major N x n (lda); its shares are the row
+// ranges of rows_per_wg rows the single-matrix launch gives its workgroups;
+// share0: the queue index of its first share.  Outputs: part (nshares x lq
+// x n FP32 partials), W (lq x n FP64, column-major), and with Y: omega (n x l
+// FP32 values, row-major), omT (128 x 512 bfloat16), Y (N x l FP32,
+// row-major).
+struct FbBatchEntry {
+  const float* A;
+  int64_t lda, N;
+  int n, lq, l, pad_;
+  uint64_t seed;
+  int64_t rows_per_wg, share0, nshares;
+  float* part;
+  double* W;
+  float* omega;
+  __bf16* omT;
+  float* Y;
+};
+
 hipError_t launch_fill_gaussian(hipStream_t st, uint64_t seed, uint32_t stream, int64_t major0,
                                 int64_t nmajor, int64_t minor0, int64_t nminor, float* out);
 hipError_t launch_sketch(hipStream_t st, int prec, bool a_is_f64, const void* A, int64_t lda,
@@ -71,6 +91,14 @@ hipError_t launch_sketch_v2(hipStream_t st, int dmode, const float* A, int64_t l
                             int n, int lq, int l, uint64_t seed, const float* omega, __bf16* omT,
                             int num_cu, float* part, double* W, float* Y, int64_t* nparts_out);
 int64_t fused_bf16_grid(int64_t N, int num_cu, int64_t* rows_per_wg);
+bool fused_bf16_batch_supported(int64_t n, int lq, int l, int64_t lda, const void* A);
+// the batched sketch pass over d_tab (count entries, nshares shares in all;
+// max_n / max_lqn: the largest n and lq n of the batch): Omega and Omega^T
+// (with Y), the persistent pass, the FP64 sums of the partials
+hipError_t launch_sketch_fused_bf16_batch(hipStream_t st, int dmode, bool want_y,
+                                          const FbBatchEntry* d_tab, int count, int64_t nshares,
+                                          int max_n, int64_t max_lqn, unsigned int* queue,
+                                          int num_cu);
 hipError_t launch_sketch_fused_bf16(hipStream_t st, int dmode, const float* A, int64_t lda,
                                     int64_t N, int n, int lq, int l, uint64_t seed,
                                     const float* omega, __bf16* omT, int num_cu, float* part,

@@ -61,6 +61,10 @@ constexpr int FB_MTR = 8;                    // W row tiles kept in registers
 
 __device__ __forceinline__ __bf16 to_bf16(float f) { return (__bf16)f; }
 
+__global__ void k_zero_queue(unsigned int* q) {
+  if (threadIdx.x == 0) *q = 0u;
+}
+
 // panel row of operand slot (ks, g, i)
 __device__ __forceinline__ int slot_row(int ks, int g, int i) {
   return 32 * ks + (i < 4 ? 4 * g + i : 16 + 4 * g + (i - 4));
@@ -169,12 +173,19 @@ __device__ __forceinline__ void gen_psi(__bf16* __restrict__ s_psi, uint64_t see
 // chunk loop unrolls into straight-line code with no merges of accumulators.
 // ROWS: W = Psi(:, S) A(S, :) over the coarse row list `rows` (N = |S|; two
 // pass only, no Y); the list of each panel is staged in LDS.
-template <int DM, bool WANTY, int MT, int LT, int NCH, bool ROWS = false>
-__global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
+//
+// fused_tile: one workgroup's share, rows [r0, r1) of A, whose W partial
+// (FP32, column-major lq x n) goes to dst.  nch (<= NCH) chunks are
+// processed: chunks past the last column are skipped whole, so the template
+// counts only bound the register state and the results do not depend on
+// them.  The single-matrix kernel runs one share per workgroup; the batched
+// kernel runs shares of many matrices from a work queue.
+template <int DM, bool WANTY, int MT, int LT, int NCH, bool ROWS>
+__device__ __forceinline__ void fused_tile(
     const float* __restrict__ A, int64_t lda, int64_t N, int n, int lq, int l, uint64_t seed,
     const __bf16* __restrict__ omT /* LT*16 x FB_NPAD, k contiguous, zero padded */,
-    int64_t rows_per_wg, float* __restrict__ part /* grid x lq x n */, float* __restrict__ Y,
-    const int64_t* __restrict__ rows = nullptr) {
+    const int64_t r0, int64_t r1, const int nch, float* __restrict__ dst, float* __restrict__ Y,
+    const int64_t* __restrict__ rows) {
   static_assert(!(ROWS && WANTY), "a row list sketches W only");
   static_assert(FB_WAVES % LT == 0 || LT % FB_WAVES == 0, "Y tiles split evenly over the waves");
   static_assert(4 * LT >= FB_WAVES && NCH <= FB_NCH, "tile counts");
@@ -195,9 +206,6 @@ __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;  // MFMA lane coordinates
-  const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
-  int64_t r1 = r0 + rows_per_wg;
-  if (r1 > N) r1 = N;
   const int lq4 = (lq + 3) >> 2;
   const int gen_items = FB_PR * lq4;
   // wave 0 stages the row list of the panel starting at q0 (clamped to r1)
@@ -257,6 +265,7 @@ __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
     const __bf16* psi = s_psi[pb];
 #pragma unroll
     for (int j = 0; j < NCH; ++j) {
+      if (j >= nch) break;  // uniform over the workgroup
       const bool col_ok = col_w + FB_CHUNK * j < n;
       if constexpr (TAIL) {
         if constexpr (ROWS) load_chunk_rows(A, lda, n, col_w + FB_CHUNK * j, s_rows[pb], rows, lg, v);
@@ -317,12 +326,12 @@ __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
       __builtin_amdgcn_sched_barrier(0);
       if constexpr (!TAIL) {
         if constexpr (ROWS) {
-          if (j + 1 < NCH)
+          if (j + 1 < nch)
             load_chunk_rows(A, lda, n, col_w + FB_CHUNK * (j + 1), s_rows[pb], FB_PR, lg, v);
           else if (pn < r1f)
             load_chunk_rows(A, lda, n, col_w, s_rows[pb ^ 1], FB_PR, lg, v);
         } else {
-          if (j + 1 < NCH) {
+          if (j + 1 < nch) {
             load_chunk(A + p0, lda, n, col_w + FB_CHUNK * (j + 1), lg, v);
           } else if (pn < r1f) {
             load_chunk(A + pn, lda, n, col_w, lg, v);
@@ -358,7 +367,7 @@ __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
       }
       // (5) slice j of Psi(:, next panel) (the buffer the previous panel used)
       if (!TAIL && pn < r1)
-        gen_psi<FP8>(s_psi[pb ^ 1], seed, pn, r1, lq, gen_items * j / NCH, gen_items * (j + 1) / NCH,
+        gen_psi<FP8>(s_psi[pb ^ 1], seed, pn, r1, lq, gen_items * j / nch, gen_items * (j + 1) / nch,
                      tid, ROWS ? s_rows[pb ^ 1] : nullptr);
       lds_barrier();  // chunk buffer complete
       // (6) Y(panel, this wave's tiles) += A(panel, chunk) Omega(chunk, :)
@@ -403,8 +412,7 @@ __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
   for (; p0 < r1f; p0 += FB_PR, pb ^= 1) panel(std::false_type{}, p0, pb);
   if (p0 < r1) panel(std::true_type{}, p0, pb);
 
-  // W partial of this workgroup (FP32, column-major lq x n)
-  float* dst = part + (int64_t)blockIdx.x * lq * n;
+  // W partial of this share (FP32, column-major lq x n)
 #pragma unroll
   for (int j = 0; j < NCH; ++j) {
     const int col = FB_CHUNK * j + col_w;
@@ -425,6 +433,149 @@ __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
       }
     }
   }
+}
+
+template <int DM, bool WANTY, int MT, int LT, int NCH, bool ROWS = false>
+__global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
+    const float* __restrict__ A, int64_t lda, int64_t N, int n, int lq, int l, uint64_t seed,
+    const __bf16* __restrict__ omT, int64_t rows_per_wg, float* __restrict__ part /* grid x lq x n */,
+    float* __restrict__ Y, const int64_t* __restrict__ rows = nullptr) {
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
+  const int64_t r1 = r0 + rows_per_wg < N ? r0 + rows_per_wg : N;
+  fused_tile<DM, WANTY, MT, LT, NCH, ROWS>(A, lda, N, n, lq, l, seed, omT, r0, r1,
+                                           (n + FB_CHUNK - 1) / FB_CHUNK,
+                                           part + (int64_t)blockIdx.x * lq * n, Y, rows);
+}
+
+// ---------------------------------------------------------------------------
+// Batched sketch pass: many independent matrices in one persistent launch.
+// The shares of all matrices (each matrix cut into the row ranges the
+// single-matrix launch gives its workgroups, so every partial, and with the
+// same fixed-order sum W and Y, is bit for bit that of a single-matrix call)
+// form one work queue, in the order of the table (the host puts the
+// matrices with the most work per share first).  A workgroup takes the next
+// share with one atomic increment and runs it with the largest register and
+// LDS layout (MT = 10, LT = 8, NCH = 4); a share of a smaller matrix skips
+// the chunks past its columns, and the row tiles of W and column tiles of Y
+// past its sizes only compute zeros that are never stored.  Every workgroup
+// leaves when the queue is empty.
+// ---------------------------------------------------------------------------
+template <int DM, bool WANTY>
+__global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16_batch(
+    const FbBatchEntry* __restrict__ tab, int count, int64_t nshares,
+    unsigned int* __restrict__ queue) {
+  __shared__ int64_t s_share;
+  for (;;) {
+    lds_barrier();  // the previous share is done with the LDS (and s_share)
+    if (threadIdx.x == 0) s_share = (int64_t)atomicAdd(queue, 1u);
+    lds_barrier();
+    const int64_t t = s_share;
+    if (t >= nshares) break;
+    // the matrix: the last entry whose first share is <= t
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tab[mid].share0 <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const FbBatchEntry& e = tab[lo];
+    const int64_t i = t - e.share0;
+    const int64_t r0 = i * e.rows_per_wg;
+    const int64_t r1 = r0 + e.rows_per_wg < e.N ? r0 + e.rows_per_wg : e.N;
+    fused_tile<DM, WANTY, 10, 8, FB_NCH, false>(e.A, e.lda, e.N, e.n, e.lq, e.l, e.seed, e.omT, r0,
+                                                r1, (e.n + FB_CHUNK - 1) / FB_CHUNK,
+                                                e.part + i * e.lq * e.n, WANTY ? e.Y : nullptr,
+                                                nullptr);
+  }
+}
+
+// Omega's values (n x l, row-major: the single-matrix layout) and Omega^T in
+// bfloat16 with 128 zero-padded rows (the batched kernel's Y tiles) for every
+// matrix (blockIdx.y); the queue counter is cleared by block (0, 0).  Both
+// come from the same generator call, so they are the values the
+// single-matrix path forms.
+__global__ void k_batch_omega(const FbBatchEntry* __restrict__ tab, int dm_fp8,
+                              unsigned int* __restrict__ queue) {
+  const FbBatchEntry& e = tab[blockIdx.y];
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *queue = 0u;
+  const int ng = (e.l + 3) >> 2;
+  for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < e.n * ng; w += gridDim.x * blockDim.x) {
+    const int k = w / ng, g = w - k * ng;
+    float z[4];
+    gauss4(e.seed, 0u, (uint64_t)k, (uint32_t)g, z);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = 4 * g + u;
+      if (c < e.l) {
+        e.omega[(int64_t)k * e.l + c] = z[u];
+        e.omT[c * FB_NPAD + k] = to_bf16(dm_fp8 ? e4m3_value(z[u]) : z[u]);
+      }
+    }
+  }
+  // the zero padding of Omega^T: columns k >= n of rows c < l, rows l .. 127
+  for (int e2 = blockIdx.x * blockDim.x + threadIdx.x; e2 < 128 * FB_NPAD; e2 += gridDim.x * blockDim.x) {
+    const int c = e2 / FB_NPAD, k = e2 - c * FB_NPAD;
+    if (c >= e.l || k >= e.n) e.omT[e2] = to_bf16(0.0f);
+  }
+}
+
+// W of every matrix (blockIdx.y): the fixed-order FP64 sum of its partials,
+// the order of k_reduce_partials_f32
+__global__ void k_reduce_partials_batch(const FbBatchEntry* __restrict__ tab) {
+  const FbBatchEntry& m = tab[blockIdx.y];
+  const int64_t count = (int64_t)m.lq * m.n;
+  const int64_t nparts = m.nshares;
+  const float* __restrict__ part = m.part;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int64_t g = 0;
+    for (; g + 8 <= nparts; g += 8)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s[u] += (double)part[(g + u) * count + e];
+    for (; g < nparts; ++g) s[0] += (double)part[g * count + e];
+    m.W[e] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+  }
+}
+
+bool fused_bf16_batch_supported(int64_t n, int lq, int l, int64_t lda, const void* A) {
+  return n >= 1 && n <= FB_NPAD && lq <= 160 && l <= 128 && (lda % 4) == 0 &&
+         ((uintptr_t)A % 16) == 0;
+}
+
+hipError_t launch_sketch_fused_bf16_batch(hipStream_t st, int dmode, bool want_y,
+                                          const FbBatchEntry* d_tab, int count, int64_t nshares,
+                                          int max_n, int64_t max_lqn, unsigned int* queue,
+                                          int num_cu) {
+  if (count < 1) return hipSuccess;
+  if (want_y) {
+    const unsigned bx = (unsigned)((max_n * 32 + 255) / 256 < 64 ? (max_n * 32 + 255) / 256 : 64);
+    hipLaunchKernelGGL(k_batch_omega, dim3(bx < 1 ? 1 : bx, (unsigned)count), dim3(256), 0, st, d_tab,
+                       dmode == FB_FP8 ? 1 : 0, queue);
+  } else {
+    hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(64), 0, st, queue);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t g64 = nshares < num_cu ? nshares : num_cu;
+  const dim3 grid((unsigned)(g64 < 1 ? 1 : g64)), block(FB_THREADS);
+#define SID_FB_BATCH(DM_, WY_) \
+  hipLaunchKernelGGL((k_sketch_fused_bf16_batch<DM_, WY_>), grid, block, 0, st, d_tab, count, nshares, queue)
+  if (dmode == FB_BF16X2) {
+    if (want_y) SID_FB_BATCH(FB_BF16X2, true); else SID_FB_BATCH(FB_BF16X2, false);
+  } else if (dmode == FB_FP8) {
+    if (want_y) SID_FB_BATCH(FB_FP8, true); else SID_FB_BATCH(FB_FP8, false);
+  } else {
+    if (want_y) SID_FB_BATCH(FB_BF16, true); else SID_FB_BATCH(FB_BF16, false);
+  }
+#undef SID_FB_BATCH
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int64_t bx = (max_lqn + 255) / 256;
+  if (bx > 256) bx = 256;
+  hipLaunchKernelGGL(k_reduce_partials_batch, dim3((unsigned)bx, (unsigned)count), dim3(256), 0, st,
+                     d_tab);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

@@ -218,6 +218,32 @@ def dct_lowrank(N: int, n: int, sigma: np.ndarray, seed: int,
     return out
 
 
+def batched_shapes(count: int = 64, seed: int = 4004) -> list:
+    """Shapes of the uneven batch: (N, n, k) per matrix with N log-uniform in
+    [16384, 1048576], n uniform in [64, 512] and k uniform in [8, 64]."""
+    rng = np.random.default_rng(seed)
+    N = np.rint(np.exp(rng.uniform(math.log(16384), math.log(1048576), count))).astype(np.int64)
+    n = rng.integers(64, 513, count)
+    k = rng.integers(8, 65, count)
+    return [(int(a), int(b), int(c)) for a, b, c in zip(N, n, k)]
+
+
+def batched_matrix(N: int, n: int, seed: int, device="cpu", ld_multiple: int = 4) -> torch.Tensor:
+    """One matrix of the uneven batch: sigma_j = j^-1.5 (j = 1 .. n) on
+    DCT-based orthonormal factors (``dct_lowrank``), FP32, column-major with
+    the leading dimension rounded up to ``ld_multiple`` (16-byte aligned
+    columns)."""
+    sigma = np.arange(1, n + 1, dtype=np.float64) ** -1.5
+    A = dct_lowrank(N, n, sigma, seed, dtype=torch.float32, device=device)
+    ld = (N + ld_multiple - 1) // ld_multiple * ld_multiple
+    if ld == N:
+        return A
+    store = torch.zeros((n, ld), dtype=torch.float32, device=A.device)
+    out = store[:, :N].T
+    out.copy_(A)
+    return out
+
+
 def coarse_rows_every_other(nx: int, ny: int, nz: int, ncomp: int = 3) -> np.ndarray:
     """Row indices of the grid points with even (i, j, k) in every component
     (2x sub-sampling per dimension, "direct injection"), sorted ascending."""

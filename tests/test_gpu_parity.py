@@ -264,6 +264,21 @@ def test_reconstruct_matches_oracle(sid, oracle_mod):
         out = sid.reconstruct(to_gpu(AJ64, dt), to_gpu(P64, dt))
         ref = oracle_mod.reconstruct(AJ64, P64)
         np.testing.assert_allclose(host(out), ref, rtol=0, atol=tol * np.abs(ref).max())
+    # FP32 on the matrix cores (k <= 128): per entry within 2^-15 of
+    # |AJ| |P| of the product of the FP32 values; ragged shapes around the
+    # 64-row, 32-column and 16-k tiles, k = 128, a leading dimension > N
+    for (N, k, n, ld) in [(1000, 13, 70, 1000), (4099, 128, 33, 4100), (64, 1, 1, 64),
+                          (257, 17, 95, 300), (70001, 100, 500, 70004)]:
+        AJ32 = rng.standard_normal((N, k)).astype(np.float32)
+        P32 = rng.standard_normal((k, n)).astype(np.float32)
+        AJd = to_gpu(AJ32.astype(np.float64), torch.float32, ld=ld)
+        out = sid.reconstruct(AJd, to_gpu(P32.astype(np.float64), torch.float32))
+        A64, P64b = AJ32.astype(np.float64), P32.astype(np.float64)
+        ref = A64 @ P64b
+        bound = 2.0 ** -15 * (np.abs(A64) @ np.abs(P64b)) + 1e-30
+        err = np.abs(host(out).astype(np.float64) - ref)
+        say("reconstruct mfma", N, k, n, "max err / bound", (err / bound).max())
+        assert np.all(err <= bound), (N, k, n)
 
 
 
