@@ -434,10 +434,12 @@ sid_status sid_interp_error_norms(sid_ctx *ctx, const sid_interp *ip, const void
  * long as H = A_p^T G with that same G (the Y_i^T Q B term takes up the
  * difference between G and A_p Omega), so `prec` matters as it does for the
  * ID's sketch, not through that amplification.  H and each block row of B
- * (H_i - B^T M_i) R_i^-1 are one pass over the rows each (this library's
- * kernels); B Omega_i, B B^T and V run as rocBLAS GEMMs.  Limits: l <=
+ * (H_i - B^T M_i) R_i^-1 are one pass over the rows each; B Omega_i and
+ * B B^T are split reductions over the rows (fixed summation order) and V is
+ * formed row by row in the output type.  Limits: l <=
  * min(n, 256), l % block == 0, block <= 64.  Synchronizes the stream once
- * per block (the stop test).  Workspace about (2 l + 2.5 block) N doubles.
+ * per block (the stop test).  Workspace about (2 l + 1.5 block) N doubles
+ * plus 64 MiB.
  */
 typedef struct {
     int64_t k;              /* target rank >= 1                       */

@@ -57,9 +57,7 @@ def build(verbose: bool = False) -> str:
             sys.stderr.write(f"---- {s}\n{r.stdout}{r.stderr}")
         raise RuntimeError("hipcc failed building libsid.so: " + ", ".join(s for s, _ in failed))
     tmp = LIB + ".tmp"
-    # rocBLAS for the plain N-length GEMMs of SBR-SVD
-    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs,
-           "-L/opt/rocm/lib", "-lrocblas"]
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -14,7 +14,6 @@
 #include <vector>
 
 #include "../../include/sid.h"
-#include <rocblas/rocblas.h>
 
 #include "sid_adaptive.hpp"
 #include "sid_apply.hpp"
@@ -59,7 +58,7 @@ enum Slot {
   WS_OMEGA, WS_PART, WS_W, WS_WR, WS_NRM, WS_PIV, WS_R, WS_Q, WS_KEFF, WS_STATS, WS_PD,
   WS_ERR, WS_Y, WS_M, WS_MPR, WS_WJ, WS_PIVM, WS_RM, WS_QM, WS_RKM, WS_C, WS_T, WS_MIX,
   WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COOP, WS_SYNC, WS_R11, WS_FITPART, WS_YTMP, WS_REF_W, WS_REF_WJ, WS_OMP, WS_A8, WS_IACJT, WS_IPB, WS_IB, WS_IPART, WS_AZ, WS_AE2, WS_APART, WS_SV_H, WS_SV_B, WS_SV_Q, WS_SV_OM32,
-  WS_SV_OM, WS_SV_SMALL, WS_SV_WP, WS_SV_OMN, WS_COUNT
+  WS_SV_OM, WS_SV_SMALL, WS_SV_WP, WS_SV_TSP, WS_COUNT
 };
 
 struct Buf {
@@ -127,8 +126,6 @@ struct sid_ctx {
   // runs on a side stream while mgsqr of W runs on the main one
   hipStream_t side = nullptr;
   hipEvent_t side_fork = nullptr, side_join = nullptr;
-  // library GEMMs of SBR-SVD (created on first use)
-  rocblas_handle blas = nullptr;
   // batched calls on the persistent sketch pass: the plans of the last few
   // problem sets (newest last) and the number of child streams of the
   // factorization phase (set by the autotuner)
@@ -578,7 +575,6 @@ sid_status sid_destroy(sid_ctx* ctx) {
     if (pl->dev) (void)hipFree(pl->dev);
     delete pl;
   }
-  if (ctx->blas) (void)rocblas_destroy_handle(ctx->blas);
   if (ctx->fork) (void)hipEventDestroy(ctx->fork);
   for (Buf& b : ctx->ws)
     if (b.p) (void)hipFree(b.p);
@@ -992,7 +988,10 @@ static sid_status refine_pass(sid_ctx* ctx, const void* A, sid_dtype dtype, int6
     if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
       coop_launch = false;
   }
-  if (sid::cpqr_wg_supported(l, n_))
+  if (l <= 96 && sid::cpqr_wgl_supported(l, n_) && !sid::cpqr_wg_supported(l, n_))
+    SID_CHECK(sid::launch_cpqr_wgl(st, Wp, l, l, n_, k, 0.0, w.piv, w.R, w.Q, w.keff, w.stats, Jf),
+              "mgsqr of W' in the order J");
+  else if (sid::cpqr_wg_supported(l, n_))
     SID_CHECK(sid::launch_cpqr_wg(st, Wp, l, l, n_, k, 0.0, w.piv, w.R, w.Q, w.keff, w.stats, Jf),
               "mgsqr of W' in the order J");
   else if (sid::cpqr_coop_supported(l, n_))
@@ -1042,7 +1041,14 @@ static sid_status factor(sid_ctx* ctx, const sid_params* p, const Shape& sh, con
   // general kernels use context scratch, so two of the same kind must not
   // run at once)
   auto kind = [](int m, int nc) {
-    return sid::cpqr_wg_supported(m, nc) ? 0 : (sid::cpqr_coop_supported(m, nc) ? 1 : 2);
+    // 0: one workgroup, residual in registers; 3: one workgroup, part of it
+    // in LDS (up to 96 rows: beyond, its LDS traffic per step costs more than
+    // the cooperative kernel's device-wide barrier; measured at 120 x 500);
+    // 1: several workgroups; 2: the general kernel
+    return sid::cpqr_wg_supported(m, nc)                 ? 0
+           : (m <= 96 && sid::cpqr_wgl_supported(m, nc)) ? 3
+           : sid::cpqr_coop_supported(m, nc)             ? 1
+                                                         : 2;
   };
   const int w_kind = kind(l, n_);
   // a cooperative launch cannot be recorded into a graph: under capture the
@@ -1055,7 +1061,7 @@ static sid_status factor(sid_ctx* ctx, const sid_params* p, const Shape& sh, con
       coop_launch = false;
   }
   const int m_kind = sh.single ? kind(lz, l) : 0;
-  const bool overlap = sh.single && (m_kind == 0 || m_kind != w_kind);
+  const bool overlap = sh.single && !(m_kind == w_kind && (m_kind == 1 || m_kind == 2));
   const double rcond = p->sp_rcond > 0.0 ? p->sp_rcond : default_rcond(sh.prec);
   if (sh.single) {
     // (5a) single pass, independent of the pivots: M = W(0:lz, :) Omega,
@@ -1077,7 +1083,11 @@ static sid_status factor(sid_ctx* ctx, const sid_params* p, const Shape& sh, con
     if (q > 0)
       SID_CHECK(sid::launch_gemm64(ms, q, l, n_, w.W + lz, lq, 0, w.om64, l, 1, w.Mpr, q),
                 "Mpr = Wpr Omega");
-    if (m_kind == 0)
+    if (m_kind == 3)
+      SID_CHECK(sid::launch_cpqr_wgl(ms, w.M, lz, lz, l, l, rcond, w.pivM, w.RM, w.QM, w.rkM,
+                                     w.statsM),
+                "pivoted QR of M");
+    else if (m_kind == 0)
       SID_CHECK(sid::launch_cpqr_wg(ms, w.M, lz, lz, l, l, rcond, w.pivM, w.RM, w.QM, w.rkM,
                                     w.statsM),
                 "pivoted QR of M");
@@ -1092,7 +1102,11 @@ static sid_status factor(sid_ctx* ctx, const sid_params* p, const Shape& sh, con
     if (overlap) SID_CHECK(hipEventRecord(ctx->side_join, ctx->side), "side join");
   }
   // (2) mgsqr on the selection rows of W
-  if (w_kind == 0)
+  if (w_kind == 3)
+    SID_CHECK(sid::launch_cpqr_wgl(st, w.W, lq, l, n_, k, p->rank_tol, w.piv, w.R, w.Q, w.keff,
+                                   w.stats),
+              "pivoted QR");
+  else if (w_kind == 0)
     SID_CHECK(sid::launch_cpqr_wg(st, w.W, lq, l, n_, k, p->rank_tol, w.piv, w.R, w.Q, w.keff,
                                   w.stats),
               "pivoted QR");
@@ -2399,14 +2413,6 @@ void sid_svd_params_init(sid_svd_params* p, int64_t k) {
   p->prec = SID_SK_F64;
 }
 
-#define SID_BLAS(expr, where)                                                         \
-  do {                                                                               \
-    rocblas_status b_ = (expr);                                                      \
-    if (b_ != rocblas_status_success)                                                \
-      return fail(ctx, SID_EDEVICE, std::string(where) + ": rocBLAS status " +        \
-                                        std::to_string((int)b_));                    \
-  } while (0)
-
 }  // extern "C"
 
 namespace {
@@ -2431,19 +2437,6 @@ sid_status svd_check(sid_ctx* ctx, const sid_svd_params* sp, int64_t N, int64_t 
   gp->probe_rows = 0;
   Shape sh;
   return validate(ctx, N, n, gp, &sh);
-}
-
-sid_status svd_blas(sid_ctx* ctx) {
-  if (!ctx->blas) {
-    if (rocblas_create_handle(&ctx->blas) != rocblas_status_success) {
-      ctx->blas = nullptr;
-      return fail(ctx, SID_EDEVICE, "rocblas_create_handle failed");
-    }
-  }
-  if (rocblas_set_stream(ctx->blas, ctx->stream) != rocblas_status_success ||
-      rocblas_set_pointer_mode(ctx->blas, rocblas_pointer_mode_host) != rocblas_status_success)
-    return fail(ctx, SID_EDEVICE, "rocBLAS handle set-up failed");
-  return SID_OK;
 }
 
 // H (ld N) = A W^T, or H += A W^T (accumulate), for the ncols columns of A
@@ -2473,7 +2466,11 @@ sid_status svd_blocks(sid_ctx* ctx, const sid_svd_params* sp, sid_dtype dtype, i
   double* Q = (double*)ws(ctx, WS_SV_Q, d * (size_t)n * (size_t)l);
   float* om32 = (float*)ws(ctx, WS_SV_OM32, sizeof(float) * (size_t)N * (size_t)b);
   double* om = (double*)ws(ctx, WS_SV_OM, d * (size_t)N * (size_t)b);
-  double* omn = (double*)ws(ctx, WS_SV_OMN, d * (size_t)N * (size_t)b);
+  // partials of the tall-skinny products (blocks of at most 128 x 128)
+  int64_t rpb = 0;
+  const int64_t nbt = sid::tsmm_blocks(N, ctx->num_cu, &rpb);
+  // (at least 2 x 128 x 128: it also holds (U~ S^-1)^T, up to 256 x 128)
+  double* tsp = (double*)ws(ctx, WS_SV_TSP, d * (size_t)(nbt < 2 ? 2 : nbt) * 128 * 128);
   // small buffers: Y0, Y (n x b), C, Z (l x b), R, Rt (b x b), Gram, Vj (l x l),
   // Us, Uv (l x k), mindiag (+ Jacobi's sweep count), Uout (n x k), Jacobi
   // work (l' x l', l' = l rounded up to even) and rotation records
@@ -2482,7 +2479,7 @@ sid_status svd_blocks(sid_ctx* ctx, const sid_svd_params* sp, sid_dtype dtype, i
                         2 * (size_t)(l * l) + 2 * (size_t)(l * k) + 4 + (size_t)(n * k) + le * le +
                         sid::jacobi_rot_doubles((int)l);
   double* sm = (double*)ws(ctx, WS_SV_SMALL, d * nsmall);
-  if (!Bt || !Q || !om32 || !om || !omn || !sm) return SID_ENOMEM;
+  if (!Bt || !Q || !om32 || !om || !tsp || !sm) return SID_ENOMEM;
   double* Y0 = sm;
   double* Y = Y0 + n * b;
   double* C = Y + n * b;
@@ -2497,57 +2494,63 @@ sid_status svd_blocks(sid_ctx* ctx, const sid_svd_params* sp, sid_dtype dtype, i
   double* Uo = mind + 4;
   double* Jw = Uo + n * k;  // Jacobi's working matrix when l > 128
   double* Jrot = Jw + le * le;  // Jacobi's rotation records
-  sid_status st = svd_blas(ctx);
-  if (st != SID_OK) return st;
-  rocblas_handle bh = ctx->blas;
-  const double one = 1.0, zero = 0.0, mone = -1.0;
-  double gnorm = 0.0;
-  SID_BLAS(rocblas_dnrm2(bh, (int)(l * n), W, 1, &gnorm), "||G||");
+  // X^T Y over the N rows in blocks of at most 128 x 128 (the product
+  // kernel's limit); C gets alpha X^T Y + beta C
+  auto tsmm = [&](const double* X, int p, const double* Y, int64_t ysr, int64_t ysc, int q,
+                  double alpha, double beta, double* C, int64_t ldc) -> hipError_t {
+    for (int a0 = 0; a0 < p; a0 += 128)
+      for (int c0 = 0; c0 < q; c0 += 128) {
+        const hipError_t e = sid::launch_tsmm(hs, X + (int64_t)N * a0, N, Y + ysc * c0, ysr, ysc, N,
+                                              p - a0 < 128 ? p - a0 : 128,
+                                              q - c0 < 128 ? q - c0 : 128, alpha, beta,
+                                              C + a0 + ldc * c0, ldc, tsp, ctx->num_cu);
+        if (e != hipSuccess) return e;
+      }
+    return hipSuccess;
+  };
+  // ||G||_F^2 for the stop test (read with the first block's pivot test)
+  SID_CHECK(sid::launch_sumsq(hs, W, l * n, mind + 3), "||G||^2");
+  double gnorm = -1.0;
   // (2) the blocks
   int64_t j = 0;
   const int64_t s = l / b;
   for (int64_t i = 0; i < s; ++i) {
     // Omega_i = Psi(i b .. i b + b, :)^T, rounded as the sketch read it,
-    // stored b x N (ld b)
+    // stored b x N (ld b): row r of Omega_i is b contiguous values
     SID_CHECK(sid::launch_fill_gaussian(hs, sp->seed, 1u, 0, N, i * b, b, om32), "Omega_i");
     SID_CHECK(sid::launch_omega_values(hs, sp->prec, om32, N * b, om), "Omega_i values");
     // Y_i = G_i - Q (B Omega_i), G_i = W(i b .. i b + b, :)^T
     SID_CHECK(sid::launch_transpose64(hs, W + i * b, b, n, l, Y0, n), "G_i");
     if (j > 0) {
-      // B Omega_i (j x b): Omega_i transposed to N x b, then a split-K GEMM
-      SID_CHECK(sid::launch_transpose64(hs, om, b, N, b, omn, N), "Omega_i (N x b)");
-      SID_BLAS(rocblas_dgemm(bh, rocblas_operation_transpose, rocblas_operation_none, (int)j,
-                             (int)b, (int)N, &one, Bt, (int)N, omn, (int)N, &zero, C, (int)l),
-               "B Omega_i");
-      SID_BLAS(rocblas_dgemm(bh, rocblas_operation_none, rocblas_operation_none, (int)n, (int)b,
-                             (int)j, &mone, Q, (int)n, C, (int)l, &one, Y0, (int)n),
-               "G_i - Q B Omega_i");
+      SID_CHECK(tsmm(Bt, (int)j, om, b, 1, (int)b, 1.0, 0.0, C, l), "B Omega_i");
+      SID_CHECK(sid::launch_gemm64_ab(hs, (int)n, (int)b, (int)j, Q, n, 0, C, l, 0, -1.0, 1.0, Y0,
+                                      n),
+                "G_i - Q B Omega_i");
     }
     // (Q_i, R_i) = qr(Y_i), then against Q once more: (Q_i, R~_i)
     SID_CHECK(hipMemcpyAsync(Y, Y0, d * (size_t)(n * b), hipMemcpyDeviceToDevice, hs), "copy Y");
     SID_CHECK(sid::launch_small_qr(hs, Y, (int)n, (int)b, R), "qr(Y_i)");
     if (j > 0) {
-      SID_BLAS(rocblas_dgemm(bh, rocblas_operation_transpose, rocblas_operation_none, (int)j,
-                             (int)b, (int)n, &one, Q, (int)n, Y, (int)n, &zero, Z, (int)l),
-               "Q^T Q_i");
-      SID_BLAS(rocblas_dgemm(bh, rocblas_operation_none, rocblas_operation_none, (int)n, (int)b,
-                             (int)j, &mone, Q, (int)n, Z, (int)l, &one, Y, (int)n),
-               "Q_i - Q Q^T Q_i");
+      SID_CHECK(sid::launch_gemm64_ab(hs, (int)j, (int)b, (int)n, Q, n, 1, Y, n, 0, 1.0, 0.0, Z, l),
+                "Q^T Q_i");
+      SID_CHECK(sid::launch_gemm64_ab(hs, (int)n, (int)b, (int)j, Q, n, 0, Z, l, 0, -1.0, 1.0, Y, n),
+                "Q_i - Q Q^T Q_i");
     }
     SID_CHECK(sid::launch_small_qr(hs, Y, (int)n, (int)b, Rt), "qr again");
     SID_CHECK(sid::launch_trmul(hs, Rt, R, (int)b, mind), "R_i = R~_i R_i");
-    double mdiag = 0.0;
-    SID_CHECK(hipMemcpyAsync(&mdiag, mind, d, hipMemcpyDeviceToHost, hs), "min diag");
+    double mh[4] = {0.0, 0.0, 0.0, 0.0};
+    SID_CHECK(hipMemcpyAsync(mh, mind, 4 * d, hipMemcpyDeviceToHost, hs), "min diag");
     SID_CHECK(hipStreamSynchronize(hs), "synchronize");
+    const double mdiag = mh[0];
+    if (gnorm < 0.0) gnorm = std::sqrt(mh[3]);
     // A_p Omega of rank below l: the blocks so far span it (stop)
     if (!(mdiag > 1e-12 * gnorm)) break;
     // B_i^T = (H_i - B^T (Q^T Y_i + B Omega_i)) R_i^-1 into the next b columns
     // of B^T, one pass over the rows
     double* Bi = Bt + j * N;
     if (j > 0)
-      SID_BLAS(rocblas_dgemm(bh, rocblas_operation_transpose, rocblas_operation_none, (int)j,
-                             (int)b, (int)n, &one, Q, (int)n, Y0, (int)n, &one, C, (int)l),
-               "Q^T Y_i + B Omega_i");
+      SID_CHECK(sid::launch_gemm64_ab(hs, (int)j, (int)b, (int)n, Q, n, 1, Y0, n, 0, 1.0, 1.0, C, l),
+                "Q^T Y_i + B Omega_i");
     SID_CHECK(sid::launch_block_update(hs, Bt, N, (int)j, H + i * b * N, C, l, R, (int)b, Bi),
               "B_i^T = (H_i - B^T M_i) R_i^-1");
     SID_CHECK(hipMemcpyAsync(Q + j * n, Y, d * (size_t)(n * b), hipMemcpyDeviceToDevice, hs),
@@ -2565,20 +2568,24 @@ sid_status svd_blocks(sid_ctx* ctx, const sid_svd_params* sp, sid_dtype dtype, i
   }
   // (3) B = U~ S V^T from B B^T = U~ S^2 U~^T (Jacobi); V_k = B^T U~_k S_k^-1,
   // U_k = Q U~_k
-  SID_BLAS(rocblas_dgemm(bh, rocblas_operation_transpose, rocblas_operation_none, (int)j, (int)j,
-                         (int)N, &one, Bt, (int)N, Bt, (int)N, &zero, Gm, (int)j),
-           "B B^T");
+  SID_CHECK(tsmm(Bt, (int)j, Bt, 1, N, (int)j, 1.0, 0.0, Gm, j), "B B^T");
   SID_CHECK(sid::launch_jacobi(hs, Gm, (int)j, Vj, Jw, Jrot, (int*)(mind + 2)),
             "eigen-decomposition of B B^T");
   SID_CHECK(sid::launch_eig_sort(hs, Gm, (int)j, Vj, (int)k, S, Us, Uv), "sort");
-  // (columns of Us, Uv past j are zero)
-  SID_BLAS(rocblas_dgemm(bh, rocblas_operation_none, rocblas_operation_none, (int)N, (int)k,
-                         (int)j, &one, Bt, (int)N, Us, (int)j, &zero, H, (int)N),
-           "V = B^T U~ S^-1");
-  SID_BLAS(rocblas_dgemm(bh, rocblas_operation_none, rocblas_operation_none, (int)n, (int)k,
-                         (int)j, &one, Q, (int)n, Uv, (int)j, &zero, Uo, (int)n),
-           "U = Q U~");
-  SID_CHECK(sid::launch_convert(hs, H, true, N, k, N, V, dtype == SID_F64, ldv), "V out");
+  // (columns of Us, Uv past j are zero); V in the output type, in slabs of
+  // at most 128 columns
+  for (int64_t c0 = 0; c0 < k; c0 += 128) {
+    const int kc = (int)(k - c0 < 128 ? k - c0 : 128);
+    const size_t es = dtype == SID_F64 ? d : sizeof(float);
+    // this slab of U~ S^-1 row by row (stride 128) in the products' scratch
+    SID_CHECK(sid::launch_transpose64(hs, Us + j * c0, j, kc, j, tsp, 128), "(U~ S^-1)^T");
+    SID_CHECK(sid::launch_tall_mul(hs, Bt, N, N, (int)j, tsp, 128, kc,
+                                   (unsigned char*)V + es * (size_t)(ldv * c0), dtype == SID_F64,
+                                   ldv),
+              "V = B^T U~ S^-1");
+  }
+  SID_CHECK(sid::launch_gemm64_ab(hs, (int)n, (int)k, (int)j, Q, n, 0, Uv, j, 0, 1.0, 0.0, Uo, n),
+            "U = Q U~");
   SID_CHECK(sid::launch_convert(hs, Uo, true, n, k, n, U, dtype == SID_F64, ldu), "U out");
   SID_CHECK(hipStreamSynchronize(hs), "synchronize");
   return SID_OK;

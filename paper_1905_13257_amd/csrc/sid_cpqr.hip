@@ -414,6 +414,182 @@ hipError_t launch_cpqr_wg(hipStream_t st, const double* X, int64_t ldx, int m, i
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// mgsqr in one workgroup for residuals too large for its registers alone
+// (e.g. W_sel of 120 x 500 FP64, 480 KB): 512 threads (two waves per SIMD),
+// one thread per column (up to 512 columns); each thread keeps the first RR
+// rows of its column in registers and the next CL_RL rows in LDS
+// (s_w[i][tid]: consecutive threads at consecutive addresses).  The steps are
+// those of k_cpqr_wg -- wave candidates, one barrier, every thread reduces
+// the 8 candidates, the pivot's thread writes q into LDS, one barrier, every
+// column is updated -- with no device-wide barrier and no global memory
+// round trip per step.
+// ---------------------------------------------------------------------------
+constexpr int CL_THREADS = 512;
+constexpr int CL_WAVES = CL_THREADS / 64;
+constexpr int CL_RL = 38;  // rows per thread in LDS: 38 x 8 B x 512 = 152 KiB
+
+template <int RR>
+__global__ __launch_bounds__(CL_THREADS) void k_cpqr_wgl(
+    const double* __restrict__ X, int64_t ldx, int m, int nc, int kmax, double rank_tol,
+    int64_t* __restrict__ piv, double* __restrict__ R, double* __restrict__ Q,
+    int64_t* __restrict__ keff, double* __restrict__ stats, const int64_t* __restrict__ forced) {
+  constexpr int QN = RR + CL_RL;  // rows covered
+  __shared__ double s_w[CL_RL][CL_THREADS];
+  __shared__ double s_q[2][QN];
+  __shared__ double s_wv[2][CL_WAVES];
+  __shared__ int s_wj[2][CL_WAVES];
+  __shared__ double s_sum[2][CL_WAVES];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int j = tid;
+  const bool mine = j < nc;
+  // rows m .. of q stay zero, so the loops below need no row guards (the
+  // matching entries of w are zero too)
+  for (int e = tid; e < 2 * QN; e += CL_THREADS) (&s_q[0][0])[e] = 0.0;
+
+  double w[RR];
+  double p0 = 0.0, p1 = 0.0;
+#pragma unroll
+  for (int i = 0; i < RR; ++i) {
+    w[i] = (mine && i < m) ? X[i + ldx * j] : 0.0;
+    if (i & 1) p1 = fma(w[i], w[i], p1);
+    else p0 = fma(w[i], w[i], p0);
+  }
+#pragma unroll 2
+  for (int i = 0; i < CL_RL; ++i) {
+    const int r = RR + i;
+    const double x = (mine && r < m) ? X[r + ldx * j] : 0.0;
+    s_w[i][tid] = x;
+    if (i & 1) p1 = fma(x, x, p1);
+    else p0 = fma(x, x, p0);
+  }
+  double nrm = p0 + p1;
+  const double tot_local = mine ? nrm : 0.0;
+  bool alive = mine;
+  double first = -1.0;
+  int k = 0;
+  for (; k < kmax; ++k) {
+    const int par = k & 1;
+    // 1. this wave's best live column (ties: smallest index; forced order:
+    //    the given column is the only candidate)
+    const bool cand = alive && (!forced || j == forced[k]);
+    double bv = cand ? nrm : -1.0;
+    int bj = cand ? j : 0x7fffffff;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) better(bv, bj, __shfl_xor(bv, o, 64), __shfl_xor(bj, o, 64));
+    if (lane == 0) { s_wv[par][wv] = bv; s_wj[par][wv] = bj; }
+    lds_barrier();
+    // 2. the winner, found by every thread from the wave candidates (the
+    //    same LDS words for every lane: broadcast reads)
+    bv = s_wv[par][0];
+    bj = s_wj[par][0];
+#pragma unroll
+    for (int u = 1; u < CL_WAVES; ++u) better(bv, bj, s_wv[par][u], s_wj[par][u]);
+    if (!(bv > 0.0)) break;
+    const double nu = sqrt(bv);
+    if (first < 0.0) first = nu;
+    else if (rank_tol > 0.0 && nu <= rank_tol * first) break;
+    const int p = bj;
+    // 3. the pivot column, normalized, into LDS
+    if (j == p) {
+      const double inv = 1.0 / nu;
+#pragma unroll
+      for (int i = 0; i < RR; ++i) {
+        s_q[par][i] = w[i] * inv;
+        w[i] = 0.0;
+      }
+      for (int i = 0; i < CL_RL; ++i) {
+        s_q[par][RR + i] = s_w[i][tid] * inv;
+        s_w[i][tid] = 0.0;
+      }
+      alive = false;
+      R[(int64_t)k * nc + j] = nu;
+      piv[k] = p;
+    }
+    lds_barrier();
+    for (int r = tid; r < m; r += CL_THREADS) Q[r + (int64_t)m * k] = s_q[par][r];
+    // 4. R(k, j) = q^T r_j, r_j -= R(k, j) q, new norm of r_j (q: LDS
+    //    broadcast reads; the LDS rows are read twice rather than held)
+    const double* qv = s_q[par];
+    double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+    for (int i = 0; i < RR; ++i) {
+      if (i & 1) d1 = fma(qv[i], w[i], d1);
+      else d0 = fma(qv[i], w[i], d0);
+    }
+#pragma unroll 2
+    for (int i = 0; i < CL_RL; ++i) {
+      if (i & 1) d1 = fma(qv[RR + i], s_w[i][tid], d1);
+      else d0 = fma(qv[RR + i], s_w[i][tid], d0);
+    }
+    const double d = d0 + d1;
+    asm volatile("" ::: "memory");  // q from LDS again below, not held in registers
+    if (alive) {
+      double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+      for (int i = 0; i < RR; ++i) {
+        w[i] = fma(-d, qv[i], w[i]);
+        if (i & 1) a1 = fma(w[i], w[i], a1);
+        else a0 = fma(w[i], w[i], a0);
+      }
+#pragma unroll 2
+      for (int i = 0; i < CL_RL; ++i) {
+        const double x = fma(-d, qv[RR + i], s_w[i][tid]);
+        s_w[i][tid] = x;
+        if (i & 1) a1 = fma(x, x, a1);
+        else a0 = fma(x, x, a0);
+      }
+      nrm = a0 + a1;
+      R[(int64_t)k * nc + j] = d;
+    } else {
+      nrm = 0.0;
+      if (mine && j != p) R[(int64_t)k * nc + j] = 0.0;
+    }
+  }
+
+  // statistics: final residual energy of live columns and ||X||_F^2
+  double a = alive ? nrm : 0.0, b = tot_local;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o, 64);
+    b += __shfl_xor(b, o, 64);
+  }
+  if (lane == 0) { s_sum[0][wv] = a; s_sum[1][wv] = b; }
+  __syncthreads();
+  if (tid == 0) {
+    double sa = 0.0, sb = 0.0;
+    for (int u = 0; u < CL_WAVES; ++u) { sa += s_sum[0][u]; sb += s_sum[1][u]; }
+    stats[0] = sa;
+    stats[1] = sb;
+    *keff = k;
+  }
+  for (int i = k + tid; i < kmax; i += CL_THREADS) piv[i] = -1;
+}
+
+constexpr int CL_RR_MAX = 96;
+
+bool cpqr_wgl_supported(int m, int nc) {
+  return nc >= 1 && nc <= CL_THREADS && m >= 1 && m <= CL_RR_MAX + CL_RL;
+}
+
+hipError_t launch_cpqr_wgl(hipStream_t st, const double* X, int64_t ldx, int m, int nc, int kmax,
+                           double rank_tol, int64_t* piv, double* R, double* Q, int64_t* keff,
+                           double* stats, const int64_t* forced) {
+  if (!cpqr_wgl_supported(m, nc)) return hipErrorInvalidValue;
+  const int rr = m - CL_RL;  // register rows per thread (may be <= 0)
+#define SID_CL(RR_)                                                                          \
+  hipLaunchKernelGGL((k_cpqr_wgl<RR_>), dim3(1), dim3(CL_THREADS), 0, st, X, ldx, m, nc, kmax, \
+                     rank_tol, piv, R, Q, keff, stats, forced)
+  if (rr <= 26) SID_CL(26);
+  else if (rr <= 42) SID_CL(42);
+  else if (rr <= 58) SID_CL(58);
+  else if (rr <= 74) SID_CL(74);
+  else if (rr <= 82) SID_CL(82);
+  else SID_CL(96);
+#undef SID_CL
+  return hipGetLastError();
+}
+
 // keff := -1 when a cooperative wait timed out (results invalid); the
 // context's sticky flag records it until the host reads it (sid_sync)
 __global__ void k_mark_failure(const unsigned int* fail, int64_t* keff, unsigned int* sticky) {

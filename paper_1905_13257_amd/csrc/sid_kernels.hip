@@ -404,7 +404,7 @@ __global__ void k_ratio_sqrt(const double* __restrict__ stats, double* __restric
 // ---------------------------------------------------------------------------
 __global__ void k_gemm64(int M, int Nn, int K, const double* __restrict__ A, int64_t lda, int tA,
                          const double* __restrict__ B, int64_t ldb, int tB, double* __restrict__ C,
-                         int64_t ldc) {
+                         int64_t ldc, double alpha, double beta) {
   __shared__ double sa[16][17], sb[16][17];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int row = blockIdx.x * 16 + tx;
@@ -428,7 +428,10 @@ __global__ void k_gemm64(int M, int Nn, int K, const double* __restrict__ A, int
     for (int t = 0; t < 16; ++t) acc = fma(sa[tx][t], sb[t][ty], acc);
     __syncthreads();
   }
-  if (row < M && col < Nn) C[row + ldc * col] = acc;
+  if (row < M && col < Nn) {
+    double* o = C + row + ldc * col;
+    *o = beta != 0.0 ? fma(alpha, acc, beta * *o) : (alpha == 1.0 ? acc : alpha * acc);
+  }
 }
 
 // gather columns: dst(:, t) = src(:, piv[t]) for t < keff, zero for keff <= t < kcap
@@ -772,7 +775,18 @@ hipError_t launch_omega_values(hipStream_t st, int prec, const float* z, int64_t
 hipError_t launch_gemm64(hipStream_t st, int M, int Nn, int K, const double* A, int64_t lda,
                          int tA, const double* B, int64_t ldb, int tB, double* C, int64_t ldc) {
   const dim3 grid((unsigned)((M + 15) / 16), (unsigned)((Nn + 15) / 16));
-  hipLaunchKernelGGL(k_gemm64, grid, dim3(256), 0, st, M, Nn, K, A, lda, tA, B, ldb, tB, C, ldc);
+  hipLaunchKernelGGL(k_gemm64, grid, dim3(256), 0, st, M, Nn, K, A, lda, tA, B, ldb, tB, C, ldc,
+                     1.0, 0.0);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm64_ab(hipStream_t st, int M, int Nn, int K, const double* A, int64_t lda,
+                            int tA, const double* B, int64_t ldb, int tB, double alpha, double beta,
+                            double* C, int64_t ldc) {
+  if (M <= 0 || Nn <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((M + 15) / 16), (unsigned)((Nn + 15) / 16));
+  hipLaunchKernelGGL(k_gemm64, grid, dim3(256), 0, st, M, Nn, K, A, lda, tA, B, ldb, tB, C, ldc,
+                     alpha, beta);
   return hipGetLastError();
 }
 

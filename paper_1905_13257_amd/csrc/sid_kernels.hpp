@@ -49,6 +49,10 @@ hipError_t launch_omega_values(hipStream_t st, int prec, const float* z, int64_t
 hipError_t launch_ratio_sqrt(hipStream_t st, const double* stats, double* out);
 hipError_t launch_gemm64(hipStream_t st, int M, int Nn, int K, const double* A, int64_t lda,
                          int tA, const double* B, int64_t ldb, int tB, double* C, int64_t ldc);
+// C = alpha op(A) op(B) + beta C (beta = 0: C is not read)
+hipError_t launch_gemm64_ab(hipStream_t st, int M, int Nn, int K, const double* A, int64_t lda,
+                            int tA, const double* B, int64_t ldb, int tB, double alpha, double beta,
+                            double* C, int64_t ldc);
 hipError_t launch_add_inplace(hipStream_t st, bool f64, void* y, const void* x, int64_t count,
                               int num_cu);
 hipError_t launch_gather_r11(hipStream_t st, const double* R, int nc, const int64_t* piv,
@@ -127,6 +131,12 @@ bool apply_t_bf16_supported(int k, int l);
 hipError_t launch_apply_t_bf16(hipStream_t st, const float* Y, int64_t N, int l, const double* Tm,
                                int k, void* AJ, bool aj_f64, int64_t ldaj, int num_cu);
 bool cpqr_wg_supported(int m, int nc);
+// one workgroup of 512 threads, part of the residual in LDS: nc <= 512,
+// m <= 134
+bool cpqr_wgl_supported(int m, int nc);
+hipError_t launch_cpqr_wgl(hipStream_t st, const double* X, int64_t ldx, int m, int nc, int kmax,
+                           double rank_tol, int64_t* piv, double* R, double* Q, int64_t* keff,
+                           double* stats, const int64_t* forced = nullptr);
 hipError_t launch_cpqr_wg(hipStream_t st, const double* X, int64_t ldx, int m, int nc, int kmax,
                           double rank_tol, int64_t* piv, double* R, double* Q, int64_t* keff,
                           double* stats, const int64_t* forced = nullptr);

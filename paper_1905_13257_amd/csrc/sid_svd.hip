@@ -564,4 +564,254 @@ hipError_t launch_transpose64(hipStream_t st, const double* src, int64_t rows, i
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Tall-skinny products over the N rows (SBR-SVD's B Omega_i and B B^T, Alg. 2
+// steps "B Omega_i" and the SVD of B): C = alpha X^T Y (+ beta C), X: N x p
+// column-major (ld ldx), Y: N x q with entry (r, c) at Y[r ysr + c ysc];
+// p, q <= 128.  Split over row ranges: a block stages 32 rows of X and Y in
+// LDS at a time and each thread accumulates an 8 x 8 tile of its range's
+// partial in FP64 registers (threads beyond the tiles take every G-th row of
+// the 32 and their tiles are summed in a fixed order at the end); a second
+// launch sums the blocks' partials in a fixed order.  HBM traffic: X and Y
+// once.
+// ---------------------------------------------------------------------------
+constexpr int TS_THREADS = 256;
+constexpr int TS_SUB = 32;
+// LDS layout of a staged slice: column c of row r at r * TS_LD + c + c / 8.
+// The gap after every 8 columns puts the 8-column groups that the lanes of a
+// wave read together (a lane reads 8 consecutive columns of one group) on
+// different banks; the row stride makes the staging writes (32 rows of one
+// column) conflict-free.
+constexpr int TS_LD = 145;
+__device__ __forceinline__ int ts_col(int c) { return c + (c >> 3); }
+
+__global__ __launch_bounds__(TS_THREADS) void k_tsmm_part(
+    const double* __restrict__ X, int64_t ldx, const double* __restrict__ Y, int64_t ysr,
+    int64_t ysc, int64_t N, int p, int q, int64_t rows_per_block, double* __restrict__ part) {
+  __shared__ double s_x[TS_SUB * TS_LD];
+  __shared__ double s_y[TS_SUB * TS_LD];
+  const int tid = threadIdx.x;
+  const int tq = (q + 7) / 8, nt = ((p + 7) / 8) * tq;
+  const int G = TS_THREADS / nt;  // >= 1: nt <= 256
+  const int tile = tid % nt, grp = tid / nt;
+  const bool active = grp < G;
+  const int ti = tile / tq, tj = tile - ti * tq;
+  double acc[8][8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) acc[a][b] = 0.0;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t r1 = r0 + rows_per_block < N ? r0 + rows_per_block : N;
+  // this thread's share of a 32-row slice (16 entries of X and of Y), loaded
+  // one slice ahead into registers so that the loads of the next slice are in
+  // flight while this one is multiplied.  Rows fastest for column-major X
+  // (and Y with ysr == 1): 256 contiguous bytes per column; columns fastest
+  // for row-contiguous Y.
+  constexpr int PER = TS_SUB * 128 / TS_THREADS;
+  double px[PER], py[PER];
+  auto gload = [&](int64_t s0) {
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int e = tid + TS_THREADS * t;
+      const int r = e % TS_SUB, c = e / TS_SUB;
+      const int64_t row = s0 + r;
+      px[t] = (row < r1 && c < p) ? X[row + ldx * c] : 0.0;
+      int ry, cy;
+      if (ysr == 1) { ry = r; cy = c; }
+      else { cy = e % 128; ry = e / 128; }
+      const int64_t rowy = s0 + ry;
+      py[t] = (rowy < r1 && cy < q) ? Y[rowy * ysr + cy * ysc] : 0.0;
+    }
+  };
+  if (r0 < r1) gload(r0);
+  for (int64_t s0 = r0; s0 < r1; s0 += TS_SUB) {
+    __syncthreads();  // the previous slice is consumed
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int e = tid + TS_THREADS * t;
+      const int r = e % TS_SUB, c = e / TS_SUB;
+      s_x[r * TS_LD + ts_col(c)] = px[t];
+      int ry, cy;
+      if (ysr == 1) { ry = r; cy = c; }
+      else { cy = e % 128; ry = e / 128; }
+      s_y[ry * TS_LD + ts_col(cy)] = py[t];
+    }
+    __syncthreads();
+    if (s0 + TS_SUB < r1) gload(s0 + TS_SUB);
+    if (active) {
+      for (int r = grp; r < TS_SUB; r += G) {
+        double a[8], b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          a[u] = s_x[r * TS_LD + 9 * ti + u];
+          b[u] = s_y[r * TS_LD + 9 * tj + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int v = 0; v < 8; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+      }
+    }
+  }
+  // the groups' tiles, summed in group order (G > 1 only when nt <= 128:
+  // nt x 64 doubles fit the two staging arrays)
+  // the two staging arrays serve as one buffer of 2 x 4640 doubles
+  double* red = s_x;
+  for (int g = 1; g < G; ++g) {
+    __syncthreads();
+    if (grp == g)
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+          const int idx = tile * 64 + u * 8 + v;  // < nt * 64 <= 8192
+          if (idx < TS_SUB * TS_LD) red[idx] = acc[u][v];
+          else s_y[idx - TS_SUB * TS_LD] = acc[u][v];
+        }
+    __syncthreads();
+    if (grp == 0)
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+          const int idx = tile * 64 + u * 8 + v;
+          acc[u][v] += idx < TS_SUB * TS_LD ? red[idx] : s_y[idx - TS_SUB * TS_LD];
+        }
+  }
+  if (grp == 0) {
+    double* dst = part + (int64_t)blockIdx.x * p * q;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const int a = 8 * ti + u, c = 8 * tj + v;
+        if (a < p && c < q) dst[a + p * c] = acc[u][v];
+      }
+  }
+}
+
+// C (p x q, ld ldc) = alpha * (fixed-order sum of the nb partials) + beta C
+__global__ void k_tsmm_reduce(const double* __restrict__ part, int64_t nb, int p, int q,
+                              double alpha, double beta, double* __restrict__ C, int64_t ldc) {
+  const int64_t count = (int64_t)p * q;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double sacc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int64_t g = 0;
+    for (; g + 8 <= nb; g += 8)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) sacc[u] += part[(g + u) * count + e];
+    for (; g < nb; ++g) sacc[0] += part[g * count + e];
+    const double v = ((sacc[0] + sacc[1]) + (sacc[2] + sacc[3])) +
+                     ((sacc[4] + sacc[5]) + (sacc[6] + sacc[7]));
+    const int a = (int)(e % p);
+    const int64_t c = e / p;
+    double* o = C + a + ldc * c;
+    *o = beta != 0.0 ? fma(alpha, v, beta * *o) : alpha * v;
+  }
+}
+
+int64_t tsmm_blocks(int64_t N, int num_cu, int64_t* rows_per_block) {
+  int64_t nb = 2 * (int64_t)num_cu;
+  int64_t rpb = (N + nb - 1) / nb;
+  rpb = (rpb + TS_SUB - 1) / TS_SUB * TS_SUB;
+  if (rpb < TS_SUB) rpb = TS_SUB;
+  *rows_per_block = rpb;
+  return (N + rpb - 1) / rpb;
+}
+
+hipError_t launch_tsmm(hipStream_t st, const double* X, int64_t ldx, const double* Y, int64_t ysr,
+                       int64_t ysc, int64_t N, int p, int q, double alpha, double beta, double* C,
+                       int64_t ldc, double* part, int num_cu) {
+  if (p < 1 || q < 1 || p > 128 || q > 128 || N < 1) return hipErrorInvalidValue;
+  int64_t rpb = 0;
+  const int64_t nb = tsmm_blocks(N, num_cu, &rpb);
+  hipLaunchKernelGGL(k_tsmm_part, dim3((unsigned)nb), dim3(TS_THREADS), 0, st, X, ldx, Y, ysr, ysc,
+                     N, p, q, rpb, part);
+  hipLaunchKernelGGL(k_tsmm_reduce, dim3((unsigned)(((int64_t)p * q + 255) / 256)), dim3(256), 0,
+                     st, part, nb, p, q, alpha, beta, C, ldc);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// out (N x k, ld ldo, FP32 or FP64) = X (N x j, column-major, ld ldx) S (j x k,
+// ld lds), FP64 arithmetic: SBR-SVD's V = B^T U~ S^-1 written straight in
+// the output type.  A block covers 64 rows; wave w forms output columns
+// [w kq, (w+1) kq) with kq = ceil(k / 4) <= 32, one row per lane; S's entries
+// are the same for a whole wave (scalar loads), X's 64 rows are read by the
+// four waves of the block (the later reads hit the cache).
+// ---------------------------------------------------------------------------
+template <typename OutT, int KQ>
+__global__ __launch_bounds__(256) void k_tall_mul(const double* __restrict__ X, int64_t ldx,
+                                                  int64_t N, int j, const double* __restrict__ St,
+                                                  int64_t ldst, int k, OutT* __restrict__ out,
+                                                  int64_t ldo) {
+  const int lane = threadIdx.x & 63;
+  // the wave index, made wave-uniform for the compiler: S's entries are then
+  // scalar loads shared by the wave
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t r = (int64_t)blockIdx.x * 64 + lane;
+  const int c0 = wave * KQ;
+  double acc[KQ];
+#pragma unroll
+  for (int u = 0; u < KQ; ++u) acc[u] = 0.0;
+  const int64_t rr = r < N ? r : N - 1;
+  for (int c = 0; c < j; ++c) {
+    const double x = X[rr + ldx * c];
+    // S^T stored row c = (S(c, 0), S(c, 1), ...) with stride ldst: the
+    // wave's KQ entries are contiguous (entries past k are read, their
+    // results dropped)
+    const double* srow = St + ldst * c + c0;
+#pragma unroll
+    for (int u = 0; u < KQ; ++u) acc[u] = fma(x, srow[u], acc[u]);
+  }
+  if (r < N)
+#pragma unroll
+    for (int u = 0; u < KQ; ++u)
+      if (c0 + u < k) out[r + ldo * (c0 + u)] = (OutT)acc[u];
+}
+
+hipError_t launch_tall_mul(hipStream_t st, const double* X, int64_t ldx, int64_t N, int j,
+                           const double* St, int64_t ldst, int k, void* out, bool out_f64,
+                           int64_t ldo) {
+  const int kq = (k + 3) / 4;
+  const int kqt = kq <= 8 ? 8 : kq <= 16 ? 16 : kq <= 25 ? 25 : 32;  // the instance below
+  if (k < 1 || k > 128 || j < 1 || N < 1 || ldst < 4 * kqt) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((N + 63) / 64));
+#define SID_TM(KQ_)                                                                              \
+  if (out_f64)                                                                                   \
+    hipLaunchKernelGGL((k_tall_mul<double, KQ_>), grid, dim3(256), 0, st, X, ldx, N, j, St, ldst, \
+                       k, (double*)out, ldo);                                                    \
+  else                                                                                           \
+    hipLaunchKernelGGL((k_tall_mul<float, KQ_>), grid, dim3(256), 0, st, X, ldx, N, j, St, ldst,  \
+                       k, (float*)out, ldo);
+  if (kq <= 8) { SID_TM(8) }
+  else if (kq <= 16) { SID_TM(16) }
+  else if (kq <= 25) { SID_TM(25) }
+  else { SID_TM(32) }
+#undef SID_TM
+  return hipGetLastError();
+}
+
+// out[0] = sum of x[e]^2 over count entries (one block, fixed order)
+__global__ __launch_bounds__(256) void k_sumsq(const double* __restrict__ x, int64_t count,
+                                               double* __restrict__ out) {
+  __shared__ double s[256];
+  double a = 0.0;
+  for (int64_t e = threadIdx.x; e < count; e += 256) a = fma(x[e], x[e], a);
+  s[threadIdx.x] = a;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = s[0];
+}
+
+hipError_t launch_sumsq(hipStream_t st, const double* x, int64_t count, double* out) {
+  hipLaunchKernelGGL(k_sumsq, dim3(1), dim3(256), 0, st, x, count, out);
+  return hipGetLastError();
+}
+
 }  // namespace sid

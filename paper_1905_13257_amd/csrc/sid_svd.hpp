@@ -41,4 +41,21 @@ hipError_t launch_block_update(hipStream_t st, const double* Bt, int64_t N, int 
 hipError_t launch_transpose64(hipStream_t st, const double* src, int64_t rows, int64_t cols,
                               int64_t lds, double* dst, int64_t ldd);
 
+// C (p x q, ld ldc) = alpha X^T Y + beta C over N rows (beta = 0: C is not
+// read): X N x p column-major (ld ldx); Y N x q with entry (r, c) at
+// Y[r ysr + c ysc]; p, q <= 128; part: tsmm_blocks(N, num_cu) x p x q
+// doubles of scratch.  FP64, fixed summation order.
+int64_t tsmm_blocks(int64_t N, int num_cu, int64_t* rows_per_block);
+hipError_t launch_tsmm(hipStream_t st, const double* X, int64_t ldx, const double* Y, int64_t ysr,
+                       int64_t ysc, int64_t N, int p, int q, double alpha, double beta, double* C,
+                       int64_t ldc, double* part, int num_cu);
+// out (N x k, ld ldo, FP32 or FP64) = X (N x j, ld ldx) S (j x k) in FP64;
+// k <= 128; S given row by row: St[c ldst + t] = S(c, t), ldst >= 128 (the
+// entries past k are read and their results dropped)
+hipError_t launch_tall_mul(hipStream_t st, const double* X, int64_t ldx, int64_t N, int j,
+                           const double* St, int64_t ldst, int k, void* out, bool out_f64,
+                           int64_t ldo);
+// out[0] = sum of squares of x[0:count] (fixed order)
+hipError_t launch_sumsq(hipStream_t st, const double* x, int64_t count, double* out);
+
 }  // namespace sid
