@@ -160,6 +160,96 @@ def batched_main(args, torch, sid, synth) -> int:
     return 0
 
 
+def stream_main(args, torch, sid, synth) -> int:
+    """The streamed workload: 1,572,864 x 2000 FP32 snapshots pushed in blocks
+    of 32 columns (62 of 32 and one of 16), single pass, k = 150, p = 30,
+    q = 10; the FP8 sketch (the form the in-situ setting is after), with
+    bf16x2 beside it.  A step = begin, every push, finish; the blocks are
+    resident in HBM."""
+    import numpy as np
+    A = synth.spectral_snapshots(synth.streaming_config(), device="cuda")
+    torch.cuda.synchronize()
+    N, n = A.shape
+    k, p, q = 150, 30, 10
+    total = N * n * 4
+
+    def run(prec):
+        kw = dict(seed=0, mode="single_pass", prec=prec, probe_rows=q)
+
+        def step():
+            st = sid.Stream(N, n, k, p, dtype=torch.float32, **kw)
+            for c0 in range(0, n, 32):
+                st.push(A[:, c0:c0 + 32])
+            return st.finish()
+
+        out = step()
+        ms = time_steps(step, max(2, args.steps // 4), 1, torch)
+        err = sid.error_norms(A, out.AJ, out.P)["rel_fro"]
+        return ms, err
+
+    ms8, e8 = run("fp8")
+    msb, eb = run("bf16x2")
+    line = {
+        "metric": "streamed snapshot GB/s (single-pass ID, FP8 sketch, k=150)",
+        "value": round(total / (ms8 * 1e-3) / 1e9, 2), "unit": "GB/s", "n_gpus": 1,
+        "steps": max(2, args.steps // 4), "warmup": 1, "ms_per_step": round(ms8, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp8",
+        "data": "synthetic",
+        "config": {"workload": "channel-like snapshots 1572864 x 2000 fp32 streamed in 32-column "
+                               "blocks, single-pass ID k=150 p=30 q=10",
+                   "rel_fro_error": e8,
+                   "bf16x2": {"ms_per_step": round(msb, 4),
+                              "value": round(total / (msb * 1e-3) / 1e9, 2),
+                              "rel_fro_error": eb}},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def probes_main(args, torch, sid, synth) -> int:
+    """Ceilings the kernels' design rests on, measured with the library's
+    probe kernels (sid_probe): a streaming read and two store patterns of
+    HBM, and the issue rate of the two bfloat16 matrix instructions."""
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    stream = torch.cuda.current_stream()
+    ctx = sid.Context(stream=stream)
+    out = {}
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    big = torch.empty((256, 1 << 22), dtype=torch.float32, device="cuda").T   # 4 GiB
+    ms = timed(lambda: sid.probe("read", big, ctx=ctx))
+    out["read_GBs"] = round(big.numel() * 4 / (ms * 1e-3) / 1e9, 1)
+    del big
+    c2 = torch.empty((500, 1572864), dtype=torch.float32, device="cuda").T
+    ms = timed(lambda: sid.probe("store_columns", c2, ctx=ctx))
+    out["store_columns_GBs"] = round(c2.numel() * 4 / (ms * 1e-3) / 1e9, 1)
+    ms = timed(lambda: sid.probe("store_sequential", c2, ctx=ctx))
+    out["store_sequential_GBs"] = round(c2.numel() * 4 / (ms * 1e-3) / 1e9, 1)
+    del c2
+    rounds = 20000
+    for name, flops in (("mfma_16x16x32", 2 * 16 * 16 * 32), ("mfma_32x32x16", 2 * 32 * 32 * 16)):
+        ms = timed(lambda: sid.probe(name, None, rounds, ctx=ctx), reps=3)
+        total = ncu * 8 * 4 * 8 * rounds * flops
+        out[name + "_TFLOPs"] = round(total / (ms * 1e-3) / 1e12, 1)
+    ctx.sync()
+    line = {"metric": "probe ceilings", "config": {"compute_units": ncu,
+            "read": "4 GiB, 16-byte loads", "store_columns": "1572864 x 500 FP32, 4 columns x "
+            "256 bytes per wave instruction", "mfma": "8 independent chains per wave, "
+            f"{rounds} rounds, 8 workgroups of 4 waves per compute unit"}, **out}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def coarse_main(args, torch, sid, synth) -> int:
     """Sub-sampled ID (Alg. 5 with the Gaussian sketch of the coarse rows) on
     the fine 256 x 128 x 128 channel-like grid, error on the fine grid."""
@@ -397,6 +487,12 @@ def main() -> int:
                     help="rows of the matrix the oracle baseline compresses (default: all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32-plain run")
+    ap.add_argument("--probes", action="store_true",
+                    help="the measured ceilings: HBM read and store rates, bf16 matrix-"
+                         "instruction issue rates (sid_probe)")
+    ap.add_argument("--stream", action="store_true",
+                    help="auxiliary measurement instead of the headline: the 1,572,864 x 2000 "
+                         "field streamed in 32-column blocks, FP8 sketch, k = 150, p = 30")
     ap.add_argument("--batched", action="store_true",
                     help="auxiliary measurement instead of the headline: 64 independent matrices "
                          "(N log-uniform in [2^14, 2^20], n in [64, 512], k in [8, 64], spectrum "
@@ -439,6 +535,10 @@ def main() -> int:
     import synth
 
     torch.cuda.set_device(0)
+    if args.probes:
+        return probes_main(args, torch, sid, synth)
+    if args.stream:
+        return stream_main(args, torch, sid, synth)
     if args.batched:
         return batched_main(args, torch, sid, synth)
     if args.coarse:

@@ -291,6 +291,17 @@ sid_status sid_sketch(sid_ctx *ctx, const void *A, sid_dtype dtype, int64_t N, i
 sid_status sid_sketch_noalloc(sid_ctx *ctx, const void *A, sid_dtype dtype, int64_t N, int64_t n,
                               int64_t lda, const sid_params *p, double *W, void *Y);
 
+/* Measurement hook (no part of the method): one launch of a probe kernel on
+ * the context's stream, for timing the ceilings the kernels' design rests
+ * on.  kind 0: read the N x n FP32 device buffer `buf` once (16-byte loads);
+ * 1: write it column by column with the reconstruction kernels' pattern
+ * (each wave 4 columns x 256 contiguous bytes per instruction; N % 64 == 0);
+ * 2: write it as one sequential fill; 3 / 4: N rounds of eight independent
+ * v_mfma_f32_16x16x32_bf16 / v_mfma_f32_32x32x16_bf16 per wave on register
+ * data, 8 workgroups of 4 waves per compute unit (buf and n unused).
+ * buf: 16-byte aligned, N n a multiple of 4.  Errors: SID_EINVAL. */
+sid_status sid_probe(sid_ctx *ctx, int kind, void *buf, int64_t N, int64_t n);
+
 /*
  * Streaming (snapshots that arrive a few at a time, the in-situ setting of
  * Sec. 1 and Sec. 4).  Both sketches are linear in the columns: W(:, j) =

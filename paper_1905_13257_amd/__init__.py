@@ -16,7 +16,7 @@ from __future__ import annotations
 
 from ._native import (  # noqa: F401
     SID_F32, SID_F64, PRECISIONS, MODES, Context, Compressed, Interp, RowSet, SidError, Stream,
-    Batch, batch_streams, compress, compress_batched, reconstruct, reserve, error_norms, fill_gaussian, sketch, sketch_noalloc, sync,
+    Batch, batch_streams, probe, compress, compress_batched, reconstruct, reserve, error_norms, fill_gaussian, sketch, sketch_noalloc, sync,
     interp_reconstruct, interp_error_norms, SVD, sbr_svd, SvdStream,
     library_path,
     load,

@@ -27,7 +27,7 @@ EXPORTS = [
     "sid_batch_streams",
     "sid_interp_create", "sid_interp_destroy", "sid_interp_rowset", "sid_interp_info",
     "sid_interp_reconstruct", "sid_interp_error_norms", "sid_svd_params_init", "sid_sbr_svd",
-    "sid_svd_stream_begin", "sid_svd_stream_finish", "sid_sync", "sid_sketch_noalloc",
+    "sid_svd_stream_begin", "sid_svd_stream_finish", "sid_sync", "sid_sketch_noalloc", "sid_probe",
 ]
 
 
@@ -121,6 +121,7 @@ def load():
     L.sid_reserve_batched.argtypes = [vp, vp, i64, ctypes.c_int, ctypes.c_int]
     L.sid_batch_streams.argtypes = [vp]
     L.sid_batch_streams.restype = ctypes.c_int
+    L.sid_probe.argtypes = [vp, ctypes.c_int, vp, i64, i64]
     L.sid_stream_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     L.sid_stream_save.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_size_t)]
@@ -386,6 +387,28 @@ def compress_batched(mats: list, k, oversample=10, seed=0, mode: str = "two_pass
         return []
     return Batch(mats, k, oversample, seed, mode, prec, probe_rows, rank_tol, sp_rcond,
                  want_skeleton, ctx, probe_tol).run()
+
+
+PROBES = {"read": 0, "store_columns": 1, "store_sequential": 2, "mfma_16x16x32": 3,
+          "mfma_32x32x16": 4}
+
+
+def probe(kind: str, buf: torch.Tensor | None = None, rounds: int = 0,
+          ctx: Context | None = None) -> None:
+    """sid_probe: one launch of a measurement kernel (no part of the method).
+    buf: an N x n FP32 column-major device matrix for the memory probes;
+    rounds for the matrix-instruction probes."""
+    ctx = ctx or default_context(torch.device("cuda"))
+    code = PROBES[kind]
+    if code <= 2:
+        if buf is None or buf.dtype != torch.float32:
+            raise ValueError("the memory probes take an FP32 device matrix")
+        b, ld = _colmajor(buf)
+        if ld != b.shape[0]:
+            raise ValueError("probe buffer: contiguous columns")
+        ctx.check(ctx._lib.sid_probe(ctx.handle, code, _ptr(b), b.shape[0], b.shape[1]))
+    else:
+        ctx.check(ctx._lib.sid_probe(ctx.handle, code, None, rounds, 1))
 
 
 def batch_streams(ctx: Context | None = None) -> int:

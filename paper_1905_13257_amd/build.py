@@ -17,7 +17,7 @@ SOURCES = ["csrc/sid_kernels.hip", "csrc/sid_sketch_mfma.hip", "csrc/sid_cpqr.hi
            "csrc/sid_interp.hip", "csrc/sid_adaptive.hip", "csrc/sid_svd.hip",
            "csrc/sid_apply.hip", "csrc/sid_sketch_f64.hip", "csrc/sid_sketch_v2.hip",
            "csrc/sid_sketch_v2_bf16.hip", "csrc/sid_sketch_v2_bf16x2.hip",
-           "csrc/sid_sketch_v2_fp8.hip", "csrc/sid_api.hip"]
+           "csrc/sid_sketch_v2_fp8.hip", "csrc/sid_probe.hip", "csrc/sid_api.hip"]
 LIB = os.path.join(HERE, "libsid.so")
 OBJDIR = os.path.join(HERE, "_build")
 

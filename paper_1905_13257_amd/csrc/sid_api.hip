@@ -58,7 +58,7 @@ enum Slot {
   WS_OMEGA, WS_PART, WS_W, WS_WR, WS_NRM, WS_PIV, WS_R, WS_Q, WS_KEFF, WS_STATS, WS_PD,
   WS_ERR, WS_Y, WS_M, WS_MPR, WS_WJ, WS_PIVM, WS_RM, WS_QM, WS_RKM, WS_C, WS_T, WS_MIX,
   WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COOP, WS_SYNC, WS_R11, WS_FITPART, WS_YTMP, WS_REF_W, WS_REF_WJ, WS_OMP, WS_A8, WS_IACJT, WS_IPB, WS_IB, WS_IPART, WS_AZ, WS_AE2, WS_APART, WS_SV_H, WS_SV_B, WS_SV_Q, WS_SV_OM32,
-  WS_SV_OM, WS_SV_SMALL, WS_SV_WP, WS_SV_TSP, WS_COUNT
+  WS_SV_OM, WS_SV_SMALL, WS_SV_WP, WS_SV_TSP, WS_PROBE, WS_COUNT
 };
 
 struct Buf {
@@ -914,6 +914,24 @@ sid_status sid_sketch_noalloc(sid_ctx* ctx, const void* A, sid_dtype dtype, int6
                                             (int)sh.lq, (int)sh.l, p->seed, om, omt, ctx->num_cu,
                                             part, W, (float*)Y, &np, nullptr),
               "sketch pass (allocation-free)");
+  return SID_OK;
+}
+
+sid_status sid_probe(sid_ctx* ctx, int kind, void* buf, int64_t N, int64_t n) {
+  if (!ctx) return SID_EINVAL;
+  if (kind < 0 || kind > 4) return fail(ctx, SID_EINVAL, "unknown probe");
+  if (kind <= 2) {
+    if (!buf || N < 1 || n < 1 || ((uintptr_t)buf % 16) != 0 || (N * n) % 4 != 0)
+      return fail(ctx, SID_EINVAL, "probe buffer: non-NULL, 16-byte aligned, N n a multiple of 4");
+    if (kind == 1 && N % 64 != 0) return fail(ctx, SID_EINVAL, "column-store probe: N % 64 == 0");
+  } else if (N < 1 || N > (1 << 30)) {
+    return fail(ctx, SID_EINVAL, "matrix-instruction probe: 1 <= rounds <= 2^30");
+  }
+  SID_NEED_DEVICE(ctx);
+  SID_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+  float* sink = (float*)ws(ctx, WS_PROBE, sizeof(float) * 8 * (size_t)ctx->num_cu);
+  if (!sink) return SID_ENOMEM;
+  SID_CHECK(sid::launch_probe(ctx->stream, kind, buf, N, n, ctx->num_cu, sink), "probe");
   return SID_OK;
 }
 

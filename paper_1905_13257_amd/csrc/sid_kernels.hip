@@ -548,10 +548,20 @@ __global__ __launch_bounds__(256) void k_reconstruct(const T* __restrict__ AJ, i
   const int64_t i = blockIdx.x * (int64_t)64 + (threadIdx.x & 63);
   const int cg = threadIdx.x >> 6;
   if (i >= N) return;
-  for (int c = cg; c < CB && j0 + c < n; c += 4) {
-    TC acc = 0;
-    for (int t = 0; t < k; ++t) acc = fma((TC)AJ[i + ldaj * t], s_p[t + k * c], acc);
-    out[i + ldo * (j0 + c)] = (T)acc;
+  // each AJ entry is loaded once for the lane's 8 columns (cg, cg + 4, ...);
+  // every sum runs over t in increasing order
+  TC acc[CB / 4];
+#pragma unroll
+  for (int u = 0; u < CB / 4; ++u) acc[u] = 0;
+  for (int t = 0; t < k; ++t) {
+    const TC a = (TC)AJ[i + ldaj * t];
+#pragma unroll
+    for (int u = 0; u < CB / 4; ++u) acc[u] = fma(a, s_p[t + k * (cg + 4 * u)], acc[u]);
+  }
+#pragma unroll
+  for (int u = 0; u < CB / 4; ++u) {
+    const int c = cg + 4 * u;
+    if (j0 + c < n) out[i + ldo * (j0 + c)] = (T)acc[u];
   }
 }
 
@@ -575,9 +585,21 @@ __global__ __launch_bounds__(256) void k_error_norms(const T* __restrict__ A, in
   const int cg = threadIdx.x >> 6;
   double se = 0.0, sa = 0.0, mrel = 0.0, mabs = 0.0;
   if (i < N) {
-    for (int c = cg; c < CB && j0 + c < n; c += 4) {
-      double acc = 0.0;
-      for (int t = 0; t < k; ++t) acc = fma((double)AJ[i + ldaj * t], s_p[t + k * c], acc);
+    // each AJ entry is loaded once for the lane's 8 columns (cg, cg + 4,
+    // ...); every sum runs over t in increasing order
+    double accs[CB / 4];
+#pragma unroll
+    for (int u = 0; u < CB / 4; ++u) accs[u] = 0.0;
+    for (int t = 0; t < k; ++t) {
+      const double x = (double)AJ[i + ldaj * t];
+#pragma unroll
+      for (int u = 0; u < CB / 4; ++u) accs[u] = fma(x, s_p[t + k * (cg + 4 * u)], accs[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < CB / 4; ++u) {
+      const int c = cg + 4 * u;
+      if (j0 + c >= n) continue;
+      const double acc = accs[u];
       const double a = (double)A[i + lda * (j0 + c)];
       const double d = a - acc;
       se = fma(d, d, se);

@@ -140,4 +140,9 @@ hipError_t launch_cpqr_wgl(hipStream_t st, const double* X, int64_t ldx, int m, 
 hipError_t launch_cpqr_wg(hipStream_t st, const double* X, int64_t ldx, int m, int nc, int kmax,
                           double rank_tol, int64_t* piv, double* R, double* Q, int64_t* keff,
                           double* stats, const int64_t* forced = nullptr);
+// measurement probes (sid_probe): kind 0 read / 1 column stores / 2
+// sequential fill of an N x n FP32 buffer, 3 / 4 the 16x16x32 / 32x32x16
+// bf16 matrix-instruction loop of N rounds; sink: 8 num_cu floats
+hipError_t launch_probe(hipStream_t st, int kind, void* buf, int64_t N, int64_t n, int num_cu,
+                        float* sink);
 }  // namespace sid

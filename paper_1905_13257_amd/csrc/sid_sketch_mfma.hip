@@ -180,7 +180,7 @@ __device__ __forceinline__ void gen_psi(__bf16* __restrict__ s_psi, uint64_t see
 // counts only bound the register state and the results do not depend on
 // them.  The single-matrix kernel runs one share per workgroup; the batched
 // kernel runs shares of many matrices from a work queue.
-template <int DM, bool WANTY, int MT, int LT, int NCH, bool ROWS>
+template <int DM, bool WANTY, int MT, int LT, int NCH, bool ROWS, bool GUARDS = false>
 __device__ __forceinline__ void fused_tile(
     const float* __restrict__ A, int64_t lda, int64_t N, int n, int lq, int l, uint64_t seed,
     const __bf16* __restrict__ omT /* LT*16 x FB_NPAD, k contiguous, zero padded */,
@@ -207,6 +207,10 @@ __device__ __forceinline__ void fused_tile(
   const int lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;  // MFMA lane coordinates
   const int lq4 = (lq + 3) >> 2;
+  // GUARDS (the batched kernel: a smaller matrix on the largest layout):
+  // row tiles of W past the rows below lq only feed rows that are never
+  // stored, and are skipped
+  const int mt_live = GUARDS ? (lq + 15) >> 4 : MT;
   const int gen_items = FB_PR * lq4;
   // wave 0 stages the row list of the panel starting at q0 (clamped to r1)
   auto stage_rows = [&](int64_t q0, int buf) {
@@ -233,6 +237,7 @@ __device__ __forceinline__ void fused_tile(
 #pragma unroll
   for (int r = 0; r < YR; ++r) yacc[r] = f32x4_t{0.f, 0.f, 0.f, 0.f};
   const int yc = wave % LT, rt0 = (wave / LT) * YR;
+  const bool y_live = true;  // (a Y guard as well spilled registers)
 
   // full panels end at r1f; a ragged tail panel [r1f, r1) is handled last
   const int64_t r1f = r0 + ((r1 - r0) / FB_PR) * FB_PR;
@@ -284,7 +289,7 @@ __device__ __forceinline__ void fused_tile(
       //     every panel; the opaque copy of its address keeps the compiler
       //     from hoisting the fragments of all chunks out of the loop.
       bf16x8_t of[FB_KS];
-      if constexpr (WANTY) {
+      if (WANTY && y_live) {
         uintptr_t om_addr = (uintptr_t)omT;
         asm volatile("" : "+s"(om_addr));
         const gbf16p om = (gbf16p)om_addr;
@@ -344,13 +349,14 @@ __device__ __forceinline__ void fused_tile(
       for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
         for (int mt = 0; mt < MTR; ++mt) {
+          if (mt >= mt_live) continue;
           const bf16x8_t af =
               *reinterpret_cast<const bf16x8_t*>(&psi[(mt * 16 + lr) * FB_PROW + 32 * ks + 8 * lg]);
           wacc[mt][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bh[ks], wacc[mt][j], 0, 0, 0);
           if constexpr (SPLIT)
             wacc[mt][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bl[ks], wacc[mt][j], 0, 0, 0);
         }
-      if constexpr (MTX > 0) {
+      if (MTX > 0 && mt_live > MTR) {
 #pragma unroll
         for (int mx = 0; mx < MTX; ++mx) {
           f32x4_t* wx = reinterpret_cast<f32x4_t*>(&s_wx[(((mx * NCH + j) * FB_WAVES + wave) * 64 + lane) * 4]);
@@ -371,7 +377,7 @@ __device__ __forceinline__ void fused_tile(
                      tid, ROWS ? s_rows[pb ^ 1] : nullptr);
       lds_barrier();  // chunk buffer complete
       // (6) Y(panel, this wave's tiles) += A(panel, chunk) Omega(chunk, :)
-      if constexpr (WANTY) {
+      if (WANTY && y_live) {
 #pragma unroll
         for (int ks = 0; ks < FB_KS; ++ks) {
 #pragma unroll
@@ -482,7 +488,7 @@ __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16_batch(
     const int64_t i = t - e.share0;
     const int64_t r0 = i * e.rows_per_wg;
     const int64_t r1 = r0 + e.rows_per_wg < e.N ? r0 + e.rows_per_wg : e.N;
-    fused_tile<DM, WANTY, 10, 8, FB_NCH, false>(e.A, e.lda, e.N, e.n, e.lq, e.l, e.seed, e.omT, r0,
+    fused_tile<DM, WANTY, 10, 8, FB_NCH, false, true>(e.A, e.lda, e.N, e.n, e.lq, e.l, e.seed, e.omT, r0,
                                                 r1, (e.n + FB_CHUNK - 1) / FB_CHUNK,
                                                 e.part + i * e.lq * e.n, WANTY ? e.Y : nullptr,
                                                 nullptr);
