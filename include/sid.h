@@ -150,11 +150,11 @@ typedef struct {
  * larger.
  * Refinement (refine = 1; the paper stops at the ID): after J and P0 are
  * chosen, A is sketched once more with Psi's selection rows in refine_prec,
- * W' = Psi_sel A, and P0 takes one step of iterative refinement of the
- * least-squares problem min ||W'(:, J) P - W'|| with the first pivoted QR's
- * R11 (corrected seminormal equations): P1 = P0 + R11^-1 R11^-T W'(:, J)^T
- * (W' - W'(:, J) P0).  P1(:, J) = I still holds exactly.  err and AJ are
- * those of P0's fit.
+ * W' = Psi_sel A; with J kept, P is recomputed as the least-squares solution
+ * P1 = argmin ||W'(:, J) X - W'||_F (mgsqr of W' with its pivot order forced
+ * to J, then the usual back substitution), so P1(:, J) = I exactly.  err is
+ * re-fitted with P1 on the rows of the first sketch; AJ does not depend on P
+ * and is unchanged.
  * Psi row layout: rows [0, l) select J and P (Alg. 4); in single pass rows
  * [l, l + e) are the extra co-range rows; the last q rows are the probe. */
 void sid_params_init(sid_params *p, int64_t k);
