@@ -439,8 +439,16 @@ SketchPath plan_sketch(const sid_ctx* ctx, sid_dtype dtype, int64_t lda, const v
   return SketchPath::GENERAL;
 }
 
+// whether run_sketch can add this pass's part of Y in the kernel (y_add):
+// the workgroup-pair pass does
+bool sketch_adds_y(const sid_ctx* ctx, sid_dtype dtype, int64_t lda, const void* A,
+                   const Shape& sh) {
+  return plan_sketch(ctx, dtype, lda, A, sh.prec, sh, false, true) == SketchPath::PAIR_BF16;
+}
+
 // reserve what run_sketch takes beyond reserve(): the matrix-core pass's
-// partials and Omega^T, the slab sum of Y, the FP8 data copy
+// partials and Omega^T, the slab sum of Y (the one-workgroup pass), the FP8
+// data copy
 sid_status reserve_sketch(sid_ctx* ctx, const Shape& sh, int prec, bool has_rows,
                                  bool want_y) {
   const SketchPath path = plan_sketch(ctx, SID_F32, 4, nullptr, prec, sh, has_rows, want_y);
@@ -452,8 +460,6 @@ sid_status reserve_sketch(sid_ctx* ctx, const Shape& sh, int prec, bool has_rows
     const int64_t pairs = sid::sketch_v2_pairs(sh.N, ctx->num_cu, &rpp);
     if (!ws(ctx, WS_PARTF, sizeof(float) * (size_t)(pairs * sh.lq * vs)) ||
         !ws(ctx, WS_OMT, sizeof(uint16_t) * sid::sketch_v2_omt_elems((int)sh.l, (int)vs)))
-      return SID_ENOMEM;
-    if (want_y && sh.n > vs && !ws(ctx, WS_YTMP, sizeof(float) * (size_t)(sh.N * sh.l)))
       return SID_ENOMEM;
   } else if (path == SketchPath::FUSED_BF16 || path == SketchPath::FUSED_F32) {
     int64_t rpw = 0;
@@ -713,10 +719,11 @@ static sid_status refine_pass(sid_ctx* ctx, const void* A, sid_dtype dtype, int6
 
 // The sketch pass over the columns col0 .. col0 + sh.n - 1 of the matrix
 // (A points at column col0): W (lq x sh.n) and, if Y is given, Y = A Omega
-// with Omega's rows col0 .. col0 + sh.n - 1.
+// with Omega's rows col0 .. col0 + sh.n - 1 (y_add: Y += A Omega; only the
+// workgroup-pair pass takes it, see sketch_adds_y).
 static sid_status run_sketch(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t lda,
                              const sid_params* p, const Shape& sh, const Work& w, double* W,
-                             void* Y, int64_t col0 = 0) {
+                             void* Y, int64_t col0 = 0, bool y_add = false) {
   hipStream_t st = ctx->stream;
   if (Y) {
     SID_CHECK(sid::launch_fill_gaussian(st, p->seed, 0u, col0, sh.n, 0, sh.l, w.omega),
@@ -739,28 +746,22 @@ static sid_status run_sketch(sid_ctx* ctx, const void* A, sid_dtype dtype, int64
     float* partf = (float*)ws(ctx, WS_PARTF, sizeof(float) * (size_t)(pairs * sh.lq * vs));
     __bf16* omT = (__bf16*)ws(ctx, WS_OMT, sizeof(uint16_t) * sid::sketch_v2_omt_elems((int)sh.l, (int)vs));
     if (!partf || !omT) return SID_ENOMEM;
-    float* ytmp = nullptr;
-    if (Y && sh.n > vs) {
-      ytmp = (float*)ws(ctx, WS_YTMP, sizeof(float) * (size_t)(sh.N * sh.l));
-      if (!ytmp) return SID_ENOMEM;
-    }
     const int dmode = sh.prec == SID_SK_BF16X2   ? sid::FB_BF16X2
                       : sh.prec == SID_SK_FP8E4M3 ? sid::FB_FP8
                                                   : sid::FB_BF16;
+    // every slab after the first adds its part of Y in the kernel
     for (int64_t c0 = 0; c0 < sh.n; c0 += vs) {
       const int64_t nb = sh.n - c0 < vs ? sh.n - c0 : vs;
-      float* yd = Y ? (c0 == 0 ? (float*)Y : ytmp) : nullptr;
       int64_t nparts = 0;
       SID_CHECK(sid::launch_sketch_v2(st, dmode, (const float*)A + c0 * lda, lda, sh.N, (int)nb,
                                       (int)sh.lq, (int)sh.l, p->seed, w.omega + c0 * sh.l, omT,
-                                      ctx->num_cu, partf, W + c0 * sh.lq, yd, &nparts),
+                                      ctx->num_cu, partf, W + c0 * sh.lq, (float*)Y, &nparts,
+                                      c0 > 0 || y_add),
                 "sketch pass (workgroup pairs)");
-      if (Y && c0 > 0)
-        SID_CHECK(sid::launch_add_inplace(st, false, Y, ytmp, sh.N * sh.l, ctx->num_cu),
-                  "Y slab sum");
     }
     return SID_OK;
   }
+  if (y_add) return fail(ctx, SID_EINVAL, "internal: Y accumulation on a path without it");
   if (path == SketchPath::FP8_GENERAL) {
     // general kernels: the e4m3 data values are formed first (one more pass
     // over A and an N x n FP32 copy in the workspace)
@@ -1357,11 +1358,15 @@ sid_status stream_flush(sid_stream* s, const void* src, int64_t ld, int64_t ncol
   sh.n = ncols;
   Work w;
   if (reserve(ctx, sh, &w) != SID_OK) return SID_ENOMEM;
+  // Y accumulates over the flushes: in the kernel on the workgroup-pair
+  // pass, else through the workspace's Y and an add pass (the same sums)
+  const bool kadd = s->single && s->y_init && sketch_adds_y(ctx, s->dtype, ld, src, sh);
   void* ydst = nullptr;
-  if (s->single) ydst = s->y_init ? w.Y : s->Y;
-  st = run_sketch(ctx, src, s->dtype, ld, &s->p, sh, w, s->W + s->lq * s->cols, ydst, s->cols);
+  if (s->single) ydst = (s->y_init && !kadd) ? w.Y : s->Y;
+  st = run_sketch(ctx, src, s->dtype, ld, &s->p, sh, w, s->W + s->lq * s->cols, ydst, s->cols,
+                  kadd);
   if (st != SID_OK) return st;
-  if (s->single && s->y_init)
+  if (s->single && s->y_init && !kadd)
     SID_CHECK(sid::launch_add_inplace(ctx->stream, s->p.prec == SID_SK_F64, s->Y, w.Y,
                                       s->N * s->l, ctx->num_cu),
               "stream: Y accumulation");

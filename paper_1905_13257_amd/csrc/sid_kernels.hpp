@@ -91,9 +91,12 @@ int sketch_v2_slab(int lq, int l, bool wanty);
 bool sketch_v2_supported(int64_t n, int lq, int l, bool wanty, int64_t lda, const void* A);
 size_t sketch_v2_omt_elems(int l, int n);
 int64_t sketch_v2_pairs(int64_t N, int num_cu, int64_t* rows_per_pair);
+// y_add: Y += A Omega (the sums a separate Y + part pass would form) instead
+// of Y = A Omega
 hipError_t launch_sketch_v2(hipStream_t st, int dmode, const float* A, int64_t lda, int64_t N,
                             int n, int lq, int l, uint64_t seed, const float* omega, __bf16* omT,
-                            int num_cu, float* part, double* W, float* Y, int64_t* nparts_out);
+                            int num_cu, float* part, double* W, float* Y, int64_t* nparts_out,
+                            bool y_add = false);
 int64_t fused_bf16_grid(int64_t N, int num_cu, int64_t* rows_per_wg);
 bool fused_bf16_batch_supported(int64_t n, int lq, int l, int64_t lda, const void* A);
 // the batched sketch pass over d_tab (count entries, nshares shares in all;

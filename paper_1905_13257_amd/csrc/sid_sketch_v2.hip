@@ -74,7 +74,8 @@ int64_t sketch_v2_pairs(int64_t N, int num_cu, int64_t* rows_per_pair) {
 
 hipError_t launch_sketch_v2(hipStream_t st, int dmode, const float* A, int64_t lda, int64_t N,
                             int n, int lq, int l, uint64_t seed, const float* omega, __bf16* omT,
-                            int num_cu, float* part, double* W, float* Y, int64_t* nparts_out) {
+                            int num_cu, float* part, double* W, float* Y, int64_t* nparts_out,
+                            bool y_add) {
   const int nct = (n + V2_CHUNK - 1) / V2_CHUNK;
   if (n < 1 || !v2_fits(nct, lq, l, Y != nullptr)) return hipErrorInvalidValue;
   if (Y && (uint64_t)N * (uint64_t)l * 4u >= (1ull << 32)) return hipErrorInvalidValue;
@@ -87,9 +88,10 @@ hipError_t launch_sketch_v2(hipStream_t st, int dmode, const float* A, int64_t l
   const int64_t pairs = sketch_v2_pairs(N, num_cu, &rpp);
   *nparts_out = pairs;
   const dim3 g((unsigned)(2 * pairs));
-  hipError_t e = dmode == FB_BF16X2 ? v2_launch_bf16x2(st, g, A, lda, N, n, lq, l, seed, omT, rpp, part, Y)
-                 : dmode == FB_FP8  ? v2_launch_fp8(st, g, A, lda, N, n, lq, l, seed, omT, rpp, part, Y)
-                                    : v2_launch_bf16(st, g, A, lda, N, n, lq, l, seed, omT, rpp, part, Y);
+  const int ya = (Y && y_add) ? 1 : 0;
+  hipError_t e = dmode == FB_BF16X2 ? v2_launch_bf16x2(st, g, A, lda, N, n, lq, l, seed, omT, rpp, part, Y, ya)
+                 : dmode == FB_FP8  ? v2_launch_fp8(st, g, A, lda, N, n, lq, l, seed, omT, rpp, part, Y, ya)
+                                    : v2_launch_bf16(st, g, A, lda, N, n, lq, l, seed, omT, rpp, part, Y, ya);
   if (e != hipSuccess) return e;
   const int64_t count = (int64_t)lq * n;
   int64_t blocks = (count + 255) / 256;

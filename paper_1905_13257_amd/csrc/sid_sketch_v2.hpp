@@ -105,7 +105,7 @@ __global__ __launch_bounds__(V2_THREADS, 1) void k_sketch_v2(
     const float* __restrict__ A, int64_t lda, int64_t N, int n, int lq, int hsplit, int l,
     uint64_t seed, const __bf16* __restrict__ omT /* 64 LT x 128 NCT, k in chunk-buffer order */,
     int64_t rows_per_pair, float* __restrict__ part /* pairs x lq x n, row-major per pair */,
-    float* __restrict__ Y /* N x l row-major */) {
+    float* __restrict__ Y /* N x l row-major */, int yadd /* 1: Y += A Omega */) {
   static_assert(LT == 2 || LT == 4, "Y column tiles per half");
   constexpr bool SPLIT = DM == FB_BF16X2;
   constexpr bool FP8 = DM == FB_FP8;
@@ -251,6 +251,21 @@ __global__ __launch_bounds__(V2_THREADS, 1) void k_sketch_v2(
         const uint32_t ob = (uint32_t)(((p0 + rb) * l + ycol) * 4);
         f32x16_t t = yacc[r];
         asm volatile("" : "+v"(t));
+        if (yadd) {
+          // Y += this pass's part: all sixteen old values are loaded before
+          // the first sum, and the sums are those of a separate Y + part pass
+          float old[16];
+#pragma unroll
+          for (int e = 0; e < 16; ++e) {
+            const int dr = 8 * (e >> 2) + (e & 3);
+            old[e] = (ycol < l && rb + dr < rows)
+                         ? *reinterpret_cast<const float*>(reinterpret_cast<const char*>(Y) +
+                                                           (ob + (uint32_t)(dr * l * 4)))
+                         : 0.0f;
+          }
+#pragma unroll
+          for (int e = 0; e < 16; ++e) t[e] = old[e] + t[e];
+        }
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
           const int dr = 8 * (e >> 2) + (e & 3);
@@ -489,10 +504,10 @@ inline bool v2_fits(int nct, int lq, int l, bool wanty) {
 template <int DM, bool WY, int MT, int NCT, int LT>
 hipError_t v2_launch_one(hipStream_t st, dim3 grid, const float* A, int64_t lda, int64_t N, int n,
                          int lq, int l, uint64_t seed, const __bf16* omT, int64_t rpp, float* part,
-                         float* Y) {
+                         float* Y, int yadd) {
   if constexpr (v2_fits_t(MT, NCT, LT, WY)) {
     hipLaunchKernelGGL((k_sketch_v2<DM, WY, MT, NCT, LT>), grid, dim3(V2_THREADS), 0, st, A, lda,
-                       N, n, lq, v2_hsplit(lq), l, seed, omT, rpp, part, Y);
+                       N, n, lq, v2_hsplit(lq), l, seed, omT, rpp, part, Y, yadd);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
@@ -503,10 +518,10 @@ hipError_t v2_launch_one(hipStream_t st, dim3 grid, const float* A, int64_t lda,
 template <int DM>
 hipError_t v2_launch_dm(hipStream_t st, dim3 grid, const float* A, int64_t lda, int64_t N, int n,
                         int lq, int l, uint64_t seed, const __bf16* omT, int64_t rpp, float* part,
-                        float* Y) {
+                        float* Y, int yadd) {
   const int mt = v2_mt(lq), lt = v2_lt(l), nct = (n + V2_CHUNK - 1) / V2_CHUNK;
 #define SID_V2(WY, MT_, NCT_, LT_) \
-  return v2_launch_one<DM, WY, MT_, NCT_, LT_>(st, grid, A, lda, N, n, lq, l, seed, omT, rpp, part, Y)
+  return v2_launch_one<DM, WY, MT_, NCT_, LT_>(st, grid, A, lda, N, n, lq, l, seed, omT, rpp, part, Y, yadd)
 #define SID_V2_LT(MT_, NCT_)                     \
   if (!Y) SID_V2(false, MT_, NCT_, 2);           \
   else if (lt == 2) SID_V2(true, MT_, NCT_, 2);  \
@@ -527,12 +542,12 @@ hipError_t v2_launch_dm(hipStream_t st, dim3 grid, const float* A, int64_t lda, 
 
 hipError_t v2_launch_bf16(hipStream_t st, dim3 grid, const float* A, int64_t lda, int64_t N, int n,
                           int lq, int l, uint64_t seed, const __bf16* omT, int64_t rpp, float* part,
-                          float* Y);
+                          float* Y, int yadd);
 hipError_t v2_launch_bf16x2(hipStream_t st, dim3 grid, const float* A, int64_t lda, int64_t N,
                             int n, int lq, int l, uint64_t seed, const __bf16* omT, int64_t rpw,
-                            float* part, float* Y);
+                            float* part, float* Y, int yadd);
 hipError_t v2_launch_fp8(hipStream_t st, dim3 grid, const float* A, int64_t lda, int64_t N, int n,
                          int lq, int l, uint64_t seed, const __bf16* omT, int64_t rpw, float* part,
-                         float* Y);
+                         float* Y, int yadd);
 
 }  // namespace sid

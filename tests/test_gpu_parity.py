@@ -633,6 +633,41 @@ def test_streaming_pass_edge_shapes(sid, oracle_mod, prec):
             assert np.array_equal(host(out.P)[:ke][:, J], np.eye(ke))
 
 
+@pytest.mark.parametrize("prec", ["bf16x2", "fp8"])
+def test_pair_pass_y_over_column_slabs(sid, oracle_mod, prec):
+    """The workgroup-pair pass (l = 180 > 128) over a matrix wider than its
+    column slab: every slab after the first adds its part of Y in the kernel.
+    W and Y against the oracle (per-entry bound); a single-pass stream of
+    ragged blocks (each flush after the first adds in the kernel as well)
+    against the resident call: the same W bit for bit (J, P identical) and
+    AJ to rounding of the Y sums."""
+    N, n, k, p, q = 3000, 900, 150, 30, 6
+    l, lq = k + p, k + 2 * p + q
+    A64, _ = c1_matrix(N=N, n=n, seed=1006)
+    A64 = A64.astype(np.float32).astype(np.float64)
+    A = to_gpu(A64, torch.float32)
+    say("pair-pass Y slabs", prec)
+    W, Y = sid.sketch(A, k, p, seed=5, prec=prec, probe_rows=q, want_y=True)
+    Wo = oracle_mod.sketch_w(A64, None, lq, 5, prec)
+    bound = _absbound(A64, np.arange(N), lq, 5, prec, oracle_mod)
+    assert np.all(np.abs(host(W) - Wo) <= RTOL[prec] * bound + 1e-30)
+    Om = oracle_mod.omega(5, n, l, prec)
+    Yo = oracle_mod.sketch_y(A64, Om, prec)
+    ybound = np.abs(oracle_mod.data_values(A64, prec)) @ np.abs(Om)
+    assert np.all(np.abs(host(Y).astype(np.float64) - Yo) <= RTOL[prec] * ybound + 1e-30)
+    st = sid.Stream(N, n, k, p, seed=5, dtype=torch.float32, mode="single_pass", prec=prec,
+                    probe_rows=q)
+    for c0, w in _blocks(n, [300, 7, 450, 64]):
+        st.push(A[:, c0:c0 + w])
+    got = st.finish()
+    ref = sid.compress(A, k, p, seed=5, mode="single_pass", prec=prec, probe_rows=q)
+    torch.cuda.synchronize()
+    assert host(got.J).tolist() == host(ref.J).tolist()
+    assert np.array_equal(host(got.P), host(ref.P))
+    np.testing.assert_allclose(host(got.AJ), host(ref.AJ), rtol=0,
+                               atol=2e-4 * np.abs(host(ref.AJ)).max())
+
+
 def test_graph_capture_replay(sid, oracle_mod):
     """sid_reserve covers every allocation of a compress call; the call is
     then captured into a HIP graph and replayed several times, with eager
