@@ -57,7 +57,7 @@ void* noalloc_scratch_init(int device) {
 enum Slot {
   WS_OMEGA, WS_PART, WS_W, WS_WR, WS_NRM, WS_PIV, WS_R, WS_Q, WS_KEFF, WS_STATS, WS_PD,
   WS_ERR, WS_Y, WS_M, WS_MPR, WS_WJ, WS_PIVM, WS_RM, WS_QM, WS_RKM, WS_C, WS_T, WS_MIX,
-  WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COOP, WS_SYNC, WS_R11, WS_FITPART, WS_YTMP, WS_REF_W, WS_REF_WJ, WS_OMP, WS_A8, WS_IACJT, WS_IPB, WS_IB, WS_IPART, WS_AZ, WS_AE2, WS_APART, WS_SV_H, WS_SV_B, WS_SV_Q, WS_SV_OM32,
+  WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COOP, WS_SYNC, WS_R11, WS_R11M, WS_FITPART, WS_YTMP, WS_REF_W, WS_REF_WJ, WS_OMP, WS_A8, WS_IACJT, WS_IPB, WS_IB, WS_IPART, WS_AZ, WS_AE2, WS_APART, WS_SV_H, WS_SV_B, WS_SV_Q, WS_SV_OM32,
   WS_SV_OM, WS_SV_SMALL, WS_SV_WP, WS_SV_TSP, WS_PROBE, WS_COUNT
 };
 
@@ -337,6 +337,7 @@ struct Work {
   void* coop;
   unsigned int* sync2;
   double* R11;
+  double* R11M;  // single pass: the triangular factor of M's solve (beside R11's use)
   double* fitpart;
 };
 
@@ -398,8 +399,9 @@ sid_status reserve(sid_ctx* c, const Shape& s, Work* w, bool sketch_bufs = true)
     w->pivM = (int64_t*)ws(c, WS_PIVM, sizeof(int64_t) * (size_t)s.l);
     w->rkM = (int64_t*)ws(c, WS_RKM, sizeof(int64_t));
     w->om64 = (double*)ws(c, WS_OM64, d * (size_t)(s.n * s.l));
+    w->R11M = (double*)ws(c, WS_R11M, d * (size_t)(s.l * s.l));
     if (!w->om64 || !w->Y || !w->M || !w->Mpr || !w->WJ || !w->RM || !w->QM || !w->C || !w->T || !w->mix ||
-        !w->statsM || !w->pivM || !w->rkM)
+        !w->statsM || !w->pivM || !w->rkM || !w->R11M)
       return SID_ENOMEM;
   }
   return SID_OK;
@@ -1144,17 +1146,26 @@ static sid_status factor(sid_ctx* ctx, const sid_params* p, const Shape& sh, con
     SID_CHECK(sid::launch_probe_adapt(st, w.W, lq, lz, q, n_, w.piv, w.keff, w.R, k, w.R11, w.az,
                                       w.apart, w.ae2, p->probe_tol),
               "adaptive rank");
-  // (3) coefficients P = R11^{-1} R(:, j) on the non-pivot columns
-  SID_CHECK(sid::launch_id_coefficients(st, w.R, n_, w.piv, w.keff, k, w.R11, w.Pd, P, ldp, f64),
+  // (3) coefficients P = R11^{-1} R(:, j) on the non-pivot columns, and
+  // (4) the estimates: err[1] sketch fit (final residual of mgsqr, or at an
+  // adaptive rank the fit of the selection rows), err[0] probe rows.  In
+  // single pass with the side stream, P and err[1] are formed there while
+  // the main stream goes on to T and AJ (they do not depend on P).
+  const bool p_side = sh.single && overlap && AJ && !adaptive;
+  hipStream_t ps = st;
+  if (p_side) {
+    SID_CHECK(hipEventRecord(ctx->side_fork, st), "side fork");
+    SID_CHECK(hipStreamWaitEvent(ctx->side, ctx->side_fork, 0), "side fork wait");
+    ps = ctx->side;
+  }
+  SID_CHECK(sid::launch_id_coefficients(ps, w.R, n_, w.piv, w.keff, k, w.R11, w.Pd, P, ldp, f64),
             "coefficients");
-  // (4) estimates: err[1] sketch fit (final residual of mgsqr, or at an
-  // adaptive rank the fit of the selection rows), err[0] probe rows
   if (adaptive)
     SID_CHECK(sid::launch_fit_residual(st, w.W, lq, 0, l, n_, w.piv, w.keff, w.Pd, k, nullptr,
                                        w.fitpart, w.err + 1),
               "sketch residual");
   else
-    SID_CHECK(sid::launch_ratio_sqrt(st, w.stats, w.err + 1), "sketch residual");
+    SID_CHECK(sid::launch_ratio_sqrt(ps, w.stats, w.err + 1), "sketch residual");
   if (!sh.single) {
     SID_CHECK(sid::launch_fit_residual(st, w.W, lq, l, q, n_, w.piv, w.keff, w.Pd, k, nullptr,
                                        w.fitpart, w.err),
@@ -1176,10 +1187,12 @@ static sid_status factor(sid_ctx* ctx, const sid_params* p, const Shape& sh, con
     // the ill-conditioned case the paper warns about in Sec. 2.3).  M^+ is
     // applied through mgsqr of M (step 5a) truncated at sp_rcond (least
     // squares on the pivoted columns).
+    // (the join recorded after M's mgsqr: the coefficients queued on the
+    // side stream since are not waited for here)
     if (overlap) SID_CHECK(hipStreamWaitEvent(st, ctx->side_join, 0), "side join wait");
     SID_CHECK(sid::launch_gather_block(st, w.W, lq, 0, lz, w.piv, w.keff, k, w.WJ), "W(:, J)");
     SID_CHECK(sid::launch_gemm64(st, l, k, lz, w.QM, lz, 1, w.WJ, lz, 0, w.C, l), "QM^T W(:, J)");
-    SID_CHECK(sid::launch_small_solve(st, w.RM, l, w.pivM, w.rkM, w.R11, w.C, l, k, w.T), "T");
+    SID_CHECK(sid::launch_small_solve(st, w.RM, l, w.pivM, w.rkM, w.R11M, w.C, l, k, w.T), "T");
     // the probe estimate needs T but not AJ: on the side stream it runs
     // during AJ = Y T (and the err / J copies below wait for it)
     hipStream_t es = st;
@@ -2500,7 +2513,7 @@ sid_status svd_blocks(sid_ctx* ctx, const sid_svd_params* sp, sid_dtype dtype, i
   const size_t le = (size_t)(l + (l & 1));
   const size_t nsmall = 2 * (size_t)(n * b) + 2 * (size_t)(l * b) + 2 * (size_t)(b * b) +
                         2 * (size_t)(l * l) + 2 * (size_t)(l * k) + 4 + (size_t)(n * k) + le * le +
-                        sid::jacobi_rot_doubles((int)l);
+                        sid::jacobi_rot_doubles((int)l) + 2;
   double* sm = (double*)ws(ctx, WS_SV_SMALL, d * nsmall);
   if (!Bt || !Q || !om32 || !om || !tsp || !sm) return SID_ENOMEM;
   double* Y0 = sm;
@@ -2517,6 +2530,8 @@ sid_status svd_blocks(sid_ctx* ctx, const sid_svd_params* sp, sid_dtype dtype, i
   double* Uo = mind + 4;
   double* Jw = Uo + n * k;  // Jacobi's working matrix when l > 128
   double* Jrot = Jw + le * le;  // Jacobi's rotation records
+  // the stop test's state on the device: basis columns so far, stopped flag
+  int64_t* jstate = (int64_t*)(Jrot + sid::jacobi_rot_doubles((int)l));
   // X^T Y over the N rows in blocks of at most 128 x 128 (the product
   // kernel's limit); C gets alpha X^T Y + beta C
   auto tsmm = [&](const double* X, int p, const double* Y, int64_t ysr, int64_t ysc, int q,
@@ -2531,10 +2546,13 @@ sid_status svd_blocks(sid_ctx* ctx, const sid_svd_params* sp, sid_dtype dtype, i
       }
     return hipSuccess;
   };
-  // ||G||_F^2 for the stop test (read with the first block's pivot test)
+  // ||G||_F^2 for the stop test
   SID_CHECK(sid::launch_sumsq(hs, W, l * n, mind + 3), "||G||^2");
-  double gnorm = -1.0;
-  // (2) the blocks
+  // (2) the blocks.  The stop test runs on the device (in k_trmul), so the
+  // blocks are queued without waiting for it: after a rank-deficient block
+  // the remaining blocks only write basis columns past the stop, which the
+  // steps after the loop never read; one read of the column count follows
+  // the loop.  j counts the columns the queued blocks assume.
   int64_t j = 0;
   const int64_t s = l / b;
   for (int64_t i = 0; i < s; ++i) {
@@ -2560,14 +2578,8 @@ sid_status svd_blocks(sid_ctx* ctx, const sid_svd_params* sp, sid_dtype dtype, i
                 "Q_i - Q Q^T Q_i");
     }
     SID_CHECK(sid::launch_small_qr(hs, Y, (int)n, (int)b, Rt), "qr again");
-    SID_CHECK(sid::launch_trmul(hs, Rt, R, (int)b, mind), "R_i = R~_i R_i");
-    double mh[4] = {0.0, 0.0, 0.0, 0.0};
-    SID_CHECK(hipMemcpyAsync(mh, mind, 4 * d, hipMemcpyDeviceToHost, hs), "min diag");
-    SID_CHECK(hipStreamSynchronize(hs), "synchronize");
-    const double mdiag = mh[0];
-    if (gnorm < 0.0) gnorm = std::sqrt(mh[3]);
-    // A_p Omega of rank below l: the blocks so far span it (stop)
-    if (!(mdiag > 1e-12 * gnorm)) break;
+    SID_CHECK(sid::launch_trmul(hs, Rt, R, (int)b, mind, mind + 3, i, jstate),
+              "R_i = R~_i R_i and the stop test");
     // B_i^T = (H_i - B^T (Q^T Y_i + B Omega_i)) R_i^-1 into the next b columns
     // of B^T, one pass over the rows
     double* Bi = Bt + j * N;
@@ -2579,6 +2591,13 @@ sid_status svd_blocks(sid_ctx* ctx, const sid_svd_params* sp, sid_dtype dtype, i
     SID_CHECK(hipMemcpyAsync(Q + j * n, Y, d * (size_t)(n * b), hipMemcpyDeviceToDevice, hs),
               "Q_i");
     j += b;
+  }
+  {
+    int64_t jd = 0;
+    SID_CHECK(hipMemcpyAsync(&jd, jstate, sizeof(int64_t), hipMemcpyDeviceToHost, hs),
+              "basis column count");
+    SID_CHECK(hipStreamSynchronize(hs), "synchronize");
+    j = jd;
   }
   if (rank) *rank = j;
   if (j == 0) {

@@ -90,7 +90,9 @@ __global__ __launch_bounds__(QR_THREADS) void k_small_qr(double* __restrict__ Y,
 // also the smallest |R(c, c)| into *mindiag
 __global__ __launch_bounds__(SV_THREADS) void k_trmul(const double* __restrict__ Rt,
                                                       double* __restrict__ R, int b,
-                                                      double* __restrict__ mindiag) {
+                                                      double* __restrict__ mindiag,
+                                                      const double* __restrict__ g2, int64_t blk,
+                                                      int64_t* __restrict__ state) {
   __shared__ double out[64 * 64];
   for (int e = threadIdx.x; e < b * b; e += SV_THREADS) {
     const int i = e % b, j = e / b;
@@ -105,6 +107,14 @@ __global__ __launch_bounds__(SV_THREADS) void k_trmul(const double* __restrict__
     double m = INFINITY;
     for (int c = 0; c < b; ++c) m = fmin(m, fabs(out[c + b * c]));
     *mindiag = m;
+    // the stop test: A_p Omega of rank below the columns so far means the
+    // blocks before this one span it
+    const int64_t stopped = blk == 0 ? 0 : state[1];
+    if (!stopped) {
+      const bool deficient = !(m > 1e-12 * sqrt(*g2));
+      state[0] = deficient ? blk * b : (blk + 1) * b;
+      state[1] = deficient ? 1 : 0;
+    }
   }
 }
 
@@ -467,9 +477,10 @@ hipError_t launch_small_qr(hipStream_t st, double* Y, int n, int b, double* R) {
   return hipGetLastError();
 }
 
-hipError_t launch_trmul(hipStream_t st, const double* Rt, double* R, int b, double* mindiag) {
-  if (b > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_trmul, dim3(1), dim3(SV_THREADS), 0, st, Rt, R, b, mindiag);
+hipError_t launch_trmul(hipStream_t st, const double* Rt, double* R, int b, double* mindiag,
+                        const double* g2, int64_t blk, int64_t* state) {
+  if (b > 64 || !g2 || !state || blk < 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_trmul, dim3(1), dim3(SV_THREADS), 0, st, Rt, R, b, mindiag, g2, blk, state);
   return hipGetLastError();
 }
 

@@ -7,8 +7,13 @@ namespace sid {
 
 // in-place thin QR (CGS2) of Y (n x b, ld n), R (b x b, ld b); b <= 64
 hipError_t launch_small_qr(hipStream_t st, double* Y, int n, int b, double* R);
-// R = Rt R for b x b upper triangular factors (ld b); min |R(c, c)| into *mindiag
-hipError_t launch_trmul(hipStream_t st, const double* Rt, double* R, int b, double* mindiag);
+// R = Rt R for b x b upper triangular factors (ld b); min |R(c, c)| into *mindiag.
+// The block loop's stop test on the device: state[0] = columns of the basis
+// so far, state[1] = 1 once a block was rank deficient (reset at blk = 0);
+// block blk counts (state[0] = (blk + 1) b) unless min |R(c, c)| <=
+// 1e-12 sqrt(*g2), which stops the loop at blk b columns for good.
+hipError_t launch_trmul(hipStream_t st, const double* Rt, double* R, int b, double* mindiag,
+                        const double* g2, int64_t blk, int64_t* state);
 // Jacobi eigensolver of a symmetric m x m matrix (ld m, m <= 256; the upper
 // triangle is read): M becomes
 // diagonal (eigenvalues), V (m x m, ld m) the eigenvectors; work: (m rounded
