@@ -1037,14 +1037,7 @@ static sid_status refine_pass(sid_ctx* ctx, const void* A, sid_dtype dtype, int6
             "sketch residual (refined P)");
   // a pivot whose column W' reproduces from the earlier ones ends the forced
   // factorization early: J and k_eff are copied again
-  if (J) SID_CHECK(hipMemcpyAsync(J, w.piv, sizeof(int64_t) * (size_t)k, hipMemcpyDeviceToDevice, st),
-                   "copy J");
-  if (k_eff)
-    SID_CHECK(hipMemcpyAsync(k_eff, w.keff, sizeof(int64_t), hipMemcpyDeviceToDevice, st),
-              "copy k_eff");
-  if (err)
-    SID_CHECK(hipMemcpyAsync(err, w.err, 2 * sizeof(double), hipMemcpyDeviceToDevice, st),
-              "copy err");
+  SID_CHECK(sid::launch_copy_results(st, J, w.piv, k, k_eff, w.keff, err, w.err), "results");
   return SID_OK;
 }
 
@@ -1228,14 +1221,7 @@ static sid_status factor(sid_ctx* ctx, const sid_params* p, const Shape& sh, con
     }
     if (es != st) SID_CHECK(hipStreamWaitEvent(st, ctx->side_join, 0), "side join wait");
   }
-  if (J) SID_CHECK(hipMemcpyAsync(J, w.piv, sizeof(int64_t) * (size_t)k, hipMemcpyDeviceToDevice, st),
-                   "copy J");
-  if (k_eff)
-    SID_CHECK(hipMemcpyAsync(k_eff, w.keff, sizeof(int64_t), hipMemcpyDeviceToDevice, st),
-              "copy k_eff");
-  if (err)
-    SID_CHECK(hipMemcpyAsync(err, w.err, 2 * sizeof(double), hipMemcpyDeviceToDevice, st),
-              "copy err");
+  SID_CHECK(sid::launch_copy_results(st, J, w.piv, k, k_eff, w.keff, err, w.err), "results");
   return SID_OK;
 }
 

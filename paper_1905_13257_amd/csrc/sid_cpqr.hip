@@ -84,7 +84,7 @@ __global__ __launch_bounds__(CQ_THREADS) void k_cpqr_coop(
     double* __restrict__ pub_col, double* __restrict__ red, unsigned int* __restrict__ bar,
     unsigned int* __restrict__ fail, int64_t* __restrict__ piv, double* __restrict__ R,
     double* __restrict__ Q, int64_t* __restrict__ keff, double* __restrict__ stats,
-    const int64_t* __restrict__ forced) {
+    const int64_t* __restrict__ forced, unsigned int* __restrict__ sticky) {
   static_assert(TPC * RPT <= CQ_MSTRIDE, "published column slot");
   constexpr int CQ_TPC = TPC;
   constexpr int CQ_CPW = CQ_THREADS / TPC;
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(CQ_THREADS) void k_cpqr_coop(
   __shared__ double s_wv[CQ_THREADS / 64];
   __shared__ int s_wj[CQ_THREADS / 64];
   __shared__ double s_win_v;
-  __shared__ int s_win_j, s_win_g;
+  __shared__ int s_win_j, s_win_g, s_failed;
   __shared__ double s_sum[2][CQ_THREADS / 64];
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -235,19 +235,29 @@ __global__ __launch_bounds__(CQ_THREADS) void k_cpqr_coop(
     for (int u = 0; u < CQ_THREADS / 64; ++u) { sa += s_sum[0][u]; sb += s_sum[1][u]; }
     red[2 * g] = sa;
     red[2 * g + 1] = sb;
-    __threadfence();
-    ok = grid_barrier(bar, (unsigned)G * (unsigned)(nbar + 1)) && ok;
+    // a timed-out wait of this workgroup is recorded before its arrival
     if (!ok) atomicOr(fail, 1u);
+    __threadfence();
+    const bool okb = grid_barrier(bar, (unsigned)G * (unsigned)(nbar + 1));
+    if (!okb) atomicOr(fail, 1u);
     if (g == 0) {
       double ta = 0.0, tb = 0.0;
       for (int h = 0; h < G; ++h) { ta += ld_agent(&red[2 * h]); tb += ld_agent(&red[2 * h + 1]); }
       stats[0] = ta;
       stats[1] = tb;
+      s_failed = (!okb || ld_agent(fail) != 0u) ? 1 : 0;
     }
   }
   if (g == 0) {
+    __syncthreads();
     for (int i = k + tid; i < kmax; i += CQ_THREADS) piv[i] = -1;
-    if (tid == 0) *keff = k;
+    // keff = -1 marks a timed-out wait (results invalid); the context's
+    // sticky flag keeps it until the host reads it (sid_sync)
+    if (tid == 0) {
+      const bool failed = s_failed != 0;
+      *keff = failed ? -1 : k;
+      if (failed && sticky) *sticky = 1u;
+    }
   }
 }
 
@@ -604,15 +614,6 @@ hipError_t launch_cpqr_wgl(hipStream_t st, const double* X, int64_t ldx, int m, 
   return hipGetLastError();
 }
 
-// keff := -1 when a cooperative wait timed out (results invalid); the
-// context's sticky flag records it until the host reads it (sid_sync)
-__global__ void k_mark_failure(const unsigned int* fail, int64_t* keff, unsigned int* sticky) {
-  if (threadIdx.x == 0 && blockIdx.x == 0 && *fail) {
-    *keff = -1;
-    if (sticky) *sticky = 1u;
-  }
-}
-
 bool cpqr_coop_supported(int m, int nc) { return m <= 256 && nc <= 64 * CQ_MINCPW && nc >= 1; }
 
 static int coop_tpc(int m, int nc) {
@@ -645,7 +646,7 @@ hipError_t launch_cpqr_coop(hipStream_t st, const double* X, int64_t ldx, int m,
   void* args[] = {(void*)&X, (void*)&ldx, (void*)&m, (void*)&nc, (void*)&kmax, (void*)&rank_tol,
                   (void*)&G, (void*)&stride, (void*)&pub_v, (void*)&pub_j, (void*)&pub_col,
                   (void*)&red, (void*)&bar, (void*)&fail, (void*)&piv, (void*)&R, (void*)&Q,
-                  (void*)&keff, (void*)&stats, (void*)&forced};
+                  (void*)&keff, (void*)&stats, (void*)&forced, (void*)&sticky};
   const int rpt = (m + tpc - 1) / tpc;
   const void* kern =
       tpc == 2 ? (rpt <= 8    ? (const void*)k_cpqr_coop<2, 8>
@@ -668,9 +669,7 @@ hipError_t launch_cpqr_coop(hipStream_t st, const double* X, int64_t ldx, int m,
   const hipError_t e = cooperative
                            ? hipLaunchCooperativeKernel(kern, grid, block, args, 0, st)
                            : hipLaunchKernel(kern, grid, block, args, 0, st);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_mark_failure, dim3(1), dim3(64), 0, st, fail, keff, sticky);
-  return hipGetLastError();
+  return e;
 }
 
 // ---------------------------------------------------------------------------

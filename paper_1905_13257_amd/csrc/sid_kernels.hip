@@ -820,6 +820,26 @@ __global__ void k_add_inplace(T* __restrict__ y, const T* __restrict__ x, int64_
     y[e] += x[e];
 }
 
+// the results a compression hands back, in one launch: J (k pivots), k_eff
+// and the two estimates (each skipped when its destination is NULL)
+__global__ void k_copy_results(int64_t* __restrict__ J, const int64_t* __restrict__ piv, int k,
+                               int64_t* __restrict__ k_eff, const int64_t* __restrict__ keff,
+                               double* __restrict__ err, const double* __restrict__ werr) {
+  const int t = threadIdx.x;
+  if (J)
+    for (int i = t; i < k; i += blockDim.x) J[i] = piv[i];
+  if (t == 0 && k_eff) *k_eff = *keff;
+  if (t < 2 && err) err[t] = werr[t];
+}
+
+hipError_t launch_copy_results(hipStream_t st, int64_t* J, const int64_t* piv, int k,
+                               int64_t* k_eff, const int64_t* keff, double* err,
+                               const double* werr) {
+  if (!J && !k_eff && !err) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_results, dim3(1), dim3(256), 0, st, J, piv, k, k_eff, keff, err, werr);
+  return hipGetLastError();
+}
+
 hipError_t launch_add_inplace(hipStream_t st, bool f64, void* y, const void* x, int64_t count,
                               int num_cu) {
   if (count <= 0) return hipSuccess;

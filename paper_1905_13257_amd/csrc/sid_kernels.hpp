@@ -55,6 +55,10 @@ hipError_t launch_gemm64_ab(hipStream_t st, int M, int Nn, int K, const double* 
                             double* C, int64_t ldc);
 hipError_t launch_add_inplace(hipStream_t st, bool f64, void* y, const void* x, int64_t count,
                               int num_cu);
+// J = piv (k entries), *k_eff = *keff, err[0:2] = werr[0:2]; NULL destinations skipped
+hipError_t launch_copy_results(hipStream_t st, int64_t* J, const int64_t* piv, int k,
+                               int64_t* k_eff, const int64_t* keff, double* err,
+                               const double* werr);
 hipError_t launch_gather_r11(hipStream_t st, const double* R, int nc, const int64_t* piv,
                              const int64_t* keff, int kcap, double* R11);
 hipError_t launch_gather_cols(hipStream_t st, const void* src, bool src_f64, int64_t lds,
