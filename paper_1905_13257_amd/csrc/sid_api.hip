@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -70,12 +71,22 @@ struct Buf {
 // only for exactly the same values)
 struct BatchSig {
   const void* A;
-  int64_t N, n, lda, lq, l;
+  int64_t N, n, lda, lq, l, lz, k;
   uint64_t seed;
+  double rank_tol, rcond;  // the mgsqr jobs' stopping tolerances
   bool operator==(const BatchSig& o) const {
     return A == o.A && N == o.N && n == o.n && lda == o.lda && lq == o.lq && l == o.l &&
-           seed == o.seed;
+           lz == o.lz && k == o.k && seed == o.seed && rank_tol == o.rank_tol && rcond == o.rcond;
   }
+};
+
+// One problem's factorization results that the batched mgsqr launches write
+// (W's mgsqr; in single pass also M = W(0:lz, :) Omega, Mpr and M's mgsqr)
+struct BatchFactor {
+  bool pre = false;  // its mgsqr runs in the batched launches
+  int64_t *piv = nullptr, *keff = nullptr, *pivM = nullptr, *rkM = nullptr;
+  double *R = nullptr, *Q = nullptr, *stats = nullptr, *om64 = nullptr, *M = nullptr,
+         *Mpr = nullptr, *RM = nullptr, *QM = nullptr, *statsM = nullptr;
 };
 
 // Device state of one batch of problems for the persistent sketch pass: the
@@ -94,6 +105,10 @@ struct BatchPlan {
   int max_n = 0;
   std::vector<double*> W;       // by problem index
   std::vector<float*> Y, omega;
+  std::vector<BatchFactor> fac;  // by problem index
+  // the batched mgsqr launches: jobs grouped by kernel instance
+  sid::CpqrJob* d_jobs = nullptr;
+  std::vector<std::array<int, 3>> job_groups;  // (instance, first job, count)
 };
 
 }  // namespace
@@ -225,6 +240,19 @@ struct Shape {
   bool single;
   int prec;
 };
+
+// which mgsqr kernel an (m x nc) factorization uses.  0: one workgroup,
+// residual in registers; 3: one workgroup, part of it in LDS (up to 96 rows:
+// beyond, its LDS traffic per step costs more than the cooperative kernel's
+// device-wide barrier; measured at 120 x 500); 1: several workgroups; 2: the
+// general kernel.  (The cooperative and the general kernels use context
+// scratch, so two of the same kind must not run at once.)
+int mgsqr_kind(int m, int nc) {
+  return sid::cpqr_wg_supported(m, nc)                 ? 0
+         : (m <= 96 && sid::cpqr_wgl_supported(m, nc)) ? 3
+         : sid::cpqr_coop_supported(m, nc)             ? 1
+                                                       : 2;
+}
 
 double default_rcond(int prec) {
   switch (prec) {
@@ -714,7 +742,8 @@ sid_status sid_reserve(sid_ctx* ctx, int64_t N, int64_t n, const sid_params* p) 
 
 static sid_status factor(sid_ctx* ctx, const sid_params* p, const Shape& sh, const Work& w,
                          sid_dtype dtype, const void* A, int64_t lda, int64_t* J, void* P,
-                         int64_t ldp, void* AJ, int64_t ldaj, double* err, int64_t* k_eff);
+                         int64_t ldp, void* AJ, int64_t ldaj, double* err, int64_t* k_eff,
+                         bool prefactored = false);
 static sid_status refine_pass(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t lda,
                               const sid_params* p, const Shape& sh, const Work& w, int64_t* J,
                               void* P, int64_t ldp, double* err, int64_t* k_eff);
@@ -1044,27 +1073,18 @@ static sid_status refine_pass(sid_ctx* ctx, const void* A, sid_dtype dtype, int6
 // Everything after the sketch pass, from W (w.W, lq x n), single pass also
 // Y (w.Y) and Omega's values (w.omega, n x l): mgsqr, coefficients,
 // estimates and the skeleton.  A is read only by the two-pass gather.
+// prefactored (the batched path): mgsqr of W_sel and, in single pass, M,
+// Mpr, Omega's FP64 values and mgsqr of M are already in w (steps 5a and 2
+// are skipped).
 static sid_status factor(sid_ctx* ctx, const sid_params* p, const Shape& sh, const Work& w,
                          sid_dtype dtype, const void* A, int64_t lda, int64_t* J, void* P,
-                         int64_t ldp, void* AJ, int64_t ldaj, double* err, int64_t* k_eff) {
+                         int64_t ldp, void* AJ, int64_t ldaj, double* err, int64_t* k_eff,
+                         bool prefactored) {
   hipStream_t st = ctx->stream;
   const bool f64 = dtype == SID_F64;
   const int k = (int)sh.k, l = (int)sh.l, q = (int)sh.q, lz = (int)sh.lz, lq = (int)sh.lq,
             n_ = (int)sh.n;
-  // which mgsqr kernel each factorization uses (the cooperative and the
-  // general kernels use context scratch, so two of the same kind must not
-  // run at once)
-  auto kind = [](int m, int nc) {
-    // 0: one workgroup, residual in registers; 3: one workgroup, part of it
-    // in LDS (up to 96 rows: beyond, its LDS traffic per step costs more than
-    // the cooperative kernel's device-wide barrier; measured at 120 x 500);
-    // 1: several workgroups; 2: the general kernel
-    return sid::cpqr_wg_supported(m, nc)                 ? 0
-           : (m <= 96 && sid::cpqr_wgl_supported(m, nc)) ? 3
-           : sid::cpqr_coop_supported(m, nc)             ? 1
-                                                         : 2;
-  };
-  const int w_kind = kind(l, n_);
+  const int w_kind = mgsqr_kind(l, n_);
   // a cooperative launch cannot be recorded into a graph: under capture the
   // multi-workgroup QR is a plain launch (its bounded waits report through
   // the sticky flag)
@@ -1074,20 +1094,20 @@ static sid_status factor(sid_ctx* ctx, const sid_params* p, const Shape& sh, con
     if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
       coop_launch = false;
   }
-  const int m_kind = sh.single ? kind(lz, l) : 0;
+  const int m_kind = sh.single ? mgsqr_kind(lz, l) : 0;
   const bool overlap = sh.single && !(m_kind == w_kind && (m_kind == 1 || m_kind == 2));
+  if (overlap && !ctx->side) {
+    SID_CHECK(hipStreamCreate(&ctx->side), "side stream");
+    SID_CHECK(hipEventCreateWithFlags(&ctx->side_fork, hipEventDisableTiming), "side event");
+    SID_CHECK(hipEventCreateWithFlags(&ctx->side_join, hipEventDisableTiming), "side event");
+  }
   const double rcond = p->sp_rcond > 0.0 ? p->sp_rcond : default_rcond(sh.prec);
-  if (sh.single) {
+  if (sh.single && !prefactored) {
     // (5a) single pass, independent of the pivots: M = W(0:lz, :) Omega,
     // Mpr = W_pr Omega and mgsqr of M, on a side stream when they can
     // overlap mgsqr of W (step 2)
     hipStream_t ms = st;
     if (overlap) {
-      if (!ctx->side) {
-        SID_CHECK(hipStreamCreate(&ctx->side), "side stream");
-        SID_CHECK(hipEventCreateWithFlags(&ctx->side_fork, hipEventDisableTiming), "side event");
-        SID_CHECK(hipEventCreateWithFlags(&ctx->side_join, hipEventDisableTiming), "side event");
-      }
       SID_CHECK(hipEventRecord(ctx->side_fork, st), "side fork");
       SID_CHECK(hipStreamWaitEvent(ctx->side, ctx->side_fork, 0), "side fork wait");
       ms = ctx->side;
@@ -1116,7 +1136,9 @@ static sid_status factor(sid_ctx* ctx, const sid_params* p, const Shape& sh, con
     if (overlap) SID_CHECK(hipEventRecord(ctx->side_join, ctx->side), "side join");
   }
   // (2) mgsqr on the selection rows of W
-  if (w_kind == 3)
+  if (prefactored) {
+    // (run by the batched launches)
+  } else if (w_kind == 3)
     SID_CHECK(sid::launch_cpqr_wgl(st, w.W, lq, l, n_, k, p->rank_tol, w.piv, w.R, w.Q, w.keff,
                                    w.stats),
               "pivoted QR");
@@ -1182,7 +1204,8 @@ static sid_status factor(sid_ctx* ctx, const sid_params* p, const Shape& sh, con
     // squares on the pivoted columns).
     // (the join recorded after M's mgsqr: the coefficients queued on the
     // side stream since are not waited for here)
-    if (overlap) SID_CHECK(hipStreamWaitEvent(st, ctx->side_join, 0), "side join wait");
+    if (overlap && !prefactored)
+      SID_CHECK(hipStreamWaitEvent(st, ctx->side_join, 0), "side join wait");
     SID_CHECK(sid::launch_gather_block(st, w.W, lq, 0, lz, w.piv, w.keff, k, w.WJ), "W(:, J)");
     SID_CHECK(sid::launch_gemm64(st, l, k, lz, w.QM, lz, 1, w.WJ, lz, 0, w.C, l), "QM^T W(:, J)");
     SID_CHECK(sid::launch_small_solve(st, w.RM, l, w.pivM, w.rkM, w.R11M, w.C, l, k, w.T), "T");
@@ -1773,7 +1796,9 @@ sid_status batch_plan(sid_ctx* ctx, const sid_problem* probs, int64_t count,
   std::vector<BatchSig> sig((size_t)count);
   for (int64_t b = 0; b < count; ++b) {
     const Shape& s = sh[(size_t)b];
-    sig[(size_t)b] = BatchSig{probs[b].A, s.N, s.n, probs[b].lda, s.lq, s.l, probs[b].params.seed};
+    const sid_params& q = probs[b].params;
+    sig[(size_t)b] = BatchSig{probs[b].A, s.N, s.n, probs[b].lda, s.lq, s.l, s.lz, s.k, q.seed,
+                              q.rank_tol, q.sp_rcond > 0.0 ? q.sp_rcond : default_rcond(s.prec)};
   }
   for (size_t i = 0; i < ctx->plans.size(); ++i) {
     BatchPlan* pl = ctx->plans[i];
@@ -1799,7 +1824,29 @@ sid_status batch_plan(sid_ctx* ctx, const sid_problem* probs, int64_t count,
     return rpw[(size_t)x] * sh[(size_t)x].n > rpw[(size_t)y] * sh[(size_t)y].n;
   });
   auto up = [](size_t v) { return (v + 255) / 256 * 256; };
-  size_t bytes = up(sizeof(sid::FbBatchEntry) * (size_t)count) + 256;
+  // the problems whose mgsqr runs in the batched launches: the one-workgroup
+  // kernels take W_sel (and, single pass, M)
+  auto batchable = [](int m, int nc) {
+    const int kd = mgsqr_kind(m, nc);
+    return kd == 0 || kd == 3;
+  };
+  std::vector<char> pre((size_t)count);
+  for (int64_t b = 0; b < count; ++b) {
+    const Shape& s = sh[(size_t)b];
+    pre[(size_t)b] = batchable((int)s.l, (int)s.n) && (!wanty || batchable((int)s.lz, (int)s.l));
+  }
+  const size_t d = sizeof(double), i8 = sizeof(int64_t);
+  auto fac_bytes = [&](const Shape& s) {
+    size_t v = up(i8 * (size_t)s.k) + up(d * (size_t)(s.k * s.n)) + up(d * (size_t)(s.l * s.k)) +
+               up(i8) + up(2 * d);
+    if (wanty)
+      v += up(d * (size_t)(s.n * s.l)) + up(d * (size_t)(s.lz * s.l)) +
+           up(d * (size_t)((s.q > 0 ? s.q : 1) * s.l)) + up(i8 * (size_t)s.l) +
+           up(d * (size_t)(s.l * s.l)) + up(d * (size_t)(s.lz * s.l)) + up(i8) + up(2 * d);
+    return v;
+  };
+  size_t bytes = up(sizeof(sid::FbBatchEntry) * (size_t)count) + 256 +
+                 up(sizeof(sid::CpqrJob) * (size_t)(2 * count));
   for (int64_t b = 0; b < count; ++b) {
     const Shape& s = sh[(size_t)b];
     bytes += up(sizeof(float) * (size_t)(nsh[(size_t)b] * s.lq * s.n)) +
@@ -1807,6 +1854,7 @@ sid_status batch_plan(sid_ctx* ctx, const sid_problem* probs, int64_t count,
     if (wanty)
       bytes += up(sizeof(float) * (size_t)(s.n * s.l)) + up(sizeof(uint16_t) * 128 * 512) +
                up(sizeof(float) * (size_t)(s.N * s.l));
+    if (pre[(size_t)b]) bytes += fac_bytes(s);
   }
   if (ctx->plans.size() >= SID_BATCH_PLANS) {
     // the oldest plan goes; nothing queued may still read it
@@ -1837,9 +1885,11 @@ sid_status batch_plan(sid_ctx* ctx, const sid_problem* probs, int64_t count,
   };
   pl->d_tab = (sid::FbBatchEntry*)take(sizeof(sid::FbBatchEntry) * (size_t)count);
   pl->d_queue = (unsigned int*)take(256);
+  pl->d_jobs = (sid::CpqrJob*)take(sizeof(sid::CpqrJob) * (size_t)(2 * count));
   pl->W.assign((size_t)count, nullptr);
   pl->Y.assign((size_t)count, nullptr);
   pl->omega.assign((size_t)count, nullptr);
+  pl->fac.assign((size_t)count, BatchFactor{});
   std::vector<sid::FbBatchEntry> tab((size_t)count);
   int64_t share0 = 0;
   for (int64_t qpos = 0; qpos < count; ++qpos) {
@@ -1875,8 +1925,55 @@ sid_status batch_plan(sid_ctx* ctx, const sid_problem* probs, int64_t count,
     if (s.lq * s.n > pl->max_lqn) pl->max_lqn = s.lq * s.n;
   }
   pl->nshares = share0;
+  // the factorization buffers and the mgsqr jobs (W_sel's, then M's),
+  // grouped by kernel instance
+  std::vector<std::pair<int, sid::CpqrJob>> jobs;
+  for (int64_t b = 0; b < count; ++b) {
+    if (!pre[(size_t)b]) continue;
+    const Shape& s = sh[(size_t)b];
+    const BatchSig& g = sig[(size_t)b];
+    BatchFactor& f = pl->fac[(size_t)b];
+    f.pre = true;
+    f.piv = (int64_t*)take(i8 * (size_t)s.k);
+    f.R = (double*)take(d * (size_t)(s.k * s.n));
+    f.Q = (double*)take(d * (size_t)(s.l * s.k));
+    f.keff = (int64_t*)take(i8);
+    f.stats = (double*)take(2 * d);
+    const bool wl = mgsqr_kind((int)s.l, (int)s.n) == 3;
+    jobs.push_back({sid::cpqr_batch_instance((int)s.l, (int)s.n, wl),
+                    sid::CpqrJob{pl->W[(size_t)b], s.lq, (int)s.l, (int)s.n, (int)s.k, 0,
+                                 g.rank_tol, f.piv, f.R, f.Q, f.keff, f.stats}});
+    if (wanty) {
+      f.om64 = (double*)take(d * (size_t)(s.n * s.l));
+      f.M = (double*)take(d * (size_t)(s.lz * s.l));
+      f.Mpr = (double*)take(d * (size_t)((s.q > 0 ? s.q : 1) * s.l));
+      f.pivM = (int64_t*)take(i8 * (size_t)s.l);
+      f.RM = (double*)take(d * (size_t)(s.l * s.l));
+      f.QM = (double*)take(d * (size_t)(s.lz * s.l));
+      f.rkM = (int64_t*)take(i8);
+      f.statsM = (double*)take(2 * d);
+      const bool ml = mgsqr_kind((int)s.lz, (int)s.l) == 3;
+      jobs.push_back({sid::cpqr_batch_instance((int)s.lz, (int)s.l, ml),
+                      sid::CpqrJob{f.M, s.lz, (int)s.lz, (int)s.l, (int)s.l, 0, g.rcond, f.pivM,
+                                   f.RM, f.QM, f.rkM, f.statsM}});
+    }
+  }
+  std::stable_sort(jobs.begin(), jobs.end(),
+                   [](const std::pair<int, sid::CpqrJob>& x, const std::pair<int, sid::CpqrJob>& y) {
+                     return x.first < y.first;
+                   });
+  std::vector<sid::CpqrJob> jtab;
+  for (size_t i = 0; i < jobs.size(); ++i) {
+    if (i == 0 || jobs[i].first != jobs[i - 1].first)
+      pl->job_groups.push_back({jobs[i].first, (int)i, 0});
+    ++pl->job_groups.back()[2];
+    jtab.push_back(jobs[i].second);
+  }
   hipError_t e = hipMemcpyAsync(pl->d_tab, tab.data(), sizeof(sid::FbBatchEntry) * (size_t)count,
                                 hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess && !jtab.empty())
+    e = hipMemcpyAsync(pl->d_jobs, jtab.data(), sizeof(sid::CpqrJob) * jtab.size(),
+                       hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) {
     (void)hipFree(pl->dev);
@@ -1907,6 +2004,41 @@ sid_status compress_batch(sid_ctx* ctx, const sid_problem* probs, int64_t count,
   SID_CHECK(hipEventRecord(ctx->fork, ctx->stream), "batched: fork event");
   for (int c = 0; c < nstreams; ++c)
     SID_CHECK(hipStreamWaitEvent(ctx->children[c]->stream, ctx->fork, 0), "batched: fork wait");
+  // The mgsqr runs of all problems whose shapes the one-workgroup kernels
+  // take go into a few launches (one per kernel instance), after the small
+  // products they need (single pass: Omega's FP64 values, M and Mpr) on the
+  // child streams; every job gets the bits of the single call.
+  bool any_pre = false;
+  if (persistent)
+    for (const BatchFactor& f : plan->fac) any_pre = any_pre || f.pre;
+  if (any_pre) {
+    if (sh[0].single)
+      for (int64_t b = 0; b < count; ++b) {
+        const BatchFactor& f = plan->fac[(size_t)b];
+        if (!f.pre) continue;
+        const Shape& s = sh[(size_t)b];
+        hipStream_t cs = ctx->children[(size_t)(b % nstreams)]->stream;
+        const int l = (int)s.l, lz = (int)s.lz, lq = (int)s.lq, q = (int)s.q, n_ = (int)s.n;
+        SID_CHECK(sid::launch_omega_values(cs, s.prec, plan->omega[(size_t)b], s.n * s.l, f.om64),
+                  "batched: omega values");
+        SID_CHECK(sid::launch_gemm64(cs, lz, l, n_, plan->W[(size_t)b], lq, 0, f.om64, l, 1, f.M, lz),
+                  "batched: M = W Omega");
+        if (q > 0)
+          SID_CHECK(sid::launch_gemm64(cs, q, l, n_, plan->W[(size_t)b] + lz, lq, 0, f.om64, l, 1,
+                                       f.Mpr, q),
+                    "batched: Mpr = Wpr Omega");
+      }
+    for (int c = 0; c < nstreams; ++c) {
+      SID_CHECK(hipEventRecord(ctx->child_done[c], ctx->children[c]->stream), "batched: join event");
+      SID_CHECK(hipStreamWaitEvent(ctx->stream, ctx->child_done[c], 0), "batched: join wait");
+    }
+    for (const auto& g : plan->job_groups)
+      SID_CHECK(sid::launch_cpqr_batch(ctx->stream, g[0], plan->d_jobs + g[1], g[2]),
+                "batched: pivoted QR");
+    SID_CHECK(hipEventRecord(ctx->fork, ctx->stream), "batched: fork event");
+    for (int c = 0; c < nstreams; ++c)
+      SID_CHECK(hipStreamWaitEvent(ctx->children[c]->stream, ctx->fork, 0), "batched: fork wait");
+  }
   sid_status result = SID_OK;
   for (int64_t b = 0; b < count && result == SID_OK; ++b) {
     const sid_problem& q = probs[b];
@@ -1921,8 +2053,26 @@ sid_status compress_batch(sid_ctx* ctx, const sid_problem* probs, int64_t count,
       w.W = plan->W[(size_t)b];
       w.Y = plan->Y[(size_t)b];
       w.omega = plan->omega[(size_t)b];
+      const BatchFactor& f = plan->fac[(size_t)b];
+      if (f.pre) {
+        w.piv = f.piv;
+        w.R = f.R;
+        w.Q = f.Q;
+        w.keff = f.keff;
+        w.stats = f.stats;
+        if (sh[(size_t)b].single) {
+          w.om64 = f.om64;
+          w.M = f.M;
+          w.Mpr = f.Mpr;
+          w.pivM = f.pivM;
+          w.RM = f.RM;
+          w.QM = f.QM;
+          w.rkM = f.rkM;
+          w.statsM = f.statsM;
+        }
+      }
       result = factor(c, &q.params, sh[(size_t)b], w, dtype, q.A, q.lda, q.J, q.P, q.ldp, q.AJ,
-                      q.ldaj, q.err, q.k_eff);
+                      q.ldaj, q.err, q.k_eff, f.pre);
     } else {
       // row sets are bound to the parent context; the child reads the same
       // device array

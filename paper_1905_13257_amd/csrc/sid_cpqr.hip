@@ -275,11 +275,31 @@ constexpr int CW_THREADS = 512;
 constexpr int CW_WAVES = CW_THREADS / 64;
 constexpr int CW_MMAX = 256;
 
+// a batched launch: this workgroup's job replaces the arguments
+#define SID_CPQR_TAKE_JOB()                                                       \
+  if (jobs) {                                                                     \
+    const CpqrJob jb = jobs[blockIdx.x];                                          \
+    X = jb.X;                                                                     \
+    ldx = jb.ldx;                                                                 \
+    m = jb.m;                                                                     \
+    nc = jb.nc;                                                                   \
+    kmax = jb.kmax;                                                               \
+    rank_tol = jb.rank_tol;                                                       \
+    piv = jb.piv;                                                                 \
+    R = jb.R;                                                                     \
+    Q = jb.Q;                                                                     \
+    keff = jb.keff;                                                               \
+    stats = jb.stats;                                                             \
+    forced = nullptr;                                                             \
+  }
+
 template <int TPC, int RPT>
 __global__ __launch_bounds__(CW_THREADS) void k_cpqr_wg(
     const double* __restrict__ X, int64_t ldx, int m, int nc, int kmax, double rank_tol,
     int64_t* __restrict__ piv, double* __restrict__ R, double* __restrict__ Q,
-    int64_t* __restrict__ keff, double* __restrict__ stats, const int64_t* __restrict__ forced) {
+    int64_t* __restrict__ keff, double* __restrict__ stats, const int64_t* __restrict__ forced,
+    const CpqrJob* __restrict__ jobs) {
+  SID_CPQR_TAKE_JOB()
   constexpr int QN = TPC * RPT;  // rows covered by a column's threads
   __shared__ double s_q[2][QN];
   __shared__ double s_wv[2][CW_WAVES];
@@ -421,7 +441,7 @@ hipError_t launch_cpqr_wg(hipStream_t st, const double* X, int64_t ldx, int m, i
   const int rpt = (m + tpc - 1) / tpc;
 #define SID_CW(TPC_, RPT_)                                                                    \
   hipLaunchKernelGGL((k_cpqr_wg<TPC_, RPT_>), dim3(1), dim3(CW_THREADS), 0, st, X, ldx, m, nc, \
-                     kmax, rank_tol, piv, R, Q, keff, stats, forced)
+                     kmax, rank_tol, piv, R, Q, keff, stats, forced, (const CpqrJob*)nullptr)
 #define SID_CW_R(TPC_)                    \
   if (rpt <= 8) SID_CW(TPC_, 8);          \
   else if (rpt <= 16) SID_CW(TPC_, 16);   \
@@ -457,7 +477,9 @@ template <int RR>
 __global__ __launch_bounds__(CL_THREADS) void k_cpqr_wgl(
     const double* __restrict__ X, int64_t ldx, int m, int nc, int kmax, double rank_tol,
     int64_t* __restrict__ piv, double* __restrict__ R, double* __restrict__ Q,
-    int64_t* __restrict__ keff, double* __restrict__ stats, const int64_t* __restrict__ forced) {
+    int64_t* __restrict__ keff, double* __restrict__ stats, const int64_t* __restrict__ forced,
+    const CpqrJob* __restrict__ jobs) {
+  SID_CPQR_TAKE_JOB()
   constexpr int QN = RR + CL_RL;  // rows covered
   __shared__ double s_w[CL_RL][CL_THREADS];
   __shared__ double s_q[2][QN];
@@ -603,7 +625,7 @@ hipError_t launch_cpqr_wgl(hipStream_t st, const double* X, int64_t ldx, int m, 
   const int rr = m - CL_RL;  // register rows per thread (may be <= 0)
 #define SID_CL(RR_)                                                                          \
   hipLaunchKernelGGL((k_cpqr_wgl<RR_>), dim3(1), dim3(CL_THREADS), 0, st, X, ldx, m, nc, kmax, \
-                     rank_tol, piv, R, Q, keff, stats, forced)
+                     rank_tol, piv, R, Q, keff, stats, forced, (const CpqrJob*)nullptr)
   if (rr <= 26) SID_CL(26);
   else if (rr <= 42) SID_CL(42);
   else if (rr <= 58) SID_CL(58);
@@ -611,6 +633,67 @@ hipError_t launch_cpqr_wgl(hipStream_t st, const double* X, int64_t ldx, int m, 
   else if (rr <= 82) SID_CL(82);
   else SID_CL(96);
 #undef SID_CL
+  return hipGetLastError();
+}
+
+// Instance ids: the register kernel 8 * tpc_index + rpt_index + 1 (the
+// choices of launch_cpqr_wg), the LDS kernel -(rr_index + 1) (those of
+// launch_cpqr_wgl).
+int cpqr_batch_instance(int m, int nc, bool wgl) {
+  if (wgl) {
+    if (!cpqr_wgl_supported(m, nc)) return 0;
+    const int rr = m - CL_RL;
+    const int ri = rr <= 26 ? 0 : rr <= 42 ? 1 : rr <= 58 ? 2 : rr <= 74 ? 3 : rr <= 82 ? 4 : 5;
+    return -(ri + 1);
+  }
+  if (!cpqr_wg_supported(m, nc)) return 0;
+  const int tpc = cw_tpc(nc);
+  const int rpt = (m + tpc - 1) / tpc;
+  const int ti = tpc == 8 ? 0 : tpc == 4 ? 1 : tpc == 2 ? 2 : 3;
+  const int ri = rpt <= 8 ? 0 : rpt <= 16 ? 1 : rpt <= 24 ? 2 : rpt <= 32 ? 3 : rpt <= 40 ? 4 : 5;
+  return 8 * ti + ri + 1;
+}
+
+hipError_t launch_cpqr_batch(hipStream_t st, int instance, const CpqrJob* jobs, int njobs) {
+  if (njobs <= 0) return hipSuccess;
+  if (!jobs || instance == 0) return hipErrorInvalidValue;
+  const dim3 g((unsigned)njobs);
+  const double* X0 = nullptr;
+  int64_t* pnull = nullptr;
+  double* dnull = nullptr;
+#define SID_CWB(TPC_, RPT_)                                                                   \
+  hipLaunchKernelGGL((k_cpqr_wg<TPC_, RPT_>), g, dim3(CW_THREADS), 0, st, X0, (int64_t)0, 0, 0, \
+                     0, 0.0, pnull, dnull, dnull, pnull, dnull, (const int64_t*)nullptr, jobs)
+#define SID_CWB_R(TPC_, RI_)             \
+  if (RI_ == 0) SID_CWB(TPC_, 8);        \
+  else if (RI_ == 1) SID_CWB(TPC_, 16);  \
+  else if (RI_ == 2) SID_CWB(TPC_, 24);  \
+  else if (RI_ == 3) SID_CWB(TPC_, 32);  \
+  else if (RI_ == 4) SID_CWB(TPC_, 40);  \
+  else SID_CWB(TPC_, 48);
+#define SID_CLB(RR_)                                                                         \
+  hipLaunchKernelGGL((k_cpqr_wgl<RR_>), g, dim3(CL_THREADS), 0, st, X0, (int64_t)0, 0, 0, 0, \
+                     0.0, pnull, dnull, dnull, pnull, dnull, (const int64_t*)nullptr, jobs)
+  if (instance > 0) {
+    const int ti = (instance - 1) / 8, ri = (instance - 1) % 8;
+    if (ri > 5 || ti > 3) return hipErrorInvalidValue;
+    if (ti == 0) { SID_CWB_R(8, ri) }
+    else if (ti == 1) { SID_CWB_R(4, ri) }
+    else if (ti == 2) { SID_CWB_R(2, ri) }
+    else { SID_CWB_R(1, ri) }
+  } else {
+    const int ri = -instance - 1;
+    if (ri == 0) SID_CLB(26);
+    else if (ri == 1) SID_CLB(42);
+    else if (ri == 2) SID_CLB(58);
+    else if (ri == 3) SID_CLB(74);
+    else if (ri == 4) SID_CLB(82);
+    else if (ri == 5) SID_CLB(96);
+    else return hipErrorInvalidValue;
+  }
+#undef SID_CLB
+#undef SID_CWB_R
+#undef SID_CWB
   return hipGetLastError();
 }
 

@@ -147,6 +147,25 @@ hipError_t launch_cpqr_wgl(hipStream_t st, const double* X, int64_t ldx, int m, 
 hipError_t launch_cpqr_wg(hipStream_t st, const double* X, int64_t ldx, int m, int nc, int kmax,
                           double rank_tol, int64_t* piv, double* R, double* Q, int64_t* keff,
                           double* stats, const int64_t* forced = nullptr);
+// One mgsqr of a batch: the arguments of launch_cpqr_wg / launch_cpqr_wgl
+// (no forced order).  A batched launch runs one job per workgroup with the
+// kernel instance that the single launch would pick for each of its jobs
+// (cpqr_batch_instance), so every job gets the single launch's bits.
+struct CpqrJob {
+  const double* X;
+  int64_t ldx;
+  int m, nc, kmax, pad_;
+  double rank_tol;
+  int64_t* piv;
+  double* R;
+  double* Q;
+  int64_t* keff;
+  double* stats;
+};
+// kernel instance of an (m x nc) mgsqr: > 0 for the register kernel, < 0
+// for the LDS kernel (wgl = true), 0 if neither takes the shape
+int cpqr_batch_instance(int m, int nc, bool wgl);
+hipError_t launch_cpqr_batch(hipStream_t st, int instance, const CpqrJob* jobs, int njobs);
 // measurement probes (sid_probe): kind 0 read / 1 column stores / 2
 // sequential fill of an N x n FP32 buffer, 3 / 4 the 16x16x32 / 32x32x16
 // bf16 matrix-instruction loop of N rounds; sink: 8 num_cu floats
