@@ -109,6 +109,11 @@ struct BatchPlan {
   // the batched mgsqr launches: jobs grouped by kernel instance
   sid::CpqrJob* d_jobs = nullptr;
   std::vector<std::array<int, 3>> job_groups;  // (instance, first job, count)
+  // single pass: the products before M's mgsqr, in two launches
+  sid::OmegaJob* d_om_jobs = nullptr;
+  sid::Gemm64Job* d_mm_jobs = nullptr;
+  int n_om_jobs = 0, n_mm_jobs = 0, mm_max_m = 0, mm_max_n = 0;
+  int64_t om_max_count = 0;
 };
 
 }  // namespace
@@ -1846,7 +1851,9 @@ sid_status batch_plan(sid_ctx* ctx, const sid_problem* probs, int64_t count,
     return v;
   };
   size_t bytes = up(sizeof(sid::FbBatchEntry) * (size_t)count) + 256 +
-                 up(sizeof(sid::CpqrJob) * (size_t)(2 * count));
+                 up(sizeof(sid::CpqrJob) * (size_t)(2 * count)) +
+                 up(sizeof(sid::OmegaJob) * (size_t)count) +
+                 up(sizeof(sid::Gemm64Job) * (size_t)(2 * count));
   for (int64_t b = 0; b < count; ++b) {
     const Shape& s = sh[(size_t)b];
     bytes += up(sizeof(float) * (size_t)(nsh[(size_t)b] * s.lq * s.n)) +
@@ -1886,6 +1893,8 @@ sid_status batch_plan(sid_ctx* ctx, const sid_problem* probs, int64_t count,
   pl->d_tab = (sid::FbBatchEntry*)take(sizeof(sid::FbBatchEntry) * (size_t)count);
   pl->d_queue = (unsigned int*)take(256);
   pl->d_jobs = (sid::CpqrJob*)take(sizeof(sid::CpqrJob) * (size_t)(2 * count));
+  pl->d_om_jobs = (sid::OmegaJob*)take(sizeof(sid::OmegaJob) * (size_t)count);
+  pl->d_mm_jobs = (sid::Gemm64Job*)take(sizeof(sid::Gemm64Job) * (size_t)(2 * count));
   pl->W.assign((size_t)count, nullptr);
   pl->Y.assign((size_t)count, nullptr);
   pl->omega.assign((size_t)count, nullptr);
@@ -1928,6 +1937,8 @@ sid_status batch_plan(sid_ctx* ctx, const sid_problem* probs, int64_t count,
   // the factorization buffers and the mgsqr jobs (W_sel's, then M's),
   // grouped by kernel instance
   std::vector<std::pair<int, sid::CpqrJob>> jobs;
+  std::vector<sid::OmegaJob> omj;
+  std::vector<sid::Gemm64Job> mmj;
   for (int64_t b = 0; b < count; ++b) {
     if (!pre[(size_t)b]) continue;
     const Shape& s = sh[(size_t)b];
@@ -1956,8 +1967,22 @@ sid_status batch_plan(sid_ctx* ctx, const sid_problem* probs, int64_t count,
       jobs.push_back({sid::cpqr_batch_instance((int)s.lz, (int)s.l, ml),
                       sid::CpqrJob{f.M, s.lz, (int)s.lz, (int)s.l, (int)s.l, 0, g.rcond, f.pivM,
                                    f.RM, f.QM, f.rkM, f.statsM}});
+      // Omega's values, M = W(0:lz, :) Omega and Mpr = W_pr Omega, the
+      // launches of the single call's step 5a
+      omj.push_back(sid::OmegaJob{pl->omega[(size_t)b], s.n * s.l, f.om64});
+      pl->om_max_count = std::max(pl->om_max_count, s.n * s.l);
+      const double* Wb = pl->W[(size_t)b];
+      mmj.push_back(sid::Gemm64Job{(int)s.lz, (int)s.l, (int)s.n, 0, 1, 0, Wb, s.lq, f.om64, s.l,
+                                   f.M, s.lz, 1.0, 0.0});
+      if (s.q > 0)
+        mmj.push_back(sid::Gemm64Job{(int)s.q, (int)s.l, (int)s.n, 0, 1, 0, Wb + s.lz, s.lq, f.om64,
+                                     s.l, f.Mpr, s.q, 1.0, 0.0});
+      pl->mm_max_m = std::max(pl->mm_max_m, (int)s.lz);
+      pl->mm_max_n = std::max(pl->mm_max_n, (int)s.l);
     }
   }
+  pl->n_om_jobs = (int)omj.size();
+  pl->n_mm_jobs = (int)mmj.size();
   std::stable_sort(jobs.begin(), jobs.end(),
                    [](const std::pair<int, sid::CpqrJob>& x, const std::pair<int, sid::CpqrJob>& y) {
                      return x.first < y.first;
@@ -1973,6 +1998,12 @@ sid_status batch_plan(sid_ctx* ctx, const sid_problem* probs, int64_t count,
                                 hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess && !jtab.empty())
     e = hipMemcpyAsync(pl->d_jobs, jtab.data(), sizeof(sid::CpqrJob) * jtab.size(),
+                       hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess && !omj.empty())
+    e = hipMemcpyAsync(pl->d_om_jobs, omj.data(), sizeof(sid::OmegaJob) * omj.size(),
+                       hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess && !mmj.empty())
+    e = hipMemcpyAsync(pl->d_mm_jobs, mmj.data(), sizeof(sid::Gemm64Job) * mmj.size(),
                        hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) {
@@ -2005,36 +2036,33 @@ sid_status compress_batch(sid_ctx* ctx, const sid_problem* probs, int64_t count,
   for (int c = 0; c < nstreams; ++c)
     SID_CHECK(hipStreamWaitEvent(ctx->children[c]->stream, ctx->fork, 0), "batched: fork wait");
   // The mgsqr runs of all problems whose shapes the one-workgroup kernels
-  // take go into a few launches (one per kernel instance), after the small
-  // products they need (single pass: Omega's FP64 values, M and Mpr) on the
-  // child streams; every job gets the bits of the single call.
+  // take go into a few launches (one per kernel instance, on the child
+  // streams side by side), after the small products they need (single pass:
+  // Omega's FP64 values, M and Mpr, two launches for the whole batch); every
+  // job gets the bits of the single call.
   bool any_pre = false;
   if (persistent)
     for (const BatchFactor& f : plan->fac) any_pre = any_pre || f.pre;
   if (any_pre) {
-    if (sh[0].single)
-      for (int64_t b = 0; b < count; ++b) {
-        const BatchFactor& f = plan->fac[(size_t)b];
-        if (!f.pre) continue;
-        const Shape& s = sh[(size_t)b];
-        hipStream_t cs = ctx->children[(size_t)(b % nstreams)]->stream;
-        const int l = (int)s.l, lz = (int)s.lz, lq = (int)s.lq, q = (int)s.q, n_ = (int)s.n;
-        SID_CHECK(sid::launch_omega_values(cs, s.prec, plan->omega[(size_t)b], s.n * s.l, f.om64),
-                  "batched: omega values");
-        SID_CHECK(sid::launch_gemm64(cs, lz, l, n_, plan->W[(size_t)b], lq, 0, f.om64, l, 1, f.M, lz),
-                  "batched: M = W Omega");
-        if (q > 0)
-          SID_CHECK(sid::launch_gemm64(cs, q, l, n_, plan->W[(size_t)b] + lz, lq, 0, f.om64, l, 1,
-                                       f.Mpr, q),
-                    "batched: Mpr = Wpr Omega");
-      }
-    for (int c = 0; c < nstreams; ++c) {
+    SID_CHECK(sid::launch_omega_values_batch(ctx->stream, sh[0].prec, plan->d_om_jobs,
+                                             plan->n_om_jobs, plan->om_max_count),
+              "batched: omega values");
+    SID_CHECK(sid::launch_gemm64_batch(ctx->stream, plan->d_mm_jobs, plan->n_mm_jobs,
+                                       plan->mm_max_m, plan->mm_max_n),
+              "batched: M = W Omega, Mpr");
+    // one kernel instance per child stream, side by side
+    SID_CHECK(hipEventRecord(ctx->fork, ctx->stream), "batched: fork event");
+    const int ng = (int)plan->job_groups.size();
+    for (int i = 0; i < ng; ++i) {
+      const auto& g = plan->job_groups[(size_t)i];
+      hipStream_t cs = ctx->children[(size_t)(i % nstreams)]->stream;
+      if (i < nstreams) SID_CHECK(hipStreamWaitEvent(cs, ctx->fork, 0), "batched: fork wait");
+      SID_CHECK(sid::launch_cpqr_batch(cs, g[0], plan->d_jobs + g[1], g[2]), "batched: pivoted QR");
+    }
+    for (int c = 0; c < nstreams && c < ng; ++c) {
       SID_CHECK(hipEventRecord(ctx->child_done[c], ctx->children[c]->stream), "batched: join event");
       SID_CHECK(hipStreamWaitEvent(ctx->stream, ctx->child_done[c], 0), "batched: join wait");
     }
-    for (const auto& g : plan->job_groups)
-      SID_CHECK(sid::launch_cpqr_batch(ctx->stream, g[0], plan->d_jobs + g[1], g[2]),
-                "batched: pivoted QR");
     SID_CHECK(hipEventRecord(ctx->fork, ctx->stream), "batched: fork event");
     for (int c = 0; c < nstreams; ++c)
       SID_CHECK(hipStreamWaitEvent(ctx->children[c]->stream, ctx->fork, 0), "batched: fork wait");

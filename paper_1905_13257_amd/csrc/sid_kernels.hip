@@ -402,23 +402,26 @@ __global__ void k_ratio_sqrt(const double* __restrict__ stats, double* __restric
 // opX = transpose when tX != 0.  A: M x K (or K x M transposed), col-major.
 // Used for the l x l and l x k products of the single-pass solve.
 // ---------------------------------------------------------------------------
-__global__ void k_gemm64(int M, int Nn, int K, const double* __restrict__ A, int64_t lda, int tA,
-                         const double* __restrict__ B, int64_t ldb, int tB, double* __restrict__ C,
-                         int64_t ldc, double alpha, double beta) {
+// one 16 x 16 tile (bx, by) of C = alpha op(A) op(B) + beta C
+__device__ __forceinline__ void gemm64_tile(int bx, int by, int M, int Nn, int K,
+                                            const double* __restrict__ A, int64_t lda, int tA,
+                                            const double* __restrict__ B, int64_t ldb, int tB,
+                                            double* __restrict__ C, int64_t ldc, double alpha,
+                                            double beta) {
   __shared__ double sa[16][17], sb[16][17];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int row = blockIdx.x * 16 + tx;
-  const int col = blockIdx.y * 16 + ty;
+  const int row = bx * 16 + tx;
+  const int col = by * 16 + ty;
   double acc = 0.0;
   for (int k0 = 0; k0 < K; k0 += 16) {
     {
-      const int r = blockIdx.x * 16 + tx, kk = k0 + ty;
+      const int r = bx * 16 + tx, kk = k0 + ty;
       double v = 0.0;
       if (r < M && kk < K) v = tA ? A[kk + lda * r] : A[r + lda * kk];
       sa[tx][ty] = v;
     }
     {
-      const int kk = k0 + tx, c = blockIdx.y * 16 + ty;
+      const int kk = k0 + tx, c = by * 16 + ty;
       double v = 0.0;
       if (kk < K && c < Nn) v = tB ? B[c + ldb * kk] : B[kk + ldb * c];
       sb[tx][ty] = v;
@@ -432,6 +435,21 @@ __global__ void k_gemm64(int M, int Nn, int K, const double* __restrict__ A, int
     double* o = C + row + ldc * col;
     *o = beta != 0.0 ? fma(alpha, acc, beta * *o) : (alpha == 1.0 ? acc : alpha * acc);
   }
+}
+
+__global__ void k_gemm64(int M, int Nn, int K, const double* __restrict__ A, int64_t lda, int tA,
+                         const double* __restrict__ B, int64_t ldb, int tB, double* __restrict__ C,
+                         int64_t ldc, double alpha, double beta) {
+  gemm64_tile(blockIdx.x, blockIdx.y, M, Nn, K, A, lda, tA, B, ldb, tB, C, ldc, alpha, beta);
+}
+
+// many products in one launch: job blockIdx.z, its tiles (bx, by) (blocks
+// past a job's tile grid return)
+__global__ void k_gemm64_batch(const Gemm64Job* __restrict__ jobs) {
+  const Gemm64Job jb = jobs[blockIdx.z];
+  if ((int)blockIdx.x * 16 >= jb.M || (int)blockIdx.y * 16 >= jb.Nn) return;
+  gemm64_tile(blockIdx.x, blockIdx.y, jb.M, jb.Nn, jb.K, jb.A, jb.lda, jb.tA, jb.B, jb.ldb, jb.tB,
+              jb.C, jb.ldc, jb.alpha, jb.beta);
 }
 
 // gather columns: dst(:, t) = src(:, piv[t]) for t < keff, zero for keff <= t < kcap
@@ -654,6 +672,15 @@ __global__ void k_omega_values(const float* __restrict__ z, int64_t count, doubl
     out[e] = (double)gauss_value<PREC>(z[e]);
 }
 
+// many value arrays in one launch: job blockIdx.y
+template <int PREC>
+__global__ void k_omega_values_batch(const OmegaJob* __restrict__ jobs) {
+  const OmegaJob jb = jobs[blockIdx.y];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < jb.count;
+       e += (int64_t)gridDim.x * blockDim.x)
+    jb.out[e] = (double)gauss_value<PREC>(jb.z[e]);
+}
+
 // ---------------------------------------------------------------------------
 // explicit instantiations / launchers
 // ---------------------------------------------------------------------------
@@ -791,6 +818,32 @@ hipError_t launch_omega_values(hipStream_t st, int prec, const float* z, int64_t
     case P_FP8: hipLaunchKernelGGL(k_omega_values<P_FP8>, dim3((unsigned)b), dim3(256), 0, st, z, count, out); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_omega_values_batch(hipStream_t st, int prec, const OmegaJob* jobs, int njobs,
+                                     int64_t max_count) {
+  if (njobs <= 0) return hipSuccess;
+  int64_t b = (max_count + 255) / 256;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  const dim3 g((unsigned)b, (unsigned)njobs);
+  switch (prec) {
+    case P_F64: hipLaunchKernelGGL(k_omega_values_batch<P_F64>, g, dim3(256), 0, st, jobs); break;
+    case P_F32: hipLaunchKernelGGL(k_omega_values_batch<P_F32>, g, dim3(256), 0, st, jobs); break;
+    case P_BF16: hipLaunchKernelGGL(k_omega_values_batch<P_BF16>, g, dim3(256), 0, st, jobs); break;
+    case P_BF16X2: hipLaunchKernelGGL(k_omega_values_batch<P_BF16X2>, g, dim3(256), 0, st, jobs); break;
+    case P_FP8: hipLaunchKernelGGL(k_omega_values_batch<P_FP8>, g, dim3(256), 0, st, jobs); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm64_batch(hipStream_t st, const Gemm64Job* jobs, int njobs, int max_m,
+                               int max_n) {
+  if (njobs <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((max_m + 15) / 16), (unsigned)((max_n + 15) / 16), (unsigned)njobs);
+  hipLaunchKernelGGL(k_gemm64_batch, grid, dim3(256), 0, st, jobs);
   return hipGetLastError();
 }
 

@@ -50,6 +50,27 @@ hipError_t launch_ratio_sqrt(hipStream_t st, const double* stats, double* out);
 hipError_t launch_gemm64(hipStream_t st, int M, int Nn, int K, const double* A, int64_t lda,
                          int tA, const double* B, int64_t ldb, int tB, double* C, int64_t ldc);
 // C = alpha op(A) op(B) + beta C (beta = 0: C is not read)
+// batched forms of launch_omega_values and launch_gemm64(_ab): one job per
+// product, the same arithmetic as the single launch
+struct OmegaJob {
+  const float* z;
+  int64_t count;
+  double* out;
+};
+hipError_t launch_omega_values_batch(hipStream_t st, int prec, const OmegaJob* jobs, int njobs,
+                                     int64_t max_count);
+struct Gemm64Job {
+  int M, Nn, K, tA, tB, pad_;
+  const double* A;
+  int64_t lda;
+  const double* B;
+  int64_t ldb;
+  double* C;
+  int64_t ldc;
+  double alpha, beta;
+};
+hipError_t launch_gemm64_batch(hipStream_t st, const Gemm64Job* jobs, int njobs, int max_m,
+                               int max_n);
 hipError_t launch_gemm64_ab(hipStream_t st, int M, int Nn, int K, const double* A, int64_t lda,
                             int tA, const double* B, int64_t ldb, int tB, double alpha, double beta,
                             double* C, int64_t ldc);
