@@ -504,10 +504,12 @@ def test_batched_equals_individual(sid, oracle_mod, mode, prec):
     """A batch of matrices of mixed shapes and ranks (spectrum j^-1.5, as in
     the batched workload) == one sid_compress per matrix, bit for bit in J
     and P (same kernels, own workspace per internal stream), and the
-    oracle's pivots until its first near-tie."""
+    oracle's pivots until its first near-tie.  The shapes cover both
+    one-workgroup mgsqr kernels (run as batched launches) and, at l = 100,
+    n = 400, the multi-workgroup one (run in the problem's own sequence)."""
     rng = np.random.default_rng(21)
     shapes = [(16384, 64, 8), (5120, 300, 40), (40000, 128, 20), (2048, 512, 64), (9000, 90, 12),
-              (30000, 200, 33), (4096, 77, 9)]
+              (30000, 200, 33), (4096, 77, 9), (12000, 400, 90)]
     mats, A64s = [], []
     for (N, n, k) in shapes:
         sig = np.arange(1, n + 1) ** -1.5
