@@ -74,9 +74,11 @@ struct BatchSig {
   int64_t N, n, lda, lq, l, lz, k;
   uint64_t seed;
   double rank_tol, rcond;  // the mgsqr jobs' stopping tolerances
+  double probe_tol;        // adaptive rank (> 0) keeps the per-problem tail
   bool operator==(const BatchSig& o) const {
     return A == o.A && N == o.N && n == o.n && lda == o.lda && lq == o.lq && l == o.l &&
-           lz == o.lz && k == o.k && seed == o.seed && rank_tol == o.rank_tol && rcond == o.rcond;
+           lz == o.lz && k == o.k && seed == o.seed && rank_tol == o.rank_tol &&
+           rcond == o.rcond && probe_tol == o.probe_tol;
   }
 };
 
@@ -87,6 +89,10 @@ struct BatchFactor {
   int64_t *piv = nullptr, *keff = nullptr, *pivM = nullptr, *rkM = nullptr;
   double *R = nullptr, *Q = nullptr, *stats = nullptr, *om64 = nullptr, *M = nullptr,
          *Mpr = nullptr, *RM = nullptr, *QM = nullptr, *statsM = nullptr;
+  // the steps after mgsqr, when the whole batch runs them as batched
+  // launches (BatchPlan::tail)
+  double *R11 = nullptr, *Pd = nullptr, *WJ = nullptr, *C = nullptr, *T = nullptr,
+         *R11M = nullptr, *mix = nullptr, *fitpart = nullptr, *err = nullptr;
 };
 
 // Device state of one batch of problems for the persistent sketch pass: the
@@ -114,6 +120,18 @@ struct BatchPlan {
   sid::Gemm64Job* d_mm_jobs = nullptr;
   int n_om_jobs = 0, n_mm_jobs = 0, mm_max_m = 0, mm_max_n = 0;
   int64_t om_max_count = 0;
+  // single pass, every problem batched and no adaptive rank: the steps after
+  // mgsqr as batched launches too (job tables below, one job per problem),
+  // then per problem only P's conversion, AJ = Y T and the result copies
+  bool tail = false;
+  sid::GatherR11Job* d_gr11 = nullptr;  // [count] W's R11, then [count] M's
+  sid::TrsvJob *d_trsv0 = nullptr, *d_trsv1 = nullptr;
+  sid::RatioJob* d_ratio = nullptr;
+  sid::GatherBlockJob* d_gblock = nullptr;
+  sid::Gemm64Job *d_gemm_c = nullptr, *d_gemm_mix = nullptr;
+  sid::FitJob* d_fit = nullptr;
+  int n_gemm_mix = 0, t_max_k = 0, t_max_n = 0, t_max_l = 0, t_max_gblock = 0, t_max_q = 0,
+      t_max_qn = 0;
 };
 
 }  // namespace
@@ -1078,6 +1096,29 @@ static sid_status refine_pass(sid_ctx* ctx, const void* A, sid_dtype dtype, int6
 // Everything after the sketch pass, from W (w.W, lq x n), single pass also
 // Y (w.Y) and Omega's values (w.omega, n x l): mgsqr, coefficients,
 // estimates and the skeleton.  A is read only by the two-pass gather.
+// single pass: AJ = Y T (N x k, ld ldaj, FP64 when f64) on the kernel the
+// shape and the sketch form take
+static sid_status apply_skeleton(sid_ctx* ctx, hipStream_t st, const Shape& sh, const void* Y,
+                                 const double* T, void* AJ, int64_t ldaj, bool f64) {
+  const int k = (int)sh.k, l = (int)sh.l;
+  const bool yf64 = sh.prec == SID_SK_F64;
+  const bool ybf = sh.prec == SID_SK_BF16 || sh.prec == SID_SK_BF16X2 || sh.prec == SID_SK_FP8E4M3;
+  if (ybf && !f64 && sid::apply_t_bf16_runs_supported(k, l))
+    SID_CHECK(sid::launch_apply_t_bf16_runs(st, (const float*)Y, sh.N, l, T, k, (float*)AJ, ldaj,
+                                            ctx->num_cu),
+              "AJ = Y T");
+  else if (ybf && sid::apply_t_bf16_supported(k, l))
+    SID_CHECK(sid::launch_apply_t_bf16(st, (const float*)Y, sh.N, l, T, k, AJ, f64, ldaj,
+                                       ctx->num_cu),
+              "AJ = Y T");
+  else if (sid::apply_t_mfma_supported(k, l, yf64))
+    SID_CHECK(sid::launch_apply_t_mfma(st, Y, yf64, sh.N, l, T, k, AJ, f64, ldaj, ctx->num_cu),
+              "AJ = Y T");
+  else
+    SID_CHECK(sid::launch_apply_t(st, Y, yf64, sh.N, l, T, k, AJ, f64, ldaj), "AJ = Y T");
+  return SID_OK;
+}
+
 // prefactored (the batched path): mgsqr of W_sel and, in single pass, M,
 // Mpr, Omega's FP64 values and mgsqr of M are already in w (steps 5a and 2
 // are skipped).
@@ -1229,23 +1270,8 @@ static sid_status factor(sid_ctx* ctx, const sid_params* p, const Shape& sh, con
               "probe residual");
     if (es != st) SID_CHECK(hipEventRecord(ctx->side_join, es), "side join");
     if (AJ) {
-      const bool yf64 = sh.prec == SID_SK_F64;
-      const bool ybf = sh.prec == SID_SK_BF16 || sh.prec == SID_SK_BF16X2 ||
-                       sh.prec == SID_SK_FP8E4M3;
-      if (ybf && !f64 && sid::apply_t_bf16_runs_supported(k, l))
-        SID_CHECK(sid::launch_apply_t_bf16_runs(st, (const float*)w.Y, sh.N, l, w.T, k,
-                                                (float*)AJ, ldaj, ctx->num_cu),
-                  "AJ = Y T");
-      else if (ybf && sid::apply_t_bf16_supported(k, l))
-        SID_CHECK(sid::launch_apply_t_bf16(st, (const float*)w.Y, sh.N, l, w.T, k, AJ, f64, ldaj,
-                                           ctx->num_cu),
-                  "AJ = Y T");
-      else if (sid::apply_t_mfma_supported(k, l, yf64))
-        SID_CHECK(sid::launch_apply_t_mfma(st, w.Y, yf64, sh.N, l, w.T, k, AJ, f64, ldaj,
-                                           ctx->num_cu),
-                  "AJ = Y T");
-      else
-        SID_CHECK(sid::launch_apply_t(st, w.Y, yf64, sh.N, l, w.T, k, AJ, f64, ldaj), "AJ = Y T");
+      const sid_status as = apply_skeleton(ctx, st, sh, w.Y, w.T, AJ, ldaj, f64);
+      if (as != SID_OK) return as;
     }
     if (es != st) SID_CHECK(hipStreamWaitEvent(st, ctx->side_join, 0), "side join wait");
   }
@@ -1803,7 +1829,8 @@ sid_status batch_plan(sid_ctx* ctx, const sid_problem* probs, int64_t count,
     const Shape& s = sh[(size_t)b];
     const sid_params& q = probs[b].params;
     sig[(size_t)b] = BatchSig{probs[b].A, s.N, s.n, probs[b].lda, s.lq, s.l, s.lz, s.k, q.seed,
-                              q.rank_tol, q.sp_rcond > 0.0 ? q.sp_rcond : default_rcond(s.prec)};
+                              q.rank_tol, q.sp_rcond > 0.0 ? q.sp_rcond : default_rcond(s.prec),
+                              q.probe_tol};
   }
   for (size_t i = 0; i < ctx->plans.size(); ++i) {
     BatchPlan* pl = ctx->plans[i];
@@ -1850,10 +1877,27 @@ sid_status batch_plan(sid_ctx* ctx, const sid_problem* probs, int64_t count,
            up(d * (size_t)(s.l * s.l)) + up(d * (size_t)(s.lz * s.l)) + up(i8) + up(2 * d);
     return v;
   };
+  bool tail = wanty;
+  for (int64_t b = 0; b < count; ++b) {
+    const Shape& s = sh[(size_t)b];
+    tail = tail && pre[(size_t)b] && sig[(size_t)b].probe_tol <= 0.0 && s.k <= 128 && s.l <= 128;
+  }
+  auto tail_bytes = [&](const Shape& s) {
+    const int64_t qq = s.q > 0 ? s.q : 1;
+    return up(d * (size_t)(s.k * s.k)) + up(d * (size_t)(s.k * s.n)) + up(d * (size_t)(s.lz * s.k)) +
+           up(d * (size_t)(s.l * s.k)) + up(d * (size_t)(s.l * s.k)) + up(d * (size_t)(s.l * s.l)) +
+           up(d * (size_t)(qq * s.k)) + up(d * (size_t)(2 * ((qq * s.n + 255) / 256) + 2)) +
+           up(2 * d);
+  };
   size_t bytes = up(sizeof(sid::FbBatchEntry) * (size_t)count) + 256 +
                  up(sizeof(sid::CpqrJob) * (size_t)(2 * count)) +
                  up(sizeof(sid::OmegaJob) * (size_t)count) +
                  up(sizeof(sid::Gemm64Job) * (size_t)(2 * count));
+  if (tail)
+    bytes += up(sizeof(sid::GatherR11Job) * (size_t)(2 * count)) +
+             2 * up(sizeof(sid::TrsvJob) * (size_t)count) + up(sizeof(sid::RatioJob) * (size_t)count) +
+             up(sizeof(sid::GatherBlockJob) * (size_t)count) +
+             2 * up(sizeof(sid::Gemm64Job) * (size_t)count) + up(sizeof(sid::FitJob) * (size_t)count);
   for (int64_t b = 0; b < count; ++b) {
     const Shape& s = sh[(size_t)b];
     bytes += up(sizeof(float) * (size_t)(nsh[(size_t)b] * s.lq * s.n)) +
@@ -1862,6 +1906,7 @@ sid_status batch_plan(sid_ctx* ctx, const sid_problem* probs, int64_t count,
       bytes += up(sizeof(float) * (size_t)(s.n * s.l)) + up(sizeof(uint16_t) * 128 * 512) +
                up(sizeof(float) * (size_t)(s.N * s.l));
     if (pre[(size_t)b]) bytes += fac_bytes(s);
+    if (tail) bytes += tail_bytes(s);
   }
   if (ctx->plans.size() >= SID_BATCH_PLANS) {
     // the oldest plan goes; nothing queued may still read it
@@ -1895,6 +1940,17 @@ sid_status batch_plan(sid_ctx* ctx, const sid_problem* probs, int64_t count,
   pl->d_jobs = (sid::CpqrJob*)take(sizeof(sid::CpqrJob) * (size_t)(2 * count));
   pl->d_om_jobs = (sid::OmegaJob*)take(sizeof(sid::OmegaJob) * (size_t)count);
   pl->d_mm_jobs = (sid::Gemm64Job*)take(sizeof(sid::Gemm64Job) * (size_t)(2 * count));
+  pl->tail = tail;
+  if (tail) {
+    pl->d_gr11 = (sid::GatherR11Job*)take(sizeof(sid::GatherR11Job) * (size_t)(2 * count));
+    pl->d_trsv0 = (sid::TrsvJob*)take(sizeof(sid::TrsvJob) * (size_t)count);
+    pl->d_trsv1 = (sid::TrsvJob*)take(sizeof(sid::TrsvJob) * (size_t)count);
+    pl->d_ratio = (sid::RatioJob*)take(sizeof(sid::RatioJob) * (size_t)count);
+    pl->d_gblock = (sid::GatherBlockJob*)take(sizeof(sid::GatherBlockJob) * (size_t)count);
+    pl->d_gemm_c = (sid::Gemm64Job*)take(sizeof(sid::Gemm64Job) * (size_t)count);
+    pl->d_gemm_mix = (sid::Gemm64Job*)take(sizeof(sid::Gemm64Job) * (size_t)count);
+    pl->d_fit = (sid::FitJob*)take(sizeof(sid::FitJob) * (size_t)count);
+  }
   pl->W.assign((size_t)count, nullptr);
   pl->Y.assign((size_t)count, nullptr);
   pl->omega.assign((size_t)count, nullptr);
@@ -1938,7 +1994,12 @@ sid_status batch_plan(sid_ctx* ctx, const sid_problem* probs, int64_t count,
   // grouped by kernel instance
   std::vector<std::pair<int, sid::CpqrJob>> jobs;
   std::vector<sid::OmegaJob> omj;
-  std::vector<sid::Gemm64Job> mmj;
+  std::vector<sid::Gemm64Job> mmj, gemmc, gemmmix;
+  std::vector<sid::GatherR11Job> gr11w, gr11m;
+  std::vector<sid::TrsvJob> trsv0, trsv1;
+  std::vector<sid::RatioJob> ratio;
+  std::vector<sid::GatherBlockJob> gblock;
+  std::vector<sid::FitJob> fit;
   for (int64_t b = 0; b < count; ++b) {
     if (!pre[(size_t)b]) continue;
     const Shape& s = sh[(size_t)b];
@@ -1980,9 +2041,43 @@ sid_status batch_plan(sid_ctx* ctx, const sid_problem* probs, int64_t count,
       pl->mm_max_m = std::max(pl->mm_max_m, (int)s.lz);
       pl->mm_max_n = std::max(pl->mm_max_n, (int)s.l);
     }
+    if (tail) {
+      // the single call's steps 3, 4, 5b after mgsqr (factor()), on the
+      // plan's buffers
+      const int k = (int)s.k, l = (int)s.l, lz = (int)s.lz, q = (int)s.q, n_ = (int)s.n;
+      const int qq = q > 0 ? q : 1;
+      f.R11 = (double*)take(d * (size_t)(k * k));
+      f.Pd = (double*)take(d * (size_t)(k * n_));
+      f.WJ = (double*)take(d * (size_t)(lz * k));
+      f.C = (double*)take(d * (size_t)(l * k));
+      f.T = (double*)take(d * (size_t)(l * k));
+      f.R11M = (double*)take(d * (size_t)(l * l));
+      f.mix = (double*)take(d * (size_t)(qq * k));
+      f.fitpart = (double*)take(d * (size_t)(2 * ((qq * n_ + 255) / 256) + 2));
+      f.err = (double*)take(2 * d);
+      const double* Wb = pl->W[(size_t)b];
+      gr11w.push_back(sid::GatherR11Job{f.R, n_, f.piv, f.keff, k, 0, f.R11});
+      gr11m.push_back(sid::GatherR11Job{f.RM, l, f.pivM, f.rkM, l, 0, f.R11M});
+      trsv0.push_back(sid::TrsvJob{f.R11, k, n_, f.keff, f.piv, f.R, n_, f.Pd, k});
+      trsv1.push_back(sid::TrsvJob{f.R11M, l, k, f.rkM, f.pivM, f.C, l, f.T, l});
+      ratio.push_back(sid::RatioJob{f.stats, f.err + 1});
+      gblock.push_back(sid::GatherBlockJob{Wb, (int)s.lq, 0, lz, k, f.piv, f.keff, f.WJ});
+      gemmc.push_back(sid::Gemm64Job{l, k, lz, 1, 0, 0, f.QM, lz, f.WJ, lz, f.C, l, 1.0, 0.0});
+      if (q > 0)
+        gemmmix.push_back(sid::Gemm64Job{q, k, l, 0, 0, 0, f.Mpr, q, f.T, l, f.mix, q, 1.0, 0.0});
+      fit.push_back(sid::FitJob{Wb, (int)s.lq, lz, q, n_, k, 0, f.piv, f.keff, f.Pd,
+                                q > 0 ? f.mix : nullptr, f.fitpart, f.err});
+      pl->t_max_k = std::max(pl->t_max_k, k);
+      pl->t_max_n = std::max(pl->t_max_n, n_);
+      pl->t_max_l = std::max(pl->t_max_l, l);
+      pl->t_max_gblock = std::max(pl->t_max_gblock, lz * k);
+      pl->t_max_q = std::max(pl->t_max_q, q);
+      pl->t_max_qn = std::max(pl->t_max_qn, q * n_);
+    }
   }
   pl->n_om_jobs = (int)omj.size();
   pl->n_mm_jobs = (int)mmj.size();
+  pl->n_gemm_mix = (int)gemmmix.size();
   std::stable_sort(jobs.begin(), jobs.end(),
                    [](const std::pair<int, sid::CpqrJob>& x, const std::pair<int, sid::CpqrJob>& y) {
                      return x.first < y.first;
@@ -2005,6 +2100,22 @@ sid_status batch_plan(sid_ctx* ctx, const sid_problem* probs, int64_t count,
   if (e == hipSuccess && !mmj.empty())
     e = hipMemcpyAsync(pl->d_mm_jobs, mmj.data(), sizeof(sid::Gemm64Job) * mmj.size(),
                        hipMemcpyHostToDevice, ctx->stream);
+  if (tail) {
+    // the M jobs of the R11 gather follow the W jobs
+    gr11w.insert(gr11w.end(), gr11m.begin(), gr11m.end());
+    auto upl = [&](void* dst, const void* src, size_t nb) {
+      if (e == hipSuccess && nb > 0)
+        e = hipMemcpyAsync(dst, src, nb, hipMemcpyHostToDevice, ctx->stream);
+    };
+    upl(pl->d_gr11, gr11w.data(), sizeof(sid::GatherR11Job) * gr11w.size());
+    upl(pl->d_trsv0, trsv0.data(), sizeof(sid::TrsvJob) * trsv0.size());
+    upl(pl->d_trsv1, trsv1.data(), sizeof(sid::TrsvJob) * trsv1.size());
+    upl(pl->d_ratio, ratio.data(), sizeof(sid::RatioJob) * ratio.size());
+    upl(pl->d_gblock, gblock.data(), sizeof(sid::GatherBlockJob) * gblock.size());
+    upl(pl->d_gemm_c, gemmc.data(), sizeof(sid::Gemm64Job) * gemmc.size());
+    upl(pl->d_gemm_mix, gemmmix.data(), sizeof(sid::Gemm64Job) * gemmmix.size());
+    upl(pl->d_fit, fit.data(), sizeof(sid::FitJob) * fit.size());
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) {
     (void)hipFree(pl->dev);
@@ -2063,12 +2174,56 @@ sid_status compress_batch(sid_ctx* ctx, const sid_problem* probs, int64_t count,
       SID_CHECK(hipEventRecord(ctx->child_done[c], ctx->children[c]->stream), "batched: join event");
       SID_CHECK(hipStreamWaitEvent(ctx->stream, ctx->child_done[c], 0), "batched: join wait");
     }
+    if (plan->tail) {
+      // the steps after mgsqr, each one launch for the batch (the single
+      // call's kernels on the plan's buffers): R11, P's solve into Pd, the
+      // sketch-fit estimate, W(:, J), C = QM^T W(:, J), M's R11, T, Mpr T,
+      // the probe estimate
+      const int cnt = (int)count;
+      SID_CHECK(sid::launch_gather_r11_batch(ctx->stream, plan->d_gr11, 2 * cnt), "batched: R11");
+      SID_CHECK(sid::launch_trsv_batch(ctx->stream, 0, plan->d_trsv0, cnt, plan->t_max_k,
+                                       plan->t_max_n),
+                "batched: coefficients");
+      SID_CHECK(sid::launch_ratio_sqrt_batch(ctx->stream, plan->d_ratio, cnt), "batched: sketch fit");
+      SID_CHECK(sid::launch_gather_block_batch(ctx->stream, plan->d_gblock, cnt, plan->t_max_gblock),
+                "batched: W(:, J)");
+      SID_CHECK(sid::launch_gemm64_batch(ctx->stream, plan->d_gemm_c, cnt, plan->t_max_l,
+                                         plan->t_max_k),
+                "batched: QM^T W(:, J)");
+      SID_CHECK(sid::launch_trsv_batch(ctx->stream, 1, plan->d_trsv1, cnt, plan->t_max_l,
+                                       plan->t_max_k),
+                "batched: T");
+      SID_CHECK(sid::launch_gemm64_batch(ctx->stream, plan->d_gemm_mix, plan->n_gemm_mix,
+                                         plan->t_max_q, plan->t_max_k),
+                "batched: Mpr T");
+      SID_CHECK(sid::launch_fit_residual_batch(ctx->stream, plan->d_fit, cnt, plan->t_max_qn),
+                "batched: probe residual");
+    }
     SID_CHECK(hipEventRecord(ctx->fork, ctx->stream), "batched: fork event");
     for (int c = 0; c < nstreams; ++c)
       SID_CHECK(hipStreamWaitEvent(ctx->children[c]->stream, ctx->fork, 0), "batched: fork wait");
   }
   sid_status result = SID_OK;
-  for (int64_t b = 0; b < count && result == SID_OK; ++b) {
+  const bool tail = any_pre && plan->tail;
+  if (tail) {
+    // per problem: P from Pd in the caller's type and layout (the values the
+    // single call's solve writes), AJ = Y T, the result copies
+    const bool f64 = dtype == SID_F64;
+    for (int64_t b = 0; b < count && result == SID_OK; ++b) {
+      const sid_problem& q = probs[b];
+      const Shape& s = sh[(size_t)b];
+      const BatchFactor& f = plan->fac[(size_t)b];
+      hipStream_t cs = ctx->children[(size_t)(b % nstreams)]->stream;
+      hipError_t he = hipSuccess;
+      if (q.P) he = sid::launch_convert(cs, f.Pd, true, s.k, s.n, s.k, q.P, f64, q.ldp);
+      if (he == hipSuccess && q.AJ)
+        result = apply_skeleton(ctx, cs, s, plan->Y[(size_t)b], f.T, q.AJ, q.ldaj, f64);
+      if (he == hipSuccess && result == SID_OK)
+        he = sid::launch_copy_results(cs, q.J, f.piv, (int)s.k, q.k_eff, f.keff, q.err, f.err);
+      if (he != hipSuccess) result = hip_fail(ctx, he, "batched: per-problem results");
+    }
+  }
+  for (int64_t b = 0; !tail && b < count && result == SID_OK; ++b) {
     const sid_problem& q = probs[b];
     sid_ctx* c = ctx->children[(size_t)(b % nstreams)];
     if (persistent) {

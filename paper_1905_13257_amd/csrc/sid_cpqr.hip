@@ -762,7 +762,17 @@ hipError_t launch_cpqr_coop(hipStream_t st, const double* X, int64_t ldx, int m,
 // ---------------------------------------------------------------------------
 __global__ void k_gather_r11(const double* __restrict__ R, int64_t ldr /* = nc */,
                              const int64_t* __restrict__ piv, const int64_t* __restrict__ keff_p,
-                             int kcap, double* __restrict__ R11) {
+                             int kcap, double* __restrict__ R11,
+                             const GatherR11Job* __restrict__ jobs) {
+  if (jobs) {  // a batched launch: job blockIdx.y
+    const GatherR11Job jb = jobs[blockIdx.y];
+    R = jb.R;
+    ldr = jb.ldr;
+    piv = jb.piv;
+    keff_p = jb.keff;
+    kcap = jb.kcap;
+    R11 = jb.R11;
+  }
   const int keff = (int)*keff_p;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < kcap * kcap; e += gridDim.x * blockDim.x) {
     const int a = e / kcap, b = e - a * kcap;
@@ -822,7 +832,21 @@ template <typename OutT, int MODE>
 __global__ __launch_bounds__(64 * TW_WAVES) void k_trsv_wave(
     const double* __restrict__ R11, int kcap, const int64_t* __restrict__ keff_p,
     const int64_t* __restrict__ piv, const double* __restrict__ rhs, int64_t ldrhs, int ncols,
-    double* __restrict__ out64, int64_t ldo64, OutT* __restrict__ out, int64_t ldo) {
+    double* __restrict__ out64, int64_t ldo64, OutT* __restrict__ out, int64_t ldo,
+    const TrsvJob* __restrict__ jobs) {
+  if (jobs) {  // a batched launch: job blockIdx.y, out64 only
+    const TrsvJob jb = jobs[blockIdx.y];
+    R11 = jb.R11;
+    kcap = jb.kcap;
+    keff_p = jb.keff;
+    piv = jb.piv;
+    rhs = jb.rhs;
+    ldrhs = jb.ldrhs;
+    ncols = jb.ncols;
+    out64 = jb.out64;
+    ldo64 = jb.ldo64;
+    out = nullptr;
+  }
   extern __shared__ double s_tw[];
   double* s_rt = s_tw;                           // [a][b] = R11(b, a), kcap^2 (+128 pad)
   double* s_dinv = s_rt + kcap * kcap + 128;     // 1 / R11(a, a)
@@ -902,7 +926,26 @@ static hipError_t trsv_wave_launch(hipStream_t st, const double* R11, int kcap, 
   if (shm > 65536)
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   hipLaunchKernelGGL(kern, dim3((unsigned)((ncols + TW_WAVES - 1) / TW_WAVES)), dim3(64 * TW_WAVES),
-                     shm, st, R11, kcap, keff, piv, rhs, ldrhs, ncols, out64, ldo64, out, ldo);
+                     shm, st, R11, kcap, keff, piv, rhs, ldrhs, ncols, out64, ldo64, out, ldo,
+                     (const TrsvJob*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_trsv_batch(hipStream_t st, int mode, const TrsvJob* jobs, int njobs,
+                             int max_kcap, int max_ncols) {
+  if (njobs <= 0) return hipSuccess;
+  if (!jobs || max_kcap < 1 || max_kcap > 128 || max_ncols < 1) return hipErrorInvalidValue;
+  const size_t shm =
+      sizeof(double) * ((size_t)max_kcap * max_kcap + 128 + max_kcap + (size_t)TW_WAVES * max_kcap) +
+      sizeof(int) * (size_t)max_kcap;
+  auto kern = mode == 0 ? k_trsv_wave<double, 0> : k_trsv_wave<double, 1>;
+  if (shm > 65536)
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  const double* dn = nullptr;
+  const int64_t* in = nullptr;
+  hipLaunchKernelGGL(kern, dim3((unsigned)((max_ncols + TW_WAVES - 1) / TW_WAVES), (unsigned)njobs),
+                     dim3(64 * TW_WAVES), shm, st, dn, 0, in, in, dn, (int64_t)0, 0, (double*)nullptr,
+                     (int64_t)0, (double*)nullptr, (int64_t)0, jobs);
   return hipGetLastError();
 }
 
@@ -921,14 +964,25 @@ static hipError_t trsv_launch(hipStream_t st, const double* R11, int kcap, const
 
 hipError_t launch_gather_r11(hipStream_t st, const double* R, int nc, const int64_t* piv,
                              const int64_t* keff, int kcap, double* R11) {
-  hipLaunchKernelGGL(k_gather_r11, dim3(64), dim3(256), 0, st, R, (int64_t)nc, piv, keff, kcap, R11);
+  hipLaunchKernelGGL(k_gather_r11, dim3(64), dim3(256), 0, st, R, (int64_t)nc, piv, keff, kcap, R11,
+                     (const GatherR11Job*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_r11_batch(hipStream_t st, const GatherR11Job* jobs, int njobs) {
+  if (njobs <= 0) return hipSuccess;
+  const double* dn = nullptr;
+  const int64_t* in = nullptr;
+  hipLaunchKernelGGL(k_gather_r11, dim3(64, (unsigned)njobs), dim3(256), 0, st, dn, (int64_t)0, in,
+                     in, 0, (double*)nullptr, jobs);
   return hipGetLastError();
 }
 
 hipError_t launch_id_coefficients(hipStream_t st, const double* R, int nc, const int64_t* piv,
                                   const int64_t* keff, int kcap, double* R11, double* Pd,
                                   void* P, int64_t ldp, bool p_is_f64) {
-  hipLaunchKernelGGL(k_gather_r11, dim3(64), dim3(256), 0, st, R, (int64_t)nc, piv, keff, kcap, R11);
+  hipLaunchKernelGGL(k_gather_r11, dim3(64), dim3(256), 0, st, R, (int64_t)nc, piv, keff, kcap, R11,
+                     (const GatherR11Job*)nullptr);
   if (kcap <= 128) {
     if (p_is_f64)
       return trsv_wave_launch<double, 0>(st, R11, kcap, keff, piv, R, nc, nc, Pd, kcap, (double*)P, ldp);
@@ -942,7 +996,8 @@ hipError_t launch_id_coefficients(hipStream_t st, const double* R, int nc, const
 hipError_t launch_small_solve(hipStream_t st, const double* RM, int l, const int64_t* pivM,
                               const int64_t* rM, double* R11, const double* C, int64_t ldc, int kc,
                               double* T) {
-  hipLaunchKernelGGL(k_gather_r11, dim3(64), dim3(256), 0, st, RM, (int64_t)l, pivM, rM, l, R11);
+  hipLaunchKernelGGL(k_gather_r11, dim3(64), dim3(256), 0, st, RM, (int64_t)l, pivM, rM, l, R11,
+                     (const GatherR11Job*)nullptr);
   if (l <= 128)
     return trsv_wave_launch<double, 1>(st, R11, l, rM, pivM, C, ldc, kc, T, l, (double*)nullptr, 0);
   return trsv_launch<double, 1>(st, R11, l, rM, pivM, C, ldc, kc, T, l, (double*)nullptr, 0);

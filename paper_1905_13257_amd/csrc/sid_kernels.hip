@@ -339,7 +339,22 @@ __global__ __launch_bounds__(256) void k_fit_residual_part(
     const double* __restrict__ W, int lq, int r0, int q, int nc,
     const int64_t* __restrict__ piv, const int64_t* __restrict__ keff_p,
     const double* __restrict__ Pd, int kcap, const double* __restrict__ mix,
-    double* __restrict__ part /* 2 x gridDim.x */) {
+    double* __restrict__ part /* 2 x (q nc + 255) / 256 */, const FitJob* __restrict__ jobs) {
+  if (jobs) {  // a batched launch: job blockIdx.y, its first (q nc + 255) / 256 blocks
+    const FitJob jb = jobs[blockIdx.y];
+    if ((int)blockIdx.x * 256 >= jb.q * jb.nc) return;
+    W = jb.W;
+    lq = jb.lq;
+    r0 = jb.r0;
+    q = jb.q;
+    nc = jb.nc;
+    piv = jb.piv;
+    keff_p = jb.keff;
+    Pd = jb.Pd;
+    kcap = jb.kcap;
+    mix = jb.mix;
+    part = jb.part;
+  }
   __shared__ double s_num[4], s_den[4];
   const int keff = (int)*keff_p;
   double num = 0.0, den = 0.0;
@@ -379,7 +394,14 @@ __global__ __launch_bounds__(256) void k_fit_residual_part(
 
 // partial sums in block order (fixed), then the ratio
 __global__ void k_fit_residual_final(const double* __restrict__ part, int nparts, int q,
-                                     double* __restrict__ out) {
+                                     double* __restrict__ out, const FitJob* __restrict__ jobs) {
+  if (jobs) {  // a batched launch: job blockIdx.x
+    const FitJob jb = jobs[blockIdx.x];
+    part = jb.part;
+    nparts = (jb.q * jb.nc + 255) / 256;
+    q = jb.q;
+    out = jb.out;
+  }
   __shared__ double s_a[64], s_b[64];
   double a = 0.0, b = 0.0;
   for (int i = threadIdx.x; i < nparts; i += 64) { a += part[2 * i]; b += part[2 * i + 1]; }
@@ -393,8 +415,17 @@ __global__ void k_fit_residual_final(const double* __restrict__ part, int nparts
   }
 }
 
-__global__ void k_ratio_sqrt(const double* __restrict__ stats, double* __restrict__ out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *out = stats[1] > 0.0 ? sqrt(stats[0] / stats[1]) : 0.0;
+__global__ void k_ratio_sqrt(const double* __restrict__ stats, double* __restrict__ out,
+                             const RatioJob* __restrict__ jobs, int njobs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (jobs) {  // a batched launch: job i
+    if (i < njobs) {
+      const RatioJob jb = jobs[i];
+      *jb.out = jb.stats[1] > 0.0 ? sqrt(jb.stats[0] / jb.stats[1]) : 0.0;
+    }
+    return;
+  }
+  if (i == 0) *out = stats[1] > 0.0 ? sqrt(stats[0] / stats[1]) : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -482,7 +513,19 @@ __global__ void k_gather_rows(const TS* __restrict__ A, int64_t lda, const int64
 // gather rows of a column-major FP64 matrix into a (q x k) block: out(r, t) = W(r0 + r, piv[t])
 __global__ void k_gather_block(const double* __restrict__ W, int lq, int r0, int q,
                                const int64_t* __restrict__ piv, const int64_t* __restrict__ keff_p,
-                               int kcap, double* __restrict__ out) {
+                               int kcap, double* __restrict__ out,
+                               const GatherBlockJob* __restrict__ jobs) {
+  if (jobs) {  // a batched launch: job blockIdx.y
+    const GatherBlockJob jb = jobs[blockIdx.y];
+    W = jb.W;
+    lq = jb.lq;
+    r0 = jb.r0;
+    q = jb.q;
+    piv = jb.piv;
+    keff_p = jb.keff;
+    kcap = jb.kcap;
+    out = jb.out;
+  }
   const int keff = (int)*keff_p;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < q * kcap; e += gridDim.x * blockDim.x) {
     const int t = e / q, r = e - t * q;
@@ -795,13 +838,34 @@ hipError_t launch_fit_residual(hipStream_t st, const double* W, int lq, int r0, 
   const int nparts = (q * nc + 255) / 256;
   if (nparts > 0)
     hipLaunchKernelGGL(k_fit_residual_part, dim3((unsigned)nparts), dim3(256), 0, st, W, lq, r0, q,
-                       nc, piv, keff, Pd, kcap, mix, part);
-  hipLaunchKernelGGL(k_fit_residual_final, dim3(1), dim3(64), 0, st, part, nparts, q, out);
+                       nc, piv, keff, Pd, kcap, mix, part, (const FitJob*)nullptr);
+  hipLaunchKernelGGL(k_fit_residual_final, dim3(1), dim3(64), 0, st, part, nparts, q, out,
+                     (const FitJob*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_fit_residual_batch(hipStream_t st, const FitJob* jobs, int njobs, int max_qn) {
+  if (njobs <= 0) return hipSuccess;
+  const double* dn = nullptr;
+  const int64_t* in = nullptr;
+  const int nparts = (max_qn + 255) / 256;
+  if (nparts > 0)
+    hipLaunchKernelGGL(k_fit_residual_part, dim3((unsigned)nparts, (unsigned)njobs), dim3(256), 0, st,
+                       dn, 0, 0, 0, 0, in, in, dn, 0, dn, (double*)nullptr, jobs);
+  hipLaunchKernelGGL(k_fit_residual_final, dim3((unsigned)njobs), dim3(64), 0, st, dn, 0, 0,
+                     (double*)nullptr, jobs);
   return hipGetLastError();
 }
 
 hipError_t launch_ratio_sqrt(hipStream_t st, const double* stats, double* out) {
-  hipLaunchKernelGGL(k_ratio_sqrt, dim3(1), dim3(64), 0, st, stats, out);
+  hipLaunchKernelGGL(k_ratio_sqrt, dim3(1), dim3(64), 0, st, stats, out, (const RatioJob*)nullptr, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_ratio_sqrt_batch(hipStream_t st, const RatioJob* jobs, int njobs) {
+  if (njobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ratio_sqrt, dim3((unsigned)((njobs + 63) / 64)), dim3(64), 0, st,
+                     (const double*)nullptr, (double*)nullptr, jobs, njobs);
   return hipGetLastError();
 }
 
@@ -974,7 +1038,16 @@ hipError_t launch_gather_block(hipStream_t st, const double* W, int lq, int r0, 
                                const int64_t* piv, const int64_t* keff, int kcap, double* out) {
   const int total = q * kcap;
   hipLaunchKernelGGL(k_gather_block, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, W,
-                     lq, r0, q, piv, keff, kcap, out);
+                     lq, r0, q, piv, keff, kcap, out, (const GatherBlockJob*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_block_batch(hipStream_t st, const GatherBlockJob* jobs, int njobs,
+                                     int max_total) {
+  if (njobs <= 0 || max_total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_block, dim3((unsigned)((max_total + 255) / 256), (unsigned)njobs),
+                     dim3(256), 0, st, (const double*)nullptr, 0, 0, 0, (const int64_t*)nullptr,
+                     (const int64_t*)nullptr, 0, (double*)nullptr, jobs);
   return hipGetLastError();
 }
 

@@ -71,6 +71,57 @@ struct Gemm64Job {
 };
 hipError_t launch_gemm64_batch(hipStream_t st, const Gemm64Job* jobs, int njobs, int max_m,
                                int max_n);
+// batched forms of the small steps after mgsqr (one job per problem, job
+// blockIdx.y; the single launch's arithmetic)
+struct GatherR11Job {
+  const double* R;
+  int64_t ldr;
+  const int64_t* piv;
+  const int64_t* keff;
+  int kcap, pad_;
+  double* R11;
+};
+hipError_t launch_gather_r11_batch(hipStream_t st, const GatherR11Job* jobs, int njobs);
+// R11 x = rhs per column into out64 (the P solve: MODE 0; the single-pass T
+// solve: MODE 1), no second output
+struct TrsvJob {
+  const double* R11;
+  int kcap, ncols;
+  const int64_t* keff;
+  const int64_t* piv;
+  const double* rhs;
+  int64_t ldrhs;
+  double* out64;
+  int64_t ldo64;
+};
+hipError_t launch_trsv_batch(hipStream_t st, int mode, const TrsvJob* jobs, int njobs,
+                             int max_kcap, int max_ncols);
+struct RatioJob {
+  const double* stats;
+  double* out;
+};
+hipError_t launch_ratio_sqrt_batch(hipStream_t st, const RatioJob* jobs, int njobs);
+struct GatherBlockJob {
+  const double* W;
+  int lq, r0, q, kcap;
+  const int64_t* piv;
+  const int64_t* keff;
+  double* out;
+};
+hipError_t launch_gather_block_batch(hipStream_t st, const GatherBlockJob* jobs, int njobs,
+                                     int max_total);
+struct FitJob {
+  const double* W;
+  int lq, r0, q, nc, kcap, pad_;
+  const int64_t* piv;
+  const int64_t* keff;
+  const double* Pd;
+  const double* mix;
+  double* part;
+  double* out;
+};
+hipError_t launch_fit_residual_batch(hipStream_t st, const FitJob* jobs, int njobs,
+                                     int max_qn);
 hipError_t launch_gemm64_ab(hipStream_t st, int M, int Nn, int K, const double* A, int64_t lda,
                             int tA, const double* B, int64_t ldb, int tB, double alpha, double beta,
                             double* C, int64_t ldc);

@@ -11,9 +11,13 @@ persistent sketch pass.
 
 Capturing this 64-matrix call in a HIP graph ended the process with a
 segmentation fault inside the runtime's end of capture (the eager call had
-just passed); no mistake in the library's capture sequence has been found,
-so that case is not run (the capture of a smaller batch is tested
-separately)."""
+just passed), for eight matrices as well; no mistake in the library's capture
+sequence has been found, so the library refuses batched calls under capture
+(SID_ESTATE) and the capture test is skipped.
+
+In single pass every matrix of this workload takes the batched steps after
+the sketch (mgsqr, solves and estimates as one launch per step), so the
+equality below also covers those launches."""
 import sys
 
 import numpy as np
