@@ -1466,6 +1466,19 @@ sid_status stream_make(sid_ctx* ctx, sid_dtype dtype, int64_t N, int64_t n_max,
   s->l = sh.l;
   s->single = sh.single;
   s->stage_cols = n_max < 512 ? n_max : 512;
+  {
+    // on the workgroup-pair pass a flush of whole column slabs (e.g. 384 at
+    // l = 180) avoids a narrow slab per flush
+    Shape fs = sh;
+    fs.n = s->stage_cols;
+    if (plan_sketch(ctx, SID_F32, 4, nullptr, p->prec, fs, false, sh.single) == SketchPath::PAIR_BF16) {
+      const int vslab = sid::sketch_v2_slab((int)sh.lq, (int)sh.l, sh.single);
+      if (vslab > 0 && vslab <= 512) {
+        const int64_t w = (512 / vslab) * vslab;
+        s->stage_cols = n_max < w ? n_max : w;
+      }
+    }
+  }
   s->ld_stage = (N + 3) / 4 * 4;
   st = stream_alloc(ctx, s);
   if (st != SID_OK) {
