@@ -1748,6 +1748,8 @@ sid_status sid_stream_restore(sid_ctx* ctx, const void* host_buf, size_t bytes, 
 // The children start after the work already queued on the context's stream
 // and the context's stream waits for all of them.
 // ---------------------------------------------------------------------------
+// (C++ linkage: these helpers pass std::string and std::vector)
+extern "C++" {
 namespace {
 constexpr int SID_BATCH_STREAMS_MAX = 8;
 constexpr size_t SID_BATCH_PLANS = 8;
@@ -2334,6 +2336,7 @@ int tune_lookup(sid_ctx* ctx, const std::string& key) {
   return 0;
 }
 }  // namespace
+}  // extern "C++"
 
 sid_status sid_compress_batched(sid_ctx* ctx, const sid_problem* probs, int64_t count,
                                 sid_dtype dtype) {
