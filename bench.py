@@ -331,7 +331,7 @@ def spid_main(args, torch, sid, synth) -> int:
                                             "bytes": rbytes,
                                             "timed": "whole call: operand packing + fused kernel"},
                    "error_kernel_ms": round(ms_e, 4),
-                   "rel_fro_error_fine": err["rel_fro"], "rel_max_error_fine": err["rel_max"],
+                   "rel_fro_error_fine": err["rel_fro"], "max_abs_error_fine": err["max_abs"],
                    "rel_fro_error_subsampled_two_pass": err_sub["rel_fro"],
                    "probe_estimate_coarse": float(c.err[0]), "k_eff": int(c.k_eff[0])},
     }
