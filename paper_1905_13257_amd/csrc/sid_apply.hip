@@ -35,8 +35,8 @@ typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 constexpr int AS_WAVES = 4;
 constexpr int AS_THREADS = 64 * AS_WAVES;
-constexpr int AS_LPAD = 128;        // l <= 128: four K steps of 32
-constexpr int AS_LS = AS_LPAD + 8;  // LDS row stride of T's split (bf16)
+// LP: l padded to a multiple of 32 (128: four K steps, 192: six); the LDS
+// row stride of T's split is LP + 8 bf16
 constexpr int AS_RT = 1;                  // row tiles of 16 per wave
 constexpr int AS_ROWS = AS_WAVES * 16 * AS_RT;  // rows per block (64)
 constexpr int AS_OS = AS_ROWS + 4;        // LDS row stride of the output staging (floats)
@@ -44,15 +44,17 @@ constexpr int AS_SL = AS_ROWS / 4;        // threads per column in the store pha
 
 __device__ __forceinline__ __bf16 to_bf16(float f) { return (__bf16)f; }
 
-template <int KT, bool VEC>
+template <int KT, bool VEC, int LP>
 __global__ __launch_bounds__(AS_THREADS) void k_apply_t_bf16_runs(
     const float* __restrict__ Y, int64_t N, int l, const double* __restrict__ Tm /* l x k */,
     int k, float* __restrict__ AJ, int64_t ldaj) {
+  constexpr int AS_LS = LP + 8;
+  constexpr int NKS = LP / 32;
   __shared__ __attribute__((aligned(16))) __bf16 s_th[KT * 16 * AS_LS];
   __shared__ __attribute__((aligned(16))) __bf16 s_tl[KT * 16 * AS_LS];
   __shared__ __attribute__((aligned(16))) float s_o[16 * AS_OS];
-  for (int e = threadIdx.x; e < KT * 16 * AS_LPAD; e += AS_THREADS) {
-    const int m = e / AS_LPAD, c = e - m * AS_LPAD;
+  for (int e = threadIdx.x; e < KT * 16 * LP; e += AS_THREADS) {
+    const int m = e / LP, c = e - m * LP;
     const float x = (m < k && c < l) ? (float)Tm[c + (int64_t)l * m] : 0.0f;
     const __bf16 h = to_bf16(x);
     s_th[m * AS_LS + c] = h;
@@ -68,14 +70,14 @@ __global__ __launch_bounds__(AS_THREADS) void k_apply_t_bf16_runs(
   // t / AS_SL (+ AS_THREADS / AS_SL per pass) of the group
   const int sr = 4 * (threadIdx.x % AS_SL), sc = threadIdx.x / AS_SL;
   constexpr int SPASS = 16 / (AS_THREADS / AS_SL);
-  f32x4_t y[AS_RT][4][2];
+  f32x4_t y[AS_RT][NKS][2];
   auto load_block = [&](int64_t b) {
     const int64_t row0 = b * AS_ROWS + wave * 16 * AS_RT;
 #pragma unroll
     for (int rt = 0; rt < AS_RT; ++rt) {
       const int64_t row = row0 + rt * 16 + lr;
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks)
+      for (int ks = 0; ks < NKS; ++ks)
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const int c = 32 * ks + 8 * lg + 4 * h;
@@ -88,11 +90,11 @@ __global__ __launch_bounds__(AS_THREADS) void k_apply_t_bf16_runs(
   if (b < nblk) load_block(b);
   for (; b < nblk; b += gridDim.x) {
     const int64_t blk0 = b * AS_ROWS;
-    bf16x8_t bh[AS_RT][4], bl[AS_RT][4];
+    bf16x8_t bh[AS_RT][NKS], bl[AS_RT][NKS];
 #pragma unroll
     for (int rt = 0; rt < AS_RT; ++rt)
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks)
+      for (int ks = 0; ks < NKS; ++ks)
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
           const float x = y[rt][ks][i >> 2][i & 3];
@@ -107,7 +109,7 @@ __global__ __launch_bounds__(AS_THREADS) void k_apply_t_bf16_runs(
 #pragma unroll
       for (int kt = 0; kt < KT; ++kt) acc[rt][kt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
+    for (int ks = 0; ks < NKS; ++ks) {
       if (ks >= nks) break;
 #pragma unroll
       for (int kt = 0; kt < KT; ++kt) {
@@ -163,7 +165,8 @@ __global__ __launch_bounds__(AS_THREADS) void k_apply_t_bf16_runs(
 }  // namespace
 
 bool apply_t_bf16_runs_supported(int k, int l) {
-  return k >= 1 && k <= 128 && l >= 1 && l <= AS_LPAD && (l % 4) == 0;
+  if (k < 1 || l < 1 || (l % 4) != 0) return false;
+  return (l <= 128 && k <= 128) || (l <= 192 && k <= 160);
 }
 
 hipError_t launch_apply_t_bf16_runs(hipStream_t st, const float* Y, int64_t N, int l,
@@ -175,18 +178,29 @@ hipError_t launch_apply_t_bf16_runs(hipStream_t st, const float* Y, int64_t N, i
   const dim3 grid((unsigned)g), block(AS_THREADS);
   const bool vec = (ldaj % 4) == 0 && ((uintptr_t)AJ % 16) == 0;
   const int kt = (k + 15) / 16;
-#define SID_AS(KT_)                                                                            \
+#define SID_AS(KT_, LP_)                                                                       \
   case KT_:                                                                                    \
     if (vec)                                                                                   \
-      hipLaunchKernelGGL((k_apply_t_bf16_runs<KT_, true>), grid, block, 0, st, Y, N, l, Tm, k, \
-                         AJ, ldaj);                                                            \
+      hipLaunchKernelGGL((k_apply_t_bf16_runs<KT_, true, LP_>), grid, block, 0, st, Y, N, l,   \
+                         Tm, k, AJ, ldaj);                                                     \
     else                                                                                       \
-      hipLaunchKernelGGL((k_apply_t_bf16_runs<KT_, false>), grid, block, 0, st, Y, N, l, Tm,   \
-                         k, AJ, ldaj);                                                         \
+      hipLaunchKernelGGL((k_apply_t_bf16_runs<KT_, false, LP_>), grid, block, 0, st, Y, N, l,  \
+                         Tm, k, AJ, ldaj);                                                     \
     break;
-  switch (kt) {
-    SID_AS(1) SID_AS(2) SID_AS(3) SID_AS(4) SID_AS(5) SID_AS(6) SID_AS(7) SID_AS(8)
-    default: return hipErrorInvalidValue;
+  if (l <= 128) {
+    switch (kt) {
+      SID_AS(1, 128) SID_AS(2, 128) SID_AS(3, 128) SID_AS(4, 128) SID_AS(5, 128) SID_AS(6, 128)
+      SID_AS(7, 128) SID_AS(8, 128)
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    // l up to 192: six K steps; T's split takes up to 128 KB of LDS (one
+    // workgroup per CU)
+    switch (kt) {
+      SID_AS(1, 192) SID_AS(2, 192) SID_AS(3, 192) SID_AS(4, 192) SID_AS(5, 192) SID_AS(6, 192)
+      SID_AS(7, 192) SID_AS(8, 192) SID_AS(9, 192) SID_AS(10, 192)
+      default: return hipErrorInvalidValue;
+    }
   }
 #undef SID_AS
   return hipGetLastError();

@@ -668,6 +668,24 @@ def test_pair_pass_y_over_column_slabs(sid, oracle_mod, prec):
     assert np.array_equal(host(got.P), host(ref.P))
     np.testing.assert_allclose(host(got.AJ), host(ref.AJ), rtol=0,
                                atol=2e-4 * np.abs(host(ref.AJ)).max())
+    # AJ = Y T at l = 180, k = 150 on the bf16 matrix cores (hi + lo splits of
+    # Y and T, three products): T = M^+ W(0:lz, J) with M = W(0:lz, :) Omega
+    # formed from the GPU's W (no truncation on either side), each entry of AJ
+    # within 2^-15 of sum_t |Y(i, t)| |T(t, j)|
+    tight = sid.compress(A, k, p, seed=5, mode="single_pass", prec=prec, probe_rows=q,
+                         sp_rcond=1e-12)
+    torch.cuda.synchronize()
+    J = host(tight.J)
+    Wg = host(W).astype(np.float64)
+    Yg = host(Y).astype(np.float64)
+    lz = l + p
+    M = Wg[:lz] @ Om
+    T = np.linalg.pinv(M, rcond=1e-12) @ Wg[:lz][:, J]
+    AJo = Yg @ T
+    bound = 2.0 ** -15 * (np.abs(Yg) @ np.abs(T)) + 1e-30
+    dAJ = np.abs(host(tight.AJ).astype(np.float64) - AJo)
+    say("pair-pass AJ max |dAJ| / bound", (dAJ / bound).max())
+    assert np.all(dAJ <= bound)
 
 
 def test_graph_capture_replay(sid, oracle_mod):
