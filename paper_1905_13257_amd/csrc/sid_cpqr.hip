@@ -824,11 +824,19 @@ __global__ __launch_bounds__(64) void k_trsv_multi(
 
 // The same solves with one wave per right-hand side (column-oriented back
 // substitution: x_a = rhs_a / R11(a, a), then rhs_b -= R11(b, a) x_a for
-// b < a in parallel over the lanes), R11 staged transposed in LDS.  For
-// kcap <= 128 (two rows per lane).
+// b < a in parallel over the lanes), R11 staged transposed in LDS.  NV = 2:
+// kcap <= 128 (two rows per lane), R11 as a full kcap x kcap array; NV = 3:
+// kcap <= TW_KMAX3 (three rows per lane), only the upper triangle, column a
+// (rows 0..a) at a (a + 1) / 2, so that it fits the LDS.  The same
+// operations in the same order either way.
 constexpr int TW_WAVES = 8;
+constexpr int TW_KMAX3 = 184;
 
-template <typename OutT, int MODE>
+__host__ __device__ constexpr int trsv_wave_rt(int nv, int kcap) {
+  return nv == 2 ? kcap * kcap + 128 : kcap * (kcap + 1) / 2 + 192;
+}
+
+template <typename OutT, int MODE, int NV = 2>
 __global__ __launch_bounds__(64 * TW_WAVES) void k_trsv_wave(
     const double* __restrict__ R11, int kcap, const int64_t* __restrict__ keff_p,
     const int64_t* __restrict__ piv, const double* __restrict__ rhs, int64_t ldrhs, int ncols,
@@ -848,15 +856,22 @@ __global__ __launch_bounds__(64 * TW_WAVES) void k_trsv_wave(
     out = nullptr;
   }
   extern __shared__ double s_tw[];
-  double* s_rt = s_tw;                           // [a][b] = R11(b, a), kcap^2 (+128 pad)
-  double* s_dinv = s_rt + kcap * kcap + 128;     // 1 / R11(a, a)
-  double* s_x = s_dinv + kcap;                   // [wave][a]
-  int* s_inv = (int*)(s_x + TW_WAVES * kcap);    // inverse pivot permutation (mode 1)
+  double* s_rt = s_tw;                              // R11 transposed (see above; padded)
+  double* s_dinv = s_rt + trsv_wave_rt(NV, kcap);   // 1 / R11(a, a)
+  double* s_x = s_dinv + kcap;                      // [wave][a]
+  int* s_inv = (int*)(s_x + TW_WAVES * kcap);       // inverse pivot permutation (mode 1)
   const int keff = (int)*keff_p;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int e = tid; e < kcap * kcap + 128; e += 64 * TW_WAVES) {
-    const int a = e / kcap, b = e - a * kcap;
-    s_rt[e] = (a < keff && b < keff) ? R11[(int64_t)b * kcap + a] : 0.0;
+  if constexpr (NV == 2) {
+    for (int e = tid; e < kcap * kcap + 128; e += 64 * TW_WAVES) {
+      const int a = e / kcap, b = e - a * kcap;
+      s_rt[e] = (a < keff && b < keff) ? R11[(int64_t)b * kcap + a] : 0.0;
+    }
+  } else {
+    for (int a = w; a < kcap; a += TW_WAVES)
+      for (int b = lane; b <= a; b += 64)
+        s_rt[a * (a + 1) / 2 + b] = (a < keff && b < keff) ? R11[(int64_t)b * kcap + a] : 0.0;
+    for (int e = tid; e < 192; e += 64 * TW_WAVES) s_rt[kcap * (kcap + 1) / 2 + e] = 0.0;
   }
   for (int a = tid; a < kcap; a += 64 * TW_WAVES) {
     s_dinv[a] = a < keff ? 1.0 / R11[(int64_t)a * kcap + a] : 0.0;
@@ -868,44 +883,57 @@ __global__ __launch_bounds__(64 * TW_WAVES) void k_trsv_wave(
   __syncthreads();
   const int j = blockIdx.x * TW_WAVES + w;
   if (j >= ncols) return;
-  const int b0 = lane, b1 = lane + 64;
+  const int b0 = lane, b1 = lane + 64, b2 = lane + 128;
   auto rhs_at = [&](int a) -> double {
     return MODE == 0 ? rhs[(int64_t)a * ldrhs + j] : rhs[a + ldrhs * (int64_t)j];
   };
   double v0 = b0 < keff ? rhs_at(b0) : 0.0;
   double v1 = b1 < keff ? rhs_at(b1) : 0.0;
+  double v2 = (NV == 3 && b2 < keff) ? rhs_at(b2) : 0.0;
   int pos = -1;
   if (MODE == 0) {
     const bool hit0 = b0 < keff && piv[b0] == j, hit1 = b1 < keff && piv[b1] == j;
     const uint64_t m0 = __ballot(hit0), m1 = __ballot(hit1);
     pos = m0 ? __ffsll((unsigned long long)m0) - 1 : m1 ? 64 + __ffsll((unsigned long long)m1) - 1 : -1;
+    if constexpr (NV == 3) {
+      const uint64_t m2 = __ballot(b2 < keff && piv[b2] == j);
+      if (pos < 0 && m2) pos = 128 + __ffsll((unsigned long long)m2) - 1;
+    }
   }
   if (pos < 0) {
     for (int a = keff - 1; a >= 0; --a) {
       // rhs_a (already reduced) from lane a & 63, as two 32-bit halves
-      const long long bits = __double_as_longlong(a < 64 ? v0 : v1);
+      const double va = NV == 3 ? (a < 64 ? v0 : a < 128 ? v1 : v2) : (a < 64 ? v0 : v1);
+      const long long bits = __double_as_longlong(va);
       const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)bits, a & 63);
       const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(bits >> 32), a & 63);
       const double xa = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo)) * s_dinv[a];
-      const double* col = s_rt + a * kcap;
+      // (entries past row a of the column are read but not used)
+      const double* col = s_rt + (NV == 2 ? a * kcap : a * (a + 1) / 2);
       const double u0 = fma(-col[b0], xa, v0), u1 = fma(-col[b1], xa, v1);
       v0 = b0 < a ? u0 : (b0 == a ? xa : v0);
       v1 = b1 < a ? u1 : (b1 == a ? xa : v1);
+      if constexpr (NV == 3) {
+        const double u2 = fma(-col[b2], xa, v2);
+        v2 = b2 < a ? u2 : (b2 == a ? xa : v2);
+      }
     }
   }
   if (MODE == 0) {
     double* x = out64 + ldo64 * j;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int a = h ? b1 : b0;
+    for (int h = 0; h < NV; ++h) {
+      const int a = h == 0 ? b0 : h == 1 ? b1 : b2;
       if (a >= kcap) continue;
-      const double v = pos >= 0 ? (a == pos ? 1.0 : 0.0) : (a < keff ? (h ? v1 : v0) : 0.0);
+      const double vh = h == 0 ? v0 : h == 1 ? v1 : v2;
+      const double v = pos >= 0 ? (a == pos ? 1.0 : 0.0) : (a < keff ? vh : 0.0);
       x[a] = v;
       if (out) out[a + ldo * j] = (OutT)v;
     }
   } else {
     if (b0 < keff) s_x[w * kcap + b0] = v0;
     if (b1 < keff) s_x[w * kcap + b1] = v1;
+    if (NV == 3 && b2 < keff) s_x[w * kcap + b2] = v2;
     __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): this wave's LDS writes done
     __builtin_amdgcn_wave_barrier();
     double* x = out64 + ldo64 * j;
@@ -916,13 +944,14 @@ __global__ __launch_bounds__(64 * TW_WAVES) void k_trsv_wave(
   }
 }
 
-template <typename OutT, int MODE>
+template <typename OutT, int MODE, int NV = 2>
 static hipError_t trsv_wave_launch(hipStream_t st, const double* R11, int kcap, const int64_t* keff,
                                    const int64_t* piv, const double* rhs, int64_t ldrhs, int ncols,
                                    double* out64, int64_t ldo64, OutT* out, int64_t ldo) {
-  const size_t shm = sizeof(double) * ((size_t)kcap * kcap + 128 + kcap + (size_t)TW_WAVES * kcap) +
-                     sizeof(int) * (size_t)kcap;
-  auto kern = k_trsv_wave<OutT, MODE>;
+  const size_t shm =
+      sizeof(double) * ((size_t)trsv_wave_rt(NV, kcap) + kcap + (size_t)TW_WAVES * kcap) +
+      sizeof(int) * (size_t)kcap;
+  auto kern = k_trsv_wave<OutT, MODE, NV>;
   if (shm > 65536)
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   hipLaunchKernelGGL(kern, dim3((unsigned)((ncols + TW_WAVES - 1) / TW_WAVES)), dim3(64 * TW_WAVES),
@@ -988,6 +1017,13 @@ hipError_t launch_id_coefficients(hipStream_t st, const double* R, int nc, const
       return trsv_wave_launch<double, 0>(st, R11, kcap, keff, piv, R, nc, nc, Pd, kcap, (double*)P, ldp);
     return trsv_wave_launch<float, 0>(st, R11, kcap, keff, piv, R, nc, nc, Pd, kcap, (float*)P, ldp);
   }
+  if (kcap <= TW_KMAX3) {
+    if (p_is_f64)
+      return trsv_wave_launch<double, 0, 3>(st, R11, kcap, keff, piv, R, nc, nc, Pd, kcap, (double*)P,
+                                            ldp);
+    return trsv_wave_launch<float, 0, 3>(st, R11, kcap, keff, piv, R, nc, nc, Pd, kcap, (float*)P,
+                                         ldp);
+  }
   if (p_is_f64)
     return trsv_launch<double, 0>(st, R11, kcap, keff, piv, R, nc, nc, Pd, kcap, (double*)P, ldp);
   return trsv_launch<float, 0>(st, R11, kcap, keff, piv, R, nc, nc, Pd, kcap, (float*)P, ldp);
@@ -1000,6 +1036,8 @@ hipError_t launch_small_solve(hipStream_t st, const double* RM, int l, const int
                      (const GatherR11Job*)nullptr);
   if (l <= 128)
     return trsv_wave_launch<double, 1>(st, R11, l, rM, pivM, C, ldc, kc, T, l, (double*)nullptr, 0);
+  if (l <= TW_KMAX3)
+    return trsv_wave_launch<double, 1, 3>(st, R11, l, rM, pivM, C, ldc, kc, T, l, (double*)nullptr, 0);
   return trsv_launch<double, 1>(st, R11, l, rM, pivM, C, ldc, kc, T, l, (double*)nullptr, 0);
 }
 
