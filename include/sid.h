@@ -502,11 +502,19 @@ sid_status sid_svd_stream_finish(sid_stream *s, double *S, void *U, int64_t ldu,
  * Gaussian selection over all rows, no refinement, n <= 512, l <= 128 and
  * l + e + q <= 160, one persistent launch sketches all of them: a work queue
  * of every problem's row shares (the problems with the most work per share
- * first), then one launch forms every W.  The factorizations then run per
- * problem on up to 8 internal child streams (own workspace each).  Other
- * batches run each problem's sid_compress on the child streams.  Everything
- * runs after the work already queued on the context's stream, which waits
- * for all of it before the call returns.
+ * first), then one launch forms every W.  The pivoted QRs of all problems
+ * whose shapes a one-workgroup factorization takes (W_sel's l x n and,
+ * single pass, M's lz x l) go into a few launches, one per
+ * kernel instance, side by side on up to 8 internal child streams, after two
+ * launches for the single-pass products they need.  When every problem is
+ * single pass with a fixed rank k <= 128, the steps after the QR (R11, the
+ * coefficient solve, both estimates, T) are one launch each for the batch,
+ * and only P's conversion, AJ = Y T and the result copies run per problem
+ * on the child streams; otherwise each problem's remaining factorization
+ * runs on a child stream (own workspace each).  Other batches run each
+ * problem's sid_compress on the child streams.  Everything runs after the
+ * work already queued on the context's stream, which waits for all of it
+ * before the call returns.
  *
  * The persistent path keeps a plan per problem set (the queue table and the
  * problems' partials, W, Omega and Y in device memory owned by the context;
