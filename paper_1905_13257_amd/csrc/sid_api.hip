@@ -106,8 +106,9 @@ struct BatchPlan {
   void* dev = nullptr;
   size_t bytes = 0;
   sid::FbBatchEntry* d_tab = nullptr;
-  unsigned int* d_queue = nullptr;
-  int64_t nshares = 0, max_lqn = 0;
+  unsigned int* d_queue = nullptr;          // one counter per layout class
+  std::vector<sid::FbBatchClass> classes;  // the table's layout classes, in order
+  int64_t max_lqn = 0;
   int max_n = 0;
   std::vector<double*> W;       // by problem index
   std::vector<float*> Y, omega;
@@ -1860,14 +1861,16 @@ sid_status batch_plan(sid_ctx* ctx, const sid_problem* probs, int64_t count,
     return fail(ctx, SID_ESTATE,
                 "batched call under graph capture: build its plan first (sid_reserve_batched, or "
                 "an eager call with the same problems)");
-  // queue order: the most work per share first
+  // queue order: by layout class, then the most work per share first
   std::vector<int64_t> rpw((size_t)count), nsh((size_t)count);
-  std::vector<int> order((size_t)count);
+  std::vector<int> order((size_t)count), cls((size_t)count);
   for (int64_t b = 0; b < count; ++b) {
     nsh[(size_t)b] = sid::fused_bf16_grid(sh[(size_t)b].N, ctx->num_cu, &rpw[(size_t)b]);
     order[(size_t)b] = (int)b;
+    cls[(size_t)b] = sid::fused_bf16_batch_class((int)sh[(size_t)b].lq, (int)sh[(size_t)b].l, wanty);
   }
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    if (cls[(size_t)x] != cls[(size_t)y]) return cls[(size_t)x] < cls[(size_t)y];
     return rpw[(size_t)x] * sh[(size_t)x].n > rpw[(size_t)y] * sh[(size_t)y].n;
   });
   auto up = [](size_t v) { return (v + 255) / 256 * 256; };
@@ -1972,9 +1975,16 @@ sid_status batch_plan(sid_ctx* ctx, const sid_problem* probs, int64_t count,
   pl->fac.assign((size_t)count, BatchFactor{});
   std::vector<sid::FbBatchEntry> tab((size_t)count);
   int64_t share0 = 0;
+  pl->classes.clear();
   for (int64_t qpos = 0; qpos < count; ++qpos) {
     const int b = order[(size_t)qpos];
     const Shape& s = sh[(size_t)b];
+    if (pl->classes.empty() || pl->classes.back().cls != cls[(size_t)b]) {
+      // a new class: its own queue, shares numbered from 0
+      pl->classes.push_back(sid::FbBatchClass{cls[(size_t)b], (int)qpos, 0, 0});
+      share0 = 0;
+    }
+    ++pl->classes.back().count;
     sid::FbBatchEntry& e = tab[(size_t)qpos];
     e.A = (const float*)probs[b].A;
     e.lda = probs[b].lda;
@@ -1982,12 +1992,13 @@ sid_status batch_plan(sid_ctx* ctx, const sid_problem* probs, int64_t count,
     e.n = (int)s.n;
     e.lq = (int)s.lq;
     e.l = (int)s.l;
-    e.pad_ = 0;
+    e.cls = cls[(size_t)b];
     e.seed = probs[b].params.seed;
     e.rows_per_wg = rpw[(size_t)b];
     e.share0 = share0;
     e.nshares = nsh[(size_t)b];
     share0 += e.nshares;
+    pl->classes.back().nshares = share0;
     e.part = (float*)take(sizeof(float) * (size_t)(e.nshares * s.lq * s.n));
     e.W = (double*)take(sizeof(double) * (size_t)(s.lq * s.n));
     e.omega = nullptr;
@@ -2004,7 +2015,6 @@ sid_status batch_plan(sid_ctx* ctx, const sid_problem* probs, int64_t count,
     if (s.n > pl->max_n) pl->max_n = (int)s.n;
     if (s.lq * s.n > pl->max_lqn) pl->max_lqn = s.lq * s.n;
   }
-  pl->nshares = share0;
   // the factorization buffers and the mgsqr jobs (W_sel's, then M's),
   // grouped by kernel instance
   std::vector<std::pair<int, sid::CpqrJob>> jobs;
@@ -2151,13 +2161,33 @@ sid_status compress_batch(sid_ctx* ctx, const sid_problem* probs, int64_t count,
     if (ps != SID_OK) return ps;
   }
   const int nstreams = count < nstreams_want ? (int)count : nstreams_want;
-  sid_status st = ensure_children(ctx, nstreams);
+  const int ncls = persistent ? (int)plan->classes.size() : 0;
+  sid_status st = ensure_children(ctx, std::max(nstreams, ncls - 1));
   if (st != SID_OK) return st;
-  if (persistent)
-    SID_CHECK(sid::launch_sketch_fused_bf16_batch(ctx->stream, plan->dmode, plan->wanty, plan->d_tab,
-                                                  (int)count, plan->nshares, plan->max_n,
-                                                  plan->max_lqn, plan->d_queue, ctx->num_cu),
-              "batched sketch pass");
+  if (persistent) {
+    // the setup, then one persistent launch per layout class: the first on
+    // the context's stream, the others beside it on child streams, joined
+    // before the sums of the partials
+    SID_CHECK(sid::launch_sketch_batch_setup(ctx->stream, plan->dmode, plan->wanty, plan->d_tab,
+                                             (int)count, plan->max_n, plan->d_queue),
+              "batched sketch: setup");
+    if (ncls > 1) SID_CHECK(hipEventRecord(ctx->fork, ctx->stream), "batched sketch: fork event");
+    for (int c = 0; c < ncls; ++c) {
+      hipStream_t cs = c == 0 ? ctx->stream : ctx->children[(size_t)(c - 1)]->stream;
+      if (c > 0) SID_CHECK(hipStreamWaitEvent(cs, ctx->fork, 0), "batched sketch: fork wait");
+      SID_CHECK(sid::launch_sketch_batch_class(cs, plan->dmode, plan->wanty, plan->d_tab,
+                                               plan->classes[(size_t)c], plan->d_queue, ctx->num_cu),
+                "batched sketch pass");
+    }
+    for (int c = 1; c < ncls; ++c) {
+      const size_t ci = (size_t)(c - 1);
+      SID_CHECK(hipEventRecord(ctx->child_done[ci], ctx->children[ci]->stream),
+                "batched sketch: join event");
+      SID_CHECK(hipStreamWaitEvent(ctx->stream, ctx->child_done[ci], 0), "batched sketch: join wait");
+    }
+    SID_CHECK(sid::launch_reduce_partials_batch(ctx->stream, plan->d_tab, (int)count, plan->max_lqn),
+              "batched sketch: sums of the partials");
+  }
   SID_CHECK(hipEventRecord(ctx->fork, ctx->stream), "batched: fork event");
   for (int c = 0; c < nstreams; ++c)
     SID_CHECK(hipStreamWaitEvent(ctx->children[c]->stream, ctx->fork, 0), "batched: fork wait");

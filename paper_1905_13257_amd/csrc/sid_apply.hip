@@ -44,7 +44,10 @@ constexpr int AS_SL = AS_ROWS / 4;        // threads per column in the store pha
 
 __device__ __forceinline__ __bf16 to_bf16(float f) { return (__bf16)f; }
 
-template <int KT, bool VEC, int LP>
+// AL: l % 4 == 0, so Y's rows are 16-byte aligned and each lane's 8 entries
+// are two 16-byte loads; otherwise (l <= 128 only) eight 4-byte loads, the
+// entries past l zero.
+template <int KT, bool VEC, int LP, bool AL = true>
 __global__ __launch_bounds__(AS_THREADS) void k_apply_t_bf16_runs(
     const float* __restrict__ Y, int64_t N, int l, const double* __restrict__ Tm /* l x k */,
     int k, float* __restrict__ AJ, int64_t ldaj) {
@@ -81,8 +84,13 @@ __global__ __launch_bounds__(AS_THREADS) void k_apply_t_bf16_runs(
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const int c = 32 * ks + 8 * lg + 4 * h;
-          y[rt][ks][h] = (row < N && c + 4 <= l) ? *(gptr4)(Y + row * l + c)
-                                                 : f32x4_t{0.f, 0.f, 0.f, 0.f};
+          if constexpr (AL) {
+            y[rt][ks][h] = (row < N && c + 4 <= l) ? *(gptr4)(Y + row * l + c)
+                                                   : f32x4_t{0.f, 0.f, 0.f, 0.f};
+          } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) y[rt][ks][h][t] = (row < N && c + t < l) ? Y[row * l + c + t] : 0.f;
+          }
         }
     }
   };
@@ -165,8 +173,8 @@ __global__ __launch_bounds__(AS_THREADS) void k_apply_t_bf16_runs(
 }  // namespace
 
 bool apply_t_bf16_runs_supported(int k, int l) {
-  if (k < 1 || l < 1 || (l % 4) != 0) return false;
-  return (l <= 128 && k <= 128) || (l <= 192 && k <= 160);
+  if (k < 1 || l < 1) return false;
+  return (l <= 128 && k <= 128) || (l <= 192 && k <= 160 && (l % 4) == 0);
 }
 
 hipError_t launch_apply_t_bf16_runs(hipStream_t st, const float* Y, int64_t N, int l,
@@ -178,31 +186,39 @@ hipError_t launch_apply_t_bf16_runs(hipStream_t st, const float* Y, int64_t N, i
   const dim3 grid((unsigned)g), block(AS_THREADS);
   const bool vec = (ldaj % 4) == 0 && ((uintptr_t)AJ % 16) == 0;
   const int kt = (k + 15) / 16;
-#define SID_AS(KT_, LP_)                                                                       \
-  case KT_:                                                                                    \
-    if (vec)                                                                                   \
-      hipLaunchKernelGGL((k_apply_t_bf16_runs<KT_, true, LP_>), grid, block, 0, st, Y, N, l,   \
-                         Tm, k, AJ, ldaj);                                                     \
-    else                                                                                       \
-      hipLaunchKernelGGL((k_apply_t_bf16_runs<KT_, false, LP_>), grid, block, 0, st, Y, N, l,  \
-                         Tm, k, AJ, ldaj);                                                     \
+  const bool al = (l % 4) == 0;
+#define SID_AS_LAUNCH(KT_, V_, LP_, AL_)                                                        \
+  hipLaunchKernelGGL((k_apply_t_bf16_runs<KT_, V_, LP_, AL_>), grid, block, 0, st, Y, N, l, Tm, \
+                     k, AJ, ldaj)
+#define SID_AS(KT_, LP_, AL_)                     \
+  case KT_:                                       \
+    if (vec) SID_AS_LAUNCH(KT_, true, LP_, AL_);  \
+    else SID_AS_LAUNCH(KT_, false, LP_, AL_);     \
     break;
-  if (l <= 128) {
+  if (l <= 128 && al) {
     switch (kt) {
-      SID_AS(1, 128) SID_AS(2, 128) SID_AS(3, 128) SID_AS(4, 128) SID_AS(5, 128) SID_AS(6, 128)
-      SID_AS(7, 128) SID_AS(8, 128)
+      SID_AS(1, 128, true) SID_AS(2, 128, true) SID_AS(3, 128, true) SID_AS(4, 128, true)
+      SID_AS(5, 128, true) SID_AS(6, 128, true) SID_AS(7, 128, true) SID_AS(8, 128, true)
+      default: return hipErrorInvalidValue;
+    }
+  } else if (l <= 128) {
+    switch (kt) {
+      SID_AS(1, 128, false) SID_AS(2, 128, false) SID_AS(3, 128, false) SID_AS(4, 128, false)
+      SID_AS(5, 128, false) SID_AS(6, 128, false) SID_AS(7, 128, false) SID_AS(8, 128, false)
       default: return hipErrorInvalidValue;
     }
   } else {
     // l up to 192: six K steps; T's split takes up to 128 KB of LDS (one
     // workgroup per CU)
     switch (kt) {
-      SID_AS(1, 192) SID_AS(2, 192) SID_AS(3, 192) SID_AS(4, 192) SID_AS(5, 192) SID_AS(6, 192)
-      SID_AS(7, 192) SID_AS(8, 192) SID_AS(9, 192) SID_AS(10, 192)
+      SID_AS(1, 192, true) SID_AS(2, 192, true) SID_AS(3, 192, true) SID_AS(4, 192, true)
+      SID_AS(5, 192, true) SID_AS(6, 192, true) SID_AS(7, 192, true) SID_AS(8, 192, true)
+      SID_AS(9, 192, true) SID_AS(10, 192, true)
       default: return hipErrorInvalidValue;
     }
   }
 #undef SID_AS
+#undef SID_AS_LAUNCH
   return hipGetLastError();
 }
 

@@ -8,14 +8,15 @@ namespace sid {
 // One matrix of the batched sketch pass (device table, one entry per matrix
 // in queue order).  A: FP32 column-major N x n (lda); its shares are the row
 // ranges of rows_per_wg rows the single-matrix launch gives its workgroups;
-// share0: the queue index of its first share.  Outputs: part (nshares x lq
+// share0: the queue index of its first share in its layout class; cls: the
+// class (fused_bf16_batch_class).  Outputs: part (nshares x lq
 // x n FP32 partials), W (lq x n FP64, column-major), and with Y: omega (n x l
 // FP32 values, row-major), omT (128 x 512 bfloat16), Y (N x l FP32,
 // row-major).
 struct FbBatchEntry {
   const float* A;
   int64_t lda, N;
-  int n, lq, l, pad_;
+  int n, lq, l, cls;
   uint64_t seed;
   int64_t rows_per_wg, share0, nshares;
   float* part;
@@ -175,13 +176,32 @@ hipError_t launch_sketch_v2(hipStream_t st, int dmode, const float* A, int64_t l
                             bool y_add = false);
 int64_t fused_bf16_grid(int64_t N, int num_cu, int64_t* rows_per_wg);
 bool fused_bf16_batch_supported(int64_t n, int lq, int l, int64_t lda, const void* A);
-// the batched sketch pass over d_tab (count entries, nshares shares in all;
-// max_n / max_lqn: the largest n and lq n of the batch): Omega and Omega^T
-// (with Y), the persistent pass, the FP64 sums of the partials
-hipError_t launch_sketch_fused_bf16_batch(hipStream_t st, int dmode, bool want_y,
-                                          const FbBatchEntry* d_tab, int count, int64_t nshares,
-                                          int max_n, int64_t max_lqn, unsigned int* queue,
-                                          int num_cu);
+// Layout classes of the batched sketch pass (the register and LDS layout a
+// matrix's shares run with): 0: W row tiles MT = 10, Y column tiles LT = 8;
+// 1: MT = 10, LT = 4 (l <= 64); 2: MT = 4, LT = 4 (lq <= 64).  Without Y
+// every matrix takes class 0.  The layout bounds only the register state,
+// so every class gives the bits of the single-matrix pass.
+constexpr int FB_NCLASS = 3;
+int fused_bf16_batch_class(int lq, int l, bool want_y);
+// One class of the table: entries [first, first + count), whose shares are
+// numbered from 0 (share0 relative to the class), nshares in all.
+struct FbBatchClass {
+  int cls, first, count;
+  int64_t nshares;
+};
+// The batched sketch pass over d_tab (count entries grouped by class; queue:
+// FB_NCLASS counters): the setup (every Omega and Omega^T with Y, the
+// counters cleared), one persistent launch per class (the classes may run on
+// different streams once the setup is done), then the FP64 sums of every
+// matrix's partials (max_n / max_lqn: the largest n and lq n of the batch).
+hipError_t launch_sketch_batch_setup(hipStream_t st, int dmode, bool want_y,
+                                     const FbBatchEntry* d_tab, int count, int max_n,
+                                     unsigned int* queue);
+hipError_t launch_sketch_batch_class(hipStream_t st, int dmode, bool want_y,
+                                     const FbBatchEntry* d_tab, const FbBatchClass& k,
+                                     unsigned int* queue, int num_cu);
+hipError_t launch_reduce_partials_batch(hipStream_t st, const FbBatchEntry* d_tab, int count,
+                                        int64_t max_lqn);
 hipError_t launch_sketch_fused_bf16(hipStream_t st, int dmode, const float* A, int64_t lda,
                                     int64_t N, int n, int lq, int l, uint64_t seed,
                                     const float* omega, __bf16* omT, int num_cu, float* part,

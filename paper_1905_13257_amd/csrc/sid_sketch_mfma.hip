@@ -62,7 +62,7 @@ constexpr int FB_MTR = 8;                    // W row tiles kept in registers
 __device__ __forceinline__ __bf16 to_bf16(float f) { return (__bf16)f; }
 
 __global__ void k_zero_queue(unsigned int* q) {
-  if (threadIdx.x == 0) *q = 0u;
+  if (threadIdx.x < FB_NCLASS) q[threadIdx.x] = 0u;
 }
 
 // panel row of operand slot (ks, g, i)
@@ -459,14 +459,16 @@ __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16(
 // single-matrix launch gives its workgroups, so every partial, and with the
 // same fixed-order sum W and Y, is bit for bit that of a single-matrix call)
 // form one work queue, in the order of the table (the host puts the
-// matrices with the most work per share first).  A workgroup takes the next
-// share with one atomic increment and runs it with the largest register and
-// LDS layout (MT = 10, LT = 8, NCH = 4); a share of a smaller matrix skips
-// the chunks past its columns, and the row tiles of W and column tiles of Y
-// past its sizes only compute zeros that are never stored.  Every workgroup
-// leaves when the queue is empty.
+// matrices with the most work per share first), one queue per layout class:
+// the matrices whose W rows and Y columns fit a smaller register layout
+// (fused_bf16_batch_class) run in their own launch, beside the others on
+// another stream.  A workgroup takes the next share of its class with one
+// atomic increment and runs it with the class's layout (MT, LT) and NCH =
+// 4; a share of a smaller matrix skips the chunks past its columns, and the
+// row tiles of W and column tiles of Y past its sizes only compute zeros
+// that are never stored.  Every workgroup leaves when its queue is empty.
 // ---------------------------------------------------------------------------
-template <int DM, bool WANTY>
+template <int DM, bool WANTY, int MT, int LT>
 __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16_batch(
     const FbBatchEntry* __restrict__ tab, int count, int64_t nshares,
     unsigned int* __restrict__ queue) {
@@ -488,7 +490,7 @@ __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16_batch(
     const int64_t i = t - e.share0;
     const int64_t r0 = i * e.rows_per_wg;
     const int64_t r1 = r0 + e.rows_per_wg < e.N ? r0 + e.rows_per_wg : e.N;
-    fused_tile<DM, WANTY, 10, 8, FB_NCH, false, true>(e.A, e.lda, e.N, e.n, e.lq, e.l, e.seed, e.omT, r0,
+    fused_tile<DM, WANTY, MT, LT, FB_NCH, false, true>(e.A, e.lda, e.N, e.n, e.lq, e.l, e.seed, e.omT, r0,
                                                 r1, (e.n + FB_CHUNK - 1) / FB_CHUNK,
                                                 e.part + i * e.lq * e.n, WANTY ? e.Y : nullptr,
                                                 nullptr);
@@ -497,13 +499,13 @@ __global__ __launch_bounds__(FB_THREADS) void k_sketch_fused_bf16_batch(
 
 // Omega's values (n x l, row-major: the single-matrix layout) and Omega^T in
 // bfloat16 with 128 zero-padded rows (the batched kernel's Y tiles) for every
-// matrix (blockIdx.y); the queue counter is cleared by block (0, 0).  Both
+// matrix (blockIdx.y); the queue counters are cleared by block (0, 0).  Both
 // come from the same generator call, so they are the values the
 // single-matrix path forms.
 __global__ void k_batch_omega(const FbBatchEntry* __restrict__ tab, int dm_fp8,
                               unsigned int* __restrict__ queue) {
   const FbBatchEntry& e = tab[blockIdx.y];
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *queue = 0u;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < FB_NCLASS) queue[threadIdx.x] = 0u;
   const int ng = (e.l + 3) >> 2;
   for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < e.n * ng; w += gridDim.x * blockDim.x) {
     const int k = w / ng, g = w - k * ng;
@@ -549,10 +551,14 @@ bool fused_bf16_batch_supported(int64_t n, int lq, int l, int64_t lda, const voi
          ((uintptr_t)A % 16) == 0;
 }
 
-hipError_t launch_sketch_fused_bf16_batch(hipStream_t st, int dmode, bool want_y,
-                                          const FbBatchEntry* d_tab, int count, int64_t nshares,
-                                          int max_n, int64_t max_lqn, unsigned int* queue,
-                                          int num_cu) {
+int fused_bf16_batch_class(int lq, int l, bool want_y) {
+  if (!want_y) return 0;
+  return lq <= 64 ? 2 : l <= 64 ? 1 : 0;
+}
+
+hipError_t launch_sketch_batch_setup(hipStream_t st, int dmode, bool want_y,
+                                     const FbBatchEntry* d_tab, int count, int max_n,
+                                     unsigned int* queue) {
   if (count < 1) return hipSuccess;
   if (want_y) {
     const unsigned bx = (unsigned)((max_n * 32 + 255) / 256 < 64 ? (max_n * 32 + 255) / 256 : 64);
@@ -561,22 +567,41 @@ hipError_t launch_sketch_fused_bf16_batch(hipStream_t st, int dmode, bool want_y
   } else {
     hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(64), 0, st, queue);
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const int64_t g64 = nshares < num_cu ? nshares : num_cu;
-  const dim3 grid((unsigned)(g64 < 1 ? 1 : g64)), block(FB_THREADS);
-#define SID_FB_BATCH(DM_, WY_) \
-  hipLaunchKernelGGL((k_sketch_fused_bf16_batch<DM_, WY_>), grid, block, 0, st, d_tab, count, nshares, queue)
+  return hipGetLastError();
+}
+
+hipError_t launch_sketch_batch_class(hipStream_t st, int dmode, bool want_y,
+                                     const FbBatchEntry* d_tab, const FbBatchClass& k,
+                                     unsigned int* queue, int num_cu) {
+  if (k.count < 1 || k.nshares < 1) return hipSuccess;
+  if (k.cls < 0 || k.cls >= FB_NCLASS || (!want_y && k.cls != 0)) return hipErrorInvalidValue;
+  const int64_t g64 = k.nshares < num_cu ? k.nshares : num_cu;
+  const dim3 grid((unsigned)g64), block(FB_THREADS);
+  const FbBatchEntry* tab = d_tab + k.first;
+  unsigned int* q = queue + k.cls;
+#define SID_FB_BATCH(DM_, WY_, MT_, LT_)                                                       \
+  hipLaunchKernelGGL((k_sketch_fused_bf16_batch<DM_, WY_, MT_, LT_>), grid, block, 0, st, tab, \
+                     k.count, k.nshares, q)
+#define SID_FB_BATCH_Y(DM_)                            \
+  if (!want_y) SID_FB_BATCH(DM_, false, 10, 8);        \
+  else if (k.cls == 0) SID_FB_BATCH(DM_, true, 10, 8); \
+  else if (k.cls == 1) SID_FB_BATCH(DM_, true, 10, 4); \
+  else SID_FB_BATCH(DM_, true, 4, 4);
   if (dmode == FB_BF16X2) {
-    if (want_y) SID_FB_BATCH(FB_BF16X2, true); else SID_FB_BATCH(FB_BF16X2, false);
+    SID_FB_BATCH_Y(FB_BF16X2)
   } else if (dmode == FB_FP8) {
-    if (want_y) SID_FB_BATCH(FB_FP8, true); else SID_FB_BATCH(FB_FP8, false);
+    SID_FB_BATCH_Y(FB_FP8)
   } else {
-    if (want_y) SID_FB_BATCH(FB_BF16, true); else SID_FB_BATCH(FB_BF16, false);
+    SID_FB_BATCH_Y(FB_BF16)
   }
+#undef SID_FB_BATCH_Y
 #undef SID_FB_BATCH
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials_batch(hipStream_t st, const FbBatchEntry* d_tab, int count,
+                                        int64_t max_lqn) {
+  if (count < 1) return hipSuccess;
   int64_t bx = (max_lqn + 255) / 256;
   if (bx > 256) bx = 256;
   hipLaunchKernelGGL(k_reduce_partials_batch, dim3((unsigned)bx, (unsigned)count), dim3(256), 0, st,

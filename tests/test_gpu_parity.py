@@ -688,6 +688,35 @@ def test_pair_pass_y_over_column_slabs(sid, oracle_mod, prec):
     assert np.all(dAJ <= bound)
 
 
+@pytest.mark.parametrize("k,p", [(37, 10), (61, 6)])
+def test_apply_rows_not_16_byte_aligned(sid, oracle_mod, k, p):
+    """AJ = Y T on the bf16 matrix cores when l % 4 != 0 (Y's rows are not
+    16-byte aligned, so each lane reads its entries one by one): each entry
+    of AJ within 2^-15 of sum_t |Y(i, t)| |T(t, j)|, with T = M^+ W(0:lz, J)
+    formed from the GPU's W and Omega (ragged last row block)."""
+    N, n, q = 5000, 300, 6
+    l, lz = k + p, k + 2 * p
+    assert l % 4 != 0
+    A64, _ = c1_matrix(N=N, n=n, seed=1007)
+    A = to_gpu(A64.astype(np.float32).astype(np.float64), torch.float32)
+    say("unaligned apply", k, p)
+    W, Y = sid.sketch(A, k, p, seed=9, prec="bf16x2", probe_rows=q, want_y=True)
+    out = sid.compress(A, k, p, seed=9, mode="single_pass", prec="bf16x2", probe_rows=q,
+                       sp_rcond=1e-12)
+    torch.cuda.synchronize()
+    J = host(out.J)
+    Wg = host(W).astype(np.float64)
+    Yg = host(Y).astype(np.float64)
+    Om = oracle_mod.omega(9, n, l, "bf16x2")
+    M = Wg[:lz] @ Om
+    T = np.linalg.pinv(M, rcond=1e-12) @ Wg[:lz][:, J]
+    AJo = Yg @ T
+    bound = 2.0 ** -15 * (np.abs(Yg) @ np.abs(T)) + 1e-30
+    dAJ = np.abs(host(out.AJ).astype(np.float64) - AJo)
+    say("unaligned AJ max |dAJ| / bound", (dAJ / bound).max())
+    assert np.all(dAJ <= bound)
+
+
 def test_graph_capture_replay(sid, oracle_mod):
     """sid_reserve covers every allocation of a compress call; the call is
     then captured into a HIP graph and replayed several times, with eager
