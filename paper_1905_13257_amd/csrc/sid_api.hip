@@ -131,6 +131,11 @@ struct BatchPlan {
   sid::GatherBlockJob* d_gblock = nullptr;
   sid::Gemm64Job *d_gemm_c = nullptr, *d_gemm_mix = nullptr;
   sid::FitJob* d_fit = nullptr;
+  // AJ = Y T of every problem with an output in one launch: the device job
+  // table and the host copy it was last uploaded from (the outputs are the
+  // caller's and may change from call to call)
+  sid::ApplyJob* d_apply = nullptr;
+  std::vector<sid::ApplyJob> apply_host;
   int n_gemm_mix = 0, t_max_k = 0, t_max_n = 0, t_max_l = 0, t_max_gblock = 0, t_max_q = 0,
       t_max_qn = 0;
 };
@@ -1915,7 +1920,8 @@ sid_status batch_plan(sid_ctx* ctx, const sid_problem* probs, int64_t count,
     bytes += up(sizeof(sid::GatherR11Job) * (size_t)(2 * count)) +
              2 * up(sizeof(sid::TrsvJob) * (size_t)count) + up(sizeof(sid::RatioJob) * (size_t)count) +
              up(sizeof(sid::GatherBlockJob) * (size_t)count) +
-             2 * up(sizeof(sid::Gemm64Job) * (size_t)count) + up(sizeof(sid::FitJob) * (size_t)count);
+             2 * up(sizeof(sid::Gemm64Job) * (size_t)count) + up(sizeof(sid::FitJob) * (size_t)count) +
+             up(sizeof(sid::ApplyJob) * (size_t)count);
   for (int64_t b = 0; b < count; ++b) {
     const Shape& s = sh[(size_t)b];
     bytes += up(sizeof(float) * (size_t)(nsh[(size_t)b] * s.lq * s.n)) +
@@ -1968,6 +1974,7 @@ sid_status batch_plan(sid_ctx* ctx, const sid_problem* probs, int64_t count,
     pl->d_gemm_c = (sid::Gemm64Job*)take(sizeof(sid::Gemm64Job) * (size_t)count);
     pl->d_gemm_mix = (sid::Gemm64Job*)take(sizeof(sid::Gemm64Job) * (size_t)count);
     pl->d_fit = (sid::FitJob*)take(sizeof(sid::FitJob) * (size_t)count);
+    pl->d_apply = (sid::ApplyJob*)take(sizeof(sid::ApplyJob) * (size_t)count);
   }
   pl->W.assign((size_t)count, nullptr);
   pl->Y.assign((size_t)count, nullptr);
@@ -2251,9 +2258,45 @@ sid_status compress_batch(sid_ctx* ctx, const sid_problem* probs, int64_t count,
   sid_status result = SID_OK;
   const bool tail = any_pre && plan->tail;
   if (tail) {
-    // per problem: P from Pd in the caller's type and layout (the values the
-    // single call's solve writes), AJ = Y T, the result copies
+    // AJ = Y T of every problem with an output: one launch on the context's
+    // stream (the one-problem kernel's arithmetic, so the single call's
+    // bits); per problem on the child streams: P from Pd in the caller's
+    // type and layout (the values the single call's solve writes) and the
+    // result copies
     const bool f64 = dtype == SID_F64;
+    std::vector<sid::ApplyJob> aj;
+    int max_nwg = 0, kmax = 0;
+    for (int64_t b = 0; b < count; ++b) {
+      const sid_problem& q = probs[b];
+      const Shape& s = sh[(size_t)b];
+      if (!q.AJ || f64 || !sid::apply_t_bf16_runs_supported((int)s.k, (int)s.l)) continue;
+      sid::ApplyJob j{};
+      j.Y = plan->Y[(size_t)b];
+      j.T = plan->fac[(size_t)b].T;
+      j.AJ = (float*)q.AJ;
+      j.N = s.N;
+      j.ldaj = q.ldaj;
+      j.l = (int)s.l;
+      j.k = (int)s.k;
+      j.al = s.l % 4 == 0;
+      j.vec = q.ldaj % 4 == 0 && (uintptr_t)q.AJ % 16 == 0;
+      j.nwg = sid::apply_batch_workgroups(s.N, ctx->num_cu);
+      aj.push_back(j);
+      max_nwg = std::max(max_nwg, j.nwg);
+      kmax = std::max(kmax, (int)s.k);
+    }
+    if (!aj.empty()) {
+      if (aj.size() != plan->apply_host.size() ||
+          std::memcmp(aj.data(), plan->apply_host.data(), sizeof(sid::ApplyJob) * aj.size()) != 0) {
+        SID_CHECK(hipMemcpyAsync(plan->d_apply, aj.data(), sizeof(sid::ApplyJob) * aj.size(),
+                                 hipMemcpyHostToDevice, ctx->stream),
+                  "batched: AJ job table");
+        plan->apply_host = aj;
+      }
+      SID_CHECK(sid::launch_apply_t_bf16_runs_batch(ctx->stream, plan->d_apply, (int)aj.size(),
+                                                    max_nwg, kmax),
+                "batched: AJ = Y T");
+    }
     for (int64_t b = 0; b < count && result == SID_OK; ++b) {
       const sid_problem& q = probs[b];
       const Shape& s = sh[(size_t)b];
@@ -2261,7 +2304,8 @@ sid_status compress_batch(sid_ctx* ctx, const sid_problem* probs, int64_t count,
       hipStream_t cs = ctx->children[(size_t)(b % nstreams)]->stream;
       hipError_t he = hipSuccess;
       if (q.P) he = sid::launch_convert(cs, f.Pd, true, s.k, s.n, s.k, q.P, f64, q.ldp);
-      if (he == hipSuccess && q.AJ)
+      if (he == hipSuccess && q.AJ &&
+          (f64 || !sid::apply_t_bf16_runs_supported((int)s.k, (int)s.l)))
         result = apply_skeleton(ctx, cs, s, plan->Y[(size_t)b], f.T, q.AJ, q.ldaj, f64);
       if (he == hipSuccess && result == SID_OK)
         he = sid::launch_copy_results(cs, q.J, f.piv, (int)s.k, q.k_eff, f.keff, q.err, f.err);

@@ -46,19 +46,48 @@ __device__ __forceinline__ __bf16 to_bf16(float f) { return (__bf16)f; }
 
 // AL: l % 4 == 0, so Y's rows are 16-byte aligned and each lane's 8 entries
 // are two 16-byte loads; otherwise (l <= 128 only) eight 4-byte loads, the
-// entries past l zero.
-template <int KT, bool VEC, int LP, bool AL = true>
-__global__ __launch_bounds__(AS_THREADS) void k_apply_t_bf16_runs(
-    const float* __restrict__ Y, int64_t N, int l, const double* __restrict__ Tm /* l x k */,
-    int k, float* __restrict__ AJ, int64_t ldaj) {
+// entries past l zero.  VEC: AJ's columns are 16-byte aligned.
+//
+// The body serves one problem (the arguments) or, with a job table, job
+// blockIdx.y (the work of a one-problem launch, dealt over the job's first
+// nwg workgroups; AL and VEC per job).  KT only bounds the column tiles: a job
+// with fewer skeleton columns computes zero tiles that are never stored, so
+// every entry has the bits of the one-problem launch.
+template <int KT, bool VEC, int LP, bool AL, bool BATCH>
+__device__ __forceinline__ void apply_runs_body(const float* __restrict__ Y, int64_t N, int l,
+                                                const double* __restrict__ Tm, int k,
+                                                float* __restrict__ AJ, int64_t ldaj,
+                                                const ApplyJob* __restrict__ jobs) {
   constexpr int AS_LS = LP + 8;
   constexpr int NKS = LP / 32;
   __shared__ __attribute__((aligned(16))) __bf16 s_th[KT * 16 * AS_LS];
   __shared__ __attribute__((aligned(16))) __bf16 s_tl[KT * 16 * AS_LS];
   __shared__ __attribute__((aligned(16))) float s_o[16 * AS_OS];
+  // every access through a job's pointers is a global (not flat) access:
+  // flat accesses count in the LDS counter too, so waiting for an LDS read
+  // would wait for the prefetched rows
+  typedef const __attribute__((address_space(1))) double* gcd;
+  typedef const __attribute__((address_space(1))) float* gcf;
+  typedef __attribute__((address_space(1))) float* gf;
+  bool al = AL, vec = VEC;
+  int64_t nwg = gridDim.x;  // workgroups dealing the blocks
+  if constexpr (BATCH) {
+    const ApplyJob& jb = jobs[blockIdx.y];
+    nwg = jb.nwg;
+    if ((int64_t)blockIdx.x >= nwg) return;
+    Y = jb.Y;
+    N = jb.N;
+    l = jb.l;
+    Tm = jb.T;
+    k = jb.k;
+    AJ = jb.AJ;
+    ldaj = jb.ldaj;
+    al = jb.al != 0;
+    vec = jb.vec != 0;
+  }
   for (int e = threadIdx.x; e < KT * 16 * LP; e += AS_THREADS) {
     const int m = e / LP, c = e - m * LP;
-    const float x = (m < k && c < l) ? (float)Tm[c + (int64_t)l * m] : 0.0f;
+    const float x = (m < k && c < l) ? (float)((gcd)Tm)[c + (int64_t)l * m] : 0.0f;
     const __bf16 h = to_bf16(x);
     s_th[m * AS_LS + c] = h;
     s_tl[m * AS_LS + c] = to_bf16(x - (float)h);
@@ -84,19 +113,20 @@ __global__ __launch_bounds__(AS_THREADS) void k_apply_t_bf16_runs(
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const int c = 32 * ks + 8 * lg + 4 * h;
-          if constexpr (AL) {
+          if (al) {
             y[rt][ks][h] = (row < N && c + 4 <= l) ? *(gptr4)(Y + row * l + c)
                                                    : f32x4_t{0.f, 0.f, 0.f, 0.f};
           } else {
 #pragma unroll
-            for (int t = 0; t < 4; ++t) y[rt][ks][h][t] = (row < N && c + t < l) ? Y[row * l + c + t] : 0.f;
+            for (int t = 0; t < 4; ++t)
+              y[rt][ks][h][t] = (row < N && c + t < l) ? ((gcf)Y)[row * l + c + t] : 0.f;
           }
         }
     }
   };
   int64_t b = blockIdx.x;
   if (b < nblk) load_block(b);
-  for (; b < nblk; b += gridDim.x) {
+  for (; b < nblk; b += nwg) {
     const int64_t blk0 = b * AS_ROWS;
     bf16x8_t bh[AS_RT][NKS], bl[AS_RT][NKS];
 #pragma unroll
@@ -110,7 +140,7 @@ __global__ __launch_bounds__(AS_THREADS) void k_apply_t_bf16_runs(
           bh[rt][ks][i] = hv;
           bl[rt][ks][i] = to_bf16(x - (float)hv);
         }
-    if (b + gridDim.x < nblk) load_block(b + gridDim.x);
+    if (b + nwg < nblk) load_block(b + nwg);
     f32x4_t acc[AS_RT][KT];
 #pragma unroll
     for (int rt = 0; rt < AS_RT; ++rt)
@@ -135,6 +165,7 @@ __global__ __launch_bounds__(AS_THREADS) void k_apply_t_bf16_runs(
     const bool full = blk0 + AS_ROWS <= N;
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt) {
+      if (BATCH && kt * 16 >= k) break;  // uniform: the job's last column tile is done
       // C entry (rt, t) of this lane: column 4 lg + t of the group, row
       // 16 (AS_RT wave + rt) + lr of the block
 #pragma unroll
@@ -150,9 +181,9 @@ __global__ __launch_bounds__(AS_THREADS) void k_apply_t_bf16_runs(
         const int m = m0 < k ? m0 : k - 1;            // past k: column k - 1 again
         const int cl = m - kt * 16;
         const f32x4_t v = *reinterpret_cast<const f32x4_t*>(&s_o[cl * AS_OS + sr]);
-        float* dst = AJ + blk0 + sr + ldaj * (int64_t)m;
+        const gf dst = (gf)(AJ + blk0 + sr + ldaj * (int64_t)m);
         if (full) {
-          if constexpr (VEC) {
+          if (vec) {
             typedef __attribute__((address_space(1))) f32x4_t* optr4;
             __builtin_nontemporal_store(v, (optr4)dst);
           } else {
@@ -168,6 +199,20 @@ __global__ __launch_bounds__(AS_THREADS) void k_apply_t_bf16_runs(
       __syncthreads();
     }
   }
+}
+
+template <int KT, bool VEC, int LP, bool AL = true>
+__global__ __launch_bounds__(AS_THREADS) void k_apply_t_bf16_runs(
+    const float* __restrict__ Y, int64_t N, int l, const double* __restrict__ Tm /* l x k */,
+    int k, float* __restrict__ AJ, int64_t ldaj) {
+  apply_runs_body<KT, VEC, LP, AL, false>(Y, N, l, Tm, k, AJ, ldaj, nullptr);
+}
+
+// every job's AJ = Y T in one launch: job blockIdx.y (l <= 128, k <= 16 KT)
+template <int KT>
+__global__ __launch_bounds__(AS_THREADS) void k_apply_t_bf16_runs_batch(
+    const ApplyJob* __restrict__ jobs) {
+  apply_runs_body<KT, true, 128, true, true>(nullptr, 0, 0, nullptr, 0, nullptr, 0, jobs);
 }
 
 }  // namespace
@@ -219,6 +264,32 @@ hipError_t launch_apply_t_bf16_runs(hipStream_t st, const float* Y, int64_t N, i
   }
 #undef SID_AS
 #undef SID_AS_LAUNCH
+  return hipGetLastError();
+}
+
+int apply_batch_workgroups(int64_t N, int num_cu) {
+  // at least APPLY_MIN_BLOCKS blocks per workgroup, so that staging T is
+  // spread over them; at most the one-problem launch's grid
+  const int64_t nblk = (N + AS_ROWS - 1) / AS_ROWS;
+  int64_t g = (nblk + APPLY_MIN_BLOCKS - 1) / APPLY_MIN_BLOCKS;
+  if (g > (int64_t)num_cu * 4) g = (int64_t)num_cu * 4;
+  return (int)(g < 1 ? 1 : g);
+}
+
+hipError_t launch_apply_t_bf16_runs_batch(hipStream_t st, const ApplyJob* jobs, int njobs,
+                                          int max_nwg, int kmax) {
+  if (njobs < 1 || max_nwg < 1) return hipSuccess;
+  if (kmax < 1 || kmax > 128) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)max_nwg, (unsigned)njobs), block(AS_THREADS);
+#define SID_ASB(KT_)                                                                  \
+  case KT_:                                                                           \
+    hipLaunchKernelGGL((k_apply_t_bf16_runs_batch<KT_>), grid, block, 0, st, jobs);   \
+    break;
+  switch ((kmax + 15) / 16) {
+    SID_ASB(1) SID_ASB(2) SID_ASB(3) SID_ASB(4) SID_ASB(5) SID_ASB(6) SID_ASB(7) SID_ASB(8)
+    default: return hipErrorInvalidValue;
+  }
+#undef SID_ASB
   return hipGetLastError();
 }
 

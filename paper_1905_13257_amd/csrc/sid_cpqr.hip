@@ -279,25 +279,32 @@ constexpr int CW_MMAX = 256;
 #define SID_CPQR_TAKE_JOB()                                                       \
   if (jobs) {                                                                     \
     const CpqrJob jb = jobs[blockIdx.x];                                          \
-    X = jb.X;                                                                     \
+    X_ = jb.X;                                                                    \
     ldx = jb.ldx;                                                                 \
     m = jb.m;                                                                     \
     nc = jb.nc;                                                                   \
     kmax = jb.kmax;                                                               \
     rank_tol = jb.rank_tol;                                                       \
-    piv = jb.piv;                                                                 \
-    R = jb.R;                                                                     \
-    Q = jb.Q;                                                                     \
-    keff = jb.keff;                                                               \
-    stats = jb.stats;                                                             \
-    forced = nullptr;                                                             \
-  }
+    piv_ = jb.piv;                                                                \
+    R_ = jb.R;                                                                    \
+    Q_ = jb.Q;                                                                    \
+    keff_ = jb.keff;                                                              \
+    stats_ = jb.stats;                                                            \
+    forced_ = nullptr;                                                            \
+  }                                                                               \
+  const auto X = to_global(X_);                                                   \
+  const auto piv = to_global(piv_);                                               \
+  const auto R = to_global(R_);                                                   \
+  const auto Q = to_global(Q_);                                                   \
+  const auto keff = to_global(keff_);                                             \
+  const auto stats = to_global(stats_);                                           \
+  const auto forced = to_global(forced_);
 
 template <int TPC, int RPT>
 __global__ __launch_bounds__(CW_THREADS) void k_cpqr_wg(
-    const double* __restrict__ X, int64_t ldx, int m, int nc, int kmax, double rank_tol,
-    int64_t* __restrict__ piv, double* __restrict__ R, double* __restrict__ Q,
-    int64_t* __restrict__ keff, double* __restrict__ stats, const int64_t* __restrict__ forced,
+    const double* __restrict__ X_, int64_t ldx, int m, int nc, int kmax, double rank_tol,
+    int64_t* __restrict__ piv_, double* __restrict__ R_, double* __restrict__ Q_,
+    int64_t* __restrict__ keff_, double* __restrict__ stats_, const int64_t* __restrict__ forced_,
     const CpqrJob* __restrict__ jobs) {
   SID_CPQR_TAKE_JOB()
   constexpr int QN = TPC * RPT;  // rows covered by a column's threads
@@ -475,9 +482,9 @@ constexpr int CL_RL = 38;  // rows per thread in LDS: 38 x 8 B x 512 = 152 KiB
 
 template <int RR>
 __global__ __launch_bounds__(CL_THREADS) void k_cpqr_wgl(
-    const double* __restrict__ X, int64_t ldx, int m, int nc, int kmax, double rank_tol,
-    int64_t* __restrict__ piv, double* __restrict__ R, double* __restrict__ Q,
-    int64_t* __restrict__ keff, double* __restrict__ stats, const int64_t* __restrict__ forced,
+    const double* __restrict__ X_, int64_t ldx, int m, int nc, int kmax, double rank_tol,
+    int64_t* __restrict__ piv_, double* __restrict__ R_, double* __restrict__ Q_,
+    int64_t* __restrict__ keff_, double* __restrict__ stats_, const int64_t* __restrict__ forced_,
     const CpqrJob* __restrict__ jobs) {
   SID_CPQR_TAKE_JOB()
   constexpr int QN = RR + CL_RL;  // rows covered
@@ -760,19 +767,23 @@ hipError_t launch_cpqr_coop(hipStream_t st, const double* X, int64_t ldx, int m,
 // R11 (r x r, row-major ld r, r = *keff) gathered from the pivoted columns of
 // mgsqr's R: R11(a, b) = R(a, piv[b]).
 // ---------------------------------------------------------------------------
-__global__ void k_gather_r11(const double* __restrict__ R, int64_t ldr /* = nc */,
-                             const int64_t* __restrict__ piv, const int64_t* __restrict__ keff_p,
-                             int kcap, double* __restrict__ R11,
+__global__ void k_gather_r11(const double* __restrict__ R_, int64_t ldr /* = nc */,
+                             const int64_t* __restrict__ piv_, const int64_t* __restrict__ keff_,
+                             int kcap, double* __restrict__ R11_,
                              const GatherR11Job* __restrict__ jobs) {
   if (jobs) {  // a batched launch: job blockIdx.y
     const GatherR11Job jb = jobs[blockIdx.y];
-    R = jb.R;
+    R_ = jb.R;
     ldr = jb.ldr;
-    piv = jb.piv;
-    keff_p = jb.keff;
+    piv_ = jb.piv;
+    keff_ = jb.keff;
     kcap = jb.kcap;
-    R11 = jb.R11;
+    R11_ = jb.R11;
   }
+  const auto R = to_global(R_);
+  const auto piv = to_global(piv_);
+  const auto keff_p = to_global(keff_);
+  const auto R11 = to_global(R11_);
   const int keff = (int)*keff_p;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < kcap * kcap; e += gridDim.x * blockDim.x) {
     const int a = e / kcap, b = e - a * kcap;
@@ -809,14 +820,14 @@ __global__ __launch_bounds__(64) void k_trsv_multi(
     }
   }
   if (MODE == 0) {
-    double* x = out64 + ldo64 * j;
+    const auto x = out64 + ldo64 * j;
     for (int a = 0; a < kcap; ++a) {
       const double v = (pos >= 0) ? (a == pos ? 1.0 : 0.0) : (a < keff ? s_x[a * 64 + t] : 0.0);
       x[a] = v;
       if (out) out[a + ldo * j] = (OutT)v;
     }
   } else {
-    double* x = out64 + ldo64 * j;
+    const auto x = out64 + ldo64 * j;
     for (int a = 0; a < kcap; ++a) x[a] = 0.0;
     for (int a = 0; a < keff; ++a) x[piv[a]] = s_x[a * 64 + t];
   }
@@ -838,23 +849,29 @@ __host__ __device__ constexpr int trsv_wave_rt(int nv, int kcap) {
 
 template <typename OutT, int MODE, int NV = 2>
 __global__ __launch_bounds__(64 * TW_WAVES) void k_trsv_wave(
-    const double* __restrict__ R11, int kcap, const int64_t* __restrict__ keff_p,
-    const int64_t* __restrict__ piv, const double* __restrict__ rhs, int64_t ldrhs, int ncols,
-    double* __restrict__ out64, int64_t ldo64, OutT* __restrict__ out, int64_t ldo,
+    const double* __restrict__ R11_, int kcap, const int64_t* __restrict__ keff_,
+    const int64_t* __restrict__ piv_, const double* __restrict__ rhs_, int64_t ldrhs, int ncols,
+    double* __restrict__ out64_, int64_t ldo64, OutT* __restrict__ out_, int64_t ldo,
     const TrsvJob* __restrict__ jobs) {
   if (jobs) {  // a batched launch: job blockIdx.y, out64 only
     const TrsvJob jb = jobs[blockIdx.y];
-    R11 = jb.R11;
+    R11_ = jb.R11;
     kcap = jb.kcap;
-    keff_p = jb.keff;
-    piv = jb.piv;
-    rhs = jb.rhs;
+    keff_ = jb.keff;
+    piv_ = jb.piv;
+    rhs_ = jb.rhs;
     ldrhs = jb.ldrhs;
     ncols = jb.ncols;
-    out64 = jb.out64;
+    out64_ = jb.out64;
     ldo64 = jb.ldo64;
-    out = nullptr;
+    out_ = nullptr;
   }
+  const auto R11 = to_global(R11_);
+  const auto keff_p = to_global(keff_);
+  const auto piv = to_global(piv_);
+  const auto rhs = to_global(rhs_);
+  const auto out64 = to_global(out64_);
+  const auto out = to_global(out_);
   extern __shared__ double s_tw[];
   double* s_rt = s_tw;                              // R11 transposed (see above; padded)
   double* s_dinv = s_rt + trsv_wave_rt(NV, kcap);   // 1 / R11(a, a)
@@ -920,7 +937,7 @@ __global__ __launch_bounds__(64 * TW_WAVES) void k_trsv_wave(
     }
   }
   if (MODE == 0) {
-    double* x = out64 + ldo64 * j;
+    const auto x = out64 + ldo64 * j;
 #pragma unroll
     for (int h = 0; h < NV; ++h) {
       const int a = h == 0 ? b0 : h == 1 ? b1 : b2;
@@ -936,7 +953,7 @@ __global__ __launch_bounds__(64 * TW_WAVES) void k_trsv_wave(
     if (NV == 3 && b2 < keff) s_x[w * kcap + b2] = v2;
     __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): this wave's LDS writes done
     __builtin_amdgcn_wave_barrier();
-    double* x = out64 + ldo64 * j;
+    const auto x = out64 + ldo64 * j;
     for (int r = lane; r < kcap; r += 64) {
       const int a = s_inv[r];
       x[r] = a >= 0 ? s_x[w * kcap + a] : 0.0;

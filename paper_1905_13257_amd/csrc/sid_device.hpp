@@ -14,6 +14,17 @@
 
 namespace sid {
 
+// A pointer as a global-memory pointer.  Kernel arguments are known to be
+// global; a pointer read from a device job table (or a value merged from
+// both) is not, and accesses through it become flat instructions, which
+// count in the LDS counter as well as the vector-memory counter, so that
+// every wait for an LDS access would also wait for them.  Kernels that take
+// job tables access memory through these.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* to_global(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10
 // ---------------------------------------------------------------------------

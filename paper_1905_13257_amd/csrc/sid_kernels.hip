@@ -336,25 +336,31 @@ __global__ void k_backsolve(const double* __restrict__ R, const int64_t* __restr
 // Single block; result to *out.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_fit_residual_part(
-    const double* __restrict__ W, int lq, int r0, int q, int nc,
-    const int64_t* __restrict__ piv, const int64_t* __restrict__ keff_p,
-    const double* __restrict__ Pd, int kcap, const double* __restrict__ mix,
-    double* __restrict__ part /* 2 x (q nc + 255) / 256 */, const FitJob* __restrict__ jobs) {
+    const double* __restrict__ W_, int lq, int r0, int q, int nc,
+    const int64_t* __restrict__ piv_, const int64_t* __restrict__ keff_,
+    const double* __restrict__ Pd_, int kcap, const double* __restrict__ mix_,
+    double* __restrict__ part_ /* 2 x (q nc + 255) / 256 */, const FitJob* __restrict__ jobs) {
   if (jobs) {  // a batched launch: job blockIdx.y, its first (q nc + 255) / 256 blocks
     const FitJob jb = jobs[blockIdx.y];
     if ((int)blockIdx.x * 256 >= jb.q * jb.nc) return;
-    W = jb.W;
+    W_ = jb.W;
     lq = jb.lq;
     r0 = jb.r0;
     q = jb.q;
     nc = jb.nc;
-    piv = jb.piv;
-    keff_p = jb.keff;
-    Pd = jb.Pd;
+    piv_ = jb.piv;
+    keff_ = jb.keff;
+    Pd_ = jb.Pd;
     kcap = jb.kcap;
-    mix = jb.mix;
-    part = jb.part;
+    mix_ = jb.mix;
+    part_ = jb.part;
   }
+  const auto W = to_global(W_);
+  const auto piv = to_global(piv_);
+  const auto keff_p = to_global(keff_);
+  const auto Pd = to_global(Pd_);
+  const auto mix = to_global(mix_);
+  const auto part = to_global(part_);
   __shared__ double s_num[4], s_den[4];
   const int keff = (int)*keff_p;
   double num = 0.0, den = 0.0;
@@ -362,7 +368,7 @@ __global__ __launch_bounds__(256) void k_fit_residual_part(
   if (e < q * nc) {
     const int j = e / q, r = r0 + (e - j * q);
     const double w = W[r + (int64_t)lq * j];
-    const double* pj = Pd + (int64_t)kcap * j;
+    const auto pj = Pd + (int64_t)kcap * j;
     double a0 = 0.0, a1 = 0.0;
     int t = 0;
     for (; t + 1 < keff; t += 2) {
@@ -435,10 +441,12 @@ __global__ void k_ratio_sqrt(const double* __restrict__ stats, double* __restric
 // ---------------------------------------------------------------------------
 // one 16 x 16 tile (bx, by) of C = alpha op(A) op(B) + beta C
 __device__ __forceinline__ void gemm64_tile(int bx, int by, int M, int Nn, int K,
-                                            const double* __restrict__ A, int64_t lda, int tA,
-                                            const double* __restrict__ B, int64_t ldb, int tB,
-                                            double* __restrict__ C, int64_t ldc, double alpha,
-                                            double beta) {
+                                            const __attribute__((address_space(1))) double* __restrict__ A,
+                                            int64_t lda, int tA,
+                                            const __attribute__((address_space(1))) double* __restrict__ B,
+                                            int64_t ldb, int tB,
+                                            __attribute__((address_space(1))) double* __restrict__ C,
+                                            int64_t ldc, double alpha, double beta) {
   __shared__ double sa[16][17], sb[16][17];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int row = bx * 16 + tx;
@@ -463,7 +471,7 @@ __device__ __forceinline__ void gemm64_tile(int bx, int by, int M, int Nn, int K
     __syncthreads();
   }
   if (row < M && col < Nn) {
-    double* o = C + row + ldc * col;
+    __attribute__((address_space(1))) double* o = C + row + ldc * col;
     *o = beta != 0.0 ? fma(alpha, acc, beta * *o) : (alpha == 1.0 ? acc : alpha * acc);
   }
 }
@@ -471,7 +479,8 @@ __device__ __forceinline__ void gemm64_tile(int bx, int by, int M, int Nn, int K
 __global__ void k_gemm64(int M, int Nn, int K, const double* __restrict__ A, int64_t lda, int tA,
                          const double* __restrict__ B, int64_t ldb, int tB, double* __restrict__ C,
                          int64_t ldc, double alpha, double beta) {
-  gemm64_tile(blockIdx.x, blockIdx.y, M, Nn, K, A, lda, tA, B, ldb, tB, C, ldc, alpha, beta);
+  gemm64_tile(blockIdx.x, blockIdx.y, M, Nn, K, to_global(A), lda, tA, to_global(B), ldb, tB,
+              to_global(C), ldc, alpha, beta);
 }
 
 // many products in one launch: job blockIdx.z, its tiles (bx, by) (blocks
@@ -479,8 +488,8 @@ __global__ void k_gemm64(int M, int Nn, int K, const double* __restrict__ A, int
 __global__ void k_gemm64_batch(const Gemm64Job* __restrict__ jobs) {
   const Gemm64Job jb = jobs[blockIdx.z];
   if ((int)blockIdx.x * 16 >= jb.M || (int)blockIdx.y * 16 >= jb.Nn) return;
-  gemm64_tile(blockIdx.x, blockIdx.y, jb.M, jb.Nn, jb.K, jb.A, jb.lda, jb.tA, jb.B, jb.ldb, jb.tB,
-              jb.C, jb.ldc, jb.alpha, jb.beta);
+  gemm64_tile(blockIdx.x, blockIdx.y, jb.M, jb.Nn, jb.K, to_global(jb.A), jb.lda, jb.tA,
+              to_global(jb.B), jb.ldb, jb.tB, to_global(jb.C), jb.ldc, jb.alpha, jb.beta);
 }
 
 // gather columns: dst(:, t) = src(:, piv[t]) for t < keff, zero for keff <= t < kcap

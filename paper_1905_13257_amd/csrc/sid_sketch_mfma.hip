@@ -399,7 +399,10 @@ __device__ __forceinline__ void fused_tile(
       // the panel loop
       int lg4 = 4 * lg;
       asm volatile("" : "+v"(lg4));
-      float* yp = Y + p0 * (int64_t)l;
+      // global (not flat) stores: the batched kernel's pointers come from
+      // its table, and flat stores would also count in the LDS counter
+      typedef __attribute__((address_space(1))) float* gfp;
+      const gfp yp = (gfp)(Y + p0 * (int64_t)l);
       const int c = yc * 16 + lr;
 #pragma unroll
       for (int r = 0; r < YR; ++r) {
@@ -435,7 +438,7 @@ __device__ __forceinline__ void fused_tile(
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int m = mt * 16 + 4 * lg + t;
-        if (m < lq) dst[m + (int64_t)lq * col] = w4[t];
+        if (m < lq) ((__attribute__((address_space(1))) float*)dst)[m + (int64_t)lq * col] = w4[t];
       }
     }
   }
@@ -533,7 +536,10 @@ __global__ void k_reduce_partials_batch(const FbBatchEntry* __restrict__ tab) {
   const FbBatchEntry& m = tab[blockIdx.y];
   const int64_t count = (int64_t)m.lq * m.n;
   const int64_t nparts = m.nshares;
-  const float* __restrict__ part = m.part;
+  // global (not flat) accesses through the table's pointers
+  const __attribute__((address_space(1))) float* __restrict__ part =
+      (const __attribute__((address_space(1))) float*)m.part;
+  __attribute__((address_space(1))) double* Wm = (__attribute__((address_space(1))) double*)m.W;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
        e += (int64_t)gridDim.x * blockDim.x) {
     double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -542,7 +548,7 @@ __global__ void k_reduce_partials_batch(const FbBatchEntry* __restrict__ tab) {
 #pragma unroll
       for (int u = 0; u < 8; ++u) s[u] += (double)part[(g + u) * count + e];
     for (; g < nparts; ++g) s[0] += (double)part[g * count + e];
-    m.W[e] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+    Wm[e] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
   }
 }
 
@@ -1165,7 +1171,9 @@ constexpr int AB_LPAD = 128;               // l <= 128: four K steps of 32
 constexpr int AB_LS = AB_LPAD + 8;         // LDS row stride (bf16)
 constexpr int AB_ROWS = 4 * 32;            // rows per block
 
-template <int KT, typename OutT>
+// AL: l % 4 == 0 (16-byte aligned rows of Y: two 16-byte loads per lane
+// and K step); otherwise eight 4-byte loads, the entries past l zero
+template <int KT, typename OutT, bool AL = true>
 __global__ __launch_bounds__(AB_THREADS) void k_apply_t_bf16(
     const float* __restrict__ Y, int64_t N, int l, const double* __restrict__ Tm /* l x k */,
     int k, OutT* __restrict__ AJ, int64_t ldaj) {
@@ -1198,8 +1206,13 @@ __global__ __launch_bounds__(AB_THREADS) void k_apply_t_bf16(
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const int c = 32 * ks + 8 * lg + 4 * h;
-          y[rt][ks][h] = (row < N && c + 4 <= l) ? *(gptr4)(Y + row * l + c)
-                                                 : f32x4_t{0.f, 0.f, 0.f, 0.f};
+          if constexpr (AL) {
+            y[rt][ks][h] = (row < N && c + 4 <= l) ? *(gptr4)(Y + row * l + c)
+                                                   : f32x4_t{0.f, 0.f, 0.f, 0.f};
+          } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) y[rt][ks][h][t] = (row < N && c + t < l) ? Y[row * l + c + t] : 0.f;
+          }
         }
     }
   };
@@ -1257,7 +1270,7 @@ __global__ __launch_bounds__(AB_THREADS) void k_apply_t_bf16(
 }
 
 bool apply_t_bf16_supported(int k, int l) {
-  return k >= 1 && k <= 128 && l >= 1 && l <= AB_LPAD && (l % 4) == 0;
+  return k >= 1 && k <= 128 && l >= 1 && l <= AB_LPAD;
 }
 
 hipError_t launch_apply_t_bf16(hipStream_t st, const float* Y, int64_t N, int l, const double* Tm,
@@ -1267,15 +1280,20 @@ hipError_t launch_apply_t_bf16(hipStream_t st, const float* Y, int64_t N, int l,
   int64_t g = (int64_t)num_cu * 4;
   if (g > nblk) g = nblk;
   const dim3 grid((unsigned)g), block(AB_THREADS);
-#define SID_AB(KT_)                                                                           \
-  if (aj_f64) hipLaunchKernelGGL((k_apply_t_bf16<KT_, double>), grid, block, 0, st, Y, N, l, \
-                                 Tm, k, (double*)AJ, ldaj);                                   \
-  else hipLaunchKernelGGL((k_apply_t_bf16<KT_, float>), grid, block, 0, st, Y, N, l, Tm, k,   \
+  const bool al = (l % 4) == 0;
+#define SID_AB2(KT_, AL_)                                                                          \
+  if (aj_f64) hipLaunchKernelGGL((k_apply_t_bf16<KT_, double, AL_>), grid, block, 0, st, Y, N, l, \
+                                 Tm, k, (double*)AJ, ldaj);                                        \
+  else hipLaunchKernelGGL((k_apply_t_bf16<KT_, float, AL_>), grid, block, 0, st, Y, N, l, Tm, k,   \
                           (float*)AJ, ldaj);
+#define SID_AB(KT_)              \
+  if (al) { SID_AB2(KT_, true) } \
+  else { SID_AB2(KT_, false) }
   if (k <= 32) { SID_AB(2) }
   else if (k <= 64) { SID_AB(4) }
   else { SID_AB(8) }
 #undef SID_AB
+#undef SID_AB2
   return hipGetLastError();
 }
 
