@@ -2044,9 +2044,9 @@ sid_status batch_plan(sid_ctx* ctx, const sid_problem* probs, int64_t count,
     f.keff = (int64_t*)take(i8);
     f.stats = (double*)take(2 * d);
     const bool wl = mgsqr_kind((int)s.l, (int)s.n) == 3;
-    jobs.push_back({sid::cpqr_batch_instance((int)s.l, (int)s.n, wl),
-                    sid::CpqrJob{pl->W[(size_t)b], s.lq, (int)s.l, (int)s.n, (int)s.k, 0,
-                                 g.rank_tol, f.piv, f.R, f.Q, f.keff, f.stats}});
+    const int wi = sid::cpqr_batch_instance((int)s.l, (int)s.n, wl);
+    jobs.push_back({wi, sid::CpqrJob{pl->W[(size_t)b], s.lq, (int)s.l, (int)s.n, (int)s.k, wi,
+                                     g.rank_tol, f.piv, f.R, f.Q, f.keff, f.stats}});
     if (wanty) {
       f.om64 = (double*)take(d * (size_t)(s.n * s.l));
       f.M = (double*)take(d * (size_t)(s.lz * s.l));
@@ -2057,9 +2057,9 @@ sid_status batch_plan(sid_ctx* ctx, const sid_problem* probs, int64_t count,
       f.rkM = (int64_t*)take(i8);
       f.statsM = (double*)take(2 * d);
       const bool ml = mgsqr_kind((int)s.lz, (int)s.l) == 3;
-      jobs.push_back({sid::cpqr_batch_instance((int)s.lz, (int)s.l, ml),
-                      sid::CpqrJob{f.M, s.lz, (int)s.lz, (int)s.l, (int)s.l, 0, g.rcond, f.pivM,
-                                   f.RM, f.QM, f.rkM, f.statsM}});
+      const int mi = sid::cpqr_batch_instance((int)s.lz, (int)s.l, ml);
+      jobs.push_back({mi, sid::CpqrJob{f.M, s.lz, (int)s.lz, (int)s.l, (int)s.l, mi, g.rcond,
+                                       f.pivM, f.RM, f.QM, f.rkM, f.statsM}});
       // Omega's values, M = W(0:lz, :) Omega and Mpr = W_pr Omega, the
       // launches of the single call's step 5a
       omj.push_back(sid::OmegaJob{pl->omega[(size_t)b], s.n * s.l, f.om64});
@@ -2114,10 +2114,13 @@ sid_status batch_plan(sid_ctx* ctx, const sid_problem* probs, int64_t count,
                    [](const std::pair<int, sid::CpqrJob>& x, const std::pair<int, sid::CpqrJob>& y) {
                      return x.first < y.first;
                    });
+  // one group per LDS-kernel instance (those come first), then every
+  // register-kernel job in one group of its own launch
   std::vector<sid::CpqrJob> jtab;
   for (size_t i = 0; i < jobs.size(); ++i) {
-    if (i == 0 || jobs[i].first != jobs[i - 1].first)
-      pl->job_groups.push_back({jobs[i].first, (int)i, 0});
+    const int gi = jobs[i].first > 0 ? sid::CPQR_BATCH_ANY_WG : jobs[i].first;
+    if (pl->job_groups.empty() || pl->job_groups.back()[0] != gi)
+      pl->job_groups.push_back({gi, (int)i, 0});
     ++pl->job_groups.back()[2];
     jtab.push_back(jobs[i].second);
   }
@@ -2199,8 +2202,8 @@ sid_status compress_batch(sid_ctx* ctx, const sid_problem* probs, int64_t count,
   for (int c = 0; c < nstreams; ++c)
     SID_CHECK(hipStreamWaitEvent(ctx->children[c]->stream, ctx->fork, 0), "batched: fork wait");
   // The mgsqr runs of all problems whose shapes the one-workgroup kernels
-  // take go into a few launches (one per kernel instance, on the child
-  // streams side by side), after the small products they need (single pass:
+  // take go into a few launches (one for all register-kernel jobs, one per
+  // LDS-kernel instance, side by side), after the small products they need (single pass:
   // Omega's FP64 values, M and Mpr, two launches for the whole batch); every
   // job gets the bits of the single call.
   bool any_pre = false;
@@ -2213,16 +2216,18 @@ sid_status compress_batch(sid_ctx* ctx, const sid_problem* probs, int64_t count,
     SID_CHECK(sid::launch_gemm64_batch(ctx->stream, plan->d_mm_jobs, plan->n_mm_jobs,
                                        plan->mm_max_m, plan->mm_max_n),
               "batched: M = W Omega, Mpr");
-    // one kernel instance per child stream, side by side
+    // the groups side by side: the first on the context's stream, the
+    // others on the child streams
     SID_CHECK(hipEventRecord(ctx->fork, ctx->stream), "batched: fork event");
     const int ng = (int)plan->job_groups.size();
     for (int i = 0; i < ng; ++i) {
       const auto& g = plan->job_groups[(size_t)i];
-      hipStream_t cs = ctx->children[(size_t)(i % nstreams)]->stream;
-      if (i < nstreams) SID_CHECK(hipStreamWaitEvent(cs, ctx->fork, 0), "batched: fork wait");
+      hipStream_t cs = i == 0 ? ctx->stream : ctx->children[(size_t)((i - 1) % nstreams)]->stream;
+      if (i > 0 && i - 1 < nstreams)
+        SID_CHECK(hipStreamWaitEvent(cs, ctx->fork, 0), "batched: fork wait");
       SID_CHECK(sid::launch_cpqr_batch(cs, g[0], plan->d_jobs + g[1], g[2]), "batched: pivoted QR");
     }
-    for (int c = 0; c < nstreams && c < ng; ++c) {
+    for (int c = 0; c < nstreams && c < ng - 1; ++c) {
       SID_CHECK(hipEventRecord(ctx->child_done[c], ctx->children[c]->stream), "batched: join event");
       SID_CHECK(hipStreamWaitEvent(ctx->stream, ctx->child_done[c], 0), "batched: join wait");
     }

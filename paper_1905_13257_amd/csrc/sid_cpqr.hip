@@ -301,7 +301,7 @@ constexpr int CW_MMAX = 256;
   const auto forced = to_global(forced_);
 
 template <int TPC, int RPT>
-__global__ __launch_bounds__(CW_THREADS) void k_cpqr_wg(
+__device__ __forceinline__ void cpqr_wg_body(
     const double* __restrict__ X_, int64_t ldx, int m, int nc, int kmax, double rank_tol,
     int64_t* __restrict__ piv_, double* __restrict__ R_, double* __restrict__ Q_,
     int64_t* __restrict__ keff_, double* __restrict__ stats_, const int64_t* __restrict__ forced_,
@@ -431,6 +431,46 @@ __global__ __launch_bounds__(CW_THREADS) void k_cpqr_wg(
     *keff = k;
   }
   for (int i = k + tid; i < kmax; i += CW_THREADS) piv[i] = -1;
+}
+
+template <int TPC, int RPT>
+__global__ __launch_bounds__(CW_THREADS) void k_cpqr_wg(
+    const double* __restrict__ X_, int64_t ldx, int m, int nc, int kmax, double rank_tol,
+    int64_t* __restrict__ piv_, double* __restrict__ R_, double* __restrict__ Q_,
+    int64_t* __restrict__ keff_, double* __restrict__ stats_, const int64_t* __restrict__ forced_,
+    const CpqrJob* __restrict__ jobs) {
+  cpqr_wg_body<TPC, RPT>(X_, ldx, m, nc, kmax, rank_tol, piv_, R_, Q_, keff_, stats_, forced_,
+                         jobs);
+}
+
+// Every job of a batch that the register kernel takes, whatever its
+// instance, in one launch: workgroup b runs job b with the instance in
+// jobs[b].inst (the arithmetic, and so the bits, of its own launch).  One
+// launch keeps the jobs side by side: launches of separate instances on
+// separate streams share the few hardware queues and partly serialize.
+__global__ __launch_bounds__(CW_THREADS) void k_cpqr_wg_any(const CpqrJob* __restrict__ jobs) {
+  const int inst = jobs[blockIdx.x].inst;
+#define SID_CWA(TI_, TPC_)                                                                    \
+  case 8 * TI_ + 1: cpqr_wg_body<TPC_, 8>(nullptr, 0, 0, 0, 0, 0.0, nullptr, nullptr, nullptr, \
+                                          nullptr, nullptr, nullptr, jobs); break;             \
+  case 8 * TI_ + 2: cpqr_wg_body<TPC_, 16>(nullptr, 0, 0, 0, 0, 0.0, nullptr, nullptr, nullptr, \
+                                           nullptr, nullptr, nullptr, jobs); break;            \
+  case 8 * TI_ + 3: cpqr_wg_body<TPC_, 24>(nullptr, 0, 0, 0, 0, 0.0, nullptr, nullptr, nullptr, \
+                                           nullptr, nullptr, nullptr, jobs); break;            \
+  case 8 * TI_ + 4: cpqr_wg_body<TPC_, 32>(nullptr, 0, 0, 0, 0, 0.0, nullptr, nullptr, nullptr, \
+                                           nullptr, nullptr, nullptr, jobs); break;            \
+  case 8 * TI_ + 5: cpqr_wg_body<TPC_, 40>(nullptr, 0, 0, 0, 0, 0.0, nullptr, nullptr, nullptr, \
+                                           nullptr, nullptr, nullptr, jobs); break;            \
+  case 8 * TI_ + 6: cpqr_wg_body<TPC_, 48>(nullptr, 0, 0, 0, 0, 0.0, nullptr, nullptr, nullptr, \
+                                           nullptr, nullptr, nullptr, jobs); break;
+  switch (inst) {
+    SID_CWA(0, 8)
+    SID_CWA(1, 4)
+    SID_CWA(2, 2)
+    SID_CWA(3, 1)
+    default: break;
+  }
+#undef SID_CWA
 }
 
 static int cw_tpc(int nc) { return nc <= 64 ? 8 : nc <= 128 ? 4 : nc <= 256 ? 2 : 1; }
@@ -665,6 +705,10 @@ hipError_t launch_cpqr_batch(hipStream_t st, int instance, const CpqrJob* jobs, 
   if (njobs <= 0) return hipSuccess;
   if (!jobs || instance == 0) return hipErrorInvalidValue;
   const dim3 g((unsigned)njobs);
+  if (instance == CPQR_BATCH_ANY_WG) {
+    hipLaunchKernelGGL(k_cpqr_wg_any, g, dim3(CW_THREADS), 0, st, jobs);
+    return hipGetLastError();
+  }
   const double* X0 = nullptr;
   int64_t* pnull = nullptr;
   double* dnull = nullptr;

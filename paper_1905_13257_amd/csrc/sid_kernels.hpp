@@ -246,7 +246,7 @@ hipError_t launch_cpqr_wg(hipStream_t st, const double* X, int64_t ldx, int m, i
 struct CpqrJob {
   const double* X;
   int64_t ldx;
-  int m, nc, kmax, pad_;
+  int m, nc, kmax, inst;  // inst: cpqr_batch_instance of (m, nc)
   double rank_tol;
   int64_t* piv;
   double* R;
@@ -257,6 +257,9 @@ struct CpqrJob {
 // kernel instance of an (m x nc) mgsqr: > 0 for the register kernel, < 0
 // for the LDS kernel (wgl = true), 0 if neither takes the shape
 int cpqr_batch_instance(int m, int nc, bool wgl);
+// launch_cpqr_batch's instance for jobs of any register-kernel instance
+// (each job's inst field picks it), all in one launch
+constexpr int CPQR_BATCH_ANY_WG = 1000;
 hipError_t launch_cpqr_batch(hipStream_t st, int instance, const CpqrJob* jobs, int njobs);
 // measurement probes (sid_probe): kind 0 read / 1 column stores / 2
 // sequential fill of an N x n FP32 buffer, 3 / 4 the 16x16x32 / 32x32x16
