@@ -179,12 +179,14 @@ sid_status sid_set_workspace_limit(sid_ctx *ctx, size_t bytes);
 /* Wait for all work queued on the context (and its batched children), then
  * report device-side failures since the previous sid_sync: the
  * multi-workgroup pivoted QR needs its workgroups resident together; it is
- * launched cooperatively (which guarantees that) except under graph
- * capture, where a plain launch is used and a bounded wait that times out
- * (other work kept some workgroups from starting) sets k_eff = -1 for that
- * compression and a flag this call reads and clears.  Returns SID_OK, or
- * SID_EDEVICE with sid_last_error naming the failure (the results with
- * k_eff = -1 are then invalid). */
+ * a plain launch whose grid is checked against the device's occupancy on
+ * the host (the environment variable SID_COOPERATIVE=1 at context creation
+ * selects a cooperative launch outside graph capture instead, which
+ * guarantees co-residency but waits for the device's other work to drain).
+ * A bounded wait that times out (other work kept some workgroups from
+ * starting) sets k_eff = -1 for that compression and a flag this call reads
+ * and clears.  Returns SID_OK, or SID_EDEVICE with sid_last_error naming
+ * the failure (the results with k_eff = -1 are then invalid). */
 sid_status sid_sync(sid_ctx *ctx);
 
 /* Coarse row set S (Sec. 2.5 eq. (A_c): the sub-sampled degrees of freedom).

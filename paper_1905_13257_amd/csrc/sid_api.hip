@@ -146,8 +146,9 @@ struct sid_ctx {
   int device = 0;
   int num_cu = 1;
   // cooperative launch of the multi-workgroup pivoted QR outside graph
-  // capture (SID_COOPERATIVE=0 turns it off)
-  bool cooperative = true;
+  // capture (SID_COOPERATIVE=1 turns it on; by default a plain launch
+  // checked against the device's occupancy)
+  bool cooperative = false;
   // sticky device flag: a device-wide wait of the pivoted QR timed out
   // (set by the kernels, read and cleared by sid_sync)
   unsigned int* fail_flag = nullptr;
@@ -592,7 +593,7 @@ sid_status sid_create(sid_ctx** out, int device, void* hip_stream) {
   c->device = device;
   {
     const char* env = std::getenv("SID_COOPERATIVE");
-    c->cooperative = !(env && env[0] == '0');
+    c->cooperative = env && env[0] == '1';
     const char* vp = std::getenv("SID_SKETCH_PAIRS");
     c->sketch_pairs = vp && vp[0] == '1';
   }

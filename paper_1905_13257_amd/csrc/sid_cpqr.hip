@@ -793,13 +793,23 @@ hipError_t launch_cpqr_coop(hipStream_t st, const double* X, int64_t ldx, int m,
                   : rpt <= 32 ? (const void*)k_cpqr_coop<4, 32>
                   : rpt <= 48 ? (const void*)k_cpqr_coop<4, 48>
                               : (const void*)k_cpqr_coop<4, 64>);
-  // The G workgroups must be resident together.  A cooperative launch
-  // guarantees it (the default outside graph capture); a plain launch (used
-  // under capture, where cooperative launches cannot be recorded) of at most
-  // 256 workgroups of 256 threads fits the device at once, and if other work
-  // keeps some of them waiting for longer than the bounded spin, the wait
-  // gives up: keff = -1 and the context's sticky flag, which sid_sync
-  // reports, instead of a hang.
+  // The G workgroups must be resident together.  A plain launch (the
+  // default) is checked against the device's occupancy for this kernel
+  // first: the whole grid must fit at once; if other work keeps some
+  // workgroups waiting for longer than the bounded spin, the wait gives up
+  // (keff = -1 and the context's sticky flag, which sid_sync reports)
+  // instead of hanging.  A cooperative launch (opt-in) guarantees
+  // co-residency but waits for the device's other work to drain first,
+  // which serialized it with the side stream's small solves (0.4 ms per
+  // step on a non-default stream); it cannot be recorded into a graph.
+  if (!cooperative) {
+    int dev = 0, ncu = 0, per_cu = 0;
+    hipError_t qe = hipGetDevice(&dev);
+    if (qe == hipSuccess) qe = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (qe == hipSuccess) qe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, CQ_THREADS, 0);
+    if (qe != hipSuccess) return qe;
+    if ((int64_t)per_cu * ncu < (int64_t)grid.x) return hipErrorCooperativeLaunchTooLarge;
+  }
   const hipError_t e = cooperative
                            ? hipLaunchCooperativeKernel(kern, grid, block, args, 0, st)
                            : hipLaunchKernel(kern, grid, block, args, 0, st);
