@@ -717,6 +717,73 @@ def test_apply_rows_not_16_byte_aligned(sid, oracle_mod, k, p):
     assert np.all(dAJ <= bound)
 
 
+def test_cooperative_launch_matches_plain(sid, oracle_mod):
+    """The multi-workgroup pivoted QR (W_sel of 120 x 500 takes it) as the
+    default plain launch and as the opt-in cooperative one (SID_COOPERATIVE=1
+    when the context is created): the same pivots, P, AJ and estimates bit
+    for bit, and both contexts report no failed device-side wait."""
+    import os
+    A64, _ = c1_matrix(N=6000, n=500, seed=1008)
+    A = to_gpu(A64.astype(np.float32).astype(np.float64), torch.float32)
+    say("cooperative vs plain QR launch")
+    kw = dict(seed=4, mode="single_pass", prec="bf16x2", probe_rows=10)
+    plain = sid.compress(A, 100, 20, **kw)
+    old = os.environ.get("SID_COOPERATIVE")
+    os.environ["SID_COOPERATIVE"] = "1"
+    try:
+        ctx = sid.Context()
+    finally:
+        if old is None:
+            del os.environ["SID_COOPERATIVE"]
+        else:
+            os.environ["SID_COOPERATIVE"] = old
+    coop = sid.compress(A, 100, 20, ctx=ctx, **kw)
+    ctx.sync()
+    sid.sync()
+    torch.cuda.synchronize()
+    for a, b in ((plain.J, coop.J), (plain.P, coop.P), (plain.AJ, coop.AJ), (plain.err, coop.err),
+                 (plain.k_eff, coop.k_eff)):
+        assert torch.equal(a, b)
+    assert int(plain.k_eff[0]) == 100
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "bf16x2"])
+def test_ties_across_qr_workgroups(sid, oracle_mod, prec):
+    """Exact ties decided across the workgroups of the multi-workgroup QR
+    (W_sel of 100 x 500: 128 columns per workgroup): duplicated columns in
+    different workgroups give equal candidates, and both sides take the
+    smallest index (Sec. 2.4 mgsqr).  Ties at steps 0, 4 and 6 (140 / 420,
+    10 / 300, 3 / 260); every other step's margin is above 4e-5, so the
+    GPU's pivots on its own W must equal the oracle's mgsqr of that W."""
+    rng = np.random.default_rng(45)
+    N, n, k, p = 3000, 500, 80, 20
+    A64 = rng.standard_normal((N, n)) * (0.985 ** np.arange(n))
+    pairs = [(10, 300), (140, 420), (3, 260), (200, 499)]
+    for a, b in pairs:
+        A64[:, b] = A64[:, a]
+    A64[:, 140] *= 20.0
+    A64[:, 420] = A64[:, 140]
+    dt = torch.float64 if prec == "f64" else torch.float32
+    if dt == torch.float32:
+        A64 = A64.astype(np.float32).astype(np.float64)
+    A = to_gpu(A64, dt)
+    say("ties across QR workgroups", prec)
+    for mode in ("two_pass", "single_pass"):
+        out = sid.compress(A, k, p, seed=5, mode=mode, prec=prec, probe_rows=4)
+        Wg, _ = sid.sketch(A, k, p, seed=5, prec=prec, probe_rows=4, want_y=(mode == "single_pass"))
+        torch.cuda.synchronize()
+        Wg = host(Wg)
+        for a, b in pairs:
+            assert np.array_equal(Wg[:, a], Wg[:, b]), (prec, a, b)
+        cp = oracle_mod.cpqr(Wg[:k + p], k)
+        J = host(out.J)
+        assert J[0] == 140, (prec, mode, J[:3])
+        assert J.tolist() == cp.J.tolist(), (prec, mode)
+        m = np.asarray(cp.margins)
+        assert np.count_nonzero(m == 0) >= 3 and m[m > 0].min() > 1e-5
+
+
 def test_graph_capture_replay(sid, oracle_mod):
     """sid_reserve covers every allocation of a compress call; the call is
     then captured into a HIP graph and replayed several times, with eager
