@@ -499,12 +499,14 @@ sid_status sid_svd_stream_finish(sid_stream *s, double *S, void *U, int64_t ldu,
  * sid_last_error).  Results are bit for bit those of one sid_compress per
  * problem.
  *
- * When every problem has FP32 data (16-byte aligned, lda % 4 == 0), the same
- * BF16 / BF16X2 / FP8E4M3 sketch form and mode (two-pass or single-pass), the
- * Gaussian selection over all rows, no refinement, n <= 512, l <= 128 and
- * l + e + q <= 160, one persistent launch sketches all of them: a work queue
- * of every problem's row shares (the problems with the most work per share
- * first), then one launch forms every W.  The pivoted QRs of all problems
+ * When at most 16384 problems all have FP32 data (16-byte aligned,
+ * lda % 4 == 0), the same BF16 / BF16X2 / FP8E4M3 sketch form and mode
+ * (two-pass or single-pass), the Gaussian selection over all rows, no
+ * refinement, n <= 512, l <= 128 and l + e + q <= 160, persistent launches
+ * sketch all of them: one per register layout class of the problems (at
+ * most three, side by side), each over a work queue of its problems' row
+ * shares (the problems with the most work per share first); then one launch
+ * forms every W.  The pivoted QRs of all problems
  * whose shapes a one-workgroup factorization takes (W_sel's l x n and,
  * single pass, M's lz x l) go into a few launches, one per
  * kernel instance, side by side on up to 8 internal child streams, after two

@@ -1820,7 +1820,8 @@ sid_status validate_batch(sid_ctx* ctx, const sid_problem* probs, int64_t count,
 
 bool batch_persistent_ok(const sid_ctx* ctx, const sid_problem* probs, int64_t count,
                          sid_dtype dtype, const std::vector<Shape>& sh) {
-  if (dtype != SID_F32 || count < 1 || ctx->sketch_pairs) return false;
+  // (the batched launches put up to 2 count jobs in one grid dimension)
+  if (dtype != SID_F32 || count < 1 || count > 16384 || ctx->sketch_pairs) return false;
   const int prec = probs[0].params.prec;
   if (prec != SID_SK_BF16 && prec != SID_SK_BF16X2 && prec != SID_SK_FP8E4M3) return false;
   const bool single = sh[0].single;
