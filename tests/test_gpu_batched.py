@@ -106,3 +106,52 @@ def test_batched_persistent(sid, oracle_mod, batch, mode):
         e_o = oracle_mod.error_norms(A64, orc.AJ, orc.P)["rel_fro"]
         say("batch", mode, b, "rel_fro gpu", e_g, "oracle", e_o)
         assert abs(e_g - e_o) <= 0.05 * e_o
+
+
+@pytest.mark.timeout(600)
+def test_batched_outputs_change_between_calls(sid, batch):
+    """The batched skeleton estimate (one launch for every problem's
+    AJ = Y T) follows the caller's output table from call to call: problems
+    without an AJ buffer are skipped (their other outputs still written,
+    the problem's previous AJ buffer untouched), and a second call with new
+    AJ buffers (another row stride) writes those.  Every AJ equals the single
+    call's bit for bit."""
+    shapes, mats = batch
+    order = np.argsort([N * n for N, n, _ in shapes])[:10].tolist()
+    sub = [mats[b] for b in order]
+    ks = [shapes[b][2] for b in order]
+    seeds = [31 + i for i in range(len(sub))]
+    kw = dict(oversample=10, mode="single_pass", prec="bf16x2", probe_rows=10)
+    bt = sid.Batch(sub, ks, seed=seeds, **kw).reserve()
+    refs = []
+    for A, k, sd in zip(sub, ks, seeds):
+        refs.append(sid.compress(A, k, kw["oversample"], seed=sd, mode=kw["mode"],
+                                 prec=kw["prec"], probe_rows=kw["probe_rows"]))
+    torch.cuda.synchronize()
+    # first call: odd problems without AJ (their buffers hold a sentinel)
+    for i, o in enumerate(bt.outs):
+        o.AJ.fill_(float("nan"))
+        if i % 2:
+            bt.probs[i].AJ = None
+    outs = bt.run()
+    torch.cuda.synchronize()
+    for i, (o, r) in enumerate(zip(outs, refs)):
+        assert torch.equal(o.J, r.J) and torch.equal(o.P, r.P) and torch.equal(o.err, r.err), i
+        if i % 2:
+            assert torch.isnan(o.AJ).all(), i
+        else:
+            assert torch.equal(o.AJ, r.AJ), i
+    # second call: new AJ buffers with a padded leading dimension
+    fresh = []
+    for i, (A, k) in enumerate(zip(sub, ks)):
+        N = A.shape[0]
+        buf = torch.full((k, N + 3), float("nan"), dtype=torch.float32, device="cuda")
+        fresh.append(buf)
+        bt.probs[i].AJ = buf.data_ptr()
+        bt.probs[i].ldaj = N + 3
+    bt.run()
+    torch.cuda.synchronize()
+    for i, (buf, r) in enumerate(zip(fresh, refs)):
+        N = sub[i].shape[0]
+        assert torch.equal(buf[:, :N].T, r.AJ), i
+        assert torch.isnan(buf[:, N:]).all(), i
