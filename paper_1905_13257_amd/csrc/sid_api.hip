@@ -58,7 +58,7 @@ void* noalloc_scratch_init(int device) {
 enum Slot {
   WS_OMEGA, WS_PART, WS_W, WS_WR, WS_NRM, WS_PIV, WS_R, WS_Q, WS_KEFF, WS_STATS, WS_PD,
   WS_ERR, WS_Y, WS_M, WS_MPR, WS_WJ, WS_PIVM, WS_RM, WS_QM, WS_RKM, WS_C, WS_T, WS_MIX,
-  WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COOP, WS_SYNC, WS_R11, WS_R11M, WS_FITPART, WS_YTMP, WS_REF_W, WS_REF_WJ, WS_OMP, WS_A8, WS_IACJT, WS_IPB, WS_IB, WS_IPART, WS_AZ, WS_AE2, WS_APART, WS_SV_H, WS_SV_B, WS_SV_Q, WS_SV_OM32,
+  WS_STATSM, WS_NORMPART, WS_NORMOUT, WS_OM64, WS_PARTF, WS_OMT, WS_COOP, WS_SYNC, WS_R11, WS_R11M, WS_FITPART, WS_YTMP, WS_REF_W, WS_REF_WJ, WS_OMP, WS_A8, WS_PSIIMG, WS_IACJT, WS_IPB, WS_IB, WS_IPART, WS_AZ, WS_AE2, WS_APART, WS_SV_H, WS_SV_B, WS_SV_Q, WS_SV_OM32,
   WS_SV_OM, WS_SV_SMALL, WS_SV_WP, WS_SV_TSP, WS_PROBE, WS_COUNT
 };
 
@@ -200,6 +200,7 @@ struct sid_stream {
   int64_t stage_cols = 0;   // stage capacity (columns)
   int64_t ld_stage = 0;     // stage leading dimension (multiple of 4)
   void* stage = nullptr;    // N x stage_cols (data type), allocated on first use
+  __bf16* psi_img = nullptr;  // Psi images of the workgroup-pair pass (formed once)
   double* W = nullptr;      // lq x n_max, column-major
   void* Y = nullptr;        // N x l row-major (single pass), FP64 for F64 sketches else FP32
   bool y_init = false;
@@ -521,6 +522,8 @@ sid_status reserve_sketch(sid_ctx* ctx, const Shape& sh, int prec, bool has_rows
     if (!ws(ctx, WS_PARTF, sizeof(float) * (size_t)(pairs * sh.lq * vs)) ||
         !ws(ctx, WS_OMT, sizeof(uint16_t) * sid::sketch_v2_omt_elems((int)sh.l, (int)vs)))
       return SID_ENOMEM;
+    const size_t img_bytes = sid::sketch_v2_psi_image_bytes(sh.N, (int)sh.lq);
+    if (sh.n > vs && img_bytes > 0 && !ws(ctx, WS_PSIIMG, img_bytes)) return SID_ENOMEM;
   } else if (path == SketchPath::FUSED_BF16 || path == SketchPath::FUSED_F32) {
     int64_t rpw = 0;
     const int64_t grid = sid::fused_bf16_grid(sh.N, ctx->num_cu, &rpw);  // N >= Ns: the larger
@@ -784,7 +787,8 @@ static sid_status refine_pass(sid_ctx* ctx, const void* A, sid_dtype dtype, int6
 // workgroup-pair pass takes it, see sketch_adds_y).
 static sid_status run_sketch(sid_ctx* ctx, const void* A, sid_dtype dtype, int64_t lda,
                              const sid_params* p, const Shape& sh, const Work& w, double* W,
-                             void* Y, int64_t col0 = 0, bool y_add = false) {
+                             void* Y, int64_t col0 = 0, bool y_add = false,
+                             const __bf16* psi_img = nullptr) {
   hipStream_t st = ctx->stream;
   if (Y) {
     SID_CHECK(sid::launch_fill_gaussian(st, p->seed, 0u, col0, sh.n, 0, sh.l, w.omega),
@@ -810,6 +814,16 @@ static sid_status run_sketch(sid_ctx* ctx, const void* A, sid_dtype dtype, int64
     const int dmode = sh.prec == SID_SK_BF16X2   ? sid::FB_BF16X2
                       : sh.prec == SID_SK_FP8E4M3 ? sid::FB_FP8
                                                   : sid::FB_BF16;
+    // over several slabs, Psi is formed once as images that every slab's
+    // launch reads (the values the launches would generate)
+    const size_t img_bytes = sid::sketch_v2_psi_image_bytes(sh.N, (int)sh.lq);
+    if (!psi_img && sh.n > vs && img_bytes > 0) {
+      __bf16* img = (__bf16*)ws(ctx, WS_PSIIMG, img_bytes);
+      if (!img) return SID_ENOMEM;
+      SID_CHECK(sid::launch_sketch_v2_psi_image(st, dmode, p->seed, sh.N, (int)sh.lq, img),
+                "Psi images");
+      psi_img = img;
+    }
     // every slab after the first adds its part of Y in the kernel
     for (int64_t c0 = 0; c0 < sh.n; c0 += vs) {
       const int64_t nb = sh.n - c0 < vs ? sh.n - c0 : vs;
@@ -817,7 +831,7 @@ static sid_status run_sketch(sid_ctx* ctx, const void* A, sid_dtype dtype, int64
       SID_CHECK(sid::launch_sketch_v2(st, dmode, (const float*)A + c0 * lda, lda, sh.N, (int)nb,
                                       (int)sh.lq, (int)sh.l, p->seed, w.omega + c0 * sh.l, omT,
                                       ctx->num_cu, partf, W + c0 * sh.lq, (float*)Y, &nparts,
-                                      c0 > 0 || y_add),
+                                      c0 > 0 || y_add, psi_img),
                 "sketch pass (workgroup pairs)");
     }
     return SID_OK;
@@ -1377,6 +1391,7 @@ void stream_free(sid_stream* s) {
     (void)hipSetDevice(s->ctx->device);
     (void)hipStreamSynchronize(s->ctx->stream);
     if (s->stage) (void)hipFree(s->stage);
+    if (s->psi_img) (void)hipFree(s->psi_img);
     if (s->W) (void)hipFree(s->W);
     if (s->Y) (void)hipFree(s->Y);
     if (s->H) (void)hipFree(s->H);
@@ -1423,8 +1438,28 @@ sid_status stream_flush(sid_stream* s, const void* src, int64_t ld, int64_t ncol
   const bool kadd = s->single && s->y_init && sketch_adds_y(ctx, s->dtype, ld, src, sh);
   void* ydst = nullptr;
   if (s->single) ydst = (s->y_init && !kadd) ? w.Y : s->Y;
+  // on the workgroup-pair pass, a stream of more columns than one stage
+  // forms Psi once as images (stream-owned) that every flush reads
+  if (!s->psi_img && s->n_max > s->stage_cols && s->dtype == SID_F32 &&
+      plan_sketch(ctx, s->dtype, ld, src, sh.prec, sh, s->p.coarse != nullptr, s->single) ==
+          SketchPath::PAIR_BF16) {
+    const size_t ib = sid::sketch_v2_psi_image_bytes(s->N, (int)sh.lq);
+    if (ib > 0) {
+      if (hipMalloc((void**)&s->psi_img, ib) != hipSuccess) {
+        (void)hipGetLastError();
+        s->psi_img = nullptr;
+        return fail(ctx, SID_ENOMEM, "stream: device allocation of the Psi images failed");
+      }
+      const int dmode = sh.prec == SID_SK_BF16X2   ? sid::FB_BF16X2
+                        : sh.prec == SID_SK_FP8E4M3 ? sid::FB_FP8
+                                                    : sid::FB_BF16;
+      SID_CHECK(sid::launch_sketch_v2_psi_image(ctx->stream, dmode, s->p.seed, s->N, (int)sh.lq,
+                                                s->psi_img),
+                "stream: Psi images");
+    }
+  }
   st = run_sketch(ctx, src, s->dtype, ld, &s->p, sh, w, s->W + s->lq * s->cols, ydst, s->cols,
-                  kadd);
+                  kadd, s->psi_img);
   if (st != SID_OK) return st;
   if (s->single && s->y_init && !kadd)
     SID_CHECK(sid::launch_add_inplace(ctx->stream, s->p.prec == SID_SK_F64, s->Y, w.Y,

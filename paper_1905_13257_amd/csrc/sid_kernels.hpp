@@ -173,7 +173,15 @@ int64_t sketch_v2_pairs(int64_t N, int num_cu, int64_t* rows_per_pair);
 hipError_t launch_sketch_v2(hipStream_t st, int dmode, const float* A, int64_t lda, int64_t N,
                             int n, int lq, int l, uint64_t seed, const float* omega, __bf16* omT,
                             int num_cu, float* part, double* W, float* Y, int64_t* nparts_out,
-                            bool y_add = false);
+                            bool y_add = false, const __bf16* psi_img = nullptr);
+// Psi images for launch_sketch_v2 (psi_img): the half-panel LDS images of
+// Psi that the pass would generate, formed once and read by every launch
+// over the same rows, seed and lq (a matrix wider than one slab, a stream's
+// flushes); the bits are those of the generating pass.  0 bytes (images not
+// taken) unless the shape has 4 W row tiles per half.
+size_t sketch_v2_psi_image_bytes(int64_t N, int lq);
+hipError_t launch_sketch_v2_psi_image(hipStream_t st, int dmode, uint64_t seed, int64_t N, int lq,
+                                      __bf16* img);
 int64_t fused_bf16_grid(int64_t N, int num_cu, int64_t* rows_per_wg);
 bool fused_bf16_batch_supported(int64_t n, int lq, int l, int64_t lda, const void* A);
 // Layout classes of the batched sketch pass (the register and LDS layout a

@@ -72,10 +72,55 @@ int64_t sketch_v2_pairs(int64_t N, int num_cu, int64_t* rows_per_pair) {
   return pairs;
 }
 
+// Psi images: for every panel P of 64 rows and pair half h, the LDS image of
+// the half's Psi rows (MT = 4 tiles of 32 rows x 64 panel rows, bf16, the
+// kernel's XOR placement) that the pass would generate for that panel: the
+// same generator call per (row, group of four Psi rows), FP8-rounded in the
+// FP8 form, rows past N and Psi rows past the half zero.  One thread per
+// (panel row, group).
+__global__ void k_psi_image(uint64_t seed, int64_t N, int lq, int hsplit, int fp8,
+                            __bf16* __restrict__ img, int64_t npanels) {
+  constexpr int MT = 4, PIMG = MT * 32 * V2_PS;
+  const int64_t items = npanels * 2 * (MT * 8) * V2_PR;
+  for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < items;
+       w += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(w % V2_PR);
+    const int g = (int)((w / V2_PR) % (MT * 8));
+    const int h = (int)((w / (V2_PR * MT * 8)) % 2);
+    const int64_t P = w / (V2_PR * MT * 8 * 2);
+    const int mb = h ? hsplit : 0, mc = h ? lq - hsplit : hsplit;
+    const int64_t r = P * V2_PR + k;
+    float z[4] = {0.f, 0.f, 0.f, 0.f};
+    if (r < N && 4 * g < mc) gauss4(seed, 1u, (uint64_t)r, (uint32_t)((mb >> 2) + g), z);
+    __bf16* out = img + (P * 2 + h) * (int64_t)PIMG;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int m = 4 * g + e;
+      const float v = m < mc ? (fp8 ? e4m3_value(z[e]) : z[e]) : 0.0f;
+      out[psi_idx(m, k)] = (__bf16)v;
+    }
+  }
+}
+
+size_t sketch_v2_psi_image_bytes(int64_t N, int lq) {
+  if (v2_mt(lq) != 4) return 0;
+  const int64_t npanels = (N + V2_PR - 1) / V2_PR;
+  return sizeof(uint16_t) * (size_t)npanels * 2 * (size_t)(4 * 32 * V2_PS);
+}
+
+hipError_t launch_sketch_v2_psi_image(hipStream_t st, int dmode, uint64_t seed, int64_t N, int lq,
+                                      __bf16* img) {
+  if (v2_mt(lq) != 4 || N < 1) return hipErrorInvalidValue;
+  const int64_t npanels = (N + V2_PR - 1) / V2_PR;
+  hipLaunchKernelGGL(k_psi_image, dim3(4096), dim3(256), 0, st, seed, N, lq, v2_hsplit(lq),
+                     dmode == FB_FP8 ? 1 : 0, img, npanels);
+  return hipGetLastError();
+}
+
 hipError_t launch_sketch_v2(hipStream_t st, int dmode, const float* A, int64_t lda, int64_t N,
                             int n, int lq, int l, uint64_t seed, const float* omega, __bf16* omT,
                             int num_cu, float* part, double* W, float* Y, int64_t* nparts_out,
-                            bool y_add) {
+                            bool y_add, const __bf16* psi_img) {
   const int nct = (n + V2_CHUNK - 1) / V2_CHUNK;
   if (n < 1 || !v2_fits(nct, lq, l, Y != nullptr)) return hipErrorInvalidValue;
   if (Y && (uint64_t)N * (uint64_t)l * 4u >= (1ull << 32)) return hipErrorInvalidValue;
@@ -89,9 +134,10 @@ hipError_t launch_sketch_v2(hipStream_t st, int dmode, const float* A, int64_t l
   *nparts_out = pairs;
   const dim3 g((unsigned)(2 * pairs));
   const int ya = (Y && y_add) ? 1 : 0;
-  hipError_t e = dmode == FB_BF16X2 ? v2_launch_bf16x2(st, g, A, lda, N, n, lq, l, seed, omT, rpp, part, Y, ya)
-                 : dmode == FB_FP8  ? v2_launch_fp8(st, g, A, lda, N, n, lq, l, seed, omT, rpp, part, Y, ya)
-                                    : v2_launch_bf16(st, g, A, lda, N, n, lq, l, seed, omT, rpp, part, Y, ya);
+  const __bf16* img = v2_mt(lq) == 4 ? psi_img : nullptr;
+  hipError_t e = dmode == FB_BF16X2 ? v2_launch_bf16x2(st, g, A, lda, N, n, lq, l, seed, omT, rpp, part, Y, ya, img)
+                 : dmode == FB_FP8  ? v2_launch_fp8(st, g, A, lda, N, n, lq, l, seed, omT, rpp, part, Y, ya, img)
+                                    : v2_launch_bf16(st, g, A, lda, N, n, lq, l, seed, omT, rpp, part, Y, ya, img);
   if (e != hipSuccess) return e;
   const int64_t count = (int64_t)lq * n;
   int64_t blocks = (count + 255) / 256;

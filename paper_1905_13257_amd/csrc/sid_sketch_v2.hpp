@@ -105,8 +105,12 @@ __global__ __launch_bounds__(V2_THREADS, 1) void k_sketch_v2(
     const float* __restrict__ A, int64_t lda, int64_t N, int n, int lq, int hsplit, int l,
     uint64_t seed, const __bf16* __restrict__ omT /* 64 LT x 128 NCT, k in chunk-buffer order */,
     int64_t rows_per_pair, float* __restrict__ part /* pairs x lq x n, row-major per pair */,
-    float* __restrict__ Y /* N x l row-major */, int yadd /* 1: Y += A Omega */) {
+    float* __restrict__ Y /* N x l row-major */, int yadd /* 1: Y += A Omega */,
+    const __bf16* __restrict__ psi_img /* optional: Psi images (MT = 4 only) */) {
   static_assert(LT == 2 || LT == 4, "Y column tiles per half");
+  // Psi images are taken for MT = 4 only (MT pieces per thread: the counts
+  // of the waits at (2))
+  constexpr bool PSI_IMG_OK = MT == 4;
   constexpr bool SPLIT = DM == FB_BF16X2;
   constexpr bool FP8 = DM == FB_FP8;
   constexpr int NH = SPLIT ? 2 : 1;
@@ -287,6 +291,17 @@ __global__ __launch_bounds__(V2_THREADS, 1) void k_sketch_v2(
     const int rows_left = TAIL ? (int)(r1 - p0) : V2_PR;
     const int col = V2_CHUNK * j + colw + lc;
     const bool col_ok = col < n;
+    // (0) with Psi images: the first chunk of a panel loads the next panel's
+    //     image of this half (MT pieces of 16 bytes per thread), written to
+    //     LDS at (5); issued first, so that the waits below count them
+    const bool img = PSI_IMG_OK && psi_img && !TAIL && j == 0 && p0 + V2_PR < r1;
+    bf16x8_t imv[MT];
+    if (img) {
+      typedef const __attribute__((address_space(1))) bf16x8_t* gimg;
+      const gimg src = (gimg)(psi_img + ((p0 / V2_PR + 1) * 2 + half) * (int64_t)(MT * 32 * V2_PS));
+#pragma unroll
+      for (int i = 0; i < MT; ++i) imv[i] = src[tid + V2_THREADS * i];
+    }
     // (1) Omega^T fragments of this chunk (used at its end)
     bf16x8_t of[8];
     if constexpr (WANTY) {
@@ -328,12 +343,23 @@ __global__ __launch_bounds__(V2_THREADS, 1) void k_sketch_v2(
       // the DMA of this chunk was issued two chunks ago; the one of the next
       // chunk (8 loads, if there is a next chunk: one_more) and this chunk's
       // Omega fragments (8) may still be outstanding
+      // (with an image load this chunk: its MT = 4 loads as well)
       if constexpr (WANTY) {
-        if (one_more) asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
-        else asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
+        if (img) {
+          if (one_more) asm volatile("s_waitcnt vmcnt(20)" ::: "memory");
+          else asm volatile("s_waitcnt vmcnt(12)" ::: "memory");
+        } else {
+          if (one_more) asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
+          else asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
+        }
       } else {
-        if (one_more) asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
-        else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        if (img) {
+          if (one_more) asm volatile("s_waitcnt vmcnt(12)" ::: "memory");
+          else asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
+        } else {
+          if (one_more) asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
+          else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        }
       }
       if (store_prev) store_y(p0 - V2_PR, V2_PR);
       if constexpr (FP8) {
@@ -404,9 +430,16 @@ __global__ __launch_bounds__(V2_THREADS, 1) void k_sketch_v2(
       }
       __builtin_amdgcn_sched_barrier(0);
     }
-    // (5) slice j of Psi(:, next panel)
-    if (!TAIL && p0 + V2_PR < r1)
+    // (5) slice j of Psi(:, next panel), or the whole of it from its image
+    if (PSI_IMG_OK && psi_img) {
+      if (img) {
+        bf16x8_t* dstp = reinterpret_cast<bf16x8_t*>(&s_psi[pb ^ 1][0]);
+#pragma unroll
+        for (int i = 0; i < MT; ++i) dstp[tid + V2_THREADS * i] = imv[i];
+      }
+    } else if (!TAIL && p0 + V2_PR < r1) {
       gen(p0 + V2_PR, pb ^ 1, gen_iters * j / NCT, gen_iters * (j + 1) / NCT);
+    }
     lds_barrier();  // chunk buffer complete (and, after the last chunk, the next Psi)
     // (6) Y(panel, this wave's tiles) += A(panel, chunk) Omega(chunk, :)
     if constexpr (WANTY) {
@@ -504,10 +537,11 @@ inline bool v2_fits(int nct, int lq, int l, bool wanty) {
 template <int DM, bool WY, int MT, int NCT, int LT>
 hipError_t v2_launch_one(hipStream_t st, dim3 grid, const float* A, int64_t lda, int64_t N, int n,
                          int lq, int l, uint64_t seed, const __bf16* omT, int64_t rpp, float* part,
-                         float* Y, int yadd) {
+                         float* Y, int yadd, const __bf16* psi_img) {
   if constexpr (v2_fits_t(MT, NCT, LT, WY)) {
     hipLaunchKernelGGL((k_sketch_v2<DM, WY, MT, NCT, LT>), grid, dim3(V2_THREADS), 0, st, A, lda,
-                       N, n, lq, v2_hsplit(lq), l, seed, omT, rpp, part, Y, yadd);
+                       N, n, lq, v2_hsplit(lq), l, seed, omT, rpp, part, Y, yadd,
+                       MT == 4 ? psi_img : nullptr);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
@@ -518,10 +552,11 @@ hipError_t v2_launch_one(hipStream_t st, dim3 grid, const float* A, int64_t lda,
 template <int DM>
 hipError_t v2_launch_dm(hipStream_t st, dim3 grid, const float* A, int64_t lda, int64_t N, int n,
                         int lq, int l, uint64_t seed, const __bf16* omT, int64_t rpp, float* part,
-                        float* Y, int yadd) {
+                        float* Y, int yadd, const __bf16* psi_img) {
   const int mt = v2_mt(lq), lt = v2_lt(l), nct = (n + V2_CHUNK - 1) / V2_CHUNK;
 #define SID_V2(WY, MT_, NCT_, LT_) \
-  return v2_launch_one<DM, WY, MT_, NCT_, LT_>(st, grid, A, lda, N, n, lq, l, seed, omT, rpp, part, Y, yadd)
+  return v2_launch_one<DM, WY, MT_, NCT_, LT_>(st, grid, A, lda, N, n, lq, l, seed, omT, rpp, part, Y, \
+                                               yadd, psi_img)
 #define SID_V2_LT(MT_, NCT_)                     \
   if (!Y) SID_V2(false, MT_, NCT_, 2);           \
   else if (lt == 2) SID_V2(true, MT_, NCT_, 2);  \
@@ -542,12 +577,12 @@ hipError_t v2_launch_dm(hipStream_t st, dim3 grid, const float* A, int64_t lda, 
 
 hipError_t v2_launch_bf16(hipStream_t st, dim3 grid, const float* A, int64_t lda, int64_t N, int n,
                           int lq, int l, uint64_t seed, const __bf16* omT, int64_t rpp, float* part,
-                          float* Y, int yadd);
+                          float* Y, int yadd, const __bf16* psi_img);
 hipError_t v2_launch_bf16x2(hipStream_t st, dim3 grid, const float* A, int64_t lda, int64_t N,
                             int n, int lq, int l, uint64_t seed, const __bf16* omT, int64_t rpw,
-                            float* part, float* Y, int yadd);
+                            float* part, float* Y, int yadd, const __bf16* psi_img);
 hipError_t v2_launch_fp8(hipStream_t st, dim3 grid, const float* A, int64_t lda, int64_t N, int n,
                          int lq, int l, uint64_t seed, const __bf16* omT, int64_t rpw, float* part,
-                         float* Y, int yadd);
+                         float* Y, int yadd, const __bf16* psi_img);
 
 }  // namespace sid

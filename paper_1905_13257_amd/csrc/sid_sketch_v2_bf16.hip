@@ -7,8 +7,8 @@ namespace sid {
 
 hipError_t v2_launch_bf16(hipStream_t st, dim3 grid, const float* A, int64_t lda, int64_t N, int n,
                          int lq, int l, uint64_t seed, const __bf16* omT, int64_t rpp, float* part,
-                         float* Y, int yadd) {
-  return v2_launch_dm<FB_BF16>(st, grid, A, lda, N, n, lq, l, seed, omT, rpp, part, Y, yadd);
+                         float* Y, int yadd, const __bf16* psi_img) {
+  return v2_launch_dm<FB_BF16>(st, grid, A, lda, N, n, lq, l, seed, omT, rpp, part, Y, yadd, psi_img);
 }
 
 }  // namespace sid

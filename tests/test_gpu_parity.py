@@ -784,6 +784,25 @@ def test_ties_across_qr_workgroups(sid, oracle_mod, prec):
         assert np.count_nonzero(m == 0) >= 3 and m[m > 0].min() > 1e-5
 
 
+@pytest.mark.parametrize("prec", ["bf16x2", "fp8"])
+def test_pair_pass_psi_images_bitwise(sid, oracle_mod, prec):
+    """Over more than one column slab the workgroup-pair pass reads Psi from
+    images formed once (instead of generating it in every slab's launch):
+    W of the first slab's columns equals, bit for bit, the sketch of those
+    columns alone (one launch, Psi generated in the kernel); a ragged last
+    row panel is covered (N = 3000).  (W and Y of the wide call against the
+    oracle: test_pair_pass_y_over_column_slabs.)"""
+    N, n, k, p, q = 3000, 900, 150, 30, 6
+    A64, _ = c1_matrix(N=N, n=n, seed=1009)
+    A = to_gpu(A64.astype(np.float32).astype(np.float64), torch.float32)
+    say("pair pass Psi images", prec)
+    W_all, _ = sid.sketch(A, k, p, seed=7, prec=prec, probe_rows=q, want_y=True)
+    W_one, _ = sid.sketch(A[:, :384].contiguous(), k, p, seed=7, prec=prec, probe_rows=q,
+                          want_y=True)
+    torch.cuda.synchronize()
+    assert torch.equal(W_all[:, :384], W_one)
+
+
 def test_graph_capture_replay(sid, oracle_mod):
     """sid_reserve covers every allocation of a compress call; the call is
     then captured into a HIP graph and replayed several times, with eager
